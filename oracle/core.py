@@ -1,0 +1,506 @@
+"""Plain FP64 oracle (test infrastructure only; see the package docstring).
+
+Every function cites the passage of the paper it follows.  Fields use the
+canonical layout: spinors ``psi[V, 4, 3]`` and gauge fields ``U[V, 4, 3, 3]``
+(complex128), ``site = x0 + L0*(x1 + L1*(x2 + L2*x3))``.
+
+Pins (tests under ``tests/test_oracle_*.py``):
+  * operator          free-field plane waves (closed form), U(1) background
+                      (closed form), gamma5-hermiticity, gauge covariance,
+                      free-field log det (closed form)
+  * blocks / hops     D = sum of parts; entries equal the masked dense D;
+                      det D = prod_b det D_b * det Dhat (Sec. 3, eq. ddfactor);
+                      Dhat psi = psi on black-interior support (Sec. 4)
+  * even/odd          det D = det(1 - kappa^2 H_eo H_oe) (dense)
+  * solver            residual, dense numpy solve
+  * SAP / MR          multiplicative Schwarz closed form with dense block
+                      inverses; MR residual monotonic; odd-site equations exact
+  * noise             Philox4x64-10 vs numpy.random.Philox and published
+                      known-answer vectors; moments
+  * path              endpoints, SU(3), geodesic step length, scipy
+                      fractional_matrix_power; telescoping of eq. param
+  * sample            dense -eta^+(M^+M - 1)eta; E[s] = -tr(M^+M - 1)
+  * log ratio         exact dense log R; sum of factor log dets (eq. param)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wdr_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C part of the oracle with gcc (OpenMP)."""
+    os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        # OpenMP threads that spin between calls starve numpy's BLAS threads
+        os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i = ctypes.c_int
+        d = ctypes.c_double
+        L.oracle_gamma.argtypes = [i, P]
+        L.oracle_site_maps.argtypes = [P, P, P, P, P]
+        L.oracle_apply_D.argtypes = [P, P, d, P, P, P]
+        L.oracle_apply_Dblock.argtypes = [P, P, P, d, P, i, P, P]
+        L.oracle_apply_Dhop.argtypes = [P, P, P, d, P, i, P, P]
+        L.oracle_apply_Dee.argtypes = [P, P, P, d, P, i, P, P]
+        L.oracle_mul_g5.argtypes = [ctypes.c_long, P, P]
+        L.oracle_cgne.argtypes = [P, P, P, d, P, i, i, P, P, P, d, i, P]
+        L.oracle_cgne.restype = i
+        L.oracle_sap.argtypes = [P, P, P, d, P, i, i, P, P]
+        L.oracle_philox4x64_10.argtypes = [P, P, P]
+        L.oracle_noise.argtypes = [P, i, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _i4(v):
+    return np.ascontiguousarray(np.asarray(v, dtype=np.int32))
+
+
+# ----------------------------------------------------------------------------
+# Geometry (Sec. 3: blocks, checkerboard colouring, black blocks first)
+
+
+@dataclass
+class Lattice:
+    """Periodic 4-d lattice L[0..3] split into blocks B[0..3] (B divides L).
+
+    bc[mu] = +1 periodic, -1 antiperiodic in direction mu.
+    """
+
+    L: tuple
+    B: tuple = None
+    bc: tuple = (1, 1, 1, 1)
+    _cache: dict = field(default_factory=dict, repr=False, compare=False)
+
+    def __post_init__(self):
+        self.L = tuple(int(v) for v in self.L)
+        self.B = tuple(int(v) for v in (self.B if self.B is not None else self.L))
+        self.bc = tuple(int(v) for v in self.bc)
+        for l, b in zip(self.L, self.B):
+            if b <= 0 or l % b:
+                raise ValueError("block extent must divide the lattice extent")
+
+    @property
+    def V(self) -> int:
+        return int(np.prod(self.L))
+
+    @property
+    def NB(self) -> tuple:
+        return tuple(l // b for l, b in zip(self.L, self.B))
+
+    @property
+    def Vb(self) -> int:
+        return int(np.prod(self.B))
+
+    @property
+    def nblocks(self) -> int:
+        return int(np.prod(self.NB))
+
+    def arrays(self):
+        return _i4(self.L), _i4(self.B), _i4(self.bc)
+
+    def coords(self) -> np.ndarray:
+        """x[site, mu] for every canonical site."""
+        s = np.arange(self.V)
+        out = np.empty((self.V, 4), dtype=np.int64)
+        for mu in range(4):
+            out[:, mu] = s % self.L[mu]
+            s = s // self.L[mu]
+        return out
+
+    def maps(self):
+        """(block id, block colour, site parity) per canonical site, from C."""
+        if "maps" not in self._cache:
+            L, B, _ = self.arrays()
+            bid = np.empty(self.V, np.int32)
+            col = np.empty(self.V, np.int32)
+            par = np.empty(self.V, np.int32)
+            lib().oracle_site_maps(_p(L), _p(B), _p(bid), _p(col), _p(par))
+            self._cache["maps"] = (bid, col, par)
+        return self._cache["maps"]
+
+
+def block_order(lat: Lattice) -> np.ndarray:
+    """Site ordering of Sec. 3: the sites of the first black block come
+    first, then the second black block, ..., then the white blocks.  Blocks
+    of one colour are taken in lexicographic order of their block
+    coordinates; inside a block the even sites come before the odd sites and
+    each parity is in lexicographic order (the paper leaves the in-block order
+    open; this is the project's choice).  Returns perm with
+    perm[position] = canonical site.
+    """
+    bid, col, par = lat.maps()
+    x = lat.coords()
+    local = np.zeros(lat.V, dtype=np.int64)
+    for mu in (3, 2, 1, 0):
+        local = local * lat.B[mu] + (x[:, mu] % lat.B[mu])
+    # rank of each block among blocks of the same colour
+    nb = lat.nblocks
+    bcol = np.zeros(nb, dtype=np.int64)
+    bcol[bid] = col
+    slot = np.zeros(nb, dtype=np.int64)
+    nblack = int(np.sum(bcol == 0))
+    slot[bcol == 0] = np.arange(nblack)
+    slot[bcol == 1] = nblack + np.arange(nb - nblack)
+    keys = np.lexsort((local, par, slot[bid]))
+    return keys
+
+
+def active_links(lat: Lattice, lo: int = 0, hi: int | None = None) -> np.ndarray:
+    """Active-link mask (Sec. 3): inside every block, take the region R of
+    sites whose in-block coordinates all lie in [lo, hi]; the active links
+    are the links with both ends in R and at most one end on the boundary of
+    R.  lo = 0, hi = B-1 is the rule for the whole block (about 10% of the
+    links for 4^4 blocks, Sec. 5); lo = 1, hi = 6 in 8^4 blocks is the 6^4
+    core of Sec. 6 (8%).  Returns mask[site, mu] for the link x -> x+mu.
+    """
+    x = lat.coords()
+    V = lat.V
+    mask = np.zeros((V, 4), dtype=bool)
+    for mu in range(4):
+        h = (hi if hi is not None else lat.B[mu] - 1)
+        ok = np.ones(V, dtype=bool)
+        for nu in range(4):
+            hn = hi if hi is not None else lat.B[nu] - 1
+            r = x[:, nu] % lat.B[nu]
+            if nu == mu:
+                # both ends x, x+mu inside R: lo <= r and r + 1 <= h
+                ok &= (r >= lo) & (r + 1 <= h)
+            else:
+                # both ends share this coordinate; one end interior needs it
+                # strictly inside R
+                ok &= (r > lo) & (r < hn)
+        mask[:, mu] = ok
+    return mask
+
+
+# ----------------------------------------------------------------------------
+# Operator (Sec. 5: plain Wilson-Dirac operator with hopping parameter kappa;
+# Sec. 3, eq. domdec: Dirichlet blocks and interaction hops)
+
+
+def gamma(mu: int) -> np.ndarray:
+    out = np.empty(32, dtype=np.float64)
+    lib().oracle_gamma(mu, _p(out))
+    return out.view(np.complex128).reshape(4, 4)
+
+
+GAMMA5 = np.diag([1.0, 1.0, -1.0, -1.0]).astype(np.complex128)
+
+
+def _c(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def g5(psi: np.ndarray) -> np.ndarray:
+    out = _c(psi).copy()
+    out[:, 2:, :] *= -1
+    return out
+
+
+def apply_D(lat: Lattice, U, kappa: float, psi) -> np.ndarray:
+    U, psi = _c(U), _c(psi)
+    out = np.empty_like(psi)
+    L, _, bc = lat.arrays()
+    lib().oracle_apply_D(_p(L), _p(bc), kappa, _p(U), _p(psi), _p(out))
+    return out
+
+
+def apply_Dblock(lat: Lattice, U, kappa: float, psi, colour: int) -> np.ndarray:
+    """D_bb (colour 0), D_ww (colour 1) or both (2): Dirichlet block operators."""
+    U, psi = _c(U), _c(psi)
+    out = np.empty_like(psi)
+    L, B, bc = lat.arrays()
+    lib().oracle_apply_Dblock(_p(L), _p(B), _p(bc), kappa, _p(U), colour, _p(psi), _p(out))
+    return out
+
+
+def apply_Dhop(lat: Lattice, U, kappa: float, psi, from_colour: int) -> np.ndarray:
+    """Block-interaction hops: from_colour 1 gives D_bw, 0 gives D_wb."""
+    U, psi = _c(U), _c(psi)
+    out = np.empty_like(psi)
+    L, B, bc = lat.arrays()
+    lib().oracle_apply_Dhop(_p(L), _p(B), _p(bc), kappa, _p(U), from_colour, _p(psi), _p(out))
+    return out
+
+
+def apply_Dee(lat: Lattice, U, kappa: float, psi, blocked: bool = False) -> np.ndarray:
+    """(1 - kappa^2 H_eo H_oe) psi_e, global or with in-block hops only."""
+    U, psi = _c(U), _c(psi)
+    out = np.empty_like(psi)
+    L, B, bc = lat.arrays()
+    lib().oracle_apply_Dee(_p(L), _p(B), _p(bc), kappa, _p(U), int(blocked), _p(psi), _p(out))
+    return out
+
+
+def colour_mask(lat: Lattice, colour: int) -> np.ndarray:
+    _, col, _ = lat.maps()
+    return col == colour
+
+
+# ----------------------------------------------------------------------------
+# Solvers ("one inversion for each factor", Sec. 4)
+
+
+class NoConvergence(RuntimeError):
+    pass
+
+
+def solve(lat: Lattice, U, kappa: float, b, op: str = "full", colour: int = 2, tol: float = 1e-13,
+          maxit: int = 100000):
+    """Solve A x = b, A = D (op 'full') or the Dirichlet blocks of one colour
+    (op 'block'), by CG on A A^+ y = b.  Returns (x, y, iterations, true
+    relative residual)."""
+    U, b = _c(U), _c(b)
+    x = np.empty_like(b)
+    y = np.empty_like(b)
+    res = ctypes.c_double()
+    L, B, bc = lat.arrays()
+    it = lib().oracle_cgne(_p(L), _p(B), _p(bc), kappa, _p(U), 0 if op == "full" else 1, colour, _p(b), _p(x),
+                           _p(y), tol, maxit, ctypes.byref(res))
+    if it < 0:
+        raise NoConvergence("oracle CGNE did not reach %g (residual %g)" % (tol, res.value))
+    return x, y, it, res.value
+
+
+def sap(lat: Lattice, U, kappa: float, eta, ncy: int, nmr: int) -> np.ndarray:
+    """Schwarz alternating procedure with ncy cycles and nmr even-odd MR
+    steps per block (Luscher hep-lat/0310048, cited in Secs. 1 and 3)."""
+    U, eta = _c(U), _c(eta)
+    x = np.empty_like(eta)
+    L, B, bc = lat.arrays()
+    lib().oracle_sap(_p(L), _p(B), _p(bc), kappa, _p(U), ncy, nmr, _p(eta), _p(x))
+    return x
+
+
+def schur_apply(lat: Lattice, U, kappa: float, eta, block_tol: float = 1e-14) -> np.ndarray:
+    """Dhat eta = eta - D_bb^-1 D_bw D_ww^-1 D_wb eta on black sites
+    (Sec. 3, eq. ddfactor).  White sites of the result are zero."""
+    black = colour_mask(lat, 0)
+    e = _c(eta).copy()
+    e[~black] = 0
+    t = apply_Dhop(lat, U, kappa, e, from_colour=0)            # D_wb eta   (white)
+    t, _, _, _ = solve(lat, U, kappa, t, "block", 1, block_tol)  # D_ww^-1   (white)
+    t = apply_Dhop(lat, U, kappa, t, from_colour=1)            # D_bw ...   (black)
+    t, _, _, _ = solve(lat, U, kappa, t, "block", 0, block_tol)  # D_bb^-1   (black)
+    out = e - t
+    out[~black] = 0
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Noise (Sec. 4: complex Gaussian noise, fresh for every factor)
+
+
+def philox4x64_10(counter, key) -> np.ndarray:
+    c = np.asarray(counter, dtype=np.uint64)
+    k = np.asarray(key, dtype=np.uint64)
+    out = np.empty(4, dtype=np.uint64)
+    lib().oracle_philox4x64_10(_p(c), _p(k), _p(out))
+    return out
+
+
+NOISE_Z2, NOISE_GAUSS = 0, 1
+
+
+def noise(lat: Lattice, kind: int, seed: int, step: int, k: int, support=None) -> np.ndarray:
+    """Noise vector for path step `step`, sample k; support is None (all
+    sites) or a boolean site mask."""
+    out = np.empty((lat.V, 4, 3), dtype=np.complex128)
+    L = _i4(lat.L)
+    m = None if support is None else np.ascontiguousarray(support, dtype=np.uint8)
+    lib().oracle_noise(_p(L), kind, ctypes.c_uint64(seed), step, k, None if m is None else _p(m), _p(out))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Path U_0 = U, ..., U_N = U' (Sec. 4, eq. param)
+
+
+def interpolate(U, Up, i: int, N: int) -> np.ndarray:
+    """U_i = exp((i/N) log W) U with W = U' U^+ per link (the geodesic from U
+    to U'; the paper only asks ||U_i - U_{i+1}|| ~ 1/N).  log W is taken from
+    the eigen-decomposition of W with principal angles in (-pi, pi]; if they
+    sum to +-2 pi, the largest (smallest) angle is moved by -+2 pi so that
+    log W is traceless and U_i stays in SU(3).  U_0 = U and U_N = U'
+    exactly; links with U' == U are copied."""
+    U = _c(U)
+    Up = _c(Up)
+    if i == 0:
+        return U.copy()
+    if i == N:
+        return Up.copy()
+    t = i / N
+    out = U.copy()
+    same = np.all((U == Up).reshape(U.shape[0], 4, 9), axis=2)
+    idx = np.nonzero(~same)
+    if len(idx[0]) == 0:
+        return out
+    u = U[idx]
+    W = Up[idx] @ np.conj(np.swapaxes(u, -1, -2))
+    lam, vec = np.linalg.eig(W)
+    th = np.angle(lam)
+    s = th.sum(axis=1)
+    j_hi = np.argmax(th, axis=1)
+    j_lo = np.argmin(th, axis=1)
+    r = np.arange(len(th))
+    fix_hi = s > np.pi
+    fix_lo = s < -np.pi
+    th[r[fix_hi], j_hi[fix_hi]] -= 2 * np.pi
+    th[r[fix_lo], j_lo[fix_lo]] += 2 * np.pi
+    ph = np.exp(1j * t * th)
+    Wt = vec @ (ph[:, :, None] * np.linalg.inv(vec))
+    out[idx] = Wt @ u
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Stochastic estimator (Sec. 4)
+
+OP_FULL, OP_SCHUR, OP_BLOCKS = 0, 1, 2
+
+
+def _dot(a, b) -> complex:
+    return complex(np.vdot(a.ravel(), b.ravel()))
+
+
+def sample(lat: Lattice, U0, U1, kappa: float, op: int, eta, tol: float = 1e-13, block_tol: float = 1e-14):
+    """One sample s = -eta^+ (M^+ M - 1) eta, M = X'^-1 X with X = D (FULL),
+    X = the Dirichlet blocks (BLOCKS, one value per block) or X = Dhat
+    (SCHUR), X built on U0 and X' on U1 (Sec. 4).
+
+    E over complex Gaussian eta of exp(s) is det(M^+ M)^-1 =
+    det(X'^+ X') / det(X^+ X), the ratio the acceptance step needs.
+
+    ||M eta||^2 = ||P z||^2 with z = A'^-1 y is evaluated as
+    ||P z~||^2 + 2 Re w^+ (y - A' z~), A'^+ w = P z~, which equals it up to
+    ||A'^-1 (y - A' z~)||^2 (both solves tight).
+    """
+    eta = _c(eta)
+    if op == OP_FULL:
+        y = apply_D(lat, U0, kappa, eta)
+        z, w, _, _ = solve(lat, U1, kappa, y, "full", 2, tol)
+        # with CGNE, z = A'^+ w exactly, so w solves A'^+ w = z
+        r = y - apply_D(lat, U1, kappa, z)
+        q = np.vdot(z, z).real + 2 * _dot(w, r).real
+        return float(np.vdot(eta, eta).real - q)
+    if op == OP_BLOCKS:
+        bid, _, _ = lat.maps()
+        y = apply_Dblock(lat, U0, kappa, eta, 2)
+        z, w, _, _ = solve(lat, U1, kappa, y, "block", 2, block_tol)
+        r = y - apply_Dblock(lat, U1, kappa, z, 2)
+        per_site = (np.abs(eta) ** 2).sum(axis=(1, 2)) - (np.abs(z) ** 2).sum(axis=(1, 2)) \
+            - 2 * np.real(np.conj(w) * r).sum(axis=(1, 2))
+        return np.bincount(bid, weights=per_site, minlength=lat.nblocks)
+    if op == OP_SCHUR:
+        black = colour_mask(lat, 0)
+        e = eta.copy()
+        e[~black] = 0
+        phi = schur_apply(lat, U0, kappa, e, block_tol)
+        y = apply_Dblock(lat, U1, kappa, phi, 0)               # A' Dhat eta, black
+        z, _, _, _ = solve(lat, U1, kappa, y, "full", 2, tol)  # D' z = [y; 0]
+        pz = z.copy()
+        pz[~black] = 0
+        # adjoint: D'^+ w = P z  <=>  D' (g5 w) = g5 P z
+        v, _, _, _ = solve(lat, U1, kappa, g5(pz), "full", 2, tol)
+        w = g5(v)
+        r = y - apply_D(lat, U1, kappa, z)
+        q = np.vdot(pz, pz).real + 2 * _dot(w, r).real
+        return float(np.vdot(e, e).real - q)
+    raise ValueError("unknown operator")
+
+
+def noise_support(lat: Lattice, op: int):
+    return colour_mask(lat, 0) if op == OP_SCHUR else None
+
+
+def log_mean_exp(s: np.ndarray, axis: int = 0) -> np.ndarray:
+    m = np.max(s, axis=axis, keepdims=True)
+    return np.squeeze(m, axis=axis) + np.log(np.mean(np.exp(s - m), axis=axis))
+
+
+def combine(samples: np.ndarray) -> np.ndarray:
+    """log Rhat = sum_i log( (1/K) sum_k exp(s_{i,k}) ) over the factors of
+    eq. param; samples[i, k] (or samples[i, k, block])."""
+    return np.sum(log_mean_exp(samples, axis=1), axis=0)
+
+
+def logdet_ratio(lat: Lattice, U, Up, kappa: float, op: int, n_steps: int, n_noise: int, kind: int, seed: int,
+                 tol: float = 1e-13, block_tol: float = 1e-14):
+    """Stochastic estimate of log det(X'^+ X') / det(X^+ X) along the path
+    U_0 = U ... U_N = U' (eq. param), one noise vector per factor and sample.
+    Returns (samples, log Rhat)."""
+    support = noise_support(lat, op)
+    shape = (n_steps, n_noise) + ((lat.nblocks,) if op == OP_BLOCKS else ())
+    samples = np.zeros(shape)
+    Ui = interpolate(U, Up, 0, n_steps)
+    for i in range(n_steps):
+        Ui1 = interpolate(U, Up, i + 1, n_steps)
+        for k in range(n_noise):
+            eta = noise(lat, kind, seed, i, k, support)
+            samples[i, k] = sample(lat, Ui, Ui1, kappa, op, eta, tol, block_tol)
+        Ui = Ui1
+    return samples, combine(samples)
+
+
+# ----------------------------------------------------------------------------
+# Dense forms (small lattices only)
+
+
+def dense(apply, n_sites: int, cols=None) -> np.ndarray:
+    """Dense matrix of a linear map on canonical spinor fields, column by
+    column (cols: subset of the 12*V unit vectors)."""
+    n = 12 * n_sites
+    cols = np.arange(n) if cols is None else np.asarray(cols)
+    M = np.empty((n, len(cols)), dtype=np.complex128)
+    e = np.zeros((n_sites, 4, 3), dtype=np.complex128)
+    flat = e.reshape(-1)
+    for j, c in enumerate(cols):
+        flat[c] = 1.0
+        M[:, j] = apply(e).reshape(-1)
+        flat[c] = 0.0
+    return M
+
+
+def log_abs_det(M: np.ndarray) -> float:
+    sign, ld = np.linalg.slogdet(M)
+    return float(ld)
+
+
+def exact_log_ratio(lat: Lattice, U, Up, kappa: float) -> float:
+    """log det(D'^+ D') - log det(D^+ D) = 2 (log|det D'| - log|det D|) by
+    dense LU (Sec. 2, two-step acceptance)."""
+    D0 = dense(lambda v: apply_D(lat, U, kappa, v), lat.V)
+    D1 = dense(lambda v: apply_D(lat, Up, kappa, v), lat.V)
+    return 2.0 * (log_abs_det(D1) - log_abs_det(D0))
+
+
+def site_dofs(mask: np.ndarray) -> np.ndarray:
+    """Indices of the 12 components of every site where mask is true."""
+    s = np.nonzero(mask)[0]
+    return (12 * s[:, None] + np.arange(12)[None, :]).ravel()
