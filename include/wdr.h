@@ -1,0 +1,228 @@
+/*
+ * wdr.h -- C ABI of the MI355X library for stochastic estimates of Wilson
+ * fermion-determinant ratios det(D'^+ D') / det(D^+ D) (Leder, Finkenrath,
+ * Knechtli, "Fermions as global correction in lattice QCD", Lattice 2011).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Lattice: extents L[0..3], site = x0 + L0*(x1 + L1*(x2 + L2*x3)); mu = 3 is
+ * "time".  Blocks (paper Sec. 3): extents B[0..3] dividing L, every B[mu]
+ * even; block colour = (sum_mu floor(x_mu / B_mu)) mod 2, black = 0.  Calls
+ * that use the block decomposition need L[mu]/B[mu] even in every direction
+ * (a 2-colourable checkerboard); otherwise they return WDR_EINVAL.
+ *
+ * Canonical fields (what callers pass): FP64 complex, interleaved re/im.
+ *   spinor  [site][spin 4][colour 3][2]        12 complex per site
+ *   gauge   [site][mu 4][row 3][col 3][2]      U_mu(x), the link x -> x+mu
+ * Operator (paper Sec. 5, "plain Wilson-Dirac operator"):
+ *   (D psi)(x) = psi(x) - kappa sum_mu [(1 - g_mu) U_mu(x) psi(x+mu)
+ *                                      + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu)]
+ * chiral basis, g_k = [[0, -i s_k], [i s_k, 0]] (mu = 0,1,2 -> k = 1,2,3),
+ * g_4 = [[0, 1], [1, 0]] (mu = 3), g_5 = diag(1, 1, -1, -1); a hop that wraps
+ * around the lattice in direction mu is multiplied by bc[mu] (+1 or -1).
+ *
+ * Memory: pointers named dev_* are device memory owned by the caller
+ * (e.g. a torch tensor's data pointer); host_* are host memory.  Contexts
+ * and gauge handles are owned by the library.  `stream` is a hipStream_t
+ * (NULL = the default stream); every call is ordered on it.  Calls that
+ * return host scalars (solve info, log ratios, samples to host) synchronise
+ * the stream before returning.
+ *
+ * Errors: no call throws.  Each returns a wdr_status; wdr_last_error()
+ * gives a message for the calling thread.  A solver that reaches its
+ * iteration limit returns WDR_ENOCONV with its outputs and info written.
+ */
+#ifndef WDR_H
+#define WDR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    WDR_OK = 0,
+    WDR_EINVAL = -1,   /* invalid argument (geometry, kappa, pointer, size) */
+    WDR_ENOMEM = -2,   /* device allocation failed */
+    WDR_EDEVICE = -3,  /* a HIP call failed */
+    WDR_ENOCONV = -4,  /* a solver stopped at max_iter above its tolerance */
+    WDR_ESTATE = -5    /* handles that do not belong together */
+} wdr_status;
+
+typedef enum { WDR_F64 = 0, WDR_F32 = 1, WDR_F16 = 2 } wdr_prec;
+typedef enum { WDR_NOISE_Z2 = 0, WDR_NOISE_GAUSS = 1 } wdr_noise_kind;
+
+/* which determinant ratio is estimated (paper Sec. 3 eq. 4step, Sec. 4):
+ * FULL   det(D'^+ D') / det(D^+ D)
+ * SCHUR  det(Dhat'^+ Dhat') / det(Dhat^+ Dhat), Dhat = 1 - D_bb^-1 D_bw D_ww^-1 D_wb
+ * BLOCKS det(D_b'^+ D_b') / det(D_b^+ D_b) for every block b separately */
+typedef enum { WDR_OP_FULL = 0, WDR_OP_SCHUR = 1, WDR_OP_BLOCKS = 2 } wdr_op;
+
+/* global solver: flexible GCR preconditioned by the Schwarz alternating
+ * procedure, or CG on the normal equations D D^+ y = b, x = D^+ y */
+typedef enum { WDR_SOLVER_FGCR_SAP = 0, WDR_SOLVER_CGNE = 1 } wdr_solver;
+
+typedef struct {
+    int32_t L[4];
+    int32_t B[4];
+    int32_t bc[4];
+} wdr_geom;
+
+typedef struct {
+    wdr_solver solver;
+    int32_t restart;     /* FGCR Krylov space before restart (16) */
+    int32_t max_iter;    /* outer iterations (FGCR) or CG iterations */
+    int32_t sap_cycles;  /* Schwarz cycles per preconditioner call (4) */
+    int32_t mr_steps;    /* minimal-residual steps per block and cycle (5) */
+    double tol;          /* ||b - D x|| / ||b|| of the global solves (1e-10) */
+    double block_tol;    /* largest per-block relative residual of the
+                            Dirichlet block solves (1e-13) */
+    double adj_tol;      /* adjoint solves of the second-order sample (1e-7) */
+    wdr_prec inner;      /* precision of SAP / inner iterations */
+} wdr_solver_params;
+
+typedef struct {
+    int32_t iters;        /* outer iterations of the last solve */
+    int32_t converged;    /* 1 if every solve met its tolerance */
+    double true_rel_resid;/* FP64 ||b - D x|| / ||b|| of the last solve */
+    double seconds;       /* wall time of the call */
+    int64_t total_iters;  /* summed over all solves of the call */
+} wdr_solve_info;
+
+typedef struct {
+    wdr_op op;
+    int32_t n_steps;   /* N of eq. param: factors U_i -> U_{i+1}, i < N */
+    int32_t n_noise;   /* independent noise vectors per factor */
+    wdr_noise_kind noise;
+    uint64_t seed;     /* Philox4x64-10 key (seed, 3) */
+    wdr_solver_params sp;
+} wdr_est_params;
+
+typedef struct wdr_ctx wdr_ctx;
+typedef struct wdr_gauge wdr_gauge;
+
+/* Message of the last error on the calling thread (never NULL). */
+const char *wdr_last_error(void);
+const char *wdr_status_str(wdr_status s);
+
+/* Default solver parameters (FGCR(16)+SAP(4 cycles, 5 MR), tol 1e-10,
+ * block_tol 1e-13, adj_tol 1e-7, FP32 inner). */
+void wdr_default_solver_params(wdr_solver_params *out);
+
+/* Create a context for one lattice geometry on HIP device `device`.  Builds
+ * the site ordering of Sec. 3 (black blocks first) and workspaces.
+ * EINVAL for non-positive or non-dividing extents, odd B[mu], bc not +-1. */
+wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out);
+wdr_status wdr_ctx_destroy(wdr_ctx *ctx);
+
+/* Number of sites V and block count of the context. */
+int64_t wdr_ctx_volume(const wdr_ctx *ctx);
+int32_t wdr_ctx_nblocks(const wdr_ctx *ctx);
+
+/* Geometry maps (Sec. 3), written to caller device buffers of V int32:
+ * block id (lexicographic block coordinates), block colour, site parity and
+ * position of the site in the black-first block ordering. Any may be NULL. */
+wdr_status wdr_site_maps(wdr_ctx *ctx, int32_t *dev_block_id, int32_t *dev_colour, int32_t *dev_parity,
+                         int32_t *dev_position, void *stream);
+
+/* Active-link mask (Sec. 3): for every block, the links with both ends in
+ * the region of in-block coordinates [lo, hi]^4 and at most one end on the
+ * boundary of that region (lo = 0, hi = B-1: whole blocks, Sec. 5; lo = 1,
+ * hi = 6 in 8^4 blocks: the 6^4 core of Sec. 6).  dev_mask: V*4 uint8,
+ * [site][mu] for the link x -> x+mu. */
+wdr_status wdr_active_links(wdr_ctx *ctx, int32_t lo, int32_t hi, uint8_t *dev_mask, void *stream);
+
+/* Upload a gauge field (canonical layout, dev_U device memory of V*4*9
+ * complex).  The handle keeps FP64 and FP32 copies in the internal layout
+ * with the boundary phases folded in. */
+wdr_status wdr_gauge_create(wdr_ctx *ctx, const double *dev_U, wdr_gauge **out, void *stream);
+wdr_status wdr_gauge_destroy(wdr_gauge *g);
+
+/* Path of eq. param: out = U_i = exp((i/N) log(U' U^+)) U link by link
+ * (geodesic with the traceless branch of the logarithm; U_0 = U and U_N = U'
+ * exactly; links with U' == U copied). dev_out: canonical, V*4*9 complex. */
+wdr_status wdr_interpolate(wdr_ctx *ctx, const double *dev_U, const double *dev_Up, int32_t i, int32_t N,
+                           double *dev_out, void *stream);
+
+/* Noise vector for path step `step`, sample k: for every site (all sites,
+ * or only black-block sites if black_only), the words of
+ * Philox4x64-10(counter = (site, step, k, j), key = (seed, 3)), j = 0..5,
+ * give complex Gaussian components sqrt(-ln u) exp(2 pi i u') with
+ * u = ((w >> 11) + 1/2) 2^-53 (E|eta|^2 = 1), or Z2 components
+ * 1 - 2 * bit a of the first word. dev_out: canonical spinor. */
+wdr_status wdr_noise(wdr_ctx *ctx, wdr_noise_kind kind, uint64_t seed, int32_t step, int32_t k, int32_t black_only,
+                     double *dev_out, void *stream);
+
+/* Internal layout (for callers that keep fields resident between calls):
+ * one spinor field in precision prec (F64: complex double, F32: complex
+ * float) occupies wdr_field_bytes(ctx, prec) bytes of device memory, ordered
+ * block by block (black blocks first, paper Sec. 3), even sites before odd
+ * sites inside a block, component-major inside a block.  wdr_pack converts
+ * a canonical FP64 spinor to it (rounding to prec), wdr_unpack back. */
+int64_t wdr_field_bytes(const wdr_ctx *ctx, wdr_prec prec);
+wdr_status wdr_pack(wdr_ctx *ctx, wdr_prec prec, const double *dev_canon, void *dev_internal, void *stream);
+wdr_status wdr_unpack(wdr_ctx *ctx, wdr_prec prec, const void *dev_internal, double *dev_canon, void *stream);
+
+/* out = D in on internal-layout fields of precision prec: exactly one
+ * stencil kernel launch on `stream`, no conversion. */
+wdr_status wdr_apply_D_internal(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec,
+                                const void *dev_in, void *dev_out, void *stream);
+
+/* out = D in (canonical spinors), computed in precision `prec`. */
+wdr_status wdr_apply_D(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, const double *dev_in,
+                       double *dev_out, void *stream);
+
+/* Dirichlet block operators (Sec. 3, eq. domdec): colour 0 gives D_bb,
+ * 1 gives D_ww, 2 both; zero on sites outside the selected blocks. */
+wdr_status wdr_apply_Dblock(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t colour,
+                            const double *dev_in, double *dev_out, void *stream);
+
+/* Block-interaction hops: from_colour 1 gives D_bw (white -> black sites),
+ * 0 gives D_wb; zero on the sites of colour from_colour. */
+wdr_status wdr_apply_Dhop(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t from_colour,
+                          const double *dev_in, double *dev_out, void *stream);
+
+/* Even-odd reduced operator (1 - kappa^2 H_eo H_oe) on even sites, with all
+ * hops (blocked = 0) or in-block hops only (blocked = 1); odd sites zero. */
+wdr_status wdr_apply_Dee(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t blocked,
+                         const double *dev_in, double *dev_out, void *stream);
+
+/* Schwarz alternating procedure: sp->sap_cycles cycles over black then white
+ * blocks, each block updated by sp->mr_steps even-odd minimal-residual steps,
+ * in precision sp->inner.  out approximates D^-1 in. */
+wdr_status wdr_sap(wdr_ctx *ctx, const wdr_gauge *U, double kappa, const wdr_solver_params *sp,
+                   const double *dev_in, double *dev_out, void *stream);
+
+/* Solve D x = b to sp->tol (true FP64 residual). */
+wdr_status wdr_solve(wdr_ctx *ctx, const wdr_gauge *U, double kappa, const wdr_solver_params *sp,
+                     const double *dev_b, double *dev_x, wdr_solve_info *host_info, void *stream);
+
+/* Solve the Dirichlet block systems of one colour (2: all blocks) to
+ * sp->block_tol: x = D_cc^-1 b on those blocks, zero elsewhere. */
+wdr_status wdr_block_solve(wdr_ctx *ctx, const wdr_gauge *U, double kappa, int32_t colour,
+                           const wdr_solver_params *sp, const double *dev_b, double *dev_x,
+                           wdr_solve_info *host_info, void *stream);
+
+/* Schur complement (Sec. 3, eq. ddfactor): out = Dhat in
+ * = in - D_bb^-1 D_bw D_ww^-1 D_wb in on black sites (white sites of in
+ * ignored, of out zero); block solves to sp->block_tol. */
+wdr_status wdr_apply_schur(wdr_ctx *ctx, const wdr_gauge *U, double kappa, const wdr_solver_params *sp,
+                           const double *dev_in, double *dev_out, void *stream);
+
+/* Stochastic estimate of the log determinant ratio for U -> U' (Sec. 4):
+ * for i < n_steps and k < n_noise, with U_i from the path of eq. param and
+ * eta_{i,k} from wdr_noise (black sites for SCHUR), the sample
+ *   s_{i,k} = -eta^+ (M_i^+ M_i - 1) eta,  M_i = X(U_{i+1})^-1 X(U_i),
+ * evaluated to second order in the solver residual.  host_samples receives
+ * n_steps*n_noise values ([i][k]), times nblocks for BLOCKS ([i][k][block]);
+ * *host_log_ratio = sum_i log((1/n_noise) sum_k exp(s_{i,k})) (for BLOCKS
+ * the sum over blocks).  Either output pointer may be NULL. */
+wdr_status wdr_logdet_ratio(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *Up, double kappa,
+                            const wdr_est_params *p, double *host_samples, double *host_log_ratio,
+                            wdr_solve_info *host_info, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WDR_H */

@@ -1,0 +1,413 @@
+// extern "C" entry points of include/wdr.h: argument checks, canonical <->
+// internal layout conversion, and dispatch to the drivers.
+#include <chrono>
+#include <cmath>
+
+#include "runtime.h"
+
+using namespace wdr;
+
+namespace {
+
+hipStream_t S(void *stream) { return (hipStream_t)stream; }
+
+wdr_status pre(wdr_ctx *c, const void *a, const void *b)
+{
+    if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
+    if (!a || !b) {
+        set_error("null field pointer");
+        return WDR_EINVAL;
+    }
+    if (hipSetDevice(c->device) != hipSuccess) {
+        set_error("hipSetDevice failed");
+        return WDR_EDEVICE;
+    }
+    return WDR_OK;
+}
+
+wdr_status check_gauge(const wdr_ctx *c, const wdr_gauge *U)
+{
+    if (!U) {
+        set_error("null gauge handle");
+        return WDR_EINVAL;
+    }
+    if (U->ctx != c) {
+        set_error("gauge handle belongs to another context");
+        return WDR_ESTATE;
+    }
+    return WDR_OK;
+}
+
+wdr_status check_kappa(double kappa)
+{
+    if (!(kappa > 0) || !std::isfinite(kappa)) {
+        set_error("kappa must be positive");
+        return WDR_EINVAL;
+    }
+    return WDR_OK;
+}
+
+wdr_status finish(hipStream_t s)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string("kernel launch failed: ") + hipGetErrorString(e));
+        return WDR_EDEVICE;
+    }
+    (void)s;
+    return WDR_OK;
+}
+
+// runs op(in_internal, out_internal) in precision T on canonical FP64 fields
+template <typename T, class F>
+wdr_status with_fields(wdr_ctx *c, const double *in, double *out, hipStream_t s, F &&op)
+{
+    const int prec = sizeof(T) == 8 ? WDR_F64 : WDR_F32;
+    Work a(c, field_bytes(c, prec)), b(c, field_bytes(c, prec));
+    if (!a.ok() || !b.ok()) return WDR_ENOMEM;
+    typedef typename C2<T>::type T2;
+    launch_pack_spinor<T>(c->g, reinterpret_cast<const double2 *>(in), a.as<T2>(), s);
+    launch_zero<T>(b.as<T2>(), field_n(c), s);
+    op(a.as<T2>(), b.as<T2>());
+    launch_unpack_spinor<T>(c->g, b.as<T2>(), reinterpret_cast<double2 *>(out), s);
+    return finish(s);
+}
+
+template <typename T> const typename C2<T>::type *links(const wdr_gauge *U);
+template <> const double2 *links<double>(const wdr_gauge *U) { return U->u64; }
+template <> const float2 *links<float>(const wdr_gauge *U) { return U->u32; }
+
+template <typename T>
+wdr_status stencil_call(wdr_ctx *c, const wdr_gauge *U, double kappa, int kind, int arg, const double *in,
+                        double *out, hipStream_t s)
+{
+    typedef typename C2<T>::type T2;
+    const Geo &g = c->g;
+    return with_fields<T>(c, in, out, s, [&](T2 *a, T2 *b) {
+        const T k = (T)kappa;
+        if (kind == 0) {  // D
+            launch_dslash<T>(g, HOPS_ALL, -1, 0, links<T>(U), a, a, b, k, 0, g.nblk, s);
+        } else if (kind == 1) {  // Dirichlet blocks of colour arg
+            int s0, n;
+            colour_slots(c, arg, s0, n);
+            launch_dslash<T>(g, HOPS_IN, -1, 0, links<T>(U), a, a, b, k, s0, n, s);
+        } else if (kind == 2) {  // hops from colour arg to the other colour
+            int s0, n;
+            colour_slots(c, 1 - arg, s0, n);
+            launch_dslash<T>(g, HOPS_CROSS, -1, 0, links<T>(U), a, nullptr, b, k, s0, n, s);
+        } else {  // even-odd reduced, blocked = arg
+            Work t(c, field_bytes(c, sizeof(T) == 8 ? WDR_F64 : WDR_F32));
+            const int hops = arg ? HOPS_IN : HOPS_ALL;
+            launch_dslash<T>(g, hops, 1, 0, links<T>(U), a, nullptr, t.as<T2>(), k, 0, g.nblk, s);
+            launch_dslash<T>(g, hops, 0, 0, links<T>(U), t.as<T2>(), a, b, (T)(-kappa), 0, g.nblk, s);
+        }
+    });
+}
+
+wdr_status stencil_entry(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr_prec prec, int kind, int arg,
+                         const double *in, double *out, void *stream)
+{
+    wdr_status e = pre(c, in, out);
+    if (e != WDR_OK) return e;
+    if ((e = check_gauge(c, U)) != WDR_OK) return e;
+    if ((e = check_kappa(kappa)) != WDR_OK) return e;
+    if ((kind == 1 || kind == 2) && (e = check_blocks_usable(c, false)) != WDR_OK) return e;
+    if (prec == WDR_F64) return stencil_call<double>(c, U, kappa, kind, arg, in, out, S(stream));
+    if (prec == WDR_F32) return stencil_call<float>(c, U, kappa, kind, arg, in, out, S(stream));
+    set_error("precision must be F64 or F32");
+    return WDR_EINVAL;
+}
+
+void fill_info(wdr_solve_info *info, const Stats &st, double secs)
+{
+    if (!info) return;
+    info->iters = st.iters;
+    info->converged = st.converged;
+    info->true_rel_resid = st.rel;
+    info->seconds = secs;
+    info->total_iters = st.total;
+}
+
+double now()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+wdr_status wdr_site_maps(wdr_ctx *c, int32_t *bid, int32_t *col, int32_t *par, int32_t *pos, void *stream)
+{
+    if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
+    WDR_HIP(hipSetDevice(c->device));
+    launch_site_maps(c->g, bid, col, par, pos, S(stream));
+    return finish(S(stream));
+}
+
+wdr_status wdr_active_links(wdr_ctx *c, int32_t lo, int32_t hi, uint8_t *mask, void *stream)
+{
+    if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
+    if (!mask) {
+        set_error("null mask");
+        return WDR_EINVAL;
+    }
+    for (int mu = 0; mu < 4; ++mu)
+        if (lo < 0 || hi >= c->g.B[mu] || hi - lo < 2) {
+            set_error("need 0 <= lo, hi - lo >= 2 and hi < B[mu]");
+            return WDR_EINVAL;
+        }
+    WDR_HIP(hipSetDevice(c->device));
+    launch_active_links(c->g, lo, hi, mask, S(stream));
+    return finish(S(stream));
+}
+
+wdr_status wdr_interpolate(wdr_ctx *c, const double *U, const double *Up, int32_t i, int32_t N, double *out,
+                           void *stream)
+{
+    wdr_status e = pre(c, U, out);
+    if (e != WDR_OK) return e;
+    if (!Up || N < 1 || i < 0 || i > N) {
+        set_error("need 0 <= i <= N, N >= 1 and non-null fields");
+        return WDR_EINVAL;
+    }
+    hipStream_t s = S(stream);
+    const size_t n = (size_t)c->g.V * 36;
+    if (i == 0 || i == N) {
+        WDR_HIP(hipMemcpyAsync(out, i == 0 ? U : Up, n * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        return WDR_OK;
+    }
+    Work a(c, n * sizeof(double2)), b(c, n * sizeof(double2)), o(c, n * sizeof(double2));
+    if (!a.ok() || !b.ok() || !o.ok()) return WDR_ENOMEM;
+    launch_pack_gauge<double>(c->g, c->geom.bc, reinterpret_cast<const double2 *>(U), a.as<double2>(), s);
+    launch_pack_gauge<double>(c->g, c->geom.bc, reinterpret_cast<const double2 *>(Up), b.as<double2>(), s);
+    launch_interpolate(c->g, a.as<double2>(), b.as<double2>(), (double)i / N, o.as<double2>(), s);
+    launch_unpack_gauge(c->g, c->geom.bc, o.as<double2>(), reinterpret_cast<double2 *>(out), s);
+    return finish(s);
+}
+
+wdr_status wdr_noise(wdr_ctx *c, wdr_noise_kind kind, uint64_t seed, int32_t step, int32_t k, int32_t black_only,
+                     double *out, void *stream)
+{
+    wdr_status e = pre(c, out, out);
+    if (e != WDR_OK) return e;
+    if (kind != WDR_NOISE_Z2 && kind != WDR_NOISE_GAUSS) {
+        set_error("unknown noise kind");
+        return WDR_EINVAL;
+    }
+    if (black_only && (e = check_blocks_usable(c, false)) != WDR_OK) return e;
+    Work a(c, field_bytes(c, WDR_F64));
+    if (!a.ok()) return WDR_ENOMEM;
+    launch_noise(c->g, kind, seed, step, k, black_only, a.as<double2>(), S(stream));
+    launch_unpack_spinor<double>(c->g, a.as<double2>(), reinterpret_cast<double2 *>(out), S(stream));
+    return finish(S(stream));
+}
+
+int64_t wdr_field_bytes(const wdr_ctx *c, wdr_prec prec)
+{
+    if (!c || (prec != WDR_F64 && prec != WDR_F32)) return 0;
+    return (int64_t)field_bytes(c, prec);
+}
+
+wdr_status wdr_pack(wdr_ctx *c, wdr_prec prec, const double *canon, void *internal, void *stream)
+{
+    wdr_status e = pre(c, canon, internal);
+    if (e != WDR_OK) return e;
+    if (prec == WDR_F64)
+        launch_pack_spinor<double>(c->g, reinterpret_cast<const double2 *>(canon), static_cast<double2 *>(internal),
+                                   S(stream));
+    else if (prec == WDR_F32)
+        launch_pack_spinor<float>(c->g, reinterpret_cast<const double2 *>(canon), static_cast<float2 *>(internal),
+                                  S(stream));
+    else {
+        set_error("precision must be F64 or F32");
+        return WDR_EINVAL;
+    }
+    return finish(S(stream));
+}
+
+wdr_status wdr_unpack(wdr_ctx *c, wdr_prec prec, const void *internal, double *canon, void *stream)
+{
+    wdr_status e = pre(c, internal, canon);
+    if (e != WDR_OK) return e;
+    if (prec == WDR_F64)
+        launch_unpack_spinor<double>(c->g, static_cast<const double2 *>(internal), reinterpret_cast<double2 *>(canon),
+                                     S(stream));
+    else if (prec == WDR_F32)
+        launch_unpack_spinor<float>(c->g, static_cast<const float2 *>(internal), reinterpret_cast<double2 *>(canon),
+                                    S(stream));
+    else {
+        set_error("precision must be F64 or F32");
+        return WDR_EINVAL;
+    }
+    return finish(S(stream));
+}
+
+wdr_status wdr_apply_D_internal(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr_prec prec, const void *in,
+                                void *out, void *stream)
+{
+    wdr_status e = pre(c, in, out);
+    if (e != WDR_OK) return e;
+    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
+    if (in == out) {
+        set_error("in and out must not alias");
+        return WDR_EINVAL;
+    }
+    const Geo &g = c->g;
+    if (prec == WDR_F64)
+        launch_dslash<double>(g, HOPS_ALL, -1, 0, U->u64, static_cast<const double2 *>(in),
+                              static_cast<const double2 *>(in), static_cast<double2 *>(out), kappa, 0, g.nblk,
+                              S(stream));
+    else if (prec == WDR_F32)
+        launch_dslash<float>(g, HOPS_ALL, -1, 0, U->u32, static_cast<const float2 *>(in),
+                             static_cast<const float2 *>(in), static_cast<float2 *>(out), (float)kappa, 0, g.nblk,
+                             S(stream));
+    else {
+        set_error("precision must be F64 or F32");
+        return WDR_EINVAL;
+    }
+    return finish(S(stream));
+}
+
+wdr_status wdr_apply_D(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr_prec prec, const double *in, double *out,
+                       void *stream)
+{
+    return stencil_entry(c, U, kappa, prec, 0, 0, in, out, stream);
+}
+
+wdr_status wdr_apply_Dblock(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t colour,
+                            const double *in, double *out, void *stream)
+{
+    if (colour < 0 || colour > 2) {
+        set_error("colour must be 0, 1 or 2");
+        return WDR_EINVAL;
+    }
+    return stencil_entry(c, U, kappa, prec, 1, colour, in, out, stream);
+}
+
+wdr_status wdr_apply_Dhop(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t from_colour,
+                          const double *in, double *out, void *stream)
+{
+    if (from_colour < 0 || from_colour > 1) {
+        set_error("from_colour must be 0 or 1");
+        return WDR_EINVAL;
+    }
+    return stencil_entry(c, U, kappa, prec, 2, from_colour, in, out, stream);
+}
+
+wdr_status wdr_apply_Dee(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t blocked,
+                         const double *in, double *out, void *stream)
+{
+    return stencil_entry(c, U, kappa, prec, 3, blocked ? 1 : 0, in, out, stream);
+}
+
+wdr_status wdr_sap(wdr_ctx *c, const wdr_gauge *U, double kappa, const wdr_solver_params *sp, const double *in,
+                   double *out, void *stream)
+{
+    wdr_status e = pre(c, in, out);
+    if (e != WDR_OK) return e;
+    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
+    if (!sp) {
+        set_error("null solver parameters");
+        return WDR_EINVAL;
+    }
+    wdr_solver_params p = *sp;
+    p.solver = WDR_SOLVER_FGCR_SAP;
+    if ((e = check_params(c, p, true)) != WDR_OK) return e;
+    wdr_status se = WDR_OK;
+    e = with_fields<double>(c, in, out, S(stream), [&](double2 *a, double2 *b) {
+        se = sap64(c, view(U), kappa, p, a, b, S(stream));
+    });
+    return e != WDR_OK ? e : se;
+}
+
+wdr_status wdr_solve(wdr_ctx *c, const wdr_gauge *U, double kappa, const wdr_solver_params *sp, const double *b,
+                     double *x, wdr_solve_info *info, void *stream)
+{
+    wdr_status e = pre(c, b, x);
+    if (e != WDR_OK) return e;
+    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
+    if (!sp) {
+        set_error("null solver parameters");
+        return WDR_EINVAL;
+    }
+    if ((e = check_params(c, *sp, false)) != WDR_OK) return e;
+    const double t0 = now();
+    Stats st;
+    wdr_status se = WDR_OK;
+    e = with_fields<double>(c, b, x, S(stream), [&](double2 *a, double2 *o) {
+        se = solve64(c, view(U), kappa, *sp, sp->tol, a, o, st, S(stream));
+    });
+    (void)hipStreamSynchronize(S(stream));
+    fill_info(info, st, now() - t0);
+    return e != WDR_OK ? e : se;
+}
+
+wdr_status wdr_block_solve(wdr_ctx *c, const wdr_gauge *U, double kappa, int32_t colour, const wdr_solver_params *sp,
+                           const double *b, double *x, wdr_solve_info *info, void *stream)
+{
+    wdr_status e = pre(c, b, x);
+    if (e != WDR_OK) return e;
+    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
+    if (!sp || colour < 0 || colour > 2) {
+        set_error("null solver parameters or colour not in 0..2");
+        return WDR_EINVAL;
+    }
+    if ((e = check_params(c, *sp, true)) != WDR_OK) return e;
+    const double t0 = now();
+    Stats st;
+    wdr_status se = WDR_OK;
+    e = with_fields<double>(c, b, x, S(stream), [&](double2 *a, double2 *o) {
+        se = block_solve64(c, view(U), kappa, colour, *sp, sp->block_tol, a, o, st, S(stream));
+    });
+    (void)hipStreamSynchronize(S(stream));
+    fill_info(info, st, now() - t0);
+    return e != WDR_OK ? e : se;
+}
+
+wdr_status wdr_apply_schur(wdr_ctx *c, const wdr_gauge *U, double kappa, const wdr_solver_params *sp,
+                           const double *in, double *out, void *stream)
+{
+    wdr_status e = pre(c, in, out);
+    if (e != WDR_OK) return e;
+    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
+    if (!sp) {
+        set_error("null solver parameters");
+        return WDR_EINVAL;
+    }
+    if ((e = check_params(c, *sp, true)) != WDR_OK) return e;
+    Stats st;
+    wdr_status se = WDR_OK;
+    e = with_fields<double>(c, in, out, S(stream), [&](double2 *a, double2 *o) {
+        // white sites of the input are ignored
+        launch_zero<double>(a + 12L * c->g.Vb * c->g.nblack, 12L * c->g.Vb * (c->g.nblk - c->g.nblack), S(stream));
+        se = schur64(c, view(U), kappa, *sp, a, o, st, S(stream));
+    });
+    return e != WDR_OK ? e : se;
+}
+
+wdr_status wdr_logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, double kappa,
+                            const wdr_est_params *p, double *samples, double *log_ratio, wdr_solve_info *info,
+                            void *stream)
+{
+    if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
+    wdr_status e;
+    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_gauge(c, Up)) != WDR_OK) return e;
+    if ((e = check_kappa(kappa)) != WDR_OK) return e;
+    if (!p || p->n_steps < 1 || p->n_noise < 1 || (p->op != WDR_OP_FULL && p->op != WDR_OP_SCHUR && p->op != WDR_OP_BLOCKS) ||
+        (p->noise != WDR_NOISE_Z2 && p->noise != WDR_NOISE_GAUSS)) {
+        set_error("invalid estimator parameters");
+        return WDR_EINVAL;
+    }
+    if ((e = check_params(c, p->sp, p->op != WDR_OP_FULL)) != WDR_OK) return e;
+    WDR_HIP(hipSetDevice(c->device));
+    const double t0 = now();
+    Stats st;
+    e = logdet_ratio(c, U, Up, kappa, *p, samples, log_ratio, st, S(stream));
+    (void)hipStreamSynchronize(S(stream));
+    fill_info(info, st, now() - t0);
+    if (e == WDR_OK) e = finish(S(stream));
+    return e;
+}
+
+}  // extern "C"

@@ -1,0 +1,161 @@
+// Noise vectors, geometry maps, active-link masks and the per-block
+// reduction of the stochastic sample.
+//
+// Noise (paper Sec. 4: a complex Gaussian vector, fresh for every factor of
+// eq. param): Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
+// counter (canonical site, path step, sample, j) and key (seed, 3).
+#include "stencil.h"
+
+namespace wdr {
+namespace {
+
+using namespace dev;
+
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
+{
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+}
+
+__device__ __forceinline__ long canon_of(const Geo &g, int slot, int l, int x[4])
+{
+    int b = g.slot_blk[slot];
+    int loc[4];
+    local_coords(g, l, loc);
+    for (int mu = 0; mu < 4; ++mu) {
+        x[mu] = (b % g.NB[mu]) * g.B[mu] + loc[mu];
+        b /= g.NB[mu];
+    }
+    return x[0] + (long)g.L[0] * (x[1] + (long)g.L[1] * (x[2] + (long)g.L[2] * x[3]));
+}
+
+// writes the internal-layout FP64 noise field
+__global__ __launch_bounds__(256) void k_noise(Geo g, int kind, uint64_t seed, uint32_t step, uint32_t k,
+                                               int black_only, double2 *__restrict__ out)
+{
+    const int l = blockIdx.x * 256 + threadIdx.x;
+    if (l >= g.Vb) return;
+    const int slot = blockIdx.y;
+    const long base = (long)slot * 12 * g.Vb + l;
+    if (black_only && slot >= g.nblack) {
+        for (int c = 0; c < 12; ++c) out[base + (long)c * g.Vb] = make_double2(0.0, 0.0);
+        return;
+    }
+    int x[4];
+    const uint64_t site = (uint64_t)canon_of(g, slot, l, x);
+    if (kind == WDR_NOISE_Z2) {
+        uint64_t c[4] = {site, step, k, 0};
+        philox4x64_10(c, seed, 3);
+        for (int a = 0; a < 12; ++a)
+            out[base + (long)a * g.Vb] = make_double2(1.0 - 2.0 * (double)((c[0] >> a) & 1ull), 0.0);
+        return;
+    }
+    for (int j = 0; j < 6; ++j) {
+        uint64_t c[4] = {site, step, k, (uint64_t)j};
+        philox4x64_10(c, seed, 3);
+        for (int h = 0; h < 2; ++h) {
+            const double u1 = ((double)(c[2 * h] >> 11) + 0.5) * 0x1p-53;
+            const double u2 = ((double)(c[2 * h + 1] >> 11) + 0.5) * 0x1p-53;
+            const double rad = sqrt(-log(u1));
+            double sn, cs;
+            sincos(2.0 * M_PI * u2, &sn, &cs);
+            out[base + (long)(2 * j + h) * g.Vb] = make_double2(rad * cs, rad * sn);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_site_maps(Geo g, int32_t *bid, int32_t *col, int32_t *par, int32_t *pos)
+{
+    const int l = blockIdx.x * 256 + threadIdx.x;
+    if (l >= g.Vb) return;
+    const int slot = blockIdx.y;
+    int x[4];
+    const long s = canon_of(g, slot, l, x);
+    if (bid) bid[s] = g.slot_blk[slot];
+    if (col) col[s] = slot >= g.nblack;
+    if (par) par[s] = (x[0] + x[1] + x[2] + x[3]) & 1;
+    if (pos) pos[s] = slot * g.Vb + l;
+}
+
+// link (x, mu) active: both ends in the region [lo, hi]^4 of in-block
+// coordinates, at most one end on its boundary (paper Sec. 3)
+__global__ __launch_bounds__(256) void k_active(Geo g, int lo, int hi, uint8_t *mask)
+{
+    const int l = blockIdx.x * 256 + threadIdx.x;
+    if (l >= g.Vb) return;
+    const int slot = blockIdx.y;
+    int x[4];
+    const long s = canon_of(g, slot, l, x);
+    int r[4];
+    local_coords(g, l, r);
+    for (int mu = 0; mu < 4; ++mu) {
+        bool ok = r[mu] >= lo && r[mu] + 1 <= hi;
+        for (int nu = 0; nu < 4; ++nu)
+            if (nu != mu) ok = ok && r[nu] > lo && r[nu] < hi;
+        mask[s * 4 + mu] = ok ? 1 : 0;
+    }
+}
+
+// per-slot sum of |eta|^2 - |z|^2 - 2 Re(conj(w) r); one workgroup per slot
+__global__ __launch_bounds__(256) void k_sample_terms(Geo g, const double2 *eta, const double2 *z, const double2 *w,
+                                                      const double2 *r, double *out, int slot0)
+{
+    __shared__ double sh[4];
+    const int slot = slot0 + blockIdx.x;
+    const long base = (long)slot * 12 * g.Vb;
+    const long n = 12L * g.Vb;
+    double acc = 0;
+    for (long i = threadIdx.x; i < n; i += 256) {
+        double2 e = eta[base + i];
+        double v = e.x * e.x + e.y * e.y;
+        if (z) {
+            double2 a = z[base + i];
+            v -= a.x * a.x + a.y * a.y;
+        }
+        if (w && r) {
+            double2 a = w[base + i], b = r[base + i];
+            v -= 2.0 * (a.x * b.x + a.y * b.y);
+        }
+        acc += v;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+}  // namespace
+
+void launch_noise(const Geo &g, int kind, uint64_t seed, int step, int k, int black_only, double2 *out, hipStream_t s)
+{
+    k_noise<<<dim3((g.Vb + 255) / 256, g.nblk), 256, 0, s>>>(g, kind, seed, (uint32_t)step, (uint32_t)k, black_only,
+                                                             out);
+}
+void launch_site_maps(const Geo &g, int32_t *bid, int32_t *col, int32_t *par, int32_t *pos, hipStream_t s)
+{
+    k_site_maps<<<dim3((g.Vb + 255) / 256, g.nblk), 256, 0, s>>>(g, bid, col, par, pos);
+}
+void launch_active_links(const Geo &g, int lo, int hi, uint8_t *mask, hipStream_t s)
+{
+    k_active<<<dim3((g.Vb + 255) / 256, g.nblk), 256, 0, s>>>(g, lo, hi, mask);
+}
+void launch_sample_terms(const Geo &g, const double2 *eta, const double2 *z, const double2 *w, const double2 *r,
+                         double *per_slot, int slot0, int nslots, hipStream_t s)
+{
+    if (nslots > 0) k_sample_terms<<<nslots, 256, 0, s>>>(g, eta, z, w, r, per_slot, slot0);
+}
+
+}  // namespace wdr

@@ -1,0 +1,312 @@
+// Contexts, geometry tables, workspace pool and gauge handles.
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "runtime.h"
+
+namespace wdr {
+
+static thread_local std::string g_last_error = "no error";
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *last_error() { return g_last_error.c_str(); }
+
+Work::Work(wdr_ctx *c, size_t bytes) : c_(c), bytes_(bytes), p_(nullptr)
+{
+    auto &fb = c->free_bufs;
+    for (size_t i = 0; i < fb.size(); ++i)
+        if (fb[i].bytes == bytes) {
+            p_ = fb[i].p;
+            fb.erase(fb.begin() + i);
+            return;
+        }
+    if (hipMalloc(&p_, bytes) != hipSuccess) {
+        p_ = nullptr;
+        set_error("workspace allocation of " + std::to_string(bytes) + " bytes failed");
+        return;
+    }
+    c->owned.push_back(p_);
+}
+
+Work::~Work()
+{
+    if (p_) c_->free_bufs.push_back({bytes_, p_});
+}
+
+wdr_status check_ctx(const wdr_ctx *c)
+{
+    if (!c) {
+        set_error("null context");
+        return WDR_EINVAL;
+    }
+    return WDR_OK;
+}
+
+wdr_status check_blocks_usable(const wdr_ctx *c, bool solver)
+{
+    if (!c->g.colourable) {
+        set_error("block operations need L[mu]/B[mu] even in every direction");
+        return WDR_EINVAL;
+    }
+    if (solver && c->g.Vb > 256) {
+        set_error("block solvers support blocks of at most 256 sites");
+        return WDR_EINVAL;
+    }
+    return WDR_OK;
+}
+
+wdr_status check_params(const wdr_ctx *c, const wdr_solver_params &sp, bool needs_blocks)
+{
+    if (!(sp.tol > 0) || !(sp.block_tol > 0) || !(sp.adj_tol > 0) || sp.max_iter <= 0) {
+        set_error("solver tolerances must be positive and max_iter >= 1");
+        return WDR_EINVAL;
+    }
+    if (sp.solver != WDR_SOLVER_FGCR_SAP && sp.solver != WDR_SOLVER_CGNE) {
+        set_error("unknown solver");
+        return WDR_EINVAL;
+    }
+    if (sp.inner != WDR_F64 && sp.inner != WDR_F32) {
+        set_error("inner precision must be F64 or F32");
+        return WDR_EINVAL;
+    }
+    if (sp.solver == WDR_SOLVER_FGCR_SAP || needs_blocks) {
+        if (sp.restart < 1 || sp.restart > 16 || sp.sap_cycles < 1 || sp.mr_steps < 1) {
+            set_error("FGCR restart must be in [1, 16], SAP cycles and MR steps >= 1");
+            return WDR_EINVAL;
+        }
+        wdr_status st = check_blocks_usable(c, true);
+        if (st != WDR_OK) return st;
+    }
+    return WDR_OK;
+}
+
+}  // namespace wdr
+
+using namespace wdr;
+
+extern "C" {
+
+const char *wdr_last_error(void) { return wdr::last_error(); }
+
+const char *wdr_status_str(wdr_status s)
+{
+    switch (s) {
+    case WDR_OK: return "ok";
+    case WDR_EINVAL: return "invalid argument";
+    case WDR_ENOMEM: return "out of device memory";
+    case WDR_EDEVICE: return "device error";
+    case WDR_ENOCONV: return "solver did not converge";
+    case WDR_ESTATE: return "handles do not belong together";
+    }
+    return "unknown status";
+}
+
+void wdr_default_solver_params(wdr_solver_params *out)
+{
+    if (!out) return;
+    out->solver = WDR_SOLVER_FGCR_SAP;
+    out->restart = 16;
+    out->max_iter = 2000;
+    out->sap_cycles = 4;
+    out->mr_steps = 5;
+    out->tol = 1e-10;
+    out->block_tol = 1e-13;
+    out->adj_tol = 1e-7;
+    out->inner = WDR_F32;
+}
+
+wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)
+{
+    if (!geom || !out) {
+        set_error("null argument");
+        return WDR_EINVAL;
+    }
+    *out = nullptr;
+    long V = 1, Vb = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        const int L = geom->L[mu], B = geom->B[mu];
+        if (L <= 0 || B <= 0 || L % B != 0 || B % 2 != 0 || B > 255) {
+            set_error("need 0 < B[mu] <= 255, B[mu] even and dividing L[mu]");
+            return WDR_EINVAL;
+        }
+        if (geom->bc[mu] != 1 && geom->bc[mu] != -1) {
+            set_error("bc[mu] must be +1 or -1");
+            return WDR_EINVAL;
+        }
+        V *= L;
+        Vb *= B;
+    }
+    if (Vb > 65535 || V > (1L << 30)) {
+        set_error("lattice or block too large");
+        return WDR_EINVAL;
+    }
+    int ndev = 0;
+    WDR_HIP(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) {
+        set_error("no such device");
+        return WDR_EINVAL;
+    }
+    WDR_HIP(hipSetDevice(device));
+
+    wdr_ctx *c = new wdr_ctx();
+    c->device = device;
+    c->geom = *geom;
+    Geo &g = c->g;
+    int nblk = 1, colourable = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+        g.L[mu] = geom->L[mu];
+        g.B[mu] = geom->B[mu];
+        g.NB[mu] = geom->L[mu] / geom->B[mu];
+        nblk *= g.NB[mu];
+        if (g.NB[mu] % 2) colourable = 0;
+    }
+    g.V = (int)V;
+    g.Vb = (int)Vb;
+    g.Vh = (int)Vb / 2;
+    g.nblk = nblk;
+    g.colourable = colourable;
+
+    // in-block order: even sites then odd sites, lexicographic within each
+    std::vector<uint32_t> loc_coord(Vb);
+    std::vector<uint16_t> loc_index(Vb);
+    {
+        int ne = 0, no = (int)Vb / 2;
+        for (int lex = 0; lex < Vb; ++lex) {
+            int x[4], r = lex;
+            for (int mu = 0; mu < 4; ++mu) {
+                x[mu] = r % g.B[mu];
+                r /= g.B[mu];
+            }
+            const int par = (x[0] + x[1] + x[2] + x[3]) & 1;
+            const int l = par ? no++ : ne++;
+            loc_coord[l] = (uint32_t)x[0] | ((uint32_t)x[1] << 8) | ((uint32_t)x[2] << 16) | ((uint32_t)x[3] << 24);
+            loc_index[lex] = (uint16_t)l;
+        }
+    }
+    // block slots: black blocks first (lexicographic), then white (paper Sec. 3)
+    std::vector<int32_t> slot_blk(nblk), slot_nbr(8L * nblk);
+    c->slot_of_block.assign(nblk, 0);
+    {
+        int nb = 0;
+        for (int colour = 0; colour < 2; ++colour)
+            for (int b = 0; b < nblk; ++b) {
+                int r = b, sum = 0;
+                for (int mu = 0; mu < 4; ++mu) {
+                    sum += r % g.NB[mu];
+                    r /= g.NB[mu];
+                }
+                if ((colourable ? (sum & 1) : 0) == colour) {
+                    c->slot_of_block[b] = nb;
+                    slot_blk[nb++] = b;
+                }
+            }
+        g.nblack = 0;
+        for (int b = 0; b < nblk; ++b) {
+            int r = b, sum = 0;
+            for (int mu = 0; mu < 4; ++mu) {
+                sum += r % g.NB[mu];
+                r /= g.NB[mu];
+            }
+            if (!colourable || (sum & 1) == 0) g.nblack++;
+        }
+        if (!colourable) g.nblack = nblk;
+        for (int s = 0; s < nblk; ++s) {
+            int n[4], r = slot_blk[s];
+            for (int mu = 0; mu < 4; ++mu) {
+                n[mu] = r % g.NB[mu];
+                r /= g.NB[mu];
+            }
+            for (int mu = 0; mu < 4; ++mu)
+                for (int d = 0; d < 2; ++d) {
+                    int m[4] = {n[0], n[1], n[2], n[3]};
+                    m[mu] = (m[mu] + (d == 0 ? 1 : g.NB[mu] - 1)) % g.NB[mu];
+                    const int bl = m[0] + g.NB[0] * (m[1] + g.NB[1] * (m[2] + g.NB[2] * m[3]));
+                    slot_nbr[8 * s + 2 * mu + d] = bl;  // block id for now, slot below
+                }
+        }
+        for (auto &v : slot_nbr) v = c->slot_of_block[v];
+    }
+
+    const size_t b1 = Vb * sizeof(uint32_t), b2 = Vb * sizeof(uint16_t), b3 = 8L * nblk * sizeof(int32_t),
+                 b4 = nblk * sizeof(int32_t);
+    const size_t o2 = (b1 + 255) & ~255ul, o3 = o2 + ((b2 + 255) & ~255ul), o4 = o3 + ((b3 + 255) & ~255ul);
+    const size_t total = o4 + b4;
+    if (hipMalloc(&c->tables, total) != hipSuccess || hipMalloc(&c->red, RED_SCRATCH * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->scal, SCAL_N * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&c->ptrs, PTRS_N * sizeof(void *)) != hipSuccess) {
+        set_error("context allocation failed");
+        wdr_ctx_destroy(c);
+        return WDR_ENOMEM;
+    }
+    char *t = static_cast<char *>(c->tables);
+    if (hipMemcpy(t, loc_coord.data(), b1, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t + o2, loc_index.data(), b2, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t + o3, slot_nbr.data(), b3, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t + o4, slot_blk.data(), b4, hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("context upload failed");
+        wdr_ctx_destroy(c);
+        return WDR_EDEVICE;
+    }
+    g.loc_coord = reinterpret_cast<const uint32_t *>(t);
+    g.loc_index = reinterpret_cast<const uint16_t *>(t + o2);
+    g.slot_nbr = reinterpret_cast<const int32_t *>(t + o3);
+    g.slot_blk = reinterpret_cast<const int32_t *>(t + o4);
+    *out = c;
+    return WDR_OK;
+}
+
+wdr_status wdr_ctx_destroy(wdr_ctx *c)
+{
+    if (!c) return WDR_OK;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    for (void *p : c->owned) hipFree(p);
+    if (c->tables) hipFree(c->tables);
+    if (c->red) hipFree(c->red);
+    if (c->scal) hipFree(c->scal);
+    if (c->ptrs) hipFree(c->ptrs);
+    delete c;
+    return WDR_OK;
+}
+
+int64_t wdr_ctx_volume(const wdr_ctx *c) { return c ? c->g.V : 0; }
+int32_t wdr_ctx_nblocks(const wdr_ctx *c) { return c ? c->g.nblk : 0; }
+
+wdr_status wdr_gauge_create(wdr_ctx *c, const double *dev_U, wdr_gauge **out, void *stream)
+{
+    if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
+    if (!dev_U || !out) {
+        set_error("null argument");
+        return WDR_EINVAL;
+    }
+    WDR_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    wdr_gauge *g = new wdr_gauge();
+    g->ctx = c;
+    g->device = c->device;
+    const size_t n = (size_t)c->g.V * 36;
+    if (hipMalloc(&g->u64, n * sizeof(double2)) != hipSuccess || hipMalloc(&g->u32, n * sizeof(float2)) != hipSuccess) {
+        if (g->u64) hipFree(g->u64);
+        delete g;
+        set_error("gauge allocation failed");
+        return WDR_ENOMEM;
+    }
+    launch_pack_gauge<double>(c->g, c->geom.bc, reinterpret_cast<const double2 *>(dev_U), g->u64, s);
+    launch_convert_gauge_f32(c->g, g->u64, g->u32, s);
+    WDR_HIP(hipGetLastError());
+    *out = g;
+    return WDR_OK;
+}
+
+wdr_status wdr_gauge_destroy(wdr_gauge *g)
+{
+    if (!g) return WDR_OK;
+    (void)hipSetDevice(g->device);
+    (void)hipDeviceSynchronize();
+    hipFree(g->u64);
+    hipFree(g->u32);
+    delete g;
+    return WDR_OK;
+}
+
+}  // extern "C"

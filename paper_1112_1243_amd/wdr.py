@@ -1,0 +1,299 @@
+"""Python binding of the HIP library ``libwdr.so`` (C ABI in include/wdr.h).
+
+Argument marshalling only: every step runs in the library's kernels.
+Fields are torch tensors on the GPU in the canonical layout:
+  spinors  complex128 [V, 4, 3]      gauge fields  complex128 [V, 4, 3, 3]
+and calls are ordered on torch's current HIP stream.  There is no CPU
+fallback: if the library is missing, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("WDR_LIB", os.path.join(_HERE, "libwdr.so"))
+
+# ---------------------------------------------------------------- constants (wdr.h)
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
+F64, F32, F16 = 0, 1, 2
+NOISE_Z2, NOISE_GAUSS = 0, 1
+OP_FULL, OP_SCHUR, OP_BLOCKS = 0, 1, 2
+SOLVER_FGCR_SAP, SOLVER_CGNE = 0, 1
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32 * 4), ("B", ctypes.c_int32 * 4), ("bc", ctypes.c_int32 * 4)]
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("sap_cycles", ctypes.c_int32), ("mr_steps", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("block_tol", ctypes.c_double), ("adj_tol", ctypes.c_double), ("inner", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("true_rel_resid", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("total_iters", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class EstParams(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("n_steps", ctypes.c_int32), ("n_noise", ctypes.c_int32),
+                ("noise", ctypes.c_int), ("seed", ctypes.c_uint64), ("sp", SolverParams)]
+
+
+class WdrError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("wdr status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libwdr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library %s is not built: run __graft_entry__.build() or "
+                               "python paper_1112_1243_amd/build.py" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+        L.wdr_last_error.restype = ctypes.c_char_p
+        L.wdr_status_str.restype = ctypes.c_char_p
+        L.wdr_status_str.argtypes = [ctypes.c_int]
+        L.wdr_default_solver_params.argtypes = [ctypes.POINTER(SolverParams)]
+        L.wdr_default_solver_params.restype = None
+        L.wdr_ctx_create.argtypes = [ctypes.POINTER(Geom), ctypes.c_int, ctypes.POINTER(P)]
+        L.wdr_ctx_destroy.argtypes = [P]
+        L.wdr_ctx_volume.argtypes = [P]
+        L.wdr_ctx_volume.restype = ctypes.c_int64
+        L.wdr_ctx_nblocks.argtypes = [P]
+        L.wdr_ctx_nblocks.restype = ctypes.c_int32
+        L.wdr_site_maps.argtypes = [P, P, P, P, P, P]
+        L.wdr_active_links.argtypes = [P, i32, i32, P, P]
+        L.wdr_gauge_create.argtypes = [P, P, ctypes.POINTER(P), P]
+        L.wdr_gauge_destroy.argtypes = [P]
+        L.wdr_interpolate.argtypes = [P, P, P, i32, i32, P, P]
+        L.wdr_noise.argtypes = [P, ctypes.c_int, ctypes.c_uint64, i32, i32, i32, P, P]
+        L.wdr_field_bytes.argtypes = [P, ctypes.c_int]
+        L.wdr_field_bytes.restype = ctypes.c_int64
+        L.wdr_pack.argtypes = [P, ctypes.c_int, P, P, P]
+        L.wdr_unpack.argtypes = [P, ctypes.c_int, P, P, P]
+        L.wdr_apply_D_internal.argtypes = [P, P, d, ctypes.c_int, P, P, P]
+        for f in ("wdr_apply_D",):
+            getattr(L, f).argtypes = [P, P, d, ctypes.c_int, P, P, P]
+        for f in ("wdr_apply_Dblock", "wdr_apply_Dhop", "wdr_apply_Dee"):
+            getattr(L, f).argtypes = [P, P, d, ctypes.c_int, i32, P, P, P]
+        L.wdr_sap.argtypes = [P, P, d, ctypes.POINTER(SolverParams), P, P, P]
+        L.wdr_solve.argtypes = [P, P, d, ctypes.POINTER(SolverParams), P, P, ctypes.POINTER(SolveInfo), P]
+        L.wdr_block_solve.argtypes = [P, P, d, i32, ctypes.POINTER(SolverParams), P, P, ctypes.POINTER(SolveInfo),
+                                      P]
+        L.wdr_apply_schur.argtypes = [P, P, d, ctypes.POINTER(SolverParams), P, P, P]
+        L.wdr_logdet_ratio.argtypes = [P, P, P, d, ctypes.POINTER(EstParams), P, P, ctypes.POINTER(SolveInfo), P]
+        _lib = L
+    return _lib
+
+
+def _check(status: int, allow=(OK,)):
+    if status not in allow:
+        raise WdrError(status, lib().wdr_last_error().decode())
+    return status
+
+
+def default_params(**kw) -> SolverParams:
+    p = SolverParams()
+    lib().wdr_default_solver_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _dev(t, shape, dtype_name="complex128"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a GPU torch tensor")
+    if str(t.dtype) != "torch." + dtype_name:
+        raise TypeError("expected dtype %s, got %s" % (dtype_name, t.dtype))
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor of shape %s, got %s" % (tuple(shape), tuple(t.shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Gauge:
+    ctx: "Context"
+    handle: ctypes.c_void_p
+
+    def __del__(self):
+        if self.handle and _lib is not None:
+            _lib.wdr_gauge_destroy(self.handle)
+            self.handle = None
+
+
+class Context:
+    """A lattice geometry (L, blocks B, boundary phases bc) on one device."""
+
+    def __init__(self, L, B, bc=(1, 1, 1, 1), device: int = 0):
+        g = Geom()
+        for mu in range(4):
+            g.L[mu], g.B[mu], g.bc[mu] = int(L[mu]), int(B[mu]), int(bc[mu])
+        h = ctypes.c_void_p()
+        _check(lib().wdr_ctx_create(ctypes.byref(g), device, ctypes.byref(h)))
+        self.handle = h
+        self.L, self.B, self.bc = tuple(L), tuple(B), tuple(bc)
+        self.V = int(lib().wdr_ctx_volume(h))
+        self.nblocks = int(lib().wdr_ctx_nblocks(h))
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _torch().cuda.synchronize()
+            lib().wdr_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- tensors
+    def _empty(self, *shape, dtype=None):
+        torch = _torch()
+        return torch.empty(*shape, dtype=dtype or torch.complex128, device="cuda:%d" % self.device)
+
+    def spinor_like(self):
+        return self._empty(self.V, 4, 3)
+
+    # ---- geometry
+    def site_maps(self):
+        torch = _torch()
+        out = [self._empty(self.V, dtype=torch.int32) for _ in range(4)]
+        _check(lib().wdr_site_maps(self.handle, *[ctypes.c_void_p(t.data_ptr()) for t in out], _stream()))
+        return out
+
+    def active_links(self, lo: int, hi: int):
+        torch = _torch()
+        m = self._empty(self.V, 4, dtype=torch.uint8)
+        _check(lib().wdr_active_links(self.handle, lo, hi, ctypes.c_void_p(m.data_ptr()), _stream()))
+        return m
+
+    # ---- gauge fields and path
+    def gauge(self, U) -> Gauge:
+        h = ctypes.c_void_p()
+        _check(lib().wdr_gauge_create(self.handle, _dev(U, (self.V, 4, 3, 3)), ctypes.byref(h), _stream()))
+        return Gauge(self, h)
+
+    def interpolate(self, U, Up, i: int, N: int):
+        out = self._empty(self.V, 4, 3, 3)
+        shp = (self.V, 4, 3, 3)
+        _check(lib().wdr_interpolate(self.handle, _dev(U, shp), _dev(Up, shp), i, N,
+                                     ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    # ---- noise and operators
+    def noise(self, kind: int, seed: int, step: int, k: int, black_only: bool = False):
+        out = self.spinor_like()
+        _check(lib().wdr_noise(self.handle, kind, ctypes.c_uint64(seed), step, k, int(black_only),
+                               ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def _op(self, fn, gauge: Gauge, kappa, psi, prec, *extra):
+        out = self.spinor_like()
+        _check(getattr(lib(), fn)(self.handle, gauge.handle, kappa, prec, *extra,
+                                  _dev(psi, (self.V, 4, 3)), ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    # ---- internal-layout fields (flat byte tensors owned by the caller)
+    def internal_field(self, prec=F64):
+        torch = _torch()
+        n = int(lib().wdr_field_bytes(self.handle, prec))
+        return self._empty(n, dtype=torch.uint8)
+
+    def pack(self, psi, prec=F64):
+        out = self.internal_field(prec)
+        _check(lib().wdr_pack(self.handle, prec, _dev(psi, (self.V, 4, 3)), ctypes.c_void_p(out.data_ptr()),
+                              _stream()))
+        return out
+
+    def unpack(self, f, prec=F64):
+        out = self.spinor_like()
+        _check(lib().wdr_unpack(self.handle, prec, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                _stream()))
+        return out
+
+    def apply_D_internal(self, gauge, kappa, fin, fout, prec=F64):
+        _check(lib().wdr_apply_D_internal(self.handle, gauge.handle, kappa, prec, ctypes.c_void_p(fin.data_ptr()),
+                                          ctypes.c_void_p(fout.data_ptr()), _stream()))
+        return fout
+
+    def apply_D(self, gauge, kappa, psi, prec=F64):
+        return self._op("wdr_apply_D", gauge, kappa, psi, prec)
+
+    def apply_Dblock(self, gauge, kappa, psi, colour, prec=F64):
+        return self._op("wdr_apply_Dblock", gauge, kappa, psi, prec, colour)
+
+    def apply_Dhop(self, gauge, kappa, psi, from_colour, prec=F64):
+        return self._op("wdr_apply_Dhop", gauge, kappa, psi, prec, from_colour)
+
+    def apply_Dee(self, gauge, kappa, psi, blocked=False, prec=F64):
+        return self._op("wdr_apply_Dee", gauge, kappa, psi, prec, int(blocked))
+
+    # ---- solvers
+    def sap(self, gauge, kappa, psi, params: SolverParams):
+        out = self.spinor_like()
+        _check(lib().wdr_sap(self.handle, gauge.handle, kappa, ctypes.byref(params), _dev(psi, (self.V, 4, 3)),
+                             ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def solve(self, gauge, kappa, b, params: SolverParams, allow_noconv=False):
+        out = self.spinor_like()
+        info = SolveInfo()
+        st = lib().wdr_solve(self.handle, gauge.handle, kappa, ctypes.byref(params), _dev(b, (self.V, 4, 3)),
+                             ctypes.c_void_p(out.data_ptr()), ctypes.byref(info), _stream())
+        _check(st, (OK, ENOCONV) if allow_noconv else (OK,))
+        return out, info
+
+    def block_solve(self, gauge, kappa, colour, b, params: SolverParams):
+        out = self.spinor_like()
+        info = SolveInfo()
+        _check(lib().wdr_block_solve(self.handle, gauge.handle, kappa, colour, ctypes.byref(params),
+                                     _dev(b, (self.V, 4, 3)), ctypes.c_void_p(out.data_ptr()), ctypes.byref(info),
+                                     _stream()))
+        return out, info
+
+    def schur(self, gauge, kappa, psi, params: SolverParams):
+        out = self.spinor_like()
+        _check(lib().wdr_apply_schur(self.handle, gauge.handle, kappa, ctypes.byref(params),
+                                     _dev(psi, (self.V, 4, 3)), ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def logdet_ratio(self, U: Gauge, Up: Gauge, kappa, op, n_steps, n_noise, noise, seed, params: SolverParams):
+        """Returns (samples [n_steps, n_noise] (x nblocks for BLOCKS), log Rhat, info)."""
+        ep = EstParams()
+        ep.op, ep.n_steps, ep.n_noise, ep.noise, ep.seed, ep.sp = op, n_steps, n_noise, noise, seed, params
+        shape = (n_steps, n_noise) + ((self.nblocks,) if op == OP_BLOCKS else ())
+        samples = np.zeros(shape, dtype=np.float64)
+        lr = ctypes.c_double()
+        info = SolveInfo()
+        _check(lib().wdr_logdet_ratio(self.handle, U.handle, Up.handle, kappa, ctypes.byref(ep),
+                                      samples.ctypes.data_as(ctypes.c_void_p), ctypes.byref(lr), ctypes.byref(info),
+                                      _stream()))
+        return samples, lr.value, info

@@ -1,0 +1,200 @@
+"""GPU parity of the geometry, noise, stencil, path and preconditioner calls
+against the FP64 oracle (calls go through the C ABI)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1112_1243_amd import synth
+from tests.gpu_util import dev, host, rel, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+# (L, B, bc): tiny blocks, 4^4 blocks with antiperiodic time, mixed shapes, and
+# 384-site blocks whose 256-lane tiles leave a ragged tail
+GEOMS = [
+    ((4, 4, 4, 4), (2, 2, 2, 2), (1, 1, 1, 1)),
+    ((8, 8, 8, 8), (4, 4, 4, 4), (1, 1, 1, -1)),
+    ((8, 4, 4, 8), (4, 2, 2, 4), (1, 1, -1, 1)),
+    ((8, 8, 12, 8), (4, 4, 6, 4), (1, 1, 1, 1)),
+]
+
+
+def _ctx(L, B, bc):
+    torch_cuda()
+    from paper_1112_1243_amd import wdr
+    say("ctx", L, B, bc)
+    return wdr.Context(L, B, bc)
+
+
+@pytest.fixture(scope="module", params=GEOMS, ids=lambda g: "L%s_B%s" % ("x".join(map(str, g[0])), "x".join(map(str, g[1]))))
+def case(request):
+    L, B, bc = request.param
+    lat = oracle.Lattice(L, B, bc)
+    ctx = _ctx(L, B, bc)
+    U = synth.gauge_field(L, 0.6, 101)
+    psi = synth.spinor(L, 102)
+    yield lat, ctx, U, ctx.gauge(dev(U)), psi
+    ctx.close()
+
+
+def test_site_maps(case):
+    lat, ctx, *_ = case
+    bid, col, par, pos = [host(t) for t in ctx.site_maps()]
+    obid, ocol, opar = lat.maps()
+    assert np.array_equal(bid, obid) and np.array_equal(col, ocol) and np.array_equal(par, opar)
+    perm = oracle.block_order(lat)
+    assert np.array_equal(perm[pos], np.arange(lat.V))
+
+
+@pytest.mark.parametrize("L,B,lo,hi", [((8, 8, 8, 8), (4, 4, 4, 4), 0, 3), ((16, 16, 16, 16), (8, 8, 8, 8), 1, 6),
+                                       ((8, 8, 8, 16), (4, 4, 4, 4), 0, 3)])
+def test_active_links(L, B, lo, hi):
+    from paper_1112_1243_amd import wdr
+    torch_cuda()
+    ctx = wdr.Context(L, B)
+    m = host(ctx.active_links(lo, hi)).astype(bool)
+    want = oracle.active_links(oracle.Lattice(L, B), lo, None if hi == B[0] - 1 else hi)
+    assert np.array_equal(m, want)
+    ctx.close()
+
+
+@pytest.mark.parametrize("kind", [oracle.NOISE_Z2, oracle.NOISE_GAUSS])
+@pytest.mark.parametrize("black", [False, True])
+def test_noise(case, kind, black):
+    lat, ctx, *_ = case
+    for step, k in ((0, 0), (3, 7)):
+        g = host(ctx.noise(kind, 1112124300, step, k, black_only=black))
+        o = oracle.noise(lat, kind, 1112124300, step, k, support=oracle.colour_mask(lat, 0) if black else None)
+        if kind == oracle.NOISE_Z2:
+            assert np.array_equal(g, o)
+        else:
+            assert np.abs(g - o).max() < 2e-15 * max(1.0, np.abs(o).max())
+
+
+def test_apply_D(case):
+    from paper_1112_1243_amd import wdr
+    lat, ctx, U, gU, psi = case
+    k = 0.137
+    want = oracle.apply_D(lat, U, k, psi)
+    g64 = host(ctx.apply_D(gU, k, dev(psi), wdr.F64))
+    g32 = host(ctx.apply_D(gU, k, dev(psi), wdr.F32))
+    say("D f64 rel", rel(g64, want), "f32 rel", rel(g32, want))
+    assert rel(g64, want) < 1e-14
+    assert rel(g32, want) < 2e-6
+
+
+def test_apply_block_parts(case):
+    from paper_1112_1243_amd import wdr
+    lat, ctx, U, gU, psi = case
+    k = 0.129
+    for colour in (0, 1, 2):
+        want = oracle.apply_Dblock(lat, U, k, psi, colour)
+        got = host(ctx.apply_Dblock(gU, k, dev(psi), colour, wdr.F64))
+        assert rel(got, want) < 1e-14
+        assert rel(host(ctx.apply_Dblock(gU, k, dev(psi), colour, wdr.F32)), want) < 2e-6
+    for fc in (0, 1):
+        want = oracle.apply_Dhop(lat, U, k, psi, fc)
+        got = host(ctx.apply_Dhop(gU, k, dev(psi), fc, wdr.F64))
+        assert rel(got, want) < 1e-14
+
+
+@pytest.mark.parametrize("blocked", [False, True])
+def test_apply_even_odd(case, blocked):
+    from paper_1112_1243_amd import wdr
+    lat, ctx, U, gU, psi = case
+    k = 0.141
+    want = oracle.apply_Dee(lat, U, k, psi, blocked)
+    for prec, tol in ((wdr.F64, 1e-14), (wdr.F32, 2e-6)):
+        got = host(ctx.apply_Dee(gU, k, dev(psi), blocked, prec))
+        assert rel(got, want) < tol
+
+
+@pytest.mark.parametrize("L", [(16, 16, 16, 16), (32, 32, 32, 32)])
+def test_apply_D_full_size(L):
+    """The stencil at the full sizes of the 16^4 and 32^4 workloads."""
+    from paper_1112_1243_amd import wdr
+    torch_cuda()
+    lat = oracle.Lattice(L, (4, 4, 4, 4))
+    ctx = wdr.Context(L, (4, 4, 4, 4))
+    U = synth.gauge_field(L, 0.2, 103)
+    psi = synth.spinor(L, 104)
+    gU = ctx.gauge(dev(U))
+    want = oracle.apply_D(lat, U, 0.155, psi)
+    assert rel(host(ctx.apply_D(gU, 0.155, dev(psi), wdr.F64)), want) < 1e-14
+    assert rel(host(ctx.apply_D(gU, 0.155, dev(psi), wdr.F32)), want) < 2e-6
+    del gU
+    ctx.close()
+
+
+def test_interpolate(case):
+    lat, ctx, U, _, _ = case
+    Up = synth.redraw(U, synth.bernoulli_links(lat.L, 0.3, 105), 0.6, 105)
+    dU, dUp = dev(U), dev(Up)
+    for i, N in ((0, 4), (1, 4), (3, 4), (4, 4), (2, 7)):
+        got = host(ctx.interpolate(dU, dUp, i, N))
+        want = oracle.interpolate(U, Up, i, N)
+        err = np.abs(got - want).max()
+        assert err < 1e-13, (i, N, err)
+        if i in (0, N):
+            assert np.array_equal(got, want)
+
+
+def test_sap_matches_oracle():
+    """Same algorithm (cycles, MR steps) in FP64 and FP32 against the oracle."""
+    from paper_1112_1243_amd import wdr
+    for L, B in (((4, 4, 4, 4), (2, 2, 2, 2)), ((8, 8, 8, 8), (4, 4, 4, 4))):
+        lat = oracle.Lattice(L, B)
+        ctx = _ctx(L, B, (1, 1, 1, 1))
+        U = synth.gauge_field(L, 0.5, 106)
+        eta = synth.spinor(L, 107)
+        gU = ctx.gauge(dev(U))
+        for ncy, nmr in ((1, 1), (2, 5), (4, 5)):
+            want = oracle.sap(lat, U, 0.135, eta, ncy, nmr)
+            for prec, tol in ((wdr.F64, 1e-12), (wdr.F32, 2e-5)):
+                p = wdr.default_params(sap_cycles=ncy, mr_steps=nmr, inner=prec)
+                got = host(ctx.sap(gU, 0.135, dev(eta), p))
+                say("sap", L, ncy, nmr, prec, rel(got, want))
+                assert rel(got, want) < tol
+        del gU
+        ctx.close()
+
+
+@pytest.mark.parametrize("inner", [0, 1])
+def test_block_solve(inner):
+    from paper_1112_1243_amd import wdr
+    L, B = (8, 8, 8, 8), (4, 4, 4, 4)
+    lat = oracle.Lattice(L, B)
+    ctx = _ctx(L, B, (1, 1, 1, 1))
+    U = synth.gauge_field(L, 0.5, 108)
+    b = synth.spinor(L, 109)
+    gU = ctx.gauge(dev(U))
+    p = wdr.default_params(inner=inner)
+    for colour in (0, 1, 2):
+        x, info = ctx.block_solve(gU, 0.135, colour, dev(b), p)
+        x = host(x)
+        bb = b.copy()
+        if colour < 2:
+            bb[~oracle.colour_mask(lat, colour)] = 0
+        want, _, _, _ = oracle.solve(lat, U, 0.135, bb, "block", colour, tol=1e-14)
+        say("block solve", colour, info.as_dict(), rel(x, want))
+        assert info.converged and info.true_rel_resid <= 1e-13
+        assert rel(x, want) < 1e-12
+    del gU
+    ctx.close()
+
+
+def test_schur():
+    from paper_1112_1243_amd import wdr
+    L, B = (8, 8, 8, 8), (4, 4, 4, 4)
+    lat = oracle.Lattice(L, B)
+    ctx = _ctx(L, B, (1, 1, 1, 1))
+    U = synth.gauge_field(L, 0.5, 110)
+    eta = synth.spinor(L, 111)
+    gU = ctx.gauge(dev(U))
+    got = host(ctx.schur(gU, 0.135, dev(eta), wdr.default_params()))
+    want = oracle.schur_apply(lat, U, 0.135, eta)
+    say("schur rel", rel(got, want))
+    assert rel(got, want) < 1e-12
+    assert np.all(got[~oracle.colour_mask(lat, 0)] == 0)
+    del gU
+    ctx.close()
