@@ -73,9 +73,9 @@ wdr_status with_fields(wdr_ctx *c, const double *in, double *out, hipStream_t s,
     return finish(s);
 }
 
-template <typename T> const typename C2<T>::type *links(const wdr_gauge *U);
-template <> const double2 *links<double>(const wdr_gauge *U) { return U->u64; }
-template <> const float2 *links<float>(const wdr_gauge *U) { return U->u32; }
+template <typename T> UTab<T> links(const wdr_gauge *U);
+template <> UTab<double> links<double>(const wdr_gauge *U) { return view(U).u64; }
+template <> UTab<float> links<float>(const wdr_gauge *U) { return view(U).u32; }
 
 template <typename T>
 wdr_status stencil_call(wdr_ctx *c, const wdr_gauge *U, double kappa, int kind, int arg, const double *in,
@@ -83,23 +83,25 @@ wdr_status stencil_call(wdr_ctx *c, const wdr_gauge *U, double kappa, int kind, 
 {
     typedef typename C2<T>::type T2;
     const Geo &g = c->g;
+    Sys one = all_sys(c, 1);
+    one.su3 = U->su3;
     return with_fields<T>(c, in, out, s, [&](T2 *a, T2 *b) {
         const T k = (T)kappa;
         if (kind == 0) {  // D
-            launch_dslash<T>(g, HOPS_ALL, -1, 0, links<T>(U), a, a, b, k, 0, g.nblk, s);
+            launch_dslash<T>(g, one, links<T>(U), HOPS_ALL, -1, 0, a, a, b, k, 0, g.nblk, s);
         } else if (kind == 1) {  // Dirichlet blocks of colour arg
             int s0, n;
             colour_slots(c, arg, s0, n);
-            launch_dslash<T>(g, HOPS_IN, -1, 0, links<T>(U), a, a, b, k, s0, n, s);
+            launch_dslash<T>(g, one, links<T>(U), HOPS_IN, -1, 0, a, a, b, k, s0, n, s);
         } else if (kind == 2) {  // hops from colour arg to the other colour
             int s0, n;
             colour_slots(c, 1 - arg, s0, n);
-            launch_dslash<T>(g, HOPS_CROSS, -1, 0, links<T>(U), a, nullptr, b, k, s0, n, s);
+            launch_dslash<T>(g, one, links<T>(U), HOPS_CROSS, -1, 0, a, nullptr, b, k, s0, n, s);
         } else {  // even-odd reduced, blocked = arg
             Work t(c, field_bytes(c, sizeof(T) == 8 ? WDR_F64 : WDR_F32));
             const int hops = arg ? HOPS_IN : HOPS_ALL;
-            launch_dslash<T>(g, hops, 1, 0, links<T>(U), a, nullptr, t.as<T2>(), k, 0, g.nblk, s);
-            launch_dslash<T>(g, hops, 0, 0, links<T>(U), t.as<T2>(), a, b, (T)(-kappa), 0, g.nblk, s);
+            launch_dslash<T>(g, one, links<T>(U), hops, 1, 0, a, nullptr, t.as<T2>(), k, 0, g.nblk, s);
+            launch_dslash<T>(g, one, links<T>(U), hops, 0, 0, t.as<T2>(), a, b, (T)(-kappa), 0, g.nblk, s);
         }
     });
 }
@@ -196,9 +198,12 @@ wdr_status wdr_noise(wdr_ctx *c, wdr_noise_kind kind, uint64_t seed, int32_t ste
         return WDR_EINVAL;
     }
     if (black_only && (e = check_blocks_usable(c, false)) != WDR_OK) return e;
-    Work a(c, field_bytes(c, WDR_F64));
-    if (!a.ok()) return WDR_ENOMEM;
-    launch_noise(c->g, kind, seed, step, k, black_only, a.as<double2>(), S(stream));
+    Work a(c, field_bytes(c, WDR_F64)), idx(c, 2 * sizeof(int32_t));
+    if (!a.ok() || !idx.ok()) return WDR_ENOMEM;
+    const int32_t sk[2] = {step, k};
+    WDR_HIP(hipMemcpyAsync(idx.as<void>(), sk, sizeof(sk), hipMemcpyHostToDevice, S(stream)));
+    launch_noise(c->g, all_sys(c, 1), kind, seed, idx.as<int32_t>(), idx.as<int32_t>() + 1, black_only,
+                 a.as<double2>(), S(stream));
     launch_unpack_spinor<double>(c->g, a.as<double2>(), reinterpret_cast<double2 *>(out), S(stream));
     return finish(S(stream));
 }
@@ -254,12 +259,14 @@ wdr_status wdr_apply_D_internal(wdr_ctx *c, const wdr_gauge *U, double kappa, wd
         return WDR_EINVAL;
     }
     const Geo &g = c->g;
+    Sys one = all_sys(c, 1);
+    one.su3 = U->su3;
     if (prec == WDR_F64)
-        launch_dslash<double>(g, HOPS_ALL, -1, 0, U->u64, static_cast<const double2 *>(in),
+        launch_dslash<double>(g, one, view(U).u64, HOPS_ALL, -1, 0, static_cast<const double2 *>(in),
                               static_cast<const double2 *>(in), static_cast<double2 *>(out), kappa, 0, g.nblk,
                               S(stream));
     else if (prec == WDR_F32)
-        launch_dslash<float>(g, HOPS_ALL, -1, 0, U->u32, static_cast<const float2 *>(in),
+        launch_dslash<float>(g, one, view(U).u32, HOPS_ALL, -1, 0, static_cast<const float2 *>(in),
                              static_cast<const float2 *>(in), static_cast<float2 *>(out), (float)kappa, 0, g.nblk,
                              S(stream));
     else {
@@ -316,7 +323,7 @@ wdr_status wdr_sap(wdr_ctx *c, const wdr_gauge *U, double kappa, const wdr_solve
     if ((e = check_params(c, p, true)) != WDR_OK) return e;
     wdr_status se = WDR_OK;
     e = with_fields<double>(c, in, out, S(stream), [&](double2 *a, double2 *b) {
-        se = sap64(c, view(U), kappa, p, a, b, S(stream));
+        se = sap64(c, all_sys(c, 1), view(U), kappa, p, a, b, S(stream));
     });
     return e != WDR_OK ? e : se;
 }
@@ -333,13 +340,13 @@ wdr_status wdr_solve(wdr_ctx *c, const wdr_gauge *U, double kappa, const wdr_sol
     }
     if ((e = check_params(c, *sp, false)) != WDR_OK) return e;
     const double t0 = now();
-    Stats st;
+    std::vector<Stats> st;
     wdr_status se = WDR_OK;
     e = with_fields<double>(c, b, x, S(stream), [&](double2 *a, double2 *o) {
-        se = solve64(c, view(U), kappa, *sp, sp->tol, a, o, st, S(stream));
+        se = solve64(c, 1, view(U), kappa, *sp, sp->tol, a, o, st, S(stream));
     });
     (void)hipStreamSynchronize(S(stream));
-    fill_info(info, st, now() - t0);
+    fill_info(info, summarize(st), now() - t0);
     return e != WDR_OK ? e : se;
 }
 
@@ -355,13 +362,13 @@ wdr_status wdr_block_solve(wdr_ctx *c, const wdr_gauge *U, double kappa, int32_t
     }
     if ((e = check_params(c, *sp, true)) != WDR_OK) return e;
     const double t0 = now();
-    Stats st;
+    std::vector<Stats> st;
     wdr_status se = WDR_OK;
     e = with_fields<double>(c, b, x, S(stream), [&](double2 *a, double2 *o) {
-        se = block_solve64(c, view(U), kappa, colour, *sp, sp->block_tol, a, o, st, S(stream));
+        se = block_solve64(c, 1, view(U), kappa, colour, *sp, sp->block_tol, a, o, st, S(stream));
     });
     (void)hipStreamSynchronize(S(stream));
-    fill_info(info, st, now() - t0);
+    fill_info(info, summarize(st), now() - t0);
     return e != WDR_OK ? e : se;
 }
 
@@ -376,12 +383,12 @@ wdr_status wdr_apply_schur(wdr_ctx *c, const wdr_gauge *U, double kappa, const w
         return WDR_EINVAL;
     }
     if ((e = check_params(c, *sp, true)) != WDR_OK) return e;
-    Stats st;
+    std::vector<Stats> st;
     wdr_status se = WDR_OK;
     e = with_fields<double>(c, in, out, S(stream), [&](double2 *a, double2 *o) {
         // white sites of the input are ignored
-        launch_zero<double>(a + 12L * c->g.Vb * c->g.nblack, 12L * c->g.Vb * (c->g.nblk - c->g.nblack), S(stream));
-        se = schur64(c, view(U), kappa, *sp, a, o, st, S(stream));
+        launch_keep_slots(c->g, all_sys(c, 1), a, 0, c->g.nblack, S(stream));
+        se = schur64(c, 1, view(U), kappa, *sp, a, o, st, S(stream));
     });
     return e != WDR_OK ? e : se;
 }

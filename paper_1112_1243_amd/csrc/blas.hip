@@ -1,10 +1,10 @@
-// BLAS-1 kernels and deterministic FP64 reductions.
+// BLAS-1 kernels and deterministic FP64 reductions over batches of fields.
 //
-// Reductions run in two passes with a fixed grid: every workgroup sums a
-// fixed, strided share of the elements in FP64 (wavefront shuffles, then
-// LDS across the 4 wavefronts), and one workgroup adds the partial sums in
-// a fixed order.  The result therefore does not depend on scheduling and is
-// bit-reproducible from run to run.
+// Reductions run in two passes with a fixed grid: workgroup (c, m) sums a
+// fixed, strided share of system m's elements in FP64 (wavefront shuffles,
+// then LDS across the 4 wavefronts), and one workgroup per system adds the
+// partial sums in a fixed order.  Results do not depend on scheduling and
+// are bit-reproducible from run to run.
 #include "ops.h"
 
 namespace wdr {
@@ -19,7 +19,7 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// sums v over the workgroup into lane 0 of wave 0; sh: 4 doubles of LDS
+// sums v over the workgroup into thread 0; sh: 4 doubles of LDS
 __device__ __forceinline__ double block_sum(double v, double *sh)
 {
     v = wave_sum(v);
@@ -37,45 +37,53 @@ template <typename T> __device__ __forceinline__ double2 toD(typename C2<T>::typ
     return make_double2((double)v.x, (double)v.y);
 }
 
-// partial[j * 2 * G + 2 * blk + {0,1}] = re/im of the workgroup's share of <v_j, y>
+__device__ __forceinline__ bool off(const int32_t *active, int m) { return active && !active[m]; }
+
+// partial[(m * nv + j) * 2G + 2c + {0,1}]
 template <typename T>
-__global__ __launch_bounds__(NT) void k_multidot_partial(const typename C2<T>::type *const *v, int m,
-                                                         const typename C2<T>::type *__restrict__ y, long n,
-                                                         double *partial)
+__global__ __launch_bounds__(NT) void k_multidot_partial(const int32_t *active, long n,
+                                                         const typename C2<T>::type *const *v, int nv,
+                                                         const typename C2<T>::type *__restrict__ y, double *partial)
 {
     __shared__ double sh[4];
-    const int G = gridDim.x;
-    for (int j = 0; j < m; ++j) {
-        const typename C2<T>::type *vj = v[j];
+    const int G = gridDim.x, m = blockIdx.y;
+    if (off(active, m)) return;
+    const typename C2<T>::type *ym = y + m * n;
+    for (int j = 0; j < nv; ++j) {
+        const typename C2<T>::type *vj = v[j] + m * n;
         double re = 0, im = 0;
         for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)G * NT) {
-            double2 a = toD<T>(vj[i]), b = toD<T>(y[i]);
+            const double2 a = toD<T>(vj[i]), b = toD<T>(ym[i]);
             re += a.x * b.x + a.y * b.y;
             im += a.x * b.y - a.y * b.x;
         }
         re = block_sum(re, sh);
         im = block_sum(im, sh);
         if (threadIdx.x == 0) {
-            partial[j * 2 * G + 2 * blockIdx.x] = re;
-            partial[j * 2 * G + 2 * blockIdx.x + 1] = im;
+            partial[((long)m * nv + j) * 2 * G + 2 * blockIdx.x] = re;
+            partial[((long)m * nv + j) * 2 * G + 2 * blockIdx.x + 1] = im;
         }
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_dot_partial(const typename C2<T>::type *__restrict__ a,
-                                                    const typename C2<T>::type *__restrict__ b, long n, int norm,
+__global__ __launch_bounds__(NT) void k_dot_partial(const int32_t *active, long n,
+                                                    const typename C2<T>::type *__restrict__ a,
+                                                    const typename C2<T>::type *__restrict__ b, int norm,
                                                     double *partial)
 {
     __shared__ double sh[4];
-    const int G = gridDim.x;
+    const int G = gridDim.x, m = blockIdx.y;
+    if (off(active, m)) return;
+    a += m * n;
+    b += m * n;
     double re = 0, im = 0;
     for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)G * NT) {
-        double2 x = toD<T>(a[i]);
+        const double2 x = toD<T>(a[i]);
         if (norm) {
             re += x.x * x.x + x.y * x.y;
         } else {
-            double2 y = toD<T>(b[i]);
+            const double2 y = toD<T>(b[i]);
             re += x.x * y.x + x.y * y.y;
             im += x.x * y.y - x.y * y.x;
         }
@@ -83,30 +91,34 @@ __global__ __launch_bounds__(NT) void k_dot_partial(const typename C2<T>::type *
     re = block_sum(re, sh);
     im = block_sum(im, sh);
     if (threadIdx.x == 0) {
-        partial[2 * blockIdx.x] = re;
-        partial[2 * blockIdx.x + 1] = im;
+        partial[(long)m * 2 * G + 2 * blockIdx.x] = re;
+        partial[(long)m * 2 * G + 2 * blockIdx.x + 1] = im;
     }
 }
 
-// out[j] = sum over G partials, fixed order (pairwise tree over lanes)
-__global__ __launch_bounds__(NT) void k_final(const double *partial, int G, int m, double2 *out)
+// out[m * ostride + j] = sum over the G partials, fixed order
+__global__ __launch_bounds__(NT) void k_final(const int32_t *active, const double *partial, int G, int nv,
+                                              double2 *out, int ostride)
 {
     __shared__ double sh[4];
-    for (int j = 0; j < m; ++j) {
+    const int m = blockIdx.x;
+    if (off(active, m)) return;
+    for (int j = 0; j < nv; ++j) {
+        const double *p = partial + ((long)m * nv + j) * 2 * G;
         double re = 0, im = 0;
         for (int i = threadIdx.x; i < G; i += NT) {
-            re += partial[j * 2 * G + 2 * i];
-            im += partial[j * 2 * G + 2 * i + 1];
+            re += p[2 * i];
+            im += p[2 * i + 1];
         }
         re = block_sum(re, sh);
         im = block_sum(im, sh);
-        if (threadIdx.x == 0) out[j] = make_double2(re, im);
+        if (threadIdx.x == 0) out[(long)m * ostride + j] = make_double2(re, im);
     }
 }
 
 int red_grid(long n)
 {
-    long g = (n + NT * 4 - 1) / (NT * 4);
+    long g = (n + NT * 8 - 1) / (NT * 8);
     if (g < 1) g = 1;
     if (g > RED_BLOCKS) g = RED_BLOCKS;
     return (int)g;
@@ -114,103 +126,132 @@ int red_grid(long n)
 
 template <typename TO, typename TI>
 __global__ __launch_bounds__(NT) void k_convert(const typename C2<TI>::type *__restrict__ a,
-                                                typename C2<TO>::type *__restrict__ out, long n)
+                                                typename C2<TO>::type *__restrict__ out, long total)
 {
     const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
-    typename C2<TI>::type v = a[i];
+    if (i >= total) return;
+    const typename C2<TI>::type v = a[i];
     typename C2<TO>::type w;
     w.x = (TO)v.x;
     w.y = (TO)v.y;
     out[i] = w;
 }
 
-template <typename T> __global__ __launch_bounds__(NT) void k_zero(typename C2<T>::type *a, long n)
+template <typename T> __global__ __launch_bounds__(NT) void k_zero(typename C2<T>::type *a, long total)
 {
     const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
+    if (i >= total) return;
     typename C2<T>::type z;
     z.x = 0;
     z.y = 0;
     a[i] = z;
 }
 
-__global__ __launch_bounds__(NT) void k_axpy_dev(const double2 *c, double f, const double2 *__restrict__ x,
-                                                 double2 *__restrict__ y, long n)
+// zero outside [lo, hi) of every field (element index within the field)
+__global__ __launch_bounds__(NT) void k_keep_range(double2 *f, long n, long total, long lo, long hi)
 {
     const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
-    const double cr = f * c->x, ci = f * c->y;
-    double2 a = x[i], b = y[i];
+    if (i >= total) return;
+    const long e = i % n;
+    if (e < lo || e >= hi) f[i] = make_double2(0.0, 0.0);
+}
+
+__global__ __launch_bounds__(NT) void k_axpy_dev(const int32_t *active, long n, long total, const double2 *c,
+                                                 int cstride, double f, const double2 *__restrict__ x,
+                                                 double2 *__restrict__ y)
+{
+    const long i = (long)blockIdx.x * NT + threadIdx.x;
+    if (i >= total) return;
+    const int m = (int)(i / n);
+    if (off(active, m)) return;
+    const double2 cm = c[(long)m * cstride];
+    const double cr = f * cm.x, ci = f * cm.y;
+    const double2 a = x[i];
+    double2 b = y[i];
     b.x += cr * a.x - ci * a.y;
     b.y += cr * a.y + ci * a.x;
     y[i] = b;
 }
 
-__global__ __launch_bounds__(NT) void k_multi_axpy(const double2 *c, double f, const double2 *const *v, int m,
-                                                   double2 *__restrict__ y, long n, int acc)
+__global__ __launch_bounds__(NT) void k_multi_axpy(const int32_t *active, long n, long total, const double2 *c,
+                                                   int cstride, double f, const double2 *const *v, int nv,
+                                                   const int32_t *cnt, double2 *__restrict__ y, int acc)
 {
     const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
+    if (i >= total) return;
+    const int m = (int)(i / n);
+    if (off(active, m)) return;
+    const int k = cnt ? cnt[m] : nv;
     double2 b = acc ? y[i] : make_double2(0.0, 0.0);
-    for (int j = 0; j < m; ++j) {
-        const double cr = f * c[j].x, ci = f * c[j].y;
-        double2 a = v[j][i];
+    for (int j = 0; j < k; ++j) {
+        const double2 cj = c[(long)m * cstride + j];
+        const double cr = f * cj.x, ci = f * cj.y;
+        const double2 a = v[j][i];
         b.x += cr * a.x - ci * a.y;
         b.y += cr * a.y + ci * a.x;
     }
     y[i] = b;
 }
 
-__global__ __launch_bounds__(NT) void k_scale_invsqrt(const double2 *nrm, double2 *y, long n)
+__global__ __launch_bounds__(NT) void k_scale_invsqrt(const int32_t *active, long n, long total, const double2 *nrm,
+                                                      int nstride, double2 *y)
 {
     const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
-    const double f = 1.0 / sqrt(nrm->x);
-    double2 v = y[i];
+    if (i >= total) return;
+    const int m = (int)(i / n);
+    if (off(active, m)) return;
+    const double f = 1.0 / sqrt(nrm[(long)m * nstride].x);
+    const double2 v = y[i];
     y[i] = make_double2(f * v.x, f * v.y);
 }
 
-__global__ __launch_bounds__(NT) void k_sub(const double2 *b, const double2 *a, double2 *r, long n)
+__global__ __launch_bounds__(NT) void k_sub(const int32_t *active, long n, long total, const double2 *b,
+                                            const double2 *a, double2 *r)
 {
     const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
-    double2 u = b[i], v = a[i];
+    if (i >= total) return;
+    if (off(active, (int)(i / n))) return;
+    const double2 u = b[i], v = a[i];
     r[i] = make_double2(u.x - v.x, u.y - v.y);
 }
 
-__global__ __launch_bounds__(NT) void k_axpby(double a, const double2 *x, double b, double2 *y, long n)
-{
-    const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
-    double2 u = x[i], v = y[i];
-    y[i] = make_double2(a * u.x + b * v.x, a * u.y + b * v.y);
-}
-
 template <typename T>
-__global__ __launch_bounds__(NT) void k_add_to64(const typename C2<T>::type *x, double2 *y, long n)
+__global__ __launch_bounds__(NT) void k_add_to64(const int32_t *active, long n, long total,
+                                                 const typename C2<T>::type *x, double2 *y)
 {
     const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= n) return;
-    typename C2<T>::type u = x[i];
-    double2 v = y[i];
+    if (i >= total) return;
+    if (off(active, (int)(i / n))) return;
+    const typename C2<T>::type u = x[i];
+    const double2 v = y[i];
     y[i] = make_double2(v.x + (double)u.x, v.y + (double)u.y);
 }
 
-// per-slot squared norm, one workgroup per slot
-__global__ __launch_bounds__(NT) void k_slot_norm2(Geo g, const double2 *a, double *out, int slot0)
+__global__ __launch_bounds__(NT) void k_copy_flagged(long n, long total, const int32_t *flag, const double2 *src,
+                                                     double2 *dst)
+{
+    const long i = (long)blockIdx.x * NT + threadIdx.x;
+    if (i >= total) return;
+    if (!flag[i / n]) return;
+    dst[i] = src[i];
+}
+
+// per-slot squared norm, workgroup (slot, m)
+__global__ __launch_bounds__(NT) void k_slot_norm2(Geo g, const int32_t *active, long n, const double2 *a,
+                                                   double *out, int slot0)
 {
     __shared__ double sh[4];
-    const int slot = slot0 + blockIdx.x;
-    const long base = (long)slot * 12 * g.Vb;
-    const long n = 12L * g.Vb;
+    const int slot = slot0 + blockIdx.x, m = blockIdx.y;
+    if (off(active, m)) return;
+    const long base = m * n + (long)slot * 12 * g.Vb;
+    const long cnt = 12L * g.Vb;
     double s = 0;
-    for (long i = threadIdx.x; i < n; i += NT) {
-        double2 v = a[base + i];
+    for (long i = threadIdx.x; i < cnt; i += NT) {
+        const double2 v = a[base + i];
         s += v.x * v.x + v.y * v.y;
     }
     s = block_sum(s, sh);
-    if (threadIdx.x == 0) out[blockIdx.x] = s;
+    if (threadIdx.x == 0) out[(long)m * g.nblk + slot] = s;
 }
 
 inline unsigned nblk(long n) { return (unsigned)((n + NT - 1) / NT); }
@@ -218,81 +259,96 @@ inline unsigned nblk(long n) { return (unsigned)((n + NT - 1) / NT); }
 }  // namespace
 
 template <typename T>
-void launch_multidot(const typename C2<T>::type *const *v_dev, int m, const typename C2<T>::type *y, long n,
-                     double *red, double2 *out, hipStream_t s)
+void launch_multidot(const Sys &sy, const T2<T> *const *v, int nv, const T2<T> *y, double *red, double2 *out,
+                     int ostride, hipStream_t s)
 {
-    const int G = red_grid(n);
-    k_multidot_partial<T><<<G, NT, 0, s>>>(v_dev, m, y, n, red);
-    k_final<<<1, NT, 0, s>>>(red, G, m, out);
+    if (nv <= 0) return;
+    const int G = red_grid(sy.n);
+    k_multidot_partial<T><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, v, nv, y, red);
+    k_final<<<sy.M, NT, 0, s>>>(sy.active, red, G, nv, out, ostride);
 }
 
 template <typename T>
-void launch_dot(const typename C2<T>::type *a, const typename C2<T>::type *b, long n, double *red, double2 *out,
-                hipStream_t s)
+void launch_dot(const Sys &sy, const T2<T> *a, const T2<T> *b, double *red, double2 *out, int ostride, hipStream_t s)
 {
-    const int G = red_grid(n);
-    k_dot_partial<T><<<G, NT, 0, s>>>(a, b, n, 0, red);
-    k_final<<<1, NT, 0, s>>>(red, G, 1, out);
+    const int G = red_grid(sy.n);
+    k_dot_partial<T><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, a, b, 0, red);
+    k_final<<<sy.M, NT, 0, s>>>(sy.active, red, G, 1, out, ostride);
 }
 
-template <typename T> void launch_norm2(const typename C2<T>::type *a, long n, double *red, double2 *out, hipStream_t s)
+template <typename T>
+void launch_norm2(const Sys &sy, const T2<T> *a, double *red, double2 *out, int ostride, hipStream_t s)
 {
-    const int G = red_grid(n);
-    k_dot_partial<T><<<G, NT, 0, s>>>(a, a, n, 1, red);
-    k_final<<<1, NT, 0, s>>>(red, G, 1, out);
+    const int G = red_grid(sy.n);
+    k_dot_partial<T><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, a, a, 1, red);
+    k_final<<<sy.M, NT, 0, s>>>(sy.active, red, G, 1, out, ostride);
 }
 
-template <typename TO, typename TI>
-void launch_convert(const typename C2<TI>::type *a, typename C2<TO>::type *out, long n, hipStream_t s)
+template <typename TO, typename TI> void launch_convert(const Sys &sy, const T2<TI> *a, T2<TO> *out, hipStream_t s)
 {
-    if (n > 0) k_convert<TO, TI><<<nblk(n), NT, 0, s>>>(a, out, n);
+    const long total = sy.n * sy.M;
+    if (total > 0) k_convert<TO, TI><<<nblk(total), NT, 0, s>>>(a, out, total);
 }
-template <typename T> void launch_zero(typename C2<T>::type *a, long n, hipStream_t s)
+template <typename T> void launch_zero(T2<T> *a, long n, hipStream_t s)
 {
     if (n > 0) k_zero<T><<<nblk(n), NT, 0, s>>>(a, n);
 }
-void launch_axpy_dev(const double2 *c, double f, const double2 *x, double2 *y, long n, hipStream_t s)
+void launch_keep_slots(const Geo &g, const Sys &sy, double2 *f, int slot0, int nslots, hipStream_t s)
 {
-    k_axpy_dev<<<nblk(n), NT, 0, s>>>(c, f, x, y, n);
+    const long per = 12L * g.Vb, total = sy.n * sy.M;
+    if (slot0 == 0 && nslots == g.nblk) return;
+    k_keep_range<<<nblk(total), NT, 0, s>>>(f, sy.n, total, per * slot0, per * (slot0 + nslots));
 }
-void launch_multi_axpy(const double2 *c, double f, const double2 *const *v_dev, int m, double2 *y, long n, int acc,
+void launch_axpy_dev(const Sys &sy, const double2 *c, int cstride, double f, const double2 *x, double2 *y,
+                     hipStream_t s)
+{
+    const long total = sy.n * sy.M;
+    k_axpy_dev<<<nblk(total), NT, 0, s>>>(sy.active, sy.n, total, c, cstride, f, x, y);
+}
+void launch_multi_axpy(const Sys &sy, const double2 *c, int cstride, double f, const double2 *const *v, int nv,
+                       const int32_t *cnt, double2 *y, int acc, hipStream_t s)
+{
+    const long total = sy.n * sy.M;
+    k_multi_axpy<<<nblk(total), NT, 0, s>>>(sy.active, sy.n, total, c, cstride, f, v, nv, cnt, y, acc);
+}
+void launch_scale_invsqrt(const Sys &sy, const double2 *nrm, int nstride, double2 *y, hipStream_t s)
+{
+    const long total = sy.n * sy.M;
+    k_scale_invsqrt<<<nblk(total), NT, 0, s>>>(sy.active, sy.n, total, nrm, nstride, y);
+}
+void launch_sub(const Sys &sy, const double2 *b, const double2 *a, double2 *r, hipStream_t s)
+{
+    const long total = sy.n * sy.M;
+    k_sub<<<nblk(total), NT, 0, s>>>(sy.active, sy.n, total, b, a, r);
+}
+template <typename T> void launch_add_to64(const Sys &sy, const T2<T> *x, double2 *y, hipStream_t s)
+{
+    const long total = sy.n * sy.M;
+    k_add_to64<T><<<nblk(total), NT, 0, s>>>(sy.active, sy.n, total, x, y);
+}
+void launch_copy_flagged(const Sys &sy, const int32_t *flag, const double2 *src, double2 *dst, hipStream_t s)
+{
+    const long total = sy.n * sy.M;
+    k_copy_flagged<<<nblk(total), NT, 0, s>>>(sy.n, total, flag, src, dst);
+}
+void launch_slot_norm2(const Geo &g, const Sys &sy, const double2 *a, double *out, int slot0, int nslots,
                        hipStream_t s)
 {
-    k_multi_axpy<<<nblk(n), NT, 0, s>>>(c, f, v_dev, m, y, n, acc);
-}
-void launch_scale_invsqrt(const double2 *nrm, double2 *y, long n, hipStream_t s)
-{
-    k_scale_invsqrt<<<nblk(n), NT, 0, s>>>(nrm, y, n);
-}
-void launch_sub(const double2 *b, const double2 *a, double2 *r, long n, hipStream_t s)
-{
-    k_sub<<<nblk(n), NT, 0, s>>>(b, a, r, n);
-}
-void launch_axpby(double a, const double2 *x, double b, double2 *y, long n, hipStream_t s)
-{
-    k_axpby<<<nblk(n), NT, 0, s>>>(a, x, b, y, n);
-}
-template <typename T> void launch_add_to64(const typename C2<T>::type *x, double2 *y, long n, hipStream_t s)
-{
-    k_add_to64<T><<<nblk(n), NT, 0, s>>>(x, y, n);
-}
-void launch_slot_norm2(const Geo &g, const double2 *a, double *out, int slot0, int nslots, hipStream_t s)
-{
-    if (nslots > 0) k_slot_norm2<<<nslots, NT, 0, s>>>(g, a, out, slot0);
+    if (nslots > 0) k_slot_norm2<<<dim3(nslots, sy.M), NT, 0, s>>>(g, sy.active, sy.n, a, out, slot0);
 }
 
 #define INST(T)                                                                                                  \
-    template void launch_multidot<T>(const C2<T>::type *const *, int, const C2<T>::type *, long, double *,       \
-                                     double2 *, hipStream_t);                                                    \
-    template void launch_dot<T>(const C2<T>::type *, const C2<T>::type *, long, double *, double2 *, hipStream_t); \
-    template void launch_norm2<T>(const C2<T>::type *, long, double *, double2 *, hipStream_t);                  \
-    template void launch_zero<T>(C2<T>::type *, long, hipStream_t);                                              \
-    template void launch_add_to64<T>(const C2<T>::type *, double2 *, long, hipStream_t);
+    template void launch_multidot<T>(const Sys &, const T2<T> *const *, int, const T2<T> *, double *, double2 *, \
+                                     int, hipStream_t);                                                          \
+    template void launch_dot<T>(const Sys &, const T2<T> *, const T2<T> *, double *, double2 *, int, hipStream_t); \
+    template void launch_norm2<T>(const Sys &, const T2<T> *, double *, double2 *, int, hipStream_t);            \
+    template void launch_zero<T>(T2<T> *, long, hipStream_t);                                                     \
+    template void launch_add_to64<T>(const Sys &, const T2<T> *, double2 *, hipStream_t);
 INST(double)
 INST(float)
 #undef INST
-template void launch_convert<double, float>(const float2 *, double2 *, long, hipStream_t);
-template void launch_convert<float, double>(const double2 *, float2 *, long, hipStream_t);
-template void launch_convert<double, double>(const double2 *, double2 *, long, hipStream_t);
+template void launch_convert<double, float>(const Sys &, const float2 *, double2 *, hipStream_t);
+template void launch_convert<float, double>(const Sys &, const double2 *, float2 *, hipStream_t);
+template void launch_convert<double, double>(const Sys &, const double2 *, double2 *, hipStream_t);
 
 }  // namespace wdr

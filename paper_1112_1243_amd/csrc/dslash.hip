@@ -31,17 +31,23 @@ template <typename T> struct G5Loader {
 };
 
 template <typename T, int HOPS>
-__global__ __launch_bounds__(256) void k_dslash(Geo g, int par, int dag, const typename C2<T>::type *__restrict__ U,
-                                                const typename C2<T>::type *__restrict__ in,
+__global__ __launch_bounds__(256) void k_dslash(Geo g, const int32_t *__restrict__ active, UTab<T> Utab, long n,
+                                                int par, int dag, const typename C2<T>::type *__restrict__ in,
                                                 const typename C2<T>::type *__restrict__ diag,
                                                 typename C2<T>::type *__restrict__ out, T kappa, int slot0)
 {
+    const int m = blockIdx.z;
+    if (active && !active[m]) return;
     const int Vb = g.Vb;
     const int nloc = par < 0 ? Vb : g.Vh;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= nloc) return;
     const int l = (par > 0 ? g.Vh : 0) + i;
     const int slot = slot0 + blockIdx.y;
+    const typename C2<T>::type *__restrict__ U = Utab[m];
+    in += m * n;
+    out += m * n;
+    if (diag) diag += m * n;
     int x[4];
     local_coords(g, l, x);
     spinor<T> acc;
@@ -57,6 +63,333 @@ __global__ __launch_bounds__(256) void k_dslash(Geo g, int par, int dag, const t
             if (diag) v = v + ld<T>(diag, base + (long)(3 * sp + a) * Vb);
             st<T>(out, base + (long)(3 * sp + a) * Vb, v);
         }
+}
+
+// ---------------------------------------------------------------- B^4 blocks
+// Direction-parallel stencil for B^4 blocks.  A workgroup takes 64 sites of
+// one block (grid.x = blocks x chunks of 64 sites) with four wavefronts:
+// wavefront w computes the two hops of direction mu = w for all 64 sites
+// (mu is uniform per wavefront, so its spin projection is specialised at
+// compile time) and issues the loads of both hops in one round trip.  The
+// four partial sums meet in LDS; wavefront w then adds spin w of the diagonal
+// term and writes spin w of the result (contiguous over the 64 sites).
+template <typename T, int HOPS, int B, int DAG>
+__global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__restrict__ active, UTab<T> Utab, long n,
+                                                    const int32_t *__restrict__ sched, int par, int chunks,
+                                                    const T2<T> *__restrict__ in, const T2<T> *__restrict__ diag,
+                                                    T2<T> *__restrict__ out, T kappa)
+{
+    typedef Cube<B> CB;
+    constexpr int Vb = CB::Vb;
+    __shared__ T2<T> part[4][12][64];  // [mu][colour-spin component][site]
+    const int m = blockIdx.y;
+    if (active && !active[m]) return;
+    const int slot = sched[blockIdx.x / chunks];
+    const int chunk = blockIdx.x % chunks;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int mu = __builtin_amdgcn_readfirstlane(w);
+    const int l = (par > 0 ? CB::Vh : 0) + chunk * 64 + lane;
+    const auto *Ug = as_global(Utab[m]);
+    const auto *ing = as_global(in + m * n);
+    int x[4];
+    CB::coords(l, x);
+    int nbr[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
+    // spin mu of the diagonal term, issued early
+    cx<T> dg[3] = {mk<T>(0, 0), mk<T>(0, 0), mk<T>(0, 0)};
+    const long obase = m * n + (long)slot * 12 * Vb + l;
+    if (diag) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dg[a] = ld<T>(diag, obase + (long)(3 * mu + a) * Vb);
+    }
+    spinor<T> acc;
+    zero(acc);
+    switch (mu) {
+    case 0: hop_dir_cube<T, HOPS, B, DAG, 0>(Ug, ing, slot, nbr, l, x, 0, acc); break;
+    case 1: hop_dir_cube<T, HOPS, B, DAG, 1>(Ug, ing, slot, nbr, l, x, 0, acc); break;
+    case 2: hop_dir_cube<T, HOPS, B, DAG, 2>(Ug, ing, slot, nbr, l, x, 0, acc); break;
+    default: hop_dir_cube<T, HOPS, B, DAG, 3>(Ug, ing, slot, nbr, l, x, 0, acc); break;
+    }
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) st<T>(&part[w][0][0], (3 * sp + a) * 64 + lane, acc.s[sp].c[a]);
+    __syncthreads();
+    // wavefront w sums spin w over the four directions
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int c = 3 * mu + a;
+        cx<T> v = ld<T>(&part[0][0][0], c * 64 + lane);
+#pragma unroll
+        for (int d = 1; d < 4; ++d) v = v + ld<T>(&part[d][0][0], c * 64 + lane);
+        v = scale(-kappa, v);
+        if (DAG && mu >= 2) v = neg(v);
+        st<T>(out, obase + (long)c * Vb, v + dg[a]);
+    }
+}
+
+template <typename T, int B>
+bool launch_cube(const Geo &g, const Sys &sy, UTab<T> U, int hops, int par, int dag, const T2<T> *in,
+                 const T2<T> *diag, T2<T> *out, T kappa, int slot0, int nslots, hipStream_t s)
+{
+    if (g.B[0] != B || g.B[1] != B || g.B[2] != B || g.B[3] != B) return false;
+    const int si = sched_index(g, slot0, nslots);
+    if (si < 0) return false;
+    const int nt = par < 0 ? Cube<B>::Vb : Cube<B>::Vh;
+    static_assert(Cube<B>::Vh % 64 == 0, "sites of one parity fill whole wavefronts");
+    const int chunks = nt / 64;
+    const dim3 grid(nslots * chunks, sy.M);
+    const int32_t *sc = g.sched[si];
+#define WDR_DIR(H, D) \
+    k_dslash_dir<T, H, B, D><<<grid, 256, 0, s>>>(g, sy.active, U, sy.n, sc, par, chunks, in, diag, out, kappa)
+    if (hops == HOPS_ALL) {
+        if (dag) WDR_DIR(HOPS_ALL, 1);
+        else WDR_DIR(HOPS_ALL, 0);
+    } else if (hops == HOPS_IN) {
+        if (dag) WDR_DIR(HOPS_IN, 1);
+        else WDR_DIR(HOPS_IN, 0);
+    } else {
+        if (dag) WDR_DIR(HOPS_CROSS, 1);
+        else WDR_DIR(HOPS_CROSS, 0);
+    }
+#undef WDR_DIR
+    return true;
+}
+
+// ---------------------------------------------------------------- LDS-staged stencil
+// The full operator for 4^4 blocks when every link is SU(3): a workgroup
+// stages its block's spinor and the first two rows of its links in LDS with
+// one coalesced pass, serves every in-block hop from LDS, and reads global
+// memory only for hops that leave the block.  The third row of a link is
+// conj(row0 x row1), times the boundary phase for a link that wraps around
+// the lattice (those have the phase folded in).  Each block's own data is
+// fetched from HBM exactly once per application.
+template <typename T> struct StencilLds {
+    T2<T> psi[12 * 256];
+    T2<T> lk[4 * 6 * 256];
+};
+
+template <typename T> __device__ __forceinline__ void rebuild_row2(su3<T> &u, T sign)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int a = (c + 1) % 3, b = (c + 2) % 3;
+        const cx<T> v = u.m[0][a] * u.m[1][b] - u.m[0][b] * u.m[1][a];
+        u.m[2][c] = mk<T>(sign * v.re, -sign * v.im);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_dslash_lds(Geo g, const int32_t *__restrict__ active, UTab<T> Utab, long n,
+                                                    const int32_t *__restrict__ sched, int dag,
+                                                    const T2<T> *__restrict__ in, const T2<T> *__restrict__ diag,
+                                                    T2<T> *__restrict__ out, T kappa)
+{
+    typedef Cube<4> CB;
+    constexpr int Vb = 256;
+    __shared__ StencilLds<T> S;
+    const int m = blockIdx.y;
+    if (active && !active[m]) return;
+    const int slot = sched[blockIdx.x];
+    const T2<T> *__restrict__ U = Utab[m];
+    const bool diag_in = diag == in;
+    in += m * n;
+    out += m * n;
+    if (diag) diag += m * n;
+    const int l = threadIdx.x;
+    const long sbase = (long)slot * 12 * Vb;
+    // stage the block: spinor (gamma5 applied for the adjoint) and two link rows
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        T2<T> v = in[sbase + (long)c * Vb + l];
+        if (dag && c >= 6) {
+            v.x = -v.x;
+            v.y = -v.y;
+        }
+        S.psi[c * Vb + l] = v;
+    }
+    {
+        const long ubase = (long)slot * 4 * 9 * Vb + l;
+        const auto *Ug = as_global(U);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int e = 0; e < 6; ++e) st<T>(S.lk, (mu * 6 + e) * Vb + l, ldg<T>(Ug, ubase + (long)(mu * 9 + e) * Vb));
+    }
+    int x[4], nb[4], nbr[8];
+    CB::coords(l, x);
+    {
+        int b = g.slot_blk[slot];
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            nb[mu] = b % g.NB[mu];
+            b /= g.NB[mu];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
+    __syncthreads();
+
+    auto lds_spinor = [&](int nl, spinor<T> &p) {
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) p.s[sp].c[a] = ld<T>(S.psi, (3 * sp + a) * Vb + nl);
+    };
+    auto glb_spinor = [&](int ns, int nl, spinor<T> &p) {
+        const long base = (long)ns * 12 * Vb + nl;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                cx<T> v = ld<T>(in, base + (long)(3 * sp + a) * Vb);
+                p.s[sp].c[a] = (dag && sp >= 2) ? neg(v) : v;
+            }
+    };
+
+    spinor<T> acc;
+    zero(acc);
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        {   // forward: (1 - g_mu) U_mu(x) psi(x + mu)
+            const bool inside = x[mu] + 1 < 4;
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            y[mu] = inside ? x[mu] + 1 : 0;
+            const int nl = CB::index(y);
+            spinor<T> p;
+            if (inside) lds_spinor(nl, p);
+            else glb_spinor(nbr[2 * mu], nl, p);
+            vec3<T> a0, a1;
+            A_dn(mu, p.s[2], p.s[3], a0, a1);
+            vec3<T> h0, h1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                h0.c[a] = p.s[0].c[a] - a0.c[a];
+                h1.c[a] = p.s[1].c[a] - a1.c[a];
+            }
+            su3<T> u;
+#pragma unroll
+            for (int e = 0; e < 6; ++e) u.m[e / 3][e % 3] = ld<T>(S.lk, (mu * 6 + e) * Vb + l);
+            rebuild_row2(u, (T)((!inside && nb[mu] == g.NB[mu] - 1) ? g.bc[mu] : 1));
+            const vec3<T> c0 = mul(u, h0), c1 = mul(u, h1);
+            vec3<T> d0, d1;
+            Adag_h(mu, c0, c1, d0, d1);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
+                acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
+                acc.s[2].c[a] = acc.s[2].c[a] - d0.c[a];
+                acc.s[3].c[a] = acc.s[3].c[a] - d1.c[a];
+            }
+        }
+        {   // backward: (1 + g_mu) U_mu(x - mu)^+ psi(x - mu)
+            const bool inside = x[mu] > 0;
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            y[mu] = inside ? x[mu] - 1 : 3;
+            const int nl = CB::index(y);
+            const int ns = inside ? slot : nbr[2 * mu + 1];
+            spinor<T> p;
+            su3<T> u;
+            if (inside) {
+                lds_spinor(nl, p);
+#pragma unroll
+                for (int e = 0; e < 6; ++e) u.m[e / 3][e % 3] = ld<T>(S.lk, (mu * 6 + e) * Vb + nl);
+            } else {
+                glb_spinor(ns, nl, p);
+                const long ub = ((long)ns * 4 + mu) * 9 * Vb + nl;
+                const auto *Ug = as_global(U);
+#pragma unroll
+                for (int e = 0; e < 6; ++e) u.m[e / 3][e % 3] = ldg<T>(Ug, ub + (long)e * Vb);
+            }
+            rebuild_row2(u, (T)((!inside && nb[mu] == 0) ? g.bc[mu] : 1));
+            vec3<T> a0, a1;
+            A_dn(mu, p.s[2], p.s[3], a0, a1);
+            vec3<T> h0, h1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                h0.c[a] = p.s[0].c[a] + a0.c[a];
+                h1.c[a] = p.s[1].c[a] + a1.c[a];
+            }
+            const vec3<T> c0 = mul_dag(u, h0), c1 = mul_dag(u, h1);
+            vec3<T> d0, d1;
+            Adag_h(mu, c0, c1, d0, d1);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
+                acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
+                acc.s[2].c[a] = acc.s[2].c[a] + d0.c[a];
+                acc.s[3].c[a] = acc.s[3].c[a] + d1.c[a];
+            }
+        }
+    }
+    const long base = sbase + l;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            cx<T> v = scale(-kappa, acc.s[sp].c[a]);
+            if (dag && sp >= 2) v = neg(v);
+            if (diag) {
+                cx<T> d;
+                if (diag_in) {
+                    d = ld<T>(S.psi, (3 * sp + a) * Vb + l);
+                    if (dag && sp >= 2) d = neg(d);
+                } else {
+                    d = ld<T>(diag, base + (long)(3 * sp + a) * Vb);
+                }
+                v = v + d;
+            }
+            st<T>(out, base + (long)(3 * sp + a) * Vb, v);
+        }
+}
+
+// SU(3) deviation of canonical FP64 links: per workgroup max into partial
+__global__ __launch_bounds__(256) void k_su3_dev(long nlinks, const double2 *__restrict__ U, double *partial)
+{
+    __shared__ double sh[256];
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    double dev = 0;
+    if (i < nlinks) {
+        su3<double> u;
+        for (int e = 0; e < 9; ++e) {
+            const double2 v = U[i * 9 + e];
+            u.m[e / 3][e % 3] = mk<double>(v.x, v.y);
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                cx<double> s = mk<double>(0, 0);
+                for (int k = 0; k < 3; ++k) s = s + u.m[a][k] * mk<double>(u.m[b][k].re, -u.m[b][k].im);
+                const double want = a == b ? 1.0 : 0.0;
+                dev = fmax(dev, fabs(s.re - want) + fabs(s.im));
+            }
+        const cx<double> det = u.m[0][0] * (u.m[1][1] * u.m[2][2] - u.m[1][2] * u.m[2][1]) -
+                               u.m[0][1] * (u.m[1][0] * u.m[2][2] - u.m[1][2] * u.m[2][0]) +
+                               u.m[0][2] * (u.m[1][0] * u.m[2][1] - u.m[1][1] * u.m[2][0]);
+        dev = fmax(dev, fabs(det.re - 1.0) + fabs(det.im));
+        if (!(dev == dev)) dev = 1e300;  // NaN
+    }
+    sh[threadIdx.x] = dev;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_max_final(int n, const double *partial, double *out)
+{
+    __shared__ double sh[256];
+    double v = 0;
+    for (int i = threadIdx.x; i < n; i += 256) v = fmax(v, partial[i]);
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
 }
 
 // ---------------------------------------------------------------- packing
@@ -160,40 +493,46 @@ __global__ __launch_bounds__(256) void k_convert_gauge_f32(long n, const double2
     out[i] = make_float2((float)v.x, (float)v.y);
 }
 
+// gamma_5 on every element of the batch: component c = (i / Vb) mod 12,
+// spins 2 and 3 are the components c >= 6
 template <typename T>
-__global__ __launch_bounds__(256) void k_g5(Geo g, const typename C2<T>::type *__restrict__ in,
-                                            typename C2<T>::type *__restrict__ out, int slot0)
+__global__ __launch_bounds__(256) void k_g5(long total, int Vb, const typename C2<T>::type *__restrict__ in,
+                                            typename C2<T>::type *__restrict__ out)
 {
-    const int l = blockIdx.x * 256 + threadIdx.x;
-    if (l >= g.Vb) return;
-    const long base = (long)(slot0 + blockIdx.y) * 12 * g.Vb + l;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        typename C2<T>::type v = in[base + (long)c * g.Vb];
-        if (c >= 6) {
-            v.x = -v.x;
-            v.y = -v.y;
-        }
-        out[base + (long)c * g.Vb] = v;
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    typename C2<T>::type v = in[i];
+    if ((i / Vb) % 12 >= 6) {
+        v.x = -v.x;
+        v.y = -v.y;
     }
+    out[i] = v;
 }
 
 }  // namespace
 
 template <typename T>
-void launch_dslash(const Geo &g, int hops, int par, int dag, const typename C2<T>::type *U,
-                   const typename C2<T>::type *in, const typename C2<T>::type *diag, typename C2<T>::type *out,
-                   T kappa, int slot0, int nslots, hipStream_t s)
+void launch_dslash(const Geo &g, const Sys &sy, UTab<T> U, int hops, int par, int dag, const T2<T> *in,
+                   const T2<T> *diag, T2<T> *out, T kappa, int slot0, int nslots, hipStream_t s)
 {
-    if (nslots <= 0) return;
+    if (nslots <= 0 || sy.M <= 0) return;
+    if (sy.su3 && hops == HOPS_ALL && par < 0 && g.B[0] == 4 && g.B[1] == 4 && g.B[2] == 4 && g.B[3] == 4) {
+        const int si = sched_index(g, slot0, nslots);
+        if (si >= 0) {
+            k_dslash_lds<T><<<dim3(nslots, sy.M), 256, 0, s>>>(g, sy.active, U, sy.n, g.sched[si], dag, in, diag, out,
+                                                               kappa);
+            return;
+        }
+    }
+    if (launch_cube<T, 4>(g, sy, U, hops, par, dag, in, diag, out, kappa, slot0, nslots, s)) return;
     const int nloc = par < 0 ? g.Vb : g.Vh;
-    dim3 grid((nloc + 255) / 256, nslots);
+    dim3 grid((nloc + 255) / 256, nslots, sy.M);
     if (hops == HOPS_ALL)
-        k_dslash<T, HOPS_ALL><<<grid, 256, 0, s>>>(g, par, dag, U, in, diag, out, kappa, slot0);
+        k_dslash<T, HOPS_ALL><<<grid, 256, 0, s>>>(g, sy.active, U, sy.n, par, dag, in, diag, out, kappa, slot0);
     else if (hops == HOPS_IN)
-        k_dslash<T, HOPS_IN><<<grid, 256, 0, s>>>(g, par, dag, U, in, diag, out, kappa, slot0);
+        k_dslash<T, HOPS_IN><<<grid, 256, 0, s>>>(g, sy.active, U, sy.n, par, dag, in, diag, out, kappa, slot0);
     else
-        k_dslash<T, HOPS_CROSS><<<grid, 256, 0, s>>>(g, par, dag, U, in, diag, out, kappa, slot0);
+        k_dslash<T, HOPS_CROSS><<<grid, 256, 0, s>>>(g, sy.active, U, sy.n, par, dag, in, diag, out, kappa, slot0);
 }
 
 template <typename T> void launch_pack_spinor(const Geo &g, const double2 *canon, typename C2<T>::type *out, hipStream_t s)
@@ -215,26 +554,32 @@ void launch_unpack_gauge(const Geo &g, const int bc[4], const double2 *in, doubl
     k_unpack_gauge<<<dim3((g.Vb + 255) / 256, g.nblk), 256, 0, s>>>(g, make_int4(bc[0], bc[1], bc[2], bc[3]), in,
                                                                     canon);
 }
+void launch_su3_deviation(const Geo &g, const double2 *U, double *partial, double *dev_out, hipStream_t s)
+{
+    const long nl = (long)g.V * 4;
+    const int nb = (int)((nl + 255) / 256);
+    k_su3_dev<<<nb, 256, 0, s>>>(nl, U, partial);
+    k_max_final<<<1, 256, 0, s>>>(nb, partial, dev_out);
+}
+
 void launch_convert_gauge_f32(const Geo &g, const double2 *in, float2 *out, hipStream_t s)
 {
     long n = (long)g.V * 36;
     k_convert_gauge_f32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, in, out);
 }
-template <typename T>
-void launch_g5(const Geo &g, const typename C2<T>::type *in, typename C2<T>::type *out, int slot0, int nslots,
-               hipStream_t s)
+template <typename T> void launch_g5(const Geo &g, const Sys &sy, const T2<T> *in, T2<T> *out, hipStream_t s)
 {
-    if (nslots <= 0) return;
-    k_g5<T><<<dim3((g.Vb + 255) / 256, nslots), 256, 0, s>>>(g, in, out, slot0);
+    const long total = sy.n * sy.M;
+    k_g5<T><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(total, g.Vb, in, out);
 }
 
 #define INST(T)                                                                                                  \
-    template void launch_dslash<T>(const Geo &, int, int, int, const C2<T>::type *, const C2<T>::type *,         \
-                                   const C2<T>::type *, C2<T>::type *, T, int, int, hipStream_t);                \
+    template void launch_dslash<T>(const Geo &, const Sys &, UTab<T>, int, int, int, const T2<T> *,              \
+                                   const T2<T> *, T2<T> *, T, int, int, hipStream_t);                            \
     template void launch_pack_spinor<T>(const Geo &, const double2 *, C2<T>::type *, hipStream_t);               \
     template void launch_unpack_spinor<T>(const Geo &, const C2<T>::type *, double2 *, hipStream_t);             \
     template void launch_pack_gauge<T>(const Geo &, const int *, const double2 *, C2<T>::type *, hipStream_t);   \
-    template void launch_g5<T>(const Geo &, const C2<T>::type *, C2<T>::type *, int, int, hipStream_t);
+    template void launch_g5<T>(const Geo &, const Sys &, const T2<T> *, T2<T> *, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

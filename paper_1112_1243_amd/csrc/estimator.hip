@@ -11,9 +11,13 @@
 // the solver residual r = y - A' z:
 //     ||P z||^2 = ||P z~||^2 + 2 Re w^+ r + O(|r|^2),   A'^+ w = P z~,
 // with the adjoint solve done as A' (g5 w) = g5 P z~ (gamma5-hermiticity).
+//
+// All (i, k) samples are independent given the path, so they are solved
+// together as one batch of systems (in chunks that fit a memory budget):
+// every kernel launch covers every sample of the chunk.
 #include <algorithm>
-#include <chrono>
 #include <cmath>
+#include <memory>
 #include <vector>
 
 #include "runtime.h"
@@ -23,24 +27,28 @@ namespace {
 
 struct TmpGauge {
     Work u64, u32;
-    TmpGauge(wdr_ctx *c) : u64(c, (size_t)c->g.V * 36 * sizeof(double2)), u32(c, (size_t)c->g.V * 36 * sizeof(float2)) {}
+    explicit TmpGauge(wdr_ctx *c)
+        : u64(c, (size_t)c->g.V * 36 * sizeof(double2)), u32(c, (size_t)c->g.V * 36 * sizeof(float2))
+    {
+    }
     bool ok() const { return u64.ok() && u32.ok(); }
-    GaugeView view() const { return {u64.as<double2>(), u32.as<float2>()}; }
 };
 
-// builds U_i of the path into dst
+// U_i of the path into dst
 void make_path_gauge(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, int i, int N, TmpGauge &dst, hipStream_t s)
 {
     const size_t n = (size_t)c->g.V * 36;
-    if (i == 0) {
-        hipMemcpyAsync(dst.u64.as<double2>(), U->u64, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
-    } else if (i == N) {
-        hipMemcpyAsync(dst.u64.as<double2>(), Up->u64, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
-    } else {
+    if (i == 0)
+        (void)hipMemcpyAsync(dst.u64.as<double2>(), U->u64, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
+    else if (i == N)
+        (void)hipMemcpyAsync(dst.u64.as<double2>(), Up->u64, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
+    else
         launch_interpolate(c->g, U->u64, Up->u64, (double)i / N, dst.u64.as<double2>(), s);
-    }
     launch_convert_gauge_f32(c->g, dst.u64.as<double2>(), dst.u32.as<float2>(), s);
 }
+
+// device memory budget for the fields of one chunk of samples
+constexpr double CHUNK_BYTES = 48e9;
 
 }  // namespace
 
@@ -49,106 +57,133 @@ wdr_status logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, dou
 {
     const auto &g = c->g;
     const long n = field_n(c);
-    const size_t fb = field_bytes(c, WDR_F64);
     const wdr_solver_params &sp = p.sp;
-    TmpGauge ga(c), gb(c);
-    Work eta(c, fb), y(c, fb), z(c, fb), w(c, fb), r(c, fb), t(c, fb), per(c, sizeof(double) * g.nblk);
-    if (!ga.ok() || !gb.ok() || !eta.ok() || !y.ok() || !z.ok() || !w.ok() || !r.ok() || !t.ok() || !per.ok())
-        return WDR_ENOMEM;
+    const int N = p.n_steps, K = p.n_noise, total = N * K;
     const int nout = p.op == WDR_OP_BLOCKS ? g.nblk : 1;
-    std::vector<double> samples((size_t)p.n_steps * p.n_noise * nout, 0.0);
-    std::vector<double> slot_vals(g.nblk);
+
+    // the path U_0 .. U_N
+    std::vector<std::unique_ptr<TmpGauge>> path;
+    for (int i = 0; i <= N; ++i) {
+        path.emplace_back(new TmpGauge(c));
+        if (!path.back()->ok()) return WDR_ENOMEM;
+        make_path_gauge(c, U, Up, i, N, *path.back(), s);
+    }
+
+    // chunk size: sample fields plus solver work space per system
+    const size_t fb = field_bytes(c, WDR_F64);
+    const int per_system = 8 + (sp.solver == WDR_SOLVER_FGCR_SAP ? 2 * sp.restart + 4 : 6);
+    const int Mmax = std::max(1, std::min(total, (int)(CHUNK_BYTES / ((double)per_system * fb))));
+
+    std::vector<double> samples((size_t)total * nout, 0.0);
+    std::vector<double> per((size_t)g.nblk * Mmax);
     int b0, bn;
     colour_slots(c, 0, b0, bn);
-    st = Stats();
+    std::vector<Stats> all_stats;
     wdr_status status = WDR_OK;
 
-    TmpGauge *cur = &ga, *nxt = &gb;
-    make_path_gauge(c, U, Up, 0, p.n_steps, *cur, s);
-    for (int i = 0; i < p.n_steps; ++i) {
-        make_path_gauge(c, U, Up, i + 1, p.n_steps, *nxt, s);
-        const GaugeView X = cur->view(), Xp = nxt->view();
-        for (int k = 0; k < p.n_noise; ++k) {
-            Stats s1;
-            wdr_status e = WDR_OK;
-            double2 *E = eta.as<double2>(), *Y = y.as<double2>(), *Z = z.as<double2>(), *W = w.as<double2>(),
-                    *R = r.as<double2>(), *Tm = t.as<double2>();
-            launch_noise(g, p.noise, p.seed, i, k, p.op == WDR_OP_SCHUR, E, s);
-            if (p.op == WDR_OP_FULL) {
-                apply_D64(c, X, kappa, E, Y, s);                                  // y = D eta
-                e = solve64(c, Xp, kappa, sp, sp.tol, Y, Z, s1, s);               // D' z = y
-                st.merge(s1);
-                if (e != WDR_OK && e != WDR_ENOCONV) return e;
+    for (int m0 = 0; m0 < total; m0 += Mmax) {
+        const int M = std::min(Mmax, total - m0);
+        const size_t fbm = fb * M;
+        Work eta(c, fbm), y(c, fbm), z(c, fbm), w(c, fbm), r(c, fbm), t(c, fbm), pr(c, sizeof(double) * g.nblk * M);
+        Work tabs(c, 4 * M * sizeof(void *)), idx(c, 2 * M * sizeof(int32_t));
+        if (!eta.ok() || !y.ok() || !z.ok() || !w.ok() || !r.ok() || !t.ok() || !pr.ok() || !tabs.ok() || !idx.ok())
+            return WDR_ENOMEM;
+        // per-system tables: X on U_i, X' on U_{i+1}; noise (step, sample)
+        std::vector<const void *> ht(4 * M);
+        std::vector<int32_t> hi(2 * M);
+        for (int j = 0; j < M; ++j) {
+            const int m = m0 + j, i = m / K, k = m % K;
+            ht[j] = path[i]->u64.as<void>();
+            ht[M + j] = path[i]->u32.as<void>();
+            ht[2 * M + j] = path[i + 1]->u64.as<void>();
+            ht[3 * M + j] = path[i + 1]->u32.as<void>();
+            hi[j] = i;
+            hi[M + j] = k;
+        }
+        WDR_HIP(hipMemcpyAsync(tabs.as<void>(), ht.data(), ht.size() * sizeof(void *), hipMemcpyHostToDevice, s));
+        WDR_HIP(hipMemcpyAsync(idx.as<void>(), hi.data(), hi.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        const void *const *tb = tabs.as<const void *const>();
+        // the geodesic path stays in SU(3) when both ends are
+        const int su3 = U->su3 && Up->su3;
+        const GaugeTab X{reinterpret_cast<UTab<double>>(tb), reinterpret_cast<UTab<float>>(tb + M), su3};
+        const GaugeTab Xp{reinterpret_cast<UTab<double>>(tb + 2 * M), reinterpret_cast<UTab<float>>(tb + 3 * M), su3};
+        const Sys all = all_sys(c, M);
+        double2 *E = eta.as<double2>(), *Y = y.as<double2>(), *Z = z.as<double2>(), *W = w.as<double2>(),
+                *R = r.as<double2>(), *Tm = t.as<double2>();
+        std::vector<Stats> s1;
+        // records the solve statistics (main solves only) and a non-convergence;
+        // returns false on a hard error, left in `hard`
+        wdr_status hard = WDR_OK;
+        auto take = [&](wdr_status e, bool main) -> bool {
+            if (main) all_stats.insert(all_stats.end(), s1.begin(), s1.end());
+            if (e == WDR_ENOCONV) status = e;
+            if (e != WDR_OK && e != WDR_ENOCONV) hard = e;
+            return e == WDR_OK || e == WDR_ENOCONV;
+        };
+
+        launch_noise(g, all, p.noise, p.seed, idx.as<int32_t>(), idx.as<int32_t>() + M, p.op == WDR_OP_SCHUR, E, s);
+        if (p.op == WDR_OP_FULL) {
+            apply_D64(c, all, X, kappa, E, Y, s);                                          // y = D eta
+            if (!take(solve64(c, M, Xp, kappa, sp, sp.tol, Y, Z, s1, s), true)) return hard;   // D' z = y
+            launch_g5<double>(g, all, Z, Tm, s);                                           // D' v = g5 z
+            if (!take(solve64(c, M, Xp, kappa, sp, sp.adj_tol, Tm, W, s1, s), false)) return hard;
+            launch_g5<double>(g, all, W, W, s);                                            // w = g5 v
+            apply_D64(c, all, Xp, kappa, Z, Tm, s);
+            launch_sub(all, Y, Tm, R, s);                                                  // r = y - D' z
+        } else if (p.op == WDR_OP_BLOCKS) {
+            launch_dslash<double>(g, all, X.u64, HOPS_IN, -1, 0, E, E, Y, kappa, 0, g.nblk, s);  // y = D_blk eta
+            if (!take(block_solve64(c, M, Xp, kappa, 2, sp, sp.block_tol, Y, Z, s1, s), true)) return hard;
+            launch_g5<double>(g, all, Z, Tm, s);
+            if (!take(block_solve64(c, M, Xp, kappa, 2, sp, sp.block_tol, Tm, W, s1, s), false)) return hard;
+            launch_g5<double>(g, all, W, W, s);
+            launch_dslash<double>(g, all, Xp.u64, HOPS_IN, -1, 0, Z, Z, Tm, kappa, 0, g.nblk, s);
+            launch_sub(all, Y, Tm, R, s);
+        } else {  // SCHUR
+            wdr_status e = schur64(c, M, X, kappa, sp, E, Tm, s1, s);                     // Dhat eta (black)
+            if (e != WDR_OK) {
                 if (e == WDR_ENOCONV) status = e;
-                launch_g5<double>(g, Z, Tm, 0, g.nblk, s);                         // D' v = g5 z
-                e = solve64(c, Xp, kappa, sp, sp.adj_tol, Tm, W, s1, s);
-                st.total += s1.total;
-                if (e != WDR_OK && e != WDR_ENOCONV) return e;
-                if (e == WDR_ENOCONV) status = e;
-                launch_g5<double>(g, W, W, 0, g.nblk, s);                          // w = g5 v
-                apply_D64(c, Xp, kappa, Z, Tm, s);
-                launch_sub(Y, Tm, R, n, s);                                        // r = y - D' z
-            } else if (p.op == WDR_OP_BLOCKS) {
-                launch_dslash<double>(g, HOPS_IN, -1, 0, X.u64, E, E, Y, kappa, 0, g.nblk, s);  // y = D_blk eta
-                e = block_solve64(c, Xp, kappa, 2, sp, sp.block_tol, Y, Z, s1, s);
-                st.merge(s1);
-                if (e != WDR_OK && e != WDR_ENOCONV) return e;
-                if (e == WDR_ENOCONV) status = e;
-                launch_g5<double>(g, Z, Tm, 0, g.nblk, s);
-                e = block_solve64(c, Xp, kappa, 2, sp, sp.block_tol, Tm, W, s1, s);
-                st.total += s1.total;
-                if (e != WDR_OK && e != WDR_ENOCONV) return e;
-                if (e == WDR_ENOCONV) status = e;
-                launch_g5<double>(g, W, W, 0, g.nblk, s);
-                launch_dslash<double>(g, HOPS_IN, -1, 0, Xp.u64, Z, Z, Tm, kappa, 0, g.nblk, s);
-                launch_sub(Y, Tm, R, n, s);
-            } else {  // SCHUR
-                e = schur64(c, X, kappa, sp, E, Tm, s1, s);                       // Dhat eta (black)
-                st.total += s1.total;
-                if (e != WDR_OK) return e;
-                launch_zero<double>(Y, n, s);                                      // y = A' Dhat eta
-                launch_dslash<double>(g, HOPS_IN, -1, 0, Xp.u64, Tm, Tm, Y, kappa, b0, bn, s);
-                e = solve64(c, Xp, kappa, sp, sp.tol, Y, Z, s1, s);               // D' z = [y; 0]
-                st.merge(s1);
-                if (e != WDR_OK && e != WDR_ENOCONV) return e;
-                if (e == WDR_ENOCONV) status = e;
-                apply_D64(c, Xp, kappa, Z, Tm, s);
-                launch_sub(Y, Tm, R, n, s);                                        // r = y - D' z
-                launch_zero<double>(Z + 12L * g.Vb * bn, 12L * g.Vb * (g.nblk - bn), s);  // z <- P z
-                launch_g5<double>(g, Z, Tm, 0, g.nblk, s);                         // D' v = g5 P z
-                e = solve64(c, Xp, kappa, sp, sp.adj_tol, Tm, W, s1, s);
-                st.total += s1.total;
-                if (e != WDR_OK && e != WDR_ENOCONV) return e;
-                if (e == WDR_ENOCONV) status = e;
-                launch_g5<double>(g, W, W, 0, g.nblk, s);
+                else return e;
             }
-            launch_sample_terms(g, E, Z, W, R, per.as<double>(), 0, g.nblk, s);
-            WDR_HIP(hipMemcpyAsync(slot_vals.data(), per.as<double>(), g.nblk * sizeof(double), hipMemcpyDeviceToHost, s));
-            WDR_HIP(hipStreamSynchronize(s));
-            double *dst = samples.data() + ((size_t)i * p.n_noise + k) * nout;
+            launch_zero<double>(Y, n * M, s);                                              // y = A' Dhat eta
+            launch_dslash<double>(g, all, Xp.u64, HOPS_IN, -1, 0, Tm, Tm, Y, kappa, b0, bn, s);
+            if (!take(solve64(c, M, Xp, kappa, sp, sp.tol, Y, Z, s1, s), true)) return hard;  // D' z = [y; 0]
+            apply_D64(c, all, Xp, kappa, Z, Tm, s);
+            launch_sub(all, Y, Tm, R, s);                                                  // r = y - D' z
+            launch_keep_slots(g, all, Z, b0, bn, s);                                       // z <- P z
+            launch_g5<double>(g, all, Z, Tm, s);                                           // D' v = g5 P z
+            if (!take(solve64(c, M, Xp, kappa, sp, sp.adj_tol, Tm, W, s1, s), false)) return hard;
+            launch_g5<double>(g, all, W, W, s);
+        }
+        launch_sample_terms(g, all, E, Z, W, R, pr.as<double>(), s);
+        WDR_HIP(hipMemcpyAsync(per.data(), pr.as<double>(), (size_t)g.nblk * M * sizeof(double), hipMemcpyDeviceToHost,
+                               s));
+        WDR_HIP(hipStreamSynchronize(s));
+        for (int j = 0; j < M; ++j) {
+            const double *ps = per.data() + (size_t)j * g.nblk;
+            double *dst = samples.data() + (size_t)(m0 + j) * nout;
             if (p.op == WDR_OP_BLOCKS) {
-                for (int b = 0; b < g.nblk; ++b) dst[b] = slot_vals[c->slot_of_block[b]];
+                for (int b = 0; b < g.nblk; ++b) dst[b] = ps[c->slot_of_block[b]];
             } else {
                 double sum = 0;  // fixed order over slots
-                for (int sl = 0; sl < g.nblk; ++sl) sum += slot_vals[sl];
+                for (int sl = 0; sl < g.nblk; ++sl) sum += ps[sl];
                 dst[0] = sum;
             }
         }
-        std::swap(cur, nxt);
     }
+    st = summarize(all_stats);
     if (host_samples) std::copy(samples.begin(), samples.end(), host_samples);
     if (host_log_ratio) {
         // sum_i log( (1/K) sum_k exp(s_ik) ), summed over blocks for BLOCKS
-        double total = 0;
+        double tot = 0;
         for (int b = 0; b < nout; ++b)
-            for (int i = 0; i < p.n_steps; ++i) {
-                double m = -INFINITY;
-                for (int k = 0; k < p.n_noise; ++k) m = std::max(m, samples[((size_t)i * p.n_noise + k) * nout + b]);
+            for (int i = 0; i < N; ++i) {
+                double mx = -INFINITY;
+                for (int k = 0; k < K; ++k) mx = std::max(mx, samples[((size_t)i * K + k) * nout + b]);
                 double acc = 0;
-                for (int k = 0; k < p.n_noise; ++k) acc += std::exp(samples[((size_t)i * p.n_noise + k) * nout + b] - m);
-                total += m + std::log(acc / p.n_noise);
+                for (int k = 0; k < K; ++k) acc += std::exp(samples[((size_t)i * K + k) * nout + b] - mx);
+                tot += mx + std::log(acc / K);
             }
-        *host_log_ratio = total;
+        *host_log_ratio = tot;
     }
     return status;
 }

@@ -42,13 +42,14 @@ __device__ __forceinline__ long canon_of(const Geo &g, int slot, int l, int x[4]
 }
 
 // writes the internal-layout FP64 noise field
-__global__ __launch_bounds__(256) void k_noise(Geo g, int kind, uint64_t seed, uint32_t step, uint32_t k,
-                                               int black_only, double2 *__restrict__ out)
+__global__ __launch_bounds__(256) void k_noise(Geo g, long n, int kind, uint64_t seed, const int32_t *steps,
+                                               const int32_t *ks, int black_only, double2 *__restrict__ out)
 {
     const int l = blockIdx.x * 256 + threadIdx.x;
     if (l >= g.Vb) return;
-    const int slot = blockIdx.y;
-    const long base = (long)slot * 12 * g.Vb + l;
+    const int slot = blockIdx.y, m = blockIdx.z;
+    const uint32_t step = (uint32_t)steps[m], k = (uint32_t)ks[m];
+    const long base = m * n + (long)slot * 12 * g.Vb + l;
     if (black_only && slot >= g.nblack) {
         for (int c = 0; c < 12; ++c) out[base + (long)c * g.Vb] = make_double2(0.0, 0.0);
         return;
@@ -109,15 +110,17 @@ __global__ __launch_bounds__(256) void k_active(Geo g, int lo, int hi, uint8_t *
 }
 
 // per-slot sum of |eta|^2 - |z|^2 - 2 Re(conj(w) r); one workgroup per slot
-__global__ __launch_bounds__(256) void k_sample_terms(Geo g, const double2 *eta, const double2 *z, const double2 *w,
-                                                      const double2 *r, double *out, int slot0)
+__global__ __launch_bounds__(256) void k_sample_terms(Geo g, const int32_t *active, long n, const double2 *eta,
+                                                      const double2 *z, const double2 *w, const double2 *r,
+                                                      double *out)
 {
     __shared__ double sh[4];
-    const int slot = slot0 + blockIdx.x;
-    const long base = (long)slot * 12 * g.Vb;
-    const long n = 12L * g.Vb;
+    const int slot = blockIdx.x, m = blockIdx.y;
+    if (active && !active[m]) return;
+    const long base = m * n + (long)slot * 12 * g.Vb;
+    const long cnt = 12L * g.Vb;
     double acc = 0;
-    for (long i = threadIdx.x; i < n; i += 256) {
+    for (long i = threadIdx.x; i < cnt; i += 256) {
         double2 e = eta[base + i];
         double v = e.x * e.x + e.y * e.y;
         if (z) {
@@ -134,15 +137,15 @@ __global__ __launch_bounds__(256) void k_sample_terms(Geo g, const double2 *eta,
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) out[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    if (threadIdx.x == 0) out[(long)m * g.nblk + slot] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
 }
 
 }  // namespace
 
-void launch_noise(const Geo &g, int kind, uint64_t seed, int step, int k, int black_only, double2 *out, hipStream_t s)
+void launch_noise(const Geo &g, const Sys &sy, int kind, uint64_t seed, const int32_t *steps, const int32_t *ks,
+                  int black_only, double2 *out, hipStream_t s)
 {
-    k_noise<<<dim3((g.Vb + 255) / 256, g.nblk), 256, 0, s>>>(g, kind, seed, (uint32_t)step, (uint32_t)k, black_only,
-                                                             out);
+    k_noise<<<dim3((g.Vb + 255) / 256, g.nblk, sy.M), 256, 0, s>>>(g, sy.n, kind, seed, steps, ks, black_only, out);
 }
 void launch_site_maps(const Geo &g, int32_t *bid, int32_t *col, int32_t *par, int32_t *pos, hipStream_t s)
 {
@@ -152,10 +155,10 @@ void launch_active_links(const Geo &g, int lo, int hi, uint8_t *mask, hipStream_
 {
     k_active<<<dim3((g.Vb + 255) / 256, g.nblk), 256, 0, s>>>(g, lo, hi, mask);
 }
-void launch_sample_terms(const Geo &g, const double2 *eta, const double2 *z, const double2 *w, const double2 *r,
-                         double *per_slot, int slot0, int nslots, hipStream_t s)
+void launch_sample_terms(const Geo &g, const Sys &sy, const double2 *eta, const double2 *z, const double2 *w,
+                         const double2 *r, double *per_slot, hipStream_t s)
 {
-    if (nslots > 0) k_sample_terms<<<nslots, 256, 0, s>>>(g, eta, z, w, r, per_slot, slot0);
+    k_sample_terms<<<dim3(g.nblk, sy.M), 256, 0, s>>>(g, sy.active, sy.n, eta, z, w, r, per_slot);
 }
 
 }  // namespace wdr

@@ -11,9 +11,6 @@ struct wdr_ctx {
     wdr_geom geom{};
     wdr::Geo g{};
     void *tables = nullptr;        // loc_coord, loc_index, slot_nbr, slot_blk
-    double *red = nullptr;         // reduction scratch (RED_SCRATCH doubles)
-    double2 *scal = nullptr;       // device scalars (SCAL_N complex)
-    const void **ptrs = nullptr;   // device array of field pointers (PTRS_N)
     struct Buf {
         size_t bytes;
         void *p;
@@ -28,12 +25,12 @@ struct wdr_gauge {
     int device = 0;
     double2 *u64 = nullptr;  // internal FP64 links, boundary phases folded in
     float2 *u32 = nullptr;   // internal FP32 copy
+    void **tab = nullptr;    // device table {u64, u32} for single-system launches
+    int su3 = 0;             // every link is SU(3) to 1e-10 (checked at upload)
 };
 
 namespace wdr {
 
-constexpr int SCAL_N = 512;
-constexpr int PTRS_N = 64;
 
 // workspace buffers, returned to the context pool on destruction
 class Work {
@@ -57,26 +54,33 @@ inline size_t field_bytes(const wdr_ctx *c, int prec)
 }
 inline long field_n(const wdr_ctx *c) { return (long)c->g.V * 12; }
 
-// a gauge field in the internal layout, FP64 with an FP32 copy
-struct GaugeView {
-    const double2 *u64;
-    const float2 *u32;
+// per-system gauge tables (device arrays of M pointers)
+struct GaugeTab {
+    UTab<double> u64;
+    UTab<float> u32;
+    int su3;  // all fields of the table are SU(3): third link rows may be rebuilt
 };
-inline GaugeView view(const wdr_gauge *g) { return {g->u64, g->u32}; }
+inline GaugeTab view(const wdr_gauge *g)
+{
+    return {reinterpret_cast<UTab<double>>(g->tab), reinterpret_cast<UTab<float>>(g->tab + 1), g->su3};
+}
+inline Sys with_links(Sys sy, const GaugeTab &U)
+{
+    sy.su3 = U.su3;
+    return sy;
+}
 
 struct Stats {
     int iters = 0;
     int converged = 1;
     double rel = 0;
     long total = 0;
-    void merge(const Stats &o)
-    {
-        iters = o.iters;
-        converged = converged && o.converged;
-        rel = o.rel;
-        total += o.total;
-    }
 };
+// summary over the systems of a batch: max iterations, all converged, max
+// residual, summed iterations
+Stats summarize(const std::vector<Stats> &v);
+
+inline Sys all_sys(const wdr_ctx *c, int M) { return Sys{M, nullptr, field_n(c)}; }
 
 // slot ranges of the block colours
 inline void colour_slots(const wdr_ctx *c, int colour, int &slot0, int &n)
@@ -86,17 +90,17 @@ inline void colour_slots(const wdr_ctx *c, int colour, int &slot0, int &n)
     else { slot0 = 0; n = c->g.nblk; }
 }
 
-// ---- drivers (internal FP64 fields) ----
-// D, Dirichlet blocks of a colour, or cross-block hops from a colour
-void apply_D64(wdr_ctx *c, GaugeView U, double kappa, const double2 *in, double2 *out, hipStream_t s);
-wdr_status sap64(wdr_ctx *c, GaugeView U, double kappa, const wdr_solver_params &sp, const double2 *in,
-                 double2 *out, hipStream_t s);
-wdr_status solve64(wdr_ctx *c, GaugeView U, double kappa, const wdr_solver_params &sp, double tol,
-                   const double2 *b, double2 *x, Stats &st, hipStream_t s);
-wdr_status block_solve64(wdr_ctx *c, GaugeView U, double kappa, int colour, const wdr_solver_params &sp,
-                         double tol, const double2 *b, double2 *x, Stats &st, hipStream_t s);
-wdr_status schur64(wdr_ctx *c, GaugeView U, double kappa, const wdr_solver_params &sp, const double2 *in,
-                   double2 *out, Stats &st, hipStream_t s);
+// ---- drivers: batches of M systems, internal FP64 fields [M][12 V] ----
+void apply_D64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const double2 *in, double2 *out,
+               hipStream_t s);
+wdr_status sap64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
+                 const double2 *in, double2 *out, hipStream_t s);
+wdr_status solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp, double tol,
+                   const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s);
+wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int colour, const wdr_solver_params &sp,
+                         double tol, const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s);
+wdr_status schur64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
+                   const double2 *in, double2 *out, std::vector<Stats> &st, hipStream_t s);
 wdr_status logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, double kappa, const wdr_est_params &p,
                         double *host_samples, double *host_log_ratio, Stats &st, hipStream_t s);
 

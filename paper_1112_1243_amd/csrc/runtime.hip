@@ -33,6 +33,18 @@ Work::~Work()
     if (p_) c_->free_bufs.push_back({bytes_, p_});
 }
 
+Stats summarize(const std::vector<Stats> &v)
+{
+    Stats r;
+    for (const Stats &x : v) {
+        r.iters = std::max(r.iters, x.iters);
+        r.converged = r.converged && x.converged;
+        r.rel = std::max(r.rel, x.rel);
+        r.total += x.total;
+    }
+    return r;
+}
+
 wdr_status check_ctx(const wdr_ctx *c)
 {
     if (!c) {
@@ -157,6 +169,7 @@ wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)
         g.L[mu] = geom->L[mu];
         g.B[mu] = geom->B[mu];
         g.NB[mu] = geom->L[mu] / geom->B[mu];
+        g.bc[mu] = geom->bc[mu];
         nblk *= g.NB[mu];
         if (g.NB[mu] % 2) colourable = 0;
     }
@@ -227,13 +240,33 @@ wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)
         for (auto &v : slot_nbr) v = c->slot_of_block[v];
     }
 
+    // XCD-aware schedules: the slots of a range in lexicographic block order,
+    // cut into 8 contiguous chunks; workgroup i (on XCD i % 8) takes the
+    // (i / 8)-th block of chunk i % 8
+    std::vector<int32_t> sched[3];
+    for (int r = 0; r < 3; ++r) {
+        std::vector<int32_t> order;
+        for (int b = 0; b < nblk; ++b) {
+            const int sl = c->slot_of_block[b];
+            const bool black = sl < g.nblack;
+            if (r == 2 || (r == 0 && black) || (r == 1 && !black)) order.push_back(sl);
+        }
+        const int n = (int)order.size(), q = n / 8, rem = n % 8;
+        sched[r].assign(n, 0);
+        for (int i = 0; i < n; ++i) {
+            const int xcd = i % 8, t = i / 8;
+            const int start = xcd * q + std::min(xcd, rem);
+            sched[r][i] = order[start + t];
+        }
+    }
+
     const size_t b1 = Vb * sizeof(uint32_t), b2 = Vb * sizeof(uint16_t), b3 = 8L * nblk * sizeof(int32_t),
                  b4 = nblk * sizeof(int32_t);
     const size_t o2 = (b1 + 255) & ~255ul, o3 = o2 + ((b2 + 255) & ~255ul), o4 = o3 + ((b3 + 255) & ~255ul);
-    const size_t total = o4 + b4;
-    if (hipMalloc(&c->tables, total) != hipSuccess || hipMalloc(&c->red, RED_SCRATCH * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c->scal, SCAL_N * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&c->ptrs, PTRS_N * sizeof(void *)) != hipSuccess) {
+    const size_t o5 = o4 + ((b4 + 255) & ~255ul), o6 = o5 + ((sched[0].size() * 4 + 255) & ~255ul),
+                 o7 = o6 + ((sched[1].size() * 4 + 255) & ~255ul);
+    const size_t total = o7 + sched[2].size() * 4 + 256;
+    if (hipMalloc(&c->tables, total) != hipSuccess) {
         set_error("context allocation failed");
         wdr_ctx_destroy(c);
         return WDR_ENOMEM;
@@ -242,7 +275,10 @@ wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)
     if (hipMemcpy(t, loc_coord.data(), b1, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(t + o2, loc_index.data(), b2, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(t + o3, slot_nbr.data(), b3, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(t + o4, slot_blk.data(), b4, hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(t + o4, slot_blk.data(), b4, hipMemcpyHostToDevice) != hipSuccess ||
+        (sched[0].size() && hipMemcpy(t + o5, sched[0].data(), sched[0].size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+        (sched[1].size() && hipMemcpy(t + o6, sched[1].data(), sched[1].size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+        hipMemcpy(t + o7, sched[2].data(), sched[2].size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
         set_error("context upload failed");
         wdr_ctx_destroy(c);
         return WDR_EDEVICE;
@@ -251,6 +287,9 @@ wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)
     g.loc_index = reinterpret_cast<const uint16_t *>(t + o2);
     g.slot_nbr = reinterpret_cast<const int32_t *>(t + o3);
     g.slot_blk = reinterpret_cast<const int32_t *>(t + o4);
+    g.sched[0] = reinterpret_cast<const int32_t *>(t + o5);
+    g.sched[1] = reinterpret_cast<const int32_t *>(t + o6);
+    g.sched[2] = reinterpret_cast<const int32_t *>(t + o7);
     *out = c;
     return WDR_OK;
 }
@@ -262,9 +301,6 @@ wdr_status wdr_ctx_destroy(wdr_ctx *c)
     hipDeviceSynchronize();
     for (void *p : c->owned) hipFree(p);
     if (c->tables) hipFree(c->tables);
-    if (c->red) hipFree(c->red);
-    if (c->scal) hipFree(c->scal);
-    if (c->ptrs) hipFree(c->ptrs);
     delete c;
     return WDR_OK;
 }
@@ -285,14 +321,30 @@ wdr_status wdr_gauge_create(wdr_ctx *c, const double *dev_U, wdr_gauge **out, vo
     g->ctx = c;
     g->device = c->device;
     const size_t n = (size_t)c->g.V * 36;
-    if (hipMalloc(&g->u64, n * sizeof(double2)) != hipSuccess || hipMalloc(&g->u32, n * sizeof(float2)) != hipSuccess) {
+    if (hipMalloc(&g->u64, n * sizeof(double2)) != hipSuccess || hipMalloc(&g->u32, n * sizeof(float2)) != hipSuccess ||
+        hipMalloc(&g->tab, 2 * sizeof(void *)) != hipSuccess) {
         if (g->u64) hipFree(g->u64);
+        if (g->u32) hipFree(g->u32);
         delete g;
         set_error("gauge allocation failed");
         return WDR_ENOMEM;
     }
+    void *tab[2] = {g->u64, g->u32};
+    WDR_HIP(hipMemcpy(g->tab, tab, sizeof(tab), hipMemcpyHostToDevice));
     launch_pack_gauge<double>(c->g, c->geom.bc, reinterpret_cast<const double2 *>(dev_U), g->u64, s);
     launch_convert_gauge_f32(c->g, g->u64, g->u32, s);
+    {
+        // kernels that rebuild the third row of a link need SU(3) links
+        Work part(c, sizeof(double) * ((size_t)c->g.V * 4 / 256 + 2));
+        if (!part.ok()) return WDR_ENOMEM;
+        launch_su3_deviation(c->g, reinterpret_cast<const double2 *>(dev_U), part.as<double>(),
+                             part.as<double>() + ((size_t)c->g.V * 4 + 255) / 256, s);
+        double dev = 1e300;
+        WDR_HIP(hipMemcpyAsync(&dev, part.as<double>() + ((size_t)c->g.V * 4 + 255) / 256, sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        WDR_HIP(hipStreamSynchronize(s));
+        g->su3 = dev <= 1e-10;
+    }
     WDR_HIP(hipGetLastError());
     *out = g;
     return WDR_OK;
@@ -305,6 +357,7 @@ wdr_status wdr_gauge_destroy(wdr_gauge *g)
     (void)hipDeviceSynchronize();
     hipFree(g->u64);
     hipFree(g->u32);
+    hipFree(g->tab);
     delete g;
     return WDR_OK;
 }

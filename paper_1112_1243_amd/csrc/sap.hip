@@ -55,7 +55,7 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v, int width)
 //         MR on the block, x += d.
 // MODE 1: block MR for a given right-hand side: d = MR(D_b, rhs).
 template <typename T, int MODE>
-__global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const typename C2<T>::type *__restrict__ U,
+__global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const int32_t *__restrict__ active, UTab<T> Utab, long n,
                                                     const typename C2<T>::type *__restrict__ src,
                                                     typename C2<T>::type *__restrict__ dst, T kappa, int nmr,
                                                     int slot0)
@@ -66,6 +66,11 @@ __global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const typename C2<T>:
     __shared__ T red[3][MAXVB / 64];
     __shared__ T alpha_sh[2];
 
+    const int m = blockIdx.y;
+    if (active && !active[m]) return;
+    const typename C2<T>::type *__restrict__ U = Utab[m];
+    src += m * n;
+    dst += m * n;
     const int Vb = g.Vb, Vh = g.Vh;
     const int slot = slot0 + blockIdx.x;
     const int l = threadIdx.x;
@@ -193,27 +198,293 @@ __global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const typename C2<T>:
     }
 }
 
+// ---------------------------------------------------------------- 4^4 blocks
+// Same algorithm for B^4 blocks with the block's links staged in LDS: the
+// first two rows of U_mu(x) for every site (the third row is rebuilt as
+// conj(row0 x row1): in-block links never carry the boundary phase, since
+// a block never wraps around the lattice).  Every MR step then runs from
+// LDS only.  LDS: 2 x 12 x Vh spinor halves + 4 x 6 x Vb link entries
+// (FP32 74 KB, FP64 147 KB for 4^4).
+
+template <typename T, int B> struct CubeLds {
+    typedef typename C2<T>::type T2;
+    static constexpr int Vb = Cube<B>::Vb, Vh = Cube<B>::Vh;
+    T2 she[12 * Vh];
+    T2 sho[12 * Vh];
+    T2 lk[4 * 6 * Vb];
+    T red[3][Vb / 64 > 0 ? Vb / 64 : 1];
+    T alpha[2];
+};
+
+template <typename T>
+__device__ __forceinline__ void reconstruct(su3<T> &u)
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int a = (c + 1) % 3, b = (c + 2) % 3;
+        const cx<T> v = u.m[0][a] * u.m[1][b] - u.m[0][b] * u.m[1][a];
+        u.m[2][c] = mk<T>(v.re, -v.im);
+    }
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void lds_link(const typename C2<T>::type *lk, int mu, int l, su3<T> &u)
+{
+    constexpr int Vb = Cube<B>::Vb;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) u.m[e / 3][e % 3] = ld<T>(lk, (long)(mu * 6 + e) * Vb + l);
+    reconstruct(u);
+}
+
+// in-block hop sum at site l (coords x), neighbour spinors from the LDS half
+// field sh (opposite parity, local index offset off), links from LDS
+template <typename T, int B>
+__device__ __forceinline__ void hop_in_lds(const typename C2<T>::type *sh, int off, const typename C2<T>::type *lk,
+                                           int l, const int x[4], spinor<T> &acc)
+{
+    typedef Cube<B> CB;
+    zero(acc);
+    LdsLoader<T> ldr{sh, CB::Vh, off};
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        if (x[mu] + 1 < B) {
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            y[mu] += 1;
+            spinor<T> p;
+            ldr(0, CB::index(y), p);
+            vec3<T> a0, a1;
+            A_dn(mu, p.s[2], p.s[3], a0, a1);
+            vec3<T> h0, h1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                h0.c[a] = p.s[0].c[a] - a0.c[a];
+                h1.c[a] = p.s[1].c[a] - a1.c[a];
+            }
+            su3<T> u;
+            lds_link<T, B>(lk, mu, l, u);
+            const vec3<T> c0 = mul(u, h0), c1 = mul(u, h1);
+            vec3<T> d0, d1;
+            Adag_h(mu, c0, c1, d0, d1);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
+                acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
+                acc.s[2].c[a] = acc.s[2].c[a] - d0.c[a];
+                acc.s[3].c[a] = acc.s[3].c[a] - d1.c[a];
+            }
+        }
+        if (x[mu] > 0) {
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            y[mu] -= 1;
+            const int nl = CB::index(y);
+            spinor<T> p;
+            ldr(0, nl, p);
+            vec3<T> a0, a1;
+            A_dn(mu, p.s[2], p.s[3], a0, a1);
+            vec3<T> h0, h1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                h0.c[a] = p.s[0].c[a] + a0.c[a];
+                h1.c[a] = p.s[1].c[a] + a1.c[a];
+            }
+            su3<T> u;
+            lds_link<T, B>(lk, mu, nl, u);
+            const vec3<T> c0 = mul_dag(u, h0), c1 = mul_dag(u, h1);
+            vec3<T> d0, d1;
+            Adag_h(mu, c0, c1, d0, d1);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
+                acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
+                acc.s[2].c[a] = acc.s[2].c[a] + d0.c[a];
+                acc.s[3].c[a] = acc.s[3].c[a] + d1.c[a];
+            }
+        }
+    }
+}
+
+template <typename T, int MODE, int B>
+__global__ __launch_bounds__(Cube<B>::Vb) void k_block_mr_cube(Geo g, const int32_t *__restrict__ active,
+                                                               UTab<T> Utab, long n,
+                                                               const int32_t *__restrict__ sched,
+                                                               const typename C2<T>::type *__restrict__ src,
+                                                               typename C2<T>::type *__restrict__ dst, T kappa,
+                                                               int nmr)
+{
+    typedef Cube<B> CB;
+    __shared__ CubeLds<T, B> S;
+    constexpr int Vb = CB::Vb, Vh = CB::Vh;
+    const int m = blockIdx.y;
+    if (active && !active[m]) return;
+    const typename C2<T>::type *__restrict__ U = Utab[m];
+    src += m * n;
+    dst += m * n;
+    const int slot = sched[blockIdx.x];
+    const int l = threadIdx.x;
+    const bool even = l < Vh;
+    const int hi = even ? l : l - Vh;
+    int x[4];
+    CB::coords(l, x);
+
+    // stage the block's links (two rows) in LDS
+    {
+        const long base = (long)slot * 4 * 9 * Vb + l;
+        const auto *Ug = as_global(U);
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int e = 0; e < 6; ++e) st<T>(S.lk, (mu * 6 + e) * Vb + l, ldg<T>(Ug, base + (long)(mu * 9 + e) * Vb));
+    }
+
+    spinor<T> r, acc;
+    if (MODE == 0) {
+        int nbr[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
+        hop_sum_cube<T, HOPS_ALL, B, 0>(U, dst, slot, nbr, l, x, acc);
+        spinor<T> e, xs;
+        load_site<T>(src, slot, Vb, l, e);
+        load_site<T>(dst, slot, Vb, l, xs);
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                r.s[sp].c[a] = e.s[sp].c[a] - xs.s[sp].c[a] + scale(kappa, acc.s[sp].c[a]);
+    } else {
+        load_site<T>(src, slot, Vb, l, r);
+    }
+
+    if (!even) lds_store<T>(S.sho, Vh, hi, r);
+    __syncthreads();
+    spinor<T> rho, del;
+    if (even) {
+        hop_in_lds<T, B>(S.sho, Vh, S.lk, l, x, acc);
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                rho.s[sp].c[a] = r.s[sp].c[a] + scale(kappa, acc.s[sp].c[a]);
+                del.s[sp].c[a] = mk<T>(0, 0);
+            }
+        lds_store<T>(S.she, Vh, hi, rho);
+    }
+    const T k2 = kappa * kappa;
+    for (int it = 0; it < nmr; ++it) {
+        __syncthreads();
+        if (!even) {
+            hop_in_lds<T, B>(S.she, 0, S.lk, l, x, acc);
+            lds_store<T>(S.sho, Vh, hi, acc);
+        }
+        __syncthreads();
+        T pr = 0, pi = 0, pp = 0;
+        spinor<T> p;
+        if (even) {
+            hop_in_lds<T, B>(S.sho, Vh, S.lk, l, x, acc);
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    p.s[sp].c[a] = rho.s[sp].c[a] - scale(k2, acc.s[sp].c[a]);
+                    const cx<T> q = conjmul(p.s[sp].c[a], rho.s[sp].c[a]);
+                    pr += q.re;
+                    pi += q.im;
+                    pp += p.s[sp].c[a].re * p.s[sp].c[a].re + p.s[sp].c[a].im * p.s[sp].c[a].im;
+                }
+        }
+        pr = wave_sum(pr, 64);
+        pi = wave_sum(pi, 64);
+        pp = wave_sum(pp, 64);
+        if ((l & 63) == 0) {
+            S.red[0][l >> 6] = pr;
+            S.red[1][l >> 6] = pi;
+            S.red[2][l >> 6] = pp;
+        }
+        __syncthreads();
+        if (l == 0) {
+            T sr = 0, si = 0, sq = 0;
+#pragma unroll
+            for (int w = 0; w < Vb / 64; ++w) {
+                sr += S.red[0][w];
+                si += S.red[1][w];
+                sq += S.red[2][w];
+            }
+            S.alpha[0] = sq > 0 ? sr / sq : T(0);
+            S.alpha[1] = sq > 0 ? si / sq : T(0);
+        }
+        __syncthreads();
+        const cx<T> al = mk<T>(S.alpha[0], S.alpha[1]);
+        if (even) {
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    del.s[sp].c[a] = del.s[sp].c[a] + al * rho.s[sp].c[a];
+                    rho.s[sp].c[a] = rho.s[sp].c[a] - al * p.s[sp].c[a];
+                }
+            lds_store<T>(S.she, Vh, hi, rho);
+        }
+    }
+    __syncthreads();
+    if (even) lds_store<T>(S.she, Vh, hi, del);
+    __syncthreads();
+    if (!even) {
+        hop_in_lds<T, B>(S.she, 0, S.lk, l, x, acc);
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) del.s[sp].c[a] = r.s[sp].c[a] + scale(kappa, acc.s[sp].c[a]);
+    }
+    if (MODE == 0) {
+        spinor<T> xs;
+        load_site<T>(dst, slot, Vb, l, xs);
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) xs.s[sp].c[a] = xs.s[sp].c[a] + del.s[sp].c[a];
+        __syncthreads();
+        store_site<T>(dst, slot, Vb, l, xs);
+    } else {
+        store_site<T>(dst, slot, Vb, l, del);
+    }
+}
+
+template <typename T, int MODE>
+bool launch_mr_cube4(const Geo &g, const Sys &sy, UTab<T> U, const T2<T> *src, T2<T> *dst, T kappa, int nmr,
+                     int slot0, int nslots, hipStream_t s)
+{
+    if (g.B[0] != 4 || g.B[1] != 4 || g.B[2] != 4 || g.B[3] != 4) return false;
+    const int si = sched_index(g, slot0, nslots);
+    if (si < 0) return false;
+    k_block_mr_cube<T, MODE, 4><<<dim3(nslots, sy.M), 256, 0, s>>>(g, sy.active, U, sy.n, g.sched[si], src, dst,
+                                                                   kappa, nmr);
+    return true;
+}
+
 }  // namespace
 
 template <typename T>
-void launch_sap_colour(const Geo &g, const typename C2<T>::type *U, const typename C2<T>::type *eta,
-                       typename C2<T>::type *x, T kappa, int nmr, int slot0, int nslots, hipStream_t s)
+void launch_sap_colour(const Geo &g, const Sys &sy, UTab<T> U, const T2<T> *eta, T2<T> *x, T kappa, int nmr,
+                       int slot0, int nslots, hipStream_t s)
 {
-    if (nslots > 0) k_block_mr<T, 0><<<nslots, g.Vb, 0, s>>>(g, U, eta, x, kappa, nmr, slot0);
+    if (nslots <= 0 || sy.M <= 0) return;
+    if (launch_mr_cube4<T, 0>(g, sy, U, eta, x, kappa, nmr, slot0, nslots, s)) return;
+    k_block_mr<T, 0><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U, sy.n, eta, x, kappa, nmr, slot0);
 }
 
 template <typename T>
-void launch_block_mr(const Geo &g, const typename C2<T>::type *U, const typename C2<T>::type *r,
-                     typename C2<T>::type *d, T kappa, int nmr, int slot0, int nslots, hipStream_t s)
+void launch_block_mr(const Geo &g, const Sys &sy, UTab<T> U, const T2<T> *r, T2<T> *d, T kappa, int nmr, int slot0,
+                     int nslots, hipStream_t s)
 {
-    if (nslots > 0) k_block_mr<T, 1><<<nslots, g.Vb, 0, s>>>(g, U, r, d, kappa, nmr, slot0);
+    if (nslots <= 0 || sy.M <= 0) return;
+    if (launch_mr_cube4<T, 1>(g, sy, U, r, d, kappa, nmr, slot0, nslots, s)) return;
+    k_block_mr<T, 1><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U, sy.n, r, d, kappa, nmr, slot0);
 }
 
 #define INST(T)                                                                                                  \
-    template void launch_sap_colour<T>(const Geo &, const C2<T>::type *, const C2<T>::type *, C2<T>::type *, T,  \
-                                       int, int, int, hipStream_t);                                              \
-    template void launch_block_mr<T>(const Geo &, const C2<T>::type *, const C2<T>::type *, C2<T>::type *, T,    \
-                                     int, int, int, hipStream_t);
+    template void launch_sap_colour<T>(const Geo &, const Sys &, UTab<T>, const T2<T> *, T2<T> *, T, int, int,   \
+                                       int, hipStream_t);                                                        \
+    template void launch_block_mr<T>(const Geo &, const Sys &, UTab<T>, const T2<T> *, T2<T> *, T, int, int, int, \
+                                     hipStream_t);
 INST(double)
 INST(float)
 #undef INST

@@ -1,13 +1,17 @@
-// Solver drivers: Schwarz preconditioner, flexible GCR, CG on the normal
-// equations, Dirichlet block solves and the Schur complement (paper Sec. 3,
-// eqs. domdec and ddfactor; Sec. 4, "one inversion for each factor").
+// Batched solver drivers: Schwarz preconditioner, flexible GCR, CG on the
+// normal equations, Dirichlet block solves and the Schur complement
+// (paper Sec. 3, eqs. domdec and ddfactor; Sec. 4, "one inversion for each
+// factor").
 //
-// Outer iterations are FP64 with FP64 true residuals and deterministic FP64
+// A call advances M independent systems (same geometry, own gauge field,
+// own right-hand side) in lockstep: every kernel launch covers all systems
+// that are still iterating, so small lattices still fill the GPU.  Outer
+// iterations are FP64 with FP64 true residuals and deterministic FP64
 // reductions; the Schwarz preconditioner and the inner block MR run in
-// sp.inner (FP32 by default).  Scalars of the Krylov recursions live in
-// device memory; the host reads one residual norm per iteration to decide
-// convergence.
-#include <chrono>
+// sp.inner (FP32 by default).  Krylov scalars stay in device memory; the
+// host reads the M residual norms once per iteration to stop converged
+// systems.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -18,215 +22,271 @@ namespace {
 
 // ------------------------------------------------------------ small kernels
 
-// CG scalars in c->scal:  [0] rr, [1] ww, [2] alpha, [3] rr_new, [4] beta
-__global__ void k_cg_alpha(double2 *sc)
+// CG scalars per system, 8 per system: [0] rr, [1] ww, [2] alpha,
+// [3] rr_new, [4] beta, [5] true residual
+__global__ void k_cg_alpha(int M, const int32_t *active, double2 *sc)
 {
-    const double ww = sc[1].x;
-    sc[2] = make_double2(ww > 0 ? sc[0].x / ww : 0.0, 0.0);
+    const int m = blockIdx.x * 64 + threadIdx.x;
+    if (m >= M || (active && !active[m])) return;
+    double2 *q = sc + 8L * m;
+    const double ww = q[1].x;
+    q[2] = make_double2(ww > 0 ? q[0].x / ww : 0.0, 0.0);
 }
-__global__ void k_cg_beta(double2 *sc)
+__global__ void k_cg_beta(int M, const int32_t *active, double2 *sc)
 {
-    const double rr = sc[0].x;
-    sc[4] = make_double2(rr > 0 ? sc[3].x / rr : 0.0, 0.0);
-    sc[0] = sc[3];
+    const int m = blockIdx.x * 64 + threadIdx.x;
+    if (m >= M || (active && !active[m])) return;
+    double2 *q = sc + 8L * m;
+    const double rr = q[0].x;
+    q[4] = make_double2(rr > 0 ? q[3].x / rr : 0.0, 0.0);
+    q[0] = q[3];
 }
-// x += alpha w, r -= alpha q, y += alpha p (y optional)
-__global__ __launch_bounds__(256) void k_cg_update(const double2 *sc, double2 *x, const double2 *w, double2 *r,
-                                                   const double2 *q, double2 *y, const double2 *p, long n)
+// restart from the true residual: rr = true residual where flag is set
+__global__ void k_cg_restart(int M, const int32_t *flag, double2 *sc)
+{
+    const int m = blockIdx.x * 64 + threadIdx.x;
+    if (m >= M || !flag[m]) return;
+    sc[8L * m] = sc[8L * m + 5];
+}
+// x += alpha w, r -= alpha q
+__global__ __launch_bounds__(256) void k_cg_update(const int32_t *active, long n, long total, const double2 *sc,
+                                                   double2 *x, const double2 *w, double2 *r, const double2 *q)
 {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const double a = sc[2].x;
-    double2 xi = x[i], wi = w[i], ri = r[i], qi = q[i];
+    if (i >= total) return;
+    const int m = (int)(i / n);
+    if (active && !active[m]) return;
+    const double a = sc[8L * m + 2].x;
+    const double2 xi = x[i], wi = w[i], ri = r[i], qi = q[i];
     x[i] = make_double2(xi.x + a * wi.x, xi.y + a * wi.y);
     r[i] = make_double2(ri.x - a * qi.x, ri.y - a * qi.y);
-    if (y) {
-        double2 yi = y[i], pi = p[i];
-        y[i] = make_double2(yi.x + a * pi.x, yi.y + a * pi.y);
-    }
 }
 // p = r + beta p
-__global__ __launch_bounds__(256) void k_cg_p(const double2 *sc, const double2 *r, double2 *p, long n)
+__global__ __launch_bounds__(256) void k_cg_p(const int32_t *active, long n, long total, const double2 *sc,
+                                              const double2 *r, double2 *p)
 {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const double b = sc[4].x;
-    double2 ri = r[i], pi = p[i];
+    if (i >= total) return;
+    const int m = (int)(i / n);
+    if (active && !active[m]) return;
+    const double b = sc[8L * m + 4].x;
+    const double2 ri = r[i], pi = p[i];
     p[i] = make_double2(ri.x + b * pi.x, ri.y + b * pi.y);
 }
 
-// zero the slots outside [slot0, slot0 + n) of a FP64 field
-void zero_outside(wdr_ctx *c, double2 *f, int slot0, int n, hipStream_t s)
-{
-    const long per = 12L * c->g.Vb;
-    if (slot0 > 0) launch_zero<double>(f, per * slot0, s);
-    const int end = slot0 + n;
-    if (end < c->g.nblk) launch_zero<double>(f + per * end, per * (c->g.nblk - end), s);
-}
-
-double read_scalar(wdr_ctx *c, int idx, hipStream_t s)
-{
-    double2 v;
-    hipMemcpyAsync(&v, c->scal + idx, sizeof(double2), hipMemcpyDeviceToHost, s);
-    hipStreamSynchronize(s);
-    return v.x;
-}
-
 inline unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
+inline unsigned nb64(long n) { return (unsigned)((n + 63) / 64); }
+
+// a device copy of a host int vector, refreshed on demand
+struct DevFlags {
+    Work w;
+    std::vector<int32_t> h;
+    DevFlags(wdr_ctx *c, int M) : w(c, sizeof(int32_t) * std::max(M, 1)), h(M, 0) {}
+    int32_t *d() const { return w.as<int32_t>(); }
+    void upload(hipStream_t s) { (void)hipMemcpyAsync(d(), h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s); }
+    bool any() const
+    {
+        for (int v : h)
+            if (v) return true;
+        return false;
+    }
+};
+
+// reads `count` device values (`stride` complex numbers apart, the .x part)
+// to host; copies exactly the (count - 1) * stride + 1 entries spanned
+void read_x(const double2 *dev, int count, int stride, std::vector<double> &out, hipStream_t s)
+{
+    std::vector<double2> tmp((size_t)(count - 1) * stride + 1);
+    (void)hipMemcpyAsync(tmp.data(), dev, tmp.size() * sizeof(double2), hipMemcpyDeviceToHost, s);
+    (void)hipStreamSynchronize(s);
+    out.resize(count);
+    for (int m = 0; m < count; ++m) out[m] = tmp[(size_t)m * stride].x;
+}
 
 }  // namespace
 
-void apply_D64(wdr_ctx *c, GaugeView U, double kappa, const double2 *in, double2 *out, hipStream_t s)
+void apply_D64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const double2 *in, double2 *out,
+               hipStream_t s)
 {
-    launch_dslash<double>(c->g, HOPS_ALL, -1, 0, U.u64, in, in, out, kappa, 0, c->g.nblk, s);
+    launch_dslash<double>(c->g, with_links(sy, U), U.u64, HOPS_ALL, -1, 0, in, in, out, kappa, 0, c->g.nblk, s);
 }
 
 // ------------------------------------------------------------ SAP
 
 template <typename T>
-static void sap_run(wdr_ctx *c, const typename C2<T>::type *U, T kappa, int ncy, int nmr,
-                    const typename C2<T>::type *eta, typename C2<T>::type *x, hipStream_t s)
+static void sap_run(wdr_ctx *c, const Sys &sy, UTab<T> U, T kappa, int ncy, int nmr, const T2<T> *eta, T2<T> *x,
+                    hipStream_t s)
 {
-    launch_zero<T>(x, field_n(c), s);
+    launch_zero<T>(x, sy.n * sy.M, s);
     int b0, bn, w0, wn;
     colour_slots(c, 0, b0, bn);
     colour_slots(c, 1, w0, wn);
     for (int cy = 0; cy < ncy; ++cy) {
-        launch_sap_colour<T>(c->g, U, eta, x, kappa, nmr, b0, bn, s);
-        launch_sap_colour<T>(c->g, U, eta, x, kappa, nmr, w0, wn, s);
+        launch_sap_colour<T>(c->g, sy, U, eta, x, kappa, nmr, b0, bn, s);
+        launch_sap_colour<T>(c->g, sy, U, eta, x, kappa, nmr, w0, wn, s);
     }
 }
 
-wdr_status sap64(wdr_ctx *c, GaugeView U, double kappa, const wdr_solver_params &sp, const double2 *in,
-                 double2 *out, hipStream_t s)
+wdr_status sap64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
+                 const double2 *in, double2 *out, hipStream_t s)
 {
     if (sp.inner == WDR_F64) {
-        sap_run<double>(c, U.u64, kappa, sp.sap_cycles, sp.mr_steps, in, out, s);
+        sap_run<double>(c, sy, U.u64, kappa, sp.sap_cycles, sp.mr_steps, in, out, s);
         return WDR_OK;
     }
-    Work e(c, field_bytes(c, WDR_F32)), x(c, field_bytes(c, WDR_F32));
+    Work e(c, field_bytes(c, WDR_F32) * sy.M), x(c, field_bytes(c, WDR_F32) * sy.M);
     if (!e.ok() || !x.ok()) return WDR_ENOMEM;
-    launch_convert<float, double>(in, e.as<float2>(), field_n(c), s);
-    sap_run<float>(c, U.u32, (float)kappa, sp.sap_cycles, sp.mr_steps, e.as<float2>(), x.as<float2>(), s);
-    launch_convert<double, float>(x.as<float2>(), out, field_n(c), s);
+    launch_convert<float, double>(sy, in, e.as<float2>(), s);
+    sap_run<float>(c, sy, U.u32, (float)kappa, sp.sap_cycles, sp.mr_steps, e.as<float2>(), x.as<float2>(), s);
+    launch_convert<double, float>(sy, x.as<float2>(), out, s);
     return WDR_OK;
 }
 
 // ------------------------------------------------------------ FGCR + SAP
 
-static wdr_status fgcr(wdr_ctx *c, GaugeView U, double kappa, const wdr_solver_params &sp, double tol,
-                       const double2 *b, double2 *x, Stats &st, hipStream_t s)
+static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp, double tol,
+                       const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
     const long n = field_n(c);
-    const size_t fb = field_bytes(c, WDR_F64);
+    const size_t fb = field_bytes(c, WDR_F64) * M;
     const int nkv = sp.restart;
-    std::vector<Work *> phi, chi;
-    for (int j = 0; j < nkv; ++j) {
-        phi.push_back(new Work(c, fb));
-        chi.push_back(new Work(c, fb));
-    }
-    Work r(c, fb);
+    std::vector<Work *> bufs;
     struct Cleanup {
-        std::vector<Work *> &a, &b;
+        std::vector<Work *> &v;
         ~Cleanup()
         {
-            for (auto *w : a) delete w;
-            for (auto *w : b) delete w;
+            for (auto *w : v) delete w;
         }
-    } cleanup{phi, chi};
-    for (int j = 0; j < nkv; ++j)
-        if (!phi[j]->ok() || !chi[j]->ok()) return WDR_ENOMEM;
-    if (!r.ok()) return WDR_ENOMEM;
-
-    // device pointer table: chi_0..chi_{nkv-1}, phi_0..phi_{nkv-1}
+    } cleanup{bufs};
+    for (int j = 0; j < 2 * nkv + 2; ++j) {
+        bufs.push_back(new Work(c, fb));
+        if (!bufs.back()->ok()) return WDR_ENOMEM;
+    }
+    double2 *r = bufs[2 * nkv]->as<double2>(), *t = bufs[2 * nkv + 1]->as<double2>();
+    // device tables: chi_0..chi_{nkv-1}, phi_0..phi_{nkv-1}
+    Work tab(c, 2 * nkv * sizeof(void *));
+    // scalars: A[2][M][16][16] (two CGS passes), bj[M][16], cj[M][16], al[M][16], nr[M]
+    Work scal(c, sizeof(double2) * ((size_t)M * (2 * 256 + 16 * 3 + 1)));
+    Work red(c, sizeof(double) * red_scratch(M));
+    DevFlags act(c, M), alive(c, M), cnt(c, M);
+    if (!tab.ok() || !scal.ok() || !red.ok() || !act.w.ok() || !alive.w.ok() || !cnt.w.ok()) return WDR_ENOMEM;
     std::vector<const void *> hp(2 * nkv);
     for (int j = 0; j < nkv; ++j) {
-        hp[j] = chi[j]->as<void>();
-        hp[nkv + j] = phi[j]->as<void>();
+        hp[j] = bufs[j]->as<void>();
+        hp[nkv + j] = bufs[nkv + j]->as<void>();
     }
-    WDR_HIP(hipMemcpyAsync(c->ptrs, hp.data(), hp.size() * sizeof(void *), hipMemcpyHostToDevice, s));
-    const double2 *const *chis = reinterpret_cast<const double2 *const *>(c->ptrs);
+    WDR_HIP(hipMemcpyAsync(tab.as<void>(), hp.data(), hp.size() * sizeof(void *), hipMemcpyHostToDevice, s));
+    const double2 *const *chis = tab.as<const double2 *const>();
     const double2 *const *phis = chis + nkv;
+    auto chi = [&](int j) { return bufs[j]->as<double2>(); };
+    auto phi = [&](int j) { return bufs[nkv + j]->as<double2>(); };
+    double2 *A = scal.as<double2>();
+    double2 *bj = A + (size_t)M * 512, *cj = bj + (size_t)M * 16, *al = cj + (size_t)M * 16, *nr = al + (size_t)M * 16;
 
-    // scalars: A[l][j] at scal[l*16 + j] (two CGS passes summed), b_j at
-    // scal[256 + j], c_j at scal[272 + j], alpha at scal[288 + j], norms at 320+
-    double2 *A = c->scal, *bj = c->scal + 256, *cj = c->scal + 272, *al = c->scal + 288, *nr = c->scal + 320;
-
-    launch_norm2<double>(b, n, c->red, nr, s);
-    const double bn2 = read_scalar(c, 320, s);
-    launch_zero<double>(x, n, s);
-    st = Stats();
-    if (bn2 == 0.0) return WDR_OK;
-    launch_convert<double, double>(b, r.as<double2>(), n, s);
-    const double tol2 = tol * tol * bn2;
-    double rn2 = bn2;
-    int it = 0;
-    while (it < sp.max_iter) {
-        int m = 0;
-        std::vector<double2> hA(16 * 16), hb(16), hc(16);
-        for (int j = 0; j < nkv && it < sp.max_iter; ++j) {
-            wdr_status e = sap64(c, U, kappa, sp, r.as<double2>(), phi[j]->as<double2>(), s);
+    const Sys all = all_sys(c, M);
+    std::vector<double> bn2, rn2;
+    launch_norm2<double>(all, b, red.as<double>(), nr, 1, s);
+    read_x(nr, M, 1, bn2, s);
+    launch_zero<double>(x, n * M, s);
+    launch_convert<double, double>(all, b, r, s);
+    st.assign(M, Stats());
+    std::vector<int> its(M, 0);
+    for (int m = 0; m < M; ++m) alive.h[m] = bn2[m] > 0;
+    alive.upload(s);
+    std::vector<double2> hA((size_t)M * 512), hb((size_t)M * 16), hc((size_t)M * 16), ha((size_t)M * 16);
+    rn2 = bn2;
+    while (alive.any()) {
+        act.h = alive.h;
+        act.upload(s);
+        std::fill(cnt.h.begin(), cnt.h.end(), 0);
+        const Sys sa{M, act.d(), n};
+        for (int j = 0; j < nkv; ++j) {
+            wdr_status e = sap64(c, sa, U, kappa, sp, r, phi(j), s);
             if (e != WDR_OK) return e;
-            apply_D64(c, U, kappa, phi[j]->as<double2>(), chi[j]->as<double2>(), s);
+            apply_D64(c, sa, U, kappa, phi(j), chi(j), s);
             if (j > 0) {
-                // classical Gram-Schmidt, twice (CGS2); coefficients summed
+                // classical Gram-Schmidt, twice (CGS2)
                 for (int pass = 0; pass < 2; ++pass) {
-                    double2 *coef = c->scal + 352 + pass * 16;
-                    launch_multidot<double>(chis, j, chi[j]->as<double2>(), n, c->red, coef, s);
-                    launch_multi_axpy(coef, -1.0, chis, j, chi[j]->as<double2>(), n, 1, s);
+                    double2 *co = A + (size_t)pass * M * 256 + j * 16;
+                    launch_multidot<double>(sa, chis, j, chi(j), red.as<double>(), co, 256, s);
+                    launch_multi_axpy(sa, co, 256, -1.0, chis, j, nullptr, chi(j), 1, s);
                 }
-                // A[l][j] = coef pass0 + pass1 (host side below)
             }
-            launch_norm2<double>(chi[j]->as<double2>(), n, c->red, bj + j, s);
-            launch_scale_invsqrt(bj + j, chi[j]->as<double2>(), n, s);
-            launch_dot<double>(chi[j]->as<double2>(), r.as<double2>(), n, c->red, cj + j, s);
-            launch_axpy_dev(cj + j, -1.0, chi[j]->as<double2>(), r.as<double2>(), n, s);
-            if (j > 0) {
-                double2 co[32];
-                WDR_HIP(hipMemcpyAsync(co, c->scal + 352, 32 * sizeof(double2), hipMemcpyDeviceToHost, s));
-                WDR_HIP(hipStreamSynchronize(s));
-                for (int l = 0; l < j; ++l)
-                    hA[l * 16 + j] = make_double2(co[l].x + co[16 + l].x, co[l].y + co[16 + l].y);
+            launch_norm2<double>(sa, chi(j), red.as<double>(), bj + j, 16, s);
+            launch_scale_invsqrt(sa, bj + j, 16, chi(j), s);
+            launch_dot<double>(sa, chi(j), r, red.as<double>(), cj + j, 16, s);
+            launch_axpy_dev(sa, cj + j, 16, -1.0, chi(j), r, s);
+            launch_norm2<double>(sa, r, red.as<double>(), nr, 1, s);
+            std::vector<double> cur;
+            read_x(nr, M, 1, cur, s);
+            bool changed = false;
+            for (int m = 0; m < M; ++m) {
+                if (!act.h[m]) continue;
+                rn2[m] = cur[m];
+                cnt.h[m] = j + 1;
+                ++its[m];
+                if (!(rn2[m] > tol * tol * bn2[m]) || its[m] >= sp.max_iter) {
+                    act.h[m] = 0;
+                    changed = true;
+                }
             }
-            launch_norm2<double>(r.as<double2>(), n, c->red, nr, s);
-            rn2 = read_scalar(c, 320, s);
-            ++it;
-            ++m;
-            if (!(rn2 > tol2)) break;
+            if (!act.any()) break;
+            if (changed) act.upload(s);
         }
-        // x += sum_j alpha_j phi_j with back-substitution
-        WDR_HIP(hipMemcpyAsync(hb.data(), bj, 16 * sizeof(double2), hipMemcpyDeviceToHost, s));
-        WDR_HIP(hipMemcpyAsync(hc.data(), cj, 16 * sizeof(double2), hipMemcpyDeviceToHost, s));
+        // back substitution per system: D phi_j = b_j chi_j + sum_{l<j} A_lj chi_l
+        WDR_HIP(hipMemcpyAsync(hA.data(), A, hA.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+        WDR_HIP(hipMemcpyAsync(hb.data(), bj, hb.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+        WDR_HIP(hipMemcpyAsync(hc.data(), cj, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
         WDR_HIP(hipStreamSynchronize(s));
-        std::vector<double2> ha(16);
-        for (int l = m - 1; l >= 0; --l) {
-            double re = hc[l].x, im = hc[l].y;
-            for (int j = l + 1; j < m; ++j) {
-                const double2 a = hA[l * 16 + j], aj = ha[j];
-                re -= a.x * aj.x - a.y * aj.y;
-                im -= a.x * aj.y + a.y * aj.x;
+        for (int m = 0; m < M; ++m) {
+            const int k = cnt.h[m];
+            for (int l = k - 1; l >= 0; --l) {
+                double re = hc[m * 16 + l].x, im = hc[m * 16 + l].y;
+                for (int jj = l + 1; jj < k; ++jj) {
+                    const double2 a0 = hA[(size_t)m * 256 + jj * 16 + l], a1 = hA[(size_t)M * 256 + m * 256 + jj * 16 + l];
+                    const double ar = a0.x + a1.x, ai = a0.y + a1.y;
+                    const double2 aj = ha[m * 16 + jj];
+                    re -= ar * aj.x - ai * aj.y;
+                    im -= ar * aj.y + ai * aj.x;
+                }
+                const double bb = std::sqrt(hb[m * 16 + l].x);
+                ha[m * 16 + l] = make_double2(re / bb, im / bb);
             }
-            const double bb = std::sqrt(hb[l].x);
-            ha[l] = make_double2(re / bb, im / bb);
         }
-        WDR_HIP(hipMemcpyAsync(al, ha.data(), m * sizeof(double2), hipMemcpyHostToDevice, s));
-        launch_multi_axpy(al, 1.0, phis, m, x, n, 1, s);
+        WDR_HIP(hipMemcpyAsync(al, ha.data(), ha.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+        cnt.upload(s);
+        const Sys sw{M, alive.d(), n};
+        launch_multi_axpy(sw, al, 16, 1.0, phis, nkv, cnt.d(), x, 1, s);
         // true residual
-        apply_D64(c, U, kappa, x, chi[0]->as<double2>(), s);
-        launch_sub(b, chi[0]->as<double2>(), r.as<double2>(), n, s);
-        launch_norm2<double>(r.as<double2>(), n, c->red, nr, s);
-        rn2 = read_scalar(c, 320, s);
-        if (!std::isfinite(rn2)) break;
-        if (rn2 <= tol2) break;
+        apply_D64(c, sw, U, kappa, x, t, s);
+        launch_sub(sw, b, t, r, s);
+        launch_norm2<double>(sw, r, red.as<double>(), nr, 1, s);
+        std::vector<double> cur;
+        read_x(nr, M, 1, cur, s);
+        bool changed = false;
+        for (int m = 0; m < M; ++m) {
+            if (!alive.h[m]) continue;
+            rn2[m] = cur[m];
+            if (!std::isfinite(rn2[m]) || rn2[m] <= tol * tol * bn2[m] || its[m] >= sp.max_iter) {
+                alive.h[m] = 0;
+                changed = true;
+            }
+        }
+        if (changed) alive.upload(s);
     }
-    st.iters = it;
-    st.total = it;
-    st.rel = std::sqrt(rn2 / bn2);
-    st.converged = st.rel <= tol;
+    bool ok = true;
+    for (int m = 0; m < M; ++m) {
+        st[m].iters = its[m];
+        st[m].total = its[m];
+        st[m].rel = bn2[m] > 0 ? std::sqrt(rn2[m] / bn2[m]) : 0.0;
+        st[m].converged = st[m].rel <= tol;
+        ok = ok && st[m].converged;
+    }
     WDR_HIP(hipGetLastError());
-    if (!st.converged) {
-        set_error("FGCR stopped at " + std::to_string(it) + " iterations, relative residual " +
-                  std::to_string(st.rel));
+    if (!ok) {
+        const Stats sm = summarize(st);
+        set_error("FGCR stopped at " + std::to_string(sm.iters) + " iterations, relative residual " +
+                  std::to_string(sm.rel));
         return WDR_ENOCONV;
     }
     return WDR_OK;
@@ -234,136 +294,187 @@ static wdr_status fgcr(wdr_ctx *c, GaugeView U, double kappa, const wdr_solver_p
 
 // ------------------------------------------------------------ CGNE
 
-static wdr_status cgne(wdr_ctx *c, GaugeView U, double kappa, const wdr_solver_params &sp, double tol,
-                       const double2 *b, double2 *x, Stats &st, hipStream_t s)
+static wdr_status cgne(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp, double tol,
+                       const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
-    const long n = field_n(c);
-    const size_t fb = field_bytes(c, WDR_F64);
-    Work r(c, fb), p(c, fb), w(c, fb), q(c, fb);
-    if (!r.ok() || !p.ok() || !w.ok() || !q.ok()) return WDR_ENOMEM;
-    double2 *sc = c->scal;
+    const long n = field_n(c), total = n * M;
+    const size_t fb = field_bytes(c, WDR_F64) * M;
+    Work rw(c, fb), pw(c, fb), ww(c, fb), qw(c, fb), scal(c, sizeof(double2) * 8 * M),
+        red(c, sizeof(double) * red_scratch(M));
+    DevFlags alive(c, M), flag(c, M);
+    if (!rw.ok() || !pw.ok() || !ww.ok() || !qw.ok() || !scal.ok() || !red.ok() || !alive.w.ok() || !flag.w.ok())
+        return WDR_ENOMEM;
+    double2 *r = rw.as<double2>(), *p = pw.as<double2>(), *w = ww.as<double2>(), *q = qw.as<double2>();
+    double2 *sc = scal.as<double2>();
     const auto &g = c->g;
-    launch_zero<double>(x, n, s);
-    launch_convert<double, double>(b, r.as<double2>(), n, s);
-    launch_convert<double, double>(b, p.as<double2>(), n, s);
-    launch_norm2<double>(b, n, c->red, sc + 0, s);
-    const double bn2 = read_scalar(c, 0, s);
-    st = Stats();
-    if (bn2 == 0.0) return WDR_OK;
-    const double tol2 = tol * tol * bn2;
-    double rn2 = bn2;
+    const Sys all = all_sys(c, M);
+    launch_zero<double>(x, total, s);
+    launch_convert<double, double>(all, b, r, s);
+    launch_convert<double, double>(all, b, p, s);
+    launch_norm2<double>(all, b, red.as<double>(), sc, 8, s);
+    std::vector<double> bn2, rr;
+    read_x(sc, M, 8, bn2, s);
+    st.assign(M, Stats());
+    std::vector<int> its(M, 0);
+    for (int m = 0; m < M; ++m) alive.h[m] = bn2[m] > 0;
+    alive.upload(s);
+    std::vector<double> rn2 = bn2;
     int it = 0;
-    while (it < sp.max_iter) {
+    while (alive.any() && it < sp.max_iter) {
+        const Sys sa{M, alive.d(), n};
         // w = D^+ p, q = D w
-        launch_dslash<double>(g, HOPS_ALL, -1, 1, U.u64, p.as<double2>(), p.as<double2>(), w.as<double2>(), kappa,
-                              0, g.nblk, s);
-        apply_D64(c, U, kappa, w.as<double2>(), q.as<double2>(), s);
-        launch_norm2<double>(w.as<double2>(), n, c->red, sc + 1, s);
-        k_cg_alpha<<<1, 1, 0, s>>>(sc);
-        k_cg_update<<<nb256(n), 256, 0, s>>>(sc, x, w.as<double2>(), r.as<double2>(), q.as<double2>(), nullptr,
-                                             nullptr, n);
-        launch_norm2<double>(r.as<double2>(), n, c->red, sc + 3, s);
-        k_cg_beta<<<1, 1, 0, s>>>(sc);
-        k_cg_p<<<nb256(n), 256, 0, s>>>(sc, r.as<double2>(), p.as<double2>(), n);
+        launch_dslash<double>(g, with_links(sa, U), U.u64, HOPS_ALL, -1, 1, p, p, w, kappa, 0, g.nblk, s);
+        apply_D64(c, sa, U, kappa, w, q, s);
+        launch_norm2<double>(sa, w, red.as<double>(), sc + 1, 8, s);
+        k_cg_alpha<<<nb64(M), 64, 0, s>>>(M, alive.d(), sc);
+        k_cg_update<<<nb256(total), 256, 0, s>>>(alive.d(), n, total, sc, x, w, r, q);
+        launch_norm2<double>(sa, r, red.as<double>(), sc + 3, 8, s);
+        k_cg_beta<<<nb64(M), 64, 0, s>>>(M, alive.d(), sc);
+        k_cg_p<<<nb256(total), 256, 0, s>>>(alive.d(), n, total, sc, r, p);
         ++it;
-        if (it % 4 == 0 || it >= sp.max_iter) {
-            rn2 = read_scalar(c, 0, s);
-            if (!std::isfinite(rn2)) break;
-            if (rn2 <= tol2) {
-                // confirm with the true residual; restart the directions from it
-                apply_D64(c, U, kappa, x, q.as<double2>(), s);
-                launch_sub(b, q.as<double2>(), r.as<double2>(), n, s);
-                launch_norm2<double>(r.as<double2>(), n, c->red, sc + 0, s);
-                rn2 = read_scalar(c, 0, s);
-                if (rn2 <= tol2) break;
-                launch_convert<double, double>(r.as<double2>(), p.as<double2>(), n, s);
+        for (int m = 0; m < M; ++m)
+            if (alive.h[m]) ++its[m];
+        if (it % 4 != 0 && it < sp.max_iter) continue;
+        read_x(sc, M, 8, rr, s);
+        bool any_flag = false;
+        for (int m = 0; m < M; ++m) {
+            flag.h[m] = alive.h[m] && (!std::isfinite(rr[m]) || rr[m] <= tol * tol * bn2[m]);
+            any_flag = any_flag || flag.h[m];
+        }
+        if (!any_flag) continue;
+        // confirm with the true residual; restart the others from it
+        flag.upload(s);
+        const Sys sf{M, flag.d(), n};
+        apply_D64(c, sf, U, kappa, x, q, s);
+        launch_sub(sf, b, q, w, s);
+        launch_norm2<double>(sf, w, red.as<double>(), sc + 5, 8, s);
+        std::vector<double> tr;
+        read_x(sc + 5, M, 8, tr, s);
+        for (int m = 0; m < M; ++m) {
+            if (!flag.h[m]) continue;
+            rn2[m] = tr[m];
+            if (!std::isfinite(tr[m]) || tr[m] <= tol * tol * bn2[m]) {
+                alive.h[m] = 0;
+                flag.h[m] = 0;
             }
         }
+        flag.upload(s);
+        launch_copy_flagged(all, flag.d(), w, r, s);
+        launch_copy_flagged(all, flag.d(), w, p, s);
+        k_cg_restart<<<nb64(M), 64, 0, s>>>(M, flag.d(), sc);
+        alive.upload(s);
     }
-    apply_D64(c, U, kappa, x, q.as<double2>(), s);
-    launch_sub(b, q.as<double2>(), r.as<double2>(), n, s);
-    launch_norm2<double>(r.as<double2>(), n, c->red, sc + 5, s);
-    rn2 = read_scalar(c, 5, s);
-    st.iters = it;
-    st.total = it;
-    st.rel = std::sqrt(rn2 / bn2);
-    st.converged = st.rel <= tol;
+    // final true residuals
+    apply_D64(c, all, U, kappa, x, q, s);
+    launch_sub(all, b, q, r, s);
+    launch_norm2<double>(all, r, red.as<double>(), sc + 5, 8, s);
+    read_x(sc + 5, M, 8, rn2, s);
+    bool ok = true;
+    for (int m = 0; m < M; ++m) {
+        st[m].iters = its[m];
+        st[m].total = its[m];
+        st[m].rel = bn2[m] > 0 ? std::sqrt(rn2[m] / bn2[m]) : 0.0;
+        st[m].converged = st[m].rel <= tol;
+        ok = ok && st[m].converged;
+    }
     WDR_HIP(hipGetLastError());
-    if (!st.converged) {
-        set_error("CGNE stopped at " + std::to_string(it) + " iterations, relative residual " +
-                  std::to_string(st.rel));
+    if (!ok) {
+        const Stats sm = summarize(st);
+        set_error("CGNE stopped at " + std::to_string(sm.iters) + " iterations, relative residual " +
+                  std::to_string(sm.rel));
         return WDR_ENOCONV;
     }
     return WDR_OK;
 }
 
-wdr_status solve64(wdr_ctx *c, GaugeView U, double kappa, const wdr_solver_params &sp, double tol,
-                   const double2 *b, double2 *x, Stats &st, hipStream_t s)
+wdr_status solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp, double tol,
+                   const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
-    if (sp.solver == WDR_SOLVER_CGNE) return cgne(c, U, kappa, sp, tol, b, x, st, s);
-    return fgcr(c, U, kappa, sp, tol, b, x, st, s);
+    if (sp.solver == WDR_SOLVER_CGNE) return cgne(c, M, U, kappa, sp, tol, b, x, st, s);
+    return fgcr(c, M, U, kappa, sp, tol, b, x, st, s);
 }
 
 // ------------------------------------------------------------ block solves
 
-wdr_status block_solve64(wdr_ctx *c, GaugeView U, double kappa, int colour, const wdr_solver_params &sp,
-                         double tol, const double2 *b, double2 *x, Stats &st, hipStream_t s)
+wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int colour, const wdr_solver_params &sp,
+                         double tol, const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
     const auto &g = c->g;
     int slot0, ns;
     colour_slots(c, colour, slot0, ns);
     const long n = field_n(c);
-    const size_t fb = field_bytes(c, WDR_F64);
-    Work r(c, fb), t(c, fb), d32(c, field_bytes(c, WDR_F32)), r32(c, field_bytes(c, WDR_F32)), d64(c, fb);
-    Work nrm(c, 2 * sizeof(double) * g.nblk);
-    if (!r.ok() || !t.ok() || !d32.ok() || !r32.ok() || !d64.ok() || !nrm.ok()) return WDR_ENOMEM;
-    launch_zero<double>(x, n, s);
-    launch_convert<double, double>(b, r.as<double2>(), n, s);
-    zero_outside(c, r.as<double2>(), slot0, ns, s);
-    double *bn = nrm.as<double>(), *rn = bn + g.nblk;
-    launch_slot_norm2(g, r.as<double2>(), bn, slot0, ns, s);
-    std::vector<double> hb(ns), hr(ns);
-    WDR_HIP(hipMemcpyAsync(hb.data(), bn, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+    const size_t fb = field_bytes(c, WDR_F64) * M, fb32 = field_bytes(c, WDR_F32) * M;
+    Work rw(c, fb), tw(c, fb), d32(c, fb32), r32(c, fb32), d64(c, fb), nrm(c, 2 * sizeof(double) * g.nblk * M);
+    DevFlags alive(c, M);
+    if (!rw.ok() || !tw.ok() || !d32.ok() || !r32.ok() || !d64.ok() || !nrm.ok() || !alive.w.ok()) return WDR_ENOMEM;
+    double2 *r = rw.as<double2>(), *t = tw.as<double2>();
+    const Sys all = all_sys(c, M);
+    launch_zero<double>(x, n * M, s);
+    launch_convert<double, double>(all, b, r, s);
+    launch_keep_slots(g, all, r, slot0, ns, s);
+    // the MR kernels write only the selected slots: the rest of d stays zero
+    launch_zero<float>(d32.as<float2>(), n * M, s);
+    launch_zero<double>(d64.as<double2>(), n * M, s);
+    double *bn = nrm.as<double>(), *rn = bn + (size_t)g.nblk * M;
+    launch_slot_norm2(g, all, r, bn, slot0, ns, s);
+    std::vector<double> hb((size_t)g.nblk * M), hr((size_t)g.nblk * M);
+    WDR_HIP(hipMemcpyAsync(hb.data(), bn, hb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     WDR_HIP(hipStreamSynchronize(s));
+    std::vector<double> worst(M, 0.0);
+    std::vector<int> its(M, 0);
+    for (int m = 0; m < M; ++m) {
+        bool any = false;
+        for (int i = slot0; i < slot0 + ns; ++i) any = any || hb[(size_t)m * g.nblk + i] > 0;
+        alive.h[m] = any;
+    }
+    alive.upload(s);
     const int nmr = 16;
-    st = Stats();
-    double worst = 0;
-    int it = 0;
-    for (; it < 40; ++it) {
+    for (int round = 0; round < 40 && alive.any(); ++round) {
+        const Sys sa{M, alive.d(), n};
         if (sp.inner == WDR_F64) {
-            launch_block_mr<double>(g, U.u64, r.as<double2>(), d64.as<double2>(), kappa, nmr, slot0, ns, s);
-            launch_add_to64<double>(d64.as<double2>() + 12L * g.Vb * slot0, x + 12L * g.Vb * slot0,
-                                    12L * g.Vb * ns, s);
+            launch_block_mr<double>(g, sa, U.u64, r, d64.as<double2>(), kappa, nmr, slot0, ns, s);
+            launch_add_to64<double>(sa, d64.as<double2>(), x, s);
         } else {
-            launch_convert<float, double>(r.as<double2>(), r32.as<float2>(), n, s);
-            launch_block_mr<float>(g, U.u32, r32.as<float2>(), d32.as<float2>(), (float)kappa, nmr, slot0, ns, s);
-            launch_add_to64<float>(d32.as<float2>() + 12L * g.Vb * slot0, x + 12L * g.Vb * slot0, 12L * g.Vb * ns,
-                                   s);
+            launch_convert<float, double>(all, r, r32.as<float2>(), s);
+            launch_block_mr<float>(g, sa, U.u32, r32.as<float2>(), d32.as<float2>(), (float)kappa, nmr, slot0, ns, s);
+            launch_add_to64<float>(sa, d32.as<float2>(), x, s);
         }
         // r = b - D_b x on the selected blocks
-        launch_dslash<double>(g, HOPS_IN, -1, 0, U.u64, x, x, t.as<double2>(), kappa, slot0, ns, s);
-        launch_sub(b + 12L * g.Vb * slot0, t.as<double2>() + 12L * g.Vb * slot0, r.as<double2>() + 12L * g.Vb * slot0,
-                   12L * g.Vb * ns, s);
-        launch_slot_norm2(g, r.as<double2>(), rn, slot0, ns, s);
-        WDR_HIP(hipMemcpyAsync(hr.data(), rn, ns * sizeof(double), hipMemcpyDeviceToHost, s));
+        launch_dslash<double>(g, sa, U.u64, HOPS_IN, -1, 0, x, x, t, kappa, slot0, ns, s);
+        launch_sub(sa, b, t, r, s);
+        launch_keep_slots(g, sa, r, slot0, ns, s);
+        launch_slot_norm2(g, sa, r, rn, slot0, ns, s);
+        WDR_HIP(hipMemcpyAsync(hr.data(), rn, hr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         WDR_HIP(hipStreamSynchronize(s));
-        worst = 0;
-        for (int i = 0; i < ns; ++i)
-            if (hb[i] > 0) worst = std::max(worst, hr[i] / hb[i]);
-        if (!std::isfinite(worst)) break;
-        if (worst <= tol * tol) {
-            ++it;
-            break;
+        bool changed = false;
+        for (int m = 0; m < M; ++m) {
+            if (!alive.h[m]) continue;
+            ++its[m];
+            double wv = 0;
+            for (int i = slot0; i < slot0 + ns; ++i) {
+                const size_t k = (size_t)m * g.nblk + i;
+                if (hb[k] > 0) wv = std::max(wv, hr[k] / hb[k]);
+            }
+            worst[m] = wv;
+            if (!std::isfinite(wv) || wv <= tol * tol) {
+                alive.h[m] = 0;
+                changed = true;
+            }
         }
+        if (changed) alive.upload(s);
     }
-    zero_outside(c, x, slot0, ns, s);
-    st.iters = it;
-    st.total = it;
-    st.rel = std::sqrt(worst);
-    st.converged = st.rel <= tol;
+    bool ok = true;
+    st.assign(M, Stats());
+    for (int m = 0; m < M; ++m) {
+        st[m].iters = its[m];
+        st[m].total = its[m];
+        st[m].rel = std::sqrt(worst[m]);
+        st[m].converged = st[m].rel <= tol;
+        ok = ok && st[m].converged;
+    }
     WDR_HIP(hipGetLastError());
-    if (!st.converged) {
-        set_error("block solve stopped at relative residual " + std::to_string(st.rel));
+    if (!ok) {
+        set_error("block solve stopped at relative residual " + std::to_string(summarize(st).rel));
         return WDR_ENOCONV;
     }
     return WDR_OK;
@@ -371,34 +482,43 @@ wdr_status block_solve64(wdr_ctx *c, GaugeView U, double kappa, int colour, cons
 
 // ------------------------------------------------------------ Schur complement
 
-wdr_status schur64(wdr_ctx *c, GaugeView U, double kappa, const wdr_solver_params &sp, const double2 *in,
-                   double2 *out, Stats &st, hipStream_t s)
+wdr_status schur64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
+                   const double2 *in, double2 *out, std::vector<Stats> &st, hipStream_t s)
 {
     const auto &g = c->g;
     const long n = field_n(c);
-    const size_t fb = field_bytes(c, WDR_F64);
+    const size_t fb = field_bytes(c, WDR_F64) * M;
     Work t1(c, fb), t2(c, fb);
     if (!t1.ok() || !t2.ok()) return WDR_ENOMEM;
     int b0, bn, w0, wn;
     colour_slots(c, 0, b0, bn);
     colour_slots(c, 1, w0, wn);
-    Stats s1;
+    const Sys all = all_sys(c, M);
+    std::vector<Stats> s1, s2;
     // D_wb in (white sites; cross hops from black)
-    launch_zero<double>(t1.as<double2>(), n, s);
-    launch_dslash<double>(g, HOPS_CROSS, -1, 0, U.u64, in, nullptr, t1.as<double2>(), kappa, w0, wn, s);
-    wdr_status e = block_solve64(c, U, kappa, 1, sp, sp.block_tol, t1.as<double2>(), t2.as<double2>(), s1, s);
-    st.merge(s1);
-    if (e != WDR_OK) return e;
+    launch_zero<double>(t1.as<double2>(), n * M, s);
+    launch_dslash<double>(g, all, U.u64, HOPS_CROSS, -1, 0, in, nullptr, t1.as<double2>(), kappa, w0, wn, s);
+    wdr_status e = block_solve64(c, M, U, kappa, 1, sp, sp.block_tol, t1.as<double2>(), t2.as<double2>(), s1, s);
+    if (e != WDR_OK && e != WDR_ENOCONV) return e;
+    const wdr_status first = e;
     // D_bw (...) on black sites
-    launch_zero<double>(t1.as<double2>(), n, s);
-    launch_dslash<double>(g, HOPS_CROSS, -1, 0, U.u64, t2.as<double2>(), nullptr, t1.as<double2>(), kappa, b0, bn, s);
-    e = block_solve64(c, U, kappa, 0, sp, sp.block_tol, t1.as<double2>(), t2.as<double2>(), s1, s);
-    st.merge(s1);
-    if (e != WDR_OK) return e;
+    launch_zero<double>(t1.as<double2>(), n * M, s);
+    launch_dslash<double>(g, all, U.u64, HOPS_CROSS, -1, 0, t2.as<double2>(), nullptr, t1.as<double2>(), kappa, b0, bn,
+                          s);
+    e = block_solve64(c, M, U, kappa, 0, sp, sp.block_tol, t1.as<double2>(), t2.as<double2>(), s2, s);
+    if (e != WDR_OK && e != WDR_ENOCONV) return e;
+    if (e == WDR_OK) e = first;
+    st.assign(M, Stats());
+    for (int m = 0; m < M; ++m) {
+        st[m].iters = s2[m].iters;
+        st[m].total = s1[m].total + s2[m].total;
+        st[m].rel = std::max(s1[m].rel, s2[m].rel);
+        st[m].converged = s1[m].converged && s2[m].converged;
+    }
     // out = in - t2 on black, zero on white
-    launch_sub(in, t2.as<double2>(), out, n, s);
-    zero_outside(c, out, b0, bn, s);
-    return WDR_OK;
+    launch_sub(all, in, t2.as<double2>(), out, s);
+    launch_keep_slots(g, all, out, b0, bn, s);
+    return e;
 }
 
 }  // namespace wdr

@@ -31,10 +31,11 @@ template <typename T>
 __device__ __forceinline__ void load_link(const typename C2<T>::type *U, int slot, int mu, int Vb, int l, su3<T> &u)
 {
     const long base = ((long)slot * 4 + mu) * 9 * Vb + l;
+    const auto *Ug = as_global(U);
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) u.m[a][b] = ld<T>(U, base + (long)(3 * a + b) * Vb);
+        for (int b = 0; b < 3; ++b) u.m[a][b] = ldg<T>(Ug, base + (long)(3 * a + b) * Vb);
 }
 
 template <typename T> __device__ __forceinline__ void zero(spinor<T> &p)
@@ -116,6 +117,122 @@ __device__ __forceinline__ void hop_sum(const Geo &g, const typename C2<T>::type
                     acc.s[3].c[a] = acc.s[3].c[a] + d1.c[a];
                 }
             }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- cubic blocks
+// Compile-time geometry of a B^4 block (even sites first, lexicographic in
+// each parity), so neighbour indices are integer arithmetic instead of
+// table lookups.
+template <int B> struct Cube {
+    static constexpr int Vb = B * B * B * B, Vh = Vb / 2, H = B / 2;
+    __device__ static __forceinline__ void coords(int l, int x[4])
+    {
+        const int p = l >= Vh ? 1 : 0;
+        const int idx = l - p * Vh;
+        int r = idx / H;
+        x[1] = r % B;
+        r /= B;
+        x[2] = r % B;
+        x[3] = r / B;
+        x[0] = 2 * (idx % H) + ((p + x[1] + x[2] + x[3]) & 1);
+    }
+    __device__ static __forceinline__ int index(const int x[4])
+    {
+        const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+        return p * Vh + ((x[3] * B + x[2]) * B + x[1]) * H + (x[0] >> 1);
+    }
+};
+
+// One direction mu (compile time) of the hop sum at a site of a B^4 block:
+// the forward hop (1 - g_mu) U_mu(x) psi(x + mu) and the backward hop
+// (1 + g_mu) U_mu(x - mu)^+ psi(x - mu), added to acc.  `in` and `U` are the
+// system's base pointers; offsets are 32-bit element indices.
+template <typename T, int HOPS, int B, int DAG, int MU>
+__device__ __forceinline__ void hop_dir_cube(const __attribute__((address_space(1))) typename C2<T>::type *U,
+                                             const __attribute__((address_space(1))) typename C2<T>::type *in,
+                                             int slot, const int nbr[8], int l, const int x[4], int pin,
+                                             spinor<T> &acc)
+{
+    typedef Cube<B> CB;
+    constexpr int Vb = CB::Vb;
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+        const bool fwd = dir == 0;
+        const bool inside = fwd ? x[MU] + 1 < B : x[MU] > 0;
+        if (HOPS == HOPS_IN && !inside) continue;
+        if (HOPS == HOPS_CROSS && inside) continue;
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        y[MU] = fwd ? (inside ? x[MU] + 1 : 0) : (inside ? x[MU] - 1 : B - 1);
+        const int ns = inside ? slot : nbr[2 * MU + dir];
+        const int nl = CB::index(y);
+        spinor<T> p;
+        const int sb = ns * 12 * Vb + nl + pin;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) p.s[sp].c[a] = ldg<T>(in, sb + (3 * sp + a) * Vb);
+        su3<T> u;
+        const int ub = ((fwd ? slot : ns) * 4 + MU) * 9 * Vb + (fwd ? l : nl) + pin;
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u.m[e / 3][e % 3] = ldg<T>(U, ub + e * Vb);
+        if (DAG) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                p.s[2].c[a] = neg(p.s[2].c[a]);
+                p.s[3].c[a] = neg(p.s[3].c[a]);
+            }
+        }
+        vec3<T> a0, a1;
+        A_dn(MU, p.s[2], p.s[3], a0, a1);
+        vec3<T> h0, h1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            h0.c[a] = fwd ? p.s[0].c[a] - a0.c[a] : p.s[0].c[a] + a0.c[a];
+            h1.c[a] = fwd ? p.s[1].c[a] - a1.c[a] : p.s[1].c[a] + a1.c[a];
+        }
+        const vec3<T> c0 = fwd ? mul(u, h0) : mul_dag(u, h0);
+        const vec3<T> c1 = fwd ? mul(u, h1) : mul_dag(u, h1);
+        vec3<T> d0, d1;
+        Adag_h(MU, c0, c1, d0, d1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
+            acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
+            acc.s[2].c[a] = fwd ? acc.s[2].c[a] - d0.c[a] : acc.s[2].c[a] + d0.c[a];
+            acc.s[3].c[a] = fwd ? acc.s[3].c[a] - d1.c[a] : acc.s[3].c[a] + d1.c[a];
+        }
+    }
+}
+
+// hop sum for B^4 blocks; nbr[8] are the neighbour slots of this block
+// (uniform over the workgroup).  The direction loop stays rolled (all eight
+// hops in flight need more registers than occupancy allows) and dispatches
+// on the uniform direction to a compile-time specialised body, so the spin
+// projections are plain register moves and each hop's spinor and link loads
+// issue together.  DAG applies gamma5 to the loaded spinors (the caller
+// applies it to the result).
+template <typename T, int HOPS, int B, int DAG>
+__device__ __forceinline__ void hop_sum_cube(const typename C2<T>::type *__restrict__ U,
+                                             const typename C2<T>::type *__restrict__ in, int slot, const int nbr[8],
+                                             int l, const int x[4], spinor<T> &acc)
+{
+    const auto *Ug = as_global(U);
+    const auto *ing = as_global(in);
+    zero(acc);
+    // The loop stays rolled and every iteration's loads stay in it: their
+    // addresses carry `pin`, a zero the compiler cannot see through, so the
+    // loads of all four directions are not hoisted (and kept live) together.
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        int pin = 0;
+        asm volatile("" : "+s"(pin));
+        switch (mu) {
+        case 0: hop_dir_cube<T, HOPS, B, DAG, 0>(Ug, ing, slot, nbr, l, x, pin, acc); break;
+        case 1: hop_dir_cube<T, HOPS, B, DAG, 1>(Ug, ing, slot, nbr, l, x, pin, acc); break;
+        case 2: hop_dir_cube<T, HOPS, B, DAG, 2>(Ug, ing, slot, nbr, l, x, pin, acc); break;
+        default: hop_dir_cube<T, HOPS, B, DAG, 3>(Ug, ing, slot, nbr, l, x, pin, acc); break;
         }
     }
 }

@@ -37,14 +37,27 @@ void set_error(const std::string &msg);
 // ---------------------------------------------------------------- geometry
 
 struct Geo {
-    int L[4], B[4], NB[4];
+    int L[4], B[4], NB[4], bc[4];
     int V, Vb, Vh, nblk, nblack;
     int colourable;               // L/B even in every direction
     const uint32_t *loc_coord;    // [Vb]  in-block coords of local index, 8 bits each
     const uint16_t *loc_index;    // [Vb]  local index of lexicographic in-block coords
     const int32_t *slot_nbr;      // [nblk*8] neighbour slot, entry 2*mu (+mu) / 2*mu+1 (-mu)
     const int32_t *slot_blk;      // [nblk] lexicographic block id of each slot
+    // workgroup -> slot schedules for launches over the black slots, the
+    // white slots and all slots (index 0, 1, 2): spatially contiguous runs
+    // of blocks are dealt to the same XCD (workgroup i runs on XCD i % 8)
+    const int32_t *sched[3];
 };
+
+// which schedule covers the slot range [slot0, slot0 + n), or -1
+inline int sched_index(const Geo &g, int slot0, int n)
+{
+    if (slot0 == 0 && n == g.nblk) return 2;
+    if (slot0 == 0 && n == g.nblack) return 0;
+    if (slot0 == g.nblack && n == g.nblk - g.nblack) return 1;
+    return -1;
+}
 
 // complex types
 template <typename T> struct C2;
@@ -86,6 +99,17 @@ template <typename T> __device__ __forceinline__ cx<T> ld(const typename C2<T>::
 {
     typename C2<T>::type v = p[i];
     return {v.x, v.y};
+}
+// a pointer read from a device table is generic to the compiler; kernels
+// cast it so its loads are global loads rather than flat loads
+template <typename P> __device__ __forceinline__ const __attribute__((address_space(1))) P *as_global(const P *p)
+{
+    return (const __attribute__((address_space(1))) P *)p;
+}
+template <typename T> __device__ __forceinline__ cx<T> ldg(const __attribute__((address_space(1))) typename C2<T>::type *p, long i)
+{
+    const __attribute__((address_space(1))) T *q = (const __attribute__((address_space(1))) T *)p;
+    return {q[2 * i], q[2 * i + 1]};
 }
 template <typename T> __device__ __forceinline__ void st(typename C2<T>::type *p, long i, cx<T> a)
 {

@@ -109,6 +109,23 @@ def test_apply_even_odd(case, blocked):
         assert rel(got, want) < tol
 
 
+def test_apply_D_general_links():
+    """Links that are not SU(3) (scaled by 1.01) take the stencil path that
+    reads all three rows; the result still matches the oracle."""
+    from paper_1112_1243_amd import wdr
+    L, B, bc = (8, 8, 8, 8), (4, 4, 4, 4), (1, 1, 1, -1)
+    lat = oracle.Lattice(L, B, bc)
+    ctx = _ctx(L, B, bc)
+    U = 1.01 * synth.gauge_field(L, 0.6, 112)
+    psi = synth.spinor(L, 113)
+    gU = ctx.gauge(dev(U))
+    want = oracle.apply_D(lat, U, 0.137, psi)
+    assert rel(host(ctx.apply_D(gU, 0.137, dev(psi), wdr.F64)), want) < 1e-14
+    assert rel(host(ctx.apply_D(gU, 0.137, dev(psi), wdr.F32)), want) < 2e-6
+    del gU
+    ctx.close()
+
+
 @pytest.mark.parametrize("L", [(16, 16, 16, 16), (32, 32, 32, 32)])
 def test_apply_D_full_size(L):
     """The stencil at the full sizes of the 16^4 and 32^4 workloads."""
