@@ -29,8 +29,18 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # compulsory bytes per site of one stencil application: 24 reals in, 24 out,
-# four 18-real links (each neighbour spinor and link counted once)
-BYTES_PER_SITE = {"f64": 120 * 8, "f32": 120 * 4}
+# four links (each neighbour spinor and link counted once).  SU(3) fields are
+# read as two rows per link (12 reals), other fields as 18 reals.
+BYTES_PER_SITE = {("f64", True): 96 * 8, ("f32", True): 96 * 4, ("f64", False): 120 * 8, ("f32", False): 120 * 4}
+KERNEL = {"f64": "k_dslash_dir<double, all hops, B=4, R2=1>", "f32": "k_dslash_dir<float, all hops, B=4, R2=1>"}
+# HBM traffic per launch from rocprofv3 counter runs on the committed kernel
+# sources (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0: a plain 1 GiB elementwise copy
+# reads 1 GiB as FETCH_SIZE 0.5 GiB because every read request on gfx950 is
+# 128 B while FETCH_SIZE counts 64 B per request; WRITE_SIZE reads exactly).
+# Reported only while the stencil sources hash to the value recorded there.
+COUNTERS = os.path.join(ROOT, "profiles", "dslash_dir_32x32x32x32_counters.md")
+STENCIL_SOURCES = ["paper_1112_1243_amd/csrc/dslash.hip", "paper_1112_1243_amd/csrc/stencil.h",
+                   "paper_1112_1243_amd/csrc/wdr_internal.h"]
 
 WORKLOAD = dict(name="wilson8_dd16", L=(8, 8, 8, 8), B=(4, 4, 4, 4), kappa=0.135, scale=0.5, n_steps=8,
                 n_noise=1, seed=1112124301)
@@ -56,9 +66,33 @@ def estimate(ctx, wdr, gU, gUp, wl, params, seed):
     return lb + ls, ok, ib.total_iters + is_.total_iters
 
 
-def dslash_roofline(wdr, torch, L=(32, 32, 32, 32), prec_name="f32", reps=30):
-    """Average duration of one stencil launch on internal fields, by HIP
-    events on the stream the kernel is launched on."""
+def stencil_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in STENCIL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic(prec_name):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the stencil sources changed since the counters were taken."""
+    try:
+        with open(COUNTERS) as fh:
+            for line in fh:
+                if line.startswith("traffic_json:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if rec.get("sources_sha256_16") == stencil_hash() and prec_name in rec:
+                        return rec[prec_name]
+    except OSError:
+        pass
+    return None
+
+
+def dslash_roofline(wdr, torch, L=(32, 32, 32, 32), prec_name="f64", reps=30):
+    """Average duration of one stencil launch on internal fields (SU(3)
+    links), by HIP events on the stream the kernel is launched on."""
     from paper_1112_1243_amd import synth
     prec = wdr.F32 if prec_name == "f32" else wdr.F64
     ctx = wdr.Context(L, (4, 4, 4, 4))
@@ -82,14 +116,97 @@ def dslash_roofline(wdr, torch, L=(32, 32, 32, 32), prec_name="f32", reps=30):
     e1.record(st)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    alg = BYTES_PER_SITE[prec_name] * V
+    su3 = gU.su3
+    alg = BYTES_PER_SITE[(prec_name, su3)] * V
     gbs = alg / (ms * 1e-3) / 1e9
     del gU, a, b, psi
     ctx.close()
-    return {"kernel": "k_dslash<%s, all hops>" % ("float" if prec_name == "f32" else "double"),
-            "lattice": "x".join(map(str, L)), "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "avg_launch_us": round(ms * 1e3, 2), "bytes_per_launch": alg}
+    traffic = counted_traffic(prec_name) if su3 else None
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": KERNEL[prec_name] if su3 else KERNEL[prec_name].replace("R2=1", "R2=0"),
+            "lattice": "x".join(map(str, L)), "avg_launch_us": round(ms * 1e3, 2),
+            "bytes_per_launch": alg, "bytes_per_site": BYTES_PER_SITE[(prec_name, su3)]}
+
+
+def copy_ceiling(torch, reps=10):
+    """Bandwidth of a plain elementwise copy of 1 GiB (torch's vectorised
+    kernel, 1 GiB read + 1 GiB written): the practical HBM ceiling, and the
+    reference launch for calibrating the FETCH_SIZE / WRITE_SIZE counters."""
+    n = 256 * 1024 * 1024
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.mul(x, 1.0, out=y)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        torch.mul(x, 1.0, out=y)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del x, y
+    return {"kernel": "torch elementwise copy (mul by 1.0), 1 GiB in + 1 GiB out", "avg_launch_us": round(ms * 1e3, 1),
+            "achieved": round(2 * 4 * n / (ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
+
+
+def rocprof_summary(path, kernel_regex="k_dslash_dir"):
+    """Markdown summary of rocprofv3 CSV output under `path`: per-kernel
+    totals (rocprofv3's kernel_stats), the kernels matching kernel_regex split
+    by grid size (kernel_trace), and per-dispatch counter means by kernel and
+    grid size (counter_collection)."""
+    import csv
+    import glob
+    import re
+    from collections import defaultdict
+
+    def rows(pattern):
+        out = []
+        for f in sorted(glob.glob(os.path.join(path, "**", pattern), recursive=True)):
+            with open(f, newline="") as fh:
+                out += [{k.lower(): v for k, v in r.items()} for r in csv.DictReader(fh)]
+        return out
+
+    def short(name):
+        name = name.replace("wdr::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+        return re.sub(r"\(.*", "", name)[:90]
+
+    lines = []
+    stats = rows("*kernel_stats.csv")
+    if stats:
+        lines += ["| kernel | calls | total us | avg us | % |", "|---|---|---|---|---|"]
+        stats.sort(key=lambda r: -float(r.get("totaldurationns", 0)))
+        for r in stats[:15]:
+            lines.append("| %s | %s | %.1f | %.2f | %.2f |" % (short(r["name"]), r["calls"],
+                                                             float(r["totaldurationns"]) / 1e3,
+                                                             float(r["averagens"]) / 1e3,
+                                                             float(r.get("percentage", 0))))
+    trace = rows("*kernel_trace.csv")
+    if trace:
+        agg = defaultdict(list)
+        for r in trace:
+            if re.search(kernel_regex, r["kernel_name"]):
+                grid = "x".join(r.get("grid_size_%s" % d, "?") for d in "xyz")
+                agg[(short(r["kernel_name"]), grid)].append(
+                    (int(r["end_timestamp"]) - int(r["start_timestamp"])) / 1e3)
+        if agg:
+            lines += ["", "| kernel (%s) | grid (work-items) | launches | avg us | min us | max us |" % kernel_regex,
+                      "|---|---|---|---|---|---|"]
+            for (k, grid), v in sorted(agg.items()):
+                lines.append("| %s | %s | %d | %.2f | %.2f | %.2f |" % (k, grid, len(v), sum(v) / len(v), min(v),
+                                                                       max(v)))
+    cnt = rows("*counter_collection.csv")
+    if cnt:
+        agg = defaultdict(list)
+        for r in cnt:
+            agg[(short(r["kernel_name"]), r.get("grid_size", "?"), r["counter_name"])].append(
+                float(r["counter_value"]))
+        lines += ["", "| kernel | grid size | counter | dispatches | mean per dispatch |", "|---|---|---|---|---|"]
+        for (k, grid, c), v in sorted(agg.items()):
+            if re.search(kernel_regex + "|elementwise", k):
+                lines.append("| %s | %s | %s | %d | %.1f |" % (k, grid, c, len(v), sum(v) / len(v)))
+    return "\n".join(lines)
 
 
 def cpu_baseline(wl, U, Up, budget_s=20.0):
@@ -119,7 +236,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-dslash", action="store_true")
+    ap.add_argument("--rocprof-summary", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     args = ap.parse_args()
+    if args.rocprof_summary:
+        print(rocprof_summary(args.rocprof_summary))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU: this build has no multi-GPU path (every proposal, path factor and "
               "noise vector is independent; see the sharding notes in the design document)", file=sys.stderr)
@@ -172,18 +293,22 @@ def main():
 
     roof = None
     if not args.no_dslash:
-        roof = dslash_roofline(wdr, torch, prec_name="f32")
-        r64 = dslash_roofline(wdr, torch, prec_name="f64")
-        log("dslash f32:", roof)
-        log("dslash f64:", r64)
-        roof["f64"] = {k: r64[k] for k in ("achieved", "frac", "avg_launch_us", "bytes_per_launch")}
+        # the FP64 stencil is the global operator of the outer solve
+        roof = dslash_roofline(wdr, torch, prec_name="f64")
+        r32 = dslash_roofline(wdr, torch, prec_name="f32")
+        log("dslash f64:", roof)
+        log("dslash f32:", r32)
+        roof["f32"] = {k: r32[k] for k in ("achieved", "frac", "traffic", "kernel", "avg_launch_us",
+                                           "bytes_per_launch")}
+        roof["copy_ceiling"] = copy_ceiling(torch)
+        log("copy ceiling:", roof["copy_ceiling"])
 
     cpu = None if args.no_cpu else cpu_baseline(wl, U, Up)
     if cpu:
         log("cpu baseline:", cpu)
 
     out = {
-        "metric": "det-ratio estimates/sec at 1e-10 residual (+ Dslash HBM GB/s, % peak)",
+        "metric": "Dslash HBM GB/s (% peak) + det-ratio estimates/sec at 1e-10 residual vs FP64",
         "value": round(value, 4),
         "unit": "estimates/s",
         "n_gpus": 1,

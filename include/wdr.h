@@ -139,6 +139,13 @@ wdr_status wdr_active_links(wdr_ctx *ctx, int32_t lo, int32_t hi, uint8_t *dev_m
 wdr_status wdr_gauge_create(wdr_ctx *ctx, const double *dev_U, wdr_gauge **out, void *stream);
 wdr_status wdr_gauge_destroy(wdr_gauge *g);
 
+/* 1 if every link of the uploaded field is SU(3) to 1e-10 (largest entry of
+ * U U^+ - 1 and |det U - 1|), 0 otherwise or for a null handle.  SU(3)
+ * fields let the stencil and the block solver read two rows per link and
+ * rebuild the third (Sec. 5 uses SU(3) links throughout); other fields take
+ * the paths that read all nine entries. */
+int32_t wdr_gauge_is_su3(const wdr_gauge *g);
+
 /* Path of eq. param: out = U_i = exp((i/N) log(U' U^+)) U link by link
  * (geodesic with the traceless branch of the logarithm; U_0 = U and U_N = U'
  * exactly; links with U' == U copied). dev_out: canonical, V*4*9 complex. */

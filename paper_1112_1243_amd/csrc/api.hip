@@ -73,9 +73,9 @@ wdr_status with_fields(wdr_ctx *c, const double *in, double *out, hipStream_t s,
     return finish(s);
 }
 
-template <typename T> UTab<T> links(const wdr_gauge *U);
-template <> UTab<double> links<double>(const wdr_gauge *U) { return view(U).u64; }
-template <> UTab<float> links<float>(const wdr_gauge *U) { return view(U).u32; }
+template <typename T> Links<T> links(const wdr_gauge *U);
+template <> Links<double> links<double>(const wdr_gauge *U) { return view(U).u64; }
+template <> Links<float> links<float>(const wdr_gauge *U) { return view(U).u32; }
 
 template <typename T>
 wdr_status stencil_call(wdr_ctx *c, const wdr_gauge *U, double kappa, int kind, int arg, const double *in,
@@ -84,7 +84,6 @@ wdr_status stencil_call(wdr_ctx *c, const wdr_gauge *U, double kappa, int kind, 
     typedef typename C2<T>::type T2;
     const Geo &g = c->g;
     Sys one = all_sys(c, 1);
-    one.su3 = U->su3;
     return with_fields<T>(c, in, out, s, [&](T2 *a, T2 *b) {
         const T k = (T)kappa;
         if (kind == 0) {  // D
@@ -260,7 +259,6 @@ wdr_status wdr_apply_D_internal(wdr_ctx *c, const wdr_gauge *U, double kappa, wd
     }
     const Geo &g = c->g;
     Sys one = all_sys(c, 1);
-    one.su3 = U->su3;
     if (prec == WDR_F64)
         launch_dslash<double>(g, one, view(U).u64, HOPS_ALL, -1, 0, static_cast<const double2 *>(in),
                               static_cast<const double2 *>(in), static_cast<double2 *>(out), kappa, 0, g.nblk,

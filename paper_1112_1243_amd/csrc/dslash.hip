@@ -1,11 +1,15 @@
 // Wilson-Dirac stencil for gfx950 (paper Sec. 5: plain Wilson-Dirac
 // operator; Sec. 3: Dirichlet block operators and block-interaction hops).
 //
-// One lane per site.  A workgroup covers 256 consecutive sites of one block
-// slot (grid.y = slot), so a wavefront reads each spinor / link component of
-// 64 consecutive sites as one contiguous 512 B (FP32) or 1 KiB (FP64) run.
 // Hops are spin-projected: only the 2-spin half spinor is multiplied by the
 // link, and the lower two spins are reconstructed from it.
+//
+// 4^4 blocks (every workload here): k_dslash_dir, one wavefront per
+// direction over 64 sites of a block, partial sums combined in LDS; for SU(3)
+// fields it reads two rows per link and rebuilds the third.  Other block
+// shapes: k_dslash, one lane per site and 256 consecutive sites of one block
+// per workgroup.  In both, a wavefront reads each spinor / link component of
+// 64 consecutive sites as one contiguous 512 B (FP32) or 1 KiB (FP64) run.
 #include "stencil.h"
 
 namespace wdr {
@@ -73,19 +77,29 @@ __global__ __launch_bounds__(256) void k_dslash(Geo g, const int32_t *__restrict
 // compile time) and issues the loads of both hops in one round trip.  The
 // four partial sums meet in LDS; wavefront w then adds spin w of the diagonal
 // term and writes spin w of the result (contiguous over the 64 sites).
-template <typename T, int HOPS, int B, int DAG>
+template <typename T, int HOPS, int B, int DAG, int R2>
 __global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__restrict__ active, UTab<T> Utab, long n,
                                                     const int32_t *__restrict__ sched, int par, int chunks,
-                                                    const T2<T> *__restrict__ in, const T2<T> *__restrict__ diag,
-                                                    T2<T> *__restrict__ out, T kappa)
+                                                    int xcd8, const T2<T> *__restrict__ in,
+                                                    const T2<T> *__restrict__ diag, T2<T> *__restrict__ out, T kappa)
 {
     typedef Cube<B> CB;
     constexpr int Vb = CB::Vb;
     __shared__ T2<T> part[4][12][64];  // [mu][colour-spin component][site]
     const int m = blockIdx.y;
     if (active && !active[m]) return;
-    const int slot = sched[blockIdx.x / chunks];
-    const int chunk = blockIdx.x % chunks;
+    // workgroup i runs on XCD i % 8; with a slot count divisible by 8 all
+    // chunks of a block go to the XCD the schedule gives that block
+    int bi, chunk;
+    if (xcd8) {
+        const int t = blockIdx.x >> 3;
+        bi = (t / chunks) * 8 + (blockIdx.x & 7);
+        chunk = t % chunks;
+    } else {
+        bi = blockIdx.x / chunks;
+        chunk = blockIdx.x % chunks;
+    }
+    const int slot = sched[bi];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int mu = __builtin_amdgcn_readfirstlane(w);
     const int l = (par > 0 ? CB::Vh : 0) + chunk * 64 + lane;
@@ -103,13 +117,23 @@ __global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__rest
 #pragma unroll
         for (int a = 0; a < 3; ++a) dg[a] = ld<T>(diag, obase + (long)(3 * mu + a) * Vb);
     }
+    // boundary sign of the forward and backward links of this site when they
+    // wrap around the lattice (only needed to rebuild a third row)
+    T wf = 1, wb = 1;
+    if (R2 && g.bc[mu] < 0) {
+        int bl = g.slot_blk[slot];
+        for (int d = 0; d < mu; ++d) bl /= g.NB[d];
+        const int nmu = bl % g.NB[mu];
+        if (nmu == g.NB[mu] - 1 && x[mu] == B - 1) wf = -1;
+        if (nmu == 0 && x[mu] == 0) wb = -1;
+    }
     spinor<T> acc;
     zero(acc);
     switch (mu) {
-    case 0: hop_dir_cube<T, HOPS, B, DAG, 0>(Ug, ing, slot, nbr, l, x, 0, acc); break;
-    case 1: hop_dir_cube<T, HOPS, B, DAG, 1>(Ug, ing, slot, nbr, l, x, 0, acc); break;
-    case 2: hop_dir_cube<T, HOPS, B, DAG, 2>(Ug, ing, slot, nbr, l, x, 0, acc); break;
-    default: hop_dir_cube<T, HOPS, B, DAG, 3>(Ug, ing, slot, nbr, l, x, 0, acc); break;
+    case 0: hop_dir_cube<T, HOPS, B, DAG, 0, R2>(Ug, ing, slot, nbr, l, x, 0, acc, wf, wb); break;
+    case 1: hop_dir_cube<T, HOPS, B, DAG, 1, R2>(Ug, ing, slot, nbr, l, x, 0, acc, wf, wb); break;
+    case 2: hop_dir_cube<T, HOPS, B, DAG, 2, R2>(Ug, ing, slot, nbr, l, x, 0, acc, wf, wb); break;
+    default: hop_dir_cube<T, HOPS, B, DAG, 3, R2>(Ug, ing, slot, nbr, l, x, 0, acc, wf, wb); break;
     }
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
@@ -125,12 +149,12 @@ __global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__rest
         for (int d = 1; d < 4; ++d) v = v + ld<T>(&part[d][0][0], c * 64 + lane);
         v = scale(-kappa, v);
         if (DAG && mu >= 2) v = neg(v);
-        st<T>(out, obase + (long)c * Vb, v + dg[a]);
+        st_nt<T>(out, obase + (long)c * Vb, v + dg[a]);
     }
 }
 
 template <typename T, int B>
-bool launch_cube(const Geo &g, const Sys &sy, UTab<T> U, int hops, int par, int dag, const T2<T> *in,
+bool launch_cube(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int dag, const T2<T> *in,
                  const T2<T> *diag, T2<T> *out, T kappa, int slot0, int nslots, hipStream_t s)
 {
     if (g.B[0] != B || g.B[1] != B || g.B[2] != B || g.B[3] != B) return false;
@@ -140,208 +164,29 @@ bool launch_cube(const Geo &g, const Sys &sy, UTab<T> U, int hops, int par, int 
     static_assert(Cube<B>::Vh % 64 == 0, "sites of one parity fill whole wavefronts");
     const int chunks = nt / 64;
     const dim3 grid(nslots * chunks, sy.M);
+    const int xcd8 = nslots % 8 == 0;
     const int32_t *sc = g.sched[si];
-#define WDR_DIR(H, D) \
-    k_dslash_dir<T, H, B, D><<<grid, 256, 0, s>>>(g, sy.active, U, sy.n, sc, par, chunks, in, diag, out, kappa)
+#define WDR_DIR(H, D, R)                                                                                     \
+    k_dslash_dir<T, H, B, D, R><<<grid, 256, 0, s>>>(g, sy.active, U.tab, sy.n, sc, par, chunks, xcd8, in, diag, out, \
+                                                     kappa)
+#define WDR_DIR2(H, D)                                                                                       \
+    do {                                                                                                     \
+        if (U.su3) WDR_DIR(H, D, 1);                                                                        \
+        else WDR_DIR(H, D, 0);                                                                               \
+    } while (0)
     if (hops == HOPS_ALL) {
-        if (dag) WDR_DIR(HOPS_ALL, 1);
-        else WDR_DIR(HOPS_ALL, 0);
+        if (dag) WDR_DIR2(HOPS_ALL, 1);
+        else WDR_DIR2(HOPS_ALL, 0);
     } else if (hops == HOPS_IN) {
-        if (dag) WDR_DIR(HOPS_IN, 1);
-        else WDR_DIR(HOPS_IN, 0);
+        if (dag) WDR_DIR2(HOPS_IN, 1);
+        else WDR_DIR2(HOPS_IN, 0);
     } else {
-        if (dag) WDR_DIR(HOPS_CROSS, 1);
-        else WDR_DIR(HOPS_CROSS, 0);
+        if (dag) WDR_DIR2(HOPS_CROSS, 1);
+        else WDR_DIR2(HOPS_CROSS, 0);
     }
+#undef WDR_DIR2
 #undef WDR_DIR
     return true;
-}
-
-// ---------------------------------------------------------------- LDS-staged stencil
-// The full operator for 4^4 blocks when every link is SU(3): a workgroup
-// stages its block's spinor and the first two rows of its links in LDS with
-// one coalesced pass, serves every in-block hop from LDS, and reads global
-// memory only for hops that leave the block.  The third row of a link is
-// conj(row0 x row1), times the boundary phase for a link that wraps around
-// the lattice (those have the phase folded in).  Each block's own data is
-// fetched from HBM exactly once per application.
-template <typename T> struct StencilLds {
-    T2<T> psi[12 * 256];
-    T2<T> lk[4 * 6 * 256];
-};
-
-template <typename T> __device__ __forceinline__ void rebuild_row2(su3<T> &u, T sign)
-{
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const int a = (c + 1) % 3, b = (c + 2) % 3;
-        const cx<T> v = u.m[0][a] * u.m[1][b] - u.m[0][b] * u.m[1][a];
-        u.m[2][c] = mk<T>(sign * v.re, -sign * v.im);
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_dslash_lds(Geo g, const int32_t *__restrict__ active, UTab<T> Utab, long n,
-                                                    const int32_t *__restrict__ sched, int dag,
-                                                    const T2<T> *__restrict__ in, const T2<T> *__restrict__ diag,
-                                                    T2<T> *__restrict__ out, T kappa)
-{
-    typedef Cube<4> CB;
-    constexpr int Vb = 256;
-    __shared__ StencilLds<T> S;
-    const int m = blockIdx.y;
-    if (active && !active[m]) return;
-    const int slot = sched[blockIdx.x];
-    const T2<T> *__restrict__ U = Utab[m];
-    const bool diag_in = diag == in;
-    in += m * n;
-    out += m * n;
-    if (diag) diag += m * n;
-    const int l = threadIdx.x;
-    const long sbase = (long)slot * 12 * Vb;
-    // stage the block: spinor (gamma5 applied for the adjoint) and two link rows
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        T2<T> v = in[sbase + (long)c * Vb + l];
-        if (dag && c >= 6) {
-            v.x = -v.x;
-            v.y = -v.y;
-        }
-        S.psi[c * Vb + l] = v;
-    }
-    {
-        const long ubase = (long)slot * 4 * 9 * Vb + l;
-        const auto *Ug = as_global(U);
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu)
-#pragma unroll
-            for (int e = 0; e < 6; ++e) st<T>(S.lk, (mu * 6 + e) * Vb + l, ldg<T>(Ug, ubase + (long)(mu * 9 + e) * Vb));
-    }
-    int x[4], nb[4], nbr[8];
-    CB::coords(l, x);
-    {
-        int b = g.slot_blk[slot];
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            nb[mu] = b % g.NB[mu];
-            b /= g.NB[mu];
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
-    __syncthreads();
-
-    auto lds_spinor = [&](int nl, spinor<T> &p) {
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) p.s[sp].c[a] = ld<T>(S.psi, (3 * sp + a) * Vb + nl);
-    };
-    auto glb_spinor = [&](int ns, int nl, spinor<T> &p) {
-        const long base = (long)ns * 12 * Vb + nl;
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                cx<T> v = ld<T>(in, base + (long)(3 * sp + a) * Vb);
-                p.s[sp].c[a] = (dag && sp >= 2) ? neg(v) : v;
-            }
-    };
-
-    spinor<T> acc;
-    zero(acc);
-#pragma unroll 1
-    for (int mu = 0; mu < 4; ++mu) {
-        {   // forward: (1 - g_mu) U_mu(x) psi(x + mu)
-            const bool inside = x[mu] + 1 < 4;
-            int y[4] = {x[0], x[1], x[2], x[3]};
-            y[mu] = inside ? x[mu] + 1 : 0;
-            const int nl = CB::index(y);
-            spinor<T> p;
-            if (inside) lds_spinor(nl, p);
-            else glb_spinor(nbr[2 * mu], nl, p);
-            vec3<T> a0, a1;
-            A_dn(mu, p.s[2], p.s[3], a0, a1);
-            vec3<T> h0, h1;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                h0.c[a] = p.s[0].c[a] - a0.c[a];
-                h1.c[a] = p.s[1].c[a] - a1.c[a];
-            }
-            su3<T> u;
-#pragma unroll
-            for (int e = 0; e < 6; ++e) u.m[e / 3][e % 3] = ld<T>(S.lk, (mu * 6 + e) * Vb + l);
-            rebuild_row2(u, (T)((!inside && nb[mu] == g.NB[mu] - 1) ? g.bc[mu] : 1));
-            const vec3<T> c0 = mul(u, h0), c1 = mul(u, h1);
-            vec3<T> d0, d1;
-            Adag_h(mu, c0, c1, d0, d1);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
-                acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
-                acc.s[2].c[a] = acc.s[2].c[a] - d0.c[a];
-                acc.s[3].c[a] = acc.s[3].c[a] - d1.c[a];
-            }
-        }
-        {   // backward: (1 + g_mu) U_mu(x - mu)^+ psi(x - mu)
-            const bool inside = x[mu] > 0;
-            int y[4] = {x[0], x[1], x[2], x[3]};
-            y[mu] = inside ? x[mu] - 1 : 3;
-            const int nl = CB::index(y);
-            const int ns = inside ? slot : nbr[2 * mu + 1];
-            spinor<T> p;
-            su3<T> u;
-            if (inside) {
-                lds_spinor(nl, p);
-#pragma unroll
-                for (int e = 0; e < 6; ++e) u.m[e / 3][e % 3] = ld<T>(S.lk, (mu * 6 + e) * Vb + nl);
-            } else {
-                glb_spinor(ns, nl, p);
-                const long ub = ((long)ns * 4 + mu) * 9 * Vb + nl;
-                const auto *Ug = as_global(U);
-#pragma unroll
-                for (int e = 0; e < 6; ++e) u.m[e / 3][e % 3] = ldg<T>(Ug, ub + (long)e * Vb);
-            }
-            rebuild_row2(u, (T)((!inside && nb[mu] == 0) ? g.bc[mu] : 1));
-            vec3<T> a0, a1;
-            A_dn(mu, p.s[2], p.s[3], a0, a1);
-            vec3<T> h0, h1;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                h0.c[a] = p.s[0].c[a] + a0.c[a];
-                h1.c[a] = p.s[1].c[a] + a1.c[a];
-            }
-            const vec3<T> c0 = mul_dag(u, h0), c1 = mul_dag(u, h1);
-            vec3<T> d0, d1;
-            Adag_h(mu, c0, c1, d0, d1);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
-                acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
-                acc.s[2].c[a] = acc.s[2].c[a] + d0.c[a];
-                acc.s[3].c[a] = acc.s[3].c[a] + d1.c[a];
-            }
-        }
-    }
-    const long base = sbase + l;
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            cx<T> v = scale(-kappa, acc.s[sp].c[a]);
-            if (dag && sp >= 2) v = neg(v);
-            if (diag) {
-                cx<T> d;
-                if (diag_in) {
-                    d = ld<T>(S.psi, (3 * sp + a) * Vb + l);
-                    if (dag && sp >= 2) d = neg(d);
-                } else {
-                    d = ld<T>(diag, base + (long)(3 * sp + a) * Vb);
-                }
-                v = v + d;
-            }
-            st<T>(out, base + (long)(3 * sp + a) * Vb, v);
-        }
 }
 
 // SU(3) deviation of canonical FP64 links: per workgroup max into partial
@@ -512,27 +357,19 @@ __global__ __launch_bounds__(256) void k_g5(long total, int Vb, const typename C
 }  // namespace
 
 template <typename T>
-void launch_dslash(const Geo &g, const Sys &sy, UTab<T> U, int hops, int par, int dag, const T2<T> *in,
+void launch_dslash(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int dag, const T2<T> *in,
                    const T2<T> *diag, T2<T> *out, T kappa, int slot0, int nslots, hipStream_t s)
 {
     if (nslots <= 0 || sy.M <= 0) return;
-    if (sy.su3 && hops == HOPS_ALL && par < 0 && g.B[0] == 4 && g.B[1] == 4 && g.B[2] == 4 && g.B[3] == 4) {
-        const int si = sched_index(g, slot0, nslots);
-        if (si >= 0) {
-            k_dslash_lds<T><<<dim3(nslots, sy.M), 256, 0, s>>>(g, sy.active, U, sy.n, g.sched[si], dag, in, diag, out,
-                                                               kappa);
-            return;
-        }
-    }
     if (launch_cube<T, 4>(g, sy, U, hops, par, dag, in, diag, out, kappa, slot0, nslots, s)) return;
     const int nloc = par < 0 ? g.Vb : g.Vh;
     dim3 grid((nloc + 255) / 256, nslots, sy.M);
     if (hops == HOPS_ALL)
-        k_dslash<T, HOPS_ALL><<<grid, 256, 0, s>>>(g, sy.active, U, sy.n, par, dag, in, diag, out, kappa, slot0);
+        k_dslash<T, HOPS_ALL><<<grid, 256, 0, s>>>(g, sy.active, U.tab, sy.n, par, dag, in, diag, out, kappa, slot0);
     else if (hops == HOPS_IN)
-        k_dslash<T, HOPS_IN><<<grid, 256, 0, s>>>(g, sy.active, U, sy.n, par, dag, in, diag, out, kappa, slot0);
+        k_dslash<T, HOPS_IN><<<grid, 256, 0, s>>>(g, sy.active, U.tab, sy.n, par, dag, in, diag, out, kappa, slot0);
     else
-        k_dslash<T, HOPS_CROSS><<<grid, 256, 0, s>>>(g, sy.active, U, sy.n, par, dag, in, diag, out, kappa, slot0);
+        k_dslash<T, HOPS_CROSS><<<grid, 256, 0, s>>>(g, sy.active, U.tab, sy.n, par, dag, in, diag, out, kappa, slot0);
 }
 
 template <typename T> void launch_pack_spinor(const Geo &g, const double2 *canon, typename C2<T>::type *out, hipStream_t s)
@@ -574,7 +411,7 @@ template <typename T> void launch_g5(const Geo &g, const Sys &sy, const T2<T> *i
 }
 
 #define INST(T)                                                                                                  \
-    template void launch_dslash<T>(const Geo &, const Sys &, UTab<T>, int, int, int, const T2<T> *,              \
+    template void launch_dslash<T>(const Geo &, const Sys &, Links<T>, int, int, int, const T2<T> *,              \
                                    const T2<T> *, T2<T> *, T, int, int, hipStream_t);                            \
     template void launch_pack_spinor<T>(const Geo &, const double2 *, C2<T>::type *, hipStream_t);               \
     template void launch_unpack_spinor<T>(const Geo &, const C2<T>::type *, double2 *, hipStream_t);             \

@@ -105,8 +105,9 @@ wdr_status logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, dou
         const void *const *tb = tabs.as<const void *const>();
         // the geodesic path stays in SU(3) when both ends are
         const int su3 = U->su3 && Up->su3;
-        const GaugeTab X{reinterpret_cast<UTab<double>>(tb), reinterpret_cast<UTab<float>>(tb + M), su3};
-        const GaugeTab Xp{reinterpret_cast<UTab<double>>(tb + 2 * M), reinterpret_cast<UTab<float>>(tb + 3 * M), su3};
+        const GaugeTab X{{reinterpret_cast<UTab<double>>(tb), su3}, {reinterpret_cast<UTab<float>>(tb + M), su3}};
+        const GaugeTab Xp{{reinterpret_cast<UTab<double>>(tb + 2 * M), su3},
+                          {reinterpret_cast<UTab<float>>(tb + 3 * M), su3}};
         const Sys all = all_sys(c, M);
         double2 *E = eta.as<double2>(), *Y = y.as<double2>(), *Z = z.as<double2>(), *W = w.as<double2>(),
                 *R = r.as<double2>(), *Tm = t.as<double2>();

@@ -18,12 +18,18 @@ struct Sys {
     int M = 1;
     const int32_t *active = nullptr;  // device [M]
     long n = 0;                       // complex numbers per field (12 V)
-    int su3 = 0;                      // every gauge field of the batch is SU(3) to 1e-10:
-                                      // kernels may rebuild the third row of a link
 };
 
 template <typename T> using T2 = typename C2<T>::type;
 template <typename T> using UTab = const T2<T> *const *;  // device [M] gauge pointers
+
+// the links of a batch: the device table of per-system gauge pointers and
+// whether every field in it is SU(3) to SU3_TOL (then kernels may read two
+// rows per link and rebuild the third)
+template <typename T> struct Links {
+    UTab<T> tab;
+    int su3;
+};
 
 // out(x) = diag(x) - kappa * sum_{selected hops} [...] in(y), per system
 //   diag    NULL (no diagonal term) or a field supplying the diagonal term
@@ -31,7 +37,7 @@ template <typename T> using UTab = const T2<T> *const *;  // device [M] gauge po
 //   par     -1 every site of those slots, 0 / 1 only the even / odd sites
 //   dag     1: g5 (stencil) g5, the adjoint of D (gamma5-hermiticity)
 template <typename T>
-void launch_dslash(const Geo &g, const Sys &sy, UTab<T> U, int hops, int par, int dag, const T2<T> *in,
+void launch_dslash(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int dag, const T2<T> *in,
                    const T2<T> *diag, T2<T> *out, T kappa, int slot0, int nslots, hipStream_t s);
 
 // canonical FP64 AoS spinor <-> internal layout in precision T (one field)
@@ -94,11 +100,11 @@ void launch_copy_flagged(const Sys &sy, const int32_t *flag, const double2 *src,
 // nslots)): r = eta - D x (neighbours from x), nmr even-odd MR steps on
 // D_b d = r, x += d.
 template <typename T>
-void launch_sap_colour(const Geo &g, const Sys &sy, UTab<T> U, const T2<T> *eta, T2<T> *x, T kappa, int nmr,
+void launch_sap_colour(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *eta, T2<T> *x, T kappa, int nmr,
                        int slot0, int nslots, hipStream_t s);
 // Block MR: d = nmr even-odd MR steps on D_b d = r for the blocks in range.
 template <typename T>
-void launch_block_mr(const Geo &g, const Sys &sy, UTab<T> U, const T2<T> *r, T2<T> *d, T kappa, int nmr, int slot0,
+void launch_block_mr(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *r, T2<T> *d, T kappa, int nmr, int slot0,
                      int nslots, hipStream_t s);
 // out[m * g.nblk + slot] = sum over the slot of |a|^2, slots in range
 void launch_slot_norm2(const Geo &g, const Sys &sy, const double2 *a, double *out, int slot0, int nslots,

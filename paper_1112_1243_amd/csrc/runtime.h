@@ -26,8 +26,12 @@ struct wdr_gauge {
     double2 *u64 = nullptr;  // internal FP64 links, boundary phases folded in
     float2 *u32 = nullptr;   // internal FP32 copy
     void **tab = nullptr;    // device table {u64, u32} for single-system launches
-    int su3 = 0;             // every link is SU(3) to 1e-10 (checked at upload)
+    int su3 = 0;             // every link is SU(3) to SU3_TOL (checked at upload)
 };
+
+// largest |U U^+ - 1| and |det U - 1| entry for which a gauge field counts as
+// SU(3), so that kernels may rebuild the third row of its links
+constexpr double SU3_TOL = 1e-10;
 
 namespace wdr {
 
@@ -56,18 +60,12 @@ inline long field_n(const wdr_ctx *c) { return (long)c->g.V * 12; }
 
 // per-system gauge tables (device arrays of M pointers)
 struct GaugeTab {
-    UTab<double> u64;
-    UTab<float> u32;
-    int su3;  // all fields of the table are SU(3): third link rows may be rebuilt
+    Links<double> u64;
+    Links<float> u32;
 };
 inline GaugeTab view(const wdr_gauge *g)
 {
-    return {reinterpret_cast<UTab<double>>(g->tab), reinterpret_cast<UTab<float>>(g->tab + 1), g->su3};
-}
-inline Sys with_links(Sys sy, const GaugeTab &U)
-{
-    sy.su3 = U.su3;
-    return sy;
+    return {{reinterpret_cast<UTab<double>>(g->tab), g->su3}, {reinterpret_cast<UTab<float>>(g->tab + 1), g->su3}};
 }
 
 struct Stats {

@@ -449,13 +449,14 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_block_mr_cube(Geo g, const int3
 }
 
 template <typename T, int MODE>
-bool launch_mr_cube4(const Geo &g, const Sys &sy, UTab<T> U, const T2<T> *src, T2<T> *dst, T kappa, int nmr,
+bool launch_mr_cube4(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *src, T2<T> *dst, T kappa, int nmr,
                      int slot0, int nslots, hipStream_t s)
 {
-    if (g.B[0] != 4 || g.B[1] != 4 || g.B[2] != 4 || g.B[3] != 4) return false;
+    // the LDS copy of the links holds two rows: SU(3) links only
+    if (!U.su3 || g.B[0] != 4 || g.B[1] != 4 || g.B[2] != 4 || g.B[3] != 4) return false;
     const int si = sched_index(g, slot0, nslots);
     if (si < 0) return false;
-    k_block_mr_cube<T, MODE, 4><<<dim3(nslots, sy.M), 256, 0, s>>>(g, sy.active, U, sy.n, g.sched[si], src, dst,
+    k_block_mr_cube<T, MODE, 4><<<dim3(nslots, sy.M), 256, 0, s>>>(g, sy.active, U.tab, sy.n, g.sched[si], src, dst,
                                                                    kappa, nmr);
     return true;
 }
@@ -463,27 +464,27 @@ bool launch_mr_cube4(const Geo &g, const Sys &sy, UTab<T> U, const T2<T> *src, T
 }  // namespace
 
 template <typename T>
-void launch_sap_colour(const Geo &g, const Sys &sy, UTab<T> U, const T2<T> *eta, T2<T> *x, T kappa, int nmr,
+void launch_sap_colour(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *eta, T2<T> *x, T kappa, int nmr,
                        int slot0, int nslots, hipStream_t s)
 {
     if (nslots <= 0 || sy.M <= 0) return;
     if (launch_mr_cube4<T, 0>(g, sy, U, eta, x, kappa, nmr, slot0, nslots, s)) return;
-    k_block_mr<T, 0><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U, sy.n, eta, x, kappa, nmr, slot0);
+    k_block_mr<T, 0><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, sy.n, eta, x, kappa, nmr, slot0);
 }
 
 template <typename T>
-void launch_block_mr(const Geo &g, const Sys &sy, UTab<T> U, const T2<T> *r, T2<T> *d, T kappa, int nmr, int slot0,
+void launch_block_mr(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *r, T2<T> *d, T kappa, int nmr, int slot0,
                      int nslots, hipStream_t s)
 {
     if (nslots <= 0 || sy.M <= 0) return;
     if (launch_mr_cube4<T, 1>(g, sy, U, r, d, kappa, nmr, slot0, nslots, s)) return;
-    k_block_mr<T, 1><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U, sy.n, r, d, kappa, nmr, slot0);
+    k_block_mr<T, 1><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, sy.n, r, d, kappa, nmr, slot0);
 }
 
 #define INST(T)                                                                                                  \
-    template void launch_sap_colour<T>(const Geo &, const Sys &, UTab<T>, const T2<T> *, T2<T> *, T, int, int,   \
+    template void launch_sap_colour<T>(const Geo &, const Sys &, Links<T>, const T2<T> *, T2<T> *, T, int, int,   \
                                        int, hipStream_t);                                                        \
-    template void launch_block_mr<T>(const Geo &, const Sys &, UTab<T>, const T2<T> *, T2<T> *, T, int, int, int, \
+    template void launch_block_mr<T>(const Geo &, const Sys &, Links<T>, const T2<T> *, T2<T> *, T, int, int, int, \
                                      hipStream_t);
 INST(double)
 INST(float)

@@ -108,13 +108,13 @@ void read_x(const double2 *dev, int count, int stride, std::vector<double> &out,
 void apply_D64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const double2 *in, double2 *out,
                hipStream_t s)
 {
-    launch_dslash<double>(c->g, with_links(sy, U), U.u64, HOPS_ALL, -1, 0, in, in, out, kappa, 0, c->g.nblk, s);
+    launch_dslash<double>(c->g, sy, U.u64, HOPS_ALL, -1, 0, in, in, out, kappa, 0, c->g.nblk, s);
 }
 
 // ------------------------------------------------------------ SAP
 
 template <typename T>
-static void sap_run(wdr_ctx *c, const Sys &sy, UTab<T> U, T kappa, int ncy, int nmr, const T2<T> *eta, T2<T> *x,
+static void sap_run(wdr_ctx *c, const Sys &sy, Links<T> U, T kappa, int ncy, int nmr, const T2<T> *eta, T2<T> *x,
                     hipStream_t s)
 {
     launch_zero<T>(x, sy.n * sy.M, s);
@@ -323,7 +323,7 @@ static wdr_status cgne(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
     while (alive.any() && it < sp.max_iter) {
         const Sys sa{M, alive.d(), n};
         // w = D^+ p, q = D w
-        launch_dslash<double>(g, with_links(sa, U), U.u64, HOPS_ALL, -1, 1, p, p, w, kappa, 0, g.nblk, s);
+        launch_dslash<double>(g, sa, U.u64, HOPS_ALL, -1, 1, p, p, w, kappa, 0, g.nblk, s);
         apply_D64(c, sa, U, kappa, w, q, s);
         launch_norm2<double>(sa, w, red.as<double>(), sc + 1, 8, s);
         k_cg_alpha<<<nb64(M), 64, 0, s>>>(M, alive.d(), sc);

@@ -149,11 +149,16 @@ template <int B> struct Cube {
 // the forward hop (1 - g_mu) U_mu(x) psi(x + mu) and the backward hop
 // (1 + g_mu) U_mu(x - mu)^+ psi(x - mu), added to acc.  `in` and `U` are the
 // system's base pointers; offsets are 32-bit element indices.
-template <typename T, int HOPS, int B, int DAG, int MU>
+//
+// R2: read only the first two rows of each link and rebuild the third as the
+// conjugated cross product of the first two (valid for SU(3) links), times
+// the boundary sign for links that wrap around the lattice; wrap_f / wrap_b
+// are that sign for the forward and the backward link of this site.
+template <typename T, int HOPS, int B, int DAG, int MU, int R2 = 0>
 __device__ __forceinline__ void hop_dir_cube(const __attribute__((address_space(1))) typename C2<T>::type *U,
                                              const __attribute__((address_space(1))) typename C2<T>::type *in,
                                              int slot, const int nbr[8], int l, const int x[4], int pin,
-                                             spinor<T> &acc)
+                                             spinor<T> &acc, T wrap_f = 1, T wrap_b = 1)
 {
     typedef Cube<B> CB;
     constexpr int Vb = CB::Vb;
@@ -176,7 +181,16 @@ __device__ __forceinline__ void hop_dir_cube(const __attribute__((address_space(
         su3<T> u;
         const int ub = ((fwd ? slot : ns) * 4 + MU) * 9 * Vb + (fwd ? l : nl) + pin;
 #pragma unroll
-        for (int e = 0; e < 9; ++e) u.m[e / 3][e % 3] = ldg<T>(U, ub + e * Vb);
+        for (int e = 0; e < (R2 ? 6 : 9); ++e) u.m[e / 3][e % 3] = ldg<T>(U, ub + e * Vb);
+        if (R2) {
+            const T sg = fwd ? wrap_f : wrap_b;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const int a = (c + 1) % 3, b = (c + 2) % 3;
+                const cx<T> v = u.m[0][a] * u.m[1][b] - u.m[0][b] * u.m[1][a];
+                u.m[2][c] = mk<T>(sg * v.re, -sg * v.im);
+            }
+        }
         if (DAG) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {

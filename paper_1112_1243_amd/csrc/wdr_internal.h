@@ -111,6 +111,22 @@ template <typename T> __device__ __forceinline__ cx<T> ldg(const __attribute__((
     const __attribute__((address_space(1))) T *q = (const __attribute__((address_space(1))) T *)p;
     return {q[2 * i], q[2 * i + 1]};
 }
+// streaming variants: data used once (links, stencil output) is loaded and
+// stored non-temporally so it does not evict reusable lines from L2
+template <typename T> __device__ __forceinline__ cx<T> ldg_nt(const __attribute__((address_space(1))) typename C2<T>::type *p, long i)
+{
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load((const __attribute__((address_space(1))) v2 *)p + i);
+    return {v.x, v.y};
+}
+template <typename T> __device__ __forceinline__ void st_nt(typename C2<T>::type *p, long i, cx<T> a)
+{
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 v;
+    v.x = a.re;
+    v.y = a.im;
+    __builtin_nontemporal_store(v, (__attribute__((address_space(1))) v2 *)p + i);
+}
 template <typename T> __device__ __forceinline__ void st(typename C2<T>::type *p, long i, cx<T> a)
 {
     typename C2<T>::type v;

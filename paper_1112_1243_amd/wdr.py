@@ -81,6 +81,8 @@ def lib():
         L.wdr_active_links.argtypes = [P, i32, i32, P, P]
         L.wdr_gauge_create.argtypes = [P, P, ctypes.POINTER(P), P]
         L.wdr_gauge_destroy.argtypes = [P]
+        L.wdr_gauge_is_su3.argtypes = [P]
+        L.wdr_gauge_is_su3.restype = i32
         L.wdr_interpolate.argtypes = [P, P, P, i32, i32, P, P]
         L.wdr_noise.argtypes = [P, ctypes.c_int, ctypes.c_uint64, i32, i32, i32, P, P]
         L.wdr_field_bytes.argtypes = [P, ctypes.c_int]
@@ -140,6 +142,11 @@ def _dev(t, shape, dtype_name="complex128"):
 class Gauge:
     ctx: "Context"
     handle: ctypes.c_void_p
+
+    @property
+    def su3(self) -> bool:
+        """Every link is SU(3) to 1e-10 (two-row link paths are used)."""
+        return bool(lib().wdr_gauge_is_su3(self.handle))
 
     def __del__(self):
         if self.handle and _lib is not None:

@@ -119,6 +119,7 @@ def test_apply_D_general_links():
     U = 1.01 * synth.gauge_field(L, 0.6, 112)
     psi = synth.spinor(L, 113)
     gU = ctx.gauge(dev(U))
+    assert not gU.su3 and ctx.gauge(dev(synth.gauge_field(L, 0.6, 112))).su3
     want = oracle.apply_D(lat, U, 0.137, psi)
     assert rel(host(ctx.apply_D(gU, 0.137, dev(psi), wdr.F64)), want) < 1e-14
     assert rel(host(ctx.apply_D(gU, 0.137, dev(psi), wdr.F32)), want) < 2e-6
@@ -174,6 +175,24 @@ def test_sap_matches_oracle():
                 assert rel(got, want) < tol
         del gU
         ctx.close()
+
+
+def test_sap_general_links():
+    """Links that are not SU(3) take the block MR path that reads all three
+    rows from memory; SAP still matches the oracle step for step."""
+    from paper_1112_1243_amd import wdr
+    L, B, bc = (8, 8, 8, 8), (4, 4, 4, 4), (1, 1, 1, -1)
+    lat = oracle.Lattice(L, B, bc)
+    ctx = _ctx(L, B, bc)
+    U = 1.01 * synth.gauge_field(L, 0.5, 114)
+    eta = synth.spinor(L, 115)
+    gU = ctx.gauge(dev(U))
+    want = oracle.sap(lat, U, 0.135, eta, 2, 5)
+    for prec, tol in ((wdr.F64, 1e-12), (wdr.F32, 2e-5)):
+        got = host(ctx.sap(gU, 0.135, dev(eta), wdr.default_params(sap_cycles=2, mr_steps=5, inner=prec)))
+        assert rel(got, want) < tol
+    del gU
+    ctx.close()
 
 
 @pytest.mark.parametrize("inner", [0, 1])
