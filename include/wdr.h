@@ -26,7 +26,9 @@
  * and gauge handles are owned by the library.  `stream` is a hipStream_t
  * (NULL = the default stream); every call is ordered on it.  Calls that
  * return host scalars (solve info, log ratios, samples to host) synchronise
- * the stream before returning.
+ * the stream before returning.  A context (and its gauge handles) is used
+ * by one host thread at a time: its workspace pool and solver read-back
+ * buffers are not locked.
  *
  * Errors: no call throws.  Each returns a wdr_status; wdr_last_error()
  * gives a message for the calling thread.  A solver that reaches its

@@ -18,6 +18,11 @@ struct wdr_ctx {
     std::vector<Buf> free_bufs;    // workspace pool
     std::vector<void *> owned;     // every pool allocation
     std::vector<int> slot_of_block;  // host copy: slot of each lexicographic block
+    // pinned host copies of per-system solver flags (two slots, grown on
+    // demand) and their events: solver loops poll them without stalling
+    int32_t *poll_host = nullptr;
+    size_t poll_cap = 0;
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
 };
 
 struct wdr_gauge {

@@ -304,8 +304,11 @@ wdr_status wdr_ctx_destroy(wdr_ctx *c)
     if (!c) return WDR_OK;
     hipSetDevice(c->device);
     hipDeviceSynchronize();
-    for (void *p : c->owned) hipFree(p);
-    if (c->tables) hipFree(c->tables);
+    for (void *p : c->owned) (void)hipFree(p);
+    if (c->tables) (void)hipFree(c->tables);
+    if (c->poll_host) (void)hipHostFree(c->poll_host);
+    for (hipEvent_t e : c->poll_ev)
+        if (e) (void)hipEventDestroy(e);
     delete c;
     return WDR_OK;
 }

@@ -236,71 +236,69 @@ __device__ __forceinline__ void lds_link(const typename C2<T>::type *lk, int mu,
     reconstruct(u);
 }
 
-// in-block hop sum at site l (coords x), neighbour spinors from the LDS half
-// field sh (opposite parity, local index offset off), links from LDS
+// one direction (compile-time MU) of the in-block hop sum at site l (coords
+// x): both hops that stay inside the block, neighbour spinors from the LDS
+// half field sh (opposite parity, local index minus off), links from LDS;
+// added to acc
+template <typename T, int B, int MU>
+__device__ __forceinline__ void hop_dir_lds(const typename C2<T>::type *sh, int off, const typename C2<T>::type *lk,
+                                            int l, const int x[4], spinor<T> &acc)
+{
+    typedef Cube<B> CB;
+    LdsLoader<T> ldr{sh, CB::Vh, off};
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+        const bool fwd = dir == 0;
+        if (fwd ? x[MU] + 1 >= B : x[MU] == 0) continue;
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        y[MU] += fwd ? 1 : -1;
+        const int nl = CB::index(y);
+        spinor<T> p;
+        ldr(0, nl, p);
+        vec3<T> a0, a1;
+        A_dn(MU, p.s[2], p.s[3], a0, a1);
+        vec3<T> h0, h1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            h0.c[a] = fwd ? p.s[0].c[a] - a0.c[a] : p.s[0].c[a] + a0.c[a];
+            h1.c[a] = fwd ? p.s[1].c[a] - a1.c[a] : p.s[1].c[a] + a1.c[a];
+        }
+        su3<T> u;
+        lds_link<T, B>(lk, MU, fwd ? l : nl, u);
+        const vec3<T> c0 = fwd ? mul(u, h0) : mul_dag(u, h0);
+        const vec3<T> c1 = fwd ? mul(u, h1) : mul_dag(u, h1);
+        vec3<T> d0, d1;
+        Adag_h(MU, c0, c1, d0, d1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
+            acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
+            acc.s[2].c[a] = fwd ? acc.s[2].c[a] - d0.c[a] : acc.s[2].c[a] + d0.c[a];
+            acc.s[3].c[a] = fwd ? acc.s[3].c[a] - d1.c[a] : acc.s[3].c[a] + d1.c[a];
+        }
+    }
+}
+
+template <typename T, int B>
+__device__ __forceinline__ void hop_dir_lds_rt(int mu, const typename C2<T>::type *sh, int off,
+                                               const typename C2<T>::type *lk, int l, const int x[4], spinor<T> &acc)
+{
+    switch (mu) {
+    case 0: hop_dir_lds<T, B, 0>(sh, off, lk, l, x, acc); break;
+    case 1: hop_dir_lds<T, B, 1>(sh, off, lk, l, x, acc); break;
+    case 2: hop_dir_lds<T, B, 2>(sh, off, lk, l, x, acc); break;
+    default: hop_dir_lds<T, B, 3>(sh, off, lk, l, x, acc); break;
+    }
+}
+
+// in-block hop sum at site l over all four directions
 template <typename T, int B>
 __device__ __forceinline__ void hop_in_lds(const typename C2<T>::type *sh, int off, const typename C2<T>::type *lk,
                                            int l, const int x[4], spinor<T> &acc)
 {
-    typedef Cube<B> CB;
     zero(acc);
-    LdsLoader<T> ldr{sh, CB::Vh, off};
 #pragma unroll 1
-    for (int mu = 0; mu < 4; ++mu) {
-        if (x[mu] + 1 < B) {
-            int y[4] = {x[0], x[1], x[2], x[3]};
-            y[mu] += 1;
-            spinor<T> p;
-            ldr(0, CB::index(y), p);
-            vec3<T> a0, a1;
-            A_dn(mu, p.s[2], p.s[3], a0, a1);
-            vec3<T> h0, h1;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                h0.c[a] = p.s[0].c[a] - a0.c[a];
-                h1.c[a] = p.s[1].c[a] - a1.c[a];
-            }
-            su3<T> u;
-            lds_link<T, B>(lk, mu, l, u);
-            const vec3<T> c0 = mul(u, h0), c1 = mul(u, h1);
-            vec3<T> d0, d1;
-            Adag_h(mu, c0, c1, d0, d1);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
-                acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
-                acc.s[2].c[a] = acc.s[2].c[a] - d0.c[a];
-                acc.s[3].c[a] = acc.s[3].c[a] - d1.c[a];
-            }
-        }
-        if (x[mu] > 0) {
-            int y[4] = {x[0], x[1], x[2], x[3]};
-            y[mu] -= 1;
-            const int nl = CB::index(y);
-            spinor<T> p;
-            ldr(0, nl, p);
-            vec3<T> a0, a1;
-            A_dn(mu, p.s[2], p.s[3], a0, a1);
-            vec3<T> h0, h1;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                h0.c[a] = p.s[0].c[a] + a0.c[a];
-                h1.c[a] = p.s[1].c[a] + a1.c[a];
-            }
-            su3<T> u;
-            lds_link<T, B>(lk, mu, nl, u);
-            const vec3<T> c0 = mul_dag(u, h0), c1 = mul_dag(u, h1);
-            vec3<T> d0, d1;
-            Adag_h(mu, c0, c1, d0, d1);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
-                acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
-                acc.s[2].c[a] = acc.s[2].c[a] + d0.c[a];
-                acc.s[3].c[a] = acc.s[3].c[a] + d1.c[a];
-            }
-        }
-    }
+    for (int mu = 0; mu < 4; ++mu) hop_dir_lds_rt<T, B>(mu, sh, off, lk, l, x, acc);
 }
 
 template <typename T, int MODE, int B>
@@ -448,6 +446,243 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_block_mr_cube(Geo g, const int3
     }
 }
 
+// ---------------------------------------------------------------- 4^4 blocks, direction-parallel
+// The same algorithm with 4 Vh threads per block.  In a hop phase over the
+// sites of one parity, thread (mu, h) computes the two in-block hops of
+// direction mu at site h of that parity and leaves its partial sum in LDS;
+// in the vector phases thread (q, h) owns spin q of site h, so the MR updates
+// and inner products are spread over all threads.  mu and q are uniform per
+// wavefront (Vh is a multiple of 64).  LDS: both half fields, the block's
+// links (two rows) and the four partial sums (FP32: 123 KB for 4^4).
+template <typename T, int B> struct DirLds {
+    typedef typename C2<T>::type T2;
+    static constexpr int Vb = Cube<B>::Vb, Vh = Cube<B>::Vh, NT = 4 * Vh;
+    T2 she[12 * Vh];
+    T2 sho[12 * Vh];
+    T2 lk[4 * 6 * Vb];
+    T2 part[4 * 12 * Vh];
+    T red[3][NT / 64];
+    T alpha[2];
+};
+
+// partial sum of thread (mu, h) into LDS
+template <typename T, int Vh>
+__device__ __forceinline__ void put_part(typename C2<T>::type *part, int mu, int h, const spinor<T> &acc)
+{
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) st<T>(part, (mu * 12 + 3 * sp + a) * Vh + h, acc.s[sp].c[a]);
+}
+
+// spin q of site h summed over the four partial sums
+template <typename T, int Vh>
+__device__ __forceinline__ void sum_part(const typename C2<T>::type *part, int q, int h, cx<T> v[3])
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int c = 3 * q + a;
+        v[a] = (ld<T>(part, c * Vh + h) + ld<T>(part, (12 + c) * Vh + h)) +
+               (ld<T>(part, (24 + c) * Vh + h) + ld<T>(part, (36 + c) * Vh + h));
+    }
+}
+
+template <typename T, int MODE, int B>
+__global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const int32_t *__restrict__ active,
+                                                                  UTab<T> Utab, long n,
+                                                                  const int32_t *__restrict__ sched,
+                                                                  const typename C2<T>::type *__restrict__ src,
+                                                                  typename C2<T>::type *__restrict__ dst, T kappa,
+                                                                  int nmr)
+{
+    typedef Cube<B> CB;
+    constexpr int Vb = CB::Vb, Vh = CB::Vh, NT = 4 * Vh;
+    static_assert(Vh % 64 == 0, "a wavefront covers sites of one direction / spin only");
+    __shared__ DirLds<T, B> S;
+    const int m = blockIdx.y;
+    if (active && !active[m]) return;
+    const typename C2<T>::type *__restrict__ U = Utab[m];
+    src += m * n;
+    dst += m * n;
+    const int slot = sched[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int w4 = __builtin_amdgcn_readfirstlane(tid / Vh);  // mu in hop phases, spin q in vector phases
+    const int h = tid % Vh;
+    int xe[4], xo[4];
+    CB::coords(h, xe);
+    CB::coords(Vh + h, xo);
+    const long be = (long)slot * 12 * Vb + h, bo = be + Vh;
+
+    // stage the block's links (two rows) in LDS
+    {
+        const auto *Ug = as_global(U);
+        const long base = (long)slot * 4 * 9 * Vb;
+        for (int i = tid; i < 4 * 6 * Vb; i += NT) {
+            const int mu = i / (6 * Vb), e = (i / Vb) % 6, l = i % Vb;
+            st<T>(S.lk, i, ldg<T>(Ug, base + (long)(mu * 9 + e) * Vb + l));
+        }
+    }
+
+    // residual of the block system, spin q of even site h (re) and odd site h (ro)
+    cx<T> re[3], ro[3], v[3];
+    if (MODE == 0) {
+        int nbr[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
+        const auto *Ug = as_global(U);
+        const auto *xg = as_global((const typename C2<T>::type *)dst);
+        int nmu = g.slot_blk[slot];
+        for (int d = 0; d < w4; ++d) nmu /= g.NB[d];
+        nmu %= g.NB[w4];
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            const int *x = par ? xo : xe;
+            const int l = par * Vh + h;
+            // boundary sign of wrapping links (the third row is rebuilt)
+            T wf = 1, wb = 1;
+            if (g.bc[w4] < 0) {
+                if (nmu == g.NB[w4] - 1 && x[w4] == B - 1) wf = -1;
+                if (nmu == 0 && x[w4] == 0) wb = -1;
+            }
+            spinor<T> acc;
+            zero(acc);
+            switch (w4) {
+            case 0: hop_dir_cube<T, HOPS_ALL, B, 0, 0, 1>(Ug, xg, slot, nbr, l, x, 0, acc, wf, wb); break;
+            case 1: hop_dir_cube<T, HOPS_ALL, B, 0, 1, 1>(Ug, xg, slot, nbr, l, x, 0, acc, wf, wb); break;
+            case 2: hop_dir_cube<T, HOPS_ALL, B, 0, 2, 1>(Ug, xg, slot, nbr, l, x, 0, acc, wf, wb); break;
+            default: hop_dir_cube<T, HOPS_ALL, B, 0, 3, 1>(Ug, xg, slot, nbr, l, x, 0, acc, wf, wb); break;
+            }
+            put_part<T, Vh>(S.part, w4, h, acc);
+            __syncthreads();
+            sum_part<T, Vh>(S.part, w4, h, v);
+            const long b = par ? bo : be;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const long i = b + (long)(3 * w4 + a) * Vb;
+                const cx<T> r = ld<T>(src, i) - ld<T>(dst, i) + scale(kappa, v[a]);
+                if (par) ro[a] = r;
+                else re[a] = r;
+            }
+            __syncthreads();
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            re[a] = ld<T>(src, be + (long)(3 * w4 + a) * Vb);
+            ro[a] = ld<T>(src, bo + (long)(3 * w4 + a) * Vb);
+        }
+    }
+
+    // rhs_e = r_e + kappa H_eo r_o
+#pragma unroll
+    for (int a = 0; a < 3; ++a) st<T>(S.sho, (3 * w4 + a) * Vh + h, ro[a]);
+    __syncthreads();
+    {
+        spinor<T> acc;
+        zero(acc);
+        hop_dir_lds_rt<T, B>(w4, S.sho, Vh, S.lk, h, xe, acc);
+        put_part<T, Vh>(S.part, w4, h, acc);
+    }
+    __syncthreads();
+    cx<T> rho[3], del[3];
+    sum_part<T, Vh>(S.part, w4, h, v);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rho[a] = re[a] + scale(kappa, v[a]);
+        del[a] = mk<T>(0, 0);
+        st<T>(S.she, (3 * w4 + a) * Vh + h, rho[a]);
+    }
+
+    // MR steps on (1 - kappa^2 H_eo H_oe)
+    const T k2 = kappa * kappa;
+    for (int it = 0; it < nmr; ++it) {
+        __syncthreads();
+        {  // t_o = H_oe rho
+            spinor<T> acc;
+            zero(acc);
+            hop_dir_lds_rt<T, B>(w4, S.she, 0, S.lk, Vh + h, xo, acc);
+            put_part<T, Vh>(S.part, w4, h, acc);
+        }
+        __syncthreads();
+        sum_part<T, Vh>(S.part, w4, h, v);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) st<T>(S.sho, (3 * w4 + a) * Vh + h, v[a]);
+        __syncthreads();
+        {  // H_eo t_o
+            spinor<T> acc;
+            zero(acc);
+            hop_dir_lds_rt<T, B>(w4, S.sho, Vh, S.lk, h, xe, acc);
+            put_part<T, Vh>(S.part, w4, h, acc);
+        }
+        __syncthreads();
+        sum_part<T, Vh>(S.part, w4, h, v);
+        T pr = 0, pi = 0, pp = 0;
+        cx<T> p[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            p[a] = rho[a] - scale(k2, v[a]);
+            const cx<T> q = conjmul(p[a], rho[a]);
+            pr += q.re;
+            pi += q.im;
+            pp += p[a].re * p[a].re + p[a].im * p[a].im;
+        }
+        pr = wave_sum(pr, 64);
+        pi = wave_sum(pi, 64);
+        pp = wave_sum(pp, 64);
+        if ((tid & 63) == 0) {
+            S.red[0][tid >> 6] = pr;
+            S.red[1][tid >> 6] = pi;
+            S.red[2][tid >> 6] = pp;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            T sr = 0, si = 0, sq = 0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) {
+                sr += S.red[0][w];
+                si += S.red[1][w];
+                sq += S.red[2][w];
+            }
+            S.alpha[0] = sq > 0 ? sr / sq : T(0);
+            S.alpha[1] = sq > 0 ? si / sq : T(0);
+        }
+        __syncthreads();
+        const cx<T> al = mk<T>(S.alpha[0], S.alpha[1]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            del[a] = del[a] + al * rho[a];
+            rho[a] = rho[a] - al * p[a];
+            st<T>(S.she, (3 * w4 + a) * Vh + h, rho[a]);
+        }
+    }
+
+    // d_o = r_o + kappa H_oe d_e
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 3; ++a) st<T>(S.she, (3 * w4 + a) * Vh + h, del[a]);
+    __syncthreads();
+    {
+        spinor<T> acc;
+        zero(acc);
+        hop_dir_lds_rt<T, B>(w4, S.she, 0, S.lk, Vh + h, xo, acc);
+        put_part<T, Vh>(S.part, w4, h, acc);
+    }
+    __syncthreads();
+    sum_part<T, Vh>(S.part, w4, h, v);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cx<T> dodd = ro[a] + scale(kappa, v[a]);
+        const long ie = be + (long)(3 * w4 + a) * Vb, io = bo + (long)(3 * w4 + a) * Vb;
+        if (MODE == 0) {  // x += d (this workgroup alone reads x of this block after its residual)
+            st<T>(dst, ie, ld<T>(dst, ie) + del[a]);
+            st<T>(dst, io, ld<T>(dst, io) + dodd);
+        } else {
+            st<T>(dst, ie, del[a]);
+            st<T>(dst, io, dodd);
+        }
+    }
+}
+
 template <typename T, int MODE>
 bool launch_mr_cube4(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *src, T2<T> *dst, T kappa, int nmr,
                      int slot0, int nslots, hipStream_t s)
@@ -456,8 +691,12 @@ bool launch_mr_cube4(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *src, 
     if (!U.su3 || g.B[0] != 4 || g.B[1] != 4 || g.B[2] != 4 || g.B[3] != 4) return false;
     const int si = sched_index(g, slot0, nslots);
     if (si < 0) return false;
-    k_block_mr_cube<T, MODE, 4><<<dim3(nslots, sy.M), 256, 0, s>>>(g, sy.active, U.tab, sy.n, g.sched[si], src, dst,
-                                                                   kappa, nmr);
+    if constexpr (sizeof(T) == 4)  // the FP64 partial sums would not fit in LDS next to the links
+        k_block_mr_dir<T, MODE, 4><<<dim3(nslots, sy.M), 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, U.tab, sy.n,
+                                                                                g.sched[si], src, dst, kappa, nmr);
+    else
+        k_block_mr_cube<T, MODE, 4><<<dim3(nslots, sy.M), 256, 0, s>>>(g, sy.active, U.tab, sy.n, g.sched[si], src,
+                                                                       dst, kappa, nmr);
     return true;
 }
 

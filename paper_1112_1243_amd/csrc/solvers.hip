@@ -103,6 +103,134 @@ void read_x(const double2 *dev, int count, int stride, std::vector<double> &out,
     for (int m = 0; m < count; ++m) out[m] = tmp[(size_t)m * stride].x;
 }
 
+// Asynchronous read-back of per-system device flags into the context's
+// pinned buffer (two slots).  A solver loop posts the flags after queueing
+// iteration j and inspects those of iteration j - 1, so the GPU already has
+// iteration j while the host waits.
+struct FlagPoll {
+    wdr_ctx *c;
+    int M;
+    bool ok = false;
+    FlagPoll(wdr_ctx *c_, int M_) : c(c_), M(M_)
+    {
+        if (c->poll_cap < 2 * (size_t)M) {
+            if (c->poll_host) (void)hipHostFree(c->poll_host);
+            c->poll_host = nullptr;
+            c->poll_cap = 0;
+            if (hipHostMalloc((void **)&c->poll_host, 2 * (size_t)M * sizeof(int32_t)) != hipSuccess) return;
+            c->poll_cap = 2 * (size_t)M;
+        }
+        for (auto &e : c->poll_ev)
+            if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return;
+        ok = true;
+    }
+    int32_t *slot(int k) const { return c->poll_host + (size_t)k * M; }
+    void post(const int32_t *dev, int k, hipStream_t s) const
+    {
+        (void)hipMemcpyAsync(slot(k), dev, (size_t)M * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        (void)hipEventRecord(c->poll_ev[k], s);
+    }
+    // waits for the copy posted in slot k; true if every flag there is 0
+    bool none(int k) const
+    {
+        (void)hipEventSynchronize(c->poll_ev[k]);
+        for (int m = 0; m < M; ++m)
+            if (slot(k)[m]) return false;
+        return true;
+    }
+};
+
+// ---- FGCR control on the device (one thread per system)
+
+__global__ void k_fgcr_init(int M, const double2 *nr, double *bn2, int32_t *alive, int32_t *act, int32_t *cnt,
+                            int32_t *its)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const double b = nr[m].x;
+    bn2[m] = b;
+    alive[m] = act[m] = b > 0;
+    cnt[m] = its[m] = 0;
+}
+
+// after Krylov step j: count it and stop the cycle of a converged system
+__global__ void k_fgcr_inner(int M, int j, const double2 *nr, const double *bn2, double tol2, int max_iter,
+                             int32_t *act, int32_t *cnt, int32_t *its)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M || !act[m]) return;
+    cnt[m] = j + 1;
+    const int k = ++its[m];
+    if (!(nr[m].x > tol2 * bn2[m]) || k >= max_iter) act[m] = 0;
+}
+
+// coefficients of x += sum_l al_l phi_l from the Gram-Schmidt data:
+// D phi_j = b_j chi_j + sum_{l<j} A_lj chi_l, r-component c_l along chi_l
+__global__ void k_fgcr_backsub(int M, const double2 *A, const double2 *bj, const double2 *cj, const int32_t *cnt,
+                               const int32_t *alive, double2 *al)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M || !alive[m]) return;
+    const int k = cnt[m];
+    for (int l = k - 1; l >= 0; --l) {
+        double re = cj[m * 16 + l].x, im = cj[m * 16 + l].y;
+        for (int jj = l + 1; jj < k; ++jj) {
+            const double2 a0 = A[(size_t)m * 256 + jj * 16 + l], a1 = A[(size_t)M * 256 + (size_t)m * 256 + jj * 16 + l];
+            const double ar = a0.x + a1.x, ai = a0.y + a1.y;
+            const double2 aj = al[m * 16 + jj];
+            re -= ar * aj.x - ai * aj.y;
+            im -= ar * aj.y + ai * aj.x;
+        }
+        const double bb = sqrt(bj[m * 16 + l].x);
+        al[m * 16 + l] = make_double2(re / bb, im / bb);
+    }
+}
+
+// after the true residual of a cycle: retire converged systems, start the next cycle
+__global__ void k_fgcr_outer(int M, const double2 *nr, const double *bn2, double tol2, int max_iter,
+                             const int32_t *its, int32_t *alive, int32_t *act, int32_t *cnt)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    if (alive[m]) {
+        const double r = nr[m].x;
+        if (!isfinite(r) || r <= tol2 * bn2[m] || its[m] >= max_iter) alive[m] = 0;
+    }
+    act[m] = alive[m];
+    cnt[m] = 0;
+}
+
+// ---- block-solve control on the device (one thread per system): the worst
+// relative residual over the selected blocks decides convergence
+
+__global__ void k_block_init(int M, int nblk, int slot0, int ns, const double *bn, int32_t *alive, int32_t *its,
+                             double *worst)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    bool any = false;
+    for (int i = slot0; i < slot0 + ns; ++i) any = any || bn[(size_t)m * nblk + i] > 0;
+    alive[m] = any;
+    its[m] = 0;
+    worst[m] = 0;
+}
+
+__global__ void k_block_check(int M, int nblk, int slot0, int ns, const double *bn, const double *rn, double tol2,
+                              int32_t *alive, int32_t *its, double *worst)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M || !alive[m]) return;
+    ++its[m];
+    double wv = 0;
+    for (int i = slot0; i < slot0 + ns; ++i) {
+        const size_t k = (size_t)m * nblk + i;
+        if (bn[k] > 0) wv = fmax(wv, rn[k] / bn[k]);
+    }
+    if (!isfinite(wv)) wv = INFINITY;
+    worst[m] = wv;
+    if (!(wv > tol2)) alive[m] = 0;
+}
+
 }  // namespace
 
 void apply_D64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const double2 *in, double2 *out,
@@ -168,8 +296,7 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
     // scalars: A[2][M][16][16] (two CGS passes), bj[M][16], cj[M][16], al[M][16], nr[M]
     Work scal(c, sizeof(double2) * ((size_t)M * (2 * 256 + 16 * 3 + 1)));
     Work red(c, sizeof(double) * red_scratch(M));
-    DevFlags act(c, M), alive(c, M), cnt(c, M);
-    if (!tab.ok() || !scal.ok() || !red.ok() || !act.w.ok() || !alive.w.ok() || !cnt.w.ok()) return WDR_ENOMEM;
+    if (!tab.ok() || !scal.ok() || !red.ok()) return WDR_ENOMEM;
     std::vector<const void *> hp(2 * nkv);
     for (int j = 0; j < nkv; ++j) {
         hp[j] = bufs[j]->as<void>();
@@ -184,22 +311,21 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
     double2 *bj = A + (size_t)M * 512, *cj = bj + (size_t)M * 16, *al = cj + (size_t)M * 16, *nr = al + (size_t)M * 16;
 
     const Sys all = all_sys(c, M);
-    std::vector<double> bn2, rn2;
+    // per-system control state on the device: bn2 (|b|^2), act (in the current
+    // cycle), alive (not converged), cnt (Krylov vectors of the cycle), its
+    Work ctl(c, sizeof(double) * M + 4 * sizeof(int32_t) * M);
+    FlagPoll poll(c, M);
+    if (!ctl.ok() || !poll.ok) return WDR_ENOMEM;
+    double *bn2 = ctl.as<double>();
+    int32_t *act = reinterpret_cast<int32_t *>(bn2 + M), *alive = act + M, *cnt = alive + M, *its = cnt + M;
+    const double tol2 = tol * tol;
+    const unsigned nbm = (unsigned)((M + 63) / 64);
     launch_norm2<double>(all, b, red.as<double>(), nr, 1, s);
-    read_x(nr, M, 1, bn2, s);
+    k_fgcr_init<<<nbm, 64, 0, s>>>(M, nr, bn2, alive, act, cnt, its);
     launch_zero<double>(x, n * M, s);
     launch_convert<double, double>(all, b, r, s);
-    st.assign(M, Stats());
-    std::vector<int> its(M, 0);
-    for (int m = 0; m < M; ++m) alive.h[m] = bn2[m] > 0;
-    alive.upload(s);
-    std::vector<double2> hA((size_t)M * 512), hb((size_t)M * 16), hc((size_t)M * 16), ha((size_t)M * 16);
-    rn2 = bn2;
-    while (alive.any()) {
-        act.h = alive.h;
-        act.upload(s);
-        std::fill(cnt.h.begin(), cnt.h.end(), 0);
-        const Sys sa{M, act.d(), n};
+    const Sys sa{M, act, n}, sw{M, alive, n};
+    for (;;) {
         for (int j = 0; j < nkv; ++j) {
             wdr_status e = sap64(c, sa, U, kappa, sp, r, phi(j), s);
             if (e != WDR_OK) return e;
@@ -217,68 +343,35 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
             launch_dot<double>(sa, chi(j), r, red.as<double>(), cj + j, 16, s);
             launch_axpy_dev(sa, cj + j, 16, -1.0, chi(j), r, s);
             launch_norm2<double>(sa, r, red.as<double>(), nr, 1, s);
-            std::vector<double> cur;
-            read_x(nr, M, 1, cur, s);
-            bool changed = false;
-            for (int m = 0; m < M; ++m) {
-                if (!act.h[m]) continue;
-                rn2[m] = cur[m];
-                cnt.h[m] = j + 1;
-                ++its[m];
-                if (!(rn2[m] > tol * tol * bn2[m]) || its[m] >= sp.max_iter) {
-                    act.h[m] = 0;
-                    changed = true;
-                }
-            }
-            if (!act.any()) break;
-            if (changed) act.upload(s);
+            k_fgcr_inner<<<nbm, 64, 0, s>>>(M, j, nr, bn2, tol2, sp.max_iter, act, cnt, its);
+            poll.post(act, j & 1, s);
+            // step j is queued; stop once step j - 1 left no system active
+            // (step j then runs as a no-op)
+            if (j > 0 && poll.none((j - 1) & 1)) break;
         }
-        // back substitution per system: D phi_j = b_j chi_j + sum_{l<j} A_lj chi_l
-        WDR_HIP(hipMemcpyAsync(hA.data(), A, hA.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
-        WDR_HIP(hipMemcpyAsync(hb.data(), bj, hb.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
-        WDR_HIP(hipMemcpyAsync(hc.data(), cj, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
-        WDR_HIP(hipStreamSynchronize(s));
-        for (int m = 0; m < M; ++m) {
-            const int k = cnt.h[m];
-            for (int l = k - 1; l >= 0; --l) {
-                double re = hc[m * 16 + l].x, im = hc[m * 16 + l].y;
-                for (int jj = l + 1; jj < k; ++jj) {
-                    const double2 a0 = hA[(size_t)m * 256 + jj * 16 + l], a1 = hA[(size_t)M * 256 + m * 256 + jj * 16 + l];
-                    const double ar = a0.x + a1.x, ai = a0.y + a1.y;
-                    const double2 aj = ha[m * 16 + jj];
-                    re -= ar * aj.x - ai * aj.y;
-                    im -= ar * aj.y + ai * aj.x;
-                }
-                const double bb = std::sqrt(hb[m * 16 + l].x);
-                ha[m * 16 + l] = make_double2(re / bb, im / bb);
-            }
-        }
-        WDR_HIP(hipMemcpyAsync(al, ha.data(), ha.size() * sizeof(double2), hipMemcpyHostToDevice, s));
-        cnt.upload(s);
-        const Sys sw{M, alive.d(), n};
-        launch_multi_axpy(sw, al, 16, 1.0, phis, nkv, cnt.d(), x, 1, s);
+        k_fgcr_backsub<<<nbm, 64, 0, s>>>(M, A, bj, cj, cnt, alive, al);
+        launch_multi_axpy(sw, al, 16, 1.0, phis, nkv, cnt, x, 1, s);
         // true residual
         apply_D64(c, sw, U, kappa, x, t, s);
         launch_sub(sw, b, t, r, s);
         launch_norm2<double>(sw, r, red.as<double>(), nr, 1, s);
-        std::vector<double> cur;
-        read_x(nr, M, 1, cur, s);
-        bool changed = false;
-        for (int m = 0; m < M; ++m) {
-            if (!alive.h[m]) continue;
-            rn2[m] = cur[m];
-            if (!std::isfinite(rn2[m]) || rn2[m] <= tol * tol * bn2[m] || its[m] >= sp.max_iter) {
-                alive.h[m] = 0;
-                changed = true;
-            }
-        }
-        if (changed) alive.upload(s);
+        k_fgcr_outer<<<nbm, 64, 0, s>>>(M, nr, bn2, tol2, sp.max_iter, its, alive, act, cnt);
+        poll.post(alive, 0, s);
+        if (poll.none(0)) break;
     }
+    std::vector<double> hbn2(M), rn2;
+    std::vector<int32_t> hits(M);
+    WDR_HIP(hipMemcpyAsync(hbn2.data(), bn2, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+    WDR_HIP(hipMemcpyAsync(hits.data(), its, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+    read_x(nr, M, 1, rn2, s);
+    const std::vector<double> &bn2h = hbn2;
+    const std::vector<int32_t> &itsh = hits;
+    st.assign(M, Stats());
     bool ok = true;
     for (int m = 0; m < M; ++m) {
-        st[m].iters = its[m];
-        st[m].total = its[m];
-        st[m].rel = bn2[m] > 0 ? std::sqrt(rn2[m] / bn2[m]) : 0.0;
+        st[m].iters = itsh[m];
+        st[m].total = itsh[m];
+        st[m].rel = bn2h[m] > 0 ? std::sqrt(rn2[m] / bn2h[m]) : 0.0;
         st[m].converged = st[m].rel <= tol;
         ok = ok && st[m].converged;
     }
@@ -405,9 +498,14 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
     const long n = field_n(c);
     const size_t fb = field_bytes(c, WDR_F64) * M, fb32 = field_bytes(c, WDR_F32) * M;
     Work rw(c, fb), tw(c, fb), d32(c, fb32), r32(c, fb32), d64(c, fb), nrm(c, 2 * sizeof(double) * g.nblk * M);
-    DevFlags alive(c, M);
-    if (!rw.ok() || !tw.ok() || !d32.ok() || !r32.ok() || !d64.ok() || !nrm.ok() || !alive.w.ok()) return WDR_ENOMEM;
+    Work ctl(c, sizeof(double) * M + 2 * sizeof(int32_t) * M);
+    FlagPoll poll(c, M);
+    if (!rw.ok() || !tw.ok() || !d32.ok() || !r32.ok() || !d64.ok() || !nrm.ok() || !ctl.ok() || !poll.ok)
+        return WDR_ENOMEM;
     double2 *r = rw.as<double2>(), *t = tw.as<double2>();
+    double *worst = ctl.as<double>();
+    int32_t *alive = reinterpret_cast<int32_t *>(worst + M), *its = alive + M;
+    const unsigned nbm = (unsigned)((M + 63) / 64);
     const Sys all = all_sys(c, M);
     launch_zero<double>(x, n * M, s);
     launch_convert<double, double>(all, b, r, s);
@@ -417,25 +515,15 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
     launch_zero<double>(d64.as<double2>(), n * M, s);
     double *bn = nrm.as<double>(), *rn = bn + (size_t)g.nblk * M;
     launch_slot_norm2(g, all, r, bn, slot0, ns, s);
-    std::vector<double> hb((size_t)g.nblk * M), hr((size_t)g.nblk * M);
-    WDR_HIP(hipMemcpyAsync(hb.data(), bn, hb.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    WDR_HIP(hipStreamSynchronize(s));
-    std::vector<double> worst(M, 0.0);
-    std::vector<int> its(M, 0);
-    for (int m = 0; m < M; ++m) {
-        bool any = false;
-        for (int i = slot0; i < slot0 + ns; ++i) any = any || hb[(size_t)m * g.nblk + i] > 0;
-        alive.h[m] = any;
-    }
-    alive.upload(s);
+    k_block_init<<<nbm, 64, 0, s>>>(M, g.nblk, slot0, ns, bn, alive, its, worst);
     const int nmr = 16;
-    for (int round = 0; round < 40 && alive.any(); ++round) {
-        const Sys sa{M, alive.d(), n};
+    const Sys sa{M, alive, n};
+    for (int round = 0; round < 40; ++round) {
         if (sp.inner == WDR_F64) {
             launch_block_mr<double>(g, sa, U.u64, r, d64.as<double2>(), kappa, nmr, slot0, ns, s);
             launch_add_to64<double>(sa, d64.as<double2>(), x, s);
         } else {
-            launch_convert<float, double>(all, r, r32.as<float2>(), s);
+            launch_convert<float, double>(sa, r, r32.as<float2>(), s);
             launch_block_mr<float>(g, sa, U.u32, r32.as<float2>(), d32.as<float2>(), (float)kappa, nmr, slot0, ns, s);
             launch_add_to64<float>(sa, d32.as<float2>(), x, s);
         }
@@ -444,31 +532,22 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
         launch_sub(sa, b, t, r, s);
         launch_keep_slots(g, sa, r, slot0, ns, s);
         launch_slot_norm2(g, sa, r, rn, slot0, ns, s);
-        WDR_HIP(hipMemcpyAsync(hr.data(), rn, hr.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        WDR_HIP(hipStreamSynchronize(s));
-        bool changed = false;
-        for (int m = 0; m < M; ++m) {
-            if (!alive.h[m]) continue;
-            ++its[m];
-            double wv = 0;
-            for (int i = slot0; i < slot0 + ns; ++i) {
-                const size_t k = (size_t)m * g.nblk + i;
-                if (hb[k] > 0) wv = std::max(wv, hr[k] / hb[k]);
-            }
-            worst[m] = wv;
-            if (!std::isfinite(wv) || wv <= tol * tol) {
-                alive.h[m] = 0;
-                changed = true;
-            }
-        }
-        if (changed) alive.upload(s);
+        k_block_check<<<nbm, 64, 0, s>>>(M, g.nblk, slot0, ns, bn, rn, tol * tol, alive, its, worst);
+        poll.post(alive, round & 1, s);
+        // round is queued; stop once round - 1 left no system alive
+        if (round > 0 && poll.none((round - 1) & 1)) break;
     }
+    std::vector<double> hworst(M);
+    std::vector<int32_t> hits(M);
+    WDR_HIP(hipMemcpyAsync(hworst.data(), worst, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+    WDR_HIP(hipMemcpyAsync(hits.data(), its, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+    WDR_HIP(hipStreamSynchronize(s));
     bool ok = true;
     st.assign(M, Stats());
     for (int m = 0; m < M; ++m) {
-        st[m].iters = its[m];
-        st[m].total = its[m];
-        st[m].rel = std::sqrt(worst[m]);
+        st[m].iters = hits[m];
+        st[m].total = hits[m];
+        st[m].rel = std::sqrt(hworst[m]);
         st[m].converged = st[m].rel <= tol;
         ok = ok && st[m].converged;
     }
