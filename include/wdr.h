@@ -99,7 +99,18 @@ typedef struct {
     wdr_noise_kind noise;
     uint64_t seed;     /* Philox4x64-10 key (seed, 3) */
     wdr_solver_params sp;
+    int32_t max_batch; /* most (proposal, step, noise) samples solved as the
+                          systems of one batched pass; 0 = as many as fit */
 } wdr_est_params;
+
+/* One proposal U -> U' of wdr_logdet_ratio_batch. */
+typedef struct {
+    struct wdr_ctx *ctx;          /* context of the proposal's lattice */
+    const struct wdr_gauge *U;    /* current links (a handle of ctx) */
+    const struct wdr_gauge *Up;   /* proposed links (a handle of ctx) */
+    double kappa;
+    uint64_t seed;                /* noise key (seed, 3) of this proposal */
+} wdr_proposal;
 
 typedef struct wdr_ctx wdr_ctx;
 typedef struct wdr_gauge wdr_gauge;
@@ -230,6 +241,22 @@ wdr_status wdr_apply_schur(wdr_ctx *ctx, const wdr_gauge *U, double kappa, const
 wdr_status wdr_logdet_ratio(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *Up, double kappa,
                             const wdr_est_params *p, double *host_samples, double *host_log_ratio,
                             wdr_solve_info *host_info, void *stream);
+
+/* The estimate of wdr_logdet_ratio for n independent proposals (possibly on
+ * lattices of different sizes) in one batched pass.  Proposals that share a
+ * context are solved together: every (proposal, step, noise) sample is one
+ * system of the same launches, with its own links, kappa and noise key
+ * (props[j].seed; p->seed is not used).  Groups on different contexts run
+ * concurrently, each on a stream of its context ordered after `stream`;
+ * the call returns when all are done.  host_samples: the proposals in order,
+ * each n_steps*n_noise values (times the nblocks of its context for BLOCKS);
+ * host_log_ratios: n values; host_info: summed iterations, the worst
+ * residual over all solves.  Proposals of one context must all use SU(3)
+ * links or none do (mixing only costs speed).  A context may appear in one
+ * call at a time and no other call may use it meanwhile. */
+wdr_status wdr_logdet_ratio_batch(int32_t n, const wdr_proposal *props, const wdr_est_params *p,
+                                  double *host_samples, double *host_log_ratios, wdr_solve_info *host_info,
+                                  void *stream);
 
 #ifdef __cplusplus
 }

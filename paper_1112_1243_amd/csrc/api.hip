@@ -1,5 +1,7 @@
 // extern "C" entry points of include/wdr.h: argument checks, canonical <->
 // internal layout conversion, and dispatch to the drivers.
+#include <algorithm>
+#include <thread>
 #include <chrono>
 #include <cmath>
 
@@ -201,7 +203,7 @@ wdr_status wdr_noise(wdr_ctx *c, wdr_noise_kind kind, uint64_t seed, int32_t ste
     if (!a.ok() || !idx.ok()) return WDR_ENOMEM;
     const int32_t sk[2] = {step, k};
     WDR_HIP(hipMemcpyAsync(idx.as<void>(), sk, sizeof(sk), hipMemcpyHostToDevice, S(stream)));
-    launch_noise(c->g, all_sys(c, 1), kind, seed, idx.as<int32_t>(), idx.as<int32_t>() + 1, black_only,
+    launch_noise(c->g, all_sys(c, 1), kind, seed, nullptr, idx.as<int32_t>(), idx.as<int32_t>() + 1, black_only,
                  a.as<double2>(), S(stream));
     launch_unpack_spinor<double>(c->g, a.as<double2>(), reinterpret_cast<double2 *>(out), S(stream));
     return finish(S(stream));
@@ -391,6 +393,17 @@ wdr_status wdr_apply_schur(wdr_ctx *c, const wdr_gauge *U, double kappa, const w
     return e != WDR_OK ? e : se;
 }
 
+static wdr_status check_est(const wdr_ctx *c, const wdr_est_params *p)
+{
+    if (!p || p->n_steps < 1 || p->n_noise < 1 || p->max_batch < 0 ||
+        (p->op != WDR_OP_FULL && p->op != WDR_OP_SCHUR && p->op != WDR_OP_BLOCKS) ||
+        (p->noise != WDR_NOISE_Z2 && p->noise != WDR_NOISE_GAUSS)) {
+        set_error("invalid estimator parameters");
+        return WDR_EINVAL;
+    }
+    return check_params(c, p->sp, p->op != WDR_OP_FULL);
+}
+
 wdr_status wdr_logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, double kappa,
                             const wdr_est_params *p, double *samples, double *log_ratio, wdr_solve_info *info,
                             void *stream)
@@ -399,19 +412,114 @@ wdr_status wdr_logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up,
     wdr_status e;
     if ((e = check_gauge(c, U)) != WDR_OK || (e = check_gauge(c, Up)) != WDR_OK) return e;
     if ((e = check_kappa(kappa)) != WDR_OK) return e;
-    if (!p || p->n_steps < 1 || p->n_noise < 1 || (p->op != WDR_OP_FULL && p->op != WDR_OP_SCHUR && p->op != WDR_OP_BLOCKS) ||
-        (p->noise != WDR_NOISE_Z2 && p->noise != WDR_NOISE_GAUSS)) {
-        set_error("invalid estimator parameters");
-        return WDR_EINVAL;
-    }
-    if ((e = check_params(c, p->sp, p->op != WDR_OP_FULL)) != WDR_OK) return e;
+    if ((e = check_est(c, p)) != WDR_OK) return e;
     WDR_HIP(hipSetDevice(c->device));
     const double t0 = now();
     Stats st;
-    e = logdet_ratio(c, U, Up, kappa, *p, samples, log_ratio, st, S(stream));
+    e = logdet_ratio(c, {Proposal{U, Up, kappa, p->seed}}, *p, samples, log_ratio, st, S(stream));
     (void)hipStreamSynchronize(S(stream));
     fill_info(info, st, now() - t0);
     if (e == WDR_OK) e = finish(S(stream));
+    return e;
+}
+
+wdr_status wdr_logdet_ratio_batch(int32_t n, const wdr_proposal *props, const wdr_est_params *p, double *samples,
+                                  double *log_ratios, wdr_solve_info *info, void *stream)
+{
+    if (n < 1 || !props) {
+        set_error("need at least one proposal");
+        return WDR_EINVAL;
+    }
+    // group the proposals by context, keeping their order inside a group
+    std::vector<wdr_ctx *> ctxs;
+    std::vector<std::vector<int>> members;
+    for (int j = 0; j < n; ++j) {
+        wdr_ctx *c = props[j].ctx;
+        if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
+        wdr_status e;
+        if ((e = check_gauge(c, props[j].U)) != WDR_OK || (e = check_gauge(c, props[j].Up)) != WDR_OK ||
+            (e = check_kappa(props[j].kappa)) != WDR_OK)
+            return e;
+        const size_t gi = std::find(ctxs.begin(), ctxs.end(), c) - ctxs.begin();
+        if (gi == ctxs.size()) {
+            if ((e = check_est(c, p)) != WDR_OK) return e;
+            if (!ctxs.empty() && c->device != ctxs[0]->device) {
+                set_error("all proposals of a batch must be on one device");
+                return WDR_EINVAL;
+            }
+            ctxs.push_back(c);
+            members.emplace_back();
+        }
+        members[gi].push_back(j);
+    }
+    WDR_HIP(hipSetDevice(ctxs[0]->device));
+    // output offsets of every proposal
+    const int per = p->n_steps * p->n_noise;
+    std::vector<size_t> off(n + 1, 0);
+    for (int j = 0; j < n; ++j) off[j + 1] = off[j] + (size_t)per * (p->op == WDR_OP_BLOCKS ? props[j].ctx->g.nblk : 1);
+    const size_t G = ctxs.size();
+    std::vector<std::vector<double>> gs(G), gl(G);
+    std::vector<Stats> gst(G);
+    std::vector<wdr_status> ge(G, WDR_OK);
+    std::vector<std::string> gmsg(G);
+    const double t0 = now();
+    auto run = [&](size_t gi, hipStream_t s) {
+        (void)hipSetDevice(ctxs[gi]->device);
+        std::vector<Proposal> pr;
+        size_t ns = 0;
+        for (int j : members[gi]) {
+            pr.push_back(Proposal{props[j].U, props[j].Up, props[j].kappa, props[j].seed});
+            ns += off[j + 1] - off[j];
+        }
+        gs[gi].resize(ns);
+        gl[gi].resize(pr.size());
+        ge[gi] = logdet_ratio(ctxs[gi], pr, *p, gs[gi].data(), gl[gi].data(), gst[gi], s);
+        (void)hipStreamSynchronize(s);
+        if (ge[gi] != WDR_OK) gmsg[gi] = wdr_last_error();
+    };
+    if (G == 1) {
+        run(0, S(stream));
+    } else {
+        // fork: each context's stream starts after the work queued on `stream`
+        hipEvent_t fork;
+        WDR_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        WDR_HIP(hipEventRecord(fork, S(stream)));
+        for (wdr_ctx *c : ctxs) {
+            if (!c->aux && hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking) != hipSuccess) {
+                (void)hipEventDestroy(fork);
+                set_error("stream creation failed");
+                return WDR_EDEVICE;
+            }
+            (void)hipStreamWaitEvent(c->aux, fork, 0);
+        }
+        std::vector<std::thread> th;
+        for (size_t gi = 0; gi < G; ++gi) th.emplace_back(run, gi, ctxs[gi]->aux);
+        for (auto &t : th) t.join();
+        (void)hipEventDestroy(fork);
+    }
+    // scatter the results back to proposal order
+    Stats tot;
+    wdr_status e = WDR_OK;
+    for (size_t gi = 0; gi < G; ++gi) {
+        size_t pos = 0;
+        for (size_t q = 0; q < members[gi].size(); ++q) {
+            const int j = members[gi][q];
+            const size_t len = off[j + 1] - off[j];
+            if (samples) std::copy(gs[gi].begin() + pos, gs[gi].begin() + pos + len, samples + off[j]);
+            if (log_ratios) log_ratios[j] = gl[gi][q];
+            pos += len;
+        }
+        tot.iters = std::max(tot.iters, gst[gi].iters);
+        tot.converged = tot.converged && gst[gi].converged;
+        tot.rel = std::max(tot.rel, gst[gi].rel);
+        tot.total += gst[gi].total;
+        // a hard error outranks non-convergence
+        if (ge[gi] != WDR_OK && (e == WDR_OK || e == WDR_ENOCONV)) {
+            e = ge[gi];
+            set_error(gmsg[gi]);
+        }
+    }
+    fill_info(info, tot, now() - t0);
     return e;
 }
 

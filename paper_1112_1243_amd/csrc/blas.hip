@@ -350,5 +350,6 @@ INST(float)
 template void launch_convert<double, float>(const Sys &, const float2 *, double2 *, hipStream_t);
 template void launch_convert<float, double>(const Sys &, const double2 *, float2 *, hipStream_t);
 template void launch_convert<double, double>(const Sys &, const double2 *, double2 *, hipStream_t);
+template void launch_convert<float, float>(const Sys &, const float2 *, float2 *, hipStream_t);
 
 }  // namespace wdr

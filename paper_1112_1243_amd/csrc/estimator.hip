@@ -52,27 +52,33 @@ constexpr double CHUNK_BYTES = 48e9;
 
 }  // namespace
 
-wdr_status logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, double kappa, const wdr_est_params &p,
-                        double *host_samples, double *host_log_ratio, Stats &st, hipStream_t s)
+wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wdr_est_params &p,
+                        double *host_samples, double *host_log_ratios, Stats &st, hipStream_t s)
 {
     const auto &g = c->g;
     const long n = field_n(c);
     const wdr_solver_params &sp = p.sp;
-    const int N = p.n_steps, K = p.n_noise, total = N * K;
+    const int P = (int)props.size(), N = p.n_steps, K = p.n_noise, per_prop = N * K, total = P * per_prop;
     const int nout = p.op == WDR_OP_BLOCKS ? g.nblk : 1;
 
-    // the path U_0 .. U_N
+    // the path U_0 .. U_N of every proposal
     std::vector<std::unique_ptr<TmpGauge>> path;
-    for (int i = 0; i <= N; ++i) {
-        path.emplace_back(new TmpGauge(c));
-        if (!path.back()->ok()) return WDR_ENOMEM;
-        make_path_gauge(c, U, Up, i, N, *path.back(), s);
+    int su3 = 1;
+    for (const Proposal &q : props) {
+        su3 = su3 && q.U->su3 && q.Up->su3;  // the geodesic stays in SU(3) when both ends are
+        for (int i = 0; i <= N; ++i) {
+            path.emplace_back(new TmpGauge(c));
+            if (!path.back()->ok()) return WDR_ENOMEM;
+            make_path_gauge(c, q.U, q.Up, i, N, *path.back(), s);
+        }
     }
+    auto point = [&](int prop, int i) -> TmpGauge & { return *path[(size_t)prop * (N + 1) + i]; };
 
     // chunk size: sample fields plus solver work space per system
     const size_t fb = field_bytes(c, WDR_F64);
     const int per_system = 8 + (sp.solver == WDR_SOLVER_FGCR_SAP ? 2 * sp.restart + 4 : 6);
-    const int Mmax = std::max(1, std::min(total, (int)(CHUNK_BYTES / ((double)per_system * fb))));
+    int Mmax = std::max(1, std::min(total, (int)(CHUNK_BYTES / ((double)per_system * fb))));
+    if (p.max_batch > 0) Mmax = std::min(Mmax, p.max_batch);
 
     std::vector<double> samples((size_t)total * nout, 0.0);
     std::vector<double> per((size_t)g.nblk * Mmax);
@@ -80,34 +86,42 @@ wdr_status logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, dou
     colour_slots(c, 0, b0, bn);
     std::vector<Stats> all_stats;
     wdr_status status = WDR_OK;
+    const double kappa0 = props[0].kappa;  // used only where a launch has no kappa table
 
     for (int m0 = 0; m0 < total; m0 += Mmax) {
         const int M = std::min(Mmax, total - m0);
         const size_t fbm = fb * M;
         Work eta(c, fbm), y(c, fbm), z(c, fbm), w(c, fbm), r(c, fbm), t(c, fbm), pr(c, sizeof(double) * g.nblk * M);
-        Work tabs(c, 4 * M * sizeof(void *)), idx(c, 2 * M * sizeof(int32_t));
-        if (!eta.ok() || !y.ok() || !z.ok() || !w.ok() || !r.ok() || !t.ok() || !pr.ok() || !tabs.ok() || !idx.ok())
+        Work tabs(c, 4 * M * sizeof(void *)), idx(c, 2 * M * sizeof(int32_t)), kw(c, M * sizeof(double)),
+            sw(c, M * sizeof(uint64_t));
+        if (!eta.ok() || !y.ok() || !z.ok() || !w.ok() || !r.ok() || !t.ok() || !pr.ok() || !tabs.ok() || !idx.ok() ||
+            !kw.ok() || !sw.ok())
             return WDR_ENOMEM;
-        // per-system tables: X on U_i, X' on U_{i+1}; noise (step, sample)
+        // per-system tables: X on U_i, X' on U_{i+1}; noise (step, sample, key); kappa
         std::vector<const void *> ht(4 * M);
         std::vector<int32_t> hi(2 * M);
+        std::vector<double> hk(M);
+        std::vector<uint64_t> hs(M);
         for (int j = 0; j < M; ++j) {
-            const int m = m0 + j, i = m / K, k = m % K;
-            ht[j] = path[i]->u64.as<void>();
-            ht[M + j] = path[i]->u32.as<void>();
-            ht[2 * M + j] = path[i + 1]->u64.as<void>();
-            ht[3 * M + j] = path[i + 1]->u32.as<void>();
+            const int m = m0 + j, q = m / per_prop, i = (m % per_prop) / K, k = m % K;
+            ht[j] = point(q, i).u64.as<void>();
+            ht[M + j] = point(q, i).u32.as<void>();
+            ht[2 * M + j] = point(q, i + 1).u64.as<void>();
+            ht[3 * M + j] = point(q, i + 1).u32.as<void>();
             hi[j] = i;
             hi[M + j] = k;
+            hk[j] = props[q].kappa;
+            hs[j] = props[q].seed;
         }
         WDR_HIP(hipMemcpyAsync(tabs.as<void>(), ht.data(), ht.size() * sizeof(void *), hipMemcpyHostToDevice, s));
         WDR_HIP(hipMemcpyAsync(idx.as<void>(), hi.data(), hi.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        WDR_HIP(hipMemcpyAsync(kw.as<void>(), hk.data(), hk.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        WDR_HIP(hipMemcpyAsync(sw.as<void>(), hs.data(), hs.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
         const void *const *tb = tabs.as<const void *const>();
-        // the geodesic path stays in SU(3) when both ends are
-        const int su3 = U->su3 && Up->su3;
-        const GaugeTab X{{reinterpret_cast<UTab<double>>(tb), su3}, {reinterpret_cast<UTab<float>>(tb + M), su3}};
-        const GaugeTab Xp{{reinterpret_cast<UTab<double>>(tb + 2 * M), su3},
-                          {reinterpret_cast<UTab<float>>(tb + 3 * M), su3}};
+        const double *kap = kw.as<const double>();
+        const GaugeTab X{{reinterpret_cast<UTab<double>>(tb), su3, kap}, {reinterpret_cast<UTab<float>>(tb + M), su3, kap}};
+        const GaugeTab Xp{{reinterpret_cast<UTab<double>>(tb + 2 * M), su3, kap},
+                          {reinterpret_cast<UTab<float>>(tb + 3 * M), su3, kap}};
         const Sys all = all_sys(c, M);
         double2 *E = eta.as<double2>(), *Y = y.as<double2>(), *Z = z.as<double2>(), *W = w.as<double2>(),
                 *R = r.as<double2>(), *Tm = t.as<double2>();
@@ -121,8 +135,10 @@ wdr_status logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, dou
             if (e != WDR_OK && e != WDR_ENOCONV) hard = e;
             return e == WDR_OK || e == WDR_ENOCONV;
         };
+        const double kappa = kappa0;
 
-        launch_noise(g, all, p.noise, p.seed, idx.as<int32_t>(), idx.as<int32_t>() + M, p.op == WDR_OP_SCHUR, E, s);
+        launch_noise(g, all, p.noise, p.seed, sw.as<uint64_t>(), idx.as<int32_t>(), idx.as<int32_t>() + M,
+                     p.op == WDR_OP_SCHUR, E, s);
         if (p.op == WDR_OP_FULL) {
             apply_D64(c, all, X, kappa, E, Y, s);                                          // y = D eta
             if (!take(solve64(c, M, Xp, kappa, sp, sp.tol, Y, Z, s1, s), true)) return hard;   // D' z = y
@@ -173,18 +189,21 @@ wdr_status logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, dou
     }
     st = summarize(all_stats);
     if (host_samples) std::copy(samples.begin(), samples.end(), host_samples);
-    if (host_log_ratio) {
-        // sum_i log( (1/K) sum_k exp(s_ik) ), summed over blocks for BLOCKS
-        double tot = 0;
-        for (int b = 0; b < nout; ++b)
-            for (int i = 0; i < N; ++i) {
-                double mx = -INFINITY;
-                for (int k = 0; k < K; ++k) mx = std::max(mx, samples[((size_t)i * K + k) * nout + b]);
-                double acc = 0;
-                for (int k = 0; k < K; ++k) acc += std::exp(samples[((size_t)i * K + k) * nout + b] - mx);
-                tot += mx + std::log(acc / K);
-            }
-        *host_log_ratio = tot;
+    if (host_log_ratios) {
+        // per proposal: sum_i log( (1/K) sum_k exp(s_ik) ), summed over blocks for BLOCKS
+        for (int q = 0; q < P; ++q) {
+            const double *sq = samples.data() + (size_t)q * per_prop * nout;
+            double tot = 0;
+            for (int b = 0; b < nout; ++b)
+                for (int i = 0; i < N; ++i) {
+                    double mx = -INFINITY;
+                    for (int k = 0; k < K; ++k) mx = std::max(mx, sq[((size_t)i * K + k) * nout + b]);
+                    double acc = 0;
+                    for (int k = 0; k < K; ++k) acc += std::exp(sq[((size_t)i * K + k) * nout + b] - mx);
+                    tot += mx + std::log(acc / K);
+                }
+            host_log_ratios[q] = tot;
+        }
     }
     return status;
 }

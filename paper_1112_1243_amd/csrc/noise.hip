@@ -42,13 +42,15 @@ __device__ __forceinline__ long canon_of(const Geo &g, int slot, int l, int x[4]
 }
 
 // writes the internal-layout FP64 noise field
-__global__ __launch_bounds__(256) void k_noise(Geo g, long n, int kind, uint64_t seed, const int32_t *steps,
-                                               const int32_t *ks, int black_only, double2 *__restrict__ out)
+__global__ __launch_bounds__(256) void k_noise(Geo g, long n, int kind, uint64_t seed, const uint64_t *seeds,
+                                               const int32_t *steps, const int32_t *ks, int black_only,
+                                               double2 *__restrict__ out)
 {
     const int l = blockIdx.x * 256 + threadIdx.x;
     if (l >= g.Vb) return;
     const int slot = blockIdx.y, m = blockIdx.z;
     const uint32_t step = (uint32_t)steps[m], k = (uint32_t)ks[m];
+    if (seeds) seed = seeds[m];
     const long base = m * n + (long)slot * 12 * g.Vb + l;
     if (black_only && slot >= g.nblack) {
         for (int c = 0; c < 12; ++c) out[base + (long)c * g.Vb] = make_double2(0.0, 0.0);
@@ -142,10 +144,11 @@ __global__ __launch_bounds__(256) void k_sample_terms(Geo g, const int32_t *acti
 
 }  // namespace
 
-void launch_noise(const Geo &g, const Sys &sy, int kind, uint64_t seed, const int32_t *steps, const int32_t *ks,
-                  int black_only, double2 *out, hipStream_t s)
+void launch_noise(const Geo &g, const Sys &sy, int kind, uint64_t seed, const uint64_t *seeds, const int32_t *steps,
+                  const int32_t *ks, int black_only, double2 *out, hipStream_t s)
 {
-    k_noise<<<dim3((g.Vb + 255) / 256, g.nblk, sy.M), 256, 0, s>>>(g, sy.n, kind, seed, steps, ks, black_only, out);
+    k_noise<<<dim3((g.Vb + 255) / 256, g.nblk, sy.M), 256, 0, s>>>(g, sy.n, kind, seed, seeds, steps, ks, black_only,
+                                                                    out);
 }
 void launch_site_maps(const Geo &g, int32_t *bid, int32_t *col, int32_t *par, int32_t *pos, hipStream_t s)
 {

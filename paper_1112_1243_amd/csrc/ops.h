@@ -23,12 +23,15 @@ struct Sys {
 template <typename T> using T2 = typename C2<T>::type;
 template <typename T> using UTab = const T2<T> *const *;  // device [M] gauge pointers
 
-// the links of a batch: the device table of per-system gauge pointers and
+// the links of a batch: the device table of per-system gauge pointers,
 // whether every field in it is SU(3) to SU3_TOL (then kernels may read two
-// rows per link and rebuild the third)
+// rows per link and rebuild the third), and optionally a device table of
+// per-system hopping parameters (NULL: every system uses the kappa argument
+// of the launch)
 template <typename T> struct Links {
     UTab<T> tab;
     int su3;
+    const double *kap = nullptr;
 };
 
 // out(x) = diag(x) - kappa * sum_{selected hops} [...] in(y), per system
@@ -111,9 +114,10 @@ void launch_slot_norm2(const Geo &g, const Sys &sy, const double2 *a, double *ou
                        hipStream_t s);
 
 // ---------------------------------------------------------------- noise, path
-// system m gets the noise of path step steps[m], sample ks[m] (device arrays)
-void launch_noise(const Geo &g, const Sys &sy, int kind, uint64_t seed, const int32_t *steps, const int32_t *ks,
-                  int black_only, double2 *out, hipStream_t s);
+// system m gets the noise of path step steps[m], sample ks[m] (device
+// arrays) under key (seeds[m], 3), or (seed, 3) when seeds is NULL
+void launch_noise(const Geo &g, const Sys &sy, int kind, uint64_t seed, const uint64_t *seeds, const int32_t *steps,
+                  const int32_t *ks, int black_only, double2 *out, hipStream_t s);
 // out = U_t = exp(t log(U' U^+)) U on internal FP64 links
 void launch_interpolate(const Geo &g, const double2 *U, const double2 *Up, double t, double2 *out, hipStream_t s);
 void launch_site_maps(const Geo &g, int32_t *bid, int32_t *col, int32_t *par, int32_t *pos, hipStream_t s);

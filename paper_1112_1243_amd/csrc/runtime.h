@@ -23,6 +23,9 @@ struct wdr_ctx {
     int32_t *poll_host = nullptr;
     size_t poll_cap = 0;
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
+    // stream of this context's group in a batch over several contexts
+    // (created on first use, default priority)
+    hipStream_t aux = nullptr;
 };
 
 struct wdr_gauge {
@@ -104,8 +107,17 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
                          double tol, const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s);
 wdr_status schur64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
                    const double2 *in, double2 *out, std::vector<Stats> &st, hipStream_t s);
-wdr_status logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, double kappa, const wdr_est_params &p,
-                        double *host_samples, double *host_log_ratio, Stats &st, hipStream_t s);
+// one proposal U -> U' of an estimate (links on the estimate's context)
+struct Proposal {
+    const wdr_gauge *U, *Up;
+    double kappa;
+    uint64_t seed;
+};
+// every (proposal, step, noise) sample of the proposals is one system of the
+// batched launches; samples [proposal][step][noise](x nblk for BLOCKS),
+// log ratios per proposal
+wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wdr_est_params &p,
+                        double *host_samples, double *host_log_ratios, Stats &st, hipStream_t s);
 
 // validation helpers
 wdr_status check_ctx(const wdr_ctx *c);

@@ -309,6 +309,7 @@ wdr_status wdr_ctx_destroy(wdr_ctx *c)
     if (c->poll_host) (void)hipHostFree(c->poll_host);
     for (hipEvent_t e : c->poll_ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     delete c;
     return WDR_OK;
 }

@@ -55,7 +55,8 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v, int width)
 //         MR on the block, x += d.
 // MODE 1: block MR for a given right-hand side: d = MR(D_b, rhs).
 template <typename T, int MODE>
-__global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const int32_t *__restrict__ active, UTab<T> Utab, long n,
+__global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const int32_t *__restrict__ active, UTab<T> Utab,
+                                                    const double *__restrict__ kap, long n,
                                                     const typename C2<T>::type *__restrict__ src,
                                                     typename C2<T>::type *__restrict__ dst, T kappa, int nmr,
                                                     int slot0)
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const int32_t *__rest
 
     const int m = blockIdx.y;
     if (active && !active[m]) return;
+    if (kap) kappa = (T)kap[m];
     const typename C2<T>::type *__restrict__ U = Utab[m];
     src += m * n;
     dst += m * n;
@@ -303,7 +305,7 @@ __device__ __forceinline__ void hop_in_lds(const typename C2<T>::type *sh, int o
 
 template <typename T, int MODE, int B>
 __global__ __launch_bounds__(Cube<B>::Vb) void k_block_mr_cube(Geo g, const int32_t *__restrict__ active,
-                                                               UTab<T> Utab, long n,
+                                                               UTab<T> Utab, const double *__restrict__ kap, long n,
                                                                const int32_t *__restrict__ sched,
                                                                const typename C2<T>::type *__restrict__ src,
                                                                typename C2<T>::type *__restrict__ dst, T kappa,
@@ -314,6 +316,7 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_block_mr_cube(Geo g, const int3
     constexpr int Vb = CB::Vb, Vh = CB::Vh;
     const int m = blockIdx.y;
     if (active && !active[m]) return;
+    if (kap) kappa = (T)kap[m];
     const typename C2<T>::type *__restrict__ U = Utab[m];
     src += m * n;
     dst += m * n;
@@ -489,7 +492,8 @@ __device__ __forceinline__ void sum_part(const typename C2<T>::type *part, int q
 
 template <typename T, int MODE, int B>
 __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const int32_t *__restrict__ active,
-                                                                  UTab<T> Utab, long n,
+                                                                  UTab<T> Utab, const double *__restrict__ kap,
+                                                                  long n,
                                                                   const int32_t *__restrict__ sched,
                                                                   const typename C2<T>::type *__restrict__ src,
                                                                   typename C2<T>::type *__restrict__ dst, T kappa,
@@ -501,6 +505,7 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const i
     __shared__ DirLds<T, B> S;
     const int m = blockIdx.y;
     if (active && !active[m]) return;
+    if (kap) kappa = (T)kap[m];
     const typename C2<T>::type *__restrict__ U = Utab[m];
     src += m * n;
     dst += m * n;
@@ -692,10 +697,10 @@ bool launch_mr_cube4(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *src, 
     const int si = sched_index(g, slot0, nslots);
     if (si < 0) return false;
     if constexpr (sizeof(T) == 4)  // the FP64 partial sums would not fit in LDS next to the links
-        k_block_mr_dir<T, MODE, 4><<<dim3(nslots, sy.M), 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, U.tab, sy.n,
+        k_block_mr_dir<T, MODE, 4><<<dim3(nslots, sy.M), 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n,
                                                                                 g.sched[si], src, dst, kappa, nmr);
     else
-        k_block_mr_cube<T, MODE, 4><<<dim3(nslots, sy.M), 256, 0, s>>>(g, sy.active, U.tab, sy.n, g.sched[si], src,
+        k_block_mr_cube<T, MODE, 4><<<dim3(nslots, sy.M), 256, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, g.sched[si], src,
                                                                        dst, kappa, nmr);
     return true;
 }
@@ -708,7 +713,7 @@ void launch_sap_colour(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *eta
 {
     if (nslots <= 0 || sy.M <= 0) return;
     if (launch_mr_cube4<T, 0>(g, sy, U, eta, x, kappa, nmr, slot0, nslots, s)) return;
-    k_block_mr<T, 0><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, sy.n, eta, x, kappa, nmr, slot0);
+    k_block_mr<T, 0><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, eta, x, kappa, nmr, slot0);
 }
 
 template <typename T>
@@ -717,7 +722,7 @@ void launch_block_mr(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *r, T2
 {
     if (nslots <= 0 || sy.M <= 0) return;
     if (launch_mr_cube4<T, 1>(g, sy, U, r, d, kappa, nmr, slot0, nslots, s)) return;
-    k_block_mr<T, 1><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, sy.n, r, d, kappa, nmr, slot0);
+    k_block_mr<T, 1><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, r, d, kappa, nmr, slot0);
 }
 
 #define INST(T)                                                                                                  \

@@ -49,29 +49,75 @@ __global__ void k_cg_restart(int M, const int32_t *flag, double2 *sc)
     sc[8L * m] = sc[8L * m + 5];
 }
 // x += alpha w, r -= alpha q
+template <typename T>
 __global__ __launch_bounds__(256) void k_cg_update(const int32_t *active, long n, long total, const double2 *sc,
-                                                   double2 *x, const double2 *w, double2 *r, const double2 *q)
+                                                   T2<T> *x, const T2<T> *w, T2<T> *r, const T2<T> *q)
 {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i >= total) return;
     const int m = (int)(i / n);
     if (active && !active[m]) return;
-    const double a = sc[8L * m + 2].x;
-    const double2 xi = x[i], wi = w[i], ri = r[i], qi = q[i];
-    x[i] = make_double2(xi.x + a * wi.x, xi.y + a * wi.y);
-    r[i] = make_double2(ri.x - a * qi.x, ri.y - a * qi.y);
+    const T a = (T)sc[8L * m + 2].x;
+    const T2<T> xi = x[i], wi = w[i], ri = r[i], qi = q[i];
+    x[i].x = xi.x + a * wi.x;
+    x[i].y = xi.y + a * wi.y;
+    r[i].x = ri.x - a * qi.x;
+    r[i].y = ri.y - a * qi.y;
 }
 // p = r + beta p
+template <typename T>
 __global__ __launch_bounds__(256) void k_cg_p(const int32_t *active, long n, long total, const double2 *sc,
-                                              const double2 *r, double2 *p)
+                                              const T2<T> *r, T2<T> *p)
 {
     const long i = (long)blockIdx.x * 256 + threadIdx.x;
     if (i >= total) return;
     const int m = (int)(i / n);
     if (active && !active[m]) return;
-    const double b = sc[8L * m + 4].x;
-    const double2 ri = r[i], pi = p[i];
-    p[i] = make_double2(ri.x + b * pi.x, ri.y + b * pi.y);
+    const T b = (T)sc[8L * m + 4].x;
+    const T2<T> ri = r[i], pi = p[i];
+    p[i].x = ri.x + b * pi.x;
+    p[i].y = ri.y + b * pi.y;
+}
+
+// ---- mixed-precision CGNE control (one thread per system); sc[8 m + k]:
+// 0 rr, 1 |w|^2, 2 alpha, 3 new rr, 4 beta, 5 true FP64 residual^2
+__global__ void k_cgm_init(int M, const double2 *sc, double *bn2, int32_t *alive, int32_t *act, int32_t *its)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const double b = sc[8L * m + 5].x;
+    bn2[m] = b;
+    alive[m] = act[m] = b > 0;
+    its[m] = 0;
+}
+// start of an inner cycle: its initial residual norm (sc[0]) is the reference
+__global__ void k_cgm_start(int M, const int32_t *act, const double2 *sc, double *rr0)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M || !act[m]) return;
+    rr0[m] = sc[8L * m].x;
+}
+// after an inner step: end the cycle once the FP32 residual fell by delta
+__global__ void k_cgm_inner(int M, const double2 *sc, const double *rr0, double delta2, int max_iter, int32_t *act,
+                            int32_t *its)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M || !act[m]) return;
+    const int k = ++its[m];
+    const double rr = sc[8L * m].x;
+    if (!(rr > delta2 * rr0[m]) || k >= max_iter) act[m] = 0;
+}
+// after the FP64 true residual: retire converged systems, start the next cycle
+__global__ void k_cgm_outer(int M, const double2 *sc, const double *bn2, double tol2, int max_iter,
+                            const int32_t *its, int32_t *alive, int32_t *act)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    if (alive[m]) {
+        const double r = sc[8L * m + 5].x;
+        if (!isfinite(r) || r <= tol2 * bn2[m] || its[m] >= max_iter) alive[m] = 0;
+    }
+    act[m] = alive[m];
 }
 
 inline unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
@@ -420,10 +466,10 @@ static wdr_status cgne(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
         apply_D64(c, sa, U, kappa, w, q, s);
         launch_norm2<double>(sa, w, red.as<double>(), sc + 1, 8, s);
         k_cg_alpha<<<nb64(M), 64, 0, s>>>(M, alive.d(), sc);
-        k_cg_update<<<nb256(total), 256, 0, s>>>(alive.d(), n, total, sc, x, w, r, q);
+        k_cg_update<double><<<nb256(total), 256, 0, s>>>(alive.d(), n, total, sc, x, w, r, q);
         launch_norm2<double>(sa, r, red.as<double>(), sc + 3, 8, s);
         k_cg_beta<<<nb64(M), 64, 0, s>>>(M, alive.d(), sc);
-        k_cg_p<<<nb256(total), 256, 0, s>>>(alive.d(), n, total, sc, r, p);
+        k_cg_p<double><<<nb256(total), 256, 0, s>>>(alive.d(), n, total, sc, r, p);
         ++it;
         for (int m = 0; m < M; ++m)
             if (alive.h[m]) ++its[m];
@@ -480,10 +526,103 @@ static wdr_status cgne(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
     return WDR_OK;
 }
 
+// ------------------------------------------------------------ mixed CGNE
+
+// FP64 defect correction around CG on the normal equations in FP32: each
+// cycle solves D D^+ y = r (r = b - D x, the FP64 true residual rounded to
+// FP32) until the FP32 residual has fallen by CGM_DELTA, then x += D^+ y
+// (accumulated in FP32 as e, added to x in FP64).  Convergence is decided on
+// the FP64 true residual only.
+constexpr double CGM_DELTA = 1e-5;
+
+static wdr_status cgne_mixed(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
+                             double tol, const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
+{
+    const long n = field_n(c), total = n * M;
+    const size_t fb = field_bytes(c, WDR_F64) * M, fb32 = field_bytes(c, WDR_F32) * M;
+    Work r64w(c, fb), t64w(c, fb), rw(c, fb32), pw(c, fb32), ww(c, fb32), qw(c, fb32), ew(c, fb32),
+        scal(c, sizeof(double2) * 8 * M), red(c, sizeof(double) * red_scratch(M)),
+        ctl(c, 2 * sizeof(double) * M + 3 * sizeof(int32_t) * M);
+    FlagPoll poll(c, M);
+    if (!r64w.ok() || !t64w.ok() || !rw.ok() || !pw.ok() || !ww.ok() || !qw.ok() || !ew.ok() || !scal.ok() ||
+        !red.ok() || !ctl.ok() || !poll.ok)
+        return WDR_ENOMEM;
+    double2 *r64 = r64w.as<double2>(), *t64 = t64w.as<double2>();
+    float2 *r = rw.as<float2>(), *p = pw.as<float2>(), *w = ww.as<float2>(), *q = qw.as<float2>(), *e = ew.as<float2>();
+    double2 *sc = scal.as<double2>();
+    double *bn2 = ctl.as<double>(), *rr0 = bn2 + M;
+    int32_t *act = reinterpret_cast<int32_t *>(rr0 + M), *alive = act + M, *its = alive + M;
+    const auto &g = c->g;
+    const Sys all = all_sys(c, M), sa{M, act, n}, sw{M, alive, n};
+    const unsigned nbm = nb64(M);
+    const float k32 = (float)kappa;
+    launch_zero<double>(x, total, s);
+    launch_convert<double, double>(all, b, r64, s);
+    launch_norm2<double>(all, b, red.as<double>(), sc + 5, 8, s);
+    k_cgm_init<<<nbm, 64, 0, s>>>(M, sc, bn2, alive, act, its);
+    for (;;) {
+        // inner cycle from the FP64 residual
+        launch_convert<float, double>(sw, r64, r, s);
+        launch_convert<float, float>(sw, r, p, s);
+        launch_zero<float>(e, total, s);
+        launch_norm2<float>(sa, r, red.as<double>(), sc, 8, s);
+        k_cgm_start<<<nbm, 64, 0, s>>>(M, act, sc, rr0);
+        for (int j = 0;; ++j) {
+            // w = D^+ p, q = D w
+            launch_dslash<float>(g, sa, U.u32, HOPS_ALL, -1, 1, p, p, w, k32, 0, g.nblk, s);
+            launch_dslash<float>(g, sa, U.u32, HOPS_ALL, -1, 0, w, w, q, k32, 0, g.nblk, s);
+            launch_norm2<float>(sa, w, red.as<double>(), sc + 1, 8, s);
+            k_cg_alpha<<<nbm, 64, 0, s>>>(M, act, sc);
+            k_cg_update<float><<<nb256(total), 256, 0, s>>>(act, n, total, sc, e, w, r, q);
+            launch_norm2<float>(sa, r, red.as<double>(), sc + 3, 8, s);
+            k_cg_beta<<<nbm, 64, 0, s>>>(M, act, sc);
+            k_cg_p<float><<<nb256(total), 256, 0, s>>>(act, n, total, sc, r, p);
+            k_cgm_inner<<<nbm, 64, 0, s>>>(M, sc, rr0, CGM_DELTA * CGM_DELTA, sp.max_iter, act, its);
+            // poll every other step, one poll behind
+            if (j % 2 == 1) {
+                poll.post(act, (j / 2) & 1, s);
+                if (j >= 3 && poll.none(((j / 2) - 1) & 1)) break;
+            }
+        }
+        // defect correction in FP64
+        launch_add_to64<float>(sw, e, x, s);
+        apply_D64(c, sw, U, kappa, x, t64, s);
+        launch_sub(sw, b, t64, r64, s);
+        launch_norm2<double>(sw, r64, red.as<double>(), sc + 5, 8, s);
+        k_cgm_outer<<<nbm, 64, 0, s>>>(M, sc, bn2, tol * tol, sp.max_iter, its, alive, act);
+        poll.post(alive, 0, s);
+        if (poll.none(0)) break;
+    }
+    std::vector<double> hbn2(M), rn2;
+    std::vector<int32_t> hits(M);
+    WDR_HIP(hipMemcpyAsync(hbn2.data(), bn2, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+    WDR_HIP(hipMemcpyAsync(hits.data(), its, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+    read_x(sc + 5, M, 8, rn2, s);
+    st.assign(M, Stats());
+    bool ok = true;
+    for (int m = 0; m < M; ++m) {
+        st[m].iters = hits[m];
+        st[m].total = hits[m];
+        st[m].rel = hbn2[m] > 0 ? std::sqrt(rn2[m] / hbn2[m]) : 0.0;
+        st[m].converged = st[m].rel <= tol;
+        ok = ok && st[m].converged;
+    }
+    WDR_HIP(hipGetLastError());
+    if (!ok) {
+        const Stats sm = summarize(st);
+        set_error("mixed CGNE stopped at " + std::to_string(sm.iters) + " iterations, relative residual " +
+                  std::to_string(sm.rel));
+        return WDR_ENOCONV;
+    }
+    return WDR_OK;
+}
+
 wdr_status solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp, double tol,
                    const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
-    if (sp.solver == WDR_SOLVER_CGNE) return cgne(c, M, U, kappa, sp, tol, b, x, st, s);
+    if (sp.solver == WDR_SOLVER_CGNE)
+        return sp.inner == WDR_F64 ? cgne(c, M, U, kappa, sp, tol, b, x, st, s)
+                                   : cgne_mixed(c, M, U, kappa, sp, tol, b, x, st, s);
     return fgcr(c, M, U, kappa, sp, tol, b, x, st, s);
 }
 

@@ -45,7 +45,13 @@ class SolveInfo(ctypes.Structure):
 
 class EstParams(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int), ("n_steps", ctypes.c_int32), ("n_noise", ctypes.c_int32),
-                ("noise", ctypes.c_int), ("seed", ctypes.c_uint64), ("sp", SolverParams)]
+                ("noise", ctypes.c_int), ("seed", ctypes.c_uint64), ("sp", SolverParams),
+                ("max_batch", ctypes.c_int32)]
+
+
+class Proposal(ctypes.Structure):
+    _fields_ = [("ctx", ctypes.c_void_p), ("U", ctypes.c_void_p), ("Up", ctypes.c_void_p),
+                ("kappa", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
 class WdrError(RuntimeError):
@@ -100,6 +106,8 @@ def lib():
                                       P]
         L.wdr_apply_schur.argtypes = [P, P, d, ctypes.POINTER(SolverParams), P, P, P]
         L.wdr_logdet_ratio.argtypes = [P, P, P, d, ctypes.POINTER(EstParams), P, P, ctypes.POINTER(SolveInfo), P]
+        L.wdr_logdet_ratio_batch.argtypes = [i32, ctypes.POINTER(Proposal), ctypes.POINTER(EstParams), P, P,
+                                             ctypes.POINTER(SolveInfo), P]
         _lib = L
     return _lib
 
@@ -292,10 +300,12 @@ class Context:
                                      _dev(psi, (self.V, 4, 3)), ctypes.c_void_p(out.data_ptr()), _stream()))
         return out
 
-    def logdet_ratio(self, U: Gauge, Up: Gauge, kappa, op, n_steps, n_noise, noise, seed, params: SolverParams):
+    def logdet_ratio(self, U: Gauge, Up: Gauge, kappa, op, n_steps, n_noise, noise, seed, params: SolverParams,
+                     max_batch: int = 0):
         """Returns (samples [n_steps, n_noise] (x nblocks for BLOCKS), log Rhat, info)."""
         ep = EstParams()
         ep.op, ep.n_steps, ep.n_noise, ep.noise, ep.seed, ep.sp = op, n_steps, n_noise, noise, seed, params
+        ep.max_batch = max_batch
         shape = (n_steps, n_noise) + ((self.nblocks,) if op == OP_BLOCKS else ())
         samples = np.zeros(shape, dtype=np.float64)
         lr = ctypes.c_double()
@@ -304,3 +314,29 @@ class Context:
                                       samples.ctypes.data_as(ctypes.c_void_p), ctypes.byref(lr), ctypes.byref(info),
                                       _stream()))
         return samples, lr.value, info
+
+
+def logdet_ratio_batch(props, op, n_steps, n_noise, noise, params: SolverParams, max_batch: int = 0):
+    """Estimates for a list of proposals (ctx, U, Up, kappa, seed), contexts
+    possibly of different lattice sizes, in one batched call.  Returns (list of
+    sample arrays [n_steps, n_noise] (x nblocks for BLOCKS), log Rhat array, info)."""
+    n = len(props)
+    arr = (Proposal * n)()
+    sizes = []
+    for j, (ctx, U, Up, kappa, seed) in enumerate(props):
+        arr[j].ctx, arr[j].U, arr[j].Up, arr[j].kappa, arr[j].seed = ctx.handle, U.handle, Up.handle, kappa, seed
+        sizes.append((n_steps, n_noise) + ((ctx.nblocks,) if op == OP_BLOCKS else ()))
+    ep = EstParams()
+    ep.op, ep.n_steps, ep.n_noise, ep.noise, ep.seed, ep.sp = op, n_steps, n_noise, noise, 0, params
+    ep.max_batch = max_batch
+    flat = np.zeros(sum(int(np.prod(z)) for z in sizes), dtype=np.float64)
+    lr = np.zeros(n, dtype=np.float64)
+    info = SolveInfo()
+    _check(lib().wdr_logdet_ratio_batch(n, arr, ctypes.byref(ep), flat.ctypes.data_as(ctypes.c_void_p),
+                                        lr.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info), _stream()))
+    out, pos = [], 0
+    for z in sizes:
+        k = int(np.prod(z))
+        out.append(flat[pos:pos + k].reshape(z))
+        pos += k
+    return out, lr, info

@@ -43,9 +43,10 @@ def test_struct_sizes_match_the_header():
 #include <stddef.h>
 #include "wdr.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(wdr_geom), sizeof(wdr_solver_params), sizeof(wdr_solve_info),
-         sizeof(wdr_est_params), offsetof(wdr_solver_params, tol), offsetof(wdr_est_params, sp),
-         offsetof(wdr_solver_params, inner));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(wdr_geom), sizeof(wdr_solver_params),
+         sizeof(wdr_solve_info), sizeof(wdr_est_params), offsetof(wdr_solver_params, tol),
+         offsetof(wdr_est_params, sp), offsetof(wdr_solver_params, inner), offsetof(wdr_est_params, max_batch),
+         sizeof(wdr_proposal), offsetof(wdr_proposal, kappa), offsetof(wdr_proposal, seed));
   return 0;
 }'''
     import tempfile
@@ -57,7 +58,8 @@ int main(void) {
         vals = [int(v) for v in subprocess.check_output([exe]).split()]
     want = [ctypes.sizeof(wdr.Geom), ctypes.sizeof(wdr.SolverParams), ctypes.sizeof(wdr.SolveInfo),
             ctypes.sizeof(wdr.EstParams), wdr.SolverParams.tol.offset, wdr.EstParams.sp.offset,
-            wdr.SolverParams.inner.offset]
+            wdr.SolverParams.inner.offset, wdr.EstParams.max_batch.offset, ctypes.sizeof(wdr.Proposal),
+            wdr.Proposal.kappa.offset, wdr.Proposal.seed.offset]
     assert vals == want
 
 

@@ -20,13 +20,16 @@ def _setup(L, B, scale, seed, bc=(1, 1, 1, 1)):
     return wdr, lat, ctx, U
 
 
-@pytest.mark.parametrize("solver,kappa,scale", [(0, 0.135, 0.5), (1, 0.135, 0.5), (1, 0.150, 0.25)])
-def test_solve_true_residual(solver, kappa, scale):
-    """The oracle's own stencil checks the GPU solution: ||b - D x|| <= 1e-10 ||b||."""
+@pytest.mark.parametrize("solver,kappa,scale,inner", [(0, 0.135, 0.5, 1), (1, 0.135, 0.5, 1), (1, 0.150, 0.25, 1),
+                                                      (1, 0.150, 0.25, 0), (0, 0.135, 0.5, 0)])
+def test_solve_true_residual(solver, kappa, scale, inner):
+    """The oracle's own stencil checks the GPU solution: ||b - D x|| <= 1e-10 ||b||
+    (CGNE with inner FP32 is the mixed-precision form: FP32 CG cycles inside
+    FP64 defect correction)."""
     wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), scale, 201)
     b = synth.spinor(lat.L, 202)
     gU = ctx.gauge(dev(U))
-    x, info = ctx.solve(gU, kappa, dev(b), wdr.default_params(solver=solver))
+    x, info = ctx.solve(gU, kappa, dev(b), wdr.default_params(solver=solver, inner=inner))
     x = host(x)
     r = np.linalg.norm(b - oracle.apply_D(lat, U, kappa, x)) / np.linalg.norm(b)
     say("solve", solver, kappa, info.as_dict(), "oracle residual", r)
