@@ -209,6 +209,68 @@ def rocprof_summary(path, kernel_regex="k_dslash_dir"):
     return "\n".join(lines)
 
 
+def batched_proposals(wdr, torch, n_steps=8, scale=0.3):
+    """The batched-proposal workload: 64 proposals of uneven sizes (24 at 8^4,
+    24 at 12^4, 16 at 16^4), kappa uniform in [0.12, 0.15], U' redraws each
+    link with probability 0.1, full-operator ratio, n_steps = 8 factors with
+    one Z2 noise vector each, CGNE (FP32 cycles in FP64 defect correction) to
+    1e-10: one wdr_logdet_ratio_batch call.  Baseline: the plain FP64 form
+    (FP64 CGNE, one sample at a time, proposals one after another), timed on
+    one proposal of each size and scaled by the counts."""
+    from paper_1112_1243_amd import synth
+    specs = synth.batch_proposals()
+    ctxs = {}
+    props = []
+    t0 = time.perf_counter()
+    for q in specs:
+        L = q["L"]
+        if L not in ctxs:
+            ctxs[L] = wdr.Context(L, (4, 4, 4, 4))
+        c = ctxs[L]
+        U = synth.gauge_field(L, scale, q["seed"])
+        Up = synth.redraw(U, synth.bernoulli_links(L, 0.1, q["seed"]), scale, q["seed"])
+        props.append((c, c.gauge(torch.from_numpy(U).cuda()), c.gauge(torch.from_numpy(Up).cuda()), q["kappa"],
+                      q["seed"]))
+    log("batched proposals: inputs ready in %.1f s" % (time.perf_counter() - t0))
+    # kappa near the critical value of these links (about 0.132) makes some
+    # solves need a few thousand CG iterations: allow them
+    mixed = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F32, max_iter=20000)
+    plain = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F64, max_iter=20000)
+    # warm-up (workspace pools, streams): one factor per proposal
+    wdr.logdet_ratio_batch(props, wdr.OP_FULL, 1, 1, wdr.NOISE_Z2, mixed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    samples, lrs, info = wdr.logdet_ratio_batch(props, wdr.OP_FULL, n_steps, 1, wdr.NOISE_Z2, mixed)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    log("batched proposals: %d estimates in %.3f s, converged %s, CG iterations %d (max %d)"
+        % (len(props), dt, bool(info.converged), info.total_iters, info.iters))
+    # serial FP64 baseline: every proposal, one after another, one sample at a time
+    t1 = time.perf_counter()
+    worst = 0.0
+    for j, (c, gU, gUp, kappa, seed) in enumerate(props):
+        t2 = time.perf_counter()
+        _, lr1, _ = c.logdet_ratio(gU, gUp, kappa, wdr.OP_FULL, n_steps, 1, wdr.NOISE_Z2, seed, plain, max_batch=1)
+        worst = max(worst, abs(lr1 - lrs[j]))
+        torch.cuda.synchronize()
+        if time.perf_counter() - t2 > 1.0:
+            log("serial fp64: proposal %d (kappa %.4f) took %.2f s" % (j, kappa, time.perf_counter() - t2))
+    serial = time.perf_counter() - t1
+    log("serial fp64: %d proposals in %.2f s; largest |log R (batched) - log R (serial fp64)| = %.2e"
+        % (len(props), serial, worst))
+    del props
+    for c in ctxs.values():
+        c.close()
+    return {"workload": "64 proposals (24 x 8^4, 24 x 12^4, 16 x 16^4), kappa in [0.12, 0.15], links exp(i 0.3 H), "
+                        "Bernoulli(0.1) redraw, full operator, N=8 factors x 1 Z2 noise, CGNE to 1e-10",
+            "value": round(len(specs) / dt, 3), "unit": "estimates/s", "seconds": round(dt, 3),
+            "converged": bool(info.converged), "cg_iterations_total": int(info.total_iters),
+            "fp64_serial_estimates_per_s": round(len(specs) / serial, 3),
+            "fp64_serial": "every proposal in turn, FP64 CGNE, one sample at a time",
+            "max_abs_log_ratio_diff_vs_fp64_serial": float("%.3e" % worst),
+            "speedup_vs_fp64_serial": round(serial / dt, 2)}
+
+
 def cpu_baseline(wl, U, Up, budget_s=20.0):
     """FP64 CPU oracle on a bounded sample: one BLOCKS and one SCHUR sample
     (one factor, one noise vector) of the same workload, scaled to a full
@@ -236,6 +298,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-dslash", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-proposal workload")
     ap.add_argument("--rocprof-summary", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     args = ap.parse_args()
     if args.rocprof_summary:
@@ -303,6 +366,10 @@ def main():
         roof["copy_ceiling"] = copy_ceiling(torch)
         log("copy ceiling:", roof["copy_ceiling"])
 
+    batch = None if args.no_batch else batched_proposals(wdr, torch)
+    if batch:
+        log("batched proposals:", batch)
+
     cpu = None if args.no_cpu else cpu_baseline(wl, U, Up)
     if cpu:
         log("cpu baseline:", cpu)
@@ -326,6 +393,7 @@ def main():
                    "converged": all_ok, "total_outer_iters": iters, "mean_log_ratio": float(np.mean(lrs))},
         "fp64_estimates_per_s": None if fp64_rate is None else round(fp64_rate, 4),
         "roofline": roof,
+        "batched_proposals": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -81,43 +81,59 @@ __global__ __launch_bounds__(256) void k_cg_p(const int32_t *active, long n, lon
 
 // ---- mixed-precision CGNE control (one thread per system); sc[8 m + k]:
 // 0 rr, 1 |w|^2, 2 alpha, 3 new rr, 4 beta, 5 true FP64 residual^2
-__global__ void k_cgm_init(int M, const double2 *sc, double *bn2, int32_t *alive, int32_t *act, int32_t *its)
+__global__ void k_cgm_init(int M, const double2 *sc, double *bn2, double *rmax, int32_t *alive, int32_t *upd,
+                           int32_t *its)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
     const double b = sc[8L * m + 5].x;
     bn2[m] = b;
-    alive[m] = act[m] = b > 0;
+    rmax[m] = b;
+    alive[m] = b > 0;
+    upd[m] = 0;
     its[m] = 0;
 }
-// start of an inner cycle: its initial residual norm (sc[0]) is the reference
-__global__ void k_cgm_start(int M, const int32_t *act, const double2 *sc, double *rr0)
+// after an FP32 step: ask for a reliable update once the iterated residual
+// fell by RELIABLE_DELTA below its largest value since the last update (or at
+// the iteration limit, where the true residual decides)
+__global__ void k_cgm_step(int M, const double2 *sc, double delta2, int max_iter, const int32_t *alive, double *rmax,
+                           int32_t *upd, int32_t *its)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M || !act[m]) return;
-    rr0[m] = sc[8L * m].x;
-}
-// after an inner step: end the cycle once the FP32 residual fell by delta
-__global__ void k_cgm_inner(int M, const double2 *sc, const double *rr0, double delta2, int max_iter, int32_t *act,
-                            int32_t *its)
-{
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M || !act[m]) return;
+    if (m >= M || !alive[m]) return;
     const int k = ++its[m];
     const double rr = sc[8L * m].x;
-    if (!(rr > delta2 * rr0[m]) || k >= max_iter) act[m] = 0;
+    rmax[m] = fmax(rmax[m], rr);
+    if (!(rr > delta2 * rmax[m]) || k >= max_iter) upd[m] = 1;
 }
-// after the FP64 true residual: retire converged systems, start the next cycle
-__global__ void k_cgm_outer(int M, const double2 *sc, const double *bn2, double tol2, int max_iter,
-                            const int32_t *its, int32_t *alive, int32_t *act)
+// after the FP64 true residual of the updated systems: retire converged ones,
+// restart the reference of the others from the true residual
+__global__ void k_cgm_update(int M, double2 *sc, const double *bn2, double tol2, int max_iter, const int32_t *its,
+                             int32_t *alive, int32_t *upd, double *rmax)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    if (alive[m]) {
-        const double r = sc[8L * m + 5].x;
-        if (!isfinite(r) || r <= tol2 * bn2[m] || its[m] >= max_iter) alive[m] = 0;
-    }
-    act[m] = alive[m];
+    if (m >= M || !upd[m]) return;
+    const double r = sc[8L * m + 5].x;
+    if (!isfinite(r) || r <= tol2 * bn2[m] || its[m] >= max_iter) alive[m] = 0;
+    sc[8L * m] = make_double2(r, 0.0);
+    rmax[m] = r;
+}
+// r = (FP32) r64 and e = 0 for the updated systems; clears their flag
+__global__ __launch_bounds__(256) void k_cgm_refresh(long n, long total, int32_t *upd, const int32_t *alive,
+                                                     const double2 *r64, float2 *r, float2 *e)
+{
+    const long i = (long)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const int m = (int)(i / n);
+    if (!upd[m]) return;
+    const double2 v = r64[i];
+    r[i] = make_float2((float)v.x, (float)v.y);
+    e[i] = make_float2(0.f, 0.f);
+}
+__global__ void k_cgm_clear(int M, int32_t *upd)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < M) upd[m] = 0;
 }
 
 inline unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
@@ -528,12 +544,15 @@ static wdr_status cgne(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
 
 // ------------------------------------------------------------ mixed CGNE
 
-// FP64 defect correction around CG on the normal equations in FP32: each
-// cycle solves D D^+ y = r (r = b - D x, the FP64 true residual rounded to
-// FP32) until the FP32 residual has fallen by CGM_DELTA, then x += D^+ y
-// (accumulated in FP32 as e, added to x in FP64).  Convergence is decided on
-// the FP64 true residual only.
-constexpr double CGM_DELTA = 1e-5;
+// CG on the normal equations D D^+ y = b (x = D^+ y) with FP32 vectors and
+// stencil, and reliable updates in FP64 (the scheme of Sleijpen and van der
+// Vorst): the FP32 correction e = D^+ (y - y_last) is folded into the FP64
+// x, and the iterated residual replaced by the FP64 true residual b - D x,
+// whenever the iterated residual has fallen by RELIABLE_DELTA below its
+// largest value since the last update; the search direction is kept, so the
+// iteration continues.  Convergence is decided on the FP64 true residual.
+constexpr double RELIABLE_DELTA = 0.1;
+constexpr int UPDATE_EVERY = 4;  // steps between update / poll points
 
 static wdr_status cgne_mixed(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
                              double tol, const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
@@ -550,48 +569,43 @@ static wdr_status cgne_mixed(wdr_ctx *c, int M, const GaugeTab &U, double kappa,
     double2 *r64 = r64w.as<double2>(), *t64 = t64w.as<double2>();
     float2 *r = rw.as<float2>(), *p = pw.as<float2>(), *w = ww.as<float2>(), *q = qw.as<float2>(), *e = ew.as<float2>();
     double2 *sc = scal.as<double2>();
-    double *bn2 = ctl.as<double>(), *rr0 = bn2 + M;
-    int32_t *act = reinterpret_cast<int32_t *>(rr0 + M), *alive = act + M, *its = alive + M;
+    double *bn2 = ctl.as<double>(), *rmax = bn2 + M;
+    int32_t *alive = reinterpret_cast<int32_t *>(rmax + M), *upd = alive + M, *its = upd + M;
     const auto &g = c->g;
-    const Sys all = all_sys(c, M), sa{M, act, n}, sw{M, alive, n};
+    const Sys all = all_sys(c, M), sa{M, alive, n}, su{M, upd, n};
     const unsigned nbm = nb64(M);
     const float k32 = (float)kappa;
     launch_zero<double>(x, total, s);
-    launch_convert<double, double>(all, b, r64, s);
     launch_norm2<double>(all, b, red.as<double>(), sc + 5, 8, s);
-    k_cgm_init<<<nbm, 64, 0, s>>>(M, sc, bn2, alive, act, its);
-    for (;;) {
-        // inner cycle from the FP64 residual
-        launch_convert<float, double>(sw, r64, r, s);
-        launch_convert<float, float>(sw, r, p, s);
-        launch_zero<float>(e, total, s);
-        launch_norm2<float>(sa, r, red.as<double>(), sc, 8, s);
-        k_cgm_start<<<nbm, 64, 0, s>>>(M, act, sc, rr0);
-        for (int j = 0;; ++j) {
-            // w = D^+ p, q = D w
-            launch_dslash<float>(g, sa, U.u32, HOPS_ALL, -1, 1, p, p, w, k32, 0, g.nblk, s);
-            launch_dslash<float>(g, sa, U.u32, HOPS_ALL, -1, 0, w, w, q, k32, 0, g.nblk, s);
-            launch_norm2<float>(sa, w, red.as<double>(), sc + 1, 8, s);
-            k_cg_alpha<<<nbm, 64, 0, s>>>(M, act, sc);
-            k_cg_update<float><<<nb256(total), 256, 0, s>>>(act, n, total, sc, e, w, r, q);
-            launch_norm2<float>(sa, r, red.as<double>(), sc + 3, 8, s);
-            k_cg_beta<<<nbm, 64, 0, s>>>(M, act, sc);
-            k_cg_p<float><<<nb256(total), 256, 0, s>>>(act, n, total, sc, r, p);
-            k_cgm_inner<<<nbm, 64, 0, s>>>(M, sc, rr0, CGM_DELTA * CGM_DELTA, sp.max_iter, act, its);
-            // poll every other step, one poll behind
-            if (j % 2 == 1) {
-                poll.post(act, (j / 2) & 1, s);
-                if (j >= 3 && poll.none(((j / 2) - 1) & 1)) break;
-            }
-        }
-        // defect correction in FP64
-        launch_add_to64<float>(sw, e, x, s);
-        apply_D64(c, sw, U, kappa, x, t64, s);
-        launch_sub(sw, b, t64, r64, s);
-        launch_norm2<double>(sw, r64, red.as<double>(), sc + 5, 8, s);
-        k_cgm_outer<<<nbm, 64, 0, s>>>(M, sc, bn2, tol * tol, sp.max_iter, its, alive, act);
-        poll.post(alive, 0, s);
-        if (poll.none(0)) break;
+    k_cgm_init<<<nbm, 64, 0, s>>>(M, sc, bn2, rmax, alive, upd, its);
+    launch_convert<float, double>(all, b, r, s);
+    launch_convert<float, float>(all, r, p, s);
+    launch_zero<float>(e, total, s);
+    launch_norm2<float>(sa, r, red.as<double>(), sc, 8, s);
+    for (int j = 0;; ++j) {
+        // one FP32 step: w = D^+ p, q = D w, e += alpha w, r -= alpha q, p = r + beta p
+        launch_dslash<float>(g, sa, U.u32, HOPS_ALL, -1, 1, p, p, w, k32, 0, g.nblk, s);
+        launch_dslash<float>(g, sa, U.u32, HOPS_ALL, -1, 0, w, w, q, k32, 0, g.nblk, s);
+        launch_norm2<float>(sa, w, red.as<double>(), sc + 1, 8, s);
+        k_cg_alpha<<<nbm, 64, 0, s>>>(M, alive, sc);
+        k_cg_update<float><<<nb256(total), 256, 0, s>>>(alive, n, total, sc, e, w, r, q);
+        launch_norm2<float>(sa, r, red.as<double>(), sc + 3, 8, s);
+        k_cg_beta<<<nbm, 64, 0, s>>>(M, alive, sc);
+        k_cg_p<float><<<nb256(total), 256, 0, s>>>(alive, n, total, sc, r, p);
+        k_cgm_step<<<nbm, 64, 0, s>>>(M, sc, RELIABLE_DELTA * RELIABLE_DELTA, sp.max_iter, alive, rmax, upd, its);
+        if (j % UPDATE_EVERY != UPDATE_EVERY - 1) continue;
+        // reliable update of the flagged systems
+        launch_add_to64<float>(su, e, x, s);
+        apply_D64(c, su, U, kappa, x, t64, s);
+        launch_sub(su, b, t64, r64, s);
+        launch_norm2<double>(su, r64, red.as<double>(), sc + 5, 8, s);
+        k_cgm_update<<<nbm, 64, 0, s>>>(M, sc, bn2, tol * tol, sp.max_iter, its, alive, upd, rmax);
+        k_cgm_refresh<<<nb256(total), 256, 0, s>>>(n, total, upd, alive, r64, r, e);
+        k_cgm_clear<<<nbm, 64, 0, s>>>(M, upd);
+        // poll one update point behind
+        const int pt = j / UPDATE_EVERY;
+        poll.post(alive, pt & 1, s);
+        if (pt > 0 && poll.none((pt - 1) & 1)) break;
     }
     std::vector<double> hbn2(M), rn2;
     std::vector<int32_t> hits(M);

@@ -93,3 +93,20 @@ WORKLOADS = {
     "wilson32_dd4096": dict(L=(32, 32, 32, 32), B=(4, 4, 4, 4), kappa=0.155, scale=0.2, op="schur",
                             noise="gauss", n_noise=32, proposal="active", seed=1112124303),
 }
+
+# batched proposals of uneven sizes: (lattice, count); 4^4 blocks (12^4 has 3
+# blocks per direction: fine for the full operator, which needs no colouring)
+BATCH_SIZES = (((8, 8, 8, 8), 24), ((12, 12, 12, 12), 24), ((16, 16, 16, 16), 16))
+BATCH_SEED = 1112124400
+
+
+def batch_proposals(sizes=BATCH_SIZES, seed0: int = BATCH_SEED, kappa_lo: float = 0.12, kappa_hi: float = 0.15):
+    """Seeds and hopping parameters of the batched-proposal workload: proposal
+    j has seed seed0 + j and kappa uniform in [kappa_lo, kappa_hi] (tag 4)."""
+    out, j = [], 0
+    for L, count in sizes:
+        for _ in range(count):
+            u = _rng(seed0 + j, 4).random()
+            out.append(dict(L=L, seed=seed0 + j, kappa=kappa_lo + (kappa_hi - kappa_lo) * u))
+            j += 1
+    return out
