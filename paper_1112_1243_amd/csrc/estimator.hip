@@ -26,12 +26,14 @@ namespace wdr {
 namespace {
 
 struct TmpGauge {
-    Work u64, u32;
-    explicit TmpGauge(wdr_ctx *c)
-        : u64(c, (size_t)c->g.V * 36 * sizeof(double2)), u32(c, (size_t)c->g.V * 36 * sizeof(float2))
+    Work u64, u32, u16;
+    TmpGauge(wdr_ctx *c, bool su3)
+        : u64(c, (size_t)c->g.V * 36 * sizeof(double2)), u32(c, (size_t)c->g.V * 36 * sizeof(float2)),
+          u16(c, su3 ? (size_t)c->g.V * 24 * sizeof(h2) : 256), has16(su3)
     {
     }
-    bool ok() const { return u64.ok() && u32.ok(); }
+    bool ok() const { return u64.ok() && u32.ok() && u16.ok(); }
+    bool has16;
 };
 
 // U_i of the path into dst
@@ -45,6 +47,7 @@ void make_path_gauge(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, int i,
     else
         launch_interpolate(c->g, U->u64, Up->u64, (double)i / N, dst.u64.as<double2>(), s);
     launch_convert_gauge_f32(c->g, dst.u64.as<double2>(), dst.u32.as<float2>(), s);
+    if (dst.has16) launch_pack_links_h16(c->g, dst.u64.as<double2>(), dst.u16.as<h2>(), s);
 }
 
 // device memory budget for the fields of one chunk of samples
@@ -64,10 +67,11 @@ wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wd
     // the path U_0 .. U_N of every proposal
     std::vector<std::unique_ptr<TmpGauge>> path;
     int su3 = 1;
+    for (const Proposal &q : props) su3 = su3 && q.U->su3 && q.Up->su3;  // the geodesic stays in SU(3)
+    const bool want16 = su3 && sp.inner == WDR_F16;
     for (const Proposal &q : props) {
-        su3 = su3 && q.U->su3 && q.Up->su3;  // the geodesic stays in SU(3) when both ends are
         for (int i = 0; i <= N; ++i) {
-            path.emplace_back(new TmpGauge(c));
+            path.emplace_back(new TmpGauge(c, want16));
             if (!path.back()->ok()) return WDR_ENOMEM;
             make_path_gauge(c, q.U, q.Up, i, N, *path.back(), s);
         }
@@ -92,13 +96,13 @@ wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wd
         const int M = std::min(Mmax, total - m0);
         const size_t fbm = fb * M;
         Work eta(c, fbm), y(c, fbm), z(c, fbm), w(c, fbm), r(c, fbm), t(c, fbm), pr(c, sizeof(double) * g.nblk * M);
-        Work tabs(c, 4 * M * sizeof(void *)), idx(c, 2 * M * sizeof(int32_t)), kw(c, M * sizeof(double)),
+        Work tabs(c, 6 * M * sizeof(void *)), idx(c, 2 * M * sizeof(int32_t)), kw(c, M * sizeof(double)),
             sw(c, M * sizeof(uint64_t));
         if (!eta.ok() || !y.ok() || !z.ok() || !w.ok() || !r.ok() || !t.ok() || !pr.ok() || !tabs.ok() || !idx.ok() ||
             !kw.ok() || !sw.ok())
             return WDR_ENOMEM;
         // per-system tables: X on U_i, X' on U_{i+1}; noise (step, sample, key); kappa
-        std::vector<const void *> ht(4 * M);
+        std::vector<const void *> ht(6 * M, nullptr);
         std::vector<int32_t> hi(2 * M);
         std::vector<double> hk(M);
         std::vector<uint64_t> hs(M);
@@ -108,6 +112,10 @@ wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wd
             ht[M + j] = point(q, i).u32.as<void>();
             ht[2 * M + j] = point(q, i + 1).u64.as<void>();
             ht[3 * M + j] = point(q, i + 1).u32.as<void>();
+            if (want16) {
+                ht[4 * M + j] = point(q, i).u16.as<void>();
+                ht[5 * M + j] = point(q, i + 1).u16.as<void>();
+            }
             hi[j] = i;
             hi[M + j] = k;
             hk[j] = props[q].kappa;
@@ -119,9 +127,12 @@ wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wd
         WDR_HIP(hipMemcpyAsync(sw.as<void>(), hs.data(), hs.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
         const void *const *tb = tabs.as<const void *const>();
         const double *kap = kw.as<const double>();
-        const GaugeTab X{{reinterpret_cast<UTab<double>>(tb), su3, kap}, {reinterpret_cast<UTab<float>>(tb + M), su3, kap}};
+        const GaugeTab X{{reinterpret_cast<UTab<double>>(tb), su3, kap},
+                         {reinterpret_cast<UTab<float>>(tb + M), su3, kap},
+                         {want16 ? reinterpret_cast<const h2 *const *>(tb + 4 * M) : nullptr, kap}};
         const GaugeTab Xp{{reinterpret_cast<UTab<double>>(tb + 2 * M), su3, kap},
-                          {reinterpret_cast<UTab<float>>(tb + 3 * M), su3, kap}};
+                          {reinterpret_cast<UTab<float>>(tb + 3 * M), su3, kap},
+                          {want16 ? reinterpret_cast<const h2 *const *>(tb + 5 * M) : nullptr, kap}};
         const Sys all = all_sys(c, M);
         double2 *E = eta.as<double2>(), *Y = y.as<double2>(), *Z = z.as<double2>(), *W = w.as<double2>(),
                 *R = r.as<double2>(), *Tm = t.as<double2>();

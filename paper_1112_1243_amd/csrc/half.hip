@@ -1,0 +1,116 @@
+// FP16 storage with per-block power-of-two scales for the inner solver
+// (blocks of Sec. 3).  A block's values are stored as fp16(v / s) with
+// s = 2^ceil(log2 max |component|) over the block, so every stored value lies
+// in [-1, 1] with an 11-bit significand and the scaling itself is exact;
+// arithmetic on FP16 data is done in FP32.  SU(3) links (entries of modulus
+// at most 1) are stored unscaled, first two rows only.
+#include "stencil.h"
+
+namespace wdr {
+namespace {
+
+using namespace dev;
+
+constexpr int NT = 256;
+
+// one workgroup per (slot, system): block maximum, scale, rounded store
+template <typename T>
+__global__ __launch_bounds__(NT) void k_to_h16(Geo g, const int32_t *__restrict__ active, long n, int slot0,
+                                              const T2<T> *__restrict__ in, h2 *__restrict__ out,
+                                              float *__restrict__ scale)
+{
+    __shared__ float red[NT / 64];
+    const int slot = slot0 + blockIdx.x, m = blockIdx.y;
+    if (active && !active[m]) return;
+    const long cnt = 12L * g.Vb, base = m * n + (long)slot * cnt;
+    float mx = 0.f;
+    for (long i = threadIdx.x; i < cnt; i += NT) {
+        const T2<T> v = in[base + i];
+        mx = fmaxf(mx, fmaxf(fabsf((float)v.x), fabsf((float)v.y)));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_down(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    float bmax = red[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) bmax = fmaxf(bmax, red[w]);
+    const float s = pow2_at_least(bmax), inv = 1.f / s;
+    for (long i = threadIdx.x; i < cnt; i += NT) {
+        const T2<T> v = in[base + i];
+        out[base + i] = to_h2(mk<float>((float)v.x, (float)v.y), inv);
+    }
+    if (threadIdx.x == 0) scale[(long)m * g.nblk + slot] = s;
+}
+
+__global__ __launch_bounds__(NT) void k_from_h16(Geo g, const int32_t *__restrict__ active, long n, long total,
+                                                const h2 *__restrict__ in, const float *__restrict__ scale,
+                                                double2 *__restrict__ y, int add)
+{
+    const long i = (long)blockIdx.x * NT + threadIdx.x;
+    if (i >= total) return;
+    const int m = (int)(i / n);
+    if (active && !active[m]) return;
+    const int slot = (int)((i - (long)m * n) / (12L * g.Vb));
+    const float s = scale[(long)m * g.nblk + slot];
+    const h2 v = in[i];
+    const double re = (double)((float)v.x * s), im = (double)((float)v.y * s);
+    if (add) {
+        const double2 o = y[i];
+        y[i] = make_double2(o.x + re, o.y + im);
+    } else {
+        y[i] = make_double2(re, im);
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_zero_h16(long total, long nscale, h2 *__restrict__ v, float *__restrict__ s)
+{
+    const long i = (long)blockIdx.x * NT + threadIdx.x;
+    if (i < total) v[i] = h2{(_Float16)0.f, (_Float16)0.f};
+    if (i < nscale) s[i] = 1.f;
+}
+
+// [slot][mu][9][Vb] FP64 -> [slot][mu][6][Vb] FP16 (rows 0 and 1)
+__global__ __launch_bounds__(NT) void k_pack_links_h16(long total, int Vb, const double2 *__restrict__ u64,
+                                                      h2 *__restrict__ u16)
+{
+    const long i = (long)blockIdx.x * NT + threadIdx.x;  // over slots x 4 x 6 x Vb
+    if (i >= total) return;
+    const long l = i % Vb, e = (i / Vb) % 6, sm = i / (6L * Vb);  // sm = slot * 4 + mu
+    const double2 v = u64[(sm * 9 + e) * Vb + l];
+    h2 r;
+    r.x = (_Float16)(float)v.x;
+    r.y = (_Float16)(float)v.y;
+    u16[i] = r;
+}
+
+inline unsigned nblocks(long n) { return (unsigned)((n + NT - 1) / NT); }
+
+}  // namespace
+
+template <typename T>
+void launch_to_h16(const Geo &g, const Sys &sy, const T2<T> *in, H16 out, int slot0, int nslots, hipStream_t s)
+{
+    if (nslots <= 0 || sy.M <= 0) return;
+    k_to_h16<T><<<dim3(nslots, sy.M), NT, 0, s>>>(g, sy.active, sy.n, slot0, in, out.v, out.s);
+}
+void launch_from_h16(const Geo &g, const Sys &sy, H16c in, double2 *y, int add, hipStream_t s)
+{
+    const long total = sy.n * sy.M;
+    if (total > 0) k_from_h16<<<nblocks(total), NT, 0, s>>>(g, sy.active, sy.n, total, in.v, in.s, y, add);
+}
+void launch_zero_h16(const Geo &g, const Sys &sy, H16 f, hipStream_t s)
+{
+    const long total = sy.n * sy.M, ns = (long)g.nblk * sy.M;
+    const long m = total > ns ? total : ns;
+    if (m > 0) k_zero_h16<<<nblocks(m), NT, 0, s>>>(total, ns, f.v, f.s);
+}
+void launch_pack_links_h16(const Geo &g, const double2 *u64, h2 *u16, hipStream_t s)
+{
+    const long total = (long)g.nblk * 4 * 6 * g.Vb;
+    k_pack_links_h16<<<nblocks(total), NT, 0, s>>>(total, g.Vb, u64, u16);
+}
+template void launch_to_h16<double>(const Geo &, const Sys &, const double2 *, H16, int, int, hipStream_t);
+template void launch_to_h16<float>(const Geo &, const Sys &, const float2 *, H16, int, int, hipStream_t);
+
+}  // namespace wdr

@@ -34,6 +34,23 @@ template <typename T> struct Links {
     const double *kap = nullptr;
 };
 
+// FP16 fields: [M][slot][12][Vb] values v / s with one power-of-two scale
+// s = 2^ceil(log2 max |component|) per system and block ([M][nblk] floats)
+struct H16 {
+    h2 *v;
+    float *s;
+};
+struct H16c {
+    const h2 *v;
+    const float *s;
+};
+// FP16 links of a batch: the first two rows of every link ([slot][mu][6][Vb],
+// SU(3) fields only), per-system table and optional kappa table
+struct Links16 {
+    const h2 *const *tab;
+    const double *kap = nullptr;
+};
+
 // out(x) = diag(x) - kappa * sum_{selected hops} [...] in(y), per system
 //   diag    NULL (no diagonal term) or a field supplying the diagonal term
 //   slots   [slot0, slot0 + nslots) receive output; other slots untouched
@@ -112,6 +129,22 @@ void launch_block_mr(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *r, T2
 // out[m * g.nblk + slot] = sum over the slot of |a|^2, slots in range
 void launch_slot_norm2(const Geo &g, const Sys &sy, const double2 *a, double *out, int slot0, int nslots,
                        hipStream_t s);
+
+// ---------------------------------------------------------------- FP16 storage
+// out = FP16 copy of in on the slots [slot0, slot0 + nslots) with fresh block scales
+template <typename T>
+void launch_to_h16(const Geo &g, const Sys &sy, const T2<T> *in, H16 out, int slot0, int nslots, hipStream_t s);
+// y (+)= in for every slot (add = 1: y += in)
+void launch_from_h16(const Geo &g, const Sys &sy, H16c in, double2 *y, int add, hipStream_t s);
+// values 0, scales 1
+void launch_zero_h16(const Geo &g, const Sys &sy, H16 f, hipStream_t s);
+// FP16 copy of the first two rows of the internal FP64 links
+void launch_pack_links_h16(const Geo &g, const double2 *u64, h2 *u16, hipStream_t s);
+// block MR with FP16 storage (4^4 blocks, SU(3) links): mode 0 is the Schwarz
+// sweep of launch_sap_colour, mode 1 the block MR of launch_block_mr; false
+// if the geometry or the links do not allow it
+bool launch_mr_h16(int mode, const Geo &g, const Sys &sy, Links16 U, H16c src, H16 dst, float kappa, int nmr,
+                   int slot0, int nslots, hipStream_t s);
 
 // ---------------------------------------------------------------- noise, path
 // system m gets the noise of path step steps[m], sample ks[m] (device

@@ -33,7 +33,8 @@ struct wdr_gauge {
     int device = 0;
     double2 *u64 = nullptr;  // internal FP64 links, boundary phases folded in
     float2 *u32 = nullptr;   // internal FP32 copy
-    void **tab = nullptr;    // device table {u64, u32} for single-system launches
+    wdr::h2 *u16 = nullptr;  // FP16 copy of the first two rows (SU(3) fields only)
+    void **tab = nullptr;    // device table {u64, u32, u16} for single-system launches
     int su3 = 0;             // every link is SU(3) to SU3_TOL (checked at upload)
 };
 
@@ -70,10 +71,13 @@ inline long field_n(const wdr_ctx *c) { return (long)c->g.V * 12; }
 struct GaugeTab {
     Links<double> u64;
     Links<float> u32;
+    Links16 u16;  // tab NULL when the fields are not SU(3)
 };
 inline GaugeTab view(const wdr_gauge *g)
 {
-    return {{reinterpret_cast<UTab<double>>(g->tab), g->su3}, {reinterpret_cast<UTab<float>>(g->tab + 1), g->su3}};
+    return {{reinterpret_cast<UTab<double>>(g->tab), g->su3},
+            {reinterpret_cast<UTab<float>>(g->tab + 1), g->su3},
+            {g->u16 ? reinterpret_cast<const h2 *const *>(g->tab + 2) : nullptr}};
 }
 
 struct Stats {

@@ -78,9 +78,21 @@ wdr_status check_params(const wdr_ctx *c, const wdr_solver_params &sp, bool need
         set_error("unknown solver");
         return WDR_EINVAL;
     }
-    if (sp.inner != WDR_F64 && sp.inner != WDR_F32) {
-        set_error("inner precision must be F64 or F32");
+    if (sp.inner != WDR_F64 && sp.inner != WDR_F32 && sp.inner != WDR_F16) {
+        set_error("inner precision must be F64, F32 or F16");
         return WDR_EINVAL;
+    }
+    if (sp.inner == WDR_F16) {
+        // FP16 storage is implemented in the 4^4-block Schwarz / block solver
+        if (sp.solver != WDR_SOLVER_FGCR_SAP && !needs_blocks) {
+            set_error("FP16 inner precision applies to the Schwarz preconditioner and block solves");
+            return WDR_EINVAL;
+        }
+        for (int mu = 0; mu < 4; ++mu)
+            if (c->g.B[mu] != 4) {
+                set_error("FP16 inner precision needs 4^4 blocks");
+                return WDR_EINVAL;
+            }
     }
     if (sp.solver == WDR_SOLVER_FGCR_SAP || needs_blocks) {
         if (sp.restart < 1 || sp.restart > 16 || sp.sap_cycles < 1 || sp.mr_steps < 1) {
@@ -331,12 +343,10 @@ wdr_status wdr_gauge_create(wdr_ctx *c, const double *dev_U, wdr_gauge **out, vo
     g->device = c->device;
     const size_t n = (size_t)c->g.V * 36;
     if (hipMalloc(&g->u64, n * sizeof(double2)) != hipSuccess || hipMalloc(&g->u32, n * sizeof(float2)) != hipSuccess ||
-        hipMalloc(&g->tab, 2 * sizeof(void *)) != hipSuccess) {
+        hipMalloc(&g->tab, 3 * sizeof(void *)) != hipSuccess) {
         set_error("gauge allocation failed");
         return WDR_ENOMEM;
     }
-    void *tab[2] = {g->u64, g->u32};
-    WDR_HIP(hipMemcpy(g->tab, tab, sizeof(tab), hipMemcpyHostToDevice));
     launch_pack_gauge<double>(c->g, c->geom.bc, reinterpret_cast<const double2 *>(dev_U), g->u64, s);
     launch_convert_gauge_f32(c->g, g->u64, g->u32, s);
     {
@@ -351,6 +361,16 @@ wdr_status wdr_gauge_create(wdr_ctx *c, const double *dev_U, wdr_gauge **out, vo
         WDR_HIP(hipStreamSynchronize(s));
         g->su3 = dev <= SU3_TOL;
     }
+    if (g->su3) {  // FP16 two-row copy for the FP16 inner solver
+        if (hipMalloc(&g->u16, (size_t)c->g.V * 24 * sizeof(h2)) != hipSuccess) {
+            set_error("gauge allocation failed");
+            return WDR_ENOMEM;
+        }
+        launch_pack_links_h16(c->g, g->u64, g->u16, s);
+    }
+    void *tab[3] = {g->u64, g->u32, g->u16};
+    WDR_HIP(hipMemcpyAsync(g->tab, tab, sizeof(tab), hipMemcpyHostToDevice, s));
+    WDR_HIP(hipStreamSynchronize(s));
     WDR_HIP(hipGetLastError());
     *out = g.release();
     return WDR_OK;
@@ -365,6 +385,7 @@ wdr_status wdr_gauge_destroy(wdr_gauge *g)
     (void)hipDeviceSynchronize();
     if (g->u64) (void)hipFree(g->u64);
     if (g->u32) (void)hipFree(g->u32);
+    if (g->u16) (void)hipFree(g->u16);
     if (g->tab) (void)hipFree(g->tab);
     delete g;
     return WDR_OK;

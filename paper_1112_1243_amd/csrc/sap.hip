@@ -490,26 +490,46 @@ __device__ __forceinline__ void sum_part(const typename C2<T>::type *part, int q
     }
 }
 
-template <typename T, int MODE, int B>
+//
+// ST = 1: FP16 storage (SAP / block solves with FP16 inner): links are the
+// FP16 two-row copy ([slot][mu][6][Vb]), src and dst are FP16 fields with a
+// power-of-two scale per system and block; the output's scale is the block
+// maximum of the new values (an LDS reduction: the workgroup owns the block).
+template <typename T, int MODE, int B, int ST>
 __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const int32_t *__restrict__ active,
-                                                                  UTab<T> Utab, const double *__restrict__ kap,
-                                                                  long n,
+                                                                  const void *const *__restrict__ Utab,
+                                                                  const double *__restrict__ kap, long n,
                                                                   const int32_t *__restrict__ sched,
-                                                                  const typename C2<T>::type *__restrict__ src,
-                                                                  typename C2<T>::type *__restrict__ dst, T kappa,
-                                                                  int nmr)
+                                                                  const void *__restrict__ src_v,
+                                                                  const float *__restrict__ src_s,
+                                                                  void *__restrict__ dst_v, float *__restrict__ dst_s,
+                                                                  T kappa, int nmr)
 {
     typedef Cube<B> CB;
+    typedef typename C2<T>::type T2;
     constexpr int Vb = CB::Vb, Vh = CB::Vh, NT = 4 * Vh;
     static_assert(Vh % 64 == 0, "a wavefront covers sites of one direction / spin only");
+    static_assert(ST == 0 || sizeof(T) == 4, "FP16 storage is computed in FP32");
     __shared__ DirLds<T, B> S;
     const int m = blockIdx.y;
     if (active && !active[m]) return;
     if (kap) kappa = (T)kap[m];
-    const typename C2<T>::type *__restrict__ U = Utab[m];
-    src += m * n;
-    dst += m * n;
+    const T2 *__restrict__ src = static_cast<const T2 *>(src_v) + m * n;
+    T2 *__restrict__ dst = static_cast<T2 *>(dst_v) + m * n;
+    const h2 *__restrict__ src16 = static_cast<const h2 *>(src_v) + m * n;
+    h2 *__restrict__ dst16 = static_cast<h2 *>(dst_v) + m * n;
+    const float *__restrict__ dsc = ST ? dst_s + (long)m * g.nblk : nullptr;
     const int slot = sched[blockIdx.x];
+    const float s_src = ST ? src_s[(long)m * g.nblk + slot] : 1.f, s_dst = ST ? dsc[slot] : 1.f;
+    // loads of the block's own src / dst values (element index i of the system)
+    auto ld_src = [&](long i) -> cx<T> {
+        if constexpr (ST) return ldh(as_global(src16), i, s_src);
+        else return ld<T>(src, i);
+    };
+    auto ld_dst = [&](long i) -> cx<T> {
+        if constexpr (ST) return ldh(as_global((const h2 *)dst16), i, s_dst);
+        else return ld<T>(dst, i);
+    };
     const int tid = threadIdx.x;
     const int w4 = __builtin_amdgcn_readfirstlane(tid / Vh);  // mu in hop phases, spin q in vector phases
     const int h = tid % Vh;
@@ -519,8 +539,12 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const i
     const long be = (long)slot * 12 * Vb + h, bo = be + Vh;
 
     // stage the block's links (two rows) in LDS
-    {
-        const auto *Ug = as_global(U);
+    if constexpr (ST) {
+        const auto *Ug = as_global(static_cast<const h2 *>(Utab[m]));
+        const long base = (long)slot * 4 * 6 * Vb;
+        for (int i = tid; i < 4 * 6 * Vb; i += NT) st<T>(S.lk, i, ldh(Ug, base + i, 1.f));
+    } else {
+        const auto *Ug = as_global(static_cast<const T2 *>(Utab[m]));
         const long base = (long)slot * 4 * 9 * Vb;
         for (int i = tid; i < 4 * 6 * Vb; i += NT) {
             const int mu = i / (6 * Vb), e = (i / Vb) % 6, l = i % Vb;
@@ -534,8 +558,6 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const i
         int nbr[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
-        const auto *Ug = as_global(U);
-        const auto *xg = as_global((const typename C2<T>::type *)dst);
         int nmu = g.slot_blk[slot];
         for (int d = 0; d < w4; ++d) nmu /= g.NB[d];
         nmu %= g.NB[w4];
@@ -551,11 +573,24 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const i
             }
             spinor<T> acc;
             zero(acc);
-            switch (w4) {
-            case 0: hop_dir_cube<T, HOPS_ALL, B, 0, 0, 1>(Ug, xg, slot, nbr, l, x, 0, acc, wf, wb); break;
-            case 1: hop_dir_cube<T, HOPS_ALL, B, 0, 1, 1>(Ug, xg, slot, nbr, l, x, 0, acc, wf, wb); break;
-            case 2: hop_dir_cube<T, HOPS_ALL, B, 0, 2, 1>(Ug, xg, slot, nbr, l, x, 0, acc, wf, wb); break;
-            default: hop_dir_cube<T, HOPS_ALL, B, 0, 3, 1>(Ug, xg, slot, nbr, l, x, 0, acc, wf, wb); break;
+            if constexpr (ST) {
+                const SpinorLdH<Vb> xin{as_global((const h2 *)dst16), dsc};
+                const LinkLdH<Vb> lk{as_global(static_cast<const h2 *>(Utab[m]))};
+                switch (w4) {
+                case 0: hop_dir_ld<T, HOPS_ALL, B, 0, 0, 1>(xin, lk, slot, nbr, l, x, acc, wf, wb); break;
+                case 1: hop_dir_ld<T, HOPS_ALL, B, 0, 1, 1>(xin, lk, slot, nbr, l, x, acc, wf, wb); break;
+                case 2: hop_dir_ld<T, HOPS_ALL, B, 0, 2, 1>(xin, lk, slot, nbr, l, x, acc, wf, wb); break;
+                default: hop_dir_ld<T, HOPS_ALL, B, 0, 3, 1>(xin, lk, slot, nbr, l, x, acc, wf, wb); break;
+                }
+            } else {
+                const auto *Ug = as_global(static_cast<const T2 *>(Utab[m]));
+                const auto *xg = as_global((const T2 *)dst);
+                switch (w4) {
+                case 0: hop_dir_cube<T, HOPS_ALL, B, 0, 0, 1>(Ug, xg, slot, nbr, l, x, 0, acc, wf, wb); break;
+                case 1: hop_dir_cube<T, HOPS_ALL, B, 0, 1, 1>(Ug, xg, slot, nbr, l, x, 0, acc, wf, wb); break;
+                case 2: hop_dir_cube<T, HOPS_ALL, B, 0, 2, 1>(Ug, xg, slot, nbr, l, x, 0, acc, wf, wb); break;
+                default: hop_dir_cube<T, HOPS_ALL, B, 0, 3, 1>(Ug, xg, slot, nbr, l, x, 0, acc, wf, wb); break;
+                }
             }
             put_part<T, Vh>(S.part, w4, h, acc);
             __syncthreads();
@@ -564,7 +599,7 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const i
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const long i = b + (long)(3 * w4 + a) * Vb;
-                const cx<T> r = ld<T>(src, i) - ld<T>(dst, i) + scale(kappa, v[a]);
+                const cx<T> r = ld_src(i) - ld_dst(i) + scale(kappa, v[a]);
                 if (par) ro[a] = r;
                 else re[a] = r;
             }
@@ -573,8 +608,8 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const i
     } else {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            re[a] = ld<T>(src, be + (long)(3 * w4 + a) * Vb);
-            ro[a] = ld<T>(src, bo + (long)(3 * w4 + a) * Vb);
+            re[a] = ld_src(be + (long)(3 * w4 + a) * Vb);
+            ro[a] = ld_src(bo + (long)(3 * w4 + a) * Vb);
         }
     }
 
@@ -674,16 +709,43 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const i
     }
     __syncthreads();
     sum_part<T, Vh>(S.part, w4, h, v);
+    // new values of spin q at even site h (ye) and odd site h (yo): x + d, or d
+    cx<T> ye[3], yo[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const cx<T> dodd = ro[a] + scale(kappa, v[a]);
         const long ie = be + (long)(3 * w4 + a) * Vb, io = bo + (long)(3 * w4 + a) * Vb;
-        if (MODE == 0) {  // x += d (this workgroup alone reads x of this block after its residual)
-            st<T>(dst, ie, ld<T>(dst, ie) + del[a]);
-            st<T>(dst, io, ld<T>(dst, io) + dodd);
+        // (MODE 0: this workgroup alone reads x of this block after its residual)
+        ye[a] = MODE == 0 ? ld_dst(ie) + del[a] : del[a];
+        yo[a] = MODE == 0 ? ld_dst(io) + dodd : dodd;
+    }
+    float inv = 1.f;
+    if constexpr (ST) {  // block maximum -> power-of-two scale of the output
+        float mx = 0.f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(ye[a].re), fabsf(ye[a].im)), fmaxf(fabsf(yo[a].re), fabsf(yo[a].im))));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_down(mx, off, 64));
+        __syncthreads();  // S.red is free again
+        if ((tid & 63) == 0) S.red[0][tid >> 6] = mx;
+        __syncthreads();
+        mx = S.red[0][0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) mx = fmaxf(mx, S.red[0][w]);
+        const float sc = pow2_at_least(mx);
+        inv = 1.f / sc;
+        if (tid == 0) dst_s[(long)m * g.nblk + slot] = sc;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const long ie = be + (long)(3 * w4 + a) * Vb, io = bo + (long)(3 * w4 + a) * Vb;
+        if constexpr (ST) {
+            dst16[ie] = to_h2(ye[a], inv);
+            dst16[io] = to_h2(yo[a], inv);
         } else {
-            st<T>(dst, ie, del[a]);
-            st<T>(dst, io, dodd);
+            st<T>(dst, ie, ye[a]);
+            st<T>(dst, io, yo[a]);
         }
     }
 }
@@ -697,8 +759,9 @@ bool launch_mr_cube4(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *src, 
     const int si = sched_index(g, slot0, nslots);
     if (si < 0) return false;
     if constexpr (sizeof(T) == 4)  // the FP64 partial sums would not fit in LDS next to the links
-        k_block_mr_dir<T, MODE, 4><<<dim3(nslots, sy.M), 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n,
-                                                                                g.sched[si], src, dst, kappa, nmr);
+        k_block_mr_dir<T, MODE, 4, 0><<<dim3(nslots, sy.M), 4 * Cube<4>::Vh, 0, s>>>(
+            g, sy.active, reinterpret_cast<const void *const *>(U.tab), U.kap, sy.n, g.sched[si], src, nullptr, dst,
+            nullptr, kappa, nmr);
     else
         k_block_mr_cube<T, MODE, 4><<<dim3(nslots, sy.M), 256, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, g.sched[si], src,
                                                                        dst, kappa, nmr);
@@ -723,6 +786,24 @@ void launch_block_mr(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *r, T2
     if (nslots <= 0 || sy.M <= 0) return;
     if (launch_mr_cube4<T, 1>(g, sy, U, r, d, kappa, nmr, slot0, nslots, s)) return;
     k_block_mr<T, 1><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, r, d, kappa, nmr, slot0);
+}
+
+bool launch_mr_h16(int mode, const Geo &g, const Sys &sy, Links16 U, H16c src, H16 dst, float kappa, int nmr,
+                   int slot0, int nslots, hipStream_t s)
+{
+    if (nslots <= 0 || sy.M <= 0) return true;
+    if (!U.tab || g.B[0] != 4 || g.B[1] != 4 || g.B[2] != 4 || g.B[3] != 4) return false;
+    const int si = sched_index(g, slot0, nslots);
+    if (si < 0) return false;
+    const dim3 grid(nslots, sy.M);
+    const auto *tab = reinterpret_cast<const void *const *>(U.tab);
+    if (mode == 0)
+        k_block_mr_dir<float, 0, 4, 1><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
+                                                                       src.v, src.s, dst.v, dst.s, kappa, nmr);
+    else
+        k_block_mr_dir<float, 1, 4, 1><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
+                                                                       src.v, src.s, dst.v, dst.s, kappa, nmr);
+    return true;
 }
 
 #define INST(T)                                                                                                  \

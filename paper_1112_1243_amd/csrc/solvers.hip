@@ -11,6 +11,7 @@
 // sp.inner (FP32 by default).  Krylov scalars stay in device memory; the
 // host reads the M residual norms once per iteration to stop converged
 // systems.
+#include <memory>
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -317,11 +318,48 @@ static void sap_run(wdr_ctx *c, const Sys &sy, Links<T> U, T kappa, int ncy, int
     }
 }
 
+// FP16 fields of M systems in the context's workspace pool
+struct H16Work {
+    Work v, sc;
+    H16Work(wdr_ctx *c, int M)
+        : v(c, field_bytes(c, WDR_F16) * M), sc(c, sizeof(float) * (size_t)c->g.nblk * M)
+    {
+    }
+    bool ok() const { return v.ok() && sc.ok(); }
+    H16 f() const { return {v.as<h2>(), sc.as<float>()}; }
+    H16c cf() const { return {v.as<const h2>(), sc.as<const float>()}; }
+};
+
+static wdr_status need16(const GaugeTab &U)
+{
+    if (U.u16.tab) return WDR_OK;
+    set_error("the FP16 inner solver needs SU(3) links and 4^4 blocks");
+    return WDR_EINVAL;
+}
+
 wdr_status sap64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
                  const double2 *in, double2 *out, hipStream_t s)
 {
     if (sp.inner == WDR_F64) {
         sap_run<double>(c, sy, U.u64, kappa, sp.sap_cycles, sp.mr_steps, in, out, s);
+        return WDR_OK;
+    }
+    if (sp.inner == WDR_F16) {
+        wdr_status e = need16(U);
+        if (e != WDR_OK) return e;
+        H16Work eh(c, sy.M), xh(c, sy.M);
+        if (!eh.ok() || !xh.ok()) return WDR_ENOMEM;
+        const Geo &g = c->g;
+        launch_to_h16<double>(g, sy, in, eh.f(), 0, g.nblk, s);
+        launch_zero_h16(g, sy, xh.f(), s);
+        int b0, bn, w0, wn;
+        colour_slots(c, 0, b0, bn);
+        colour_slots(c, 1, w0, wn);
+        for (int cy = 0; cy < sp.sap_cycles; ++cy)
+            if (!launch_mr_h16(0, g, sy, U.u16, eh.cf(), xh.f(), (float)kappa, sp.mr_steps, b0, bn, s) ||
+                !launch_mr_h16(0, g, sy, U.u16, eh.cf(), xh.f(), (float)kappa, sp.mr_steps, w0, wn, s))
+                return need16(GaugeTab{});
+        launch_from_h16(g, sy, xh.cf(), out, 0, s);
         return WDR_OK;
     }
     Work e(c, field_bytes(c, WDR_F32) * sy.M), x(c, field_bytes(c, WDR_F32) * sy.M);
@@ -671,10 +709,24 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
     k_block_init<<<nbm, 64, 0, s>>>(M, g.nblk, slot0, ns, bn, alive, its, worst);
     const int nmr = 16;
     const Sys sa{M, alive, n};
+    std::unique_ptr<H16Work> r16, d16;
+    if (sp.inner == WDR_F16) {
+        wdr_status e = need16(U);
+        if (e != WDR_OK) return e;
+        r16.reset(new H16Work(c, M));
+        d16.reset(new H16Work(c, M));
+        if (!r16->ok() || !d16->ok()) return WDR_ENOMEM;
+        launch_zero_h16(g, all, d16->f(), s);
+    }
     for (int round = 0; round < 40; ++round) {
         if (sp.inner == WDR_F64) {
             launch_block_mr<double>(g, sa, U.u64, r, d64.as<double2>(), kappa, nmr, slot0, ns, s);
             launch_add_to64<double>(sa, d64.as<double2>(), x, s);
+        } else if (sp.inner == WDR_F16) {
+            launch_to_h16<double>(g, sa, r, r16->f(), slot0, ns, s);
+            if (!launch_mr_h16(1, g, sa, U.u16, r16->cf(), d16->f(), (float)kappa, nmr, slot0, ns, s))
+                return need16(GaugeTab{});
+            launch_from_h16(g, sa, d16->cf(), x, 1, s);
         } else {
             launch_convert<float, double>(sa, r, r32.as<float2>(), s);
             launch_block_mr<float>(g, sa, U.u32, r32.as<float2>(), d32.as<float2>(), (float)kappa, nmr, slot0, ns, s);

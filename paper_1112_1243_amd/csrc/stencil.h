@@ -145,23 +145,56 @@ template <int B> struct Cube {
     }
 };
 
+// Loaders of the hop bodies below.  A spinor loader returns component c of
+// site nl of slot ns; a link loader returns entry e (row-major, e < 6 suffices
+// for two-row reads) of the link (slot, mu) at site l.  Offsets are 32-bit
+// element indices from the system's base pointer; `pin` is added to every
+// offset (see hop_sum_cube).
+template <typename T, int Vb> struct SpinorLd {
+    const __attribute__((address_space(1))) typename C2<T>::type *p;
+    int pin;
+    __device__ __forceinline__ cx<T> operator()(int ns, int c, int nl) const
+    {
+        return ldg<T>(p, ns * 12 * Vb + nl + pin + c * Vb);
+    }
+};
+template <typename T, int Vb> struct LinkLd {  // [slot][mu][9][Vb]
+    const __attribute__((address_space(1))) typename C2<T>::type *p;
+    int pin;
+    __device__ __forceinline__ cx<T> operator()(int sl, int mu, int e, int l) const
+    {
+        return ldg<T>(p, (sl * 4 + mu) * 9 * Vb + l + pin + e * Vb);
+    }
+};
+template <int Vb> struct SpinorLdH {  // FP16 with a scale per slot
+    const __attribute__((address_space(1))) h2 *p;
+    const float *scale;
+    __device__ __forceinline__ cx<float> operator()(int ns, int c, int nl) const
+    {
+        return ldh(p, ns * 12 * Vb + nl + c * Vb, scale[ns]);
+    }
+};
+template <int Vb> struct LinkLdH {  // FP16, first two rows: [slot][mu][6][Vb]
+    const __attribute__((address_space(1))) h2 *p;
+    __device__ __forceinline__ cx<float> operator()(int sl, int mu, int e, int l) const
+    {
+        return ldh(p, (sl * 4 + mu) * 6 * Vb + l + e * Vb, 1.f);
+    }
+};
+
 // One direction mu (compile time) of the hop sum at a site of a B^4 block:
 // the forward hop (1 - g_mu) U_mu(x) psi(x + mu) and the backward hop
-// (1 + g_mu) U_mu(x - mu)^+ psi(x - mu), added to acc.  `in` and `U` are the
-// system's base pointers; offsets are 32-bit element indices.
+// (1 + g_mu) U_mu(x - mu)^+ psi(x - mu), added to acc.
 //
 // R2: read only the first two rows of each link and rebuild the third as the
 // conjugated cross product of the first two (valid for SU(3) links), times
 // the boundary sign for links that wrap around the lattice; wrap_f / wrap_b
 // are that sign for the forward and the backward link of this site.
-template <typename T, int HOPS, int B, int DAG, int MU, int R2 = 0>
-__device__ __forceinline__ void hop_dir_cube(const __attribute__((address_space(1))) typename C2<T>::type *U,
-                                             const __attribute__((address_space(1))) typename C2<T>::type *in,
-                                             int slot, const int nbr[8], int l, const int x[4], int pin,
-                                             spinor<T> &acc, T wrap_f = 1, T wrap_b = 1)
+template <typename T, int HOPS, int B, int DAG, int MU, int R2, class SpL, class LkL>
+__device__ __forceinline__ void hop_dir_ld(const SpL &in, const LkL &U, int slot, const int nbr[8], int l,
+                                           const int x[4], spinor<T> &acc, T wrap_f, T wrap_b)
 {
     typedef Cube<B> CB;
-    constexpr int Vb = CB::Vb;
 #pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
         const bool fwd = dir == 0;
@@ -173,15 +206,13 @@ __device__ __forceinline__ void hop_dir_cube(const __attribute__((address_space(
         const int ns = inside ? slot : nbr[2 * MU + dir];
         const int nl = CB::index(y);
         spinor<T> p;
-        const int sb = ns * 12 * Vb + nl + pin;
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-            for (int a = 0; a < 3; ++a) p.s[sp].c[a] = ldg<T>(in, sb + (3 * sp + a) * Vb);
+            for (int a = 0; a < 3; ++a) p.s[sp].c[a] = in(ns, 3 * sp + a, nl);
         su3<T> u;
-        const int ub = ((fwd ? slot : ns) * 4 + MU) * 9 * Vb + (fwd ? l : nl) + pin;
 #pragma unroll
-        for (int e = 0; e < (R2 ? 6 : 9); ++e) u.m[e / 3][e % 3] = ldg<T>(U, ub + e * Vb);
+        for (int e = 0; e < (R2 ? 6 : 9); ++e) u.m[e / 3][e % 3] = U(fwd ? slot : ns, MU, e, fwd ? l : nl);
         if (R2) {
             const T sg = fwd ? wrap_f : wrap_b;
 #pragma unroll
@@ -218,6 +249,18 @@ __device__ __forceinline__ void hop_dir_cube(const __attribute__((address_space(
             acc.s[3].c[a] = fwd ? acc.s[3].c[a] - d1.c[a] : acc.s[3].c[a] + d1.c[a];
         }
     }
+}
+
+// hop_dir_ld on fields of the internal layout (FP32 / FP64 storage)
+template <typename T, int HOPS, int B, int DAG, int MU, int R2 = 0>
+__device__ __forceinline__ void hop_dir_cube(const __attribute__((address_space(1))) typename C2<T>::type *U,
+                                             const __attribute__((address_space(1))) typename C2<T>::type *in,
+                                             int slot, const int nbr[8], int l, const int x[4], int pin,
+                                             spinor<T> &acc, T wrap_f = 1, T wrap_b = 1)
+{
+    constexpr int Vb = Cube<B>::Vb;
+    hop_dir_ld<T, HOPS, B, DAG, MU, R2>(SpinorLd<T, Vb>{in, pin}, LinkLd<T, Vb>{U, pin}, slot, nbr, l, x, acc,
+                                        wrap_f, wrap_b);
 }
 
 // hop sum for B^4 blocks; nbr[8] are the neighbour slots of this block

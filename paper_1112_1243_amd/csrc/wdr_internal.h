@@ -64,6 +64,10 @@ template <typename T> struct C2;
 template <> struct C2<double> { typedef double2 type; };
 template <> struct C2<float> { typedef float2 type; };
 
+// FP16 storage of a complex number (two IEEE binary16 values); arithmetic on
+// such data is done in FP32
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
 template <typename T> struct Field {  // one spinor field in the internal layout
     typename C2<T>::type *p;
 };
@@ -111,14 +115,8 @@ template <typename T> __device__ __forceinline__ cx<T> ldg(const __attribute__((
     const __attribute__((address_space(1))) T *q = (const __attribute__((address_space(1))) T *)p;
     return {q[2 * i], q[2 * i + 1]};
 }
-// streaming variants: data used once (links, stencil output) is loaded and
-// stored non-temporally so it does not evict reusable lines from L2
-template <typename T> __device__ __forceinline__ cx<T> ldg_nt(const __attribute__((address_space(1))) typename C2<T>::type *p, long i)
-{
-    typedef T v2 __attribute__((ext_vector_type(2)));
-    const v2 v = __builtin_nontemporal_load((const __attribute__((address_space(1))) v2 *)p + i);
-    return {v.x, v.y};
-}
+// streaming store: the stencil output is not read again by the launch, so it
+// is written non-temporally
 template <typename T> __device__ __forceinline__ void st_nt(typename C2<T>::type *p, long i, cx<T> a)
 {
     typedef T v2 __attribute__((ext_vector_type(2)));
@@ -213,6 +211,29 @@ template <typename T> __device__ __forceinline__ void Adag_h(int mu, const vec3<
     case 2: o0 = vmap(h0, 2); o1 = vmap(h1, 3); break;
     default: o0 = h0; o1 = h1; break;
     }
+}
+
+// FP16 element i of a global field, times the block scale s
+__device__ __forceinline__ cx<float> ldh(const __attribute__((address_space(1))) h2 *p, long i, float s)
+{
+    const h2 v = p[i];
+    return {(float)v.x * s, (float)v.y * s};
+}
+// a / s rounded to FP16 (round to nearest even); inv = 1 / s is a power of two
+__device__ __forceinline__ h2 to_h2(cx<float> a, float inv)
+{
+    h2 r;
+    r.x = (_Float16)(a.re * inv);
+    r.y = (_Float16)(a.im * inv);
+    return r;
+}
+// the power of two 2^ceil(log2 mx) (1 for an all-zero block)
+__device__ __forceinline__ float pow2_at_least(float mx)
+{
+    if (!(mx > 0.f)) return 1.f;
+    int e;
+    const float f = frexpf(mx, &e);  // mx = f 2^e, f in [0.5, 1)
+    return ldexpf(1.f, f == 0.5f ? e - 1 : e);
 }
 
 }  // namespace dev

@@ -21,7 +21,7 @@ def _setup(L, B, scale, seed, bc=(1, 1, 1, 1)):
 
 
 @pytest.mark.parametrize("solver,kappa,scale,inner", [(0, 0.135, 0.5, 1), (1, 0.135, 0.5, 1), (1, 0.150, 0.25, 1),
-                                                      (1, 0.150, 0.25, 0), (0, 0.135, 0.5, 0)])
+                                                      (1, 0.150, 0.25, 0), (0, 0.135, 0.5, 0), (0, 0.135, 0.5, 2)])
 def test_solve_true_residual(solver, kappa, scale, inner):
     """The oracle's own stencil checks the GPU solution: ||b - D x|| <= 1e-10 ||b||
     (CGNE with inner FP32 is the mixed-precision form: FP32 CG cycles inside
@@ -58,14 +58,18 @@ def _pair(lat, U, scale, seed, rule):
     (oracle.OP_SCHUR, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 2, 1, 0),
     (oracle.OP_BLOCKS, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 2, 1, 0),
     (oracle.OP_SCHUR, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.150, 0.25, "active", 1, 1, 1),
+    # FP16 Schwarz preconditioner and FP16 block solves inside the FP64 outer solves
+    (oracle.OP_SCHUR, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 2, 1, 2),
+    (oracle.OP_BLOCKS, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 1, 1, 2),
 ])
 def test_samples_match_oracle(op, kind, L, B, kappa, scale, rule, N, K, solver):
-    """s_{i,k} within 1e-8 absolute of the oracle at solver residual 1e-10."""
+    """s_{i,k} within 1e-8 absolute of the oracle at solver residual 1e-10
+    (solver 2: FGCR with the FP16 inner solver)."""
     wdr, lat, ctx, U = _setup(L, B, scale, 1112124300 + len(L) * L[0])
     Up = _pair(lat, U, scale, 303, rule)
     gU, gUp = ctx.gauge(dev(U)), ctx.gauge(dev(Up))
     seed = 99
-    p = wdr.default_params(solver=solver)
+    p = wdr.default_params(solver=0, inner=wdr.F16) if solver == 2 else wdr.default_params(solver=solver)
     s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, op, N, K, kind, seed, p)
     want, lr_want = oracle.logdet_ratio(lat, U, Up, kappa, op, N, K, kind, seed)
     err = np.abs(s - want).max()

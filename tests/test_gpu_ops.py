@@ -195,7 +195,32 @@ def test_sap_general_links():
     ctx.close()
 
 
-@pytest.mark.parametrize("inner", [0, 1])
+def test_sap_f16_matches_oracle():
+    """FP16 storage with per-block power-of-two scales (links, source and
+    iterate; FP32 arithmetic): the Schwarz sweeps follow the FP64 oracle to
+    FP16 accuracy.  Links that are not SU(3) are refused."""
+    from paper_1112_1243_amd import wdr
+    L, B, bc = (8, 8, 8, 8), (4, 4, 4, 4), (1, 1, 1, -1)
+    lat = oracle.Lattice(L, B, bc)
+    ctx = _ctx(L, B, bc)
+    U = synth.gauge_field(L, 0.5, 116)
+    eta = synth.spinor(L, 117)
+    gU = ctx.gauge(dev(U))
+    for ncy, nmr in ((1, 1), (4, 5)):
+        want = oracle.sap(lat, U, 0.135, eta, ncy, nmr)
+        got = host(ctx.sap(gU, 0.135, dev(eta), wdr.default_params(sap_cycles=ncy, mr_steps=nmr, inner=wdr.F16)))
+        got32 = host(ctx.sap(gU, 0.135, dev(eta), wdr.default_params(sap_cycles=ncy, mr_steps=nmr, inner=wdr.F32)))
+        say("sap f16", ncy, nmr, rel(got, want), "f32", rel(got32, want))
+        assert rel(got, want) < 4e-3
+    gN = ctx.gauge(dev(1.01 * U))
+    with pytest.raises(wdr.WdrError) as e:
+        ctx.sap(gN, 0.135, dev(eta), wdr.default_params(inner=wdr.F16))
+    assert e.value.status == wdr.EINVAL
+    del gU, gN
+    ctx.close()
+
+
+@pytest.mark.parametrize("inner", [0, 1, 2])
 def test_block_solve(inner):
     from paper_1112_1243_amd import wdr
     L, B = (8, 8, 8, 8), (4, 4, 4, 4)
