@@ -56,6 +56,69 @@ def make_inputs(wl):
     return U
 
 
+def proposal_mask(ctx, rule):
+    """[site, mu] mask of the links a proposal redraws, from the library's
+    geometry maps: 'active' = the active links of every block (both ends in
+    the block, at most one on its boundary); 'black_blocks' = every link with
+    both ends in the same black block."""
+    if rule == "active":
+        return ctx.active_links(0, ctx.B[0] - 1).cpu().numpy().astype(bool)
+    assert rule == "black_blocks"
+    bid, col, _, _ = [t.cpu().numpy() for t in ctx.site_maps()]
+    L = ctx.L
+    site = np.arange(ctx.V)
+    x = [site % L[0], (site // L[0]) % L[1], (site // (L[0] * L[1])) % L[2], site // (L[0] * L[1] * L[2])]
+    mask = np.zeros((ctx.V, 4), bool)
+    for mu in range(4):
+        y = [c.copy() for c in x]
+        y[mu] = (y[mu] + 1) % L[mu]
+        nb = y[0] + L[0] * (y[1] + L[1] * (y[2] + L[2] * y[3]))
+        mask[:, mu] = (bid == bid[nb]) & (col == 0)
+    return mask
+
+
+def dd_workload(wdr, torch, name):
+    """One estimate of a larger lattice workload of synth.WORKLOADS: the mixed
+    form (FP16 block solves, CGNE with FP32 iterations and FP64 reliable
+    updates, all samples batched) against the plain FP64 form (FP64 block
+    solves and CGNE, one sample at a time)."""
+    from paper_1112_1243_amd import synth
+    w = synth.WORKLOADS[name]
+    t0 = time.perf_counter()
+    ctx = wdr.Context(w["L"], w["B"])
+    U = synth.gauge_field(w["L"], w["scale"], w["seed"])
+    Up = synth.redraw(U, proposal_mask(ctx, w["proposal"]), w["scale"], w["seed"])
+    gU, gUp = ctx.gauge(torch.from_numpy(U).cuda()), ctx.gauge(torch.from_numpy(Up).cuda())
+    del U, Up
+    log("%s: inputs ready in %.1f s" % (name, time.perf_counter() - t0))
+    op = {"schur": wdr.OP_SCHUR, "full": wdr.OP_FULL, "blocks": wdr.OP_BLOCKS}[w["op"]]
+    noise = wdr.NOISE_GAUSS if w["noise"] == "gauss" else wdr.NOISE_Z2
+    N = w["n_noise"]
+    mixed = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F16, max_iter=20000)
+    plain = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F64, max_iter=20000)
+    ctx.logdet_ratio(gU, gUp, w["kappa"], op, 1, 1, noise, 1, mixed)  # warm-up
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s_m, lr_m, info_m = ctx.logdet_ratio(gU, gUp, w["kappa"], op, N, 1, noise, w["seed"], mixed)
+    torch.cuda.synchronize()
+    t_m = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    s_p, lr_p, info_p = ctx.logdet_ratio(gU, gUp, w["kappa"], op, N, 1, noise, w["seed"], plain, max_batch=1)
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t1
+    log("%s: mixed %.3f s (CG its %d), plain fp64 %.3f s (CG its %d), max |ds| %.2e"
+        % (name, t_m, info_m.total_iters, t_p, info_p.total_iters, float(np.abs(s_m - s_p).max())))
+    del gU, gUp
+    ctx.close()
+    return {"workload": "%s: %s lattice, %s blocks, kappa %.3f, links exp(i %.2f H), %s ratio, N=%d factors x 1 %s "
+                        "noise, CGNE to 1e-10" % (name, "x".join(map(str, w["L"])), "x".join(map(str, w["B"])),
+                                                  w["kappa"], w["scale"], w["op"].upper(), N, w["noise"]),
+            "value": round(1.0 / t_m, 4), "unit": "estimates/s", "converged": bool(info_m.converged),
+            "cg_iterations_total": int(info_m.total_iters),
+            "fp64_estimates_per_s": round(1.0 / t_p, 4), "speedup_vs_fp64": round(t_p / t_m, 2),
+            "max_abs_sample_diff_vs_fp64": float("%.3e" % float(np.abs(s_m - s_p).max()))}
+
+
 def estimate(ctx, wdr, gU, gUp, wl, params, seed):
     """One complete estimate: block ratios + Schur ratio."""
     sb, lb, ib = ctx.logdet_ratio(gU, gUp, wl["kappa"], wdr.OP_BLOCKS, wl["n_steps"], wl["n_noise"],
@@ -299,6 +362,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-dslash", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-proposal workload")
+    ap.add_argument("--no-large", action="store_true", help="skip the 16^4 and 32^4 workloads")
     ap.add_argument("--rocprof-summary", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     args = ap.parse_args()
     if args.rocprof_summary:
@@ -311,15 +375,11 @@ def main():
 
     import torch
     from paper_1112_1243_amd import synth, wdr
-    import oracle  # noqa: F401  (CPU baseline only)
 
     wl = WORKLOAD
-    from oracle import Lattice, active_links
-    lat = Lattice(wl["L"], wl["B"])
-    U = make_inputs(wl)
-    Up = synth.redraw(U, active_links(lat), wl["scale"], wl["seed"])
-
     ctx = wdr.Context(wl["L"], wl["B"])
+    U = make_inputs(wl)
+    Up = synth.redraw(U, proposal_mask(ctx, "active"), wl["scale"], wl["seed"])
     gU = ctx.gauge(torch.from_numpy(U).cuda())
     gUp = ctx.gauge(torch.from_numpy(Up).cuda())
     mixed = wdr.default_params(inner=wdr.F32)
@@ -369,6 +429,9 @@ def main():
     batch = None if args.no_batch else batched_proposals(wdr, torch)
     if batch:
         log("batched proposals:", batch)
+    large = None
+    if not args.no_large:
+        large = {name: dd_workload(wdr, torch, name) for name in ("wilson16_dd256", "wilson32_dd4096")}
 
     cpu = None if args.no_cpu else cpu_baseline(wl, U, Up)
     if cpu:
@@ -394,6 +457,7 @@ def main():
         "fp64_estimates_per_s": None if fp64_rate is None else round(fp64_rate, 4),
         "roofline": roof,
         "batched_proposals": batch,
+        "large_lattices": large,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
