@@ -67,13 +67,13 @@ __global__ __launch_bounds__(NT) void k_multidot_partial(const int32_t *active, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_dot_partial(const int32_t *active, long n,
+__global__ __launch_bounds__(NT) void k_dot_partial(const int32_t *active, const int32_t *list, long n,
                                                     const typename C2<T>::type *__restrict__ a,
                                                     const typename C2<T>::type *__restrict__ b, int norm,
                                                     double *partial)
 {
     __shared__ double sh[4];
-    const int G = gridDim.x, m = blockIdx.y;
+    const int G = gridDim.x, m = sys_at(list, blockIdx.y);
     if (off(active, m)) return;
     a += m * n;
     b += m * n;
@@ -97,11 +97,11 @@ __global__ __launch_bounds__(NT) void k_dot_partial(const int32_t *active, long 
 }
 
 // out[m * ostride + j] = sum over the G partials, fixed order
-__global__ __launch_bounds__(NT) void k_final(const int32_t *active, const double *partial, int G, int nv,
-                                              double2 *out, int ostride)
+__global__ __launch_bounds__(NT) void k_final(const int32_t *active, const int32_t *list, const double *partial,
+                                              int G, int nv, double2 *out, int ostride)
 {
     __shared__ double sh[4];
-    const int m = blockIdx.x;
+    const int m = sys_at(list, blockIdx.x);
     if (off(active, m)) return;
     for (int j = 0; j < nv; ++j) {
         const double *p = partial + ((long)m * nv + j) * 2 * G;
@@ -205,36 +205,33 @@ __global__ __launch_bounds__(NT) void k_scale_invsqrt(const int32_t *active, lon
     y[i] = make_double2(f * v.x, f * v.y);
 }
 
-__global__ __launch_bounds__(NT) void k_sub(const int32_t *active, long n, long total, const double2 *b,
-                                            const double2 *a, double2 *r)
+
+__global__ __launch_bounds__(NT) void k_sub(const int32_t *active, const int32_t *list, long n, long total,
+                                            const double2 *b, const double2 *a, double2 *r)
 {
-    const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= total) return;
-    if (off(active, (int)(i / n))) return;
+    const long k = (long)blockIdx.x * NT + threadIdx.x;
+    if (k >= total) return;
+    int m;
+    const long i = batch_index(list, n, k, m);
+    if (off(active, m)) return;
     const double2 u = b[i], v = a[i];
     r[i] = make_double2(u.x - v.x, u.y - v.y);
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_add_to64(const int32_t *active, long n, long total,
+__global__ __launch_bounds__(NT) void k_add_to64(const int32_t *active, const int32_t *list, long n, long total,
                                                  const typename C2<T>::type *x, double2 *y)
 {
-    const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= total) return;
-    if (off(active, (int)(i / n))) return;
+    const long k = (long)blockIdx.x * NT + threadIdx.x;
+    if (k >= total) return;
+    int m;
+    const long i = batch_index(list, n, k, m);
+    if (off(active, m)) return;
     const typename C2<T>::type u = x[i];
     const double2 v = y[i];
     y[i] = make_double2(v.x + (double)u.x, v.y + (double)u.y);
 }
 
-__global__ __launch_bounds__(NT) void k_copy_flagged(long n, long total, const int32_t *flag, const double2 *src,
-                                                     double2 *dst)
-{
-    const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= total) return;
-    if (!flag[i / n]) return;
-    dst[i] = src[i];
-}
 
 // per-slot squared norm, workgroup (slot, m)
 __global__ __launch_bounds__(NT) void k_slot_norm2(Geo g, const int32_t *active, long n, const double2 *a,
@@ -265,23 +262,23 @@ void launch_multidot(const Sys &sy, const T2<T> *const *v, int nv, const T2<T> *
     if (nv <= 0) return;
     const int G = red_grid(sy.n);
     k_multidot_partial<T><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, v, nv, y, red);
-    k_final<<<sy.M, NT, 0, s>>>(sy.active, red, G, nv, out, ostride);
+    k_final<<<sy.M, NT, 0, s>>>(sy.active, nullptr, red, G, nv, out, ostride);
 }
 
 template <typename T>
 void launch_dot(const Sys &sy, const T2<T> *a, const T2<T> *b, double *red, double2 *out, int ostride, hipStream_t s)
 {
     const int G = red_grid(sy.n);
-    k_dot_partial<T><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, a, b, 0, red);
-    k_final<<<sy.M, NT, 0, s>>>(sy.active, red, G, 1, out, ostride);
+    k_dot_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, a, b, 0, red);
+    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
 }
 
 template <typename T>
 void launch_norm2(const Sys &sy, const T2<T> *a, double *red, double2 *out, int ostride, hipStream_t s)
 {
     const int G = red_grid(sy.n);
-    k_dot_partial<T><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, a, a, 1, red);
-    k_final<<<sy.M, NT, 0, s>>>(sy.active, red, G, 1, out, ostride);
+    k_dot_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, a, a, 1, red);
+    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
 }
 
 template <typename TO, typename TI> void launch_convert(const Sys &sy, const T2<TI> *a, T2<TO> *out, hipStream_t s)
@@ -318,18 +315,13 @@ void launch_scale_invsqrt(const Sys &sy, const double2 *nrm, int nstride, double
 }
 void launch_sub(const Sys &sy, const double2 *b, const double2 *a, double2 *r, hipStream_t s)
 {
-    const long total = sy.n * sy.M;
-    k_sub<<<nblk(total), NT, 0, s>>>(sy.active, sy.n, total, b, a, r);
+    const long total = sy.n * sy.launch_m();
+    k_sub<<<nblk(total), NT, 0, s>>>(sy.active, sy.list, sy.n, total, b, a, r);
 }
 template <typename T> void launch_add_to64(const Sys &sy, const T2<T> *x, double2 *y, hipStream_t s)
 {
-    const long total = sy.n * sy.M;
-    k_add_to64<T><<<nblk(total), NT, 0, s>>>(sy.active, sy.n, total, x, y);
-}
-void launch_copy_flagged(const Sys &sy, const int32_t *flag, const double2 *src, double2 *dst, hipStream_t s)
-{
-    const long total = sy.n * sy.M;
-    k_copy_flagged<<<nblk(total), NT, 0, s>>>(sy.n, total, flag, src, dst);
+    const long total = sy.n * sy.launch_m();
+    k_add_to64<T><<<nblk(total), NT, 0, s>>>(sy.active, sy.list, sy.n, total, x, y);
 }
 void launch_slot_norm2(const Geo &g, const Sys &sy, const double2 *a, double *out, int slot0, int nslots,
                        hipStream_t s)

@@ -35,15 +35,16 @@ template <typename T> struct G5Loader {
 };
 
 template <typename T, int HOPS>
-__global__ __launch_bounds__(256) void k_dslash(Geo g, const int32_t *__restrict__ active, UTab<T> Utab,
-                                                const double *__restrict__ kap, long n,
+__global__ __launch_bounds__(256) void k_dslash(Geo g, const int32_t *__restrict__ active,
+                                                const int32_t *__restrict__ list, UTab<T> Utab,
+                                                const double *__restrict__ kap, int kneg, long n,
                                                 int par, int dag, const typename C2<T>::type *__restrict__ in,
                                                 const typename C2<T>::type *__restrict__ diag,
                                                 typename C2<T>::type *__restrict__ out, T kappa, int slot0)
 {
-    const int m = blockIdx.z;
+    const int m = sys_at(list, blockIdx.z);
     if (active && !active[m]) return;
-    if (kap) kappa = (T)kap[m];
+    if (kap) kappa = kneg ? -(T)kap[m] : (T)kap[m];
     const int Vb = g.Vb;
     const int nloc = par < 0 ? Vb : g.Vh;
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -80,8 +81,9 @@ __global__ __launch_bounds__(256) void k_dslash(Geo g, const int32_t *__restrict
 // four partial sums meet in LDS; wavefront w then adds spin w of the diagonal
 // term and writes spin w of the result (contiguous over the 64 sites).
 template <typename T, int HOPS, int B, int DAG, int R2>
-__global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__restrict__ active, UTab<T> Utab,
-                                                    const double *__restrict__ kap, long n,
+__global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__restrict__ active,
+                                                    const int32_t *__restrict__ list, UTab<T> Utab,
+                                                    const double *__restrict__ kap, int kneg, long n,
                                                     const int32_t *__restrict__ sched, int par, int chunks,
                                                     int xcd8, const T2<T> *__restrict__ in,
                                                     const T2<T> *__restrict__ diag, T2<T> *__restrict__ out, T kappa)
@@ -89,9 +91,9 @@ __global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__rest
     typedef Cube<B> CB;
     constexpr int Vb = CB::Vb;
     __shared__ T2<T> part[4][12][64];  // [mu][colour-spin component][site]
-    const int m = blockIdx.y;
+    const int m = sys_at(list, blockIdx.y);
     if (active && !active[m]) return;
-    if (kap) kappa = (T)kap[m];
+    if (kap) kappa = kneg ? -(T)kap[m] : (T)kap[m];
     // workgroup i runs on XCD i % 8; with a slot count divisible by 8 all
     // chunks of a block go to the XCD the schedule gives that block
     int bi, chunk;
@@ -167,11 +169,11 @@ bool launch_cube(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int
     const int nt = par < 0 ? Cube<B>::Vb : Cube<B>::Vh;
     static_assert(Cube<B>::Vh % 64 == 0, "sites of one parity fill whole wavefronts");
     const int chunks = nt / 64;
-    const dim3 grid(nslots * chunks, sy.M);
+    const dim3 grid(nslots * chunks, sy.launch_m());
     const int xcd8 = nslots % 8 == 0;
     const int32_t *sc = g.sched[si];
 #define WDR_DIR(H, D, R)                                                                                     \
-    k_dslash_dir<T, H, B, D, R><<<grid, 256, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, sc, par, chunks, xcd8, in, diag, out, \
+    k_dslash_dir<T, H, B, D, R><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, sc, par, chunks, xcd8, in, diag, out, \
                                                      kappa)
 #define WDR_DIR2(H, D)                                                                                       \
     do {                                                                                                     \
@@ -367,13 +369,13 @@ void launch_dslash(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, i
     if (nslots <= 0 || sy.M <= 0) return;
     if (launch_cube<T, 4>(g, sy, U, hops, par, dag, in, diag, out, kappa, slot0, nslots, s)) return;
     const int nloc = par < 0 ? g.Vb : g.Vh;
-    dim3 grid((nloc + 255) / 256, nslots, sy.M);
+    dim3 grid((nloc + 255) / 256, nslots, sy.launch_m());
     if (hops == HOPS_ALL)
-        k_dslash<T, HOPS_ALL><<<grid, 256, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, par, dag, in, diag, out, kappa, slot0);
+        k_dslash<T, HOPS_ALL><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, par, dag, in, diag, out, kappa, slot0);
     else if (hops == HOPS_IN)
-        k_dslash<T, HOPS_IN><<<grid, 256, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, par, dag, in, diag, out, kappa, slot0);
+        k_dslash<T, HOPS_IN><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, par, dag, in, diag, out, kappa, slot0);
     else
-        k_dslash<T, HOPS_CROSS><<<grid, 256, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, par, dag, in, diag, out, kappa, slot0);
+        k_dslash<T, HOPS_CROSS><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, par, dag, in, diag, out, kappa, slot0);
 }
 
 template <typename T> void launch_pack_spinor(const Geo &g, const double2 *canon, typename C2<T>::type *out, hipStream_t s)

@@ -18,6 +18,12 @@ struct Sys {
     int M = 1;
     const int32_t *active = nullptr;  // device [M]
     long n = 0;                       // complex numbers per field (12 V)
+    // optional device list of the systems a launch covers (count entries);
+    // every system left out must be inactive.  Launchers that support it
+    // size their grids by count (the others launch over all M, still correct)
+    const int32_t *list = nullptr;
+    int count = 0;
+    int launch_m() const { return list ? count : M; }
 };
 
 template <typename T> using T2 = typename C2<T>::type;
@@ -32,6 +38,7 @@ template <typename T> struct Links {
     UTab<T> tab;
     int su3;
     const double *kap = nullptr;
+    int kneg = 0;  // stencil launches use -kap[m] (the kappa argument is then -kappa too)
 };
 
 // FP16 fields: [M][slot][12][Vb] values v / s with one power-of-two scale
@@ -112,8 +119,6 @@ void launch_scale_invsqrt(const Sys &sy, const double2 *nrm, int nstride, double
 void launch_sub(const Sys &sy, const double2 *b, const double2 *a, double2 *r, hipStream_t s);
 // y += x for FP64 y and x of precision T
 template <typename T> void launch_add_to64(const Sys &sy, const T2<T> *x, double2 *y, hipStream_t s);
-// per-system copy dst[m] = src[m] where flag[m] != 0
-void launch_copy_flagged(const Sys &sy, const int32_t *flag, const double2 *src, double2 *dst, hipStream_t s);
 
 // ---------------------------------------------------------------- SAP, MR
 // Schwarz half-sweep on the blocks of one colour (slots [slot0, slot0 +

@@ -42,21 +42,17 @@ __global__ void k_cg_beta(int M, const int32_t *active, double2 *sc)
     q[4] = make_double2(rr > 0 ? q[3].x / rr : 0.0, 0.0);
     q[0] = q[3];
 }
-// restart from the true residual: rr = true residual where flag is set
-__global__ void k_cg_restart(int M, const int32_t *flag, double2 *sc)
-{
-    const int m = blockIdx.x * 64 + threadIdx.x;
-    if (m >= M || !flag[m]) return;
-    sc[8L * m] = sc[8L * m + 5];
-}
+
 // x += alpha w, r -= alpha q
 template <typename T>
-__global__ __launch_bounds__(256) void k_cg_update(const int32_t *active, long n, long total, const double2 *sc,
-                                                   T2<T> *x, const T2<T> *w, T2<T> *r, const T2<T> *q)
+__global__ __launch_bounds__(256) void k_cg_update(const int32_t *active, const int32_t *list, long n, long total,
+                                                   const double2 *sc, T2<T> *x, const T2<T> *w, T2<T> *r,
+                                                   const T2<T> *q)
 {
-    const long i = (long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= total) return;
-    const int m = (int)(i / n);
+    const long k = (long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= total) return;
+    int m;
+    const long i = batch_index(list, n, k, m);
     if (active && !active[m]) return;
     const T a = (T)sc[8L * m + 2].x;
     const T2<T> xi = x[i], wi = w[i], ri = r[i], qi = q[i];
@@ -67,12 +63,13 @@ __global__ __launch_bounds__(256) void k_cg_update(const int32_t *active, long n
 }
 // p = r + beta p
 template <typename T>
-__global__ __launch_bounds__(256) void k_cg_p(const int32_t *active, long n, long total, const double2 *sc,
-                                              const T2<T> *r, T2<T> *p)
+__global__ __launch_bounds__(256) void k_cg_p(const int32_t *active, const int32_t *list, long n, long total,
+                                              const double2 *sc, const T2<T> *r, T2<T> *p)
 {
-    const long i = (long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= total) return;
-    const int m = (int)(i / n);
+    const long k = (long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= total) return;
+    int m;
+    const long i = batch_index(list, n, k, m);
     if (active && !active[m]) return;
     const T b = (T)sc[8L * m + 4].x;
     const T2<T> ri = r[i], pi = p[i];
@@ -120,16 +117,25 @@ __global__ void k_cgm_update(int M, double2 *sc, const double *bn2, double tol2,
     rmax[m] = r;
 }
 // r = (FP32) r64 and e = 0 for the updated systems; clears their flag
-__global__ __launch_bounds__(256) void k_cgm_refresh(long n, long total, int32_t *upd, const int32_t *alive,
-                                                     const double2 *r64, float2 *r, float2 *e)
+template <typename T>
+__global__ __launch_bounds__(256) void k_cgm_refresh(const int32_t *list, long n, long total, int32_t *upd,
+                                                     const double2 *r64, T2<T> *r, T2<T> *e)
 {
-    const long i = (long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= total) return;
-    const int m = (int)(i / n);
+    const long k = (long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= total) return;
+    int m;
+    const long i = batch_index(list, n, k, m);
     if (!upd[m]) return;
     const double2 v = r64[i];
-    r[i] = make_float2((float)v.x, (float)v.y);
-    e[i] = make_float2(0.f, 0.f);
+    r[i].x = (T)v.x;
+    r[i].y = (T)v.y;
+    e[i].x = e[i].y = (T)0;
+}
+// reference of the first reliable-update test: the initial iterated residual
+__global__ void k_cgm_rmax(int M, const double2 *sc, double *rmax)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < M) rmax[m] = sc[8L * m].x;
 }
 __global__ void k_cgm_clear(int M, int32_t *upd)
 {
@@ -140,20 +146,6 @@ __global__ void k_cgm_clear(int M, int32_t *upd)
 inline unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
 inline unsigned nb64(long n) { return (unsigned)((n + 63) / 64); }
 
-// a device copy of a host int vector, refreshed on demand
-struct DevFlags {
-    Work w;
-    std::vector<int32_t> h;
-    DevFlags(wdr_ctx *c, int M) : w(c, sizeof(int32_t) * std::max(M, 1)), h(M, 0) {}
-    int32_t *d() const { return w.as<int32_t>(); }
-    void upload(hipStream_t s) { (void)hipMemcpyAsync(d(), h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s); }
-    bool any() const
-    {
-        for (int v : h)
-            if (v) return true;
-        return false;
-    }
-};
 
 // reads `count` device values (`stride` complex numbers apart, the .x part)
 // to host; copies exactly the (count - 1) * stride + 1 entries spanned
@@ -487,164 +479,130 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
 
 // ------------------------------------------------------------ CGNE
 
-static wdr_status cgne(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp, double tol,
-                       const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
-{
-    const long n = field_n(c), total = n * M;
-    const size_t fb = field_bytes(c, WDR_F64) * M;
-    Work rw(c, fb), pw(c, fb), ww(c, fb), qw(c, fb), scal(c, sizeof(double2) * 8 * M),
-        red(c, sizeof(double) * red_scratch(M));
-    DevFlags alive(c, M), flag(c, M);
-    if (!rw.ok() || !pw.ok() || !ww.ok() || !qw.ok() || !scal.ok() || !red.ok() || !alive.w.ok() || !flag.w.ok())
-        return WDR_ENOMEM;
-    double2 *r = rw.as<double2>(), *p = pw.as<double2>(), *w = ww.as<double2>(), *q = qw.as<double2>();
-    double2 *sc = scal.as<double2>();
-    const auto &g = c->g;
-    const Sys all = all_sys(c, M);
-    launch_zero<double>(x, total, s);
-    launch_convert<double, double>(all, b, r, s);
-    launch_convert<double, double>(all, b, p, s);
-    launch_norm2<double>(all, b, red.as<double>(), sc, 8, s);
-    std::vector<double> bn2, rr;
-    read_x(sc, M, 8, bn2, s);
-    st.assign(M, Stats());
-    std::vector<int> its(M, 0);
-    for (int m = 0; m < M; ++m) alive.h[m] = bn2[m] > 0;
-    alive.upload(s);
-    std::vector<double> rn2 = bn2;
-    int it = 0;
-    while (alive.any() && it < sp.max_iter) {
-        const Sys sa{M, alive.d(), n};
-        // w = D^+ p, q = D w
-        launch_dslash<double>(g, sa, U.u64, HOPS_ALL, -1, 1, p, p, w, kappa, 0, g.nblk, s);
-        apply_D64(c, sa, U, kappa, w, q, s);
-        launch_norm2<double>(sa, w, red.as<double>(), sc + 1, 8, s);
-        k_cg_alpha<<<nb64(M), 64, 0, s>>>(M, alive.d(), sc);
-        k_cg_update<double><<<nb256(total), 256, 0, s>>>(alive.d(), n, total, sc, x, w, r, q);
-        launch_norm2<double>(sa, r, red.as<double>(), sc + 3, 8, s);
-        k_cg_beta<<<nb64(M), 64, 0, s>>>(M, alive.d(), sc);
-        k_cg_p<double><<<nb256(total), 256, 0, s>>>(alive.d(), n, total, sc, r, p);
-        ++it;
-        for (int m = 0; m < M; ++m)
-            if (alive.h[m]) ++its[m];
-        if (it % 4 != 0 && it < sp.max_iter) continue;
-        read_x(sc, M, 8, rr, s);
-        bool any_flag = false;
-        for (int m = 0; m < M; ++m) {
-            flag.h[m] = alive.h[m] && (!std::isfinite(rr[m]) || rr[m] <= tol * tol * bn2[m]);
-            any_flag = any_flag || flag.h[m];
-        }
-        if (!any_flag) continue;
-        // confirm with the true residual; restart the others from it
-        flag.upload(s);
-        const Sys sf{M, flag.d(), n};
-        apply_D64(c, sf, U, kappa, x, q, s);
-        launch_sub(sf, b, q, w, s);
-        launch_norm2<double>(sf, w, red.as<double>(), sc + 5, 8, s);
-        std::vector<double> tr;
-        read_x(sc + 5, M, 8, tr, s);
-        for (int m = 0; m < M; ++m) {
-            if (!flag.h[m]) continue;
-            rn2[m] = tr[m];
-            if (!std::isfinite(tr[m]) || tr[m] <= tol * tol * bn2[m]) {
-                alive.h[m] = 0;
-                flag.h[m] = 0;
-            }
-        }
-        flag.upload(s);
-        launch_copy_flagged(all, flag.d(), w, r, s);
-        launch_copy_flagged(all, flag.d(), w, p, s);
-        k_cg_restart<<<nb64(M), 64, 0, s>>>(M, flag.d(), sc);
-        alive.upload(s);
-    }
-    // final true residuals
-    apply_D64(c, all, U, kappa, x, q, s);
-    launch_sub(all, b, q, r, s);
-    launch_norm2<double>(all, r, red.as<double>(), sc + 5, 8, s);
-    read_x(sc + 5, M, 8, rn2, s);
-    bool ok = true;
-    for (int m = 0; m < M; ++m) {
-        st[m].iters = its[m];
-        st[m].total = its[m];
-        st[m].rel = bn2[m] > 0 ? std::sqrt(rn2[m] / bn2[m]) : 0.0;
-        st[m].converged = st[m].rel <= tol;
-        ok = ok && st[m].converged;
-    }
-    WDR_HIP(hipGetLastError());
-    if (!ok) {
-        const Stats sm = summarize(st);
-        set_error("CGNE stopped at " + std::to_string(sm.iters) + " iterations, relative residual " +
-                  std::to_string(sm.rel));
-        return WDR_ENOCONV;
-    }
-    return WDR_OK;
-}
-
-// ------------------------------------------------------------ mixed CGNE
-
-// CG on the normal equations D D^+ y = b (x = D^+ y) with FP32 vectors and
-// stencil, and reliable updates in FP64 (the scheme of Sleijpen and van der
-// Vorst): the FP32 correction e = D^+ (y - y_last) is folded into the FP64
-// x, and the iterated residual replaced by the FP64 true residual b - D x,
-// whenever the iterated residual has fallen by RELIABLE_DELTA below its
-// largest value since the last update; the search direction is kept, so the
-// iteration continues.  Convergence is decided on the FP64 true residual.
+// Even-odd reduction: with D = [[1, -k H_eo], [-k H_oe, 1]] on (even, odd)
+// sites, D x = b becomes
+//     Dhat x_e = bh_e,  Dhat = 1 - k^2 H_eo H_oe,  bh_e = b_e + k H_eo b_o,
+//     x_o = b_o + k H_oe x_e,
+// and then b - D x is bh_e - Dhat x_e on even sites and exactly 0 on odd
+// ones, so the solver's FP64 residual is that of the full system.  CG runs on
+// Dhat Dhat^+ y = bh (x_e = Dhat^+ y; Dhat^+ = g5 Dhat g5) with vectors and
+// stencil in T, and reliable updates in FP64 (the scheme of Sleijpen and van
+// der Vorst): whenever the iterated residual has fallen by RELIABLE_DELTA
+// below its largest value since the last update, the correction e = Dhat^+
+// (y - y_last) is folded into the FP64 x_e and the iterated residual replaced
+// by the FP64 true residual, keeping the search direction.  Vectors keep the
+// full-field layout with odd sites zero.
 constexpr double RELIABLE_DELTA = 0.1;
 constexpr int UPDATE_EVERY = 4;  // steps between update / poll points
 
-static wdr_status cgne_mixed(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
-                             double tol, const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
+template <typename T> Links<T> links_of(const GaugeTab &U);
+template <> Links<double> links_of<double>(const GaugeTab &U) { return U.u64; }
+template <> Links<float> links_of<float>(const GaugeTab &U) { return U.u32; }
+
+// out_e = (Dhat in)_e, or (Dhat^+ in)_e with dag; tmp receives -k H_oe in_e
+// on odd sites; odd sites of out are not written
+template <typename T>
+static void apply_dhat(const Geo &g, const Sys &sy, Links<T> U, T kappa, int dag, const T2<T> *in, T2<T> *tmp,
+                       T2<T> *out, hipStream_t s)
+{
+    Links<T> Un = U;
+    Un.kneg = 1;
+    launch_dslash<T>(g, sy, U, HOPS_ALL, 1, dag, in, nullptr, tmp, kappa, 0, g.nblk, s);
+    launch_dslash<T>(g, sy, Un, HOPS_ALL, 0, dag, tmp, in, out, -kappa, 0, g.nblk, s);
+}
+
+template <typename T>
+static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp, double tol,
+                          const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
     const long n = field_n(c), total = n * M;
-    const size_t fb = field_bytes(c, WDR_F64) * M, fb32 = field_bytes(c, WDR_F32) * M;
-    Work r64w(c, fb), t64w(c, fb), rw(c, fb32), pw(c, fb32), ww(c, fb32), qw(c, fb32), ew(c, fb32),
-        scal(c, sizeof(double2) * 8 * M), red(c, sizeof(double) * red_scratch(M)),
-        ctl(c, 2 * sizeof(double) * M + 3 * sizeof(int32_t) * M);
+    const int prec = sizeof(T) == 8 ? WDR_F64 : WDR_F32;
+    const size_t fb = field_bytes(c, WDR_F64) * M, fbT = field_bytes(c, prec) * M;
+    Work bhw(c, fb), r64w(c, fb), t64w(c, fb), o64w(c, fb), rw(c, fbT), pw(c, fbT), ww(c, fbT), qw(c, fbT),
+        ew(c, fbT), tw(c, fbT), scal(c, sizeof(double2) * 8 * M), red(c, sizeof(double) * red_scratch(M)),
+        ctl(c, 2 * sizeof(double) * M + 3 * sizeof(int32_t) * M), lw(c, sizeof(int32_t) * M);
     FlagPoll poll(c, M);
-    if (!r64w.ok() || !t64w.ok() || !rw.ok() || !pw.ok() || !ww.ok() || !qw.ok() || !ew.ok() || !scal.ok() ||
-        !red.ok() || !ctl.ok() || !poll.ok)
+    if (!bhw.ok() || !r64w.ok() || !t64w.ok() || !o64w.ok() || !rw.ok() || !pw.ok() || !ww.ok() || !qw.ok() ||
+        !ew.ok() || !tw.ok() || !scal.ok() || !red.ok() || !ctl.ok() || !lw.ok() || !poll.ok)
         return WDR_ENOMEM;
-    double2 *r64 = r64w.as<double2>(), *t64 = t64w.as<double2>();
-    float2 *r = rw.as<float2>(), *p = pw.as<float2>(), *w = ww.as<float2>(), *q = qw.as<float2>(), *e = ew.as<float2>();
+    double2 *bh = bhw.as<double2>(), *r64 = r64w.as<double2>(), *t64 = t64w.as<double2>(), *o64 = o64w.as<double2>();
+    T2<T> *r = rw.as<T2<T>>(), *p = pw.as<T2<T>>(), *w = ww.as<T2<T>>(), *q = qw.as<T2<T>>(), *e = ew.as<T2<T>>(),
+          *t = tw.as<T2<T>>();
     double2 *sc = scal.as<double2>();
     double *bn2 = ctl.as<double>(), *rmax = bn2 + M;
     int32_t *alive = reinterpret_cast<int32_t *>(rmax + M), *upd = alive + M, *its = upd + M;
     const auto &g = c->g;
-    const Sys all = all_sys(c, M), sa{M, alive, n}, su{M, upd, n};
+    const Links<T> UT = links_of<T>(U);
+    Links<double> U64n = U.u64;
+    U64n.kneg = 1;
+    const T kT = (T)kappa;
+    const Sys all = all_sys(c, M);
+    Sys sa{M, alive, n}, su{M, upd, n};
+    std::vector<int32_t> live;
+    int launch_m = M;
     const unsigned nbm = nb64(M);
-    const float k32 = (float)kappa;
+
+    // bh = [b_e + k H_eo b_o; 0]; odd parts of every iterated field stay 0
     launch_zero<double>(x, total, s);
+    launch_zero<double>(bh, total, s);
+    launch_zero<double>(t64, total, s);
+    launch_dslash<double>(g, all, U64n, HOPS_ALL, 0, 0, b, b, bh, -kappa, 0, g.nblk, s);
     launch_norm2<double>(all, b, red.as<double>(), sc + 5, 8, s);
-    k_cgm_init<<<nbm, 64, 0, s>>>(M, sc, bn2, rmax, alive, upd, its);
-    launch_convert<float, double>(all, b, r, s);
-    launch_convert<float, float>(all, r, p, s);
-    launch_zero<float>(e, total, s);
-    launch_norm2<float>(sa, r, red.as<double>(), sc, 8, s);
+    k_cgm_init<<<nbm, 64, 0, s>>>(M, sc, bn2, rmax, alive, upd, its);  // |b|^2 of the full system
+    launch_convert<T, double>(all, bh, r, s);
+    launch_convert<T, T>(all, r, p, s);
+    launch_zero<T>(e, total, s);
+    launch_zero<T>(w, total, s);
+    launch_zero<T>(q, total, s);
+    launch_norm2<T>(sa, r, red.as<double>(), sc, 8, s);
+    k_cgm_rmax<<<nbm, 64, 0, s>>>(M, sc, rmax);
     for (int j = 0;; ++j) {
-        // one FP32 step: w = D^+ p, q = D w, e += alpha w, r -= alpha q, p = r + beta p
-        launch_dslash<float>(g, sa, U.u32, HOPS_ALL, -1, 1, p, p, w, k32, 0, g.nblk, s);
-        launch_dslash<float>(g, sa, U.u32, HOPS_ALL, -1, 0, w, w, q, k32, 0, g.nblk, s);
-        launch_norm2<float>(sa, w, red.as<double>(), sc + 1, 8, s);
+        // one step: w = Dhat^+ p, q = Dhat w, e += alpha w, r -= alpha q, p = r + beta p
+        apply_dhat<T>(g, sa, UT, kT, 1, p, t, w, s);
+        apply_dhat<T>(g, sa, UT, kT, 0, w, t, q, s);
+        launch_norm2<T>(sa, w, red.as<double>(), sc + 1, 8, s);
+        const long tl = n * sa.launch_m();
         k_cg_alpha<<<nbm, 64, 0, s>>>(M, alive, sc);
-        k_cg_update<float><<<nb256(total), 256, 0, s>>>(alive, n, total, sc, e, w, r, q);
-        launch_norm2<float>(sa, r, red.as<double>(), sc + 3, 8, s);
+        k_cg_update<T><<<nb256(tl), 256, 0, s>>>(alive, sa.list, n, tl, sc, e, w, r, q);
+        launch_norm2<T>(sa, r, red.as<double>(), sc + 3, 8, s);
         k_cg_beta<<<nbm, 64, 0, s>>>(M, alive, sc);
-        k_cg_p<float><<<nb256(total), 256, 0, s>>>(alive, n, total, sc, r, p);
+        k_cg_p<T><<<nb256(tl), 256, 0, s>>>(alive, sa.list, n, tl, sc, r, p);
         k_cgm_step<<<nbm, 64, 0, s>>>(M, sc, RELIABLE_DELTA * RELIABLE_DELTA, sp.max_iter, alive, rmax, upd, its);
         if (j % UPDATE_EVERY != UPDATE_EVERY - 1) continue;
-        // reliable update of the flagged systems
-        launch_add_to64<float>(su, e, x, s);
-        apply_D64(c, su, U, kappa, x, t64, s);
-        launch_sub(su, b, t64, r64, s);
+        // reliable update of the flagged systems: x_e += e, r = bh - Dhat x_e in FP64
+        launch_add_to64<T>(su, e, x, s);
+        apply_dhat<double>(g, su, U.u64, kappa, 0, x, o64, t64, s);
+        launch_sub(su, bh, t64, r64, s);
         launch_norm2<double>(su, r64, red.as<double>(), sc + 5, 8, s);
         k_cgm_update<<<nbm, 64, 0, s>>>(M, sc, bn2, tol * tol, sp.max_iter, its, alive, upd, rmax);
-        k_cgm_refresh<<<nb256(total), 256, 0, s>>>(n, total, upd, alive, r64, r, e);
+        k_cgm_refresh<T><<<nb256(tl), 256, 0, s>>>(su.list, n, tl, upd, r64, r, e);
         k_cgm_clear<<<nbm, 64, 0, s>>>(M, upd);
-        // poll one update point behind
+        // poll one update point behind; compact the launches to the live systems
         const int pt = j / UPDATE_EVERY;
         poll.post(alive, pt & 1, s);
-        if (pt > 0 && poll.none((pt - 1) & 1)) break;
+        if (pt > 0) {
+            if (poll.none((pt - 1) & 1)) break;
+            const int32_t *fl = poll.slot((pt - 1) & 1);
+            int cnt = 0;
+            for (int m = 0; m < M; ++m) cnt += fl[m] != 0;
+            if (2 * cnt <= launch_m) {
+                live.clear();
+                for (int m = 0; m < M; ++m)
+                    if (fl[m]) live.push_back(m);
+                // ordered after every launch already queued with the old list
+                WDR_HIP(hipMemcpyAsync(lw.as<void>(), live.data(), live.size() * sizeof(int32_t),
+                                       hipMemcpyHostToDevice, s));
+                launch_m = cnt;
+                sa.list = su.list = lw.as<int32_t>();
+                sa.count = su.count = cnt;
+            }
+        }
     }
+    // x_o = b_o + k H_oe x_e
+    launch_zero<double>(t64, total, s);
+    launch_dslash<double>(g, all, U64n, HOPS_ALL, 1, 0, x, b, t64, -kappa, 0, g.nblk, s);
+    launch_add_to64<double>(all, t64, x, s);
+
     std::vector<double> hbn2(M), rn2;
     std::vector<int32_t> hits(M);
     WDR_HIP(hipMemcpyAsync(hbn2.data(), bn2, sizeof(double) * M, hipMemcpyDeviceToHost, s));
@@ -662,7 +620,7 @@ static wdr_status cgne_mixed(wdr_ctx *c, int M, const GaugeTab &U, double kappa,
     WDR_HIP(hipGetLastError());
     if (!ok) {
         const Stats sm = summarize(st);
-        set_error("mixed CGNE stopped at " + std::to_string(sm.iters) + " iterations, relative residual " +
+        set_error("CGNE stopped at " + std::to_string(sm.iters) + " iterations, relative residual " +
                   std::to_string(sm.rel));
         return WDR_ENOCONV;
     }
@@ -673,8 +631,8 @@ wdr_status solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr
                    const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
     if (sp.solver == WDR_SOLVER_CGNE)
-        return sp.inner == WDR_F64 ? cgne(c, M, U, kappa, sp, tol, b, x, st, s)
-                                   : cgne_mixed(c, M, U, kappa, sp, tol, b, x, st, s);
+        return sp.inner == WDR_F64 ? cgne_eo<double>(c, M, U, kappa, sp, tol, b, x, st, s)
+                                   : cgne_eo<float>(c, M, U, kappa, sp, tol, b, x, st, s);
     return fgcr(c, M, U, kappa, sp, tol, b, x, st, s);
 }
 

@@ -68,6 +68,18 @@ template <> struct C2<float> { typedef float2 type; };
 // such data is done in FP32
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 
+// system of launch index j (a compacted launch maps its j-th system through list)
+__device__ __forceinline__ int sys_at(const int32_t *list, int j) { return list ? list[j] : j; }
+// element index in the whole batch of launch element k of an elementwise
+// launch over n-element fields (a compacted launch covers the systems of list
+// back to back); m receives the system
+__device__ __forceinline__ long batch_index(const int32_t *list, long n, long k, int &m)
+{
+    const int j = (int)(k / n);
+    m = sys_at(list, j);
+    return k + (long)(m - j) * n;
+}
+
 template <typename T> struct Field {  // one spinor field in the internal layout
     typename C2<T>::type *p;
 };
