@@ -58,8 +58,12 @@ typedef enum { WDR_NOISE_Z2 = 0, WDR_NOISE_GAUSS = 1 } wdr_noise_kind;
 /* which determinant ratio is estimated (paper Sec. 3 eq. 4step, Sec. 4):
  * FULL   det(D'^+ D') / det(D^+ D)
  * SCHUR  det(Dhat'^+ Dhat') / det(Dhat^+ Dhat), Dhat = 1 - D_bb^-1 D_bw D_ww^-1 D_wb
- * BLOCKS det(D_b'^+ D_b') / det(D_b^+ D_b) for every block b separately */
-typedef enum { WDR_OP_FULL = 0, WDR_OP_SCHUR = 1, WDR_OP_BLOCKS = 2 } wdr_op;
+ * BLOCKS det(D_b'^+ D_b') / det(D_b^+ D_b) for every block b separately
+ * DD     the factorisation of eq. ddfactor: every BLOCKS ratio and the SCHUR
+ *        ratio of one proposal in one call (one path; the two parts run
+ *        concurrently); samples per (step, noise): nblocks block samples,
+ *        then the Schur sample; the log ratio is their sum */
+typedef enum { WDR_OP_FULL = 0, WDR_OP_SCHUR = 1, WDR_OP_BLOCKS = 2, WDR_OP_DD = 3 } wdr_op;
 
 /* global solver: flexible GCR preconditioned by the Schwarz alternating
  * procedure, or CG on the normal equations D D^+ y = b, x = D^+ y */
@@ -235,7 +239,8 @@ wdr_status wdr_apply_schur(wdr_ctx *ctx, const wdr_gauge *U, double kappa, const
  * eta_{i,k} from wdr_noise (black sites for SCHUR), the sample
  *   s_{i,k} = -eta^+ (M_i^+ M_i - 1) eta,  M_i = X(U_{i+1})^-1 X(U_i),
  * evaluated to second order in the solver residual.  host_samples receives
- * n_steps*n_noise values ([i][k]), times nblocks for BLOCKS ([i][k][block]);
+ * n_steps*n_noise values ([i][k]), times nblocks for BLOCKS ([i][k][block])
+ * and nblocks + 1 for DD ([i][k][block], then the Schur sample);
  * *host_log_ratio = sum_i log((1/n_noise) sum_k exp(s_{i,k})) (for BLOCKS
  * the sum over blocks).  Either output pointer may be NULL. */
 wdr_status wdr_logdet_ratio(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *Up, double kappa,

@@ -396,7 +396,7 @@ wdr_status wdr_apply_schur(wdr_ctx *c, const wdr_gauge *U, double kappa, const w
 static wdr_status check_est(const wdr_ctx *c, const wdr_est_params *p)
 {
     if (!p || p->n_steps < 1 || p->n_noise < 1 || p->max_batch < 0 ||
-        (p->op != WDR_OP_FULL && p->op != WDR_OP_SCHUR && p->op != WDR_OP_BLOCKS) ||
+        (p->op != WDR_OP_FULL && p->op != WDR_OP_SCHUR && p->op != WDR_OP_BLOCKS && p->op != WDR_OP_DD) ||
         (p->noise != WDR_NOISE_Z2 && p->noise != WDR_NOISE_GAUSS)) {
         set_error("invalid estimator parameters");
         return WDR_EINVAL;
@@ -456,7 +456,10 @@ wdr_status wdr_logdet_ratio_batch(int32_t n, const wdr_proposal *props, const wd
     // output offsets of every proposal
     const int per = p->n_steps * p->n_noise;
     std::vector<size_t> off(n + 1, 0);
-    for (int j = 0; j < n; ++j) off[j + 1] = off[j] + (size_t)per * (p->op == WDR_OP_BLOCKS ? props[j].ctx->g.nblk : 1);
+    for (int j = 0; j < n; ++j) {
+        const int nblk = props[j].ctx->g.nblk;
+        off[j + 1] = off[j] + (size_t)per * (p->op == WDR_OP_BLOCKS ? nblk : p->op == WDR_OP_DD ? nblk + 1 : 1);
+    }
     const size_t G = ctxs.size();
     std::vector<std::vector<double>> gs(G), gl(G);
     std::vector<Stats> gst(G);

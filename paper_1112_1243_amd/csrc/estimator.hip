@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <cmath>
 #include <memory>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "runtime.h"
@@ -55,28 +57,45 @@ constexpr double CHUNK_BYTES = 48e9;
 
 }  // namespace
 
-wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wdr_est_params &p,
-                        double *host_samples, double *host_log_ratios, Stats &st, hipStream_t s)
+// the path U_0 .. U_N of every proposal (workspace of c)
+struct Path {
+    std::vector<std::unique_ptr<TmpGauge>> pts;
+    int N = 0, su3 = 1;
+    bool has16 = false;
+    TmpGauge &at(int prop, int i) const { return *pts[(size_t)prop * (N + 1) + i]; }
+};
+
+static wdr_status build_path(wdr_ctx *c, const std::vector<Proposal> &props, const wdr_est_params &p, Path &path,
+                             hipStream_t s)
+{
+    path.N = p.n_steps;
+    path.su3 = 1;
+    for (const Proposal &q : props) path.su3 = path.su3 && q.U->su3 && q.Up->su3;  // the geodesic stays in SU(3)
+    path.has16 = path.su3 && p.sp.inner == WDR_F16;
+    for (const Proposal &q : props)
+        for (int i = 0; i <= path.N; ++i) {
+            path.pts.emplace_back(new TmpGauge(c, path.has16));
+            if (!path.pts.back()->ok()) return WDR_ENOMEM;
+            make_path_gauge(c, q.U, q.Up, i, path.N, *path.pts.back(), s);
+        }
+    return WDR_OK;
+}
+
+// the samples of one ratio (op FULL, SCHUR or BLOCKS) for every (proposal,
+// step, noise), in batched chunks; samples[m * nout + b], nout = nblk for
+// BLOCKS, else 1.  Work space comes from c; the path may belong to another
+// context of the same geometry.
+static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposal> &props, int op,
+                         const wdr_est_params &p, std::vector<double> &samples, Stats &st, hipStream_t s)
 {
     const auto &g = c->g;
     const long n = field_n(c);
     const wdr_solver_params &sp = p.sp;
     const int P = (int)props.size(), N = p.n_steps, K = p.n_noise, per_prop = N * K, total = P * per_prop;
-    const int nout = p.op == WDR_OP_BLOCKS ? g.nblk : 1;
-
-    // the path U_0 .. U_N of every proposal
-    std::vector<std::unique_ptr<TmpGauge>> path;
-    int su3 = 1;
-    for (const Proposal &q : props) su3 = su3 && q.U->su3 && q.Up->su3;  // the geodesic stays in SU(3)
-    const bool want16 = su3 && sp.inner == WDR_F16;
-    for (const Proposal &q : props) {
-        for (int i = 0; i <= N; ++i) {
-            path.emplace_back(new TmpGauge(c, want16));
-            if (!path.back()->ok()) return WDR_ENOMEM;
-            make_path_gauge(c, q.U, q.Up, i, N, *path.back(), s);
-        }
-    }
-    auto point = [&](int prop, int i) -> TmpGauge & { return *path[(size_t)prop * (N + 1) + i]; };
+    const int nout = op == WDR_OP_BLOCKS ? g.nblk : 1;
+    const int su3 = path.su3;
+    const bool want16 = path.has16;
+    auto point = [&](int prop, int i) -> TmpGauge & { return path.at(prop, i); };
 
     // chunk size: sample fields plus solver work space per system
     const size_t fb = field_bytes(c, WDR_F64);
@@ -84,7 +103,7 @@ wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wd
     int Mmax = std::max(1, std::min(total, (int)(CHUNK_BYTES / ((double)per_system * fb))));
     if (p.max_batch > 0) Mmax = std::min(Mmax, p.max_batch);
 
-    std::vector<double> samples((size_t)total * nout, 0.0);
+    samples.assign((size_t)total * nout, 0.0);
     std::vector<double> per((size_t)g.nblk * Mmax);
     int b0, bn;
     colour_slots(c, 0, b0, bn);
@@ -149,8 +168,8 @@ wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wd
         const double kappa = kappa0;
 
         launch_noise(g, all, p.noise, p.seed, sw.as<uint64_t>(), idx.as<int32_t>(), idx.as<int32_t>() + M,
-                     p.op == WDR_OP_SCHUR, E, s);
-        if (p.op == WDR_OP_FULL) {
+                     op == WDR_OP_SCHUR, E, s);
+        if (op == WDR_OP_FULL) {
             apply_D64(c, all, X, kappa, E, Y, s);                                          // y = D eta
             if (!take(solve64(c, M, Xp, kappa, sp, sp.tol, Y, Z, s1, s), true)) return hard;   // D' z = y
             launch_g5<double>(g, all, Z, Tm, s);                                           // D' v = g5 z
@@ -158,7 +177,7 @@ wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wd
             launch_g5<double>(g, all, W, W, s);                                            // w = g5 v
             apply_D64(c, all, Xp, kappa, Z, Tm, s);
             launch_sub(all, Y, Tm, R, s);                                                  // r = y - D' z
-        } else if (p.op == WDR_OP_BLOCKS) {
+        } else if (op == WDR_OP_BLOCKS) {
             launch_dslash<double>(g, all, X.u64, HOPS_IN, -1, 0, E, E, Y, kappa, 0, g.nblk, s);  // y = D_blk eta
             if (!take(block_solve64(c, M, Xp, kappa, 2, sp, sp.block_tol, Y, Z, s1, s), true)) return hard;
             launch_g5<double>(g, all, Z, Tm, s);
@@ -189,7 +208,7 @@ wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wd
         for (int j = 0; j < M; ++j) {
             const double *ps = per.data() + (size_t)j * g.nblk;
             double *dst = samples.data() + (size_t)(m0 + j) * nout;
-            if (p.op == WDR_OP_BLOCKS) {
+            if (op == WDR_OP_BLOCKS) {
                 for (int b = 0; b < g.nblk; ++b) dst[b] = ps[c->slot_of_block[b]];
             } else {
                 double sum = 0;  // fixed order over slots
@@ -199,9 +218,86 @@ wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wd
         }
     }
     st = summarize(all_stats);
+    return status;
+}
+
+// a second context of the same geometry with its own workspace pool, solver
+// read-back buffers and stream (for running two estimates concurrently)
+static wdr_ctx *twin_of(wdr_ctx *c)
+{
+    if (!c->twin) {
+        wdr_ctx *t = new wdr_ctx();
+        t->device = c->device;
+        t->geom = c->geom;
+        t->g = c->g;  // shares the parent's geometry tables (tables = NULL: not owned)
+        t->slot_of_block = c->slot_of_block;
+        c->twin = t;
+    }
+    return c->twin;
+}
+
+wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wdr_est_params &p,
+                        double *host_samples, double *host_log_ratios, Stats &st, hipStream_t s)
+{
+    const auto &g = c->g;
+    const int P = (int)props.size(), N = p.n_steps, K = p.n_noise, per_prop = N * K, total = P * per_prop;
+    Path path;
+    wdr_status e = build_path(c, props, p, path, s);
+    if (e != WDR_OK) return e;
+    std::vector<double> samples;
+    int nout;
+    wdr_status status = WDR_OK;
+    if (p.op != WDR_OP_DD) {
+        nout = p.op == WDR_OP_BLOCKS ? g.nblk : 1;
+        status = run_op(c, path, props, p.op, p, samples, st, s);
+        if (status != WDR_OK && status != WDR_ENOCONV) return status;
+    } else {
+        // the block ratios here and the Schur ratio on the twin context's
+        // stream, concurrently; both read the one path
+        nout = g.nblk + 1;
+        wdr_ctx *t = twin_of(c);
+        hipEvent_t fork;
+        WDR_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        WDR_HIP(hipEventRecord(fork, s));
+        if (!t->aux && hipStreamCreateWithFlags(&t->aux, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipEventDestroy(fork);
+            set_error("stream creation failed");
+            return WDR_EDEVICE;
+        }
+        (void)hipStreamWaitEvent(t->aux, fork, 0);
+        std::vector<double> sb, ss;
+        Stats stb, sts;
+        wdr_status es = WDR_OK;
+        std::string msg;
+        std::thread th([&] {
+            (void)hipSetDevice(t->device);
+            es = run_op(t, path, props, WDR_OP_SCHUR, p, ss, sts, t->aux);
+            (void)hipStreamSynchronize(t->aux);
+            if (es != WDR_OK) msg = wdr_last_error();
+        });
+        const wdr_status eb = run_op(c, path, props, WDR_OP_BLOCKS, p, sb, stb, s);
+        th.join();
+        (void)hipEventDestroy(fork);
+        for (wdr_status x : {eb, es}) {
+            if (x != WDR_OK && x != WDR_ENOCONV) {
+                if (x == es) set_error(msg);
+                return x;
+            }
+            if (x == WDR_ENOCONV) status = x;
+        }
+        if (es == WDR_ENOCONV) set_error(msg);
+        st = summarize({stb, sts});
+        samples.assign((size_t)total * nout, 0.0);
+        for (int m = 0; m < total; ++m) {
+            std::copy(sb.begin() + (size_t)m * g.nblk, sb.begin() + (size_t)(m + 1) * g.nblk,
+                      samples.begin() + (size_t)m * nout);
+            samples[(size_t)m * nout + g.nblk] = ss[m];
+        }
+    }
     if (host_samples) std::copy(samples.begin(), samples.end(), host_samples);
     if (host_log_ratios) {
-        // per proposal: sum_i log( (1/K) sum_k exp(s_ik) ), summed over blocks for BLOCKS
+        // per proposal: sum_i log( (1/K) sum_k exp(s_ik) ), summed over the
+        // separate ratios (blocks, and the Schur complement for DD)
         for (int q = 0; q < P; ++q) {
             const double *sq = samples.data() + (size_t)q * per_prop * nout;
             double tot = 0;

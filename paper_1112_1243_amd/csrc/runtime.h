@@ -26,6 +26,10 @@ struct wdr_ctx {
     // stream of this context's group in a batch over several contexts
     // (created on first use, default priority)
     hipStream_t aux = nullptr;
+    // a context of the same geometry with its own pool, read-back buffers and
+    // stream, for the concurrent half of a DD estimate (created on first use;
+    // shares this context's geometry tables)
+    wdr_ctx *twin = nullptr;
 };
 
 struct wdr_gauge {

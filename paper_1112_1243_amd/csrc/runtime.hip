@@ -316,6 +316,7 @@ wdr_status wdr_ctx_destroy(wdr_ctx *c)
     if (!c) return WDR_OK;
     hipSetDevice(c->device);
     hipDeviceSynchronize();
+    if (c->twin) wdr_ctx_destroy(c->twin);  // tables NULL: the twin frees only its own pool
     for (void *p : c->owned) (void)hipFree(p);
     if (c->tables) (void)hipFree(c->tables);
     if (c->poll_host) (void)hipHostFree(c->poll_host);

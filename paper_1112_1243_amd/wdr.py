@@ -21,7 +21,7 @@ LIB_PATH = os.environ.get("WDR_LIB", os.path.join(_HERE, "libwdr.so"))
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
 F64, F32, F16 = 0, 1, 2
 NOISE_Z2, NOISE_GAUSS = 0, 1
-OP_FULL, OP_SCHUR, OP_BLOCKS = 0, 1, 2
+OP_FULL, OP_SCHUR, OP_BLOCKS, OP_DD = 0, 1, 2, 3
 SOLVER_FGCR_SAP, SOLVER_CGNE = 0, 1
 
 
@@ -110,6 +110,12 @@ def lib():
                                              ctypes.POINTER(SolveInfo), P]
         _lib = L
     return _lib
+
+
+def _sample_tail(op, nblocks):
+    """Trailing sample dimensions: one per block for BLOCKS, blocks then the
+    Schur complement for DD."""
+    return (nblocks,) if op == OP_BLOCKS else (nblocks + 1,) if op == OP_DD else ()
 
 
 def _check(status: int, allow=(OK,)):
@@ -302,11 +308,12 @@ class Context:
 
     def logdet_ratio(self, U: Gauge, Up: Gauge, kappa, op, n_steps, n_noise, noise, seed, params: SolverParams,
                      max_batch: int = 0):
-        """Returns (samples [n_steps, n_noise] (x nblocks for BLOCKS), log Rhat, info)."""
+        """Returns (samples [n_steps, n_noise] (x nblocks for BLOCKS, x nblocks + 1
+        for DD), log Rhat, info)."""
         ep = EstParams()
         ep.op, ep.n_steps, ep.n_noise, ep.noise, ep.seed, ep.sp = op, n_steps, n_noise, noise, seed, params
         ep.max_batch = max_batch
-        shape = (n_steps, n_noise) + ((self.nblocks,) if op == OP_BLOCKS else ())
+        shape = (n_steps, n_noise) + _sample_tail(op, self.nblocks)
         samples = np.zeros(shape, dtype=np.float64)
         lr = ctypes.c_double()
         info = SolveInfo()
@@ -325,7 +332,7 @@ def logdet_ratio_batch(props, op, n_steps, n_noise, noise, params: SolverParams,
     sizes = []
     for j, (ctx, U, Up, kappa, seed) in enumerate(props):
         arr[j].ctx, arr[j].U, arr[j].Up, arr[j].kappa, arr[j].seed = ctx.handle, U.handle, Up.handle, kappa, seed
-        sizes.append((n_steps, n_noise) + ((ctx.nblocks,) if op == OP_BLOCKS else ()))
+        sizes.append((n_steps, n_noise) + _sample_tail(op, ctx.nblocks))
     ep = EstParams()
     ep.op, ep.n_steps, ep.n_noise, ep.noise, ep.seed, ep.sp = op, n_steps, n_noise, noise, 0, params
     ep.max_batch = max_batch

@@ -83,6 +83,26 @@ def test_samples_match_oracle(op, kind, L, B, kappa, scale, rule, N, K, solver):
     ctx.close()
 
 
+def test_dd_equals_blocks_and_schur():
+    """The DD estimate (block ratios and Schur ratio of one proposal in one
+    call, run concurrently on one path) gives the samples of the separate
+    BLOCKS and SCHUR calls with the same key, and their summed log ratio."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 305)
+    Up = _pair(lat, U, 0.5, 306, "active")
+    gU, gUp = ctx.gauge(dev(U)), ctx.gauge(dev(Up))
+    for inner in (wdr.F32, wdr.F16):
+        p = wdr.default_params(inner=inner)
+        sd, lrd, info = ctx.logdet_ratio(gU, gUp, 0.135, wdr.OP_DD, 3, 1, wdr.NOISE_GAUSS, 17, p)
+        sb, lrb, _ = ctx.logdet_ratio(gU, gUp, 0.135, wdr.OP_BLOCKS, 3, 1, wdr.NOISE_GAUSS, 17, p)
+        ss, lrs, _ = ctx.logdet_ratio(gU, gUp, 0.135, wdr.OP_SCHUR, 3, 1, wdr.NOISE_GAUSS, 17, p)
+        say("dd", inner, np.abs(sd[..., :-1] - sb).max(), np.abs(sd[..., -1] - ss).max(), lrd, lrb + lrs)
+        assert sd.shape == (3, 1, ctx.nblocks + 1) and info.converged
+        assert np.abs(sd[..., :-1] - sb).max() < 1e-12 and np.abs(sd[..., -1] - ss).max() < 1e-12
+        assert abs(lrd - (lrb + lrs)) < 1e-10
+    del gU, gUp
+    ctx.close()
+
+
 def test_unchanged_field_gives_zero():
     wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 304)
     gU = ctx.gauge(dev(U))
