@@ -6,9 +6,10 @@ for one proposal U -> U', through the domain-decomposition factorisation
 det D = prod_b det D_b * det Dhat of the paper's Sec. 3):
   8^4 lattice, kappa = 0.135, links exp(i 0.5 H), 16 blocks of 4^4, U'
   redraws the active links of every block; the 16 block ratios (BLOCKS) and
-  the Schur-complement ratio (SCHUR), each over a path of N = 8 factors with
-  one complex Gaussian noise vector per factor; FGCR(16)+SAP(4 cycles, 5 MR)
-  to 1e-10 with FP32 preconditioner and block solves refined in FP64.
+  the Schur-complement ratio (SCHUR) in one DD call, each over a path of
+  N = 8 factors with one complex Gaussian noise vector per factor;
+  FGCR(16)+SAP to 1e-10 with FP32 preconditioner and block solves refined in
+  FP64; Schwarz and block-solve depths chosen by wdr_autotune beforehand.
 
 Prints one JSON line: estimates/s of the mixed-precision form, the plain
 FP64 form on the same GPU, the stencil's HBM roofline fraction at 32^4, and
@@ -380,8 +381,15 @@ def main():
     Up = synth.redraw(U, proposal_mask(ctx, "active"), wl["scale"], wl["seed"])
     gU = ctx.gauge(torch.from_numpy(U).cuda())
     gUp = ctx.gauge(torch.from_numpy(Up).cuda())
-    mixed = wdr.default_params(inner=wdr.F32)
-    fp64 = wdr.default_params(inner=wdr.F64)
+    # schedule autotuning (Schwarz depth, block-solve rounds) on a short
+    # estimate with another noise key, outside the timed region
+    mixed, t_mixed = ctx.autotune(gU, gUp, wl["kappa"], wdr.OP_DD, wl["n_steps"], wl["n_noise"], wdr.NOISE_GAUSS,
+                                  500, wdr.default_params(inner=wdr.F32))
+    fp64, t_fp64 = ctx.autotune(gU, gUp, wl["kappa"], wdr.OP_DD, wl["n_steps"], wl["n_noise"], wdr.NOISE_GAUSS,
+                                500, wdr.default_params(inner=wdr.F64))
+    log("autotuned: mixed SAP(%d,%d) block MR %d; fp64 SAP(%d,%d) block MR %d"
+        % (mixed.sap_cycles, mixed.mr_steps, mixed.block_mr_steps, fp64.sap_cycles, fp64.mr_steps,
+           fp64.block_mr_steps))
 
     for w in range(args.warmup):
         estimate(ctx, wdr, gU, gUp, wl, mixed, 1000 + w)
@@ -449,9 +457,13 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "%s: 8^4 lattice, 16 blocks of 4^4, kappa 0.135, links exp(i 0.5 H), active links "
-                               "redrawn, BLOCKS + SCHUR ratios, N=8 factors x 1 Gaussian noise, FGCR(16)+SAP(4,5) "
-                               "to 1e-10" % wl["name"],
-                   "converged": all_ok, "total_outer_iters": iters, "mean_log_ratio": float(np.mean(lrs))},
+                               "redrawn, BLOCKS + SCHUR ratios (DD), N=8 factors x 1 Gaussian noise, FGCR(16)+SAP "
+                               "(autotuned depth) to 1e-10" % wl["name"],
+                   "converged": all_ok, "total_outer_iters": iters, "mean_log_ratio": float(np.mean(lrs)),
+                   "schedule": {"mixed": {"sap_cycles": mixed.sap_cycles, "mr_steps": mixed.mr_steps,
+                                          "block_mr_steps": mixed.block_mr_steps},
+                                "fp64": {"sap_cycles": fp64.sap_cycles, "mr_steps": fp64.mr_steps,
+                                         "block_mr_steps": fp64.block_mr_steps}}},
         "fp64_estimates_per_s": None if fp64_rate is None else round(fp64_rate, 4),
         "roofline": roof,
         "batched_proposals": batch,

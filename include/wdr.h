@@ -86,6 +86,7 @@ typedef struct {
                             Dirichlet block solves (1e-13) */
     double adj_tol;      /* adjoint solves of the second-order sample (1e-7) */
     wdr_prec inner;      /* precision of SAP / inner iterations */
+    int32_t block_mr_steps; /* MR steps per round of a defect-corrected block solve (16) */
 } wdr_solver_params;
 
 typedef struct {
@@ -124,7 +125,8 @@ const char *wdr_last_error(void);
 const char *wdr_status_str(wdr_status s);
 
 /* Default solver parameters (FGCR(16)+SAP(4 cycles, 5 MR), tol 1e-10,
- * block_tol 1e-13, adj_tol 1e-7, FP32 inner). */
+ * block_tol 1e-13, adj_tol 1e-7, FP32 inner, 16 MR steps per block-solve
+ * round). */
 void wdr_default_solver_params(wdr_solver_params *out);
 
 /* Create a context for one lattice geometry on HIP device `device`.  Builds
@@ -262,6 +264,17 @@ wdr_status wdr_logdet_ratio(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *U
 wdr_status wdr_logdet_ratio_batch(int32_t n, const wdr_proposal *props, const wdr_est_params *p,
                                   double *host_samples, double *host_log_ratios, wdr_solve_info *host_info,
                                   void *stream);
+
+/* Schedule autotuner for wdr_logdet_ratio on this context: times a short
+ * estimate (at most two path factors, the noise key of *p plus one) for a
+ * set of Schwarz depths (cycles x MR steps, FGCR only) and then of block-solve
+ * MR depths (ratios with block solves), and writes the fastest into p->sp.
+ * Every candidate solves to the tolerances of p->sp, so the choice changes
+ * time only.  The result is cached in the context per (ratio, solver, inner
+ * precision, kappa); host_seconds (may be NULL) receives the time of the
+ * chosen candidate. */
+wdr_status wdr_autotune(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *Up, double kappa, wdr_est_params *p,
+                        double *host_seconds, void *stream);
 
 #ifdef __cplusplus
 }

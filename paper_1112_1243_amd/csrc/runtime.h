@@ -2,6 +2,8 @@
 // the solver / estimator drivers.
 #pragma once
 
+#include <map>
+#include <string>
 #include <vector>
 
 #include "ops.h"
@@ -30,6 +32,8 @@ struct wdr_ctx {
     // stream, for the concurrent half of a DD estimate (created on first use;
     // shares this context's geometry tables)
     wdr_ctx *twin = nullptr;
+    // autotuned solver schedules, keyed by (ratio, solver, inner precision, kappa)
+    std::map<std::string, wdr_solver_params> tuned;
 };
 
 struct wdr_gauge {

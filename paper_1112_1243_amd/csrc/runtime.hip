@@ -74,6 +74,10 @@ wdr_status check_params(const wdr_ctx *c, const wdr_solver_params &sp, bool need
         set_error("solver tolerances must be positive and max_iter >= 1");
         return WDR_EINVAL;
     }
+    if (sp.block_mr_steps < 1 || sp.block_mr_steps > 1000) {
+        set_error("block_mr_steps must be in [1, 1000]");
+        return WDR_EINVAL;
+    }
     if (sp.solver != WDR_SOLVER_FGCR_SAP && sp.solver != WDR_SOLVER_CGNE) {
         set_error("unknown solver");
         return WDR_EINVAL;
@@ -138,6 +142,7 @@ void wdr_default_solver_params(wdr_solver_params *out)
     out->block_tol = 1e-13;
     out->adj_tol = 1e-7;
     out->inner = WDR_F32;
+    out->block_mr_steps = 16;
 }
 
 wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)

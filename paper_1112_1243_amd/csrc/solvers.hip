@@ -665,7 +665,7 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
     double *bn = nrm.as<double>(), *rn = bn + (size_t)g.nblk * M;
     launch_slot_norm2(g, all, r, bn, slot0, ns, s);
     k_block_init<<<nbm, 64, 0, s>>>(M, g.nblk, slot0, ns, bn, alive, its, worst);
-    const int nmr = 16;
+    const int nmr = sp.block_mr_steps;
     const Sys sa{M, alive, n};
     std::unique_ptr<H16Work> r16, d16;
     if (sp.inner == WDR_F16) {

@@ -32,7 +32,8 @@ class Geom(ctypes.Structure):
 class SolverParams(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("sap_cycles", ctypes.c_int32), ("mr_steps", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("block_tol", ctypes.c_double), ("adj_tol", ctypes.c_double), ("inner", ctypes.c_int)]
+                ("block_tol", ctypes.c_double), ("adj_tol", ctypes.c_double), ("inner", ctypes.c_int),
+                ("block_mr_steps", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -108,6 +109,7 @@ def lib():
         L.wdr_logdet_ratio.argtypes = [P, P, P, d, ctypes.POINTER(EstParams), P, P, ctypes.POINTER(SolveInfo), P]
         L.wdr_logdet_ratio_batch.argtypes = [i32, ctypes.POINTER(Proposal), ctypes.POINTER(EstParams), P, P,
                                              ctypes.POINTER(SolveInfo), P]
+        L.wdr_autotune.argtypes = [P, P, P, d, ctypes.POINTER(EstParams), ctypes.POINTER(d), P]
         _lib = L
     return _lib
 
@@ -305,6 +307,16 @@ class Context:
         _check(lib().wdr_apply_schur(self.handle, gauge.handle, kappa, ctypes.byref(params),
                                      _dev(psi, (self.V, 4, 3)), ctypes.c_void_p(out.data_ptr()), _stream()))
         return out
+
+    def autotune(self, U: Gauge, Up: Gauge, kappa, op, n_steps, n_noise, noise, seed, params: SolverParams):
+        """Tuned copy of params (Schwarz and block-solve depths) for estimates
+        of this kind on this context, and the time of the chosen schedule."""
+        ep = EstParams()
+        ep.op, ep.n_steps, ep.n_noise, ep.noise, ep.seed, ep.sp = op, n_steps, n_noise, noise, seed, params
+        secs = ctypes.c_double()
+        _check(lib().wdr_autotune(self.handle, U.handle, Up.handle, kappa, ctypes.byref(ep), ctypes.byref(secs),
+                                  _stream()))
+        return ep.sp, secs.value
 
     def logdet_ratio(self, U: Gauge, Up: Gauge, kappa, op, n_steps, n_noise, noise, seed, params: SolverParams,
                      max_batch: int = 0):

@@ -43,10 +43,11 @@ def test_struct_sizes_match_the_header():
 #include <stddef.h>
 #include "wdr.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(wdr_geom), sizeof(wdr_solver_params),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu ", sizeof(wdr_geom), sizeof(wdr_solver_params),
          sizeof(wdr_solve_info), sizeof(wdr_est_params), offsetof(wdr_solver_params, tol),
          offsetof(wdr_est_params, sp), offsetof(wdr_solver_params, inner), offsetof(wdr_est_params, max_batch),
          sizeof(wdr_proposal), offsetof(wdr_proposal, kappa), offsetof(wdr_proposal, seed));
+  printf("%zu\n", offsetof(wdr_solver_params, block_mr_steps));
   return 0;
 }'''
     import tempfile
@@ -59,7 +60,7 @@ int main(void) {
     want = [ctypes.sizeof(wdr.Geom), ctypes.sizeof(wdr.SolverParams), ctypes.sizeof(wdr.SolveInfo),
             ctypes.sizeof(wdr.EstParams), wdr.SolverParams.tol.offset, wdr.EstParams.sp.offset,
             wdr.SolverParams.inner.offset, wdr.EstParams.max_batch.offset, ctypes.sizeof(wdr.Proposal),
-            wdr.Proposal.kappa.offset, wdr.Proposal.seed.offset]
+            wdr.Proposal.kappa.offset, wdr.Proposal.seed.offset, wdr.SolverParams.block_mr_steps.offset]
     assert vals == want
 
 
@@ -67,6 +68,7 @@ def test_default_params_from_library():
     from paper_1112_1243_amd import wdr
     p = wdr.default_params()
     assert p.restart == 16 and p.sap_cycles == 4 and p.mr_steps == 5 and p.tol == 1e-10
+    assert p.block_mr_steps == 16
 
 
 def test_missing_library_raises(monkeypatch):

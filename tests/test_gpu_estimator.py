@@ -103,6 +103,27 @@ def test_dd_equals_blocks_and_schur():
     ctx.close()
 
 
+def test_autotune_keeps_results():
+    """The tuned schedule (Schwarz depth, block-solve rounds) changes time
+    only: samples stay within solver accuracy of the default schedule; the
+    second call returns the cached choice."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 307)
+    Up = _pair(lat, U, 0.5, 308, "active")
+    gU, gUp = ctx.gauge(dev(U)), ctx.gauge(dev(Up))
+    p0 = wdr.default_params()
+    tuned, secs = ctx.autotune(gU, gUp, 0.135, wdr.OP_DD, 4, 1, wdr.NOISE_GAUSS, 21, p0)
+    say("tuned", tuned.sap_cycles, tuned.mr_steps, tuned.block_mr_steps, secs)
+    assert secs > 0 and tuned.sap_cycles >= 1 and tuned.mr_steps >= 1 and tuned.block_mr_steps >= 1
+    again, _ = ctx.autotune(gU, gUp, 0.135, wdr.OP_DD, 4, 1, wdr.NOISE_GAUSS, 21, p0)
+    assert (again.sap_cycles, again.mr_steps, again.block_mr_steps) == \
+        (tuned.sap_cycles, tuned.mr_steps, tuned.block_mr_steps)
+    s0, l0, _ = ctx.logdet_ratio(gU, gUp, 0.135, wdr.OP_DD, 4, 1, wdr.NOISE_GAUSS, 22, p0)
+    s1, l1, info = ctx.logdet_ratio(gU, gUp, 0.135, wdr.OP_DD, 4, 1, wdr.NOISE_GAUSS, 22, tuned)
+    assert info.converged and np.abs(s1 - s0).max() < 1e-8
+    del gU, gUp
+    ctx.close()
+
+
 def test_unchanged_field_gives_zero():
     wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 304)
     gU = ctx.gauge(dev(U))
