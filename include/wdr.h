@@ -87,6 +87,8 @@ typedef struct {
     double adj_tol;      /* adjoint solves of the second-order sample (1e-7) */
     wdr_prec inner;      /* precision of SAP / inner iterations */
     int32_t block_mr_steps; /* MR steps per round of a defect-corrected block solve (16) */
+    int32_t update_every;   /* CGNE steps between FP64 reliable-update / convergence points (4) */
+    int32_t graph;          /* 1: CGNE replays each period of update_every steps as one HIP graph */
 } wdr_solver_params;
 
 typedef struct {

@@ -32,6 +32,8 @@ struct wdr_ctx {
     // stream, for the concurrent half of a DD estimate (created on first use;
     // shares this context's geometry tables)
     wdr_ctx *twin = nullptr;
+    // stream on which solver periods are captured into HIP graphs (created on first use)
+    hipStream_t cap = nullptr;
     // autotuned solver schedules, keyed by (ratio, solver, inner precision, kappa)
     std::map<std::string, wdr_solver_params> tuned;
 };

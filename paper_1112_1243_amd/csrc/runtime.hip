@@ -78,6 +78,10 @@ wdr_status check_params(const wdr_ctx *c, const wdr_solver_params &sp, bool need
         set_error("block_mr_steps must be in [1, 1000]");
         return WDR_EINVAL;
     }
+    if (sp.update_every < 1 || sp.update_every > 64 || (sp.graph != 0 && sp.graph != 1)) {
+        set_error("update_every must be in [1, 64] and graph 0 or 1");
+        return WDR_EINVAL;
+    }
     if (sp.solver != WDR_SOLVER_FGCR_SAP && sp.solver != WDR_SOLVER_CGNE) {
         set_error("unknown solver");
         return WDR_EINVAL;
@@ -143,6 +147,8 @@ void wdr_default_solver_params(wdr_solver_params *out)
     out->adj_tol = 1e-7;
     out->inner = WDR_F32;
     out->block_mr_steps = 16;
+    out->update_every = 4;
+    out->graph = 1;
 }
 
 wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)
@@ -328,6 +334,7 @@ wdr_status wdr_ctx_destroy(wdr_ctx *c)
     for (hipEvent_t e : c->poll_ev)
         if (e) (void)hipEventDestroy(e);
     if (c->aux) (void)hipStreamDestroy(c->aux);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     delete c;
     return WDR_OK;
 }

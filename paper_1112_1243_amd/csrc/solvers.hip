@@ -493,7 +493,48 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
 // by the FP64 true residual, keeping the search direction.  Vectors keep the
 // full-field layout with odd sites zero.
 constexpr double RELIABLE_DELTA = 0.1;
-constexpr int UPDATE_EVERY = 4;  // steps between update / poll points
+
+// An instantiated HIP graph of one solver period.  Capture runs on the
+// context's own stream (the caller's may be the legacy default stream, which
+// cannot be captured) in thread-local mode, so other host threads driving
+// other contexts are unaffected; nothing executes while capturing.
+// Replaced graphs may still be running on the launch stream, so they are kept
+// until the destructor, which first waits for that stream.
+struct PeriodGraph {
+    hipStream_t s;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<std::pair<hipGraph_t, hipGraphExec_t>> done;
+    explicit PeriodGraph(hipStream_t s_) : s(s_) {}
+    void reset()
+    {
+        if (graph || exec) done.emplace_back(graph, exec);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~PeriodGraph()
+    {
+        reset();
+        if (done.empty()) return;
+        (void)hipStreamSynchronize(s);
+        for (auto &d : done) {
+            if (d.second) (void)hipGraphExecDestroy(d.second);
+            if (d.first) (void)hipGraphDestroy(d.first);
+        }
+    }
+    template <typename F> wdr_status capture(wdr_ctx *c, F &&enqueue)
+    {
+        if (!c->cap) WDR_HIP(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+        WDR_HIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+        enqueue(c->cap);
+        const hipError_t le = hipGetLastError();
+        const hipError_t ee = hipStreamEndCapture(c->cap, &graph);
+        WDR_HIP(le);
+        WDR_HIP(ee);
+        WDR_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        return WDR_OK;
+    }
+};
 
 template <typename T> Links<T> links_of(const GaugeTab &U);
 template <> Links<double> links_of<double>(const GaugeTab &U) { return U.u64; }
@@ -526,8 +567,8 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
         !ew.ok() || !tw.ok() || !scal.ok() || !red.ok() || !ctl.ok() || !lw.ok() || !poll.ok)
         return WDR_ENOMEM;
     double2 *bh = bhw.as<double2>(), *r64 = r64w.as<double2>(), *t64 = t64w.as<double2>(), *o64 = o64w.as<double2>();
-    T2<T> *r = rw.as<T2<T>>(), *p = pw.as<T2<T>>(), *w = ww.as<T2<T>>(), *q = qw.as<T2<T>>(), *e = ew.as<T2<T>>(),
-          *t = tw.as<T2<T>>();
+    T2<T> *r = rw.as<T2<T>>(), *p = pw.as<T2<T>>(), *w = ww.as<T2<T>>(), *qv = qw.as<T2<T>>(),
+          *e = ew.as<T2<T>>(), *t = tw.as<T2<T>>();
     double2 *sc = scal.as<double2>();
     double *bn2 = ctl.as<double>(), *rmax = bn2 + M;
     int32_t *alive = reinterpret_cast<int32_t *>(rmax + M), *upd = alive + M, *its = upd + M;
@@ -553,32 +594,50 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     launch_convert<T, T>(all, r, p, s);
     launch_zero<T>(e, total, s);
     launch_zero<T>(w, total, s);
-    launch_zero<T>(q, total, s);
+    launch_zero<T>(qv, total, s);
     launch_norm2<T>(sa, r, red.as<double>(), sc, 8, s);
     k_cgm_rmax<<<nbm, 64, 0, s>>>(M, sc, rmax);
-    for (int j = 0;; ++j) {
-        // one step: w = Dhat^+ p, q = Dhat w, e += alpha w, r -= alpha q, p = r + beta p
-        apply_dhat<T>(g, sa, UT, kT, 1, p, t, w, s);
-        apply_dhat<T>(g, sa, UT, kT, 0, w, t, q, s);
-        launch_norm2<T>(sa, w, red.as<double>(), sc + 1, 8, s);
+    // one period: ue steps, then the reliable update of the flagged systems
+    const int ue = sp.update_every;
+    auto period = [&](hipStream_t q) {
         const long tl = n * sa.launch_m();
-        k_cg_alpha<<<nbm, 64, 0, s>>>(M, alive, sc);
-        k_cg_update<T><<<nb256(tl), 256, 0, s>>>(alive, sa.list, n, tl, sc, e, w, r, q);
-        launch_norm2<T>(sa, r, red.as<double>(), sc + 3, 8, s);
-        k_cg_beta<<<nbm, 64, 0, s>>>(M, alive, sc);
-        k_cg_p<T><<<nb256(tl), 256, 0, s>>>(alive, sa.list, n, tl, sc, r, p);
-        k_cgm_step<<<nbm, 64, 0, s>>>(M, sc, RELIABLE_DELTA * RELIABLE_DELTA, sp.max_iter, alive, rmax, upd, its);
-        if (j % UPDATE_EVERY != UPDATE_EVERY - 1) continue;
-        // reliable update of the flagged systems: x_e += e, r = bh - Dhat x_e in FP64
-        launch_add_to64<T>(su, e, x, s);
-        apply_dhat<double>(g, su, U.u64, kappa, 0, x, o64, t64, s);
-        launch_sub(su, bh, t64, r64, s);
-        launch_norm2<double>(su, r64, red.as<double>(), sc + 5, 8, s);
-        k_cgm_update<<<nbm, 64, 0, s>>>(M, sc, bn2, tol * tol, sp.max_iter, its, alive, upd, rmax);
-        k_cgm_refresh<T><<<nb256(tl), 256, 0, s>>>(su.list, n, tl, upd, r64, r, e);
-        k_cgm_clear<<<nbm, 64, 0, s>>>(M, upd);
-        // poll one update point behind; compact the launches to the live systems
-        const int pt = j / UPDATE_EVERY;
+        for (int i = 0; i < ue; ++i) {
+            // w = Dhat^+ p, q = Dhat w, e += alpha w, r -= alpha q, p = r + beta p
+            apply_dhat<T>(g, sa, UT, kT, 1, p, t, w, q);
+            apply_dhat<T>(g, sa, UT, kT, 0, w, t, qv, q);
+            launch_norm2<T>(sa, w, red.as<double>(), sc + 1, 8, q);
+            k_cg_alpha<<<nbm, 64, 0, q>>>(M, alive, sc);
+            k_cg_update<T><<<nb256(tl), 256, 0, q>>>(alive, sa.list, n, tl, sc, e, w, r, qv);
+            launch_norm2<T>(sa, r, red.as<double>(), sc + 3, 8, q);
+            k_cg_beta<<<nbm, 64, 0, q>>>(M, alive, sc);
+            k_cg_p<T><<<nb256(tl), 256, 0, q>>>(alive, sa.list, n, tl, sc, r, p);
+            k_cgm_step<<<nbm, 64, 0, q>>>(M, sc, RELIABLE_DELTA * RELIABLE_DELTA, sp.max_iter, alive, rmax, upd,
+                                          its);
+        }
+        // x_e += e, r = bh - Dhat x_e in FP64
+        launch_add_to64<T>(su, e, x, q);
+        apply_dhat<double>(g, su, U.u64, kappa, 0, x, o64, t64, q);
+        launch_sub(su, bh, t64, r64, q);
+        launch_norm2<double>(su, r64, red.as<double>(), sc + 5, 8, q);
+        k_cgm_update<<<nbm, 64, 0, q>>>(M, sc, bn2, tol * tol, sp.max_iter, its, alive, upd, rmax);
+        k_cgm_refresh<T><<<nb256(tl), 256, 0, q>>>(su.list, n, tl, upd, r64, r, e);
+        k_cgm_clear<<<nbm, 64, 0, q>>>(M, upd);
+    };
+    // With sp.graph the period's launches (kernels only) are captured once on
+    // the context's capture stream and replayed on s; the capture is redone
+    // whenever compaction changes the launch list.
+    PeriodGraph pg(s);
+    for (int pt = 0;; ++pt) {
+        if (sp.graph) {
+            if (!pg.exec) {
+                const wdr_status cs = pg.capture(c, period);
+                if (cs != WDR_OK) return cs;
+            }
+            WDR_HIP(hipGraphLaunch(pg.exec, s));
+        } else {
+            period(s);
+        }
+        // poll one period behind; compact the launches to the live systems
         poll.post(alive, pt & 1, s);
         if (pt > 0) {
             if (poll.none((pt - 1) & 1)) break;
@@ -595,6 +654,7 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
                 launch_m = cnt;
                 sa.list = su.list = lw.as<int32_t>();
                 sa.count = su.count = cnt;
+                pg.reset();
             }
         }
     }

@@ -33,7 +33,7 @@ class SolverParams(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("sap_cycles", ctypes.c_int32), ("mr_steps", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("block_tol", ctypes.c_double), ("adj_tol", ctypes.c_double), ("inner", ctypes.c_int),
-                ("block_mr_steps", ctypes.c_int32)]
+                ("block_mr_steps", ctypes.c_int32), ("update_every", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

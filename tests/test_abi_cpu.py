@@ -47,7 +47,8 @@ int main(void) {
          sizeof(wdr_solve_info), sizeof(wdr_est_params), offsetof(wdr_solver_params, tol),
          offsetof(wdr_est_params, sp), offsetof(wdr_solver_params, inner), offsetof(wdr_est_params, max_batch),
          sizeof(wdr_proposal), offsetof(wdr_proposal, kappa), offsetof(wdr_proposal, seed));
-  printf("%zu\n", offsetof(wdr_solver_params, block_mr_steps));
+  printf("%zu %zu %zu\n", offsetof(wdr_solver_params, block_mr_steps), offsetof(wdr_solver_params, graph),
+         sizeof(wdr_solver_params));
   return 0;
 }'''
     import tempfile
@@ -60,7 +61,8 @@ int main(void) {
     want = [ctypes.sizeof(wdr.Geom), ctypes.sizeof(wdr.SolverParams), ctypes.sizeof(wdr.SolveInfo),
             ctypes.sizeof(wdr.EstParams), wdr.SolverParams.tol.offset, wdr.EstParams.sp.offset,
             wdr.SolverParams.inner.offset, wdr.EstParams.max_batch.offset, ctypes.sizeof(wdr.Proposal),
-            wdr.Proposal.kappa.offset, wdr.Proposal.seed.offset, wdr.SolverParams.block_mr_steps.offset]
+            wdr.Proposal.kappa.offset, wdr.Proposal.seed.offset, wdr.SolverParams.block_mr_steps.offset,
+            wdr.SolverParams.graph.offset, ctypes.sizeof(wdr.SolverParams)]
     assert vals == want
 
 
@@ -68,7 +70,7 @@ def test_default_params_from_library():
     from paper_1112_1243_amd import wdr
     p = wdr.default_params()
     assert p.restart == 16 and p.sap_cycles == 4 and p.mr_steps == 5 and p.tol == 1e-10
-    assert p.block_mr_steps == 16
+    assert p.block_mr_steps == 16 and p.update_every == 4 and p.graph == 1
 
 
 def test_missing_library_raises(monkeypatch):

@@ -159,6 +159,10 @@ def test_abi_errors():
     with pytest.raises(wdr.WdrError) as e:
         ctx.solve(gU2, 0.135, psi, wdr.default_params(max_iter=1))
     assert e.value.status == wdr.ENOCONV
+    for bad in (dict(update_every=0), dict(update_every=65), dict(graph=2)):
+        with pytest.raises(wdr.WdrError) as e:
+            ctx.solve(gU2, 0.135, psi, wdr.default_params(solver=wdr.SOLVER_CGNE, **bad))
+        assert e.value.status == wdr.EINVAL
     # blocks of 8^4 are too large for the block solver
     big = wdr.Context((16, 16, 16, 16), (8, 8, 8, 8))
     gB = big.gauge(dev(synth.unit_gauge((16, 16, 16, 16))))
