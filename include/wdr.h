@@ -278,6 +278,29 @@ wdr_status wdr_logdet_ratio_batch(int32_t n, const wdr_proposal *props, const wd
 wdr_status wdr_autotune(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *Up, double kappa, wdr_est_params *p,
                         double *host_seconds, void *stream);
 
+/* Exact block factors of eq. ddfactor (paper Sec. 3): host_out[b] =
+ * log det(D_b^+ D_b) of the Dirichlet block operator D_b (in-block hops
+ * only) of every block b, indexed by lexicographic block id (nblocks
+ * doubles).  Their differences between U' and U are the exact block ratios
+ * of the first acceptance step of eq. 4step.  Computed in FP64 on the
+ * device: the even-odd reduced normal matrix Dhat_b^+ Dhat_b (6 Vb rows,
+ * det D_b = det Dhat_b) of each block is formed and Cholesky-factorised;
+ * the result is 2 sum log L_ii.  Workspace: 16 (6 Vb rounded up to a
+ * multiple of 64)^2 bytes per block matrix; the matrices are factorised in
+ * passes of max_blocks (0: as many as fit in 8 GiB).  Returns after the
+ * stream has finished.  EINVAL for blocks of more than 256 sites
+ * or L/B odd in some direction; ENOCONV if a factorisation met a
+ * non-positive pivot (D_b singular to FP64 precision): those entries are
+ * NaN, the others valid. */
+wdr_status wdr_block_logdet(wdr_ctx *ctx, const wdr_gauge *U, double kappa, int32_t max_blocks, double *host_out,
+                            void *stream);
+
+/* host_out[b] = log det(D_b'^+ D_b') - log det(D_b^+ D_b): the exact block
+ * ratios between U' and U (eq. 4step, first step), the matrices of both
+ * fields in one batch.  Errors as wdr_block_logdet. */
+wdr_status wdr_block_logdet_ratio(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *Up, double kappa,
+                                  int32_t max_blocks, double *host_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

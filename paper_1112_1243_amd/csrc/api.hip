@@ -526,4 +526,31 @@ wdr_status wdr_logdet_ratio_batch(int32_t n, const wdr_proposal *props, const wd
     return e;
 }
 
+wdr_status wdr_block_logdet(wdr_ctx *c, const wdr_gauge *U, double kappa, int32_t max_blocks, double *out,
+                            void *stream)
+{
+    return wdr_block_logdet_ratio(c, U, nullptr, kappa, max_blocks, out, stream);
+}
+
+wdr_status wdr_block_logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, double kappa,
+                                  int32_t max_blocks, double *out, void *stream)
+{
+    if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
+    wdr_status e;
+    if ((e = check_gauge(c, U)) != WDR_OK || (Up && (e = check_gauge(c, Up)) != WDR_OK)) return e;
+    if ((e = check_kappa(kappa)) != WDR_OK) return e;
+    if (!out || max_blocks < 0) {
+        set_error("null output pointer or negative max_blocks");
+        return WDR_EINVAL;
+    }
+    if ((e = check_blocks_usable(c, true)) != WDR_OK) return e;
+    WDR_HIP(hipSetDevice(c->device));
+    const int nb = c->g.nblk;
+    if (!Up) return block_logdet(c, U, nullptr, kappa, max_blocks, out, S(stream));
+    std::vector<double> both(2 * (size_t)nb);
+    e = block_logdet(c, U, Up, kappa, max_blocks, both.data(), S(stream));
+    for (int b = 0; b < nb; ++b) out[b] = both[nb + b] - both[b];
+    return e;
+}
+
 }  // extern "C"

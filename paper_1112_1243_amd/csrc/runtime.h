@@ -130,6 +130,10 @@ struct Proposal {
 // every (proposal, step, noise) sample of the proposals is one system of the
 // batched launches; samples [proposal][step][noise](x nblk for BLOCKS),
 // log ratios per proposal
+// log det(D_b^+ D_b) of every block for U0 (and U1 when not null): out[f *
+// nblk + b] by lexicographic block id b
+wdr_status block_logdet(wdr_ctx *c, const wdr_gauge *U0, const wdr_gauge *U1, double kappa, int max_blocks,
+                        double *out, hipStream_t s);
 wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wdr_est_params &p,
                         double *host_samples, double *host_log_ratios, Stats &st, hipStream_t s);
 

@@ -110,6 +110,8 @@ def lib():
         L.wdr_logdet_ratio_batch.argtypes = [i32, ctypes.POINTER(Proposal), ctypes.POINTER(EstParams), P, P,
                                              ctypes.POINTER(SolveInfo), P]
         L.wdr_autotune.argtypes = [P, P, P, d, ctypes.POINTER(EstParams), ctypes.POINTER(d), P]
+        L.wdr_block_logdet.argtypes = [P, P, d, i32, P, P]
+        L.wdr_block_logdet_ratio.argtypes = [P, P, P, d, i32, P, P]
         _lib = L
     return _lib
 
@@ -317,6 +319,21 @@ class Context:
         _check(lib().wdr_autotune(self.handle, U.handle, Up.handle, kappa, ctypes.byref(ep), ctypes.byref(secs),
                                   _stream()))
         return ep.sp, secs.value
+
+    def block_logdet(self, U: Gauge, kappa, max_blocks=0, allow_nan=False):
+        """Exact log det(D_b^+ D_b) of every block, by lexicographic block id
+        (max_blocks: block matrices per pass, 0 for as many as fit in 8 GiB)."""
+        out = np.zeros(self.nblocks, dtype=np.float64)
+        _check(lib().wdr_block_logdet(self.handle, U.handle, kappa, max_blocks, out.ctypes.data_as(ctypes.c_void_p),
+                                      _stream()), (OK, ENOCONV) if allow_nan else (OK,))
+        return out
+
+    def block_logdet_ratio(self, U: Gauge, Up: Gauge, kappa, max_blocks=0):
+        """Exact block ratios log det(D_b'^+ D_b') - log det(D_b^+ D_b)."""
+        out = np.zeros(self.nblocks, dtype=np.float64)
+        _check(lib().wdr_block_logdet_ratio(self.handle, U.handle, Up.handle, kappa, max_blocks,
+                                            out.ctypes.data_as(ctypes.c_void_p), _stream()))
+        return out
 
     def logdet_ratio(self, U: Gauge, Up: Gauge, kappa, op, n_steps, n_noise, noise, seed, params: SolverParams,
                      max_batch: int = 0):

@@ -1,0 +1,136 @@
+"""GPU parity of the exact block determinants log det(D_b^+ D_b) (paper
+Sec. 3, eq. ddfactor; their ratios are the first acceptance step of
+eq. 4step) against the FP64 oracle's dense LU, through the C ABI.
+
+Tolerance 1e-8 absolute per block: the device result is 2 sum log L_ii of a
+Cholesky factorisation of the even-odd reduced normal matrix in FP64, whose
+rounding error is below 1e-11 for these well-conditioned Dirichlet blocks;
+1e-8 is the absolute tolerance the estimator's samples are held to."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1112_1243_amd import synth
+from tests.gpu_util import dev, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-8
+
+
+def _ctx(L, B):
+    torch_cuda()
+    from paper_1112_1243_amd import wdr
+    return wdr, wdr.Context(L, B), oracle.Lattice(L, B)
+
+
+@pytest.mark.parametrize("L,B,kappa,scale,general", [
+    # n = 96 rows per block: one tile padded from 96 to 128
+    ((4, 4, 4, 4), (2, 2, 2, 2), 0.125, 0.5, False),
+    # links that are not SU(3)
+    ((4, 4, 4, 4), (2, 2, 2, 2), 0.125, 0.5, True),
+    # n = 384: six tiles, non-cubic blocks
+    ((8, 4, 4, 4), (4, 2, 2, 2), 0.13, 0.5, False),
+    ((4, 4, 8, 8), (2, 2, 4, 4), 0.13, 0.4, False),
+])
+def test_every_block_matches_oracle(L, B, kappa, scale, general):
+    wdr, ctx, lat = _ctx(L, B)
+    say("blockdet", L, B, kappa, scale, "general" if general else "su3")
+    U = synth.gauge_field(L, scale, 501)
+    if general:
+        U = 1.02 * U
+    gU = ctx.gauge(dev(U))
+    got = ctx.block_logdet(gU, kappa)
+    want = oracle.block_log_dets(lat, U, kappa)
+    say("max |d logdet|", np.abs(got - want).max(), "range", want.min(), want.max())
+    assert np.abs(got - want).max() < TOL
+    del gU
+    ctx.close()
+
+
+def test_ratio_and_passes():
+    """Block ratios for a proposal that redraws the active links, computed in
+    passes of 5 matrices (ragged last pass) and in one pass: both equal the
+    oracle's differences."""
+    L, B, kappa = (4, 4, 4, 4), (2, 2, 2, 2), 0.13
+    wdr, ctx, lat = _ctx(L, B)
+    U = synth.gauge_field(L, 0.5, 503)
+    Up = synth.redraw(U, oracle.active_links(lat), 0.5, 504)
+    gU, gUp = ctx.gauge(dev(U)), ctx.gauge(dev(Up))
+    want = oracle.block_log_dets(lat, Up, kappa) - oracle.block_log_dets(lat, U, kappa)
+    for mb in (0, 5, 1):
+        got = ctx.block_logdet_ratio(gU, gUp, kappa, max_blocks=mb)
+        say("max_blocks", mb, "max |d ratio|", np.abs(got - want).max())
+        assert np.abs(got - want).max() < TOL
+    del gU, gUp
+    ctx.close()
+
+
+def test_4x4_blocks_sampled():
+    """4^4 blocks (n = 1536, 24 tiles) on an 8^4 lattice: two blocks against
+    the oracle, for U and for U' with the active links redrawn."""
+    L, B, kappa = (8, 8, 8, 8), (4, 4, 4, 4), 0.135
+    wdr, ctx, lat = _ctx(L, B)
+    U = synth.gauge_field(L, 0.5, 505)
+    Up = synth.redraw(U, oracle.active_links(lat), 0.5, 506)
+    gU, gUp = ctx.gauge(dev(U)), ctx.gauge(dev(Up))
+    got = ctx.block_logdet(gU, kappa)
+    ratio = ctx.block_logdet_ratio(gU, gUp, kappa)
+    blocks = [0, 11]
+    w0 = oracle.block_log_dets(lat, U, kappa, blocks=blocks)
+    w1 = oracle.block_log_dets(lat, Up, kappa, blocks=blocks)
+    for b in blocks:
+        say("block", b, got[b], w0[b], "ratio", ratio[b], w1[b] - w0[b])
+        assert abs(got[b] - w0[b]) < TOL
+        assert abs(ratio[b] - (w1[b] - w0[b])) < TOL
+    del gU, gUp
+    ctx.close()
+
+
+def test_full_size_sampled_by_embedding():
+    """16^4 lattice, 256 blocks of 4^4 (the size of the 16^4 workload): a
+    block's factor depends only on its own links, so copying them into block
+    0 of an 8^4 lattice lets the oracle check that entry."""
+    L, B, kappa = (16, 16, 16, 16), (4, 4, 4, 4), 0.15
+    wdr, ctx, lat = _ctx(L, B)
+    U = synth.gauge_field(L, 0.25, 507)
+    gU = ctx.gauge(dev(U))
+    got = ctx.block_logdet(gU, kappa)
+    assert np.all(np.isfinite(got))
+    small = oracle.Lattice((8, 8, 8, 8), B)
+    xs = small.coords()
+    x16 = lat.coords()
+    site16 = lambda x: x[..., 0] + 16 * (x[..., 1] + 16 * (x[..., 2] + 16 * x[..., 3]))
+    for b in (37, 200):
+        nb = np.array([(b >> (2 * mu)) & 3 for mu in range(4)])  # block coords, NB = 4
+        in0 = np.all(xs < 4, axis=1)
+        U8 = synth.gauge_field(small.L, 0.25, 508)
+        U8[in0] = U[site16(xs[in0] + 4 * nb)]
+        want = oracle.block_log_dets(small, U8, kappa, blocks=[0])[0]
+        say("16^4 block", b, got[b], want)
+        assert abs(got[b] - want) < TOL
+    del gU
+    ctx.close()
+
+
+def test_errors():
+    wdr, ctx, lat = _ctx((4, 4, 4, 4), (2, 2, 2, 2))
+    gU = ctx.gauge(dev(synth.unit_gauge(lat.L)))
+    with pytest.raises(wdr.WdrError) as e:
+        ctx.block_logdet(gU, -0.1)
+    assert e.value.status == wdr.EINVAL
+    with pytest.raises(wdr.WdrError) as e:
+        ctx.block_logdet(gU, 0.1, max_blocks=-1)
+    assert e.value.status == wdr.EINVAL
+    # unit links at small kappa: every block equals the plaquette expansion
+    got = ctx.block_logdet(gU, 0.003)
+    assert np.ptp(got) < 1e-13 and abs(got[0] / (96 * 24 * 0.003 ** 4) - 1) < 5e-4
+    del gU
+    ctx.close()
+    big = wdr.Context((16, 8, 8, 8), (8, 4, 4, 4))  # 512-site blocks
+    gB = big.gauge(dev(synth.unit_gauge((16, 8, 8, 8))))
+    with pytest.raises(wdr.WdrError) as e:
+        big.block_logdet(gB, 0.1)
+    assert e.value.status == wdr.EINVAL
+    del gB
+    big.close()
