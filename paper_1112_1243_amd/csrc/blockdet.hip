@@ -20,14 +20,18 @@
 //  2. Right-looking blocked Cholesky with 64-wide panels, batched over
 //     blocks: k_potrf_tile factors the diagonal tile in LDS and builds
 //     W = L_pp^-1 with the same elimination steps; k_tile_gemm<0> forms the
-//     panel L_Ip = A_Ip W^+; k_tile_gemm<1> the trailing update
-//     A_IJ -= L_Ip L_Jp^+ (I >= J), on FP64 MFMA 16x16x4 with four real
-//     products per complex one.  Only the lower triangle is ever read.
+//     panel L_Ip = A_Ip W^+; k_tile_gemm<1> the updates A_IJ -= L_Ip L_Jp^+
+//     (I >= J), on FP64 MFMA 16x16x4 with four real products per complex
+//     one.  Panels come in groups of GROUP: after each panel only the rest
+//     of its group is updated, and the tiles right of the group take one
+//     update with k = 64 GROUP, so the trailing matrix is read and written
+//     once per group instead of once per panel.  Only the lower triangle is
+//     ever read.
 #include <algorithm>
 #include <cmath>
 
+#include "lds_stencil.h"
 #include "runtime.h"
-#include "stencil.h"
 
 namespace wdr {
 namespace {
@@ -36,22 +40,8 @@ using namespace dev;
 
 constexpr int TW = 64;   // tile and panel width
 constexpr int KC = 32;   // k-chunk staged in LDS by the tile GEMM
+constexpr int GROUP = 4; // panels per trailing update
 constexpr int MAX_VH = 128;
-
-// in-block neighbours from an LDS half field [12][Vh]; `off` is subtracted
-// from the local index (0 for even sites, Vh for odd ones)
-struct HalfLd {
-    const double2 *sh;
-    int Vh, off;
-    __device__ __forceinline__ void operator()(int, int nl, spinor<double> &p) const
-    {
-        const int i = nl - off;
-#pragma unroll
-        for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) p.s[sp].c[a] = ld<double>(sh, (long)(3 * sp + a) * Vh + i);
-    }
-};
 
 __device__ __forceinline__ void unpack_coords(uint32_t v, int x[4])
 {
@@ -75,7 +65,7 @@ __global__ __launch_bounds__(256) void k_normal(Geo g, const double2 *__restrict
     const double k2 = kappa * kappa;
     int x[4];
     unpack_coords(g.loc_coord[l], x);
-    const HalfLd from_e{she, Vh, 0}, from_o{sho, Vh, Vh};
+    const LdsLoader<double> from_e{she, Vh, 0}, from_o{sho, Vh, Vh};
     const int c0 = blockIdx.x * cols, c1 = min(n, c0 + cols);
     for (int col = c0; col < c1; ++col) {
         const int j = col / 12, cc = col % 12;
@@ -121,6 +111,96 @@ __global__ __launch_bounds__(256) void k_normal(Geo g, const double2 *__restrict
     }
 }
 
+// The same for B^4 blocks of SU(3) links, with the links staged in LDS and
+// the geometry known at compile time.  Every stage keeps all four
+// wavefronts busy: for output site t of the stage's parity, lane t of the
+// first half (t < Vh) sums the hops in directions 0 and 1 and lane Vh + t
+// those in directions 2 and 3.  The two partial sums meet in the half field
+// that the stage does not read: the output half of an odd stage, the input
+// half of an even stage once both partial sums are done.
+template <int B>
+__global__ __launch_bounds__(Cube<B>::Vb) void k_normal_cube(int nblk, const double2 *__restrict__ U0,
+                                                             const double2 *__restrict__ U1, int q0, int cols,
+                                                             double kappa, long np, double2 *__restrict__ A)
+{
+    typedef Cube<B> CB;
+    constexpr int Vb = CB::Vb, Vh = CB::Vh, n = 6 * Vb;
+    __shared__ CubeLds<double, B> S;
+    const int q = q0 + blockIdx.y, slot = q % nblk;
+    const auto *Ug = as_global(q / nblk ? U1 : U0);
+    double2 *Aq = A + (long)blockIdx.y * np * np;
+    const int tid = threadIdx.x, t = tid % Vh, mu0 = tid < Vh ? 0 : 2;
+    const bool first = tid < Vh;
+    const double k2 = kappa * kappa;
+    // output sites of this lane: even site t and odd site Vh + t
+    int xe[4], xo[4];
+    CB::coords(t, xe);
+    CB::coords(Vh + t, xo);
+    {
+        const long base = (long)slot * 4 * 9 * Vb + tid;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (int e = 0; e < 6; ++e)
+                st<double>(S.lk, (mu * 6 + e) * Vb + tid, ldg<double>(Ug, base + (long)(mu * 9 + e) * Vb));
+    }
+    const int c0 = blockIdx.x * cols, c1 = min(n, c0 + cols);
+    for (int col = c0; col < c1; ++col) {
+        const int j = col / 12, cc = col % 12;
+        int xj[4];
+        CB::coords(j, xj);
+        int de = 0, dn = 0;
+#pragma unroll
+        for (int mu = 0; mu < 4; ++mu) {
+            de += abs(xe[mu] - xj[mu]);
+            dn += abs(xo[mu] - xj[mu]);
+        }
+        spinor<double> acc;
+        if (first)
+            for (int k = 0; k < 12; ++k) S.she[k * Vh + t] = make_double2(t == j && k == cc ? 1.0 : 0.0, 0.0);
+        __syncthreads();
+        for (int stage = 1; stage <= 4; ++stage) {
+            zero(acc);
+            if (stage & 1) {
+                // odd sites: H_oe of the even half (reaches distance 1, then 3)
+                if (dn <= stage)
+                    for (int mu = mu0; mu < mu0 + 2; ++mu) hop_dir_lds_rt<double, B>(mu, S.she, 0, S.lk, Vh + t, xo, acc);
+                if (first) lds_store<double>(S.sho, Vh, t, acc);
+                __syncthreads();
+                if (!first) {
+#pragma unroll
+                    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const long i = (long)(3 * sp + a) * Vh + t;
+                            st<double>(S.sho, i, ld<double>(S.sho, i) + acc.s[sp].c[a]);
+                        }
+                }
+            } else {
+                // even sites: g5 (x - k^2 H_eo t) (distance 2, then 4)
+                if (de <= stage)
+                    for (int mu = mu0; mu < mu0 + 2; ++mu) hop_dir_lds_rt<double, B>(mu, S.sho, Vh, S.lk, t, xe, acc);
+                __syncthreads();
+                if (!first) lds_store<double>(S.sho, Vh, t, acc);
+                __syncthreads();
+                if (first) {
+#pragma unroll
+                    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const long i = (long)(3 * sp + a) * Vh + t;
+                            cx<double> v = ld<double>(S.she, i) - scale(k2, acc.s[sp].c[a] + ld<double>(S.sho, i));
+                            if (sp >= 2) v = neg(v);
+                            if (stage == 2) st<double>(S.she, i, v);
+                            else Aq[(long)col * np + 12 * t + 3 * sp + a] = make_double2(v.re, -v.im);
+                        }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
 // rows n .. np-1 of every matrix: the identity
 __global__ __launch_bounds__(256) void k_pad(long n, long np, double2 *__restrict__ A)
 {
@@ -150,99 +230,145 @@ __device__ __forceinline__ double2 cmul_conj(double2 a, double2 b)  // a * conj(
     return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 
-// Cholesky of the diagonal tile p of every matrix, in LDS.  Step k scales
-// column k by 1 / L_kk and updates the trailing lower triangle; the same
-// row operations turn W = 1 into L^-1.  Adds 2 sum_k log L_kk to ld[q] and
-// sets bad[q] on a pivot that is not positive.
+// Cholesky of the diagonal tile p of every matrix.  Lane (u, v) = (tid / 16,
+// tid % 16) keeps entries (u + 16 a, v + 16 b), a, b < 4, of the tile and of
+// W in registers.  Step k: the owner of entry (k, k) publishes d = L_kk; the
+// owners of column k publish L_ik = A_ik / d and those of row k of W scale
+// it by 1 / d and publish it; then every lane updates its entries,
+// A_ij -= L_ik conj(L_jk) and W_ic -= L_ik W_kc (i, j > k), so that W ends
+// as L^-1.  Adds 2 sum_k log L_kk to ld[q]; sets bad[q] on a pivot that is
+// not positive.
 __global__ __launch_bounds__(256) void k_potrf_tile(double2 *__restrict__ A, long np, int p, int q0,
                                                     double2 *__restrict__ W, double *__restrict__ ld,
                                                     int32_t *__restrict__ bad)
 {
-    __shared__ double2 a[TW][TW + 1], w[TW][TW + 1];
-    const int tid = threadIdx.x;
+    __shared__ double2 colk[TW], rowk[TW];
+    __shared__ double dsh, lsh[16];
+    __shared__ int badsh;
+    const int tid = threadIdx.x, u = tid >> 4, v = tid & 15;
     const double2 *T = A + (long)blockIdx.x * np * np + (long)TW * p * np + TW * p;
-    for (int i = tid; i < TW * TW; i += 256) {
-        const int r = i / TW, c = i % TW;
-        a[r][c] = c <= r ? T[(long)r * np + c] : make_double2(0.0, 0.0);
-        w[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
-    }
-    __syncthreads();
+    double2 a[4][4], w[4][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int r = u + 16 * x, c = v + 16 * y;
+            a[x][y] = c <= r ? T[(long)r * np + c] : make_double2(0.0, 0.0);
+            w[x][y] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+        }
+    if (tid == 0) badsh = 0;
     double lsum = 0.0;
-    int ok = 1;
     for (int k = 0; k < TW; ++k) {
-        const double akk = a[k][k].x;
-        ok &= akk > 0.0;  // also false for NaN
-        const double d = sqrt(fmax(akk, 1e-300)), inv = 1.0 / d;
-        lsum += log(d);
+        const int ku = k & 15, kx = k >> 4;
+        if (u == ku && v == ku) {
+            double akk = 0.0;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+                if (x == kx) akk = a[x][x].x;
+            if (!(akk > 0.0)) badsh = 1;  // also for NaN
+            const double d = sqrt(fmax(akk, 1e-300));
+            dsh = d;
+            lsum += log(d);
+        }
         __syncthreads();
-        if (tid < TW) {
-            if (tid > k) {
-                a[tid][k].x *= inv;
-                a[tid][k].y *= inv;
-            } else {
-                if (tid == k) a[k][k] = make_double2(d, 0.0);
-                w[k][tid].x *= inv;
-                w[k][tid].y *= inv;
+        const double inv = 1.0 / dsh;
+        if (v == ku) {  // column k of the tile: rows u + 16 x
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                double2 e = make_double2(0.0, 0.0);
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+                    if (y == kx) e = a[x][y];
+                const int r = u + 16 * x;
+                colk[r] = r > k ? make_double2(e.x * inv, e.y * inv) : make_double2(0.0, 0.0);
             }
         }
+        if (u == ku) {  // row k of W: columns v + 16 y, scaled in place
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+                if (x == kx) {
+#pragma unroll
+                    for (int y = 0; y < 4; ++y) {
+                        w[x][y].x *= inv;
+                        w[x][y].y *= inv;
+                        rowk[v + 16 * y] = w[x][y];
+                    }
+                }
+        }
         __syncthreads();
-        const int m = TW - 1 - k;
-        for (int i = tid; i < m * m; i += 256) {
-            const int r = k + 1 + i / m, c = k + 1 + i % m;
-            if (c <= r) {
-                const double2 t = cmul_conj(a[r][k], a[c][k]);
-                a[r][c].x -= t.x;
-                a[r][c].y -= t.y;
+        double2 cr[4], cc[4], rw[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            cr[x] = colk[u + 16 * x];
+            cc[x] = colk[v + 16 * x];
+            rw[x] = rowk[v + 16 * x];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                // colk is 0 at rows <= k, so only i, j > k change
+                const double2 t1 = cmul_conj(cr[x], cc[y]), t2 = cmul(cr[x], rw[y]);
+                a[x][y].x -= t1.x;
+                a[x][y].y -= t1.y;
+                w[x][y].x -= t2.x;
+                w[x][y].y -= t2.y;
             }
-        }
-        for (int i = tid; i < m * (k + 1); i += 256) {
-            const int r = k + 1 + i / (k + 1), c = i % (k + 1);
-            const double2 t = cmul(a[r][k], w[k][c]);
-            w[r][c].x -= t.x;
-            w[r][c].y -= t.y;
-        }
-        __syncthreads();
     }
     double2 *Wq = W + (long)blockIdx.x * TW * TW;
-    for (int i = tid; i < TW * TW; i += 256) Wq[i] = w[i / TW][i % TW];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) Wq[(u + 16 * x) * TW + v + 16 * y] = w[x][y];
+    if (u == v) lsh[u] = lsum;
+    __syncthreads();
     if (tid == 0) {
-        ld[q0 + blockIdx.x] += 2.0 * lsum;
-        if (!ok) bad[q0 + blockIdx.x] = 1;
+        double t = 0.0;
+        for (int i = 0; i < 16; ++i) t += lsh[i];
+        ld[q0 + blockIdx.x] += 2.0 * t;
+        if (badsh) bad[q0 + blockIdx.x] = 1;
     }
 }
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// C = X Y^+ over 64 columns of k, for 64 x 64 complex tiles:
-//   MODE 0: X = A_Ip, Y = W (L_pp^-1), C = A_Ip in place (panel solve)
-//   MODE 1: X = A_Ip, Y = A_Jp, C = A_IJ - X Y^+ for the tile pair
-//           (I, J), I >= J > p, numbered row by row.
+// C = X Y^+ for 64 x 64 complex tiles, X and Y the tiles of rows I and J
+// over columns [kbeg, kbeg + klen):
+//   MODE 0: X = A_Ip, Y = W (L_pp^-1, klen 64), C = A_Ip in place (panel
+//           solve); I = j0 + blockIdx.x
+//   MODE 1: C = A_IJ - X Y^+ for the tile pairs I >= J: with nj > 0 the
+//           rectangle I = i0 + x / nj, J = j0 + x % nj (pairs with I < J
+//           exit), with nj = 0 the triangle I >= J >= j0 numbered row by row.
 // Four wavefronts each own a 32 x 32 quadrant as 2 x 2 MFMA tiles with
 // separate real and imaginary accumulators.  MFMA 16x16x4 f64 operands:
 // lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; element r of its
-// accumulator is D[l / 16 + 4 r][l % 16].  Here
-// B[k][n] = conj(Y[n][k]), so re C += Xr Yr + Xi Yi, im C += Xi Yr - Xr Yi.
+// accumulator is D[l / 16 + 4 r][l % 16].  Here B[k][n] = conj(Y[n][k]),
+// so re C += Xr Yr + Xi Yi and im C += Xi Yr - Xr Yi.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_tile_gemm(double2 *__restrict__ A, long np, int p,
-                                                   const double2 *__restrict__ W)
+__global__ __launch_bounds__(256) void k_tile_gemm(double2 *__restrict__ A, long np, int i0, int j0, int nj,
+                                                   int kbeg, int klen, const double2 *__restrict__ W)
 {
     __shared__ double xr[TW][KC + 1], xi[TW][KC + 1], yr[TW][KC + 1], yi[TW][KC + 1];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     double2 *Aq = A + (long)blockIdx.y * np * np;
     int I, J;
     if (MODE == 0) {
-        I = p + 1 + blockIdx.x;
-        J = p;
+        I = j0 + blockIdx.x;
+        J = kbeg / TW;
+    } else if (nj > 0) {
+        I = i0 + blockIdx.x / nj;
+        J = j0 + blockIdx.x % nj;
+        if (I < J) return;
     } else {
         const int x = blockIdx.x;
         int ii = (int)((sqrt(8.0 * x + 1.0) - 1.0) * 0.5);
         while ((ii + 1) * (ii + 2) / 2 <= x) ++ii;
         while (ii * (ii + 1) / 2 > x) --ii;
-        I = p + 1 + ii;
-        J = p + 1 + (x - ii * (ii + 1) / 2);
+        I = j0 + ii;
+        J = j0 + (x - ii * (ii + 1) / 2);
     }
-    const double2 *X = Aq + (long)TW * I * np + TW * p;
-    const double2 *Y = MODE == 0 ? W + (long)blockIdx.y * TW * TW : Aq + (long)TW * J * np + TW * p;
+    const double2 *X = Aq + (long)TW * I * np + kbeg;
+    const double2 *Y = MODE == 0 ? W + (long)blockIdx.y * TW * TW : Aq + (long)TW * J * np + kbeg;
     const long ys = MODE == 0 ? TW : np;
     const int r0 = 32 * (wv >> 1), c0 = 32 * (wv & 1), m = lane & 15, kl = lane >> 4;
     d4 cre[2][2], cim[2][2];
@@ -250,7 +376,7 @@ __global__ __launch_bounds__(256) void k_tile_gemm(double2 *__restrict__ A, long
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) cre[a][b] = cim[a][b] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int kc = 0; kc < TW; kc += KC) {
+    for (int kc = 0; kc < klen; kc += KC) {
         for (int i = tid; i < TW * KC; i += 256) {
             const int r = i / KC, k = i % KC;
             const double2 u = X[(long)r * np + kc + k], v = Y[(long)r * ys + kc + k];
@@ -325,17 +451,33 @@ wdr_status block_logdet(wdr_ctx *c, const wdr_gauge *U0, const wdr_gauge *U1, do
     // about 2048 workgroups per pass for the normal-matrix columns
     const int cols = (int)std::max<long>(12, (n * per_pass + 2047) / 2048);
     const int ncg = (int)((n + cols - 1) / cols);
+    // SU(3) links of 4^4 blocks: links in LDS, compile-time geometry
+    const bool cube4 = g.B[0] == 4 && g.B[1] == 4 && g.B[2] == 4 && g.B[3] == 4 && U0->su3 && (!U1 || U1->su3);
     for (int q0 = 0; q0 < nm; q0 += per_pass) {
         const int m = std::min(per_pass, nm - q0);
-        k_normal<<<dim3(ncg, m), g.Vb, 0, s>>>(g, U0->u64, U1 ? U1->u64 : U0->u64, q0, cols, kappa, np, A);
+        if (cube4)
+            k_normal_cube<4><<<dim3(ncg, m), 256, 0, s>>>(g.nblk, U0->u64, U1 ? U1->u64 : U0->u64, q0, cols, kappa,
+                                                          np, A);
+        else
+            k_normal<<<dim3(ncg, m), g.Vb, 0, s>>>(g, U0->u64, U1 ? U1->u64 : U0->u64, q0, cols, kappa, np, A);
         if (np > n) k_pad<<<dim3((unsigned)std::min<long>(64, ((np - n) * np + 255) / 256), m), 256, 0, s>>>(n, np, A);
-        for (int p = 0; p < T; ++p) {
-            k_potrf_tile<<<m, 256, 0, s>>>(A, np, p, q0, W, ld, bad);
-            const int rest = (int)(T - 1 - p);
-            if (rest > 0) {
-                k_tile_gemm<0><<<dim3(rest, m), 256, 0, s>>>(A, np, p, W);
-                k_tile_gemm<1><<<dim3(rest * (rest + 1) / 2, m), 256, 0, s>>>(A, np, p, W);
+        // panels in groups of GROUP: each panel updates only the rest of its
+        // group; the tiles right of the group get one update per group
+        for (int g0 = 0; g0 < T; g0 += GROUP) {
+            const int g1 = (int)std::min<long>(T, g0 + GROUP);
+            for (int p = g0; p < g1; ++p) {
+                k_potrf_tile<<<m, 256, 0, s>>>(A, np, p, q0, W, ld, bad);
+                if (p + 1 < T) k_tile_gemm<0><<<dim3((unsigned)(T - 1 - p), m), 256, 0, s>>>(A, np, 0, p + 1, 0, TW * p, TW, W);
+                if (p + 1 < g1) {
+                    const int nj = g1 - p - 1;
+                    k_tile_gemm<1><<<dim3((unsigned)((T - p - 1) * nj), m), 256, 0, s>>>(A, np, p + 1, p + 1, nj, TW * p,
+                                                                                         TW, W);
+                }
             }
+            const int rest = (int)(T - g1);
+            if (rest > 0)
+                k_tile_gemm<1><<<dim3(rest * (rest + 1) / 2, m), 256, 0, s>>>(A, np, g1, g1, 0, TW * g0,
+                                                                               TW * (g1 - g0), W);
         }
     }
     WDR_HIP(hipGetLastError());
