@@ -333,6 +333,55 @@ def batched_proposals(wdr, torch, n_steps=8, scale=0.3):
             "speedup_vs_fp64_serial": round(serial / dt, 2)}
 
 
+def block_determinants(wdr, torch):
+    """Exact block ratios log det(D_b'^+ D_b') - log det(D_b^+ D_b) of every
+    4^4 block (Sec. 3, eqs. ddfactor and 4step, first step) for the proposals
+    of the 8^4 and 16^4 workloads: 2 x nblocks normal matrices of 1536 rows,
+    formed and Cholesky-factorised in FP64 in one call.  The rate is counted
+    in Cholesky flops (4/3 n^3 per matrix) over the whole call, formation of
+    the matrices included, against the FP64 matrix peak.  For the 8^4
+    workload the stochastic BLOCKS estimate of the same proposal (N = 64
+    factors x 1 Gaussian noise) is reported beside the exact sum."""
+    from paper_1112_1243_amd import synth
+    res = {}
+    for name, reps in (("wilson8_dd16", 5), ("wilson16_dd256", 2)):
+        w = synth.WORKLOADS[name]
+        ctx = wdr.Context(w["L"], w["B"])
+        U = synth.gauge_field(w["L"], w["scale"], w["seed"])
+        Up = synth.redraw(U, proposal_mask(ctx, w["proposal"]), w["scale"], w["seed"])
+        gU, gUp = ctx.gauge(torch.from_numpy(U).cuda()), ctx.gauge(torch.from_numpy(Up).cuda())
+        del U, Up
+        ctx.block_logdet_ratio(gU, gUp, w["kappa"])  # warm-up (workspace)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = ctx.block_logdet_ratio(gU, gUp, w["kappa"])
+        dt = (time.perf_counter() - t0) / reps
+        n = 6 * int(np.prod(w["B"]))
+        flops = 2 * ctx.nblocks * 4.0 / 3.0 * n ** 3
+        d = {"workload": "%s: %s lattice, %d blocks of %s, kappa %.3f, U and U' (%s)" % (
+                 name, "x".join(map(str, w["L"])), ctx.nblocks, "x".join(map(str, w["B"])), w["kappa"],
+                 w["proposal"]),
+             "value": round(ctx.nblocks / dt, 2), "unit": "exact block ratios/s", "ms_per_call": round(dt * 1e3, 3),
+             "matrices": 2 * ctx.nblocks, "rows": n,
+             "roofline": {"bound": "mfma", "achieved": round(flops / dt / 1e12, 2), "peak": 78.6,
+                          "unit": "TFLOP/s", "frac": round(flops / dt / 1e12 / 78.6, 4), "traffic": None,
+                          "what": "Cholesky flops 4/3 n^3 per matrix over the whole call (formation included)"},
+             "exact_blocks_log_ratio": float(np.sum(r))}
+        if name == "wilson8_dd16":
+            # the proposal redraws whole links, so each path factor's samples
+            # vary by about 2 per block at N = 8: with N = 64 the variance is
+            # small enough for log-mean-exp to approach the exact value
+            p = wdr.default_params()
+            s, lr, _ = ctx.logdet_ratio(gU, gUp, w["kappa"], wdr.OP_BLOCKS, 64, 1, wdr.NOISE_GAUSS, w["seed"], p)
+            d["stochastic_blocks_log_ratio_N64"] = float(lr)
+        log("block determinants %s: %s" % (name, d))
+        res[name] = d
+        del gU, gUp
+        ctx.close()
+    return res
+
+
 def cpu_baseline(wl, U, Up, budget_s=20.0):
     """FP64 CPU oracle on a bounded sample: one BLOCKS and one SCHUR sample
     (one factor, one noise vector) of the same workload, scaled to a full
@@ -362,6 +411,7 @@ def main():
     ap.add_argument("--no-dslash", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-proposal workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 16^4 and 32^4 workloads")
+    ap.add_argument("--no-blockdet", action="store_true", help="skip the exact block determinants")
     ap.add_argument("--rocprof-summary", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     args = ap.parse_args()
     if args.rocprof_summary:
@@ -439,6 +489,8 @@ def main():
     if not args.no_large:
         large = {name: dd_workload(wdr, torch, name) for name in ("wilson16_dd256", "wilson32_dd4096")}
 
+    bdet = None if args.no_blockdet else block_determinants(wdr, torch)
+
     cpu = None if args.no_cpu else cpu_baseline(wl, U, Up)
     if cpu:
         log("cpu baseline:", cpu)
@@ -468,6 +520,7 @@ def main():
         "roofline": roof,
         "batched_proposals": batch,
         "large_lattices": large,
+        "block_determinants": bdet,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
