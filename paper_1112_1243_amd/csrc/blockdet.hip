@@ -258,62 +258,64 @@ __global__ __launch_bounds__(256) void k_potrf_tile(double2 *__restrict__ A, lon
         }
     if (tid == 0) badsh = 0;
     double lsum = 0.0;
-    for (int k = 0; k < TW; ++k) {
-        const int ku = k & 15, kx = k >> 4;
-        if (u == ku && v == ku) {
-            double akk = 0.0;
+    // k = 16 kx + ku; with kx known at compile time the register arrays are
+    // indexed statically and the entries that no longer change are skipped:
+    // rows and columns of A below 16 kx + ku are final, and row k of W has
+    // nothing right of column k
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
-                if (x == kx) akk = a[x][x].x;
-            if (!(akk > 0.0)) badsh = 1;  // also for NaN
-            const double d = sqrt(fmax(akk, 1e-300));
-            dsh = d;
-            lsum += log(d);
-        }
-        __syncthreads();
-        const double inv = 1.0 / dsh;
-        if (v == ku) {  // column k of the tile: rows u + 16 x
-#pragma unroll
-            for (int x = 0; x < 4; ++x) {
-                double2 e = make_double2(0.0, 0.0);
-#pragma unroll
-                for (int y = 0; y < 4; ++y)
-                    if (y == kx) e = a[x][y];
-                const int r = u + 16 * x;
-                colk[r] = r > k ? make_double2(e.x * inv, e.y * inv) : make_double2(0.0, 0.0);
+    for (int kx = 0; kx < 4; ++kx) {
+        for (int ku = 0; ku < 16; ++ku) {
+            const int k = 16 * kx + ku;
+            if (u == ku && v == ku) {
+                const double akk = a[kx][kx].x;
+                if (!(akk > 0.0)) badsh = 1;  // also for NaN
+                const double d = sqrt(fmax(akk, 1e-300));
+                dsh = d;
+                lsum += log(d);
             }
-        }
-        if (u == ku) {  // row k of W: columns v + 16 y, scaled in place
+            __syncthreads();
+            const double inv = 1.0 / dsh;
+            if (v == ku) {  // column k of the tile: rows u + 16 x
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
-                if (x == kx) {
-#pragma unroll
-                    for (int y = 0; y < 4; ++y) {
-                        w[x][y].x *= inv;
-                        w[x][y].y *= inv;
-                        rowk[v + 16 * y] = w[x][y];
-                    }
+                for (int x = 0; x < 4; ++x) {
+                    const int r = u + 16 * x;
+                    colk[r] = r > k ? make_double2(a[x][kx].x * inv, a[x][kx].y * inv) : make_double2(0.0, 0.0);
                 }
-        }
-        __syncthreads();
-        double2 cr[4], cc[4], rw[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            cr[x] = colk[u + 16 * x];
-            cc[x] = colk[v + 16 * x];
-            rw[x] = rowk[v + 16 * x];
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) {
-                // colk is 0 at rows <= k, so only i, j > k change
-                const double2 t1 = cmul_conj(cr[x], cc[y]), t2 = cmul(cr[x], rw[y]);
-                a[x][y].x -= t1.x;
-                a[x][y].y -= t1.y;
-                w[x][y].x -= t2.x;
-                w[x][y].y -= t2.y;
             }
+            if (u == ku) {  // row k of W: columns v + 16 y, scaled in place
+#pragma unroll
+                for (int y = 0; y < 4; ++y) {
+                    w[kx][y].x *= inv;
+                    w[kx][y].y *= inv;
+                    rowk[v + 16 * y] = w[kx][y];
+                }
+            }
+            __syncthreads();
+            double2 cr[4], cc[4], rw[4];
+#pragma unroll
+            for (int x = kx; x < 4; ++x) {
+                cr[x] = colk[u + 16 * x];
+                cc[x] = colk[v + 16 * x];
+            }
+#pragma unroll
+            for (int y = 0; y <= kx; ++y) rw[y] = rowk[v + 16 * y];
+            // colk is 0 at rows <= k, so only entries below row k change
+#pragma unroll
+            for (int x = kx; x < 4; ++x) {
+#pragma unroll
+                for (int y = kx; y < 4; ++y) {
+                    const double2 t1 = cmul_conj(cr[x], cc[y]);
+                    a[x][y].x -= t1.x;
+                    a[x][y].y -= t1.y;
+                }
+#pragma unroll
+                for (int y = 0; y <= kx; ++y) {
+                    const double2 t2 = cmul(cr[x], rw[y]);
+                    w[x][y].x -= t2.x;
+                    w[x][y].y -= t2.y;
+                }
+            }
+        }
     }
     double2 *Wq = W + (long)blockIdx.x * TW * TW;
 #pragma unroll
