@@ -112,3 +112,50 @@ def test_locality():
     assert changed[5] and changed.sum() == 1
     c = oracle.block_log_dets(lat, synth.redraw(U, cross, 0.5, 45), k)
     assert np.abs(c - base).max() < 1e-12
+
+
+def extract_block(lat, U, b):
+    """Links of block b of lat as a canonical field of the block's extents
+    (in-block lexicographic order), by index arithmetic."""
+    bid, _, _ = lat.maps()
+    x = lat.coords()
+    sites = np.nonzero(bid == b)[0]
+    loc = x[sites] % np.array(lat.B)
+    B = lat.B
+    order = np.argsort(loc[:, 0] + B[0] * (loc[:, 1] + B[1] * (loc[:, 2] + B[2] * loc[:, 3])))
+    return np.ascontiguousarray(U[sites[order]]), sites[order]
+
+
+@pytest.mark.parametrize("L,B", [((4, 4, 4, 4), (2, 2, 2, 2)), ((8, 4, 8, 4), (4, 2, 4, 2))])
+def test_open_boundary_is_the_dirichlet_block(L, B):
+    """Open boundaries (bc = 0 drops the hops that wrap): the lattice operator
+    of an extracted block equals that block's Dirichlet operator D_b (Sec. 3,
+    eq. domdec), which is what makes a block a lattice of its own for eq.
+    ddrec."""
+    lat = oracle.Lattice(L, B=B, bc=(1, 1, 1, -1))
+    U = synth.gauge_field(L, 0.6, 61)
+    psi = synth.spinor(L, 62)
+    whole = oracle.apply_Dblock(lat, U, 0.13, psi, 2)
+    small = oracle.Lattice(B, bc=(0, 0, 0, 0))
+    for b in (0, lat.nblocks - 1):
+        Ub, sites = extract_block(lat, U, b)
+        got = oracle.apply_D(small, Ub, 0.13, np.ascontiguousarray(psi[sites]))
+        assert np.abs(got - whole[sites]).max() < 1e-14
+
+
+def test_ddrec_on_an_open_block():
+    """eq. ddrec: det D_b = prod_b' det D_b' det Dhat_b, i.e. eq. ddfactor on a
+    4^4 block of an 8^4 lattice, extracted with open boundaries, with 2^4
+    sub-blocks (the open lattice operator is D_b by the test above)."""
+    big = oracle.Lattice((8, 8, 8, 8), B=(4, 4, 4, 4))
+    U = synth.gauge_field(big.L, 0.5, 63)
+    k = 0.13
+    Ub, _ = extract_block(big, U, 9)
+    lat = oracle.Lattice((4, 4, 4, 4), B=(2, 2, 2, 2), bc=(0, 0, 0, 0))
+    _, col, _ = lat.maps()
+    D = _dense(lat, lambda v: oracle.apply_D(lat, Ub, k, v))
+    ld_block = 2 * oracle.log_abs_det(D)
+    black = oracle.site_dofs(col == 0)
+    Dhat = oracle.dense(lambda v: oracle.schur_apply(lat, Ub, k, v), lat.V, cols=black)[black]
+    total = oracle.block_log_dets(lat, Ub, k).sum() + 2 * oracle.log_abs_det(Dhat)
+    assert abs(total - ld_block) < 1e-8
