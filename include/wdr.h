@@ -19,7 +19,9 @@
  *                                      + (1 + g_mu) U_mu(x-mu)^+ psi(x-mu)]
  * chiral basis, g_k = [[0, -i s_k], [i s_k, 0]] (mu = 0,1,2 -> k = 1,2,3),
  * g_4 = [[0, 1], [1, 0]] (mu = 3), g_5 = diag(1, 1, -1, -1); a hop that wraps
- * around the lattice in direction mu is multiplied by bc[mu] (+1 or -1).
+ * around the lattice in direction mu is multiplied by bc[mu]: +1 periodic,
+ * -1 antiperiodic, 0 open (the hop is dropped, so the lattice operator is
+ * the Dirichlet operator of a block with these extents, paper Sec. 3).
  *
  * Memory: pointers named dev_* are device memory owned by the caller
  * (e.g. a torch tensor's data pointer); host_* are host memory.  Contexts
@@ -133,7 +135,8 @@ void wdr_default_solver_params(wdr_solver_params *out);
 
 /* Create a context for one lattice geometry on HIP device `device`.  Builds
  * the site ordering of Sec. 3 (black blocks first) and workspaces.
- * EINVAL for non-positive or non-dividing extents, odd B[mu], bc not +-1. */
+ * EINVAL for non-positive or non-dividing extents, odd B[mu], bc not in
+ * {-1, 0, 1}. */
 wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out);
 wdr_status wdr_ctx_destroy(wdr_ctx *ctx);
 
@@ -300,6 +303,30 @@ wdr_status wdr_block_logdet(wdr_ctx *ctx, const wdr_gauge *U, double kappa, int3
  * fields in one batch.  Errors as wdr_block_logdet. */
 wdr_status wdr_block_logdet_ratio(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *Up, double kappa,
                                   int32_t max_blocks, double *host_out, void *stream);
+
+/* Links of every block of ctx as a lattice of its own: dev_out[b] (b by
+ * lexicographic block id) is a canonical gauge field of extents B (the
+ * block's sites in lexicographic order, all four links of each site, the
+ * links leaving the block included), nblocks x V_b x 36 complex.  The
+ * boundary phases of ctx are not applied.  For a context with extents B and
+ * open boundaries these are the fields whose lattice operator is each
+ * block's Dirichlet operator D_b (Sec. 3). */
+wdr_status wdr_block_fields(wdr_ctx *ctx, const wdr_gauge *U, double *dev_out, void *stream);
+
+/* Recursive domain decomposition (Sec. 3, eq. ddrec; the block step 2 of
+ * eq. 4step): for every block b of ctx, the stochastic estimate of
+ *     log det(Dhat_b'^+ Dhat_b') / det(Dhat_b^+ Dhat_b),
+ * Dhat_b the Schur complement of the Dirichlet block operator D_b over
+ * sub-blocks.  `sub` describes one block: L = the blocks' extents of ctx,
+ * bc = 0 in every direction, B = the sub-block extents.  All blocks are
+ * estimated in one batched call on `sub` (wdr_logdet_ratio_batch with
+ * op WDR_OP_SCHUR, which p->op must be); block b uses the noise key
+ * p->seed + b.  host_samples: nblocks x n_steps x n_noise; host_log_ratios:
+ * nblocks; host_info: summed iterations, worst residual.  Needs SU(3) links
+ * or none in both fields; EINVAL for a mismatched `sub`. */
+wdr_status wdr_block_schur_ratio(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *Up, double kappa, wdr_ctx *sub,
+                                 const wdr_est_params *p, double *host_samples, double *host_log_ratios,
+                                 wdr_solve_info *host_info, void *stream);
 
 #ifdef __cplusplus
 }

@@ -182,10 +182,14 @@ wdr_status wdr_interpolate(wdr_ctx *c, const double *U, const double *Up, int32_
     }
     Work a(c, n * sizeof(double2)), b(c, n * sizeof(double2)), o(c, n * sizeof(double2));
     if (!a.ok() || !b.ok() || !o.ok()) return WDR_ENOMEM;
-    launch_pack_gauge<double>(c->g, c->geom.bc, reinterpret_cast<const double2 *>(U), a.as<double2>(), s);
-    launch_pack_gauge<double>(c->g, c->geom.bc, reinterpret_cast<const double2 *>(Up), b.as<double2>(), s);
+    // the path of canonical links does not depend on the boundary phases
+    // (folding a sign in and out commutes with it; an open boundary would
+    // zero the wrapping links), so none are applied here
+    const int unit[4] = {1, 1, 1, 1};
+    launch_pack_gauge<double>(c->g, unit, reinterpret_cast<const double2 *>(U), a.as<double2>(), s);
+    launch_pack_gauge<double>(c->g, unit, reinterpret_cast<const double2 *>(Up), b.as<double2>(), s);
     launch_interpolate(c->g, a.as<double2>(), b.as<double2>(), (double)i / N, o.as<double2>(), s);
-    launch_unpack_gauge(c->g, c->geom.bc, o.as<double2>(), reinterpret_cast<double2 *>(out), s);
+    launch_unpack_gauge(c->g, unit, o.as<double2>(), reinterpret_cast<double2 *>(out), s);
     return finish(s);
 }
 
@@ -550,6 +554,74 @@ wdr_status wdr_block_logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gaug
     std::vector<double> both(2 * (size_t)nb);
     e = block_logdet(c, U, Up, kappa, max_blocks, both.data(), S(stream));
     for (int b = 0; b < nb; ++b) out[b] = both[nb + b] - both[b];
+    return e;
+}
+
+wdr_status wdr_block_fields(wdr_ctx *c, const wdr_gauge *U, double *out, void *stream)
+{
+    wdr_status e = pre(c, U, out);
+    if (e != WDR_OK) return e;
+    if ((e = check_gauge(c, U)) != WDR_OK) return e;
+    launch_block_fields(c->g, c->geom.bc, U->u64, reinterpret_cast<double2 *>(out), S(stream));
+    return finish(S(stream));
+}
+
+wdr_status wdr_block_schur_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, double kappa, wdr_ctx *sub,
+                                 const wdr_est_params *p, double *samples, double *log_ratios, wdr_solve_info *info,
+                                 void *stream)
+{
+    if (check_ctx(c) != WDR_OK || check_ctx(sub) != WDR_OK) return WDR_EINVAL;
+    wdr_status e;
+    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_gauge(c, Up)) != WDR_OK) return e;
+    if ((e = check_kappa(kappa)) != WDR_OK) return e;
+    for (int mu = 0; mu < 4; ++mu)
+        if (sub->geom.L[mu] != c->geom.B[mu] || sub->geom.bc[mu] != 0) {
+            set_error("sub must have the block extents of ctx as its lattice and open boundaries");
+            return WDR_EINVAL;
+        }
+    if (sub->device != c->device) {
+        set_error("sub must live on the device of ctx");
+        return WDR_EINVAL;
+    }
+    if (!p || p->op != WDR_OP_SCHUR) {
+        set_error("the block Schur ratio needs op WDR_OP_SCHUR");
+        return WDR_EINVAL;
+    }
+    if ((e = check_est(sub, p)) != WDR_OK) return e;
+    WDR_HIP(hipSetDevice(c->device));
+    hipStream_t s = S(stream);
+    const double t0 = now();
+    const int nb = c->g.nblk;
+    const size_t per = (size_t)c->g.Vb * 36;
+    Work fw(c, 2 * nb * per * sizeof(double2));
+    if (!fw.ok()) return WDR_ENOMEM;
+    double2 *f0 = fw.as<double2>(), *f1 = f0 + nb * per;
+    launch_block_fields(c->g, c->geom.bc, U->u64, f0, s);
+    launch_block_fields(c->g, c->geom.bc, Up->u64, f1, s);
+    // one proposal per block on `sub`
+    std::vector<wdr_gauge *> hs;
+    auto release = [&] {
+        for (wdr_gauge *h : hs) (void)wdr_gauge_destroy(h);
+    };
+    std::vector<Proposal> props;
+    for (int b = 0; b < nb && e == WDR_OK; ++b) {
+        wdr_gauge *hu = nullptr, *hp = nullptr;
+        e = wdr_gauge_create(sub, reinterpret_cast<const double *>(f0 + b * per), &hu, stream);
+        if (hu) hs.push_back(hu);
+        if (e == WDR_OK) e = wdr_gauge_create(sub, reinterpret_cast<const double *>(f1 + b * per), &hp, stream);
+        if (hp) hs.push_back(hp);
+        if (e == WDR_OK) props.push_back(Proposal{hu, hp, kappa, p->seed + (uint64_t)b});
+    }
+    if (e != WDR_OK) {
+        release();
+        return e;
+    }
+    Stats st;
+    e = logdet_ratio(sub, props, *p, samples, log_ratios, st, s);
+    (void)hipStreamSynchronize(s);
+    fill_info(info, st, now() - t0);
+    release();
+    if (e == WDR_OK) e = finish(s);
     return e;
 }
 

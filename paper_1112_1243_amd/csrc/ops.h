@@ -74,6 +74,7 @@ template <typename T> void launch_unpack_spinor(const Geo &g, const T2<T> *in, d
 template <typename T>
 void launch_pack_gauge(const Geo &g, const int bc[4], const double2 *canon, T2<T> *out, hipStream_t s);
 void launch_unpack_gauge(const Geo &g, const int bc[4], const double2 *in, double2 *canon, hipStream_t s);
+void launch_block_fields(const Geo &g, const int bc[4], const double2 *in, double2 *out, hipStream_t s);
 void launch_convert_gauge_f32(const Geo &g, const double2 *in, float2 *out, hipStream_t s);
 // largest deviation from SU(3) over the links (max |U U^+ - 1|, |det U - 1|,
 // boundary phases divided out); dev_out: one double

@@ -165,8 +165,8 @@ wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)
             set_error("need 0 < B[mu] <= 255, B[mu] even and dividing L[mu]");
             return WDR_EINVAL;
         }
-        if (geom->bc[mu] != 1 && geom->bc[mu] != -1) {
-            set_error("bc[mu] must be +1 or -1");
+        if (geom->bc[mu] < -1 || geom->bc[mu] > 1) {
+            set_error("bc[mu] must be -1, 0 or +1");
             return WDR_EINVAL;
         }
         V *= L;

@@ -112,6 +112,9 @@ def lib():
         L.wdr_autotune.argtypes = [P, P, P, d, ctypes.POINTER(EstParams), ctypes.POINTER(d), P]
         L.wdr_block_logdet.argtypes = [P, P, d, i32, P, P]
         L.wdr_block_logdet_ratio.argtypes = [P, P, P, d, i32, P, P]
+        L.wdr_block_fields.argtypes = [P, P, P, P]
+        L.wdr_block_schur_ratio.argtypes = [P, P, P, d, P, ctypes.POINTER(EstParams), P, P,
+                                            ctypes.POINTER(SolveInfo), P]
         _lib = L
     return _lib
 
@@ -334,6 +337,31 @@ class Context:
         _check(lib().wdr_block_logdet_ratio(self.handle, U.handle, Up.handle, kappa, max_blocks,
                                             out.ctypes.data_as(ctypes.c_void_p), _stream()))
         return out
+
+    def block_fields(self, U: Gauge):
+        """Links of every block as a lattice of the block's extents:
+        [nblocks, V_b, 4, 3, 3] complex128 on the device."""
+        Vb = int(np.prod(self.B))
+        out = self._empty(self.nblocks * Vb, 4, 3, 3).reshape(self.nblocks, Vb, 4, 3, 3)
+        _check(lib().wdr_block_fields(self.handle, U.handle, ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def block_schur_ratio(self, U: Gauge, Up: Gauge, kappa, sub: "Context", n_steps, n_noise, noise, seed,
+                          params: SolverParams, max_batch: int = 0):
+        """Recursive DD: the Schur-complement ratio of every block's Dirichlet
+        operator over the sub-blocks of `sub` (lattice = one block, open
+        boundaries).  Returns (samples [nblocks, n_steps, n_noise], log Rhat
+        [nblocks], info)."""
+        ep = EstParams()
+        ep.op, ep.n_steps, ep.n_noise, ep.noise, ep.seed, ep.sp = OP_SCHUR, n_steps, n_noise, noise, seed, params
+        ep.max_batch = max_batch
+        samples = np.zeros((self.nblocks, n_steps, n_noise), dtype=np.float64)
+        lrs = np.zeros(self.nblocks, dtype=np.float64)
+        info = SolveInfo()
+        _check(lib().wdr_block_schur_ratio(self.handle, U.handle, Up.handle, kappa, sub.handle, ctypes.byref(ep),
+                                           samples.ctypes.data_as(ctypes.c_void_p),
+                                           lrs.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info), _stream()))
+        return samples, lrs, info
 
     def logdet_ratio(self, U: Gauge, Up: Gauge, kappa, op, n_steps, n_noise, noise, seed, params: SolverParams,
                      max_batch: int = 0):
