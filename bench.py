@@ -60,10 +60,13 @@ def make_inputs(wl):
 def proposal_mask(ctx, rule):
     """[site, mu] mask of the links a proposal redraws, from the library's
     geometry maps: 'active' = the active links of every block (both ends in
-    the block, at most one on its boundary); 'black_blocks' = every link with
-    both ends in the same black block."""
+    the block, at most one on its boundary); 'core6' = the same for the core
+    of every block without its outer layer (6^4 in 8^4 blocks); 'black_blocks'
+    = every link with both ends in the same black block."""
     if rule == "active":
         return ctx.active_links(0, ctx.B[0] - 1).cpu().numpy().astype(bool)
+    if rule == "core6":
+        return ctx.active_links(1, ctx.B[0] - 2).cpu().numpy().astype(bool)
     assert rule == "black_blocks"
     bid, col, _, _ = [t.cpu().numpy() for t in ctx.site_maps()]
     L = ctx.L
@@ -118,6 +121,53 @@ def dd_workload(wdr, torch, name):
             "cg_iterations_total": int(info_m.total_iters),
             "fp64_estimates_per_s": round(1.0 / t_p, 4), "speedup_vs_fp64": round(t_p / t_m, 2),
             "max_abs_sample_diff_vs_fp64": float("%.3e" % float(np.abs(s_m - s_p).max()))}
+
+
+def recursive_dd(wdr, torch):
+    """Recursive DD (Sec. 3 eq. ddrec, the block step 2 of eq. 4step) in the
+    block geometry of the paper's realistic run (Sec. 6): the Schur ratio of
+    each of the 16 8^4 blocks of a 16^4 lattice over its 4^4 sub-blocks, one
+    wdr_block_schur_ratio call; mixed form (CGNE with FP32 iterations and
+    FP64 reliable updates, FP16 sub-block solves, all blocks and factors
+    batched) against the plain FP64 form (one sample at a time)."""
+    from paper_1112_1243_amd import synth
+    w = synth.WORKLOADS["recursive16_dd8"]
+    t0 = time.perf_counter()
+    ctx = wdr.Context(w["L"], w["B"])
+    sub = wdr.Context(w["B"], w["Bsub"], (0, 0, 0, 0))
+    U = synth.gauge_field(w["L"], w["scale"], w["seed"])
+    mask = proposal_mask(ctx, w["proposal"])
+    Up = synth.redraw(U, mask, w["scale"], w["seed"])
+    gU, gUp = ctx.gauge(torch.from_numpy(U).cuda()), ctx.gauge(torch.from_numpy(Up).cuda())
+    del U, Up
+    log("recursive16_dd8: inputs ready in %.1f s" % (time.perf_counter() - t0))
+    N = w["n_noise"]
+    mixed = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F16, max_iter=20000)
+    plain = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F64, max_iter=20000)
+    ctx.block_schur_ratio(gU, gUp, w["kappa"], sub, 1, 1, wdr.NOISE_GAUSS, 1, mixed)  # warm-up
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s_m, lr_m, info_m = ctx.block_schur_ratio(gU, gUp, w["kappa"], sub, N, 1, wdr.NOISE_GAUSS, w["seed"], mixed)
+    t_m = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    s_p, lr_p, info_p = ctx.block_schur_ratio(gU, gUp, w["kappa"], sub, N, 1, wdr.NOISE_GAUSS, w["seed"], plain,
+                                              max_batch=1)
+    t_p = time.perf_counter() - t1
+    log("recursive16_dd8: mixed %.3f s (CG its %d), plain fp64 %.3f s, max |ds| %.2e"
+        % (t_m, info_m.total_iters, t_p, float(np.abs(s_m - s_p).max())))
+    nb = ctx.nblocks
+    del gU, gUp
+    ctx.close()
+    sub.close()
+    return {"workload": "recursive16_dd8: 16^4 lattice, 16 blocks of 8^4 with open boundaries, 4^4 sub-blocks, "
+                        "kappa %.3f, links exp(i %.2f H), links of the 6^4 core of every block redrawn (%.1f%%), "
+                        "Schur ratio of every block, N=%d factors x 1 Gaussian noise, CGNE to 1e-10"
+                        % (w["kappa"], w["scale"], 100 * float(mask.mean()), N),
+            "value": round(nb / t_m, 2), "unit": "block Schur ratios/s", "seconds": round(t_m, 4),
+            "converged": bool(info_m.converged), "cg_iterations_total": int(info_m.total_iters),
+            "fp64_ratios_per_s": round(nb / t_p, 2), "speedup_vs_fp64": round(t_p / t_m, 2),
+            "max_abs_sample_diff_vs_fp64": float("%.3e" % float(np.abs(s_m - s_p).max())),
+            "sum_log_ratio": float(np.sum(lr_m))}
 
 
 def estimate(ctx, wdr, gU, gUp, wl, params, seed):
@@ -412,6 +462,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-proposal workload")
     ap.add_argument("--no-large", action="store_true", help="skip the 16^4 and 32^4 workloads")
     ap.add_argument("--no-blockdet", action="store_true", help="skip the exact block determinants")
+    ap.add_argument("--no-recursive", action="store_true", help="skip the recursive-DD workload")
     ap.add_argument("--rocprof-summary", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     args = ap.parse_args()
     if args.rocprof_summary:
@@ -490,6 +541,9 @@ def main():
         large = {name: dd_workload(wdr, torch, name) for name in ("wilson16_dd256", "wilson32_dd4096")}
 
     bdet = None if args.no_blockdet else block_determinants(wdr, torch)
+    rdd = None if args.no_recursive else recursive_dd(wdr, torch)
+    if rdd:
+        log("recursive dd:", rdd)
 
     cpu = None if args.no_cpu else cpu_baseline(wl, U, Up)
     if cpu:
@@ -521,6 +575,7 @@ def main():
         "batched_proposals": batch,
         "large_lattices": large,
         "block_determinants": bdet,
+        "recursive_dd": rdd,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

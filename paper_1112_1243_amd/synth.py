@@ -82,7 +82,7 @@ def spinor(L, seed: int, tag: int = 7) -> np.ndarray:
 
 
 # Workloads: lattice, blocks, kappa, link scale, noise and solver settings of
-# the five standard cases.  "seed" keys the Philox streams above.
+# the standard cases.  "seed" keys the Philox streams above.
 WORKLOADS = {
     "wilson4_full_z2": dict(L=(4, 4, 4, 4), B=(2, 2, 2, 2), kappa=0.12, scale=0.3, op="full", noise="z2",
                             n_noise=12, proposal="bernoulli", p=0.10, seed=1112124300),
@@ -92,6 +92,10 @@ WORKLOADS = {
                            noise="gauss", n_noise=16, proposal="black_blocks", seed=1112124302),
     "wilson32_dd4096": dict(L=(32, 32, 32, 32), B=(4, 4, 4, 4), kappa=0.155, scale=0.2, op="schur",
                             noise="gauss", n_noise=32, proposal="active", seed=1112124303),
+    # recursive DD in the block geometry of the paper's realistic run: 8^4
+    # blocks with 4^4 sub-blocks, links of a 6^4 core redrawn in every block
+    "recursive16_dd8": dict(L=(16, 16, 16, 16), B=(8, 8, 8, 8), Bsub=(4, 4, 4, 4), kappa=0.150, scale=0.25,
+                            op="schur", noise="gauss", n_noise=8, proposal="core6", seed=1112124304),
 }
 
 # batched proposals of uneven sizes: (lattice, count); 4^4 blocks (12^4 has 3
