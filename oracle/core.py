@@ -23,7 +23,12 @@ Pins (tests under ``tests/test_oracle_*.py``):
   * log ratio         exact dense log R; sum of factor log dets (eq. param)
   * block log dets    per-block slices of the dense D_bb + D_ww; eq. ddfactor
                       with the dense Schur complement; small-kappa plaquette
-                      expansion (closed form); gauge invariance; locality
+                      expansion (closed form); gauge invariance; locality;
+                      open boundaries = Dirichlet block; eq. ddrec
+  * heat-bath         Kennedy-Pendleton a0 moments vs Bessel ratio and
+                      quadrature; one-link fixed point vs a reweighted Haar
+                      integral; SU(3) kept, unmasked links untouched;
+                      strong-coupling plaquette beta/18 + beta^2/216
 """
 from __future__ import annotations
 
@@ -538,3 +543,152 @@ def site_dofs(mask: np.ndarray) -> np.ndarray:
     """Indices of the 12 components of every site where mask is true."""
     s = np.nonzero(mask)[0]
     return (12 * s[:, None] + np.arange(12)[None, :]).ravel()
+
+
+# ----------------------------------------------------------------------------
+# Gauge update and hierarchical filter (Sec. 2 hierarchical acceptance steps;
+# Sec. 3 eq. 4step; Sec. 5: heat-bath of the active links with the Wilson
+# plaquette action, block acceptance with the exact block determinants,
+# global acceptance with the stochastic Schur-complement estimate)
+
+HB_TAG, ACC_TAG, HB_TRIALS = 5, 6, 64
+SUBGROUPS = ((0, 1), (0, 2), (1, 2))
+
+
+def uniforms(words) -> np.ndarray:
+    """53-bit uniforms in (0, 1) from Philox words (as for the noise)."""
+    w = np.asarray(words, dtype=np.uint64) >> np.uint64(11)
+    return (w.astype(np.float64) + 0.5) * 2.0 ** -53
+
+
+def kp_a0(alpha, u):
+    """One trial of Kennedy and Pendleton (Phys. Lett. B 156 (1985) 393) for
+    a0 with density sqrt(1 - a0^2) exp(alpha a0) on [-1, 1], from four
+    uniforms u[0..3] (arrays allowed): returns (accepted, a0)."""
+    x = -(np.log(u[0]) + np.cos(2.0 * np.pi * u[1]) ** 2 * np.log(u[2])) / alpha
+    return u[3] * u[3] <= 1.0 - 0.5 * x, 1.0 - x
+
+
+def _shift(lat: Lattice, s, mu, d):
+    """Canonical index of the periodic neighbour x + d mu-hat (the gauge action
+    is periodic whatever the fermion boundary phases)."""
+    x = lat.coords()[s].copy()
+    x[mu] = (x[mu] + d) % lat.L[mu]
+    return int(x[0] + lat.L[0] * (x[1] + lat.L[1] * (x[2] + lat.L[2] * x[3])))
+
+
+def staple(lat: Lattice, U, s, mu) -> np.ndarray:
+    """A with Re tr(U_mu(x) A) the sum of the six plaquettes through the link."""
+    dag = lambda m: m.conj().T
+    A = np.zeros((3, 3), dtype=np.complex128)
+    xm = _shift(lat, s, mu, 1)
+    for nu in range(4):
+        if nu == mu:
+            continue
+        xn = _shift(lat, s, nu, 1)
+        xd = _shift(lat, s, nu, -1)
+        xmd = _shift(lat, xm, nu, -1)
+        A += U[xm, nu] @ dag(U[xn, mu]) @ dag(U[s, nu])
+        A += dag(U[xmd, nu]) @ dag(U[xd, mu]) @ U[xd, nu]
+    return A
+
+
+def heatbath_link(u, A, beta: float, seed: int, site: int, mu: int, sweep: int) -> np.ndarray:
+    """Cabibbo-Marinari heat-bath update (Phys. Lett. B 119 (1982) 387) of
+    one link u with staple sum A for the Wilson plaquette action (Sec. 5):
+    the SU(2) subgroups (0,1), (0,2), (1,2) in turn.  Subgroup g: W = u A
+    restricted to the subgroup is k v with v in SU(2); Y with density
+    exp(2 beta k y0 / 3) (Kennedy-Pendleton a0, isotropic direction) gives
+    X = Y v^+ and u <- X u.  Random numbers: Philox4x64-10, key (seed, 5),
+    counter (site, sweep 2^32 + mu 2^8 + g, trial, j): j = 0 the four
+    uniforms of a Kennedy-Pendleton trial, j = 1 cos(theta) = 2 u - 1 and
+    phi = 2 pi u' of the accepted trial.  A subgroup that rejects HB_TRIALS
+    trials stays unchanged."""
+    u = np.array(u, dtype=np.complex128, copy=True)
+    for g, (i, j) in enumerate(SUBGROUPS):
+        W = u @ A
+        a = 0.5 * (W[i, i] + np.conj(W[j, j]))
+        b = 0.5 * (W[i, j] - np.conj(W[j, i]))
+        k = np.sqrt(abs(a) ** 2 + abs(b) ** 2)
+        alpha = 2.0 * beta * k / 3.0
+        ctr1 = (int(sweep) << 32) | (mu << 8) | g
+        a0 = None
+        for t in range(HB_TRIALS):
+            ok, x0 = kp_a0(alpha, uniforms(philox4x64_10((site, ctr1, t, 0), (seed, HB_TAG))))
+            if ok:
+                a0 = x0
+                break
+        if a0 is None:
+            continue
+        w = uniforms(philox4x64_10((site, ctr1, t, 1), (seed, HB_TAG)))
+        c, phi = 2.0 * w[0] - 1.0, 2.0 * np.pi * w[1]
+        r = np.sqrt(max(0.0, 1.0 - a0 * a0))
+        sn = np.sqrt(max(0.0, 1.0 - c * c))
+        y1, y2, y3 = r * sn * np.cos(phi), r * sn * np.sin(phi), r * c
+        Y = np.array([[a0 + 1j * y3, y2 + 1j * y1], [-y2 + 1j * y1, a0 - 1j * y3]])
+        v = np.array([[a, b], [-np.conj(b), np.conj(a)]]) / k
+        E = np.eye(3, dtype=np.complex128)
+        E[np.ix_((i, j), (i, j))] = Y @ v.conj().T
+        u = E @ u
+    return u
+
+
+def heatbath(lat: Lattice, U, beta: float, mask, seed: int, sweep: int) -> np.ndarray:
+    """One heat-bath sweep of the links where mask[site, mu] is true
+    (heatbath_link): mu = 0..3, within each the sites of even then odd
+    parity; links of one such class share no plaquette, so their order does
+    not matter."""
+    U = np.array(U, dtype=np.complex128, copy=True)
+    par = lat.coords().sum(axis=1) & 1
+    for mu in range(4):
+        for p in (0, 1):
+            for s in np.nonzero(np.asarray(mask)[:, mu] & (par == p))[0]:
+                U[s, mu] = heatbath_link(U[s, mu], staple(lat, U, s, mu), beta, seed, int(s), mu, sweep)
+    return U
+
+
+def plaquette(lat: Lattice, U) -> float:
+    """Mean of Re tr U_P / 3 over all plaquettes (periodic)."""
+    tot = 0.0
+    for s in range(lat.V):
+        for mu in range(4):
+            xm = _shift(lat, s, mu, 1)
+            for nu in range(mu + 1, 4):
+                xn = _shift(lat, s, nu, 1)
+                P = U[s, mu] @ U[xm, nu] @ U[xn, mu].conj().T @ U[s, nu].conj().T
+                tot += np.trace(P).real / 3.0
+    return tot / (6 * lat.V)
+
+
+def accept(r: float, u: float) -> bool:
+    """Metropolis decision with probability min(1, exp(r)) (Sec. 2)."""
+    return bool(r >= 0.0 or u < np.exp(r))
+
+
+def filter_step(lat: Lattice, U, beta: float, kappa: float, mask, n_block_steps: int, n_steps: int, n_noise: int,
+                seed: int, est_seed: int):
+    """eq. 4step with one level: the three-step algorithm of Sec. 5.
+    n_block_steps times: a heat-bath sweep of the masked links (step 0),
+    then every block accepted with probability min(1, det(D_b'^+ D_b') /
+    det(D_b^+ D_b)) from the exact block determinants (step 1, uniform from
+    Philox key (seed, 6), counter (block, step, 0, 0)).  Then the result U'
+    is accepted with probability min(1, exp(log Rhat)), log Rhat the
+    stochastic estimate of the Schur-complement ratio from U to U' (Sec. 4:
+    n_steps factors x n_noise Gaussian noise vectors, key est_seed; uniform
+    from counter (0, 0, 1, 0)).  The mask must hold links with both ends in
+    one block.  Returns (field, block accepts [n_block_steps, nblocks],
+    log Rhat, global accept)."""
+    bid, _, _ = lat.maps()
+    cur = np.array(U, dtype=np.complex128, copy=True)
+    acc = np.zeros((n_block_steps, lat.nblocks), dtype=bool)
+    for st in range(n_block_steps):
+        prop = heatbath(lat, cur, beta, mask, seed, st)
+        r = block_log_dets(lat, prop, kappa) - block_log_dets(lat, cur, kappa)
+        for b in range(lat.nblocks):
+            acc[st, b] = accept(r[b], uniforms(philox4x64_10((b, st, 0, 0), (seed, ACC_TAG)))[0])
+        take = acc[st][bid]
+        cur = np.where(take[:, None, None, None], prop, cur)
+    _, lr = logdet_ratio(lat, U, cur, kappa, OP_SCHUR, n_steps, n_noise, NOISE_GAUSS, est_seed)
+    log_r = float(np.sum(lr))
+    ok = accept(log_r, uniforms(philox4x64_10((0, 0, 1, 0), (seed, ACC_TAG)))[0])
+    return (cur if ok else np.array(U, dtype=np.complex128, copy=True)), acc, log_r, ok

@@ -1,0 +1,99 @@
+"""Pins of the oracle's gauge update (the heat-bath of step 0 of eq. 4step
+with the Wilson plaquette action, paper Sec. 5) and of its filter step."""
+import numpy as np
+import pytest
+from scipy import integrate, special, stats
+
+import oracle
+from paper_1112_1243_amd import synth
+
+
+@pytest.mark.parametrize("alpha", [0.7, 3.0, 12.0])
+def test_kennedy_pendleton_moments(alpha):
+    """Accepted a0 follow sqrt(1 - a0^2) exp(alpha a0): mean I_2/I_1 (Bessel)
+    and second moment by quadrature, within 5 standard errors."""
+    u = np.random.default_rng(17).random((4, 400000))
+    u = 1.0 - u  # (0, 1]
+    ok, a0 = oracle.kp_a0(alpha, u)
+    a0 = a0[ok]
+    assert ok.mean() > 0.3  # the method is least efficient at small alpha
+    dens = lambda x: np.sqrt(1 - x * x) * np.exp(alpha * x)
+    z = integrate.quad(dens, -1, 1)[0]
+    m2 = integrate.quad(lambda x: x * x * dens(x), -1, 1)[0] / z
+    m1 = special.iv(2, alpha) / special.iv(1, alpha)
+    se = a0.std() / np.sqrt(len(a0))
+    assert abs(a0.mean() - m1) < 5 * se
+    assert abs((a0 * a0).mean() - m2) < 5 * (a0 * a0).std() / np.sqrt(len(a0))
+    assert a0.min() >= -1.0 and a0.max() <= 1.0
+
+
+def test_one_link_fixed_point():
+    """Repeated heat-bath updates of one link with a fixed staple sample
+    exp(beta Re tr(U A) / 3) dU: the chain average of Re tr(U A) / 3 equals
+    the Haar integral, estimated by reweighting Haar-random SU(3) matrices."""
+    beta = 1.5
+    A = synth.gauge_field((1, 1, 1, 1), 0.8, 71)[0, :3].sum(axis=0)
+    u = np.eye(3, dtype=np.complex128)
+    vals = []
+    for sw in range(6000):
+        u = oracle.heatbath_link(u, A, beta, 72, 5, 1, sw)
+        vals.append(np.trace(u @ A).real / 3.0)
+    vals = np.array(vals[100:])
+    H = stats.unitary_group.rvs(3, size=200000, random_state=73)
+    H = H / np.linalg.det(H)[:, None, None] ** (1.0 / 3.0)  # Haar on SU(3)
+    f = np.einsum("nab,ba->n", H, A).real / 3.0
+    w = np.exp(beta * f)
+    want = np.sum(f * w) / np.sum(w)
+    # chain error with a generous allowance for autocorrelation
+    assert abs(vals.mean() - want) < 6 * vals.std() / np.sqrt(len(vals) / 4)
+    assert abs(np.linalg.det(u) - 1) < 1e-12
+
+
+def test_sweep_keeps_su3_and_the_mask():
+    lat = oracle.Lattice((4, 4, 4, 4), B=(2, 2, 2, 2))
+    U = synth.gauge_field(lat.L, 0.5, 74)
+    mask = synth.bernoulli_links(lat.L, 0.3, 75)
+    V = oracle.heatbath(lat, U, 5.8, mask, 76, 0)
+    assert np.array_equal(V[~mask], U[~mask])
+    W = V[mask]
+    assert np.abs(np.einsum("nab,ncb->nac", W, W.conj()) - np.eye(3)).max() < 1e-12
+    assert np.abs(np.linalg.det(W) - 1).max() < 1e-12
+    assert np.abs(W - U[mask]).min() > 1e-6  # every masked link moved
+
+
+def test_strong_coupling_plaquette():
+    """At small beta, <Re tr U_P / 3> = beta/18 + beta^2/216 + O(beta^3)
+    (character expansion with Haar integrals of SU(3))."""
+    lat = oracle.Lattice((4, 4, 4, 4), B=(2, 2, 2, 2))
+    U = synth.gauge_field(lat.L, 3.0, 77)
+    mask = np.ones((lat.V, 4), bool)
+    beta, ps = 1.0, []
+    for sw in range(25):
+        U = oracle.heatbath(lat, U, beta, mask, 78, sw)
+        if sw >= 5:
+            ps.append(oracle.plaquette(lat, U))
+    assert abs(np.mean(ps) - (beta / 18 + beta ** 2 / 216)) < 0.005
+
+
+def test_filter_step_structure():
+    """Accepted blocks take the heat-bath proposal, rejected ones keep their
+    links; with nothing to update the step changes nothing and is accepted."""
+    lat = oracle.Lattice((4, 4, 4, 4), B=(2, 2, 2, 2))
+    U = synth.gauge_field(lat.L, 0.5, 79)
+    bid, _, _ = lat.maps()
+    x = lat.coords()
+    inside = np.zeros((lat.V, 4), bool)
+    for mu in range(4):
+        y = x.copy()
+        y[:, mu] = (y[:, mu] + 1) % lat.L[mu]
+        inside[:, mu] = bid == bid[y[:, 0] + 4 * (y[:, 1] + 4 * (y[:, 2] + 4 * y[:, 3]))]
+    V, acc, log_r, ok = oracle.filter_step(lat, U, 5.8, 0.12, inside, 1, 1, 1, 80, 81)
+    prop = oracle.heatbath(lat, U, 5.8, inside, 80, 0)
+    assert 0 < acc.sum() < lat.nblocks
+    if ok:
+        take = acc[0][bid]
+        assert np.array_equal(V[take], prop[take]) and np.array_equal(V[~take], U[~take])
+    else:
+        assert np.array_equal(V, U)
+    V, acc, log_r, ok = oracle.filter_step(lat, U, 5.8, 0.12, np.zeros((lat.V, 4), bool), 1, 1, 1, 80, 81)
+    assert ok and log_r == 0.0 and acc.all() and np.array_equal(V, U)
