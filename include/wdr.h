@@ -328,6 +328,44 @@ wdr_status wdr_block_schur_ratio(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gau
                                  const wdr_est_params *p, double *host_samples, double *host_log_ratios,
                                  wdr_solve_info *host_info, void *stream);
 
+/* Heat-bath sweep of the links marked in dev_mask (V x 4 bytes, entry
+ * 4 site + mu, canonical site order) of the canonical field dev_U, in place,
+ * for the Wilson plaquette action beta sum_P (1 - Re tr U_P / 3) (paper
+ * Sec. 5; the gauge update of step 0 of eq. 4step).  Directions mu = 0..3,
+ * within each the sites of even then odd parity; each link takes the
+ * Cabibbo-Marinari steps over the SU(2) subgroups (0,1), (0,2), (1,2) with
+ * Kennedy-Pendleton sampling.  Random numbers: Philox4x64-10, key (seed, 5),
+ * counter (site, sweep 2^32 + mu 2^8 + subgroup, trial, j), uniforms
+ * ((w >> 11) + 1/2) 2^-53; j = 0 holds the four uniforms of a trial, j = 1
+ * the direction of the accepted one; a subgroup that rejects 64 trials
+ * stays unchanged.  Plaquettes are periodic whatever bc. */
+wdr_status wdr_heatbath(wdr_ctx *ctx, double beta, const uint8_t *dev_mask, uint64_t seed, int32_t sweep,
+                        double *dev_U, void *stream);
+
+typedef struct wdr_filter_info {
+    int32_t block_accepts; /* accepted blocks, summed over the block steps */
+    int32_t block_trials;  /* n_block_steps x nblocks */
+    int32_t accepted;      /* the global step accepted the result */
+    int32_t pad;
+    double log_ratio;      /* the global estimate log Rhat */
+} wdr_filter_info;
+
+/* One step of the hierarchical filter, eq. 4step with one level (the
+ * three-step algorithm of paper Sec. 5), on the canonical field dev_U in
+ * place.  n_block_steps times: a heat-bath sweep of the masked links (sweep
+ * index = step), then each block accepted with probability
+ * min(1, exp(r_b)), r_b = log det(D_b'^+ D_b') - log det(D_b^+ D_b) from the
+ * exact block determinants (uniform from Philox key (seed, 6), counter
+ * (block, step, 0, 0)); rejected blocks keep their links.  Then the result
+ * is accepted with probability min(1, exp(log Rhat)), log Rhat the estimate
+ * of *p (op WDR_OP_SCHUR) from the field before the step to the result
+ * (uniform from counter (0, 0, 1, 0)); a rejected step restores dev_U.
+ * host_accepts (NULL allowed): n_block_steps x nblocks block decisions.
+ * EINVAL if the mask holds a link that leaves its block. */
+wdr_status wdr_filter_step(wdr_ctx *ctx, double beta, double kappa, const uint8_t *dev_mask, int32_t n_block_steps,
+                           const wdr_est_params *p, uint64_t seed, double *dev_U, uint8_t *host_accepts,
+                           wdr_filter_info *host_info, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -625,4 +625,56 @@ wdr_status wdr_block_schur_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge
     return e;
 }
 
+wdr_status wdr_heatbath(wdr_ctx *c, double beta, const uint8_t *mask, uint64_t seed, int32_t sweep, double *U,
+                        void *stream)
+{
+    wdr_status e = pre(c, mask, U);
+    if (e != WDR_OK) return e;
+    if (!(beta > 0) || !std::isfinite(beta) || sweep < 0) {
+        set_error("need beta > 0 and sweep >= 0");
+        return WDR_EINVAL;
+    }
+    launch_heatbath(c, beta, mask, seed, sweep, reinterpret_cast<double2 *>(U), S(stream));
+    return finish(S(stream));
+}
+
+wdr_status wdr_filter_step(wdr_ctx *c, double beta, double kappa, const uint8_t *mask, int32_t n_block_steps,
+                           const wdr_est_params *p, uint64_t seed, double *U, uint8_t *accepts,
+                           wdr_filter_info *info, void *stream)
+{
+    wdr_status e = pre(c, mask, U);
+    if (e != WDR_OK) return e;
+    if ((e = check_kappa(kappa)) != WDR_OK) return e;
+    if (!(beta > 0) || !std::isfinite(beta) || n_block_steps < 0 || !info) {
+        set_error("need beta > 0, n_block_steps >= 0 and an info pointer");
+        return WDR_EINVAL;
+    }
+    if (!p || p->op != WDR_OP_SCHUR) {
+        set_error("the global step needs op WDR_OP_SCHUR");
+        return WDR_EINVAL;
+    }
+    if ((e = check_est(c, p)) != WDR_OK) return e;
+    if ((e = check_blocks_usable(c, true)) != WDR_OK) return e;
+    // every masked link must have both ends in one block
+    const Geo &g = c->g;
+    std::vector<uint8_t> hm((size_t)g.V * 4);
+    WDR_HIP(hipMemcpyAsync(hm.data(), mask, hm.size(), hipMemcpyDeviceToHost, S(stream)));
+    WDR_HIP(hipStreamSynchronize(S(stream)));
+    for (long s = 0; s < g.V; ++s) {
+        long r = s;
+        for (int mu = 0; mu < 4; ++mu) {
+            const int x = (int)(r % g.L[mu]);
+            r /= g.L[mu];
+            if (hm[s * 4 + mu] && x % g.B[mu] == g.B[mu] - 1) {
+                set_error("the mask holds a link that leaves its block");
+                return WDR_EINVAL;
+            }
+        }
+    }
+    e = filter_step(c, beta, kappa, mask, n_block_steps, *p, seed, reinterpret_cast<double2 *>(U), accepts, *info,
+                    S(stream));
+    if (e == WDR_OK) e = finish(S(stream));
+    return e;
+}
+
 }  // extern "C"

@@ -4,30 +4,13 @@
 // Noise (paper Sec. 4: a complex Gaussian vector, fresh for every factor of
 // eq. param): Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
 // counter (canonical site, path step, sample, j) and key (seed, 3).
+#include "philox.h"
 #include "stencil.h"
 
 namespace wdr {
 namespace {
 
 using namespace dev;
-
-__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
-{
-    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
-        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
-        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-        k0 += W0;
-        k1 += W1;
-    }
-}
 
 __device__ __forceinline__ long canon_of(const Geo &g, int slot, int l, int x[4])
 {

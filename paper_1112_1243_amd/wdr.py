@@ -44,6 +44,14 @@ class SolveInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class FilterInfo(ctypes.Structure):
+    _fields_ = [("block_accepts", ctypes.c_int32), ("block_trials", ctypes.c_int32), ("accepted", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("log_ratio", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 class EstParams(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int), ("n_steps", ctypes.c_int32), ("n_noise", ctypes.c_int32),
                 ("noise", ctypes.c_int), ("seed", ctypes.c_uint64), ("sp", SolverParams),
@@ -113,6 +121,9 @@ def lib():
         L.wdr_block_logdet.argtypes = [P, P, d, i32, P, P]
         L.wdr_block_logdet_ratio.argtypes = [P, P, P, d, i32, P, P]
         L.wdr_block_fields.argtypes = [P, P, P, P]
+        L.wdr_heatbath.argtypes = [P, d, P, ctypes.c_uint64, i32, P, P]
+        L.wdr_filter_step.argtypes = [P, d, d, P, i32, ctypes.POINTER(EstParams), ctypes.c_uint64, P, P,
+                                      ctypes.POINTER(FilterInfo), P]
         L.wdr_block_schur_ratio.argtypes = [P, P, P, d, P, ctypes.POINTER(EstParams), P, P,
                                             ctypes.POINTER(SolveInfo), P]
         _lib = L
@@ -337,6 +348,27 @@ class Context:
         _check(lib().wdr_block_logdet_ratio(self.handle, U.handle, Up.handle, kappa, max_blocks,
                                             out.ctypes.data_as(ctypes.c_void_p), _stream()))
         return out
+
+    def heatbath(self, beta, mask, seed, sweep, U):
+        """One heat-bath sweep of the links marked in mask (uint8 [V, 4]) of the
+        canonical field U (complex128 [V, 4, 3, 3] on the device), in place."""
+        _check(lib().wdr_heatbath(self.handle, beta, _dev(mask, (self.V, 4), "uint8"), seed, sweep,
+                                  _dev(U, (self.V, 4, 3, 3)), _stream()))
+        return U
+
+    def filter_step(self, beta, kappa, mask, n_block_steps, n_steps, n_noise, seed, est_seed, params: SolverParams,
+                    U):
+        """One step of the hierarchical filter on U (in place).  Returns (info,
+        block decisions [n_block_steps, nblocks])."""
+        ep = EstParams()
+        ep.op, ep.n_steps, ep.n_noise, ep.noise, ep.seed, ep.sp = OP_SCHUR, n_steps, n_noise, NOISE_GAUSS, est_seed, \
+            params
+        acc = np.zeros((max(n_block_steps, 1), self.nblocks), dtype=np.uint8)
+        info = FilterInfo()
+        _check(lib().wdr_filter_step(self.handle, beta, kappa, _dev(mask, (self.V, 4), "uint8"), n_block_steps,
+                                     ctypes.byref(ep), seed, _dev(U, (self.V, 4, 3, 3)),
+                                     acc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info), _stream()))
+        return info, acc[:n_block_steps].astype(bool)
 
     def block_fields(self, U: Gauge):
         """Links of every block as a lattice of the block's extents:

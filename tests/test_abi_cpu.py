@@ -47,8 +47,8 @@ int main(void) {
          sizeof(wdr_solve_info), sizeof(wdr_est_params), offsetof(wdr_solver_params, tol),
          offsetof(wdr_est_params, sp), offsetof(wdr_solver_params, inner), offsetof(wdr_est_params, max_batch),
          sizeof(wdr_proposal), offsetof(wdr_proposal, kappa), offsetof(wdr_proposal, seed));
-  printf("%zu %zu %zu\n", offsetof(wdr_solver_params, block_mr_steps), offsetof(wdr_solver_params, graph),
-         sizeof(wdr_solver_params));
+  printf("%zu %zu %zu %zu %zu\n", offsetof(wdr_solver_params, block_mr_steps), offsetof(wdr_solver_params, graph),
+         sizeof(wdr_solver_params), offsetof(wdr_filter_info, log_ratio), sizeof(wdr_filter_info));
   return 0;
 }'''
     import tempfile
@@ -62,7 +62,8 @@ int main(void) {
             ctypes.sizeof(wdr.EstParams), wdr.SolverParams.tol.offset, wdr.EstParams.sp.offset,
             wdr.SolverParams.inner.offset, wdr.EstParams.max_batch.offset, ctypes.sizeof(wdr.Proposal),
             wdr.Proposal.kappa.offset, wdr.Proposal.seed.offset, wdr.SolverParams.block_mr_steps.offset,
-            wdr.SolverParams.graph.offset, ctypes.sizeof(wdr.SolverParams)]
+            wdr.SolverParams.graph.offset, ctypes.sizeof(wdr.SolverParams), wdr.FilterInfo.log_ratio.offset,
+            ctypes.sizeof(wdr.FilterInfo)]
     assert vals == want
 
 

@@ -1,0 +1,128 @@
+"""GPU parity of the gauge update (heat-bath of step 0 of eq. 4step, Wilson
+plaquette action, paper Sec. 5) and of one step of the hierarchical filter
+(eq. 4step with one level, the three-step algorithm of Sec. 5) against the
+FP64 oracle through the C ABI.  Both sides draw the same Philox numbers, so
+every Kennedy-Pendleton and Metropolis decision is the same; links agree to
+rounding (1e-12)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1112_1243_amd import synth
+from tests.gpu_util import dev, host, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _wdr():
+    torch_cuda()
+    from paper_1112_1243_amd import wdr
+    return wdr
+
+
+def _in_block_mask(lat):
+    """Every link with both ends in one block."""
+    bid, _, _ = lat.maps()
+    x = lat.coords()
+    m = np.zeros((lat.V, 4), bool)
+    for mu in range(4):
+        y = x.copy()
+        y[:, mu] = (y[:, mu] + 1) % lat.L[mu]
+        t = y[:, 0] + lat.L[0] * (y[:, 1] + lat.L[1] * (y[:, 2] + lat.L[2] * y[:, 3]))
+        m[:, mu] = bid == bid[t]
+    return m
+
+
+def test_heatbath_matches_oracle():
+    """Two sweeps of a random 30% of the links of a 4^4 lattice."""
+    wdr = _wdr()
+    L = (4, 4, 4, 4)
+    ctx, lat = wdr.Context(L, (2, 2, 2, 2)), oracle.Lattice(L, (2, 2, 2, 2))
+    U = synth.gauge_field(L, 0.5, 801)
+    mask = synth.bernoulli_links(L, 0.3, 802)
+    want = U
+    gU, gm = dev(U), dev(mask.astype(np.uint8))
+    for sw in range(2):
+        want = oracle.heatbath(lat, want, 5.8, mask, 803, sw)
+        ctx.heatbath(5.8, gm, 803, sw, gU)
+    got = host(gU)
+    say("heat-bath max |dU|", np.abs(got - want).max())
+    assert np.abs(got - want).max() < 1e-12
+    assert np.array_equal(got[~mask], U[~mask])
+    ctx.close()
+
+
+def test_heatbath_active_links_8x8():
+    """One sweep of the active links of 4^4 blocks on an 8^4 lattice."""
+    wdr = _wdr()
+    L, B = (8, 8, 8, 8), (4, 4, 4, 4)
+    ctx, lat = wdr.Context(L, B), oracle.Lattice(L, B)
+    U = synth.gauge_field(L, 0.5, 804)
+    mask = oracle.active_links(lat)
+    want = oracle.heatbath(lat, U, 5.8, mask, 805, 3)
+    gU = dev(U)
+    ctx.heatbath(5.8, dev(mask.astype(np.uint8)), 805, 3, gU)
+    assert np.abs(host(gU) - want).max() < 1e-12
+    ctx.close()
+
+
+def test_heatbath_full_size_sampled():
+    """16^4, every link: the links of the first class (mu = 0, even sites)
+    are updated once, from the field as it was, so the oracle's one-link
+    update with the original staple is their exact result."""
+    wdr = _wdr()
+    L = (16, 16, 16, 16)
+    ctx, lat = wdr.Context(L, (4, 4, 4, 4)), oracle.Lattice(L, (4, 4, 4, 4))
+    U = synth.gauge_field(L, 0.4, 806)
+    mask = np.ones((lat.V, 4), bool)
+    gU = dev(U)
+    ctx.heatbath(5.8, dev(mask.astype(np.uint8)), 807, 0, gU)
+    got = host(gU)
+    par = lat.coords().sum(axis=1) & 1
+    sites = np.nonzero(par == 0)[0][::2731][:24]
+    for s in sites:
+        want = oracle.heatbath_link(U[s, 0], oracle.staple(lat, U, s, 0), 5.8, 807, int(s), 0, 0)
+        assert np.abs(got[s, 0] - want).max() < 1e-12
+    W = got.reshape(-1, 3, 3)
+    assert np.abs(np.einsum("nab,ncb->nac", W, W.conj()) - np.eye(3)).max() < 1e-12
+    ctx.close()
+
+
+def test_filter_step_matches_oracle():
+    """Two block steps (heat-bath + exact block acceptance) and the global
+    Schur step on a 4^4 lattice with 2^4 blocks, every in-block link in the
+    mask: block decisions, log Rhat, the global decision and the final field
+    equal the oracle's."""
+    wdr = _wdr()
+    L, B = (4, 4, 4, 4), (2, 2, 2, 2)
+    ctx, lat = wdr.Context(L, B), oracle.Lattice(L, B)
+    U = synth.gauge_field(L, 0.5, 808)
+    mask = _in_block_mask(lat)
+    for beta, kappa in ((1.0, 0.16), (5.8, 0.12)):
+        want, acc_w, lr_w, ok_w = oracle.filter_step(lat, U, beta, kappa, mask, 2, 1, 1, 809, 810)
+        gU = dev(U)
+        info, acc = ctx.filter_step(beta, kappa, dev(mask.astype(np.uint8)), 2, 1, 1, 809, 810,
+                                    wdr.default_params(), gU)
+        say("filter beta", beta, "blocks accepted", acc.sum(), "of", acc.size, "log R", info.log_ratio, lr_w,
+            "accepted", info.accepted, ok_w)
+        assert np.array_equal(acc, acc_w)
+        assert abs(info.log_ratio - lr_w) < 1e-8 and bool(info.accepted) == ok_w
+        assert info.block_accepts == acc_w.sum() and info.block_trials == acc_w.size
+        assert np.abs(host(gU) - want).max() < 1e-12
+    ctx.close()
+
+
+def test_filter_errors():
+    wdr = _wdr()
+    L = (8, 8, 8, 8)
+    ctx = wdr.Context(L, (4, 4, 4, 4))
+    U = dev(synth.gauge_field(L, 0.5, 811))
+    bad = np.zeros((ctx.V, 4), np.uint8)
+    bad[3, 0] = 1  # x0 = 3 -> 4 leaves the block
+    with pytest.raises(wdr.WdrError) as e:
+        ctx.filter_step(5.8, 0.13, dev(bad), 1, 1, 1, 1, 2, wdr.default_params(), U)
+    assert e.value.status == wdr.EINVAL
+    with pytest.raises(wdr.WdrError) as e:
+        ctx.heatbath(-1.0, dev(bad), 1, 0, U)
+    assert e.value.status == wdr.EINVAL
+    ctx.close()
