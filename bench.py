@@ -170,6 +170,118 @@ def recursive_dd(wdr, torch):
             "sum_log_ratio": float(np.sum(lr_m))}
 
 
+def plaquette(U, L):
+    """Mean Re tr U_P / 3 of a canonical field (host numpy), a check of the
+    thermalised ensemble (about 0.568 at beta 5.8)."""
+    V = int(np.prod(L))
+    x = np.arange(V)
+    c = [x % L[0], (x // L[0]) % L[1], (x // (L[0] * L[1])) % L[2], x // (L[0] * L[1] * L[2])]
+
+    def up(d):
+        y = [a.copy() for a in c]
+        y[d] = (y[d] + 1) % L[d]
+        return y[0] + L[0] * (y[1] + L[1] * (y[2] + L[2] * y[3]))
+    tot = 0.0
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            P = np.einsum("xab,xbc,xdc,xed->xae", U[:, mu], U[up(mu), nu], U[up(nu), mu].conj(), U[:, nu].conj())
+            tot += np.trace(P, axis1=1, axis2=2).real.mean() / 3
+    return tot / 6
+
+
+def thermalised(wdr, torch, ctx, L, beta, seed, sweeps):
+    """A quenched ensemble member: heat-bath sweeps of every link from the
+    unit field (the paper's runs use beta = 5.8 quenched fields)."""
+    from paper_1112_1243_amd import synth
+    U = torch.from_numpy(synth.unit_gauge(L)).cuda()
+    allm = torch.ones((ctx.V, 4), dtype=torch.uint8, device="cuda")
+    for sw in range(sweeps):
+        ctx.heatbath(beta, allm, seed, sw, U)
+    return U, allm
+
+
+def filter_run(wdr, torch, steps=6):
+    """The three-step algorithm of Sec. 5 (eq. 4step, one level) on an 8^4
+    lattice with 4^4 blocks at the paper's beta = 5.8 and kappa = 0.15462:
+    per filter step two block steps (heat-bath of the active links, exact
+    block acceptance), then the global Schur step with N = 16 factors x 1
+    Gaussian noise.  Starts from a field thermalised by 200 heat-bath sweeps."""
+    L, beta, kappa, seed = (8, 8, 8, 8), 5.8, 0.15462, 1112124305
+    ctx = wdr.Context(L, (4, 4, 4, 4))
+    U, _ = thermalised(wdr, torch, ctx, L, beta, seed, 200)
+    plaq0 = plaquette(U.cpu().numpy(), L)
+    mask = ctx.active_links(0, 3)
+    p = wdr.default_params()
+    ctx.filter_step(beta, kappa, mask, 1, 1, 1, seed + 99, 1, p, U.clone())  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bacc = btri = gacc = 0
+    lrs = []
+    for k in range(steps):
+        info, _ = ctx.filter_step(beta, kappa, mask, 2, 16, 1, seed + 100 + k, seed + 200 + k, p, U)
+        bacc += info.block_accepts
+        btri += info.block_trials
+        gacc += info.accepted
+        lrs.append(info.log_ratio)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    out = {"workload": "8^4 lattice, 16 blocks of 4^4, quenched beta 5.8 field (200 heat-bath sweeps from the "
+                       "unit field), kappa 0.15462; filter step = 2 x (heat-bath of the active links, exact block "
+                       "acceptance) + global Schur acceptance with N=16 x 1 Gaussian noise",
+           "value": round(1.0 / dt, 3), "unit": "filter steps/s", "steps": steps,
+           "block_acceptance": round(bacc / max(btri, 1), 3), "global_accepted": gacc,
+           "global_log_ratios": [round(float(v), 3) for v in lrs], "plaquette_start": round(float(plaq0), 5),
+           "plaquette_end": round(float(plaquette(U.cpu().numpy(), L)), 5)}
+    ctx.close()
+    return out
+
+
+def exact_acceptance(wdr, torch):
+    """The exact acceptance rate of the global step (Sec. 5): for pairs
+    (U, U') of a quenched beta = 5.8 chain (10 heat-bath sweeps apart) and
+    one block step each, the variance over pairs of the global estimate
+    log Rhat for several N, fitted as a + b / N (eq. param: the noise part
+    falls as 1/N); a is the exact variance sigma_2^2 and erfc(sqrt(a / 8))
+    the acceptance (eq. acceptance)."""
+    from scipy import special
+    beta, kappa, seed = 5.8, 0.15462, 1112124305
+    res = {}
+    for L, pairs, Ns in (((8, 8, 8, 8), 48, (4, 8, 16, 32)), ((16, 16, 16, 16), 16, (8, 16, 32, 64))):
+        t0 = time.perf_counter()
+        ctx = wdr.Context(L, (4, 4, 4, 4))
+        U, allm = thermalised(wdr, torch, ctx, L, beta, seed, 200)
+        mask = ctx.active_links(0, 3)
+        p = wdr.default_params()
+        lr = np.zeros((pairs, len(Ns)))
+        bacc = 0.0
+        sw = 200
+        for q in range(pairs):
+            for _ in range(10):
+                ctx.heatbath(beta, allm, seed, sw, U)
+                sw += 1
+            Up = U.clone()
+            _, acc = ctx.filter_step(beta, kappa, mask, 1, 0, 1, seed + 1 + q, 0, p, Up)
+            bacc += acc.mean()
+            gU, gUp = ctx.gauge(U), ctx.gauge(Up)
+            for j, N in enumerate(Ns):
+                _, lr[q, j], _ = ctx.logdet_ratio(gU, gUp, kappa, wdr.OP_SCHUR, N, 1, wdr.NOISE_GAUSS,
+                                                  seed + 1000 * q + N, p)
+            del gU, gUp
+        var = lr.var(axis=0, ddof=1)
+        A = np.vstack([np.ones(len(Ns)), 1.0 / np.array(Ns)]).T
+        a, b = np.linalg.lstsq(A, var, rcond=None)[0]
+        name = "x".join(map(str, L))
+        res[name] = {"pairs": pairs, "N": list(Ns), "var_log_ratio": [round(float(v), 4) for v in var],
+                     "mean_log_ratio": [round(float(v), 4) for v in lr.mean(axis=0)], "fit_a": round(float(a), 4),
+                     "fit_b": round(float(b), 3), "block_acceptance": round(float(bacc) / pairs, 3),
+                     "acceptance_erfc": round(float(special.erfc(np.sqrt(max(a, 0.0) / 8))), 3),
+                     "seconds": round(time.perf_counter() - t0, 2)}
+        log("exact acceptance %s: %s" % (name, res[name]))
+        ctx.close()
+    return {"workload": "quenched beta 5.8 pairs, 4^4 blocks, active links, one block step per pair, kappa "
+                        "0.15462, global Schur estimate with N factors x 1 Gaussian noise", "volumes": res}
+
+
 def estimate(ctx, wdr, gU, gUp, wl, params, seed):
     """One complete estimate: the 16 block ratios and the Schur ratio of the
     factorisation det D = prod_b det D_b det Dhat, in one DD call."""
@@ -463,6 +575,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 16^4 and 32^4 workloads")
     ap.add_argument("--no-blockdet", action="store_true", help="skip the exact block determinants")
     ap.add_argument("--no-recursive", action="store_true", help="skip the recursive-DD workload")
+    ap.add_argument("--no-filter", action="store_true", help="skip the filter and acceptance-rate runs")
     ap.add_argument("--rocprof-summary", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     args = ap.parse_args()
     if args.rocprof_summary:
@@ -544,6 +657,10 @@ def main():
     rdd = None if args.no_recursive else recursive_dd(wdr, torch)
     if rdd:
         log("recursive dd:", rdd)
+    filt = None if args.no_filter else filter_run(wdr, torch)
+    if filt:
+        log("filter:", filt)
+    acc = None if args.no_filter else exact_acceptance(wdr, torch)
 
     cpu = None if args.no_cpu else cpu_baseline(wl, U, Up)
     if cpu:
@@ -576,6 +693,8 @@ def main():
         "large_lattices": large,
         "block_determinants": bdet,
         "recursive_dd": rdd,
+        "filter": filt,
+        "exact_acceptance": acc,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -360,7 +360,9 @@ typedef struct wdr_filter_info {
  * is accepted with probability min(1, exp(log Rhat)), log Rhat the estimate
  * of *p (op WDR_OP_SCHUR) from the field before the step to the result
  * (uniform from counter (0, 0, 1, 0)); a rejected step restores dev_U.
- * host_accepts (NULL allowed): n_block_steps x nblocks block decisions.
+ * p = NULL runs the block steps only and keeps their result (the proposal
+ * the global step would judge).  host_accepts (NULL allowed):
+ * n_block_steps x nblocks block decisions.
  * EINVAL if the mask holds a link that leaves its block. */
 wdr_status wdr_filter_step(wdr_ctx *ctx, double beta, double kappa, const uint8_t *dev_mask, int32_t n_block_steps,
                            const wdr_est_params *p, uint64_t seed, double *dev_U, uint8_t *host_accepts,

@@ -676,8 +676,9 @@ def filter_step(lat: Lattice, U, beta: float, kappa: float, mask, n_block_steps:
     stochastic estimate of the Schur-complement ratio from U to U' (Sec. 4:
     n_steps factors x n_noise Gaussian noise vectors, key est_seed; uniform
     from counter (0, 0, 1, 0)).  The mask must hold links with both ends in
-    one block.  Returns (field, block accepts [n_block_steps, nblocks],
-    log Rhat, global accept)."""
+    one block.  n_steps = 0 runs the block steps only and keeps their
+    result.  Returns (field, block accepts [n_block_steps, nblocks], log Rhat,
+    global accept)."""
     bid, _, _ = lat.maps()
     cur = np.array(U, dtype=np.complex128, copy=True)
     acc = np.zeros((n_block_steps, lat.nblocks), dtype=bool)
@@ -688,6 +689,8 @@ def filter_step(lat: Lattice, U, beta: float, kappa: float, mask, n_block_steps:
             acc[st, b] = accept(r[b], uniforms(philox4x64_10((b, st, 0, 0), (seed, ACC_TAG)))[0])
         take = acc[st][bid]
         cur = np.where(take[:, None, None, None], prop, cur)
+    if n_steps == 0:
+        return cur, acc, 0.0, True
     _, lr = logdet_ratio(lat, U, cur, kappa, OP_SCHUR, n_steps, n_noise, NOISE_GAUSS, est_seed)
     log_r = float(np.sum(lr))
     ok = accept(log_r, uniforms(philox4x64_10((0, 0, 1, 0), (seed, ACC_TAG)))[0])

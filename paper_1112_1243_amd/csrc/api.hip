@@ -649,11 +649,11 @@ wdr_status wdr_filter_step(wdr_ctx *c, double beta, double kappa, const uint8_t 
         set_error("need beta > 0, n_block_steps >= 0 and an info pointer");
         return WDR_EINVAL;
     }
-    if (!p || p->op != WDR_OP_SCHUR) {
+    if (p && p->op != WDR_OP_SCHUR) {
         set_error("the global step needs op WDR_OP_SCHUR");
         return WDR_EINVAL;
     }
-    if ((e = check_est(c, p)) != WDR_OK) return e;
+    if (p && (e = check_est(c, p)) != WDR_OK) return e;
     if ((e = check_blocks_usable(c, true)) != WDR_OK) return e;
     // every masked link must have both ends in one block
     const Geo &g = c->g;
@@ -671,7 +671,7 @@ wdr_status wdr_filter_step(wdr_ctx *c, double beta, double kappa, const uint8_t 
             }
         }
     }
-    e = filter_step(c, beta, kappa, mask, n_block_steps, *p, seed, reinterpret_cast<double2 *>(U), accepts, *info,
+    e = filter_step(c, beta, kappa, mask, n_block_steps, p, seed, reinterpret_cast<double2 *>(U), accepts, *info,
                     S(stream));
     if (e == WDR_OK) e = finish(S(stream));
     return e;

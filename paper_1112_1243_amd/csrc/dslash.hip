@@ -317,31 +317,6 @@ __global__ __launch_bounds__(256) void k_pack_gauge(Geo g, int4 bc, const double
     }
 }
 
-// the links of every block as a canonical field of the block's extents:
-// out[b][site][mu][9], site lexicographic in the block, boundary phases
-// taken out again (an open boundary leaves the wrapping links zero)
-__global__ __launch_bounds__(256) void k_block_fields(Geo g, int4 bc, const double2 *__restrict__ in,
-                                                      double2 *__restrict__ out)
-{
-    const int l = blockIdx.x * 256 + threadIdx.x;
-    if (l >= g.Vb) return;
-    const int slot = blockIdx.y;
-    int x[4];
-    (void)canon_index(g, slot, l, x);
-    const long site = (x[0] % g.B[0]) + (long)g.B[0] * ((x[1] % g.B[1]) + (long)g.B[1] * ((x[2] % g.B[2]) +
-                                                                                       (long)g.B[2] * (x[3] % g.B[3])));
-    double2 *o = out + ((long)g.slot_blk[slot] * g.Vb + site) * 36;
-    const int bcv[4] = {bc.x, bc.y, bc.z, bc.w};
-    for (int mu = 0; mu < 4; ++mu) {
-        const double f = (x[mu] == g.L[mu] - 1) ? (double)bcv[mu] : 1.0;
-        const long base = ((long)slot * 4 + mu) * 9 * g.Vb + l;
-        for (int e = 0; e < 9; ++e) {
-            const double2 v = in[base + (long)e * g.Vb];
-            o[mu * 9 + e] = make_double2(f * v.x, f * v.y);
-        }
-    }
-}
-
 __global__ __launch_bounds__(256) void k_unpack_gauge(Geo g, int4 bc, const double2 *__restrict__ in,
                                                       double2 *__restrict__ canon)
 {
@@ -416,11 +391,6 @@ void launch_pack_gauge(const Geo &g, const int bc[4], const double2 *canon, type
 {
     k_pack_gauge<T><<<dim3((g.Vb + 255) / 256, g.nblk), 256, 0, s>>>(g, make_int4(bc[0], bc[1], bc[2], bc[3]), canon,
                                                                      out);
-}
-void launch_block_fields(const Geo &g, const int bc[4], const double2 *in, double2 *out, hipStream_t s)
-{
-    k_block_fields<<<dim3((g.Vb + 255) / 256, g.nblk), 256, 0, s>>>(g, make_int4(bc[0], bc[1], bc[2], bc[3]), in,
-                                                                    out);
 }
 void launch_unpack_gauge(const Geo &g, const int bc[4], const double2 *in, double2 *canon, hipStream_t s)
 {

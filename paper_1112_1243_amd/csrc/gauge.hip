@@ -180,9 +180,44 @@ __global__ __launch_bounds__(256) void k_merge_blocks(int4 L, int4 B, long V, co
     for (int e = 0; e < 36; ++e) cur[s * 36 + e] = prop[s * 36 + e];
 }
 
+// the links of every block as a canonical field of the block's extents:
+// out[b][site][mu][9], site lexicographic in the block, boundary phases
+// taken out again (an open boundary leaves the wrapping links zero)
+__global__ __launch_bounds__(256) void k_block_fields(Geo g, int4 bc, const double2 *__restrict__ in,
+                                                      double2 *__restrict__ out)
+{
+    const int l = blockIdx.x * 256 + threadIdx.x;
+    if (l >= g.Vb) return;
+    const int slot = blockIdx.y, blk = g.slot_blk[slot];
+    const uint32_t lc = g.loc_coord[l];
+    const int loc[4] = {(int)(lc & 255), (int)((lc >> 8) & 255), (int)((lc >> 16) & 255), (int)(lc >> 24)};
+    int x[4], r = blk;
+    for (int mu = 0; mu < 4; ++mu) {
+        x[mu] = (r % g.NB[mu]) * g.B[mu] + loc[mu];
+        r /= g.NB[mu];
+    }
+    const long site = loc[0] + (long)g.B[0] * (loc[1] + (long)g.B[1] * (loc[2] + (long)g.B[2] * loc[3]));
+    double2 *o = out + ((long)blk * g.Vb + site) * 36;
+    const int bcv[4] = {bc.x, bc.y, bc.z, bc.w};
+    for (int mu = 0; mu < 4; ++mu) {
+        const double f = (x[mu] == g.L[mu] - 1) ? (double)bcv[mu] : 1.0;
+        const long base = ((long)slot * 4 + mu) * 9 * g.Vb + l;
+        for (int e = 0; e < 9; ++e) {
+            const double2 v = in[base + (long)e * g.Vb];
+            o[mu * 9 + e] = make_double2(f * v.x, f * v.y);
+        }
+    }
+}
+
 int4 i4(const int v[4]) { return make_int4(v[0], v[1], v[2], v[3]); }
 
 }  // namespace
+
+void launch_block_fields(const Geo &g, const int bc[4], const double2 *in, double2 *out, hipStream_t s)
+{
+    k_block_fields<<<dim3((g.Vb + 255) / 256, g.nblk), 256, 0, s>>>(g, make_int4(bc[0], bc[1], bc[2], bc[3]), in,
+                                                                    out);
+}
 
 void launch_heatbath(const wdr_ctx *c, double beta, const uint8_t *mask, uint64_t seed, int sweep, double2 *U,
                      hipStream_t s)
@@ -202,7 +237,7 @@ bool accept_metropolis(double r, uint64_t seed, uint64_t c0, uint64_t c1, uint64
 }
 
 wdr_status filter_step(wdr_ctx *c, double beta, double kappa, const uint8_t *mask, int n_block_steps,
-                       const wdr_est_params &p, uint64_t seed, double2 *U, uint8_t *accepts, wdr_filter_info &info,
+                       const wdr_est_params *p, uint64_t seed, double2 *U, uint8_t *accepts, wdr_filter_info &info,
                        hipStream_t s)
 {
     const Geo &g = c->g;
@@ -248,12 +283,17 @@ wdr_status filter_step(wdr_ctx *c, double beta, double kappa, const uint8_t *mas
                                                                     prop, U);
         WDR_HIP(hipStreamSynchronize(s));  // acc is host memory reused next step
     }
+    if (!p) {  // block steps only: keep their result
+        info.accepted = 1;
+        WDR_HIP(hipStreamSynchronize(s));
+        return WDR_OK;
+    }
     // global step with the stochastic Schur-complement ratio
     if ((e = gauge(u0, hc)) != WDR_OK) return e;
     if ((e = gauge(U, hp)) != WDR_OK) return e;
     Stats est;
     double lr = 0.0;
-    e = logdet_ratio(c, {Proposal{hc.get(), hp.get(), kappa, p.seed}}, p, nullptr, &lr, est, s);
+    e = logdet_ratio(c, {Proposal{hc.get(), hp.get(), kappa, p->seed}}, *p, nullptr, &lr, est, s);
     if (e != WDR_OK) return e;
     info.log_ratio = lr;
     info.accepted = accept_metropolis(lr, seed, 0, 0, 1);

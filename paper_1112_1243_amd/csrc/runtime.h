@@ -138,8 +138,9 @@ wdr_status block_logdet(wdr_ctx *c, const wdr_gauge *U0, const wdr_gauge *U1, do
 void launch_heatbath(const wdr_ctx *c, double beta, const uint8_t *mask, uint64_t seed, int sweep, double2 *U,
                      hipStream_t s);
 // one step of the hierarchical filter on the canonical field U (in place)
+// (p == nullptr: block steps only)
 wdr_status filter_step(wdr_ctx *c, double beta, double kappa, const uint8_t *mask, int n_block_steps,
-                       const wdr_est_params &p, uint64_t seed, double2 *U, uint8_t *accepts, wdr_filter_info &info,
+                       const wdr_est_params *p, uint64_t seed, double2 *U, uint8_t *accepts, wdr_filter_info &info,
                        hipStream_t s);
 wdr_status logdet_ratio(wdr_ctx *c, const std::vector<Proposal> &props, const wdr_est_params &p,
                         double *host_samples, double *host_log_ratios, Stats &st, hipStream_t s);

@@ -358,15 +358,18 @@ class Context:
 
     def filter_step(self, beta, kappa, mask, n_block_steps, n_steps, n_noise, seed, est_seed, params: SolverParams,
                     U):
-        """One step of the hierarchical filter on U (in place).  Returns (info,
-        block decisions [n_block_steps, nblocks])."""
-        ep = EstParams()
-        ep.op, ep.n_steps, ep.n_noise, ep.noise, ep.seed, ep.sp = OP_SCHUR, n_steps, n_noise, NOISE_GAUSS, est_seed, \
-            params
+        """One step of the hierarchical filter on U (in place); n_steps = 0
+        runs the block steps only.  Returns (info, block decisions
+        [n_block_steps, nblocks])."""
+        ep = None
+        if n_steps > 0:
+            ep = EstParams()
+            ep.op, ep.n_steps, ep.n_noise, ep.noise, ep.seed, ep.sp = OP_SCHUR, n_steps, n_noise, NOISE_GAUSS, \
+                est_seed, params
         acc = np.zeros((max(n_block_steps, 1), self.nblocks), dtype=np.uint8)
         info = FilterInfo()
         _check(lib().wdr_filter_step(self.handle, beta, kappa, _dev(mask, (self.V, 4), "uint8"), n_block_steps,
-                                     ctypes.byref(ep), seed, _dev(U, (self.V, 4, 3, 3)),
+                                     ctypes.byref(ep) if ep is not None else None, seed, _dev(U, (self.V, 4, 3, 3)),
                                      acc.ctypes.data_as(ctypes.c_void_p), ctypes.byref(info), _stream()))
         return info, acc[:n_block_steps].astype(bool)
 

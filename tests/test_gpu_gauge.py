@@ -3,7 +3,9 @@ plaquette action, paper Sec. 5) and of one step of the hierarchical filter
 (eq. 4step with one level, the three-step algorithm of Sec. 5) against the
 FP64 oracle through the C ABI.  Both sides draw the same Philox numbers, so
 every Kennedy-Pendleton and Metropolis decision is the same; links agree to
-rounding (1e-12)."""
+rounding: 1e-12 after one sweep, 1e-10 after several (device and host log
+and cos may differ in the last bit, and each sweep feeds the next through the
+staples)."""
 import numpy as np
 import pytest
 
@@ -47,7 +49,7 @@ def test_heatbath_matches_oracle():
         ctx.heatbath(5.8, gm, 803, sw, gU)
     got = host(gU)
     say("heat-bath max |dU|", np.abs(got - want).max())
-    assert np.abs(got - want).max() < 1e-12
+    assert np.abs(got - want).max() < 1e-10
     assert np.array_equal(got[~mask], U[~mask])
     ctx.close()
 
@@ -108,7 +110,22 @@ def test_filter_step_matches_oracle():
         assert np.array_equal(acc, acc_w)
         assert abs(info.log_ratio - lr_w) < 1e-8 and bool(info.accepted) == ok_w
         assert info.block_accepts == acc_w.sum() and info.block_trials == acc_w.size
-        assert np.abs(host(gU) - want).max() < 1e-12
+        assert np.abs(host(gU) - want).max() < 1e-10
+    ctx.close()
+
+
+def test_block_steps_only():
+    """Without a global step the result of three block steps is kept."""
+    wdr = _wdr()
+    L, B = (4, 4, 4, 4), (2, 2, 2, 2)
+    ctx, lat = wdr.Context(L, B), oracle.Lattice(L, B)
+    U = synth.gauge_field(L, 0.5, 812)
+    mask = _in_block_mask(lat)
+    want, acc_w, _, _ = oracle.filter_step(lat, U, 1.0, 0.16, mask, 3, 0, 1, 813, 0)
+    gU = dev(U)
+    info, acc = ctx.filter_step(1.0, 0.16, dev(mask.astype(np.uint8)), 3, 0, 1, 813, 0, wdr.default_params(), gU)
+    assert np.array_equal(acc, acc_w) and info.accepted == 1 and 0 < acc.sum() < acc.size
+    assert np.abs(host(gU) - want).max() < 1e-10
     ctx.close()
 
 
