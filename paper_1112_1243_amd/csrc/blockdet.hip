@@ -39,7 +39,7 @@ namespace {
 using namespace dev;
 
 constexpr int TW = 64;   // tile and panel width
-constexpr int KC = 32;   // k-chunk staged in LDS by the tile GEMM
+constexpr int KC = 16;   // k-chunk staged in LDS by the tile GEMM
 constexpr int GROUP = 4; // panels per trailing update
 constexpr int MAX_VH = 128;
 
@@ -341,11 +341,12 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 //   MODE 1: C = A_IJ - X Y^+ for the tile pairs I >= J: with nj > 0 the
 //           rectangle I = i0 + x / nj, J = j0 + x % nj (pairs with I < J
 //           exit), with nj = 0 the triangle I >= J >= j0 numbered row by row.
-// Four wavefronts each own a 32 x 32 quadrant as 2 x 2 MFMA tiles with
-// separate real and imaginary accumulators.  MFMA 16x16x4 f64 operands:
-// lane l holds A[l % 16][l / 16] and B[l / 16][l % 16]; element r of its
-// accumulator is D[l / 16 + 4 r][l % 16].  Here B[k][n] = conj(Y[n][k]),
-// so re C += Xr Yr + Xi Yi and im C += Xi Yr - Xr Yi.
+// Four wavefronts each own a 32 x 32 quadrant as 2 x 2 MFMA tiles.  MFMA
+// 16x16x4 f64 operands: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16];
+// element r of its accumulator is D[l / 16 + 4 r][l % 16].  Here
+// B[k][n] = conj(Y[n][k]), and each complex product takes three real ones
+// (the 3M form): P1 = Xr Yr, P2 = Xi Yi, P3 = (Xr + Xi)(Yr - Yi), so that
+// re C = P1 + P2 and im C = P3 - P1 + P2.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_tile_gemm(double2 *__restrict__ A, long np, int i0, int j0, int nj,
                                                    int kbeg, int klen, const double2 *__restrict__ W)
@@ -373,21 +374,34 @@ __global__ __launch_bounds__(256) void k_tile_gemm(double2 *__restrict__ A, long
     const double2 *Y = MODE == 0 ? W + (long)blockIdx.y * TW * TW : Aq + (long)TW * J * np + kbeg;
     const long ys = MODE == 0 ? TW : np;
     const int r0 = 32 * (wv >> 1), c0 = 32 * (wv & 1), m = lane & 15, kl = lane >> 4;
-    d4 cre[2][2], cim[2][2];
+    d4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) cre[a][b] = cim[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < 2; ++b) p1[a][b] = p2[a][b] = p3[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    // the next k-chunk is loaded into registers while this one is computed
+    constexpr int PER = TW * KC / 256;
+    double2 nx[PER], ny[PER];
+    auto fetch = [&](int kc) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = tid + 256 * q, r = i / KC, k = i % KC;
+            nx[q] = X[(long)r * np + kc + k];
+            ny[q] = Y[(long)r * ys + kc + k];
+        }
+    };
+    fetch(0);
     for (int kc = 0; kc < klen; kc += KC) {
-        for (int i = tid; i < TW * KC; i += 256) {
-            const int r = i / KC, k = i % KC;
-            const double2 u = X[(long)r * np + kc + k], v = Y[(long)r * ys + kc + k];
-            xr[r][k] = u.x;
-            xi[r][k] = u.y;
-            yr[r][k] = v.x;
-            yi[r][k] = v.y;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int i = tid + 256 * q, r = i / KC, k = i % KC;
+            xr[r][k] = nx[q].x;
+            xi[r][k] = nx[q].y;
+            yr[r][k] = ny[q].x;
+            yi[r][k] = ny[q].y;
         }
         __syncthreads();
+        if (kc + KC < klen) fetch(kc + KC);
 #pragma unroll 2
         for (int k = 0; k < KC; k += 4) {
             double ar[2], ai[2], br[2], bi[2];
@@ -398,14 +412,19 @@ __global__ __launch_bounds__(256) void k_tile_gemm(double2 *__restrict__ A, long
                 br[t] = yr[c0 + 16 * t + m][k + kl];
                 bi[t] = yi[c0 + 16 * t + m][k + kl];
             }
+            double as[2], bd[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                as[t] = ar[t] + ai[t];
+                bd[t] = br[t] - bi[t];
+            }
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-                    cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], cre[a][b], 0, 0, 0);
-                    cre[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], cre[a][b], 0, 0, 0);
-                    cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], br[b], cim[a][b], 0, 0, 0);
-                    cim[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[a], bi[b], cim[a][b], 0, 0, 0);
+                    p1[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[a], br[b], p1[a][b], 0, 0, 0);
+                    p2[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[a], bi[b], p2[a][b], 0, 0, 0);
+                    p3[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[a], bd[b], p3[a][b], 0, 0, 0);
                 }
         }
         __syncthreads();
@@ -418,11 +437,12 @@ __global__ __launch_bounds__(256) void k_tile_gemm(double2 *__restrict__ A, long
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const long idx = (long)(r0 + 16 * a + kl + 4 * r) * np + c0 + 16 * b + m;
+                const double re = p1[a][b][r] + p2[a][b][r], im = p3[a][b][r] - p1[a][b][r] + p2[a][b][r];
                 if (MODE == 0) {
-                    C[idx] = make_double2(cre[a][b][r], cim[a][b][r]);
+                    C[idx] = make_double2(re, im);
                 } else {
                     const double2 o = C[idx];
-                    C[idx] = make_double2(o.x - cre[a][b][r], o.y - cim[a][b][r]);
+                    C[idx] = make_double2(o.x - re, o.y - im);
                 }
             }
 }
