@@ -29,6 +29,8 @@ Pins (tests under ``tests/test_oracle_*.py``):
                       quadrature; one-link fixed point vs a reweighted Haar
                       integral; SU(3) kept, unmasked links untouched;
                       strong-coupling plaquette beta/18 + beta^2/216
+  * over-relaxation   action unchanged, SU(3) kept, one subgroup an
+                      involution
 """
 from __future__ import annotations
 
@@ -644,6 +646,39 @@ def heatbath(lat: Lattice, U, beta: float, mask, seed: int, sweep: int) -> np.nd
         for p in (0, 1):
             for s in np.nonzero(np.asarray(mask)[:, mu] & (par == p))[0]:
                 U[s, mu] = heatbath_link(U[s, mu], staple(lat, U, s, mu), beta, seed, int(s), mu, sweep)
+    return U
+
+
+def overrelax_link(u, A) -> np.ndarray:
+    """Over-relaxation of one link u with staple sum A (Sec. 5 names it beside
+    the heat-bath): for each SU(2) subgroup (0,1), (0,2), (1,2) in turn, with
+    the subgroup part of W = u A equal to k v (v in SU(2)), u <- X u with
+    X = (v^+)^2, the reflection through the maximum v^+ of Re tr(X W); it
+    leaves Re tr(X W), and hence the action, unchanged."""
+    u = np.array(u, dtype=np.complex128, copy=True)
+    for i, j in SUBGROUPS:
+        W = u @ A
+        a = 0.5 * (W[i, i] + np.conj(W[j, j]))
+        b = 0.5 * (W[i, j] - np.conj(W[j, i]))
+        k = np.sqrt(abs(a) ** 2 + abs(b) ** 2)
+        if not k > 0:
+            continue
+        vd = (np.array([[a, b], [-np.conj(b), np.conj(a)]]) / k).conj().T
+        E = np.eye(3, dtype=np.complex128)
+        E[np.ix_((i, j), (i, j))] = vd @ vd
+        u = E @ u
+    return u
+
+
+def overrelax(lat: Lattice, U, mask) -> np.ndarray:
+    """One over-relaxation sweep of the masked links, in the order of
+    heatbath."""
+    U = np.array(U, dtype=np.complex128, copy=True)
+    par = lat.coords().sum(axis=1) & 1
+    for mu in range(4):
+        for p in (0, 1):
+            for s in np.nonzero(np.asarray(mask)[:, mu] & (par == p))[0]:
+                U[s, mu] = overrelax_link(U[s, mu], staple(lat, U, s, mu))
     return U
 
 

@@ -98,3 +98,39 @@ def test_filter_step_structure():
         assert np.array_equal(V, U)
     V, acc, log_r, ok = oracle.filter_step(lat, U, 5.8, 0.12, np.zeros((lat.V, 4), bool), 1, 1, 1, 80, 81)
     assert ok and abs(log_r) < 1e-10 and acc.all() and np.array_equal(V, U)
+
+
+def test_overrelaxation_keeps_the_action():
+    """An over-relaxation sweep is microcanonical: the sum of plaquettes is
+    unchanged (every link update keeps Re tr(U A), and links of one class
+    share no plaquette), SU(3) is kept, and the links move."""
+    lat = oracle.Lattice((4, 4, 4, 4), B=(2, 2, 2, 2))
+    U = synth.gauge_field(lat.L, 0.5, 82)
+    mask = np.ones((lat.V, 4), bool)
+    V = oracle.overrelax(lat, U, mask)
+    assert abs(oracle.plaquette(lat, V) - oracle.plaquette(lat, U)) < 1e-13
+    assert np.abs(np.einsum("xmab,xmcb->xmac", V, V.conj()) - np.eye(3)).max() < 1e-12
+    assert np.abs(V - U).max() > 0.1
+
+
+def test_overrelaxation_single_subgroup_is_an_involution():
+    """For one SU(2) subgroup, X = (v^+)^2 maps the subgroup part k v of W to
+    k v^+, whose reflection is X' = v^2: two steps give the identity."""
+    A = synth.gauge_field((1, 1, 1, 1), 0.8, 83)[0, :3].sum(axis=0)
+    u = synth.gauge_field((1, 1, 1, 1), 0.8, 84)[0, 0]
+
+    def one(u):
+        W = u @ A
+        a, b = 0.5 * (W[0, 0] + np.conj(W[1, 1])), 0.5 * (W[0, 1] - np.conj(W[1, 0]))
+        v = np.array([[a, b], [-np.conj(b), np.conj(a)]]) / np.sqrt(abs(a) ** 2 + abs(b) ** 2)
+        E = np.eye(3, dtype=np.complex128)
+        E[:2, :2] = v.conj().T @ v.conj().T
+        return E @ u
+    # the oracle's first subgroup step is this map; applying it twice returns u
+    assert np.abs(one(one(u)) - u).max() < 1e-13
+    saved = oracle.SUBGROUPS
+    try:
+        oracle.core.SUBGROUPS = ((0, 1),)
+        assert np.abs(oracle.overrelax_link(u, A) - one(u)).max() < 1e-14
+    finally:
+        oracle.core.SUBGROUPS = saved
