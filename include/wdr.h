@@ -342,6 +342,12 @@ wdr_status wdr_block_schur_ratio(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gau
 wdr_status wdr_heatbath(wdr_ctx *ctx, double beta, const uint8_t *dev_mask, uint64_t seed, int32_t sweep,
                         double *dev_U, void *stream);
 
+/* Over-relaxation sweep of the masked links (the alternative that Sec. 5
+ * names beside the heat-bath), in the order of wdr_heatbath: per SU(2)
+ * subgroup, with the subgroup part of W = U A equal to k v (v in SU(2)),
+ * U <- (v^+)^2 U, which keeps the Wilson action.  No random numbers. */
+wdr_status wdr_overrelax(wdr_ctx *ctx, const uint8_t *dev_mask, double *dev_U, void *stream);
+
 typedef struct wdr_filter_info {
     int32_t block_accepts; /* accepted blocks, summed over the block steps */
     int32_t block_trials;  /* n_block_steps x nblocks */

@@ -638,6 +638,14 @@ wdr_status wdr_heatbath(wdr_ctx *c, double beta, const uint8_t *mask, uint64_t s
     return finish(S(stream));
 }
 
+wdr_status wdr_overrelax(wdr_ctx *c, const uint8_t *mask, double *U, void *stream)
+{
+    wdr_status e = pre(c, mask, U);
+    if (e != WDR_OK) return e;
+    launch_overrelax(c, mask, reinterpret_cast<double2 *>(U), S(stream));
+    return finish(S(stream));
+}
+
 wdr_status wdr_filter_step(wdr_ctx *c, double beta, double kappa, const uint8_t *mask, int32_t n_block_steps,
                            const wdr_est_params *p, uint64_t seed, double *U, uint8_t *accepts,
                            wdr_filter_info *info, void *stream)

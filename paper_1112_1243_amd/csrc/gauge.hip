@@ -63,12 +63,14 @@ __device__ __forceinline__ long site_of(int4 L, const int x[4])
     return x[0] + (long)L.x * (x[1] + (long)L.y * (x[2] + (long)L.z * x[3]));
 }
 
-// one heat-bath step of every masked link (x, mu) with x of parity par
-__global__ __launch_bounds__(256) void k_heatbath(int4 L, long V, const uint8_t *__restrict__ mask, double beta,
-                                                  uint64_t seed, uint64_t sweep, int mu, int par, double2 *U)
+// canonical site s of the class (mu, par) and the staple sum A of its link,
+// Re tr(U_mu(x) A) = the six plaquettes through the link; false when the
+// link is not masked or has the other parity
+__device__ __forceinline__ bool link_and_staple(int4 L, long V, const uint8_t *__restrict__ mask, int mu, int par,
+                                                const double2 *U, long &s, M &A)
 {
-    const long s = (long)blockIdx.x * 256 + threadIdx.x;
-    if (s >= V || !mask[s * 4 + mu]) return;
+    s = (long)blockIdx.x * 256 + threadIdx.x;
+    if (s >= V || !mask[s * 4 + mu]) return false;
     const int Ls[4] = {L.x, L.y, L.z, L.w};
     int x[4];
     long r = s;
@@ -76,14 +78,12 @@ __global__ __launch_bounds__(256) void k_heatbath(int4 L, long V, const uint8_t 
         x[d] = (int)(r % Ls[d]);
         r /= Ls[d];
     }
-    if (((x[0] + x[1] + x[2] + x[3]) & 1) != par) return;
+    if (((x[0] + x[1] + x[2] + x[3]) & 1) != par) return false;
     auto nb = [&](const int *y, int d, int step) {
         int z[4] = {y[0], y[1], y[2], y[3]};
         z[d] = (z[d] + step + Ls[d]) % Ls[d];
         return site_of(L, z);
     };
-    // staple sum A: Re tr(U_mu(x) A) = the six plaquettes through the link
-    M A;
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) A.a[i][j] = {0.0, 0.0};
     const long xm = nb(x, mu, 1);
@@ -104,23 +104,55 @@ __global__ __launch_bounds__(256) void k_heatbath(int4 L, long V, const uint8_t 
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) A.a[i][j] = zadd(A.a[i][j], zadd(up.a[i][j], dn.a[i][j]));
     }
+    return true;
+}
+
+// SU(2) subgroup (i, j) of W = u A: its part k v, v = [[a, b], [-b*, a*]] / k
+__device__ __forceinline__ double subgroup_part(const M &u, const M &A, int i, int j, Z &a, Z &b)
+{
+    Z w[2][2];
+    const int ij[2] = {i, j};
+    for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q) {
+            Z t = {0.0, 0.0};
+            for (int k = 0; k < 3; ++k) t = zadd(t, zmul(u.a[ij[p]][k], A.a[k][ij[q]]));
+            w[p][q] = t;
+        }
+    a = {0.5 * (w[0][0].re + w[1][1].re), 0.5 * (w[0][0].im - w[1][1].im)};
+    b = {0.5 * (w[0][1].re - w[1][0].re), 0.5 * (w[0][1].im + w[1][0].im)};
+    return sqrt(a.re * a.re + a.im * a.im + b.re * b.re + b.im * b.im);
+}
+
+// u <- X u on rows i, j
+__device__ __forceinline__ void left_mul(M &u, const Z X[2][2], int i, int j)
+{
+    for (int col = 0; col < 3; ++col) {
+        const Z ri = u.a[i][col], rj = u.a[j][col];
+        u.a[i][col] = zadd(zmul(X[0][0], ri), zmul(X[0][1], rj));
+        u.a[j][col] = zadd(zmul(X[1][0], ri), zmul(X[1][1], rj));
+    }
+}
+
+__device__ __forceinline__ void store(double2 *U, long site, int mu, const M &u)
+{
+    double2 *p = U + (site * 4 + mu) * 9;
+    for (int e = 0; e < 9; ++e) p[e] = make_double2(u.a[e / 3][e % 3].re, u.a[e / 3][e % 3].im);
+}
+
+// one heat-bath step of every masked link (x, mu) with x of parity par
+__global__ __launch_bounds__(256) void k_heatbath(int4 L, long V, const uint8_t *__restrict__ mask, double beta,
+                                                  uint64_t seed, uint64_t sweep, int mu, int par, double2 *U)
+{
+    long s;
+    M A;
+    if (!link_and_staple(L, V, mask, mu, par, U, s, A)) return;
     M u;
     load(U, s, mu, u);
     const int sub[3][2] = {{0, 1}, {0, 2}, {1, 2}};
     for (int g = 0; g < 3; ++g) {
         const int i = sub[g][0], j = sub[g][1];
-        // subgroup part of W = u A
-        Z w[2][2];
-        const int ij[2] = {i, j};
-        for (int p = 0; p < 2; ++p)
-            for (int q = 0; q < 2; ++q) {
-                Z t = {0.0, 0.0};
-                for (int k = 0; k < 3; ++k) t = zadd(t, zmul(u.a[ij[p]][k], A.a[k][ij[q]]));
-                w[p][q] = t;
-            }
-        const Z a = {0.5 * (w[0][0].re + w[1][1].re), 0.5 * (w[0][0].im - w[1][1].im)};
-        const Z b = {0.5 * (w[0][1].re - w[1][0].re), 0.5 * (w[0][1].im + w[1][0].im)};
-        const double k = sqrt(a.re * a.re + a.im * a.im + b.re * b.re + b.im * b.im);
+        Z a, b;
+        const double k = subgroup_part(u, A, i, j, a, b);
         const double alpha = 2.0 * beta * k / 3.0;
         const uint64_t c1 = (sweep << 32) | ((uint64_t)mu << 8) | (uint64_t)g;
         double a0 = 0.0;
@@ -152,14 +184,38 @@ __global__ __launch_bounds__(256) void k_heatbath(int4 L, long V, const uint8_t 
         Z X[2][2];
         for (int p = 0; p < 2; ++p)
             for (int q = 0; q < 2; ++q) X[p][q] = zadd(zmul(Y[p][0], zcj(v[q][0])), zmul(Y[p][1], zcj(v[q][1])));
-        for (int col = 0; col < 3; ++col) {
-            const Z ri = u.a[i][col], rj = u.a[j][col];
-            u.a[i][col] = zadd(zmul(X[0][0], ri), zmul(X[0][1], rj));
-            u.a[j][col] = zadd(zmul(X[1][0], ri), zmul(X[1][1], rj));
-        }
+        left_mul(u, X, i, j);
     }
-    double2 *p = U + (s * 4 + mu) * 9;
-    for (int e = 0; e < 9; ++e) p[e] = make_double2(u.a[e / 3][e % 3].re, u.a[e / 3][e % 3].im);
+    store(U, s, mu, u);
+}
+
+// over-relaxation of every masked link (x, mu) with x of parity par: per
+// subgroup u <- (v^+)^2 u, the reflection through the maximum of Re tr(X W),
+// which keeps the action
+__global__ __launch_bounds__(256) void k_overrelax(int4 L, long V, const uint8_t *__restrict__ mask, int mu, int par,
+                                                   double2 *U)
+{
+    long s;
+    M A;
+    if (!link_and_staple(L, V, mask, mu, par, U, s, A)) return;
+    M u;
+    load(U, s, mu, u);
+    const int sub[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int g = 0; g < 3; ++g) {
+        const int i = sub[g][0], j = sub[g][1];
+        Z a, b;
+        const double k = subgroup_part(u, A, i, j, a, b);
+        if (!(k > 0.0)) continue;
+        const double ik = 1.0 / k;
+        // v^+ = [[a*, -b], [b*, a]] / k
+        const Z vd[2][2] = {{{a.re * ik, -a.im * ik}, {-b.re * ik, -b.im * ik}},
+                            {{b.re * ik, -b.im * ik}, {a.re * ik, a.im * ik}}};
+        Z X[2][2];
+        for (int p = 0; p < 2; ++p)
+            for (int q = 0; q < 2; ++q) X[p][q] = zadd(zmul(vd[p][0], vd[0][q]), zmul(vd[p][1], vd[1][q]));
+        left_mul(u, X, i, j);
+    }
+    store(U, s, mu, u);
 }
 
 // cur <- prop at every site whose block was accepted
@@ -227,6 +283,14 @@ void launch_heatbath(const wdr_ctx *c, double beta, const uint8_t *mask, uint64_
         for (int par = 0; par < 2; ++par)
             k_heatbath<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(i4(c->geom.L), V, mask, beta, seed,
                                                                     (uint64_t)(uint32_t)sweep, mu, par, U);
+}
+
+void launch_overrelax(const wdr_ctx *c, const uint8_t *mask, double2 *U, hipStream_t s)
+{
+    const long V = c->g.V;
+    for (int mu = 0; mu < 4; ++mu)
+        for (int par = 0; par < 2; ++par)
+            k_overrelax<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(i4(c->geom.L), V, mask, mu, par, U);
 }
 
 bool accept_metropolis(double r, uint64_t seed, uint64_t c0, uint64_t c1, uint64_t c2)

@@ -122,6 +122,7 @@ def lib():
         L.wdr_block_logdet_ratio.argtypes = [P, P, P, d, i32, P, P]
         L.wdr_block_fields.argtypes = [P, P, P, P]
         L.wdr_heatbath.argtypes = [P, d, P, ctypes.c_uint64, i32, P, P]
+        L.wdr_overrelax.argtypes = [P, P, P, P]
         L.wdr_filter_step.argtypes = [P, d, d, P, i32, ctypes.POINTER(EstParams), ctypes.c_uint64, P, P,
                                       ctypes.POINTER(FilterInfo), P]
         L.wdr_block_schur_ratio.argtypes = [P, P, P, d, P, ctypes.POINTER(EstParams), P, P,
@@ -354,6 +355,12 @@ class Context:
         canonical field U (complex128 [V, 4, 3, 3] on the device), in place."""
         _check(lib().wdr_heatbath(self.handle, beta, _dev(mask, (self.V, 4), "uint8"), seed, sweep,
                                   _dev(U, (self.V, 4, 3, 3)), _stream()))
+        return U
+
+    def overrelax(self, mask, U):
+        """One over-relaxation sweep of the masked links of U, in place."""
+        _check(lib().wdr_overrelax(self.handle, _dev(mask, (self.V, 4), "uint8"), _dev(U, (self.V, 4, 3, 3)),
+                                   _stream()))
         return U
 
     def filter_step(self, beta, kappa, mask, n_block_steps, n_steps, n_noise, seed, est_seed, params: SolverParams,

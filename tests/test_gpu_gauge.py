@@ -54,6 +54,23 @@ def test_heatbath_matches_oracle():
     ctx.close()
 
 
+def test_overrelax_matches_oracle():
+    """An over-relaxation sweep of a random 40% of the links equals the
+    oracle's and keeps the plaquette sum."""
+    wdr = _wdr()
+    L = (4, 4, 4, 4)
+    ctx, lat = wdr.Context(L, (2, 2, 2, 2)), oracle.Lattice(L, (2, 2, 2, 2))
+    U = synth.gauge_field(L, 0.5, 815)
+    mask = synth.bernoulli_links(L, 0.4, 816)
+    want = oracle.overrelax(lat, U, mask)
+    gU = dev(U)
+    ctx.overrelax(dev(mask.astype(np.uint8)), gU)
+    got = host(gU)
+    assert np.abs(got - want).max() < 1e-12
+    assert abs(oracle.plaquette(lat, got) - oracle.plaquette(lat, U)) < 1e-12
+    ctx.close()
+
+
 def test_heatbath_active_links_8x8():
     """One sweep of the active links of 4^4 blocks on an 8^4 lattice."""
     wdr = _wdr()
