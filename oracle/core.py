@@ -31,6 +31,8 @@ Pins (tests under ``tests/test_oracle_*.py``):
                       strong-coupling plaquette beta/18 + beta^2/216
   * over-relaxation   action unchanged, SU(3) kept, one subgroup an
                       involution
+  * relative gauge    F never decreases; block determinants unchanged; a
+                      gauge copy of U is driven back to U
 """
 from __future__ import annotations
 
@@ -680,6 +682,49 @@ def overrelax(lat: Lattice, U, mask) -> np.ndarray:
             for s in np.nonzero(np.asarray(mask)[:, mu] & (par == p))[0]:
                 U[s, mu] = overrelax_link(U[s, mu], staple(lat, U, s, mu))
     return U
+
+
+def relative_gauge_functional(U, Up) -> float:
+    """F = sum_{x,mu} Re tr(U'_mu(x) U_mu(x)^+) / 3, at most 4 V."""
+    return float(np.einsum("xmab,xmab->", Up, U.conj()).real / 3.0)
+
+
+def relative_gauge(lat: Lattice, U, Up, sweeps: int) -> np.ndarray:
+    """Relative gauge fixing of U' to U (Sec. 4: it reduces the spread of the
+    eigenvalues of M^+ M): local maximisation of F over gauge transformations
+    U'_mu(x) -> g(x) U'_mu(x) g(x+mu)^+, which leave every determinant
+    unchanged.  A sweep visits the even, then the odd sites (sites of one
+    parity share no link); at site x, with
+    K = sum_mu [U'_mu(x) U_mu(x)^+ + U'_mu(x-mu)^+ U_mu(x-mu)],
+    h is built from the identity by the subgroups (0,1), (0,2), (1,2): with
+    the subgroup part of h K equal to k v, h <- v^+ h (the maximum of
+    Re tr(X h K) in the subgroup); then U'_mu(x) <- h U'_mu(x) and
+    U'_mu(x-mu) <- U'_mu(x-mu) h^+.  Periodic in every direction."""
+    Up = np.array(Up, dtype=np.complex128, copy=True)
+    par = lat.coords().sum(axis=1) & 1
+    dag = lambda m: m.conj().T
+    for _ in range(sweeps):
+        for p in (0, 1):
+            for s in np.nonzero(par == p)[0]:
+                K = np.zeros((3, 3), dtype=np.complex128)
+                back = [_shift(lat, s, mu, -1) for mu in range(4)]
+                for mu in range(4):
+                    K += Up[s, mu] @ dag(U[s, mu]) + dag(Up[back[mu], mu]) @ U[back[mu], mu]
+                h = np.eye(3, dtype=np.complex128)
+                for i, j in SUBGROUPS:
+                    W = h @ K
+                    a = 0.5 * (W[i, i] + np.conj(W[j, j]))
+                    b = 0.5 * (W[i, j] - np.conj(W[j, i]))
+                    k = np.sqrt(abs(a) ** 2 + abs(b) ** 2)
+                    if not k > 0:
+                        continue
+                    E = np.eye(3, dtype=np.complex128)
+                    E[np.ix_((i, j), (i, j))] = dag(np.array([[a, b], [-np.conj(b), np.conj(a)]]) / k)
+                    h = E @ h
+                for mu in range(4):
+                    Up[s, mu] = h @ Up[s, mu]
+                    Up[back[mu], mu] = Up[back[mu], mu] @ dag(h)
+    return Up
 
 
 def plaquette(lat: Lattice, U) -> float:

@@ -134,3 +134,34 @@ def test_overrelaxation_single_subgroup_is_an_involution():
         assert np.abs(oracle.overrelax_link(u, A) - one(u)).max() < 1e-14
     finally:
         oracle.core.SUBGROUPS = saved
+
+
+def _gauge_transform(lat, U, g):
+    x = lat.coords()
+    out = np.empty_like(U)
+    for mu in range(4):
+        y = x.copy()
+        y[:, mu] = (y[:, mu] + 1) % lat.L[mu]
+        t = y[:, 0] + lat.L[0] * (y[:, 1] + lat.L[1] * (y[:, 2] + lat.L[2] * y[:, 3]))
+        out[:, mu] = g @ U[:, mu] @ np.conj(np.swapaxes(g[t], -1, -2))
+    return out
+
+
+def test_relative_gauge_fixing():
+    """F never decreases from sweep to sweep; the fixed field has the same
+    block determinants (gauge invariance); a random gauge copy of U is driven
+    back towards U (F close to its maximum 4 V)."""
+    lat = oracle.Lattice((4, 4, 4, 4), B=(2, 2, 2, 2))
+    U = synth.gauge_field(lat.L, 0.5, 85)
+    Up = synth.redraw(U, synth.bernoulli_links(lat.L, 0.2, 86), 0.5, 86)
+    g = synth.gauge_field(lat.L, 0.4, 87)[:, 0]
+    Ug = _gauge_transform(lat, Up, g)
+    F = [oracle.relative_gauge_functional(U, Ug)]
+    V = Ug
+    for _ in range(3):
+        V = oracle.relative_gauge(lat, U, V, 1)
+        F.append(oracle.relative_gauge_functional(U, V))
+    assert all(b >= a - 1e-12 for a, b in zip(F, F[1:])) and F[-1] > F[0] + 1.0
+    assert np.abs(oracle.block_log_dets(lat, V, 0.13) - oracle.block_log_dets(lat, Ug, 0.13)).max() < 1e-10
+    W = oracle.relative_gauge(lat, U, _gauge_transform(lat, U, g), 30)
+    assert oracle.relative_gauge_functional(U, W) > 4 * lat.V - 1e-6
