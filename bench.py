@@ -241,18 +241,21 @@ def exact_acceptance(wdr, torch):
     (U, U') of a quenched beta = 5.8 chain (10 heat-bath sweeps apart) and
     one block step each, the variance over pairs of the global estimate
     log Rhat for several N, fitted as a + b / N (eq. param: the noise part
-    falls as 1/N); a is the exact variance sigma_2^2 and erfc(sqrt(a / 8))
-    the acceptance (eq. acceptance)."""
+    falls as 1/N; weighted by the standard error of each variance estimate);
+    a is the exact variance sigma_2^2 and erfc(sqrt(a / 8)) the acceptance
+    (eq. acceptance).  Beside it, N = 8 after 20 sweeps of
+    relative gauge fixing of U' to U (Sec. 4), for the same pairs."""
     from scipy import special
     beta, kappa, seed = 5.8, 0.15462, 1112124305
     res = {}
-    for L, pairs, Ns in (((8, 8, 8, 8), 48, (4, 8, 16, 32)), ((16, 16, 16, 16), 16, (8, 16, 32, 64))):
+    for L, pairs, Ns in (((8, 8, 8, 8), 96, (8, 16, 32, 64)), ((16, 16, 16, 16), 24, (8, 16, 32, 64))):
         t0 = time.perf_counter()
         ctx = wdr.Context(L, (4, 4, 4, 4))
         U, allm = thermalised(wdr, torch, ctx, L, beta, seed, 200)
         mask = ctx.active_links(0, 3)
         p = wdr.default_params()
         lr = np.zeros((pairs, len(Ns)))
+        lr_fixed = np.zeros(pairs)  # N = 8 after relative gauge fixing of U' to U
         bacc = 0.0
         sw = 200
         for q in range(pairs):
@@ -266,15 +269,27 @@ def exact_acceptance(wdr, torch):
             for j, N in enumerate(Ns):
                 _, lr[q, j], _ = ctx.logdet_ratio(gU, gUp, kappa, wdr.OP_SCHUR, N, 1, wdr.NOISE_GAUSS,
                                                   seed + 1000 * q + N, p)
-            del gU, gUp
+            ctx.relative_gauge(U, Up, 20)
+            gUf = ctx.gauge(Up)
+            _, lr_fixed[q], _ = ctx.logdet_ratio(gU, gUf, kappa, wdr.OP_SCHUR, 8, 1, wdr.NOISE_GAUSS,
+                                                 seed + 1000 * q + 8, p)
+            del gU, gUp, gUf
         var = lr.var(axis=0, ddof=1)
-        A = np.vstack([np.ones(len(Ns)), 1.0 / np.array(Ns)]).T
-        a, b = np.linalg.lstsq(A, var, rcond=None)[0]
+        # weighted fit: a variance estimate from P pairs has standard error
+        # sigma^2 sqrt(2 / (P - 1))
+        sd = var * np.sqrt(2.0 / (pairs - 1))
+        A = np.vstack([np.ones(len(Ns)), 1.0 / np.array(Ns)]).T / sd[:, None]
+        coef, _, _, _ = np.linalg.lstsq(A, var / sd, rcond=None)
+        a, b = coef
+        a_err = float(np.sqrt(np.linalg.inv(A.T @ A)[0, 0]))
         name = "x".join(map(str, L))
         res[name] = {"pairs": pairs, "N": list(Ns), "var_log_ratio": [round(float(v), 4) for v in var],
                      "mean_log_ratio": [round(float(v), 4) for v in lr.mean(axis=0)], "fit_a": round(float(a), 4),
+                     "fit_a_err": round(a_err, 4),
                      "fit_b": round(float(b), 3), "block_acceptance": round(float(bacc) / pairs, 3),
                      "acceptance_erfc": round(float(special.erfc(np.sqrt(max(a, 0.0) / 8))), 3),
+                     "var_log_ratio_N8_relative_gauge": round(float(lr_fixed.var(ddof=1)), 4),
+                     "mean_log_ratio_N8_relative_gauge": round(float(lr_fixed.mean()), 4),
                      "seconds": round(time.perf_counter() - t0, 2)}
         log("exact acceptance %s: %s" % (name, res[name]))
         ctx.close()

@@ -348,6 +348,20 @@ wdr_status wdr_heatbath(wdr_ctx *ctx, double beta, const uint8_t *dev_mask, uint
  * U <- (v^+)^2 U, which keeps the Wilson action.  No random numbers. */
 wdr_status wdr_overrelax(wdr_ctx *ctx, const uint8_t *dev_mask, double *dev_U, void *stream);
 
+/* Relative gauge fixing of the canonical field dev_Up to dev_U, in place
+ * (paper Sec. 4: it narrows the spectrum of M^+ M, M = X'^-1 X): `sweeps`
+ * sweeps of local maximisation of F = sum_{x,mu} Re tr(U'_mu(x) U_mu(x)^+)
+ * over gauge transformations of U', even then odd sites.  At site x the
+ * transformation h is built from the identity by one pass over the SU(2)
+ * subgroups (0,1), (0,2), (1,2) maximising Re tr(h K),
+ * K = sum_mu [U'_mu(x) U_mu(x)^+ + U'_mu(x-mu)^+ U_mu(x-mu)].  Every
+ * determinant of the operators here is gauge invariant; the path U -> U'
+ * and so the estimator's variance change.  Periodic in every direction
+ * (a gauge transformation ignores bc).  host_F (may be NULL): F / 3 after
+ * the sweeps. */
+wdr_status wdr_relative_gauge(wdr_ctx *ctx, const double *dev_U, double *dev_Up, int32_t sweeps, double *host_F,
+                              void *stream);
+
 typedef struct wdr_filter_info {
     int32_t block_accepts; /* accepted blocks, summed over the block steps */
     int32_t block_trials;  /* n_block_steps x nblocks */

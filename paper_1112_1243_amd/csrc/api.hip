@@ -638,6 +638,31 @@ wdr_status wdr_heatbath(wdr_ctx *c, double beta, const uint8_t *mask, uint64_t s
     return finish(S(stream));
 }
 
+wdr_status wdr_relative_gauge(wdr_ctx *c, const double *U, double *Up, int32_t sweeps, double *F, void *stream)
+{
+    wdr_status e = pre(c, U, Up);
+    if (e != WDR_OK) return e;
+    if (sweeps < 0) {
+        set_error("sweeps must be >= 0");
+        return WDR_EINVAL;
+    }
+    hipStream_t s = S(stream);
+    launch_relgauge(c, reinterpret_cast<const double2 *>(U), reinterpret_cast<double2 *>(Up), sweeps, s);
+    if (F) {
+        // F = sum Re tr(U' U^+) / 3 = Re <U, U'> / 3 over all 36 V entries,
+        // reduced as three fields of 12 V entries
+        Work part(c, sizeof(double) * red_scratch(3)), out(c, 3 * sizeof(double2));
+        if (!part.ok() || !out.ok()) return WDR_ENOMEM;
+        launch_dot<double>(all_sys(c, 3), reinterpret_cast<const double2 *>(U), reinterpret_cast<const double2 *>(Up),
+                           part.as<double>(), out.as<double2>(), 1, s);
+        double2 h[3];
+        WDR_HIP(hipMemcpyAsync(h, out.as<void>(), sizeof(h), hipMemcpyDeviceToHost, s));
+        WDR_HIP(hipStreamSynchronize(s));
+        *F = (h[0].x + h[1].x + h[2].x) / 3.0;
+    }
+    return finish(s);
+}
+
 wdr_status wdr_overrelax(wdr_ctx *c, const uint8_t *mask, double *U, void *stream)
 {
     wdr_status e = pre(c, mask, U);

@@ -218,6 +218,67 @@ __global__ __launch_bounds__(256) void k_overrelax(int4 L, long V, const uint8_t
     store(U, s, mu, u);
 }
 
+// one relaxation step of the relative gauge fixing of Up to U at every site
+// of parity par: h maximises Re tr(h K), K = sum_mu [Up_mu(x) U_mu(x)^+ +
+// Up_mu(x-mu)^+ U_mu(x-mu)], by one pass over the SU(2) subgroups from the
+// identity; then Up_mu(x) <- h Up_mu(x), Up_mu(x-mu) <- Up_mu(x-mu) h^+
+// (links into x have their other end on the other parity, so no two
+// threads touch one link)
+__global__ __launch_bounds__(256) void k_relgauge(int4 L, long V, int par, const double2 *__restrict__ U, double2 *Up)
+{
+    const long s = (long)blockIdx.x * 256 + threadIdx.x;
+    if (s >= V) return;
+    const int Ls[4] = {L.x, L.y, L.z, L.w};
+    int x[4];
+    long r = s;
+    for (int d = 0; d < 4; ++d) {
+        x[d] = (int)(r % Ls[d]);
+        r /= Ls[d];
+    }
+    if (((x[0] + x[1] + x[2] + x[3]) & 1) != par) return;
+    long back[4];
+    for (int mu = 0; mu < 4; ++mu) {
+        int z[4] = {x[0], x[1], x[2], x[3]};
+        z[mu] = (z[mu] - 1 + Ls[mu]) % Ls[mu];
+        back[mu] = site_of(L, z);
+    }
+    M K;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) K.a[i][j] = {0.0, 0.0};
+    for (int mu = 0; mu < 4; ++mu) {
+        M a, b;
+        load(Up, s, mu, a);
+        load(U, s, mu, b);
+        const M f = mm(a, false, b, true);
+        load(Up, back[mu], mu, a);
+        load(U, back[mu], mu, b);
+        const M g = mm(a, true, b, false);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) K.a[i][j] = zadd(K.a[i][j], zadd(f.a[i][j], g.a[i][j]));
+    }
+    M h;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) h.a[i][j] = {i == j ? 1.0 : 0.0, 0.0};
+    const int sub[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int g = 0; g < 3; ++g) {
+        const int i = sub[g][0], j = sub[g][1];
+        Z a, b;
+        const double k = subgroup_part(h, K, i, j, a, b);
+        if (!(k > 0.0)) continue;
+        const double ik = 1.0 / k;
+        const Z vd[2][2] = {{{a.re * ik, -a.im * ik}, {-b.re * ik, -b.im * ik}},
+                            {{b.re * ik, -b.im * ik}, {a.re * ik, a.im * ik}}};
+        left_mul(h, vd, i, j);
+    }
+    for (int mu = 0; mu < 4; ++mu) {
+        M a;
+        load(Up, s, mu, a);
+        store(Up, s, mu, mm(h, false, a, false));
+        load(Up, back[mu], mu, a);
+        store(Up, back[mu], mu, mm(a, false, h, true));
+    }
+}
+
 // cur <- prop at every site whose block was accepted
 __global__ __launch_bounds__(256) void k_merge_blocks(int4 L, int4 B, long V, const int32_t *__restrict__ acc,
                                                       const double2 *__restrict__ prop, double2 *__restrict__ cur)
@@ -283,6 +344,14 @@ void launch_heatbath(const wdr_ctx *c, double beta, const uint8_t *mask, uint64_
         for (int par = 0; par < 2; ++par)
             k_heatbath<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(i4(c->geom.L), V, mask, beta, seed,
                                                                     (uint64_t)(uint32_t)sweep, mu, par, U);
+}
+
+void launch_relgauge(const wdr_ctx *c, const double2 *U, double2 *Up, int sweeps, hipStream_t s)
+{
+    const long V = c->g.V;
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int par = 0; par < 2; ++par)
+            k_relgauge<<<(unsigned)((V + 255) / 256), 256, 0, s>>>(i4(c->geom.L), V, par, U, Up);
 }
 
 void launch_overrelax(const wdr_ctx *c, const uint8_t *mask, double2 *U, hipStream_t s)

@@ -137,6 +137,8 @@ wdr_status block_logdet(wdr_ctx *c, const wdr_gauge *U0, const wdr_gauge *U1, do
 // heat-bath sweep of the masked links of the canonical field U (8 launches)
 void launch_heatbath(const wdr_ctx *c, double beta, const uint8_t *mask, uint64_t seed, int sweep, double2 *U,
                      hipStream_t s);
+// relative gauge fixing of the canonical field Up to U, in place
+void launch_relgauge(const wdr_ctx *c, const double2 *U, double2 *Up, int sweeps, hipStream_t s);
 // over-relaxation sweep of the masked links of the canonical field U
 void launch_overrelax(const wdr_ctx *c, const uint8_t *mask, double2 *U, hipStream_t s);
 // one step of the hierarchical filter on the canonical field U (in place)

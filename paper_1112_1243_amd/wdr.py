@@ -123,6 +123,7 @@ def lib():
         L.wdr_block_fields.argtypes = [P, P, P, P]
         L.wdr_heatbath.argtypes = [P, d, P, ctypes.c_uint64, i32, P, P]
         L.wdr_overrelax.argtypes = [P, P, P, P]
+        L.wdr_relative_gauge.argtypes = [P, P, P, i32, ctypes.POINTER(d), P]
         L.wdr_filter_step.argtypes = [P, d, d, P, i32, ctypes.POINTER(EstParams), ctypes.c_uint64, P, P,
                                       ctypes.POINTER(FilterInfo), P]
         L.wdr_block_schur_ratio.argtypes = [P, P, P, d, P, ctypes.POINTER(EstParams), P, P,
@@ -356,6 +357,14 @@ class Context:
         _check(lib().wdr_heatbath(self.handle, beta, _dev(mask, (self.V, 4), "uint8"), seed, sweep,
                                   _dev(U, (self.V, 4, 3, 3)), _stream()))
         return U
+
+    def relative_gauge(self, U, Up, sweeps):
+        """Relative gauge fixing of Up to U (canonical device fields), Up in
+        place; returns F = sum Re tr(U'_mu(x) U_mu(x)^+) / 3."""
+        F = ctypes.c_double()
+        _check(lib().wdr_relative_gauge(self.handle, _dev(U, (self.V, 4, 3, 3)), _dev(Up, (self.V, 4, 3, 3)), sweeps,
+                                        ctypes.byref(F), _stream()))
+        return F.value
 
     def overrelax(self, mask, U):
         """One over-relaxation sweep of the masked links of U, in place."""

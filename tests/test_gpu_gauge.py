@@ -71,6 +71,23 @@ def test_overrelax_matches_oracle():
     ctx.close()
 
 
+def test_relative_gauge_matches_oracle():
+    """Two sweeps of relative gauge fixing of a gauge-rotated proposal equal
+    the oracle's, with the same functional F."""
+    wdr = _wdr()
+    L = (4, 4, 4, 4)
+    ctx, lat = wdr.Context(L, (2, 2, 2, 2)), oracle.Lattice(L, (2, 2, 2, 2))
+    U = synth.gauge_field(L, 0.5, 817)
+    Up = synth.redraw(U, synth.bernoulli_links(L, 0.2, 818), 0.5, 818)
+    want = oracle.relative_gauge(lat, U, Up, 2)
+    gUp = dev(Up)
+    F = ctx.relative_gauge(dev(U), gUp, 2)
+    assert np.abs(host(gUp) - want).max() < 1e-10
+    assert abs(F - oracle.relative_gauge_functional(U, want)) < 1e-9
+    assert F > oracle.relative_gauge_functional(U, Up)
+    ctx.close()
+
+
 def test_heatbath_active_links_8x8():
     """One sweep of the active links of 4^4 blocks on an 8^4 lattice."""
     wdr = _wdr()
