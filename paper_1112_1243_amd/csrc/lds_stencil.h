@@ -125,6 +125,44 @@ __device__ __forceinline__ void hop_dir_lds_rt(int mu, const typename C2<T>::typ
     }
 }
 
+// The two in-block hops of direction MU at one site with the links held in
+// registers: uf = U_mu(x), ub = U_mu(x - mu) (all three rows), nf / nb the
+// LDS indices (in sh, [12][Vh]) of x + mu and x - mu, or -1 where that hop
+// leaves the block.  Added to acc.
+template <typename T, int MU>
+__device__ __forceinline__ void hop_dir_reg(const typename C2<T>::type *sh, int Vh, const su3<T> &uf,
+                                            const su3<T> &ub, int nf, int nb, spinor<T> &acc)
+{
+    LdsLoader<T> ldr{sh, Vh, 0};
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+        const bool fwd = dir == 0;
+        const int nl = fwd ? nf : nb;
+        if (nl < 0) continue;
+        spinor<T> p;
+        ldr(0, nl, p);
+        vec3<T> a0, a1;
+        A_dn(MU, p.s[2], p.s[3], a0, a1);
+        vec3<T> h0, h1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            h0.c[a] = fwd ? p.s[0].c[a] - a0.c[a] : p.s[0].c[a] + a0.c[a];
+            h1.c[a] = fwd ? p.s[1].c[a] - a1.c[a] : p.s[1].c[a] + a1.c[a];
+        }
+        const vec3<T> c0 = fwd ? mul(uf, h0) : mul_dag(ub, h0);
+        const vec3<T> c1 = fwd ? mul(uf, h1) : mul_dag(ub, h1);
+        vec3<T> d0, d1;
+        Adag_h(MU, c0, c1, d0, d1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
+            acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
+            acc.s[2].c[a] = fwd ? acc.s[2].c[a] - d0.c[a] : acc.s[2].c[a] + d0.c[a];
+            acc.s[3].c[a] = fwd ? acc.s[3].c[a] - d1.c[a] : acc.s[3].c[a] + d1.c[a];
+        }
+    }
+}
+
 // in-block hop sum at site l over all four directions
 template <typename T, int B>
 __device__ __forceinline__ void hop_in_lds(const typename C2<T>::type *sh, int off, const typename C2<T>::type *lk,

@@ -330,18 +330,91 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_block_mr_cube(Geo g, const int3
 // direction mu at site h of that parity and leaves its partial sum in LDS;
 // in the vector phases thread (q, h) owns spin q of site h, so the MR updates
 // and inner products are spread over all threads.  mu and q are uniform per
-// wavefront (Vh is a multiple of 64).  LDS: both half fields, the block's
-// links (two rows) and the four partial sums (FP32: 123 KB for 4^4).
+// wavefront (Vh is a multiple of 64).  Thread (mu, h) keeps the four links
+// of its hops in registers (forward and backward, at site h of either
+// parity, third rows rebuilt once), so the hop phases read only spinors from
+// LDS.  LDS: both half fields and the four partial sums (FP32: 74 KB for
+// 4^4).
 template <typename T, int B> struct DirLds {
     typedef typename C2<T>::type T2;
     static constexpr int Vb = Cube<B>::Vb, Vh = Cube<B>::Vh, NT = 4 * Vh;
     T2 she[12 * Vh];
     T2 sho[12 * Vh];
-    T2 lk[4 * 6 * Vb];
     T2 part[4 * 12 * Vh];
     T red[3][NT / 64];
     T alpha[2];
 };
+
+// The links and LDS neighbour indices of thread (MU, h) of k_block_mr_dir:
+// entry p is for the output site h of parity p (even xe / odd xo): forward
+// link U_mu(x), backward link U_mu(x - mu), and the indices of x + mu and
+// x - mu in the LDS half field of the other parity (-1: outside the block).
+template <typename T> struct HopRegs {
+    su3<T> f[2], b[2];
+    int nf[2], nb[2];
+};
+
+// reads the first two rows of the link at site l, direction MU, and rebuilds
+// the third (in-block links never carry the boundary sign)
+template <typename T, int B, int MU, int ST>
+__device__ __forceinline__ void load_link_rows(const void *Utab_m, int slot, int l, su3<T> &u)
+{
+    constexpr int Vb = Cube<B>::Vb;
+    if constexpr (ST) {
+        const auto *Ug = as_global(static_cast<const h2 *>(Utab_m));
+        const long base = (long)slot * 4 * 6 * Vb + (long)MU * 6 * Vb + l;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) u.m[e / 3][e % 3] = ldh(Ug, base + (long)e * Vb, 1.f);
+    } else {
+        const auto *Ug = as_global(static_cast<const typename C2<T>::type *>(Utab_m));
+        const long base = (long)slot * 4 * 9 * Vb + (long)MU * 9 * Vb + l;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) u.m[e / 3][e % 3] = ldg<T>(Ug, base + (long)e * Vb);
+    }
+    reconstruct(u);
+}
+
+template <typename T, int B, int MU, int ST>
+__device__ __forceinline__ void load_hop_regs(const void *Utab_m, int slot, int h, const int xe[4], const int xo[4],
+                                              HopRegs<T> &R)
+{
+    typedef Cube<B> CB;
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+        const int *x = par ? xo : xe;
+        const int l = par * CB::Vh + h;
+        const int off = par ? 0 : CB::Vh;  // the neighbours have the other parity
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        R.nf[par] = R.nb[par] = -1;
+        if (x[MU] + 1 < B) {
+            y[MU] = x[MU] + 1;
+            R.nf[par] = CB::index(y) - off;
+            load_link_rows<T, B, MU, ST>(Utab_m, slot, l, R.f[par]);
+        }
+        if (x[MU] > 0) {
+            y[MU] = x[MU] - 1;
+            const int nl = CB::index(y);
+            R.nb[par] = nl - off;
+            load_link_rows<T, B, MU, ST>(Utab_m, slot, nl, R.b[par]);
+        }
+    }
+}
+
+// hop phase of thread (mu, h): the in-block hops of direction mu at site h of
+// parity par, neighbours from the LDS half field sh of the other parity
+template <typename T, int B>
+__device__ __forceinline__ void hop_reg_rt(int mu, int par, const typename C2<T>::type *sh, const HopRegs<T> &R,
+                                           spinor<T> &acc)
+{
+    constexpr int Vh = Cube<B>::Vh;
+    zero(acc);
+    switch (mu) {
+    case 0: hop_dir_reg<T, 0>(sh, Vh, R.f[par], R.b[par], R.nf[par], R.nb[par], acc); break;
+    case 1: hop_dir_reg<T, 1>(sh, Vh, R.f[par], R.b[par], R.nf[par], R.nb[par], acc); break;
+    case 2: hop_dir_reg<T, 2>(sh, Vh, R.f[par], R.b[par], R.nf[par], R.nb[par], acc); break;
+    default: hop_dir_reg<T, 3>(sh, Vh, R.f[par], R.b[par], R.nf[par], R.nb[par], acc); break;
+    }
+}
 
 // partial sum of thread (mu, h) into LDS
 template <typename T, int Vh>
@@ -413,18 +486,13 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const i
     CB::coords(Vh + h, xo);
     const long be = (long)slot * 12 * Vb + h, bo = be + Vh;
 
-    // stage the block's links (two rows) in LDS
-    if constexpr (ST) {
-        const auto *Ug = as_global(static_cast<const h2 *>(Utab[m]));
-        const long base = (long)slot * 4 * 6 * Vb;
-        for (int i = tid; i < 4 * 6 * Vb; i += NT) st<T>(S.lk, i, ldh(Ug, base + i, 1.f));
-    } else {
-        const auto *Ug = as_global(static_cast<const T2 *>(Utab[m]));
-        const long base = (long)slot * 4 * 9 * Vb;
-        for (int i = tid; i < 4 * 6 * Vb; i += NT) {
-            const int mu = i / (6 * Vb), e = (i / Vb) % 6, l = i % Vb;
-            st<T>(S.lk, i, ldg<T>(Ug, base + (long)(mu * 9 + e) * Vb + l));
-        }
+    // the links of this thread's hops, in registers
+    HopRegs<T> R;
+    switch (w4) {
+    case 0: load_hop_regs<T, B, 0, ST>(Utab[m], slot, h, xe, xo, R); break;
+    case 1: load_hop_regs<T, B, 1, ST>(Utab[m], slot, h, xe, xo, R); break;
+    case 2: load_hop_regs<T, B, 2, ST>(Utab[m], slot, h, xe, xo, R); break;
+    default: load_hop_regs<T, B, 3, ST>(Utab[m], slot, h, xe, xo, R); break;
     }
 
     // residual of the block system, spin q of even site h (re) and odd site h (ro)
@@ -494,8 +562,7 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const i
     __syncthreads();
     {
         spinor<T> acc;
-        zero(acc);
-        hop_dir_lds_rt<T, B>(w4, S.sho, Vh, S.lk, h, xe, acc);
+        hop_reg_rt<T, B>(w4, 0, S.sho, R, acc);
         put_part<T, Vh>(S.part, w4, h, acc);
     }
     __syncthreads();
@@ -514,8 +581,7 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const i
         __syncthreads();
         {  // t_o = H_oe rho
             spinor<T> acc;
-            zero(acc);
-            hop_dir_lds_rt<T, B>(w4, S.she, 0, S.lk, Vh + h, xo, acc);
+            hop_reg_rt<T, B>(w4, 1, S.she, R, acc);
             put_part<T, Vh>(S.part, w4, h, acc);
         }
         __syncthreads();
@@ -525,8 +591,7 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const i
         __syncthreads();
         {  // H_eo t_o
             spinor<T> acc;
-            zero(acc);
-            hop_dir_lds_rt<T, B>(w4, S.sho, Vh, S.lk, h, xe, acc);
+            hop_reg_rt<T, B>(w4, 0, S.sho, R, acc);
             put_part<T, Vh>(S.part, w4, h, acc);
         }
         __syncthreads();
@@ -578,8 +643,7 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const i
     __syncthreads();
     {
         spinor<T> acc;
-        zero(acc);
-        hop_dir_lds_rt<T, B>(w4, S.she, 0, S.lk, Vh + h, xo, acc);
+        hop_reg_rt<T, B>(w4, 1, S.she, R, acc);
         put_part<T, Vh>(S.part, w4, h, acc);
     }
     __syncthreads();
