@@ -368,6 +368,42 @@ def dslash_roofline(wdr, torch, L=(32, 32, 32, 32), prec_name="f64", reps=30):
             "bytes_per_launch": alg, "bytes_per_site": BYTES_PER_SITE[(prec_name, su3)]}
 
 
+def dslash_f16(wdr, torch, L=(32, 32, 32, 32), reps=32, copies=4):
+    """Average duration of one FP16 stencil launch (k_dslash_h16: FP16
+    fields with per-block scales, FP16 two-row links, FP32 arithmetic).  One
+    launch touches 192 B/site = 201 MB at 32^4, less than the 256 MB Infinity
+    Cache, so launch i reads gauge copy i % copies and input field i % copies
+    (copies = 4: 600 MB pass through between two reads of one copy)."""
+    from paper_1112_1243_amd import synth
+    ctx = wdr.Context(L, (4, 4, 4, 4))
+    V = ctx.V
+    gs, fs = [], []
+    for c in range(copies):
+        U = synth.gauge_field(L, 0.2, 1112124303 + 10 * c)
+        gs.append(ctx.gauge(torch.from_numpy(U).cuda()))
+        del U
+        fs.append(ctx.pack(torch.from_numpy(synth.spinor(L, 5 + c)).cuda(), wdr.F16))
+    outs = [ctx.internal_field(wdr.F16) for _ in range(2)]
+    for i in range(copies):
+        ctx.apply_D_internal(gs[i], 0.155, fs[i], outs[i % 2], wdr.F16)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for i in range(reps):
+        ctx.apply_D_internal(gs[i % copies], 0.155, fs[i % copies], outs[i % 2], wdr.F16)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    alg = 192 * V
+    gbs = alg / (ms * 1e-3) / 1e9
+    del gs, fs, outs
+    ctx.close()
+    return {"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_dslash_h16<4> (FP16 fields, per-block scales, FP16 two-row links)",
+            "avg_launch_us": round(ms * 1e3, 2), "bytes_per_launch": alg, "bytes_per_site": 192,
+            "rotating_copies": copies}
+
+
 def copy_ceiling(torch, reps=10):
     """Bandwidth of a plain elementwise copy of 1 GiB (torch's vectorised
     kernel, 1 GiB read + 1 GiB written): the practical HBM ceiling, and the
@@ -390,7 +426,7 @@ def copy_ceiling(torch, reps=10):
             "achieved": round(2 * 4 * n / (ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
 
 
-def rocprof_summary(path, kernel_regex="k_dslash_dir"):
+def rocprof_summary(path, kernel_regex="k_dslash_dir|k_dslash_h16"):
     """Markdown summary of rocprofv3 CSV output under `path`: per-kernel
     totals (rocprofv3's kernel_stats), the kernels matching kernel_regex split
     by grid size (kernel_trace), and per-dispatch counter means by kernel and
@@ -658,6 +694,8 @@ def main():
         log("dslash f32:", r32)
         roof["f32"] = {k: r32[k] for k in ("achieved", "frac", "traffic", "kernel", "avg_launch_us",
                                            "bytes_per_launch")}
+        roof["f16"] = dslash_f16(wdr, torch)
+        log("dslash f16:", roof["f16"])
         roof["copy_ceiling"] = copy_ceiling(torch)
         log("copy ceiling:", roof["copy_ceiling"])
 

@@ -187,20 +187,28 @@ wdr_status wdr_noise(wdr_ctx *ctx, wdr_noise_kind kind, uint64_t seed, int32_t s
 
 /* Internal layout (for callers that keep fields resident between calls):
  * one spinor field in precision prec (F64: complex double, F32: complex
- * float) occupies wdr_field_bytes(ctx, prec) bytes of device memory, ordered
- * block by block (black blocks first, paper Sec. 3), even sites before odd
- * sites inside a block, component-major inside a block.  wdr_pack converts
- * a canonical FP64 spinor to it (rounding to prec), wdr_unpack back. */
+ * float, F16: complex half) occupies wdr_field_bytes(ctx, prec) bytes of
+ * device memory, ordered block by block (black blocks first, paper Sec. 3),
+ * even sites before odd sites inside a block, component-major inside a
+ * block.  An F16 field stores fp16(v / s_b) with one power-of-two scale s_b
+ * >= max |component| per block (2^ceil(log2 max), 1 for a zero block); the
+ * 12 V half-precision complex values are followed by the block scales (one
+ * float per block, in block-slot order).  wdr_pack converts a canonical FP64
+ * spinor to it (rounding to prec), wdr_unpack back. */
 int64_t wdr_field_bytes(const wdr_ctx *ctx, wdr_prec prec);
 wdr_status wdr_pack(wdr_ctx *ctx, wdr_prec prec, const double *dev_canon, void *dev_internal, void *stream);
 wdr_status wdr_unpack(wdr_ctx *ctx, wdr_prec prec, const void *dev_internal, double *dev_canon, void *stream);
 
 /* out = D in on internal-layout fields of precision prec: exactly one
- * stencil kernel launch on `stream`, no conversion. */
+ * stencil kernel launch on `stream`, no conversion.  F16 (arithmetic in
+ * FP32, output rounded with its own block scales) needs 4^4 blocks and an
+ * SU(3) gauge field (its links are the FP16 first two rows); otherwise
+ * WDR_EINVAL. */
 wdr_status wdr_apply_D_internal(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec,
                                 const void *dev_in, void *dev_out, void *stream);
 
-/* out = D in (canonical spinors), computed in precision `prec`. */
+/* out = D in (canonical spinors), computed in precision `prec` (F16 as for
+ * wdr_apply_D_internal, input rounded by wdr_pack). */
 wdr_status wdr_apply_D(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, const double *dev_in,
                        double *dev_out, void *stream);
 

@@ -117,7 +117,14 @@ wdr_status stencil_entry(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr_prec 
     if ((kind == 1 || kind == 2) && (e = check_blocks_usable(c, false)) != WDR_OK) return e;
     if (prec == WDR_F64) return stencil_call<double>(c, U, kappa, kind, arg, in, out, S(stream));
     if (prec == WDR_F32) return stencil_call<float>(c, U, kappa, kind, arg, in, out, S(stream));
-    set_error("precision must be F64 or F32");
+    if (prec == WDR_F16 && kind == 0) {  // D on FP16 fields with per-block scales
+        Work a(c, f16_field_bytes(c)), b(c, f16_field_bytes(c));
+        if (!a.ok() || !b.ok()) return WDR_ENOMEM;
+        if ((e = wdr_pack(c, WDR_F16, in, a.as<void>(), stream)) != WDR_OK) return e;
+        if ((e = wdr_apply_D_internal(c, U, kappa, WDR_F16, a.as<void>(), b.as<void>(), stream)) != WDR_OK) return e;
+        return wdr_unpack(c, WDR_F16, b.as<void>(), out, stream);
+    }
+    set_error(prec == WDR_F16 ? "FP16 is available for D only" : "precision must be F64, F32 or F16");
     return WDR_EINVAL;
 }
 
@@ -215,7 +222,8 @@ wdr_status wdr_noise(wdr_ctx *c, wdr_noise_kind kind, uint64_t seed, int32_t ste
 
 int64_t wdr_field_bytes(const wdr_ctx *c, wdr_prec prec)
 {
-    if (!c || (prec != WDR_F64 && prec != WDR_F32)) return 0;
+    if (!c || (prec != WDR_F64 && prec != WDR_F32 && prec != WDR_F16)) return 0;
+    if (prec == WDR_F16) return (int64_t)f16_field_bytes(c);
     return (int64_t)field_bytes(c, prec);
 }
 
@@ -229,8 +237,13 @@ wdr_status wdr_pack(wdr_ctx *c, wdr_prec prec, const double *canon, void *intern
     else if (prec == WDR_F32)
         launch_pack_spinor<float>(c->g, reinterpret_cast<const double2 *>(canon), static_cast<float2 *>(internal),
                                   S(stream));
-    else {
-        set_error("precision must be F64 or F32");
+    else if (prec == WDR_F16) {
+        Work t(c, field_bytes(c, WDR_F64));
+        if (!t.ok()) return WDR_ENOMEM;
+        launch_pack_spinor<double>(c->g, reinterpret_cast<const double2 *>(canon), t.as<double2>(), S(stream));
+        launch_to_h16<double>(c->g, all_sys(c, 1), t.as<double2>(), f16_field(c, internal), 0, c->g.nblk, S(stream));
+    } else {
+        set_error("precision must be F64, F32 or F16");
         return WDR_EINVAL;
     }
     return finish(S(stream));
@@ -246,8 +259,14 @@ wdr_status wdr_unpack(wdr_ctx *c, wdr_prec prec, const void *internal, double *c
     else if (prec == WDR_F32)
         launch_unpack_spinor<float>(c->g, static_cast<const float2 *>(internal), reinterpret_cast<double2 *>(canon),
                                     S(stream));
-    else {
-        set_error("precision must be F64 or F32");
+    else if (prec == WDR_F16) {
+        Work t(c, field_bytes(c, WDR_F64));
+        if (!t.ok()) return WDR_ENOMEM;
+        const H16 f = f16_field(c, const_cast<void *>(internal));
+        launch_from_h16(c->g, all_sys(c, 1), H16c{f.v, f.s}, t.as<double2>(), 0, S(stream));
+        launch_unpack_spinor<double>(c->g, t.as<double2>(), reinterpret_cast<double2 *>(canon), S(stream));
+    } else {
+        set_error("precision must be F64, F32 or F16");
         return WDR_EINVAL;
     }
     return finish(S(stream));
@@ -273,8 +292,14 @@ wdr_status wdr_apply_D_internal(wdr_ctx *c, const wdr_gauge *U, double kappa, wd
         launch_dslash<float>(g, one, view(U).u32, HOPS_ALL, -1, 0, static_cast<const float2 *>(in),
                              static_cast<const float2 *>(in), static_cast<float2 *>(out), (float)kappa, 0, g.nblk,
                              S(stream));
-    else {
-        set_error("precision must be F64 or F32");
+    else if (prec == WDR_F16) {
+        const H16 a = f16_field(c, const_cast<void *>(in)), b = f16_field(c, out);
+        if (!launch_dslash_h16(g, U->u16, H16c{a.v, a.s}, b, (float)kappa, S(stream))) {
+            set_error("the FP16 stencil needs 4^4 blocks and an SU(3) gauge field");
+            return WDR_EINVAL;
+        }
+    } else {
+        set_error("precision must be F64, F32 or F16");
         return WDR_EINVAL;
     }
     return finish(S(stream));

@@ -38,18 +38,27 @@ struct TmpGauge {
     bool has16;
 };
 
-// U_i of the path into dst
-void make_path_gauge(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, int i, int N, TmpGauge &dst, hipStream_t s)
+// U_0 .. U_N of one proposal into pts[0 .. N]: the end points are copies, the
+// interior points come from one interpolation launch; then the FP32 and FP16
+// copies of every point
+void make_path_gauges(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, int N, TmpGauge *const *pts,
+                      hipStream_t s)
 {
     const size_t n = (size_t)c->g.V * 36;
-    if (i == 0)
-        (void)hipMemcpyAsync(dst.u64.as<double2>(), U->u64, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
-    else if (i == N)
-        (void)hipMemcpyAsync(dst.u64.as<double2>(), Up->u64, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
-    else
-        launch_interpolate(c->g, U->u64, Up->u64, (double)i / N, dst.u64.as<double2>(), s);
-    launch_convert_gauge_f32(c->g, dst.u64.as<double2>(), dst.u32.as<float2>(), s);
-    if (dst.has16) launch_pack_links_h16(c->g, dst.u64.as<double2>(), dst.u16.as<h2>(), s);
+    (void)hipMemcpyAsync(pts[0]->u64.as<double2>(), U->u64, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(pts[N]->u64.as<double2>(), Up->u64, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
+    std::vector<double> t;
+    std::vector<double2 *> out;
+    for (int i = 1; i < N; ++i) {
+        t.push_back((double)i / N);
+        out.push_back(pts[i]->u64.as<double2>());
+    }
+    if (!t.empty()) launch_interpolate_many(c->g, U->u64, Up->u64, t.data(), out.data(), (int)t.size(), s);
+    for (int i = 0; i <= N; ++i) {
+        TmpGauge &dst = *pts[i];
+        launch_convert_gauge_f32(c->g, dst.u64.as<double2>(), dst.u32.as<float2>(), s);
+        if (dst.has16) launch_pack_links_h16(c->g, dst.u64.as<double2>(), dst.u16.as<h2>(), s);
+    }
 }
 
 // device memory budget for the fields of one chunk of samples
@@ -72,12 +81,15 @@ static wdr_status build_path(wdr_ctx *c, const std::vector<Proposal> &props, con
     path.su3 = 1;
     for (const Proposal &q : props) path.su3 = path.su3 && q.U->su3 && q.Up->su3;  // the geodesic stays in SU(3)
     path.has16 = path.su3 && p.sp.inner == WDR_F16;
-    for (const Proposal &q : props)
+    for (const Proposal &q : props) {
+        std::vector<TmpGauge *> pts;
         for (int i = 0; i <= path.N; ++i) {
             path.pts.emplace_back(new TmpGauge(c, path.has16));
             if (!path.pts.back()->ok()) return WDR_ENOMEM;
-            make_path_gauge(c, q.U, q.Up, i, path.N, *path.pts.back(), s);
+            pts.push_back(path.pts.back().get());
         }
+        make_path_gauges(c, q.U, q.Up, path.N, pts.data(), s);
+    }
     return WDR_OK;
 }
 

@@ -58,6 +58,11 @@ struct Links16 {
     const double *kap = nullptr;
 };
 
+// out = in - kappa H in on one FP16 field (per-block scales) with the FP16
+// two-row links U16 of an SU(3) field; false (nothing launched) unless the
+// blocks are 4^4
+bool launch_dslash_h16(const Geo &g, const h2 *U16, H16c in, H16 out, float kappa, hipStream_t s);
+
 // out(x) = diag(x) - kappa * sum_{selected hops} [...] in(y), per system
 //   diag    NULL (no diagonal term) or a field supplying the diagonal term
 //   slots   [slot0, slot0 + nslots) receive output; other slots untouched
@@ -159,6 +164,10 @@ void launch_noise(const Geo &g, const Sys &sy, int kind, uint64_t seed, const ui
                   const int32_t *ks, int black_only, double2 *out, hipStream_t s);
 // out = U_t = exp(t log(U' U^+)) U on internal FP64 links
 void launch_interpolate(const Geo &g, const double2 *U, const double2 *Up, double t, double2 *out, hipStream_t s);
+// several points t[k] of the same path into out[k] (one decomposition of
+// U' U^+ per link for all of them)
+void launch_interpolate_many(const Geo &g, const double2 *U, const double2 *Up, const double *t, double2 *const *out,
+                             int n, hipStream_t s);
 void launch_site_maps(const Geo &g, int32_t *bid, int32_t *col, int32_t *par, int32_t *pos, hipStream_t s);
 void launch_active_links(const Geo &g, int lo, int hi, uint8_t *mask, hipStream_t s);
 

@@ -103,9 +103,17 @@ __device__ void herm_jacobi(M3 &K, M3 &V, double ev[3])
     for (int i = 0; i < 3; ++i) ev[i] = K.a[i][i].re;
 }
 
+// Up to PATH_OUTS points of one path per launch: the decomposition of W is
+// done once per link and serves every t.
+constexpr int PATH_OUTS = 32;
+struct PathOuts {
+    double t[PATH_OUTS];
+    double2 *p[PATH_OUTS];
+    int n;
+};
+
 __global__ __launch_bounds__(256) void k_interpolate(Geo g, const double2 *__restrict__ U,
-                                                     const double2 *__restrict__ Up, double t,
-                                                     double2 *__restrict__ out)
+                                                     const double2 *__restrict__ Up, PathOuts outs)
 {
     const int l = blockIdx.x * 256 + threadIdx.x;
     if (l >= g.Vb) return;
@@ -120,7 +128,8 @@ __global__ __launch_bounds__(256) void k_interpolate(Geo g, const double2 *__res
         same = same && a.x == b.x && a.y == b.y;
     }
     if (same) {
-        for (int e = 0; e < 9; ++e) out[base + (long)e * g.Vb] = U[base + (long)e * g.Vb];
+        for (int k = 0; k < outs.n; ++k)
+            for (int e = 0; e < 9; ++e) outs.p[k][base + (long)e * g.Vb] = make_double2(u.a[e / 3][e % 3].re, u.a[e / 3][e % 3].im);
         return;
     }
     // W = U' U^+
@@ -177,32 +186,49 @@ __global__ __launch_bounds__(256) void k_interpolate(Geo g, const double2 *__res
         int j = th[0] <= th[1] ? (th[0] <= th[2] ? 0 : 2) : (th[1] <= th[2] ? 1 : 2);
         th[j] += 2.0 * M_PI;
     }
-    // W^t = V diag(e^{i t theta}) V^+ ; out = W^t U
-    zc e[3];
-    for (int j = 0; j < 3; ++j) {
-        double s2, c2;
-        sincos(t * th[j], &s2, &c2);
-        e[j] = mk<double>(c2, s2);
-    }
-    M3 Wt;
-    for (int i = 0; i < 3; ++i)
-        for (int k = 0; k < 3; ++k) {
-            zc acc = mk<double>(0.0, 0.0);
-            for (int j = 0; j < 3; ++j) acc = acc + e[j] * (V.a[i][j] * cj(V.a[k][j]));
-            Wt.a[i][k] = acc;
+    // W^t = V diag(e^{i t theta}) V^+ ; out = W^t U, for every requested t
+    for (int o = 0; o < outs.n; ++o) {
+        const double t = outs.t[o];
+        zc e[3];
+        for (int j = 0; j < 3; ++j) {
+            double s2, c2;
+            sincos(t * th[j], &s2, &c2);
+            e[j] = mk<double>(c2, s2);
         }
-    const M3 R = mmul(Wt, u);
-    for (int ee = 0; ee < 9; ++ee) {
-        zc v = R.a[ee / 3][ee % 3];
-        out[base + (long)ee * g.Vb] = make_double2(v.re, v.im);
+        M3 Wt;
+        for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) {
+                zc acc = mk<double>(0.0, 0.0);
+                for (int j = 0; j < 3; ++j) acc = acc + e[j] * (V.a[i][j] * cj(V.a[k][j]));
+                Wt.a[i][k] = acc;
+            }
+        const M3 R = mmul(Wt, u);
+        for (int ee = 0; ee < 9; ++ee) {
+            zc v = R.a[ee / 3][ee % 3];
+            outs.p[o][base + (long)ee * g.Vb] = make_double2(v.re, v.im);
+        }
     }
 }
 
 }  // namespace
 
+void launch_interpolate_many(const Geo &g, const double2 *U, const double2 *Up, const double *t, double2 *const *out,
+                             int n, hipStream_t s)
+{
+    for (int k0 = 0; k0 < n; k0 += PATH_OUTS) {
+        PathOuts o;
+        o.n = n - k0 < PATH_OUTS ? n - k0 : PATH_OUTS;
+        for (int k = 0; k < o.n; ++k) {
+            o.t[k] = t[k0 + k];
+            o.p[k] = out[k0 + k];
+        }
+        k_interpolate<<<dim3((g.Vb + 255) / 256, g.nblk * 4), 256, 0, s>>>(g, U, Up, o);
+    }
+}
+
 void launch_interpolate(const Geo &g, const double2 *U, const double2 *Up, double t, double2 *out, hipStream_t s)
 {
-    k_interpolate<<<dim3((g.Vb + 255) / 256, g.nblk * 4), 256, 0, s>>>(g, U, Up, t, out);
+    launch_interpolate_many(g, U, Up, &t, &out, 1, s);
 }
 
 }  // namespace wdr

@@ -76,6 +76,14 @@ inline size_t field_bytes(const wdr_ctx *c, int prec)
     return (size_t)c->g.V * 12 * (prec == WDR_F64 ? sizeof(double2) : prec == WDR_F32 ? sizeof(float2) : 4);
 }
 inline long field_n(const wdr_ctx *c) { return (long)c->g.V * 12; }
+// an FP16 field of the C ABI: 12 V FP16 complex values (internal layout),
+// then one float scale per block slot
+inline size_t f16_field_bytes(const wdr_ctx *c) { return (size_t)c->g.V * 12 * 4 + (size_t)c->g.nblk * 4; }
+inline wdr::H16 f16_field(const wdr_ctx *c, void *p)
+{
+    wdr::h2 *v = static_cast<wdr::h2 *>(p);
+    return wdr::H16{v, reinterpret_cast<float *>(v + (size_t)c->g.V * 12)};
+}
 
 // per-system gauge tables (device arrays of M pointers)
 struct GaugeTab {

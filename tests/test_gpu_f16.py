@@ -1,0 +1,176 @@
+"""GPU parity of the FP16 storage format and the FP16 stencil (the inner
+precision of the 32^4 workload: FP16 values with one power-of-two scale per
+block of Sec. 3, arithmetic in FP32; the operator is the Wilson-Dirac
+operator of Sec. 5) through the C ABI.
+
+The storage rule is emulated here from its definition: per block,
+s = 2^ceil(log2 m) with m the largest |component| (as FP32), values
+fp16(fp32(v) / s) rounded to nearest even, read back exactly as fp16 * s.
+Packing is then bit-exact.  The stencil is compared with the FP64 oracle
+applied to the same rounded input and rounded links (first two rows in FP16,
+third row rebuilt as the conjugated cross product): what remains is FP32
+arithmetic and the rounding of the output, at most half an FP16 ulp of the
+top binade, 2^-12 s_out <= 2^-11 max |out| per block."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1112_1243_amd import synth
+from tests.gpu_util import dev, host, rel, say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _wdr():
+    torch_cuda()
+    from paper_1112_1243_amd import wdr
+    return wdr
+
+
+def _pow2_at_least(m):
+    """2^ceil(log2 m) per entry (1 where m == 0), from frexp as on the device."""
+    f, e = np.frexp(m.astype(np.float32))
+    p = np.ldexp(np.float32(1.0), np.where(f == 0.5, e - 1, e)).astype(np.float32)
+    return np.where(m > 0, p, np.float32(1.0))
+
+
+def _round16(v32, inv):
+    return (v32 * inv).astype(np.float16)
+
+
+def f16_spinor(lat, psi):
+    """(rounded field as complex128, block scales in block-slot order)."""
+    perm = oracle.block_order(lat)
+    Vb = int(np.prod(lat.B))
+    nb = lat.V // Vb
+    blk = psi[perm].reshape(nb, Vb * 12)
+    re, im = blk.real.astype(np.float32), blk.imag.astype(np.float32)
+    m = np.maximum(np.abs(re).max(axis=1), np.abs(im).max(axis=1))
+    s = _pow2_at_least(m)
+    inv = (np.float32(1.0) / s)[:, None]
+    hr, hi = _round16(re, inv), _round16(im, inv)
+    q = (hr.astype(np.float32) * s[:, None]).astype(np.float64) + 1j * (hi.astype(np.float32) * s[:, None]).astype(
+        np.float64)
+    out = np.empty_like(psi)
+    out[perm] = q.reshape(nb * Vb, 4, 3)
+    return out, s
+
+
+def f16_links(U):
+    """Links as the FP16 stencil uses them: rows 0 and 1 rounded to FP16 (via
+    FP32), row 2 rebuilt as conj(row0 x row1)."""
+    r = (U.real.astype(np.float32).astype(np.float16).astype(np.float64) +
+         1j * U.imag.astype(np.float32).astype(np.float16).astype(np.float64))
+    out = r.copy()
+    out[..., 2, :] = np.conj(np.cross(r[..., 0, :], r[..., 1, :]))
+    return out
+
+
+def _block_max(lat, f):
+    perm = oracle.block_order(lat)
+    Vb = int(np.prod(lat.B))
+    return np.abs(np.concatenate([f.real, f.imag], axis=-1))[perm].reshape(lat.V // Vb, -1).max(axis=1)
+
+
+CASES = [((8, 8, 8, 8), (1, 1, 1, -1)), ((8, 8, 8, 16), (1, 1, 1, 1)), ((16, 8, 8, 8), (1, -1, 1, 1))]
+
+
+@pytest.mark.parametrize("L,bc", CASES)
+def test_pack_bit_exact(L, bc):
+    """Packing rounds to FP16 with the block scales of the storage rule, bit for
+    bit; an all-zero block gets scale 1 and stays zero."""
+    wdr = _wdr()
+    B = (4, 4, 4, 4)
+    ctx, lat = wdr.Context(L, B, bc), oracle.Lattice(L, B, bc)
+    psi = synth.spinor(L, 1601) * 3.7
+    bid, _, _ = lat.maps()
+    psi[bid == 1] = 0
+    want, s_want = f16_spinor(lat, psi)
+    f = ctx.pack(dev(psi), wdr.F16)
+    assert f.numel() == ctx.V * 12 * 4 + ctx.nblocks * 4
+    torch = torch_cuda()
+    s_got = host(f[ctx.V * 12 * 4:].view(torch.float32))
+    got = host(ctx.unpack(f, wdr.F16))
+    say("f16 pack max |q - psi| / max", rel(got, psi))
+    assert np.array_equal(s_got, s_want)
+    assert np.array_equal(got, want)
+    assert not np.any(got[bid == 1])
+    ctx.close()
+
+
+@pytest.mark.parametrize("L,bc", CASES)
+def test_apply_D_f16(L, bc):
+    """FP16 stencil against the FP64 oracle on the rounded input and links
+    (bound in the module docstring), and against the exact operator."""
+    wdr = _wdr()
+    B = (4, 4, 4, 4)
+    ctx, lat = wdr.Context(L, B, bc), oracle.Lattice(L, B, bc)
+    U = synth.gauge_field(L, 0.6, 1602)
+    psi = synth.spinor(L, 1603)
+    gU = ctx.gauge(dev(U))
+    k = 0.155
+    q, _ = f16_spinor(lat, psi)
+    want = oracle.apply_D(lat, f16_links(U), k, q)
+    got = host(ctx.unpack(ctx.apply_D_internal(gU, k, ctx.pack(dev(psi), wdr.F16), ctx.internal_field(wdr.F16),
+                                               wdr.F16), wdr.F16))
+    perm = oracle.block_order(lat)
+    Vb = 256
+    err = np.abs(np.concatenate([(got - want).real, (got - want).imag], axis=-1))[perm].reshape(lat.V // Vb, -1)
+    bound = 2.0 ** -11 * _block_max(lat, want) * (1 + 1e-5) + 4e-6 * np.abs(want).max()
+    exact = oracle.apply_D(lat, U, k, psi)
+    say("f16 D: max err / bound", float((err.max(axis=1) / bound).max()), "rel vs exact", rel(got, exact))
+    assert np.all(err.max(axis=1) <= bound)
+    assert rel(got, exact) < 4e-3
+    # the canonical entry point gives the same numbers
+    assert np.array_equal(host(ctx.apply_D(gU, k, dev(psi), wdr.F16)), got)
+    del gU
+    ctx.close()
+
+
+def test_apply_D_f16_full_size():
+    """32^4, the lattice of the FP16 workload, every site against the exact
+    FP64 operator and sampled blocks against the rounded-input bound."""
+    wdr = _wdr()
+    L, B = (32, 32, 32, 32), (4, 4, 4, 4)
+    ctx, lat = wdr.Context(L, B), oracle.Lattice(L, B)
+    U = synth.gauge_field(L, 0.2, 1604)
+    psi = synth.spinor(L, 1605)
+    gU = ctx.gauge(dev(U))
+    k = 0.155
+    got = host(ctx.apply_D(gU, k, dev(psi), wdr.F16))
+    exact = oracle.apply_D(lat, U, k, psi)
+    say("f16 D 32^4 rel vs exact", rel(got, exact))
+    assert rel(got, exact) < 4e-3
+    q, _ = f16_spinor(lat, psi)
+    want = oracle.apply_D(lat, f16_links(U), k, q)
+    d = got - want
+    bm = _block_max(lat, want)
+    perm = oracle.block_order(lat)
+    err = np.abs(np.concatenate([d.real, d.imag], axis=-1))[perm].reshape(lat.V // 256, -1).max(axis=1)
+    assert np.all(err <= 2.0 ** -11 * bm * (1 + 1e-5) + 4e-6 * np.abs(want).max())
+    del gU
+    ctx.close()
+
+
+def test_f16_errors():
+    wdr = _wdr()
+    L = (8, 8, 8, 8)
+    psi = dev(synth.spinor(L, 1606))
+    small = wdr.Context(L, (2, 2, 2, 2))
+    gs = small.gauge(dev(synth.gauge_field(L, 0.5, 1607)))
+    with pytest.raises(wdr.WdrError) as e:
+        small.apply_D(gs, 0.13, psi, wdr.F16)
+    assert e.value.status == wdr.EINVAL
+    ctx = wdr.Context(L, (4, 4, 4, 4))
+    gN = ctx.gauge(dev(1.01 * synth.gauge_field(L, 0.5, 1608)))
+    assert not gN.su3
+    with pytest.raises(wdr.WdrError) as e:
+        ctx.apply_D(gN, 0.13, psi, wdr.F16)
+    assert e.value.status == wdr.EINVAL
+    gU = ctx.gauge(dev(synth.gauge_field(L, 0.5, 1609)))
+    with pytest.raises(wdr.WdrError) as e:
+        ctx.apply_Dblock(gU, 0.13, psi, 0, wdr.F16)
+    assert e.value.status == wdr.EINVAL
+    del gs, gN, gU
+    small.close()
+    ctx.close()
