@@ -33,7 +33,8 @@ HBM_PEAK_GBS = 8000.0
 # four links (each neighbour spinor and link counted once).  SU(3) fields are
 # read as two rows per link (12 reals), other fields as 18 reals.
 BYTES_PER_SITE = {("f64", True): 96 * 8, ("f32", True): 96 * 4, ("f64", False): 120 * 8, ("f32", False): 120 * 4}
-KERNEL = {"f64": "k_dslash_dir<double, all hops, B=4, R2=1>", "f32": "k_dslash_dir<float, all hops, B=4, R2=1>"}
+KERNEL = {"f64": "k_dslash_blk<double, B=4, all hops> (SU(3) links, two rows)",
+          "f32": "k_dslash_blk<float, B=4, all hops> (SU(3) links, two rows)"}
 # HBM traffic per launch from rocprofv3 counter runs on the committed kernel
 # sources (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0: a plain 1 GiB elementwise copy
 # reads 1 GiB as FETCH_SIZE 0.5 GiB because every read request on gfx950 is
@@ -363,7 +364,8 @@ def dslash_roofline(wdr, torch, L=(32, 32, 32, 32), prec_name="f64", reps=30):
     traffic = counted_traffic(prec_name) if su3 else None
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": KERNEL[prec_name] if su3 else KERNEL[prec_name].replace("R2=1", "R2=0"),
+            "kernel": KERNEL[prec_name] if su3 else "k_dslash_dir<%s, all hops, B=4, R2=0>" % (
+                "double" if prec_name == "f64" else "float"),
             "lattice": "x".join(map(str, L)), "avg_launch_us": round(ms * 1e3, 2),
             "bytes_per_launch": alg, "bytes_per_site": BYTES_PER_SITE[(prec_name, su3)]}
 
@@ -426,7 +428,7 @@ def copy_ceiling(torch, reps=10):
             "achieved": round(2 * 4 * n / (ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
 
 
-def rocprof_summary(path, kernel_regex="k_dslash_dir|k_dslash_h16"):
+def rocprof_summary(path, kernel_regex="k_dslash"):
     """Markdown summary of rocprofv3 CSV output under `path`: per-kernel
     totals (rocprofv3's kernel_stats), the kernels matching kernel_regex split
     by grid size (kernel_trace), and per-dispatch counter means by kernel and

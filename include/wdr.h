@@ -144,6 +144,19 @@ wdr_status wdr_ctx_destroy(wdr_ctx *ctx);
 int64_t wdr_ctx_volume(const wdr_ctx *ctx);
 int32_t wdr_ctx_nblocks(const wdr_ctx *ctx);
 
+/* Stencil kernel for the full operator D and the Dirichlet block operators
+ * D_b (the hops of Sec. 3's blocks) on SU(3) fields with 4^4 blocks; the
+ * result is the same operator either way, up to rounding order.
+ * WDR_STENCIL_AUTO (the default): block-staged when a launch has at least
+ * 2048 workgroups (blocks x systems), else direction-split.
+ * WDR_STENCIL_DIR: direction-split (four workgroups per block, a wavefront
+ * per direction).  WDR_STENCIL_BLK: block-staged (one workgroup per block,
+ * the block's input read once into LDS).  Other operators (even-odd halves,
+ * block-interaction hops) always use the direction-split kernel.  Applies to
+ * later calls on ctx; EINVAL for another value. */
+typedef enum { WDR_STENCIL_AUTO = 0, WDR_STENCIL_DIR = 1, WDR_STENCIL_BLK = 2 } wdr_stencil;
+wdr_status wdr_ctx_set_stencil(wdr_ctx *ctx, int32_t choice);
+
 /* Geometry maps (Sec. 3), written to caller device buffers of V int32:
  * block id (lexicographic block coordinates), block colour, site parity and
  * position of the site in the black-first block ordering. Any may be NULL. */

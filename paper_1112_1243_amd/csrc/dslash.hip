@@ -4,9 +4,12 @@
 // Hops are spin-projected: only the 2-spin half spinor is multiplied by the
 // link, and the lower two spins are reconstructed from it.
 //
-// 4^4 blocks (every workload here): k_dslash_dir, one wavefront per
-// direction over 64 sites of a block, partial sums combined in LDS; for SU(3)
-// fields it reads two rows per link and rebuilds the third.  Other block
+// 4^4 blocks (every workload here): k_dslash_blk for D and D_b on SU(3)
+// fields (block input staged in LDS, one lane per site); k_dslash_dir for
+// the rest (even-odd halves, cross-boundary hops, gamma_5-conjugated forms,
+// general links), one wavefront per direction over 64 sites of a block,
+// partial sums combined in LDS.  Both read two rows per SU(3) link and
+// rebuild the third.  Other block
 // shapes: k_dslash, one lane per site and 256 consecutive sites of one block
 // per workgroup.  In both, a wavefront reads each spinor / link component of
 // 64 consecutive sites as one contiguous 512 B (FP32) or 1 KiB (FP64) run.
@@ -159,6 +162,141 @@ __global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__rest
     }
 }
 
+
+// Block-staged stencil for B^4 blocks (full-lattice operator D or the
+// Dirichlet block operator D_b, diagonal term = the input): one workgroup per
+// block and one lane per site.  The block's input spinor is read once into
+// LDS; in-block neighbours come from there, only the neighbours across the
+// block faces from global memory; links (two rows, third rebuilt) from
+// global memory.  Against k_dslash_dir this cuts the vector-memory
+// instructions per site (each in-block spinor is read once instead of once
+// per neighbour), which bound that kernel.
+template <typename T, int B, int MU, int HOPS>
+__device__ __forceinline__ void hop_blk(const T2<T> (*sh)[Cube<B>::Vb], const __attribute__((address_space(1))) T2<T> *in,
+                                        const __attribute__((address_space(1))) T2<T> *Ug, int slot, const int nbr[8],
+                                        int l, const int x[4], int pin, spinor<T> &acc, T wrap_f, T wrap_b)
+{
+    typedef Cube<B> CB;
+    constexpr int Vb = CB::Vb;
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+        const bool fwd = dir == 0;
+        const bool inside = fwd ? x[MU] + 1 < B : x[MU] > 0;
+        if (HOPS == HOPS_IN && !inside) continue;
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        y[MU] = fwd ? (inside ? x[MU] + 1 : 0) : (inside ? x[MU] - 1 : B - 1);
+        const int ns = inside ? slot : nbr[2 * MU + dir];
+        const int nl = CB::index(y);
+        spinor<T> p;
+        if (inside) {
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) p.s[sp].c[a] = ld<T>(&sh[3 * sp + a][0], nl);
+        } else {
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) p.s[sp].c[a] = ldg<T>(in, ns * 12 * Vb + nl + pin + (3 * sp + a) * Vb);
+        }
+        su3<T> u;
+        const int ls = fwd ? slot : ns, ll = fwd ? l : nl;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) u.m[e / 3][e % 3] = ldg<T>(Ug, (ls * 4 + MU) * 9 * Vb + ll + pin + e * Vb);
+        const T sg = fwd ? wrap_f : wrap_b;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int a = (c + 1) % 3, b = (c + 2) % 3;
+            const cx<T> v = u.m[0][a] * u.m[1][b] - u.m[0][b] * u.m[1][a];
+            u.m[2][c] = mk<T>(sg * v.re, -sg * v.im);
+        }
+        vec3<T> a0, a1;
+        A_dn(MU, p.s[2], p.s[3], a0, a1);
+        vec3<T> h0, h1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            h0.c[a] = fwd ? p.s[0].c[a] - a0.c[a] : p.s[0].c[a] + a0.c[a];
+            h1.c[a] = fwd ? p.s[1].c[a] - a1.c[a] : p.s[1].c[a] + a1.c[a];
+        }
+        const vec3<T> c0 = fwd ? mul(u, h0) : mul_dag(u, h0);
+        const vec3<T> c1 = fwd ? mul(u, h1) : mul_dag(u, h1);
+        vec3<T> d0, d1;
+        Adag_h(MU, c0, c1, d0, d1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
+            acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
+            acc.s[2].c[a] = fwd ? acc.s[2].c[a] - d0.c[a] : acc.s[2].c[a] + d0.c[a];
+            acc.s[3].c[a] = fwd ? acc.s[3].c[a] - d1.c[a] : acc.s[3].c[a] + d1.c[a];
+        }
+    }
+}
+
+template <typename T, int B, int HOPS>
+__global__ __launch_bounds__(Cube<B>::Vb) void k_dslash_blk(Geo g, const int32_t *__restrict__ active,
+                                                           const int32_t *__restrict__ list, UTab<T> Utab,
+                                                           const double *__restrict__ kap, int kneg, long n,
+                                                           const int32_t *__restrict__ sched,
+                                                           const T2<T> *__restrict__ in, T2<T> *__restrict__ out,
+                                                           T kappa)
+{
+    typedef Cube<B> CB;
+    constexpr int Vb = CB::Vb;
+    __shared__ T2<T> sh[12][Vb];  // the block's input, component-major
+    const int m = sys_at(list, blockIdx.y);
+    if (active && !active[m]) return;
+    if (kap) kappa = kneg ? -(T)kap[m] : (T)kap[m];
+    const int slot = sched[blockIdx.x];
+    const int l = threadIdx.x;
+    const auto *Ug = as_global(Utab[m]);
+    const auto *ing = as_global(in + m * n);
+    const long base = (long)slot * 12 * Vb + l;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) st<T>(&sh[c][0], l, ldg<T>(ing, base + c * Vb));
+    int x[4];
+    CB::coords(l, x);
+    int nbr[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
+    const int bl = g.slot_blk[slot];
+    __syncthreads();
+    spinor<T> acc;
+    zero(acc);
+    // directions one at a time (the loop stays rolled; `pin`, a zero the
+    // compiler cannot see through, keeps each direction's loads inside it)
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        int pin = 0;
+        asm volatile("" : "+s"(pin));
+        // boundary sign of this site's links that wrap around the lattice
+        T wf = 1, wb = 1;
+        if (HOPS == HOPS_ALL && g.bc[mu] < 0) {
+            int b2 = bl;
+            for (int d = 0; d < mu; ++d) b2 /= g.NB[d];
+            const int nmu = b2 % g.NB[mu];
+            if (nmu == g.NB[mu] - 1 && x[mu] == B - 1) wf = -1;
+            if (nmu == 0 && x[mu] == 0) wb = -1;
+        }
+        switch (mu) {
+        case 0: hop_blk<T, B, 0, HOPS>(sh, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
+        case 1: hop_blk<T, B, 1, HOPS>(sh, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
+        case 2: hop_blk<T, B, 2, HOPS>(sh, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
+        default: hop_blk<T, B, 3, HOPS>(sh, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
+        }
+    }
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int c = 3 * sp + a;
+            st_nt<T>(out, m * n + base + (long)c * Vb, ld<T>(&sh[c][0], l) - scale(kappa, acc.s[sp].c[a]));
+        }
+}
+
+// below this many workgroups (blocks x systems) the 4-workgroups-per-block
+// k_dslash_dir keeps more of the GPU busy
+constexpr long BLK_MIN_WORKGROUPS = 2048;
+
 template <typename T, int B>
 bool launch_cube(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int dag, const T2<T> *in,
                  const T2<T> *diag, T2<T> *out, T kappa, int slot0, int nslots, hipStream_t s)
@@ -169,9 +307,23 @@ bool launch_cube(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int
     const int nt = par < 0 ? Cube<B>::Vb : Cube<B>::Vh;
     static_assert(Cube<B>::Vh % 64 == 0, "sites of one parity fill whole wavefronts");
     const int chunks = nt / 64;
+    const int32_t *sc = g.sched[si];
+    // D or D_b with the input as diagonal term, with enough blocks to fill
+    // the GPU (one workgroup per block): the block-staged kernel
+    const bool big = (long)nslots * sy.launch_m() >= BLK_MIN_WORKGROUPS;
+    if (par < 0 && !dag && U.su3 && diag == in && (hops == HOPS_ALL || hops == HOPS_IN) &&
+        (g.stencil == WDR_STENCIL_BLK || (g.stencil == WDR_STENCIL_AUTO && big))) {
+        const dim3 gb(nslots, sy.launch_m());
+        if (hops == HOPS_ALL)
+            k_dslash_blk<T, B, HOPS_ALL><<<gb, Cube<B>::Vb, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n,
+                                                                   sc, in, out, kappa);
+        else
+            k_dslash_blk<T, B, HOPS_IN><<<gb, Cube<B>::Vb, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n,
+                                                                  sc, in, out, kappa);
+        return true;
+    }
     const dim3 grid(nslots * chunks, sy.launch_m());
     const int xcd8 = nslots % 8 == 0;
-    const int32_t *sc = g.sched[si];
 #define WDR_DIR(H, D, R)                                                                                     \
     k_dslash_dir<T, H, B, D, R><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, sc, par, chunks, xcd8, in, diag, out, \
                                                      kappa)

@@ -202,6 +202,7 @@ wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)
     g.Vh = (int)Vb / 2;
     g.nblk = nblk;
     g.colourable = colourable;
+    g.stencil = WDR_STENCIL_AUTO;
 
     // in-block order: even sites then odd sites, lexicographic within each
     std::vector<uint32_t> loc_coord(Vb);
@@ -341,6 +342,21 @@ wdr_status wdr_ctx_destroy(wdr_ctx *c)
 
 int64_t wdr_ctx_volume(const wdr_ctx *c) { return c ? c->g.V : 0; }
 int32_t wdr_ctx_nblocks(const wdr_ctx *c) { return c ? c->g.nblk : 0; }
+
+wdr_status wdr_ctx_set_stencil(wdr_ctx *c, int32_t choice)
+{
+    if (!c) {
+        set_error("null context");
+        return WDR_EINVAL;
+    }
+    if (choice < WDR_STENCIL_AUTO || choice > WDR_STENCIL_BLK) {
+        set_error("stencil choice must be WDR_STENCIL_AUTO, WDR_STENCIL_DIR or WDR_STENCIL_BLK");
+        return WDR_EINVAL;
+    }
+    c->g.stencil = choice;
+    if (c->twin) c->twin->g.stencil = choice;
+    return WDR_OK;
+}
 
 wdr_status wdr_gauge_create(wdr_ctx *c, const double *dev_U, wdr_gauge **out, void *stream)
 {

@@ -48,6 +48,7 @@ struct Geo {
     // white slots and all slots (index 0, 1, 2): spatially contiguous runs
     // of blocks are dealt to the same XCD (workgroup i runs on XCD i % 8)
     const int32_t *sched[3];
+    int stencil;  // wdr_stencil choice for D and D_b on 4^4 blocks
 };
 
 // which schedule covers the slot range [slot0, slot0 + n), or -1

@@ -20,6 +20,7 @@ LIB_PATH = os.environ.get("WDR_LIB", os.path.join(_HERE, "libwdr.so"))
 # ---------------------------------------------------------------- constants (wdr.h)
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
 F64, F32, F16 = 0, 1, 2
+STENCIL_AUTO, STENCIL_DIR, STENCIL_BLK = 0, 1, 2
 NOISE_Z2, NOISE_GAUSS = 0, 1
 OP_FULL, OP_SCHUR, OP_BLOCKS, OP_DD = 0, 1, 2, 3
 SOLVER_FGCR_SAP, SOLVER_CGNE = 0, 1
@@ -92,6 +93,7 @@ def lib():
         L.wdr_ctx_volume.restype = ctypes.c_int64
         L.wdr_ctx_nblocks.argtypes = [P]
         L.wdr_ctx_nblocks.restype = ctypes.c_int32
+        L.wdr_ctx_set_stencil.argtypes = [P, i32]
         L.wdr_site_maps.argtypes = [P, P, P, P, P, P]
         L.wdr_active_links.argtypes = [P, i32, i32, P, P]
         L.wdr_gauge_create.argtypes = [P, P, ctypes.POINTER(P), P]
@@ -202,6 +204,10 @@ class Context:
         self.V = int(lib().wdr_ctx_volume(h))
         self.nblocks = int(lib().wdr_ctx_nblocks(h))
         self.device = device
+
+    def set_stencil(self, choice: int):
+        """Stencil kernel for D and D_b (STENCIL_AUTO, STENCIL_DIR, STENCIL_BLK)."""
+        _check(lib().wdr_ctx_set_stencil(self.handle, int(choice)))
 
     def close(self):
         if getattr(self, "handle", None):

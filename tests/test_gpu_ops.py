@@ -259,3 +259,44 @@ def test_schur():
     assert np.all(got[~oracle.colour_mask(lat, 0)] == 0)
     del gU
     ctx.close()
+
+
+@pytest.mark.parametrize("choice", ["dir", "blk"])
+@pytest.mark.parametrize("L,bc", [((8, 8, 8, 8), (1, 1, 1, -1)), ((8, 16, 8, 8), (1, -1, 1, 1))])
+def test_stencil_choices(choice, L, bc):
+    """Both stencil kernels for D and the Dirichlet block operators (forced,
+    whatever the launch size) against the oracle, FP64 and FP32; the forced
+    choice reaches every call of the context."""
+    from paper_1112_1243_amd import wdr
+    B = (4, 4, 4, 4)
+    lat = oracle.Lattice(L, B, bc)
+    ctx = _ctx(L, B, bc)
+    ctx.set_stencil(wdr.STENCIL_BLK if choice == "blk" else wdr.STENCIL_DIR)
+    U = synth.gauge_field(L, 0.6, 121)
+    psi = synth.spinor(L, 122)
+    gU = ctx.gauge(dev(U))
+    k = 0.143
+    want = oracle.apply_D(lat, U, k, psi)
+    assert rel(host(ctx.apply_D(gU, k, dev(psi), wdr.F64)), want) < 1e-14
+    assert rel(host(ctx.apply_D(gU, k, dev(psi), wdr.F32)), want) < 2e-6
+    for colour in (0, 1, 2):
+        want = oracle.apply_Dblock(lat, U, k, psi, colour)
+        assert rel(host(ctx.apply_Dblock(gU, k, dev(psi), colour, wdr.F64)), want) < 1e-14
+        assert rel(host(ctx.apply_Dblock(gU, k, dev(psi), colour, wdr.F32)), want) < 2e-6
+    # internal fields (one kernel launch) give the same numbers as the canonical call
+    a = ctx.pack(dev(psi), wdr.F64)
+    b = ctx.apply_D_internal(gU, k, a, ctx.internal_field(wdr.F64), wdr.F64)
+    assert rel(host(ctx.unpack(b, wdr.F64)), oracle.apply_D(lat, U, k, psi)) < 1e-14
+    del gU
+    ctx.close()
+
+
+def test_stencil_choice_errors():
+    from paper_1112_1243_amd import wdr
+    ctx = _ctx((8, 8, 8, 8), (4, 4, 4, 4), (1, 1, 1, 1))
+    for bad in (-1, 3):
+        with pytest.raises(wdr.WdrError) as e:
+            ctx.set_stencil(bad)
+        assert e.value.status == wdr.EINVAL
+    ctx.set_stencil(wdr.STENCIL_AUTO)
+    ctx.close()
