@@ -40,7 +40,7 @@ KERNEL = {"f64": "k_dslash_blk<double, B=4, all hops> (SU(3) links, two rows)",
 # reads 1 GiB as FETCH_SIZE 0.5 GiB because every read request on gfx950 is
 # 128 B while FETCH_SIZE counts 64 B per request; WRITE_SIZE reads exactly).
 # Reported only while the stencil sources hash to the value recorded there.
-COUNTERS = os.path.join(ROOT, "profiles", "dslash_dir_32x32x32x32_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "dslash_blk_32x32x32x32_counters.md")
 STENCIL_SOURCES = ["paper_1112_1243_amd/csrc/dslash.hip", "paper_1112_1243_amd/csrc/stencil.h",
                    "paper_1112_1243_amd/csrc/wdr_internal.h"]
 
@@ -330,12 +330,14 @@ def counted_traffic(prec_name):
     return None
 
 
-def dslash_roofline(wdr, torch, L=(32, 32, 32, 32), prec_name="f64", reps=30):
+def dslash_roofline(wdr, torch, L=(32, 32, 32, 32), prec_name="f64", reps=30, stencil=0):
     """Average duration of one stencil launch on internal fields (SU(3)
-    links), by HIP events on the stream the kernel is launched on."""
+    links), by HIP events on the stream the kernel is launched on; stencil
+    is the context's kernel choice (0 = automatic)."""
     from paper_1112_1243_amd import synth
     prec = wdr.F32 if prec_name == "f32" else wdr.F64
     ctx = wdr.Context(L, (4, 4, 4, 4))
+    ctx.set_stencil(stencil)
     V = ctx.V
     U = synth.gauge_field(L, 0.2, 1112124303)
     gU = ctx.gauge(torch.from_numpy(U).cuda())
@@ -361,11 +363,12 @@ def dslash_roofline(wdr, torch, L=(32, 32, 32, 32), prec_name="f64", reps=30):
     gbs = alg / (ms * 1e-3) / 1e9
     del gU, a, b, psi
     ctx.close()
-    traffic = counted_traffic(prec_name) if su3 else None
+    traffic = counted_traffic(prec_name) if su3 and stencil != wdr.STENCIL_DIR else None
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": KERNEL[prec_name] if su3 else "k_dslash_dir<%s, all hops, B=4, R2=0>" % (
-                "double" if prec_name == "f64" else "float"),
+            "kernel": (KERNEL[prec_name] if stencil != wdr.STENCIL_DIR else
+                       "k_dslash_dir<%s, all hops, B=4, R2=1>" % ("double" if prec_name == "f64" else "float"))
+            if su3 else "k_dslash_dir<%s, all hops, B=4, R2=0>" % ("double" if prec_name == "f64" else "float"),
             "lattice": "x".join(map(str, L)), "avg_launch_us": round(ms * 1e3, 2),
             "bytes_per_launch": alg, "bytes_per_site": BYTES_PER_SITE[(prec_name, su3)]}
 
@@ -400,7 +403,7 @@ def dslash_f16(wdr, torch, L=(32, 32, 32, 32), reps=32, copies=4):
     gbs = alg / (ms * 1e-3) / 1e9
     del gs, fs, outs
     ctx.close()
-    return {"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+    return {"achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": counted_traffic("f16"),
             "kernel": "k_dslash_h16<4> (FP16 fields, per-block scales, FP16 two-row links)",
             "avg_launch_us": round(ms * 1e3, 2), "bytes_per_launch": alg, "bytes_per_site": 192,
             "rotating_copies": copies}
@@ -629,6 +632,8 @@ def main():
     ap.add_argument("--no-blockdet", action="store_true", help="skip the exact block determinants")
     ap.add_argument("--no-recursive", action="store_true", help="skip the recursive-DD workload")
     ap.add_argument("--no-filter", action="store_true", help="skip the filter and acceptance-rate runs")
+    ap.add_argument("--stencil", choices=("auto", "dir", "blk"), default="auto",
+                    help="stencil kernel for the 32^4 roofline launches (default: the library's choice)")
     ap.add_argument("--rocprof-summary", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     args = ap.parse_args()
     if args.rocprof_summary:
@@ -690,8 +695,9 @@ def main():
     roof = None
     if not args.no_dslash:
         # the FP64 stencil is the global operator of the outer solve
-        roof = dslash_roofline(wdr, torch, prec_name="f64")
-        r32 = dslash_roofline(wdr, torch, prec_name="f32")
+        sc = {"auto": wdr.STENCIL_AUTO, "dir": wdr.STENCIL_DIR, "blk": wdr.STENCIL_BLK}[args.stencil]
+        roof = dslash_roofline(wdr, torch, prec_name="f64", stencil=sc)
+        r32 = dslash_roofline(wdr, torch, prec_name="f32", stencil=sc)
         log("dslash f64:", roof)
         log("dslash f32:", r32)
         roof["f32"] = {k: r32[k] for k in ("achieved", "frac", "traffic", "kernel", "avg_launch_us",
