@@ -678,7 +678,6 @@ wdr_status wdr_relative_gauge(wdr_ctx *c, const double *U, double *Up, int32_t s
         // reduced as three fields of 12 V entries
         Work part(c, sizeof(double) * red_scratch(3)), out(c, 3 * sizeof(double2));
         if (!part.ok() || !out.ok()) return WDR_ENOMEM;
-        launch_red_init(part.as<double>(), 3, s);
         launch_dot<double>(all_sys(c, 3), reinterpret_cast<const double2 *>(U), reinterpret_cast<const double2 *>(Up),
                            part.as<double>(), out.as<double2>(), 1, s);
         double2 h[3];

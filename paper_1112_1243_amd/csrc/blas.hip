@@ -1,11 +1,10 @@
 // BLAS-1 kernels and deterministic FP64 reductions over batches of fields.
 //
-// Reductions use a fixed grid: workgroup (c, m) sums a fixed, strided share
-// of system m's elements in FP64 (wavefront shuffles, then LDS across the 4
-// wavefronts) and stores its partial sum; the last workgroup of system m to
-// finish (a per-system ticket counter, device-scope fences around it) adds
-// the partial sums in a fixed order and resets the ticket.  Results do not
-// depend on scheduling and are bit-reproducible from run to run.
+// Reductions run in two passes with a fixed grid: workgroup (c, m) sums a
+// fixed, strided share of system m's elements in FP64 (wavefront shuffles,
+// then LDS across the 4 wavefronts), and one workgroup per system adds the
+// partial sums in a fixed order.  Results do not depend on scheduling and
+// are bit-reproducible from run to run.
 #include "ops.h"
 
 namespace wdr {
@@ -40,46 +39,13 @@ template <typename T> __device__ __forceinline__ double2 toD(typename C2<T>::typ
 
 __device__ __forceinline__ bool off(const int32_t *active, int m) { return active && !active[m]; }
 
-// out[m * ostride + j] = sum over the G partials of (m, j), fixed order
-__device__ __forceinline__ void final_sums(const double *partial, int m, int G, int nv, double2 *out, int ostride,
-                                           double *sh)
-{
-    for (int j = 0; j < nv; ++j) {
-        const double *p = partial + ((long)m * nv + j) * 2 * G;
-        double re = 0, im = 0;
-        for (int i = threadIdx.x; i < G; i += NT) {
-            re += p[2 * i];
-            im += p[2 * i + 1];
-        }
-        re = block_sum(re, sh);
-        im = block_sum(im, sh);
-        if (threadIdx.x == 0) out[(long)m * ostride + j] = make_double2(re, im);
-    }
-}
-
-// called by every workgroup of system m after thread 0 stored its partial
-// sums: true in the last workgroup to arrive, which then sees every partial
-__device__ __forceinline__ bool last_to_arrive(uint32_t *ticket, int m, int G, int *flag)
-{
-    if (threadIdx.x == 0) {
-        __threadfence();
-        *flag = atomicAdd(ticket + m, 1u) == (uint32_t)(G - 1);
-    }
-    __syncthreads();
-    if (!*flag) return false;
-    __threadfence();
-    return true;
-}
-
 // partial[(m * nv + j) * 2G + 2c + {0,1}]
 template <typename T>
-__global__ __launch_bounds__(NT) void k_multidot(const int32_t *active, long n,
-                                                 const typename C2<T>::type *const *v, int nv,
-                                                 const typename C2<T>::type *__restrict__ y, double *partial,
-                                                 uint32_t *ticket, double2 *out, int ostride)
+__global__ __launch_bounds__(NT) void k_multidot_partial(const int32_t *active, long n,
+                                                         const typename C2<T>::type *const *v, int nv,
+                                                         const typename C2<T>::type *__restrict__ y, double *partial)
 {
     __shared__ double sh[4];
-    __shared__ int flag;
     const int G = gridDim.x, m = blockIdx.y;
     if (off(active, m)) return;
     const typename C2<T>::type *ym = y + m * n;
@@ -98,19 +64,15 @@ __global__ __launch_bounds__(NT) void k_multidot(const int32_t *active, long n,
             partial[((long)m * nv + j) * 2 * G + 2 * blockIdx.x + 1] = im;
         }
     }
-    if (!last_to_arrive(ticket, m, G, &flag)) return;
-    final_sums(partial, m, G, nv, out, ostride, sh);
-    if (threadIdx.x == 0) ticket[m] = 0;
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_dot(const int32_t *active, const int32_t *list, long n,
-                                            const typename C2<T>::type *__restrict__ a,
-                                            const typename C2<T>::type *__restrict__ b, int norm, double *partial,
-                                            uint32_t *ticket, double2 *out, int ostride)
+__global__ __launch_bounds__(NT) void k_dot_partial(const int32_t *active, const int32_t *list, long n,
+                                                    const typename C2<T>::type *__restrict__ a,
+                                                    const typename C2<T>::type *__restrict__ b, int norm,
+                                                    double *partial)
 {
     __shared__ double sh[4];
-    __shared__ int flag;
     const int G = gridDim.x, m = sys_at(list, blockIdx.y);
     if (off(active, m)) return;
     a += m * n;
@@ -132,15 +94,26 @@ __global__ __launch_bounds__(NT) void k_dot(const int32_t *active, const int32_t
         partial[(long)m * 2 * G + 2 * blockIdx.x] = re;
         partial[(long)m * 2 * G + 2 * blockIdx.x + 1] = im;
     }
-    if (!last_to_arrive(ticket, m, G, &flag)) return;
-    final_sums(partial, m, G, 1, out, ostride, sh);
-    if (threadIdx.x == 0) ticket[m] = 0;
 }
 
-__global__ void k_tickets_zero(uint32_t *t, int M)
+// out[m * ostride + j] = sum over the G partials, fixed order
+__global__ __launch_bounds__(NT) void k_final(const int32_t *active, const int32_t *list, const double *partial,
+                                              int G, int nv, double2 *out, int ostride)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m < M) t[m] = 0;
+    __shared__ double sh[4];
+    const int m = sys_at(list, blockIdx.x);
+    if (off(active, m)) return;
+    for (int j = 0; j < nv; ++j) {
+        const double *p = partial + ((long)m * nv + j) * 2 * G;
+        double re = 0, im = 0;
+        for (int i = threadIdx.x; i < G; i += NT) {
+            re += p[2 * i];
+            im += p[2 * i + 1];
+        }
+        re = block_sum(re, sh);
+        im = block_sum(im, sh);
+        if (threadIdx.x == 0) out[(long)m * ostride + j] = make_double2(re, im);
+    }
 }
 
 int red_grid(long n)
@@ -282,34 +255,30 @@ inline unsigned nblk(long n) { return (unsigned)((n + NT - 1) / NT); }
 
 }  // namespace
 
-void launch_red_init(double *red, int M, hipStream_t s)
-{
-    k_tickets_zero<<<(M + 255) / 256, 256, 0, s>>>(red_tickets(red, M), M);
-}
-
 template <typename T>
 void launch_multidot(const Sys &sy, const T2<T> *const *v, int nv, const T2<T> *y, double *red, double2 *out,
                      int ostride, hipStream_t s)
 {
     if (nv <= 0) return;
     const int G = red_grid(sy.n);
-    k_multidot<T><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, v, nv, y, red, red_tickets(red, sy.M), out, ostride);
+    k_multidot_partial<T><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, v, nv, y, red);
+    k_final<<<sy.M, NT, 0, s>>>(sy.active, nullptr, red, G, nv, out, ostride);
 }
 
 template <typename T>
 void launch_dot(const Sys &sy, const T2<T> *a, const T2<T> *b, double *red, double2 *out, int ostride, hipStream_t s)
 {
     const int G = red_grid(sy.n);
-    k_dot<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, a, b, 0, red, red_tickets(red, sy.M), out,
-                                                   ostride);
+    k_dot_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, a, b, 0, red);
+    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
 }
 
 template <typename T>
 void launch_norm2(const Sys &sy, const T2<T> *a, double *red, double2 *out, int ostride, hipStream_t s)
 {
     const int G = red_grid(sy.n);
-    k_dot<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, a, a, 1, red, red_tickets(red, sy.M), out,
-                                                   ostride);
+    k_dot_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, a, a, 1, red);
+    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
 }
 
 template <typename TO, typename TI> void launch_convert(const Sys &sy, const T2<TI> *a, T2<TO> *out, hipStream_t s)

@@ -97,15 +97,10 @@ void launch_keep_slots(const Geo &g, const Sys &sy, double2 *f, int slot0, int n
 // multiply spin components 2, 3 by -1 (gamma_5), in place allowed
 template <typename T> void launch_g5(const Geo &g, const Sys &sy, const T2<T> *in, T2<T> *out, hipStream_t s);
 
-// Deterministic FP64 reductions (fixed grid, fixed order, one launch each);
-// red: device scratch of red_scratch(M) doubles (partial sums, then one
-// ticket counter per system), prepared once by launch_red_init before its
-// first use (every reduction leaves the tickets at zero again); results in
-// device memory.  Reductions sharing one scratch must not run concurrently.
+// Deterministic FP64 reductions (fixed grid, fixed order); red: device
+// scratch of red_scratch(M) doubles; results in device memory.
 constexpr int RED_BLOCKS = 256;
-inline long red_scratch(int M) { return 2L * RED_BLOCKS * 16 * M + (M + 1) / 2 + 64; }
-inline uint32_t *red_tickets(double *red, int M) { return reinterpret_cast<uint32_t *>(red + 2L * RED_BLOCKS * 16 * M); }
-void launch_red_init(double *red, int M, hipStream_t s);
+inline long red_scratch(int M) { return 2L * RED_BLOCKS * 16 * M + 64; }
 // out[m * ostride + j] = <v_j[m], y[m]> for j < nv (nv <= 16), v_j given by a
 // device table of nv batch fields
 template <typename T>

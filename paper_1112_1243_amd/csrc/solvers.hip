@@ -389,7 +389,6 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
     Work scal(c, sizeof(double2) * ((size_t)M * (2 * 256 + 16 * 3 + 1)));
     Work red(c, sizeof(double) * red_scratch(M));
     if (!tab.ok() || !scal.ok() || !red.ok()) return WDR_ENOMEM;
-    launch_red_init(red.as<double>(), M, s);
     std::vector<const void *> hp(2 * nkv);
     for (int j = 0; j < nkv; ++j) {
         hp[j] = bufs[j]->as<void>();
@@ -567,7 +566,6 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     if (!bhw.ok() || !r64w.ok() || !t64w.ok() || !o64w.ok() || !rw.ok() || !pw.ok() || !ww.ok() || !qw.ok() ||
         !ew.ok() || !tw.ok() || !scal.ok() || !red.ok() || !ctl.ok() || !lw.ok() || !poll.ok)
         return WDR_ENOMEM;
-    launch_red_init(red.as<double>(), M, s);
     double2 *bh = bhw.as<double2>(), *r64 = r64w.as<double2>(), *t64 = t64w.as<double2>(), *o64 = o64w.as<double2>();
     T2<T> *r = rw.as<T2<T>>(), *p = pw.as<T2<T>>(), *w = ww.as<T2<T>>(), *qv = qw.as<T2<T>>(),
           *e = ew.as<T2<T>>(), *t = tw.as<T2<T>>();
