@@ -171,8 +171,11 @@ __global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__rest
 // global memory.  Against k_dslash_dir this cuts the vector-memory
 // instructions per site (each in-block spinor is read once instead of once
 // per neighbour), which bound that kernel.
-template <typename T, int B, int MU, int HOPS>
-__device__ __forceinline__ void hop_blk(const T2<T> (*sh)[Cube<B>::Vb], const __attribute__((address_space(1))) T2<T> *in,
+// The two hops of direction MU at site l: in-block neighbours from the LDS
+// copy sh ([12][NS], entry (c, nl - off)), the others from global memory;
+// DAG applies gamma_5 to the loaded spinors (the caller to the result).
+template <typename T, int B, int MU, int HOPS, int DAG, int NS>
+__device__ __forceinline__ void hop_blk(const T2<T> *sh, int off, const __attribute__((address_space(1))) T2<T> *in,
                                         const __attribute__((address_space(1))) T2<T> *Ug, int slot, const int nbr[8],
                                         int l, const int x[4], int pin, spinor<T> &acc, T wrap_f, T wrap_b)
 {
@@ -192,7 +195,7 @@ __device__ __forceinline__ void hop_blk(const T2<T> (*sh)[Cube<B>::Vb], const __
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) p.s[sp].c[a] = ld<T>(&sh[3 * sp + a][0], nl);
+                for (int a = 0; a < 3; ++a) p.s[sp].c[a] = ld<T>(sh, (3 * sp + a) * NS + nl - off);
         } else {
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp)
@@ -209,6 +212,13 @@ __device__ __forceinline__ void hop_blk(const T2<T> (*sh)[Cube<B>::Vb], const __
             const int a = (c + 1) % 3, b = (c + 2) % 3;
             const cx<T> v = u.m[0][a] * u.m[1][b] - u.m[0][b] * u.m[1][a];
             u.m[2][c] = mk<T>(sg * v.re, -sg * v.im);
+        }
+        if (DAG) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                p.s[2].c[a] = neg(p.s[2].c[a]);
+                p.s[3].c[a] = neg(p.s[3].c[a]);
+            }
         }
         vec3<T> a0, a1;
         A_dn(MU, p.s[2], p.s[3], a0, a1);
@@ -278,10 +288,10 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_dslash_blk(Geo g, const int32_t
             if (nmu == 0 && x[mu] == 0) wb = -1;
         }
         switch (mu) {
-        case 0: hop_blk<T, B, 0, HOPS>(sh, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
-        case 1: hop_blk<T, B, 1, HOPS>(sh, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
-        case 2: hop_blk<T, B, 2, HOPS>(sh, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
-        default: hop_blk<T, B, 3, HOPS>(sh, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
+        case 0: hop_blk<T, B, 0, HOPS, 0, Vb>(&sh[0][0], 0, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
+        case 1: hop_blk<T, B, 1, HOPS, 0, Vb>(&sh[0][0], 0, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
+        case 2: hop_blk<T, B, 2, HOPS, 0, Vb>(&sh[0][0], 0, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
+        default: hop_blk<T, B, 3, HOPS, 0, Vb>(&sh[0][0], 0, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
         }
     }
 #pragma unroll
@@ -290,6 +300,76 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_dslash_blk(Geo g, const int32_t
         for (int a = 0; a < 3; ++a) {
             const int c = 3 * sp + a;
             st_nt<T>(out, m * n + base + (long)c * Vb, ld<T>(&sh[c][0], l) - scale(kappa, acc.s[sp].c[a]));
+        }
+}
+
+// The even-odd halves of the same operator (the stencil of the even-odd
+// reduced solvers): out = diag - kappa H_{par, 1-par} in on the sites of
+// parity par, with gamma_5 on both sides for DAG.  One workgroup per block,
+// one lane per output site; the block's input sites of the other parity are
+// read once into LDS.
+template <typename T, int B, int DAG>
+__global__ __launch_bounds__(Cube<B>::Vh) void k_dslash_blk_eo(Geo g, const int32_t *__restrict__ active,
+                                                              const int32_t *__restrict__ list, UTab<T> Utab,
+                                                              const double *__restrict__ kap, int kneg, long n,
+                                                              const int32_t *__restrict__ sched, int par,
+                                                              const T2<T> *__restrict__ in,
+                                                              const T2<T> *__restrict__ diag, T2<T> *__restrict__ out,
+                                                              T kappa)
+{
+    typedef Cube<B> CB;
+    constexpr int Vb = CB::Vb, Vh = CB::Vh;
+    __shared__ T2<T> sh[12][Vh];  // the block's input on the other parity, component-major
+    const int m = sys_at(list, blockIdx.y);
+    if (active && !active[m]) return;
+    if (kap) kappa = kneg ? -(T)kap[m] : (T)kap[m];
+    const int slot = sched[blockIdx.x];
+    const int t = threadIdx.x;
+    const int off = (1 - par) * Vh;  // first local index of the input parity
+    const auto *Ug = as_global(Utab[m]);
+    const auto *ing = as_global(in + m * n);
+    const long sbase = (long)slot * 12 * Vb;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) st<T>(&sh[c][0], t, ldg<T>(ing, sbase + off + t + c * Vb));
+    const int l = par * Vh + t;
+    int x[4];
+    CB::coords(l, x);
+    int nbr[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
+    const int bl = g.slot_blk[slot];
+    __syncthreads();
+    spinor<T> acc;
+    zero(acc);
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        int pin = 0;
+        asm volatile("" : "+s"(pin));
+        T wf = 1, wb = 1;
+        if (g.bc[mu] < 0) {
+            int b2 = bl;
+            for (int d = 0; d < mu; ++d) b2 /= g.NB[d];
+            const int nmu = b2 % g.NB[mu];
+            if (nmu == g.NB[mu] - 1 && x[mu] == B - 1) wf = -1;
+            if (nmu == 0 && x[mu] == 0) wb = -1;
+        }
+        switch (mu) {
+        case 0: hop_blk<T, B, 0, HOPS_ALL, DAG, Vh>(&sh[0][0], off, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
+        case 1: hop_blk<T, B, 1, HOPS_ALL, DAG, Vh>(&sh[0][0], off, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
+        case 2: hop_blk<T, B, 2, HOPS_ALL, DAG, Vh>(&sh[0][0], off, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
+        default: hop_blk<T, B, 3, HOPS_ALL, DAG, Vh>(&sh[0][0], off, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
+        }
+    }
+    const long obase = m * n + sbase + l;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const long i = obase + (long)(3 * sp + a) * Vb;
+            cx<T> v = scale(-kappa, acc.s[sp].c[a]);
+            if (DAG && sp >= 2) v = neg(v);
+            if (diag) v = v + ld<T>(diag, i);
+            st_nt<T>(out, i, v);
         }
 }
 
@@ -320,6 +400,17 @@ bool launch_cube(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int
         else
             k_dslash_blk<T, B, HOPS_IN><<<gb, Cube<B>::Vb, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n,
                                                                   sc, in, out, kappa);
+        return true;
+    }
+    // the even-odd halves (all hops), same choice
+    if (par >= 0 && hops == HOPS_ALL && U.su3 && (g.stencil == WDR_STENCIL_BLK || (g.stencil == WDR_STENCIL_AUTO && big))) {
+        const dim3 gb(nslots, sy.launch_m());
+        if (dag)
+            k_dslash_blk_eo<T, B, 1><<<gb, Cube<B>::Vh, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, sc,
+                                                               par, in, diag, out, kappa);
+        else
+            k_dslash_blk_eo<T, B, 0><<<gb, Cube<B>::Vh, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, sc,
+                                                               par, in, diag, out, kappa);
         return true;
     }
     const dim3 grid(nslots * chunks, sy.launch_m());

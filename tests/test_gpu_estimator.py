@@ -84,17 +84,20 @@ def test_samples_match_oracle(op, kind, L, B, kappa, scale, rule, N, K, solver):
 
 
 def test_block_staged_stencil_in_estimates():
-    """SCHUR and BLOCKS samples at 8^4 with the block-staged stencil forced
-    for D and the Dirichlet blocks (batched systems, compaction lists) match
-    the oracle as with the default choice."""
+    """SCHUR and BLOCKS samples at 8^4 with the block-staged stencils forced
+    (D, the Dirichlet blocks and, in the even-odd CGNE, both halves with and
+    without gamma_5; batched systems, compaction lists) match the oracle as
+    with the default choice."""
     wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 1112124332)
     ctx.set_stencil(wdr.STENCIL_BLK)
     Up = _pair(lat, U, 0.5, 307, "active")
     gU, gUp = ctx.gauge(dev(U)), ctx.gauge(dev(Up))
-    for op in (wdr.OP_SCHUR, wdr.OP_BLOCKS):
-        s, lr, info = ctx.logdet_ratio(gU, gUp, 0.135, op, 2, 1, wdr.NOISE_GAUSS, 41, wdr.default_params())
+    for op, solver in ((wdr.OP_SCHUR, wdr.SOLVER_FGCR_SAP), (wdr.OP_BLOCKS, wdr.SOLVER_FGCR_SAP),
+                       (wdr.OP_SCHUR, wdr.SOLVER_CGNE)):
+        s, lr, info = ctx.logdet_ratio(gU, gUp, 0.135, op, 2, 1, wdr.NOISE_GAUSS, 41,
+                                       wdr.default_params(solver=solver))
         want, _ = oracle.logdet_ratio(lat, U, Up, 0.135, op, 2, 1, oracle.NOISE_GAUSS, 41)
-        say("blk stencil op", op, "max |ds|", np.abs(s - want).max())
+        say("blk stencil op", op, "solver", solver, "max |ds|", np.abs(s - want).max())
         assert info.converged and np.abs(s - want).max() < 1e-8
     del gU, gUp
     ctx.close()

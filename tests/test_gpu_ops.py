@@ -283,6 +283,11 @@ def test_stencil_choices(choice, L, bc):
         want = oracle.apply_Dblock(lat, U, k, psi, colour)
         assert rel(host(ctx.apply_Dblock(gU, k, dev(psi), colour, wdr.F64)), want) < 1e-14
         assert rel(host(ctx.apply_Dblock(gU, k, dev(psi), colour, wdr.F32)), want) < 2e-6
+    # the even-odd reduced operator (its halves have a block-staged kernel too)
+    for blocked in (False, True):
+        want = oracle.apply_Dee(lat, U, k, psi, blocked)
+        assert rel(host(ctx.apply_Dee(gU, k, dev(psi), blocked, wdr.F64)), want) < 1e-14
+        assert rel(host(ctx.apply_Dee(gU, k, dev(psi), blocked, wdr.F32)), want) < 2e-6
     # internal fields (one kernel launch) give the same numbers as the canonical call
     a = ctx.pack(dev(psi), wdr.F64)
     b = ctx.apply_D_internal(gU, k, a, ctx.internal_field(wdr.F64), wdr.F64)
