@@ -25,6 +25,10 @@ struct wdr_ctx {
     int32_t *poll_host = nullptr;
     size_t poll_cap = 0;
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
+    // pinned copies of per-system residual norms read with the flags (two
+    // slots of M, then M reference norms)
+    double2 *poll_val = nullptr;
+    size_t poll_val_cap = 0;
     // stream of this context's group in a batch over several contexts
     // (created on first use, default priority)
     hipStream_t aux = nullptr;

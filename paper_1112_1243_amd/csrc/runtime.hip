@@ -332,6 +332,7 @@ wdr_status wdr_ctx_destroy(wdr_ctx *c)
     for (void *p : c->owned) (void)hipFree(p);
     if (c->tables) (void)hipFree(c->tables);
     if (c->poll_host) (void)hipHostFree(c->poll_host);
+    if (c->poll_val) (void)hipHostFree(c->poll_val);
     for (hipEvent_t e : c->poll_ev)
         if (e) (void)hipEventDestroy(e);
     if (c->aux) (void)hipStreamDestroy(c->aux);

@@ -185,6 +185,25 @@ struct FlagPoll {
         (void)hipMemcpyAsync(slot(k), dev, (size_t)M * sizeof(int32_t), hipMemcpyDeviceToHost, s);
         (void)hipEventRecord(c->poll_ev[k], s);
     }
+    // the same with M per-system values (.x of vals) read along with the
+    // flags into vals_at(k); false if the pinned value buffer is missing
+    bool want_vals()
+    {
+        if (c->poll_val_cap < 3 * (size_t)M) {
+            if (c->poll_val) (void)hipHostFree(c->poll_val);
+            c->poll_val = nullptr;
+            c->poll_val_cap = 0;
+            if (hipHostMalloc((void **)&c->poll_val, 3 * (size_t)M * sizeof(double2)) != hipSuccess) return false;
+            c->poll_val_cap = 3 * (size_t)M;
+        }
+        return true;
+    }
+    double2 *vals_at(int k) const { return c->poll_val + (size_t)k * M; }
+    void post(const int32_t *dev, const double2 *vals, int k, hipStream_t s) const
+    {
+        (void)hipMemcpyAsync(vals_at(k), vals, (size_t)M * sizeof(double2), hipMemcpyDeviceToHost, s);
+        post(dev, k, s);
+    }
     // waits for the copy posted in slot k; true if every flag there is 0
     bool none(int k) const
     {
@@ -414,6 +433,10 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
     const unsigned nbm = (unsigned)((M + 63) / 64);
     launch_norm2<double>(all, b, red.as<double>(), nr, 1, s);
     k_fgcr_init<<<nbm, 64, 0, s>>>(M, nr, bn2, alive, act, cnt, its);
+    // |b|^2 to the host with the first flags, for the convergence forecast below
+    const bool fc = poll.want_vals();
+    if (fc) (void)hipMemcpyAsync(poll.vals_at(2), nr, (size_t)M * sizeof(double2), hipMemcpyDeviceToHost, s);
+    std::vector<double> last(M, 0.0);  // |r|^2 of each system after the previous step read
     launch_zero<double>(x, n * M, s);
     launch_convert<double, double>(all, b, r, s);
     const Sys sa{M, act, n}, sw{M, alive, n};
@@ -436,10 +459,27 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
             launch_axpy_dev(sa, cj + j, 16, -1.0, chi(j), r, s);
             launch_norm2<double>(sa, r, red.as<double>(), nr, 1, s);
             k_fgcr_inner<<<nbm, 64, 0, s>>>(M, j, nr, bn2, tol2, sp.max_iter, act, cnt, its);
-            poll.post(act, j & 1, s);
+            if (fc) poll.post(act, nr, j & 1, s);
+            else poll.post(act, j & 1, s);
             // step j is queued; stop once step j - 1 left no system active
             // (step j then runs as a no-op)
             if (j > 0 && poll.none((j - 1) & 1)) break;
+            // Forecast: if every system still active after step j - 1 reaches
+            // the tolerance in step j at the rate of its last step, wait for
+            // step j's flags now instead of queueing step j + 1, which would
+            // most likely run as a no-op.  Either way the numbers are the same.
+            if (fc && j > 0) {
+                const int32_t *f = poll.slot((j - 1) & 1);
+                const double2 *v = poll.vals_at((j - 1) & 1), *b2 = poll.vals_at(2);
+                bool done = true;
+                for (int m = 0; m < M && done; ++m) {
+                    if (!f[m]) continue;
+                    const double now = v[m].x, q = last[m] > 0 ? now / last[m] : 1.0;
+                    done = now * q <= tol2 * b2[m].x;
+                }
+                for (int m = 0; m < M; ++m) last[m] = v[m].x;
+                if (done && poll.none(j & 1)) break;
+            }
         }
         k_fgcr_backsub<<<nbm, 64, 0, s>>>(M, A, bj, cj, cnt, alive, al);
         launch_multi_axpy(sw, al, 16, 1.0, phis, nkv, cnt, x, 1, s);
