@@ -622,8 +622,8 @@ def cpu_baseline(wl, U, Up, budget_s=20.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-dslash", action="store_true")
@@ -683,7 +683,7 @@ def main():
     fp64_rate = None
     if not args.no_fp64:
         t1 = time.perf_counter()
-        n64 = max(1, min(2, args.steps))
+        n64 = max(1, min(5, args.steps))
         for k in range(n64):
             estimate(ctx, wdr, gU, gUp, wl, fp64, 2000 + k)
         torch.cuda.synchronize()
