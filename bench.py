@@ -640,8 +640,8 @@ def main():
         print(rocprof_summary(args.rocprof_summary))
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path (every proposal, path factor and "
-              "noise vector is independent; see the sharding notes in the design document)", file=sys.stderr)
+        print("bench.py runs on one GPU: the library has no multi-GPU path (every proposal, path factor and "
+              "noise vector is independent, so they would be dealt out to one process per GPU)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -402,7 +402,7 @@ typedef struct wdr_filter_info {
  * of *p (op WDR_OP_SCHUR) from the field before the step to the result
  * (uniform from counter (0, 0, 1, 0)); a rejected step restores dev_U.
  * p = NULL runs the block steps only and keeps their result (the proposal
- * the global step would judge).  host_accepts (NULL allowed):
+ * the global step would decide on).  host_accepts (NULL allowed):
  * n_block_steps x nblocks block decisions.
  * EINVAL if the mask holds a link that leaves its block. */
 wdr_status wdr_filter_step(wdr_ctx *ctx, double beta, double kappa, const uint8_t *dev_mask, int32_t n_block_steps,
