@@ -129,7 +129,8 @@ def test_apply_D_general_links():
 
 @pytest.mark.parametrize("L", [(16, 16, 16, 16), (32, 32, 32, 32)])
 def test_apply_D_full_size(L):
-    """The stencil at the full sizes of the 16^4 and 32^4 workloads."""
+    """The stencil at the full sizes of the 16^4 and 32^4 workloads (at 32^4
+    the block-staged kernels: 4096 workgroups)."""
     from paper_1112_1243_amd import wdr
     torch_cuda()
     lat = oracle.Lattice(L, (4, 4, 4, 4))
@@ -140,6 +141,11 @@ def test_apply_D_full_size(L):
     want = oracle.apply_D(lat, U, 0.155, psi)
     assert rel(host(ctx.apply_D(gU, 0.155, dev(psi), wdr.F64)), want) < 1e-14
     assert rel(host(ctx.apply_D(gU, 0.155, dev(psi), wdr.F32)), want) < 2e-6
+    if L[0] == 32:
+        # at 32^4 the even-odd halves run on the block-staged kernel as well
+        want = oracle.apply_Dee(lat, U, 0.155, psi, False)
+        assert rel(host(ctx.apply_Dee(gU, 0.155, dev(psi), False, wdr.F64)), want) < 1e-14
+        assert rel(host(ctx.apply_Dee(gU, 0.155, dev(psi), False, wdr.F32)), want) < 2e-6
     del gU
     ctx.close()
 
