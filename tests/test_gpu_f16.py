@@ -72,7 +72,8 @@ def _block_max(lat, f):
     return np.abs(np.concatenate([f.real, f.imag], axis=-1))[perm].reshape(lat.V // Vb, -1).max(axis=1)
 
 
-CASES = [((8, 8, 8, 8), (1, 1, 1, -1)), ((8, 8, 8, 16), (1, 1, 1, 1)), ((16, 8, 8, 8), (1, -1, 1, 1))]
+CASES = [((8, 8, 8, 8), (1, 1, 1, -1)), ((8, 8, 8, 16), (1, 1, 1, 1)), ((16, 8, 8, 8), (1, -1, 1, 1)),
+         ((8, 8, 8, 8), (0, 0, 0, 0))]
 
 
 @pytest.mark.parametrize("L,bc", CASES)

@@ -268,7 +268,8 @@ def test_schur():
 
 
 @pytest.mark.parametrize("choice", ["dir", "blk"])
-@pytest.mark.parametrize("L,bc", [((8, 8, 8, 8), (1, 1, 1, -1)), ((8, 16, 8, 8), (1, -1, 1, 1))])
+@pytest.mark.parametrize("L,bc", [((8, 8, 8, 8), (1, 1, 1, -1)), ((8, 16, 8, 8), (1, -1, 1, 1)),
+                                  ((8, 8, 8, 8), (0, 0, 0, 0))])
 def test_stencil_choices(choice, L, bc):
     """Both stencil kernels for D and the Dirichlet block operators (forced,
     whatever the launch size) against the oracle, FP64 and FP32; the forced
