@@ -41,7 +41,8 @@ KERNEL = {"f64": "k_dslash_blk<double, B=4, all hops> (SU(3) links, two rows)",
 # 128 B while FETCH_SIZE counts 64 B per request; WRITE_SIZE reads exactly).
 # Reported only while the stencil sources hash to the value recorded there.
 COUNTERS = os.path.join(ROOT, "profiles", "dslash_blk_32x32x32x32_counters.md")
-STENCIL_SOURCES = ["paper_1112_1243_amd/csrc/dslash.hip", "paper_1112_1243_amd/csrc/stencil.h",
+STENCIL_SOURCES = ["paper_1112_1243_amd/csrc/dslash.hip", "paper_1112_1243_amd/csrc/half.hip",
+                   "paper_1112_1243_amd/csrc/stencil.h",
                    "paper_1112_1243_amd/csrc/wdr_internal.h"]
 
 WORKLOAD = dict(name="wilson8_dd16", L=(8, 8, 8, 8), B=(4, 4, 4, 4), kappa=0.135, scale=0.5, n_steps=8,
