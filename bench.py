@@ -615,9 +615,23 @@ def cpu_baseline(wl, U, Up, budget_s=20.0):
     dt = time.perf_counter() - t0
     per_estimate = dt / 2 * 2 * wl["n_steps"] * wl["n_noise"]
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # the oracle's stencil on the 16^4 lattice, median of 3, in the compulsory
+    # bytes of a full-link FP64 stencil (960 B/site)
+    from paper_1112_1243_amd import synth
+    L16 = (16, 16, 16, 16)
+    lat16 = oracle.Lattice(L16, (4, 4, 4, 4))
+    U16, psi16 = synth.gauge_field(L16, 0.25, 1112124302), synth.spinor(L16, 11)
+    ts = []
+    for _ in range(3):
+        t1 = time.perf_counter()
+        oracle.apply_D(lat16, U16, 0.150, psi16)
+        ts.append(time.perf_counter() - t1)
+    ms = sorted(ts)[1] * 1e3
     return {"value": round(1.0 / per_estimate, 6), "unit": "estimates/s", "cores": threads, "kind": "oracle",
             "sample": "1 BLOCKS + 1 SCHUR sample (one path factor, one noise vector) at 8^4, FP64 CGNE to 1e-10, "
-                      "%.1f s, scaled x%d to one estimate" % (dt, wl["n_steps"] * wl["n_noise"])}
+                      "%.1f s, scaled x%d to one estimate" % (dt, wl["n_steps"] * wl["n_noise"]),
+            "stencil": {"lattice": "16x16x16x16", "ms": round(ms, 2), "unit": "GB/s",
+                        "value": round(960 * lat16.V / (ms * 1e-3) / 1e9, 2), "kind": "oracle apply_D, FP64, median of 3"}}
 
 
 def main():
