@@ -103,6 +103,23 @@ def test_block_staged_stencil_in_estimates():
     ctx.close()
 
 
+def test_estimates_are_bit_reproducible():
+    """Two DD estimates with the same key give the same samples bit for bit:
+    the reductions run in a fixed order, and the host's scheduling decisions
+    (lagged flag reads, convergence forecasts, compaction) only decide which
+    no-op steps are queued."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 1112124333)
+    Up = _pair(lat, U, 0.5, 309, "active")
+    gU, gUp = ctx.gauge(dev(U)), ctx.gauge(dev(Up))
+    p = wdr.default_params()
+    a, la, ia = ctx.logdet_ratio(gU, gUp, 0.135, wdr.OP_DD, 4, 1, wdr.NOISE_GAUSS, 23, p)
+    b, lb, ib = ctx.logdet_ratio(gU, gUp, 0.135, wdr.OP_DD, 4, 1, wdr.NOISE_GAUSS, 23, p)
+    assert ia.converged and ib.converged
+    assert np.array_equal(a, b) and la == lb
+    del gU, gUp
+    ctx.close()
+
+
 def test_dd_equals_blocks_and_schur():
     """The DD estimate (block ratios and Schur ratio of one proposal in one
     call, run concurrently on one path) gives the samples of the separate
