@@ -443,8 +443,12 @@ __device__ __forceinline__ void sum_part(const typename C2<T>::type *part, int q
 // FP16 two-row copy ([slot][mu][6][Vb]), src and dst are FP16 fields with a
 // power-of-two scale per system and block; the output's scale is the block
 // maximum of the new values (an LDS reduction: the workgroup owns the block).
-template <typename T, int MODE, int B, int ST>
-__global__ __launch_bounds__(4 * Cube<B>::Vh) void k_block_mr_dir(Geo g, const int32_t *__restrict__ active,
+//
+// OCC: minimum waves per SIMD the compiler must allow (1: no constraint).  The
+// FP16 block solves of large lattices (tens of thousands of blocks per
+// launch) run faster at 4 (two blocks per CU) despite a few spilled registers.
+template <typename T, int MODE, int B, int ST, int OCC = 1>
+__global__ __launch_bounds__(4 * Cube<B>::Vh) __attribute__((amdgpu_waves_per_eu(OCC))) void k_block_mr_dir(Geo g, const int32_t *__restrict__ active,
                                                                   const void *const *__restrict__ Utab,
                                                                   const double *__restrict__ kap, long n,
                                                                   const int32_t *__restrict__ sched,
@@ -740,7 +744,7 @@ bool launch_mr_h16(int mode, const Geo &g, const Sys &sy, Links16 U, H16c src, H
         k_block_mr_dir<float, 0, 4, 1><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
                                                                        src.v, src.s, dst.v, dst.s, kappa, nmr);
     else
-        k_block_mr_dir<float, 1, 4, 1><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
+        k_block_mr_dir<float, 1, 4, 1, 4><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
                                                                        src.v, src.s, dst.v, dst.s, kappa, nmr);
     return true;
 }
