@@ -444,9 +444,9 @@ __device__ __forceinline__ void sum_part(const typename C2<T>::type *part, int q
 // power-of-two scale per system and block; the output's scale is the block
 // maximum of the new values (an LDS reduction: the workgroup owns the block).
 //
-// OCC: minimum waves per SIMD the compiler must allow (1: no constraint).  The
-// FP16 block solves of large lattices (tens of thousands of blocks per
-// launch) run faster at 4 (two blocks per CU) despite a few spilled registers.
+// OCC: minimum waves per SIMD the compiler must allow (1: no constraint).
+// Block solves of large lattices (thousands of blocks per launch) run faster
+// at 4 (two blocks per CU) despite a few spilled registers.
 template <typename T, int MODE, int B, int ST, int OCC = 1>
 __global__ __launch_bounds__(4 * Cube<B>::Vh) __attribute__((amdgpu_waves_per_eu(OCC))) void k_block_mr_dir(Geo g, const int32_t *__restrict__ active,
                                                                   const void *const *__restrict__ Utab,
@@ -693,6 +693,10 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) __attribute__((amdgpu_waves_per_eu
     }
 }
 
+// block solves with at least this many workgroups (blocks x systems) use the
+// four-waves-per-SIMD form: two blocks per CU, at the price of a few spills
+constexpr long MR_OCC4_WORKGROUPS = 2048;
+
 template <typename T, int MODE>
 bool launch_mr_cube4(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *src, T2<T> *dst, T kappa, int nmr,
                      int slot0, int nslots, hipStream_t s)
@@ -701,11 +705,18 @@ bool launch_mr_cube4(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *src, 
     if (!U.su3 || g.B[0] != 4 || g.B[1] != 4 || g.B[2] != 4 || g.B[3] != 4) return false;
     const int si = sched_index(g, slot0, nslots);
     if (si < 0) return false;
-    if constexpr (sizeof(T) == 4)  // the FP64 partial sums would not fit in LDS next to the links
+    if constexpr (sizeof(T) == 4) {  // the FP64 partial sums would not fit in LDS next to the links
+        const auto *tab = reinterpret_cast<const void *const *>(U.tab);
+        if constexpr (MODE == 1) {
+            if ((long)nslots * sy.M >= MR_OCC4_WORKGROUPS) {
+                k_block_mr_dir<T, MODE, 4, 0, 4><<<dim3(nslots, sy.M), 4 * Cube<4>::Vh, 0, s>>>(
+                    g, sy.active, tab, U.kap, sy.n, g.sched[si], src, nullptr, dst, nullptr, kappa, nmr);
+                return true;
+            }
+        }
         k_block_mr_dir<T, MODE, 4, 0><<<dim3(nslots, sy.M), 4 * Cube<4>::Vh, 0, s>>>(
-            g, sy.active, reinterpret_cast<const void *const *>(U.tab), U.kap, sy.n, g.sched[si], src, nullptr, dst,
-            nullptr, kappa, nmr);
-    else
+            g, sy.active, tab, U.kap, sy.n, g.sched[si], src, nullptr, dst, nullptr, kappa, nmr);
+    } else
         k_block_mr_cube<T, MODE, 4><<<dim3(nslots, sy.M), 256, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, g.sched[si], src,
                                                                        dst, kappa, nmr);
     return true;
@@ -743,8 +754,11 @@ bool launch_mr_h16(int mode, const Geo &g, const Sys &sy, Links16 U, H16c src, H
     if (mode == 0)
         k_block_mr_dir<float, 0, 4, 1><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
                                                                        src.v, src.s, dst.v, dst.s, kappa, nmr);
-    else
+    else if ((long)nslots * sy.M >= MR_OCC4_WORKGROUPS)
         k_block_mr_dir<float, 1, 4, 1, 4><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
+                                                                       src.v, src.s, dst.v, dst.s, kappa, nmr);
+    else
+        k_block_mr_dir<float, 1, 4, 1><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
                                                                        src.v, src.s, dst.v, dst.s, kappa, nmr);
     return true;
 }
