@@ -242,13 +242,16 @@ __device__ __forceinline__ void hop_blk(const T2<T> *sh, int off, const __attrib
     }
 }
 
-template <typename T, int B, int HOPS>
+//
+// RES: write the residual b - out instead of out (the residual of a block
+// solve, r = b - D_b x, in one pass).
+template <typename T, int B, int HOPS, int RES = 0>
 __global__ __launch_bounds__(Cube<B>::Vb) void k_dslash_blk(Geo g, const int32_t *__restrict__ active,
                                                            const int32_t *__restrict__ list, UTab<T> Utab,
                                                            const double *__restrict__ kap, int kneg, long n,
                                                            const int32_t *__restrict__ sched,
-                                                           const T2<T> *__restrict__ in, T2<T> *__restrict__ out,
-                                                           T kappa)
+                                                           const T2<T> *__restrict__ in, const T2<T> *__restrict__ b,
+                                                           T2<T> *__restrict__ out, T kappa)
 {
     typedef Cube<B> CB;
     constexpr int Vb = CB::Vb;
@@ -299,7 +302,9 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_dslash_blk(Geo g, const int32_t
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const int c = 3 * sp + a;
-            st_nt<T>(out, m * n + base + (long)c * Vb, ld<T>(&sh[c][0], l) - scale(kappa, acc.s[sp].c[a]));
+            const long i = m * n + base + (long)c * Vb;
+            const cx<T> v = ld<T>(&sh[c][0], l) - scale(kappa, acc.s[sp].c[a]);
+            st_nt<T>(out, i, RES ? ld<T>(b, i) - v : v);
         }
 }
 
@@ -396,10 +401,10 @@ bool launch_cube(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int
         const dim3 gb(nslots, sy.launch_m());
         if (hops == HOPS_ALL)
             k_dslash_blk<T, B, HOPS_ALL><<<gb, Cube<B>::Vb, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n,
-                                                                   sc, in, out, kappa);
+                                                                   sc, in, nullptr, out, kappa);
         else
             k_dslash_blk<T, B, HOPS_IN><<<gb, Cube<B>::Vb, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n,
-                                                                  sc, in, out, kappa);
+                                                                  sc, in, nullptr, out, kappa);
         return true;
     }
     // the even-odd halves (all hops), same choice
@@ -619,6 +624,20 @@ void launch_dslash(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, i
         k_dslash<T, HOPS_IN><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, par, dag, in, diag, out, kappa, slot0);
     else
         k_dslash<T, HOPS_CROSS><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, par, dag, in, diag, out, kappa, slot0);
+}
+
+bool launch_block_residual(const Geo &g, const Sys &sy, Links<double> U, const double2 *x, const double2 *b,
+                           double2 *r, double kappa, int slot0, int nslots, hipStream_t s)
+{
+    if (nslots <= 0 || sy.M <= 0) return true;
+    if (g.B[0] != 4 || g.B[1] != 4 || g.B[2] != 4 || g.B[3] != 4 || !U.su3) return false;
+    const bool big = (long)nslots * sy.launch_m() >= BLK_MIN_WORKGROUPS;
+    if (!(g.stencil == WDR_STENCIL_BLK || (g.stencil == WDR_STENCIL_AUTO && big))) return false;
+    const int si = sched_index(g, slot0, nslots);
+    if (si < 0) return false;
+    k_dslash_blk<double, 4, HOPS_IN, 1><<<dim3(nslots, sy.launch_m()), Cube<4>::Vb, 0, s>>>(
+        g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, g.sched[si], x, b, r, kappa);
+    return true;
 }
 
 template <typename T> void launch_pack_spinor(const Geo &g, const double2 *canon, typename C2<T>::type *out, hipStream_t s)

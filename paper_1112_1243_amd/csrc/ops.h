@@ -68,6 +68,12 @@ bool launch_dslash_h16(const Geo &g, const h2 *U16, H16c in, H16 out, float kapp
 //   slots   [slot0, slot0 + nslots) receive output; other slots untouched
 //   par     -1 every site of those slots, 0 / 1 only the even / odd sites
 //   dag     1: g5 (stencil) g5, the adjoint of D (gamma5-hermiticity)
+// r = b - D_b x on the slots [slot0, slot0 + nslots) (FP64, in-block hops)
+// in one block-staged launch; false (nothing launched) where that kernel is
+// not the context's choice for this launch (the caller then applies D_b and
+// subtracts)
+bool launch_block_residual(const Geo &g, const Sys &sy, Links<double> U, const double2 *x, const double2 *b,
+                           double2 *r, double kappa, int slot0, int nslots, hipStream_t s);
 template <typename T>
 void launch_dslash(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int dag, const T2<T> *in,
                    const T2<T> *diag, T2<T> *out, T kappa, int slot0, int nslots, hipStream_t s);

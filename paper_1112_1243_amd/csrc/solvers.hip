@@ -791,8 +791,10 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
             launch_add_to64<float>(sa, d32.as<float2>(), x, s);
         }
         // r = b - D_b x on the selected blocks
-        launch_dslash<double>(g, sa, U.u64, HOPS_IN, -1, 0, x, x, t, kappa, slot0, ns, s);
-        launch_sub(sa, b, t, r, s);
+        if (!launch_block_residual(g, sa, U.u64, x, b, r, kappa, slot0, ns, s)) {
+            launch_dslash<double>(g, sa, U.u64, HOPS_IN, -1, 0, x, x, t, kappa, slot0, ns, s);
+            launch_sub(sa, b, t, r, s);
+        }
         launch_keep_slots(g, sa, r, slot0, ns, s);
         launch_slot_norm2(g, sa, r, rn, slot0, ns, s);
         k_block_check<<<nbm, 64, 0, s>>>(M, g.nblk, slot0, ns, bn, rn, tol * tol, alive, its, worst);
