@@ -116,6 +116,159 @@ __global__ __launch_bounds__(NT) void k_final(const int32_t *active, const int32
     }
 }
 
+// Fused passes of the Krylov solvers: an elementwise update followed by the
+// first pass of a reduction over its result, with the element split of
+// k_dot_partial, so the sums match a separate reduction over the stored
+// values.  Partials: 2G per system (k_final), 3G for k_norm_dot_partial.
+
+// One CG step on system m with s = sc[m * sstride]: alpha = s[0].x / s[1].x
+// (|r|^2 / |w|^2, 0 when |w|^2 is not positive), x += alpha w, r -= alpha q
+// in T, and the partial sums of |r|^2 of the new r.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cg_xr_partial(const int32_t *active, const int32_t *list, long n,
+                                                      const double2 *sc, int sstride,
+                                                      typename C2<T>::type *__restrict__ x,
+                                                      const typename C2<T>::type *__restrict__ w,
+                                                      typename C2<T>::type *__restrict__ r,
+                                                      const typename C2<T>::type *__restrict__ q, double *partial)
+{
+    __shared__ double sh[4];
+    const int G = gridDim.x, m = sys_at(list, blockIdx.y);
+    if (off(active, m)) return;
+    const double ww = sc[(long)m * sstride + 1].x;
+    const T a = (T)(ww > 0 ? sc[(long)m * sstride].x / ww : 0.0);
+    x += m * n;
+    w += m * n;
+    r += m * n;
+    q += m * n;
+    double re = 0;
+    for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)G * NT) {
+        typename C2<T>::type xi = x[i], ri = r[i];
+        const typename C2<T>::type wi = w[i], qi = q[i];
+        xi.x = xi.x + a * wi.x;
+        xi.y = xi.y + a * wi.y;
+        ri.x = ri.x - a * qi.x;
+        ri.y = ri.y - a * qi.y;
+        x[i] = xi;
+        r[i] = ri;
+        const double2 d = toD<T>(ri);
+        re += d.x * d.x + d.y * d.y;
+    }
+    re = block_sum(re, sh);
+    if (threadIdx.x == 0) {
+        partial[(long)m * 2 * G + 2 * blockIdx.x] = re;
+        partial[(long)m * 2 * G + 2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+// partial sums of |a|^2 and <a, b> (three per workgroup)
+__global__ __launch_bounds__(NT) void k_norm_dot_partial(const int32_t *active, long n, const double2 *__restrict__ a,
+                                                         const double2 *__restrict__ b, double *partial)
+{
+    __shared__ double sh[4];
+    const int G = gridDim.x, m = blockIdx.y;
+    if (off(active, m)) return;
+    a += m * n;
+    b += m * n;
+    double nn = 0, re = 0, im = 0;
+    for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)G * NT) {
+        const double2 x = a[i], y = b[i];
+        nn += x.x * x.x + x.y * x.y;
+        re += x.x * y.x + x.y * y.y;
+        im += x.x * y.y - x.y * y.x;
+    }
+    nn = block_sum(nn, sh);
+    re = block_sum(re, sh);
+    im = block_sum(im, sh);
+    if (threadIdx.x == 0) {
+        double *p = partial + (long)m * 3 * G + 3 * blockIdx.x;
+        p[0] = nn;
+        p[1] = re;
+        p[2] = im;
+    }
+}
+
+// out_n[m * nstride] = (|a|^2, 0), out_d[m * dstride] = <a, b> / |a|
+__global__ __launch_bounds__(NT) void k_final_norm_dot(const int32_t *active, const double *partial, int G,
+                                                       double2 *out_n, int nstride, double2 *out_d, int dstride)
+{
+    __shared__ double sh[4];
+    const int m = blockIdx.x;
+    if (off(active, m)) return;
+    const double *p = partial + (long)m * 3 * G;
+    double nn = 0, re = 0, im = 0;
+    for (int i = threadIdx.x; i < G; i += NT) {
+        nn += p[3 * i];
+        re += p[3 * i + 1];
+        im += p[3 * i + 2];
+    }
+    nn = block_sum(nn, sh);
+    re = block_sum(re, sh);
+    im = block_sum(im, sh);
+    if (threadIdx.x == 0) {
+        const double f = 1.0 / sqrt(nn);
+        out_n[(long)m * nstride] = make_double2(nn, 0.0);
+        out_d[(long)m * dstride] = make_double2(re * f, im * f);
+    }
+}
+
+// a *= 1 / sqrt(nrm[m * nstride].x), then b -= c[m * cstride] a, and the
+// partial sums of |b|^2 of the new b
+__global__ __launch_bounds__(NT) void k_orth_partial(const int32_t *active, long n, const double2 *nrm, int nstride,
+                                                     const double2 *c, int cstride, double2 *__restrict__ a,
+                                                     double2 *__restrict__ b, double *partial)
+{
+    __shared__ double sh[4];
+    const int G = gridDim.x, m = blockIdx.y;
+    if (off(active, m)) return;
+    const double f = 1.0 / sqrt(nrm[(long)m * nstride].x);
+    const double2 cm = c[(long)m * cstride];
+    const double cr = -cm.x, ci = -cm.y;
+    a += m * n;
+    b += m * n;
+    double s = 0;
+    for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)G * NT) {
+        double2 v = a[i];
+        v = make_double2(f * v.x, f * v.y);
+        a[i] = v;
+        double2 y = b[i];
+        y.x += cr * v.x - ci * v.y;
+        y.y += cr * v.y + ci * v.x;
+        b[i] = y;
+        s += y.x * y.x + y.y * y.y;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        partial[(long)m * 2 * G + 2 * blockIdx.x] = s;
+        partial[(long)m * 2 * G + 2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+// r = b - a and the partial sums of |r|^2
+__global__ __launch_bounds__(NT) void k_sub_partial(const int32_t *active, const int32_t *list, long n,
+                                                    const double2 *__restrict__ b, const double2 *__restrict__ a,
+                                                    double2 *__restrict__ r, double *partial)
+{
+    __shared__ double sh[4];
+    const int G = gridDim.x, m = sys_at(list, blockIdx.y);
+    if (off(active, m)) return;
+    a += m * n;
+    b += m * n;
+    r += m * n;
+    double s = 0;
+    for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)G * NT) {
+        const double2 u = b[i], v = a[i];
+        const double2 d = make_double2(u.x - v.x, u.y - v.y);
+        r[i] = d;
+        s += d.x * d.x + d.y * d.y;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+        partial[(long)m * 2 * G + 2 * blockIdx.x] = s;
+        partial[(long)m * 2 * G + 2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
 int red_grid(long n)
 {
     long g = (n + NT * 8 - 1) / (NT * 8);
@@ -156,23 +309,6 @@ __global__ __launch_bounds__(NT) void k_keep_range(double2 *f, long n, long tota
     if (e < lo || e >= hi) f[i] = make_double2(0.0, 0.0);
 }
 
-__global__ __launch_bounds__(NT) void k_axpy_dev(const int32_t *active, long n, long total, const double2 *c,
-                                                 int cstride, double f, const double2 *__restrict__ x,
-                                                 double2 *__restrict__ y)
-{
-    const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= total) return;
-    const int m = (int)(i / n);
-    if (off(active, m)) return;
-    const double2 cm = c[(long)m * cstride];
-    const double cr = f * cm.x, ci = f * cm.y;
-    const double2 a = x[i];
-    double2 b = y[i];
-    b.x += cr * a.x - ci * a.y;
-    b.y += cr * a.y + ci * a.x;
-    y[i] = b;
-}
-
 __global__ __launch_bounds__(NT) void k_multi_axpy(const int32_t *active, long n, long total, const double2 *c,
                                                    int cstride, double f, const double2 *const *v, int nv,
                                                    const int32_t *cnt, double2 *__restrict__ y, int acc)
@@ -192,19 +328,6 @@ __global__ __launch_bounds__(NT) void k_multi_axpy(const int32_t *active, long n
     }
     y[i] = b;
 }
-
-__global__ __launch_bounds__(NT) void k_scale_invsqrt(const int32_t *active, long n, long total, const double2 *nrm,
-                                                      int nstride, double2 *y)
-{
-    const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= total) return;
-    const int m = (int)(i / n);
-    if (off(active, m)) return;
-    const double f = 1.0 / sqrt(nrm[(long)m * nstride].x);
-    const double2 v = y[i];
-    y[i] = make_double2(f * v.x, f * v.y);
-}
-
 
 __global__ __launch_bounds__(NT) void k_sub(const int32_t *active, const int32_t *list, long n, long total,
                                             const double2 *b, const double2 *a, double2 *r)
@@ -281,6 +404,39 @@ void launch_norm2(const Sys &sy, const T2<T> *a, double *red, double2 *out, int 
     k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
 }
 
+template <typename T>
+void launch_cg_xr_norm(const Sys &sy, const double2 *sc, int sstride, T2<T> *x, const T2<T> *w, T2<T> *r,
+                       const T2<T> *q, double *red, double2 *out, int ostride, hipStream_t s)
+{
+    const int G = red_grid(sy.n);
+    k_cg_xr_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, sc, sstride, x, w, r, q, red);
+    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
+}
+
+void launch_norm_dot(const Sys &sy, const double2 *a, const double2 *b, double *red, double2 *out_n, int nstride,
+                     double2 *out_d, int dstride, hipStream_t s)
+{
+    const int G = red_grid(sy.n);
+    k_norm_dot_partial<<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, a, b, red);
+    k_final_norm_dot<<<sy.M, NT, 0, s>>>(sy.active, red, G, out_n, nstride, out_d, dstride);
+}
+
+void launch_orth_norm(const Sys &sy, const double2 *nrm, int nstride, const double2 *c, int cstride, double2 *a,
+                      double2 *b, double *red, double2 *out, int ostride, hipStream_t s)
+{
+    const int G = red_grid(sy.n);
+    k_orth_partial<<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, nrm, nstride, c, cstride, a, b, red);
+    k_final<<<sy.M, NT, 0, s>>>(sy.active, nullptr, red, G, 1, out, ostride);
+}
+
+void launch_sub_norm(const Sys &sy, const double2 *b, const double2 *a, double2 *r, double *red, double2 *out,
+                     int ostride, hipStream_t s)
+{
+    const int G = red_grid(sy.n);
+    k_sub_partial<<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, b, a, r, red);
+    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
+}
+
 template <typename TO, typename TI> void launch_convert(const Sys &sy, const T2<TI> *a, T2<TO> *out, hipStream_t s)
 {
     const long total = sy.n * sy.M;
@@ -296,22 +452,11 @@ void launch_keep_slots(const Geo &g, const Sys &sy, double2 *f, int slot0, int n
     if (slot0 == 0 && nslots == g.nblk) return;
     k_keep_range<<<nblk(total), NT, 0, s>>>(f, sy.n, total, per * slot0, per * (slot0 + nslots));
 }
-void launch_axpy_dev(const Sys &sy, const double2 *c, int cstride, double f, const double2 *x, double2 *y,
-                     hipStream_t s)
-{
-    const long total = sy.n * sy.M;
-    k_axpy_dev<<<nblk(total), NT, 0, s>>>(sy.active, sy.n, total, c, cstride, f, x, y);
-}
 void launch_multi_axpy(const Sys &sy, const double2 *c, int cstride, double f, const double2 *const *v, int nv,
                        const int32_t *cnt, double2 *y, int acc, hipStream_t s)
 {
     const long total = sy.n * sy.M;
     k_multi_axpy<<<nblk(total), NT, 0, s>>>(sy.active, sy.n, total, c, cstride, f, v, nv, cnt, y, acc);
-}
-void launch_scale_invsqrt(const Sys &sy, const double2 *nrm, int nstride, double2 *y, hipStream_t s)
-{
-    const long total = sy.n * sy.M;
-    k_scale_invsqrt<<<nblk(total), NT, 0, s>>>(sy.active, sy.n, total, nrm, nstride, y);
 }
 void launch_sub(const Sys &sy, const double2 *b, const double2 *a, double2 *r, hipStream_t s)
 {
@@ -335,7 +480,9 @@ void launch_slot_norm2(const Geo &g, const Sys &sy, const double2 *a, double *ou
     template void launch_dot<T>(const Sys &, const T2<T> *, const T2<T> *, double *, double2 *, int, hipStream_t); \
     template void launch_norm2<T>(const Sys &, const T2<T> *, double *, double2 *, int, hipStream_t);            \
     template void launch_zero<T>(T2<T> *, long, hipStream_t);                                                     \
-    template void launch_add_to64<T>(const Sys &, const T2<T> *, double2 *, hipStream_t);
+    template void launch_add_to64<T>(const Sys &, const T2<T> *, double2 *, hipStream_t);                     \
+    template void launch_cg_xr_norm<T>(const Sys &, const double2 *, int, T2<T> *, const T2<T> *, T2<T> *,       \
+                                       const T2<T> *, double *, double2 *, int, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

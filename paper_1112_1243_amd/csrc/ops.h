@@ -119,14 +119,25 @@ void launch_dot(const Sys &sy, const T2<T> *a, const T2<T> *b, double *red, doub
 template <typename T>
 void launch_norm2(const Sys &sy, const T2<T> *a, double *red, double2 *out, int ostride, hipStream_t s);
 
-// y[m] += f * c[m * cstride] * x[m]
-void launch_axpy_dev(const Sys &sy, const double2 *c, int cstride, double f, const double2 *x, double2 *y,
-                     hipStream_t s);
+// Fused solver passes (same deterministic reductions; out written like launch_norm2):
+// CG step with alpha = sc[m*sstride].x / sc[m*sstride+1].x (0 if the latter is
+// not positive): x += alpha w, r -= alpha q, out[m * ostride].x = ||r[m]||^2
+template <typename T>
+void launch_cg_xr_norm(const Sys &sy, const double2 *sc, int sstride, T2<T> *x, const T2<T> *w, T2<T> *r,
+                       const T2<T> *q, double *red, double2 *out, int ostride, hipStream_t s);
+// out_n[m * nstride] = (||a[m]||^2, 0), out_d[m * dstride] = <a[m], b[m]> / ||a[m]||
+void launch_norm_dot(const Sys &sy, const double2 *a, const double2 *b, double *red, double2 *out_n, int nstride,
+                     double2 *out_d, int dstride, hipStream_t s);
+// a[m] *= 1 / sqrt(nrm[m * nstride].x), b[m] -= c[m * cstride] a[m], out[m * ostride].x = ||b[m]||^2
+void launch_orth_norm(const Sys &sy, const double2 *nrm, int nstride, const double2 *c, int cstride, double2 *a,
+                      double2 *b, double *red, double2 *out, int ostride, hipStream_t s);
+// r = b - a, out[m * ostride].x = ||r[m]||^2
+void launch_sub_norm(const Sys &sy, const double2 *b, const double2 *a, double2 *r, double *red, double2 *out,
+                     int ostride, hipStream_t s);
+
 // y[m] = (acc ? y[m] : 0) + f * sum_{j < cnt[m]} c[m * cstride + j] v_j[m]  (cnt NULL: all nv)
 void launch_multi_axpy(const Sys &sy, const double2 *c, int cstride, double f, const double2 *const *v, int nv,
                        const int32_t *cnt, double2 *y, int acc, hipStream_t s);
-// y[m] *= 1 / sqrt(nrm[m * nstride].x)
-void launch_scale_invsqrt(const Sys &sy, const double2 *nrm, int nstride, double2 *y, hipStream_t s);
 // r = b - a
 void launch_sub(const Sys &sy, const double2 *b, const double2 *a, double2 *r, hipStream_t s);
 // y += x for FP64 y and x of precision T

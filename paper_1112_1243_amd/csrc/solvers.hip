@@ -23,44 +23,8 @@ namespace {
 
 // ------------------------------------------------------------ small kernels
 
-// CG scalars per system, 8 per system: [0] rr, [1] ww, [2] alpha,
-// [3] rr_new, [4] beta, [5] true residual
-__global__ void k_cg_alpha(int M, const int32_t *active, double2 *sc)
-{
-    const int m = blockIdx.x * 64 + threadIdx.x;
-    if (m >= M || (active && !active[m])) return;
-    double2 *q = sc + 8L * m;
-    const double ww = q[1].x;
-    q[2] = make_double2(ww > 0 ? q[0].x / ww : 0.0, 0.0);
-}
-__global__ void k_cg_beta(int M, const int32_t *active, double2 *sc)
-{
-    const int m = blockIdx.x * 64 + threadIdx.x;
-    if (m >= M || (active && !active[m])) return;
-    double2 *q = sc + 8L * m;
-    const double rr = q[0].x;
-    q[4] = make_double2(rr > 0 ? q[3].x / rr : 0.0, 0.0);
-    q[0] = q[3];
-}
-
-// x += alpha w, r -= alpha q
-template <typename T>
-__global__ __launch_bounds__(256) void k_cg_update(const int32_t *active, const int32_t *list, long n, long total,
-                                                   const double2 *sc, T2<T> *x, const T2<T> *w, T2<T> *r,
-                                                   const T2<T> *q)
-{
-    const long k = (long)blockIdx.x * 256 + threadIdx.x;
-    if (k >= total) return;
-    int m;
-    const long i = batch_index(list, n, k, m);
-    if (active && !active[m]) return;
-    const T a = (T)sc[8L * m + 2].x;
-    const T2<T> xi = x[i], wi = w[i], ri = r[i], qi = q[i];
-    x[i].x = xi.x + a * wi.x;
-    x[i].y = xi.y + a * wi.y;
-    r[i].x = ri.x - a * qi.x;
-    r[i].y = ri.y - a * qi.y;
-}
+// CG scalars per system, 8 per system: [0] rr, [1] ww, [3] rr_new,
+// [4] beta, [5] true residual (alpha = rr / ww is formed where it is used)
 // p = r + beta p
 template <typename T>
 __global__ __launch_bounds__(256) void k_cg_p(const int32_t *active, const int32_t *list, long n, long total,
@@ -91,16 +55,20 @@ __global__ void k_cgm_init(int M, const double2 *sc, double *bn2, double *rmax, 
     upd[m] = 0;
     its[m] = 0;
 }
-// after an FP32 step: ask for a reliable update once the iterated residual
-// fell by RELIABLE_DELTA below its largest value since the last update (or at
-// the iteration limit, where the true residual decides)
-__global__ void k_cgm_step(int M, const double2 *sc, double delta2, int max_iter, const int32_t *alive, double *rmax,
+// after an FP32 step: beta = rr_new / rr, rr = rr_new; then ask for a
+// reliable update once the iterated residual fell by RELIABLE_DELTA below its
+// largest value since the last update (or at the iteration limit, where the
+// true residual decides)
+__global__ void k_cgm_beta(int M, double2 *sc, double delta2, int max_iter, const int32_t *alive, double *rmax,
                            int32_t *upd, int32_t *its)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M || !alive[m]) return;
+    double2 *q = sc + 8L * m;
+    const double rr0 = q[0].x, rr = q[3].x;
+    q[4] = make_double2(rr0 > 0 ? rr / rr0 : 0.0, 0.0);
+    q[0] = q[3];
     const int k = ++its[m];
-    const double rr = sc[8L * m].x;
     rmax[m] = fmax(rmax[m], rr);
     if (!(rr > delta2 * rmax[m]) || k >= max_iter) upd[m] = 1;
 }
@@ -453,11 +421,9 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
                     launch_multi_axpy(sa, co, 256, -1.0, chis, j, nullptr, chi(j), 1, s);
                 }
             }
-            launch_norm2<double>(sa, chi(j), red.as<double>(), bj + j, 16, s);
-            launch_scale_invsqrt(sa, bj + j, 16, chi(j), s);
-            launch_dot<double>(sa, chi(j), r, red.as<double>(), cj + j, 16, s);
-            launch_axpy_dev(sa, cj + j, 16, -1.0, chi(j), r, s);
-            launch_norm2<double>(sa, r, red.as<double>(), nr, 1, s);
+            // bj = |chi_j|^2, cj = <chi_j, r> / |chi_j|; chi_j /= |chi_j|, r -= cj chi_j, nr = |r|^2
+            launch_norm_dot(sa, chi(j), r, red.as<double>(), bj + j, 16, cj + j, 16, s);
+            launch_orth_norm(sa, bj + j, 16, cj + j, 16, chi(j), r, red.as<double>(), nr, 1, s);
             k_fgcr_inner<<<nbm, 64, 0, s>>>(M, j, nr, bn2, tol2, sp.max_iter, act, cnt, its);
             if (fc) poll.post(act, nr, j & 1, s);
             else poll.post(act, j & 1, s);
@@ -485,8 +451,7 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
         launch_multi_axpy(sw, al, 16, 1.0, phis, nkv, cnt, x, 1, s);
         // true residual
         apply_D64(c, sw, U, kappa, x, t, s);
-        launch_sub(sw, b, t, r, s);
-        launch_norm2<double>(sw, r, red.as<double>(), nr, 1, s);
+        launch_sub_norm(sw, b, t, r, red.as<double>(), nr, 1, s);
         k_fgcr_outer<<<nbm, 64, 0, s>>>(M, nr, bn2, tol2, sp.max_iter, its, alive, act, cnt);
         poll.post(alive, 0, s);
         if (poll.none(0)) break;
@@ -646,19 +611,15 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
             apply_dhat<T>(g, sa, UT, kT, 1, p, t, w, q);
             apply_dhat<T>(g, sa, UT, kT, 0, w, t, qv, q);
             launch_norm2<T>(sa, w, red.as<double>(), sc + 1, 8, q);
-            k_cg_alpha<<<nbm, 64, 0, q>>>(M, alive, sc);
-            k_cg_update<T><<<nb256(tl), 256, 0, q>>>(alive, sa.list, n, tl, sc, e, w, r, qv);
-            launch_norm2<T>(sa, r, red.as<double>(), sc + 3, 8, q);
-            k_cg_beta<<<nbm, 64, 0, q>>>(M, alive, sc);
-            k_cg_p<T><<<nb256(tl), 256, 0, q>>>(alive, sa.list, n, tl, sc, r, p);
-            k_cgm_step<<<nbm, 64, 0, q>>>(M, sc, RELIABLE_DELTA * RELIABLE_DELTA, sp.max_iter, alive, rmax, upd,
+            launch_cg_xr_norm<T>(sa, sc, 8, e, w, r, qv, red.as<double>(), sc + 3, 8, q);
+            k_cgm_beta<<<nbm, 64, 0, q>>>(M, sc, RELIABLE_DELTA * RELIABLE_DELTA, sp.max_iter, alive, rmax, upd,
                                           its);
+            k_cg_p<T><<<nb256(tl), 256, 0, q>>>(alive, sa.list, n, tl, sc, r, p);
         }
         // x_e += e, r = bh - Dhat x_e in FP64
         launch_add_to64<T>(su, e, x, q);
         apply_dhat<double>(g, su, U.u64, kappa, 0, x, o64, t64, q);
-        launch_sub(su, bh, t64, r64, q);
-        launch_norm2<double>(su, r64, red.as<double>(), sc + 5, 8, q);
+        launch_sub_norm(su, bh, t64, r64, red.as<double>(), sc + 5, 8, q);
         k_cgm_update<<<nbm, 64, 0, q>>>(M, sc, bn2, tol * tol, sp.max_iter, its, alive, upd, rmax);
         k_cgm_refresh<T><<<nb256(tl), 256, 0, q>>>(su.list, n, tl, upd, r64, r, e);
         k_cgm_clear<<<nbm, 64, 0, q>>>(M, upd);
