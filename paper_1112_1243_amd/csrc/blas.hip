@@ -244,6 +244,79 @@ __global__ __launch_bounds__(NT) void k_orth_partial(const int32_t *active, long
     }
 }
 
+// One classical Gram-Schmidt update followed by the first pass of the next
+// reduction: y -= sum_{j < nv} c[m * cstride + j] v_j (nv <= CGS_MAXV), then
+// NORM = 0: <v_j, y> for j < nv (partials as k_multidot_partial);
+// NORM = 1: |y|^2 and <y, b> (partials as k_norm_dot_partial).
+constexpr int CGS_MAXV = 16;
+template <int NORM>
+__global__ __launch_bounds__(NT) void k_cgs_partial(const int32_t *active, long n, const double2 *c, int cstride,
+                                                    const double2 *const *v, int nv, double2 *__restrict__ y,
+                                                    const double2 *__restrict__ b, double *partial)
+{
+    __shared__ double sh[4];
+    const int G = gridDim.x, m = blockIdx.y;
+    if (off(active, m)) return;
+    const double2 *vp[CGS_MAXV];
+    double2 cm[CGS_MAXV];
+#pragma unroll
+    for (int j = 0; j < CGS_MAXV; ++j) {
+        vp[j] = j < nv ? v[j] + m * n : nullptr;
+        cm[j] = j < nv ? c[(long)m * cstride + j] : make_double2(0.0, 0.0);
+    }
+    y += m * n;
+    if (NORM) b += m * n;
+    constexpr int NA = NORM ? 3 : 2 * CGS_MAXV;
+    double acc[NA];
+#pragma unroll
+    for (int k = 0; k < NA; ++k) acc[k] = 0;
+    for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)G * NT) {
+        double2 a[CGS_MAXV];
+        double2 yi = y[i];
+#pragma unroll
+        for (int j = 0; j < CGS_MAXV; ++j)
+            if (j < nv) {
+                a[j] = vp[j][i];
+                const double cr = -cm[j].x, ci = -cm[j].y;
+                yi.x += cr * a[j].x - ci * a[j].y;
+                yi.y += cr * a[j].y + ci * a[j].x;
+            }
+        y[i] = yi;
+        if constexpr (NORM) {
+            const double2 bi = b[i];
+            acc[0] += yi.x * yi.x + yi.y * yi.y;
+            acc[1] += yi.x * bi.x + yi.y * bi.y;
+            acc[2] += yi.x * bi.y - yi.y * bi.x;
+        } else {
+#pragma unroll
+            for (int j = 0; j < CGS_MAXV; ++j)
+                if (j < nv) {
+                    acc[2 * j] += a[j].x * yi.x + a[j].y * yi.y;
+                    acc[2 * j + 1] += a[j].x * yi.y - a[j].y * yi.x;
+                }
+        }
+    }
+    if constexpr (NORM) {
+        const double nn = block_sum(acc[0], sh), re = block_sum(acc[1], sh), im = block_sum(acc[2], sh);
+        if (threadIdx.x == 0) {
+            double *p = partial + (long)m * 3 * G + 3 * blockIdx.x;
+            p[0] = nn;
+            p[1] = re;
+            p[2] = im;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < CGS_MAXV; ++j)
+            if (j < nv) {
+                const double re = block_sum(acc[2 * j], sh), im = block_sum(acc[2 * j + 1], sh);
+                if (threadIdx.x == 0) {
+                    partial[((long)m * nv + j) * 2 * G + 2 * blockIdx.x] = re;
+                    partial[((long)m * nv + j) * 2 * G + 2 * blockIdx.x + 1] = im;
+                }
+            }
+    }
+}
+
 // r = b - a and the partial sums of |r|^2
 __global__ __launch_bounds__(NT) void k_sub_partial(const int32_t *active, const int32_t *list, long n,
                                                     const double2 *__restrict__ b, const double2 *__restrict__ a,
@@ -427,6 +500,25 @@ void launch_orth_norm(const Sys &sy, const double2 *nrm, int nstride, const doub
     const int G = red_grid(sy.n);
     k_orth_partial<<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, nrm, nstride, c, cstride, a, b, red);
     k_final<<<sy.M, NT, 0, s>>>(sy.active, nullptr, red, G, 1, out, ostride);
+}
+
+void launch_cgs_multidot(const Sys &sy, const double2 *c, int cstride, const double2 *const *v, int nv, double2 *y,
+                         double *red, double2 *out, int ostride, hipStream_t s)
+{
+    if (nv <= 0 || nv > CGS_MAXV) return;
+    const int G = red_grid(sy.n);
+    k_cgs_partial<0><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, c, cstride, v, nv, y, nullptr, red);
+    k_final<<<sy.M, NT, 0, s>>>(sy.active, nullptr, red, G, nv, out, ostride);
+}
+
+void launch_cgs_norm_dot(const Sys &sy, const double2 *c, int cstride, const double2 *const *v, int nv, double2 *y,
+                         const double2 *b, double *red, double2 *out_n, int nstride, double2 *out_d, int dstride,
+                         hipStream_t s)
+{
+    if (nv <= 0 || nv > CGS_MAXV) return;
+    const int G = red_grid(sy.n);
+    k_cgs_partial<1><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, c, cstride, v, nv, y, b, red);
+    k_final_norm_dot<<<sy.M, NT, 0, s>>>(sy.active, red, G, out_n, nstride, out_d, dstride);
 }
 
 void launch_sub_norm(const Sys &sy, const double2 *b, const double2 *a, double2 *r, double *red, double2 *out,

@@ -131,6 +131,14 @@ void launch_norm_dot(const Sys &sy, const double2 *a, const double2 *b, double *
 // a[m] *= 1 / sqrt(nrm[m * nstride].x), b[m] -= c[m * cstride] a[m], out[m * ostride].x = ||b[m]||^2
 void launch_orth_norm(const Sys &sy, const double2 *nrm, int nstride, const double2 *c, int cstride, double2 *a,
                       double2 *b, double *red, double2 *out, int ostride, hipStream_t s);
+// y[m] -= sum_{j < nv} c[m * cstride + j] v_j[m] (1 <= nv <= 16), then
+// out[m * ostride + j] = <v_j[m], y[m]>
+void launch_cgs_multidot(const Sys &sy, const double2 *c, int cstride, const double2 *const *v, int nv, double2 *y,
+                         double *red, double2 *out, int ostride, hipStream_t s);
+// the same update, then out_n[m * nstride] = (||y[m]||^2, 0), out_d[m * dstride] = <y[m], b[m]> / ||y[m]||
+void launch_cgs_norm_dot(const Sys &sy, const double2 *c, int cstride, const double2 *const *v, int nv, double2 *y,
+                         const double2 *b, double *red, double2 *out_n, int nstride, double2 *out_d, int dstride,
+                         hipStream_t s);
 // r = b - a, out[m * ostride].x = ||r[m]||^2
 void launch_sub_norm(const Sys &sy, const double2 *b, const double2 *a, double2 *r, double *red, double2 *out,
                      int ostride, hipStream_t s);

@@ -413,16 +413,17 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
             wdr_status e = sap64(c, sa, U, kappa, sp, r, phi(j), s);
             if (e != WDR_OK) return e;
             apply_D64(c, sa, U, kappa, phi(j), chi(j), s);
+            // classical Gram-Schmidt, twice (CGS2), each update fused with the
+            // next reduction; then bj = |chi_j|^2, cj = <chi_j, r> / |chi_j|
             if (j > 0) {
-                // classical Gram-Schmidt, twice (CGS2)
-                for (int pass = 0; pass < 2; ++pass) {
-                    double2 *co = A + (size_t)pass * M * 256 + j * 16;
-                    launch_multidot<double>(sa, chis, j, chi(j), red.as<double>(), co, 256, s);
-                    launch_multi_axpy(sa, co, 256, -1.0, chis, j, nullptr, chi(j), 1, s);
-                }
+                double2 *co0 = A + j * 16, *co1 = A + (size_t)M * 256 + j * 16;
+                launch_multidot<double>(sa, chis, j, chi(j), red.as<double>(), co0, 256, s);
+                launch_cgs_multidot(sa, co0, 256, chis, j, chi(j), red.as<double>(), co1, 256, s);
+                launch_cgs_norm_dot(sa, co1, 256, chis, j, chi(j), r, red.as<double>(), bj + j, 16, cj + j, 16, s);
+            } else {
+                launch_norm_dot(sa, chi(j), r, red.as<double>(), bj + j, 16, cj + j, 16, s);
             }
-            // bj = |chi_j|^2, cj = <chi_j, r> / |chi_j|; chi_j /= |chi_j|, r -= cj chi_j, nr = |r|^2
-            launch_norm_dot(sa, chi(j), r, red.as<double>(), bj + j, 16, cj + j, 16, s);
+            // chi_j /= |chi_j|, r -= cj chi_j, nr = |r|^2
             launch_orth_norm(sa, bj + j, 16, cj + j, 16, chi(j), r, red.as<double>(), nr, 1, s);
             k_fgcr_inner<<<nbm, 64, 0, s>>>(M, j, nr, bn2, tol2, sp.max_iter, act, cnt, its);
             if (fc) poll.post(act, nr, j & 1, s);
