@@ -292,8 +292,8 @@ wdr_status wdr_logdet_ratio_batch(int32_t n, const wdr_proposal *props, const wd
                                   void *stream);
 
 /* Schedule autotuner for wdr_logdet_ratio on this context: times a short
- * estimate (at most two path factors, the noise key of *p plus one) for a
- * set of Schwarz depths (cycles x MR steps, FGCR only) and then of block-solve
+ * estimate (at most eight path factors, the noise key of *p plus one; the
+ * faster of two runs after a warm-up run) for a set of Schwarz depths (cycles x MR steps, FGCR only) and then of block-solve
  * MR depths (ratios with block solves), and writes the fastest into p->sp.
  * Every candidate solves to the tolerances of p->sp, so the choice changes
  * time only.  The result is cached in the context per (ratio, solver, inner

@@ -18,8 +18,8 @@ double wall()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// seconds of one short estimate with parameters q (after one untimed run),
-// or infinity if it fails or does not converge
+// seconds of a short estimate with parameters q, the faster of two runs
+// after one untimed run, or infinity if it fails or does not converge
 double trial(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, double kappa, const wdr_est_params &q,
              hipStream_t s)
 {
@@ -27,10 +27,14 @@ double trial(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, double kappa, 
     Stats st;
     if (logdet_ratio(c, props, q, nullptr, nullptr, st, s) != WDR_OK) return INFINITY;
     if (hipStreamSynchronize(s) != hipSuccess) return INFINITY;
-    const double t0 = wall();
-    if (logdet_ratio(c, props, q, nullptr, nullptr, st, s) != WDR_OK) return INFINITY;
-    if (hipStreamSynchronize(s) != hipSuccess) return INFINITY;
-    return wall() - t0;
+    double best = INFINITY;
+    for (int k = 0; k < 2; ++k) {
+        const double t0 = wall();
+        if (logdet_ratio(c, props, q, nullptr, nullptr, st, s) != WDR_OK) return INFINITY;
+        if (hipStreamSynchronize(s) != hipSuccess) return INFINITY;
+        best = std::min(best, wall() - t0);
+    }
+    return best;
 }
 
 }  // namespace
@@ -71,11 +75,14 @@ wdr_status wdr_autotune(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, dou
         p->sp.block_mr_steps = hit->second.block_mr_steps;
     } else {
         wdr_est_params q = *p;
-        q.n_steps = std::min(p->n_steps, 2);
+        // up to 8 path factors: the systems per launch set the balance
+        // between block launches and the rest of a solve
+        q.n_steps = std::min(p->n_steps, 8);
         q.seed = p->seed + 1;
         wdr_solver_params best = p->sp;
         if (p->sp.solver == WDR_SOLVER_FGCR_SAP) {
-            static const int sap[][2] = {{2, 3}, {2, 4}, {3, 3}, {3, 4}, {4, 3}, {4, 4}, {4, 5}, {6, 3}, {6, 4}, {8, 3}};
+            static const int sap[][2] = {{2, 3}, {2, 4}, {3, 3}, {3, 4}, {4, 3}, {4, 4}, {4, 5}, {5, 4},
+                                         {6, 3}, {6, 4}, {6, 5}, {8, 3}, {8, 4}};
             for (const auto &cand : sap) {
                 q.sp = best;
                 q.sp.sap_cycles = cand[0];
@@ -89,7 +96,7 @@ wdr_status wdr_autotune(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, dou
             }
         }
         if (p->op != WDR_OP_FULL) {
-            static const int bmr[] = {6, 8, 12, 16, 24};
+            static const int bmr[] = {6, 8, 12, 16, 24, 32};
             const wdr_solver_params base = best;
             for (int b : bmr) {
                 q.sp = base;
