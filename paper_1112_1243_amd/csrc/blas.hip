@@ -5,6 +5,8 @@
 // then LDS across the 4 wavefronts), and one workgroup per system adds the
 // partial sums in a fixed order.  Results do not depend on scheduling and
 // are bit-reproducible from run to run.
+#include <algorithm>
+
 #include "ops.h"
 
 namespace wdr {
@@ -342,9 +344,15 @@ __global__ __launch_bounds__(NT) void k_sub_partial(const int32_t *active, const
     }
 }
 
-int red_grid(long n)
+// workgroups per system of a reduction over msys systems of n elements: 8
+// elements per thread, or down to 2 while the launch has fewer than about
+// 2048 workgroups (small fields of few systems still spread over the CUs);
+// at most RED_BLOCKS
+int red_grid(long n, int msys)
 {
-    long g = (n + NT * 8 - 1) / (NT * 8);
+    const long g8 = (n + NT * 8 - 1) / (NT * 8), g2 = (n + NT * 2 - 1) / (NT * 2);
+    const long fill = (2048 + std::max(msys, 1) - 1) / std::max(msys, 1);
+    long g = std::max(g8, std::min(g2, fill));
     if (g < 1) g = 1;
     if (g > RED_BLOCKS) g = RED_BLOCKS;
     return (int)g;
@@ -456,7 +464,7 @@ void launch_multidot(const Sys &sy, const T2<T> *const *v, int nv, const T2<T> *
                      int ostride, hipStream_t s)
 {
     if (nv <= 0) return;
-    const int G = red_grid(sy.n);
+    const int G = red_grid(sy.n, sy.M);
     k_multidot_partial<T><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, v, nv, y, red);
     k_final<<<sy.M, NT, 0, s>>>(sy.active, nullptr, red, G, nv, out, ostride);
 }
@@ -464,7 +472,7 @@ void launch_multidot(const Sys &sy, const T2<T> *const *v, int nv, const T2<T> *
 template <typename T>
 void launch_dot(const Sys &sy, const T2<T> *a, const T2<T> *b, double *red, double2 *out, int ostride, hipStream_t s)
 {
-    const int G = red_grid(sy.n);
+    const int G = red_grid(sy.n, sy.launch_m());
     k_dot_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, a, b, 0, red);
     k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
 }
@@ -472,7 +480,7 @@ void launch_dot(const Sys &sy, const T2<T> *a, const T2<T> *b, double *red, doub
 template <typename T>
 void launch_norm2(const Sys &sy, const T2<T> *a, double *red, double2 *out, int ostride, hipStream_t s)
 {
-    const int G = red_grid(sy.n);
+    const int G = red_grid(sy.n, sy.launch_m());
     k_dot_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, a, a, 1, red);
     k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
 }
@@ -481,7 +489,7 @@ template <typename T>
 void launch_cg_xr_norm(const Sys &sy, const double2 *sc, int sstride, T2<T> *x, const T2<T> *w, T2<T> *r,
                        const T2<T> *q, double *red, double2 *out, int ostride, hipStream_t s)
 {
-    const int G = red_grid(sy.n);
+    const int G = red_grid(sy.n, sy.launch_m());
     k_cg_xr_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, sc, sstride, x, w, r, q, red);
     k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
 }
@@ -489,7 +497,7 @@ void launch_cg_xr_norm(const Sys &sy, const double2 *sc, int sstride, T2<T> *x, 
 void launch_norm_dot(const Sys &sy, const double2 *a, const double2 *b, double *red, double2 *out_n, int nstride,
                      double2 *out_d, int dstride, hipStream_t s)
 {
-    const int G = red_grid(sy.n);
+    const int G = red_grid(sy.n, sy.M);
     k_norm_dot_partial<<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, a, b, red);
     k_final_norm_dot<<<sy.M, NT, 0, s>>>(sy.active, red, G, out_n, nstride, out_d, dstride);
 }
@@ -497,7 +505,7 @@ void launch_norm_dot(const Sys &sy, const double2 *a, const double2 *b, double *
 void launch_orth_norm(const Sys &sy, const double2 *nrm, int nstride, const double2 *c, int cstride, double2 *a,
                       double2 *b, double *red, double2 *out, int ostride, hipStream_t s)
 {
-    const int G = red_grid(sy.n);
+    const int G = red_grid(sy.n, sy.M);
     k_orth_partial<<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, nrm, nstride, c, cstride, a, b, red);
     k_final<<<sy.M, NT, 0, s>>>(sy.active, nullptr, red, G, 1, out, ostride);
 }
@@ -506,7 +514,7 @@ void launch_cgs_multidot(const Sys &sy, const double2 *c, int cstride, const dou
                          double *red, double2 *out, int ostride, hipStream_t s)
 {
     if (nv <= 0 || nv > CGS_MAXV) return;
-    const int G = red_grid(sy.n);
+    const int G = red_grid(sy.n, sy.M);
     k_cgs_partial<0><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, c, cstride, v, nv, y, nullptr, red);
     k_final<<<sy.M, NT, 0, s>>>(sy.active, nullptr, red, G, nv, out, ostride);
 }
@@ -516,7 +524,7 @@ void launch_cgs_norm_dot(const Sys &sy, const double2 *c, int cstride, const dou
                          hipStream_t s)
 {
     if (nv <= 0 || nv > CGS_MAXV) return;
-    const int G = red_grid(sy.n);
+    const int G = red_grid(sy.n, sy.M);
     k_cgs_partial<1><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, c, cstride, v, nv, y, b, red);
     k_final_norm_dot<<<sy.M, NT, 0, s>>>(sy.active, red, G, out_n, nstride, out_d, dstride);
 }
@@ -524,7 +532,7 @@ void launch_cgs_norm_dot(const Sys &sy, const double2 *c, int cstride, const dou
 void launch_sub_norm(const Sys &sy, const double2 *b, const double2 *a, double2 *r, double *red, double2 *out,
                      int ostride, hipStream_t s)
 {
-    const int G = red_grid(sy.n);
+    const int G = red_grid(sy.n, sy.launch_m());
     k_sub_partial<<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, b, a, r, red);
     k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
 }
