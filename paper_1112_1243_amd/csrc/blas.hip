@@ -98,24 +98,23 @@ __global__ __launch_bounds__(NT) void k_dot_partial(const int32_t *active, const
     }
 }
 
-// out[m * ostride + j] = sum over the G partials, fixed order
+// out[m * ostride + j] = sum over the G partials, fixed order; workgroup
+// (system, j) for j < nv = gridDim.y
 __global__ __launch_bounds__(NT) void k_final(const int32_t *active, const int32_t *list, const double *partial,
-                                              int G, int nv, double2 *out, int ostride)
+                                              int G, double2 *out, int ostride)
 {
     __shared__ double sh[4];
-    const int m = sys_at(list, blockIdx.x);
+    const int m = sys_at(list, blockIdx.x), j = blockIdx.y, nv = gridDim.y;
     if (off(active, m)) return;
-    for (int j = 0; j < nv; ++j) {
-        const double *p = partial + ((long)m * nv + j) * 2 * G;
-        double re = 0, im = 0;
-        for (int i = threadIdx.x; i < G; i += NT) {
-            re += p[2 * i];
-            im += p[2 * i + 1];
-        }
-        re = block_sum(re, sh);
-        im = block_sum(im, sh);
-        if (threadIdx.x == 0) out[(long)m * ostride + j] = make_double2(re, im);
+    const double *p = partial + ((long)m * nv + j) * 2 * G;
+    double re = 0, im = 0;
+    for (int i = threadIdx.x; i < G; i += NT) {
+        re += p[2 * i];
+        im += p[2 * i + 1];
     }
+    re = block_sum(re, sh);
+    im = block_sum(im, sh);
+    if (threadIdx.x == 0) out[(long)m * ostride + j] = make_double2(re, im);
 }
 
 // Fused passes of the Krylov solvers: an elementwise update followed by the
@@ -466,7 +465,7 @@ void launch_multidot(const Sys &sy, const T2<T> *const *v, int nv, const T2<T> *
     if (nv <= 0) return;
     const int G = red_grid(sy.n, sy.M);
     k_multidot_partial<T><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, v, nv, y, red);
-    k_final<<<sy.M, NT, 0, s>>>(sy.active, nullptr, red, G, nv, out, ostride);
+    k_final<<<dim3(sy.M, nv), NT, 0, s>>>(sy.active, nullptr, red, G, out, ostride);
 }
 
 template <typename T>
@@ -474,7 +473,7 @@ void launch_dot(const Sys &sy, const T2<T> *a, const T2<T> *b, double *red, doub
 {
     const int G = red_grid(sy.n, sy.launch_m());
     k_dot_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, a, b, 0, red);
-    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
+    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, out, ostride);
 }
 
 template <typename T>
@@ -482,7 +481,7 @@ void launch_norm2(const Sys &sy, const T2<T> *a, double *red, double2 *out, int 
 {
     const int G = red_grid(sy.n, sy.launch_m());
     k_dot_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, a, a, 1, red);
-    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
+    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, out, ostride);
 }
 
 template <typename T>
@@ -491,7 +490,7 @@ void launch_cg_xr_norm(const Sys &sy, const double2 *sc, int sstride, T2<T> *x, 
 {
     const int G = red_grid(sy.n, sy.launch_m());
     k_cg_xr_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, sc, sstride, x, w, r, q, red);
-    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
+    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, out, ostride);
 }
 
 void launch_norm_dot(const Sys &sy, const double2 *a, const double2 *b, double *red, double2 *out_n, int nstride,
@@ -507,7 +506,7 @@ void launch_orth_norm(const Sys &sy, const double2 *nrm, int nstride, const doub
 {
     const int G = red_grid(sy.n, sy.M);
     k_orth_partial<<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, nrm, nstride, c, cstride, a, b, red);
-    k_final<<<sy.M, NT, 0, s>>>(sy.active, nullptr, red, G, 1, out, ostride);
+    k_final<<<sy.M, NT, 0, s>>>(sy.active, nullptr, red, G, out, ostride);
 }
 
 void launch_cgs_multidot(const Sys &sy, const double2 *c, int cstride, const double2 *const *v, int nv, double2 *y,
@@ -516,7 +515,7 @@ void launch_cgs_multidot(const Sys &sy, const double2 *c, int cstride, const dou
     if (nv <= 0 || nv > CGS_MAXV) return;
     const int G = red_grid(sy.n, sy.M);
     k_cgs_partial<0><<<dim3(G, sy.M), NT, 0, s>>>(sy.active, sy.n, c, cstride, v, nv, y, nullptr, red);
-    k_final<<<sy.M, NT, 0, s>>>(sy.active, nullptr, red, G, nv, out, ostride);
+    k_final<<<dim3(sy.M, nv), NT, 0, s>>>(sy.active, nullptr, red, G, out, ostride);
 }
 
 void launch_cgs_norm_dot(const Sys &sy, const double2 *c, int cstride, const double2 *const *v, int nv, double2 *y,
@@ -534,7 +533,7 @@ void launch_sub_norm(const Sys &sy, const double2 *b, const double2 *a, double2 
 {
     const int G = red_grid(sy.n, sy.launch_m());
     k_sub_partial<<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, b, a, r, red);
-    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, 1, out, ostride);
+    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, out, ostride);
 }
 
 template <typename TO, typename TI> void launch_convert(const Sys &sy, const T2<TI> *a, T2<TO> *out, hipStream_t s)
