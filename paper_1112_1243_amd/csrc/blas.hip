@@ -454,6 +454,38 @@ __global__ __launch_bounds__(NT) void k_slot_norm2(Geo g, const int32_t *active,
     if (threadIdx.x == 0) out[(long)m * g.nblk + slot] = s;
 }
 
+// Block-solve residual, workgroup (slot, m): on the selected slots
+// [slot0, slot0 + nslots) r = b - t (t NULL: r already holds the residual)
+// and out[m * nblk + slot] = |r|^2 over the slot (the order of
+// k_slot_norm2); every other slot of r is set to zero
+__global__ __launch_bounds__(NT) void k_block_resid_norm(Geo g, const int32_t *active, long n, const double2 *b,
+                                                         const double2 *t, double2 *r, double *out, int slot0,
+                                                         int nslots)
+{
+    __shared__ double sh[4];
+    const int slot = blockIdx.x, m = blockIdx.y;
+    const long cnt = 12L * g.Vb, base = m * n + (long)slot * cnt;
+    if (slot < slot0 || slot >= slot0 + nslots) {
+        for (long i = threadIdx.x; i < cnt; i += NT) r[base + i] = make_double2(0.0, 0.0);
+        return;
+    }
+    if (off(active, m)) return;
+    double s = 0;
+    for (long i = threadIdx.x; i < cnt; i += NT) {
+        double2 v;
+        if (t) {
+            const double2 u = b[base + i], w = t[base + i];
+            v = make_double2(u.x - w.x, u.y - w.y);
+            r[base + i] = v;
+        } else {
+            v = r[base + i];
+        }
+        s += v.x * v.x + v.y * v.y;
+    }
+    s = block_sum(s, sh);
+    if (threadIdx.x == 0) out[(long)m * g.nblk + slot] = s;
+}
+
 inline unsigned nblk(long n) { return (unsigned)((n + NT - 1) / NT); }
 
 }  // namespace
@@ -550,6 +582,11 @@ void launch_keep_slots(const Geo &g, const Sys &sy, double2 *f, int slot0, int n
     const long per = 12L * g.Vb, total = sy.n * sy.M;
     if (slot0 == 0 && nslots == g.nblk) return;
     k_keep_range<<<nblk(total), NT, 0, s>>>(f, sy.n, total, per * slot0, per * (slot0 + nslots));
+}
+void launch_block_resid_norm(const Geo &g, const Sys &sy, const double2 *b, const double2 *t, double2 *r,
+                             double *out, int slot0, int nslots, hipStream_t s)
+{
+    k_block_resid_norm<<<dim3(g.nblk, sy.M), NT, 0, s>>>(g, sy.active, sy.n, b, t, r, out, slot0, nslots);
 }
 void launch_multi_axpy(const Sys &sy, const double2 *c, int cstride, double f, const double2 *const *v, int nv,
                        const int32_t *cnt, double2 *y, int acc, hipStream_t s)
