@@ -370,6 +370,25 @@ __global__ __launch_bounds__(NT) void k_convert(const typename C2<TI>::type *__r
     out[i] = w;
 }
 
+// out = (TO) a and z = 0 (the start of a Schwarz preconditioner: source
+// converted, solution cleared)
+template <typename TO, typename TI>
+__global__ __launch_bounds__(NT) void k_convert_zero(const typename C2<TI>::type *__restrict__ a,
+                                                     typename C2<TO>::type *__restrict__ out,
+                                                     typename C2<TO>::type *__restrict__ z, long total)
+{
+    const long i = (long)blockIdx.x * NT + threadIdx.x;
+    if (i >= total) return;
+    const typename C2<TI>::type v = a[i];
+    typename C2<TO>::type w;
+    w.x = (TO)v.x;
+    w.y = (TO)v.y;
+    out[i] = w;
+    w.x = 0;
+    w.y = 0;
+    z[i] = w;
+}
+
 template <typename T> __global__ __launch_bounds__(NT) void k_zero(typename C2<T>::type *a, long total)
 {
     const long i = (long)blockIdx.x * NT + threadIdx.x;
@@ -568,6 +587,11 @@ void launch_sub_norm(const Sys &sy, const double2 *b, const double2 *a, double2 
     k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, out, ostride);
 }
 
+void launch_convert_zero_f32(const Sys &sy, const double2 *a, float2 *out, float2 *z, hipStream_t s)
+{
+    const long total = sy.n * sy.M;
+    if (total > 0) k_convert_zero<float, double><<<nblk(total), NT, 0, s>>>(a, out, z, total);
+}
 template <typename TO, typename TI> void launch_convert(const Sys &sy, const T2<TI> *a, T2<TO> *out, hipStream_t s)
 {
     const long total = sy.n * sy.M;

@@ -97,6 +97,8 @@ void launch_su3_deviation(const Geo &g, const double2 *U, double *partial, doubl
 
 template <typename TO, typename TI>
 void launch_convert(const Sys &sy, const T2<TI> *a, T2<TO> *out, hipStream_t s);
+// out = (float) a and z = 0 over all M fields
+void launch_convert_zero_f32(const Sys &sy, const double2 *a, float2 *out, float2 *z, hipStream_t s);
 template <typename T> void launch_zero(T2<T> *a, long n, hipStream_t s);
 // block-solve residual: on the slots [slot0, slot0 + nslots) r = b - t (t NULL:
 // r already holds it) and out[m * nblk + slot] = |r|^2 over the slot; zero

@@ -283,11 +283,12 @@ void apply_D64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const
 
 // ------------------------------------------------------------ SAP
 
+// x_zero: x is already zero
 template <typename T>
 static void sap_run(wdr_ctx *c, const Sys &sy, Links<T> U, T kappa, int ncy, int nmr, const T2<T> *eta, T2<T> *x,
-                    hipStream_t s)
+                    hipStream_t s, bool x_zero = false)
 {
-    launch_zero<T>(x, sy.n * sy.M, s);
+    if (!x_zero) launch_zero<T>(x, sy.n * sy.M, s);
     int b0, bn, w0, wn;
     colour_slots(c, 0, b0, bn);
     colour_slots(c, 1, w0, wn);
@@ -343,8 +344,8 @@ wdr_status sap64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, con
     }
     Work e(c, field_bytes(c, WDR_F32) * sy.M), x(c, field_bytes(c, WDR_F32) * sy.M);
     if (!e.ok() || !x.ok()) return WDR_ENOMEM;
-    launch_convert<float, double>(sy, in, e.as<float2>(), s);
-    sap_run<float>(c, sy, U.u32, (float)kappa, sp.sap_cycles, sp.mr_steps, e.as<float2>(), x.as<float2>(), s);
+    launch_convert_zero_f32(sy, in, e.as<float2>(), x.as<float2>(), s);
+    sap_run<float>(c, sy, U.u32, (float)kappa, sp.sap_cycles, sp.mr_steps, e.as<float2>(), x.as<float2>(), s, true);
     launch_convert<double, float>(sy, x.as<float2>(), out, s);
     return WDR_OK;
 }
@@ -722,8 +723,8 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
     launch_convert<double, double>(all, b, r, s);
     launch_keep_slots(g, all, r, slot0, ns, s);
     // the MR kernels write only the selected slots: the rest of d stays zero
-    launch_zero<float>(d32.as<float2>(), n * M, s);
-    launch_zero<double>(d64.as<double2>(), n * M, s);
+    if (sp.inner == WDR_F32) launch_zero<float>(d32.as<float2>(), n * M, s);
+    if (sp.inner == WDR_F64) launch_zero<double>(d64.as<double2>(), n * M, s);
     double *bn = nrm.as<double>(), *rn = bn + (size_t)g.nblk * M;
     launch_slot_norm2(g, all, r, bn, slot0, ns, s);
     k_block_init<<<nbm, 64, 0, s>>>(M, g.nblk, slot0, ns, bn, alive, its, worst);
