@@ -32,3 +32,14 @@ def test_counter_summary_matches_stencil_sources():
     # FP64 moves more than its algorithmic 768 B per site at 32^4, and less than twice that
     alg = 768 * 32 ** 4
     assert alg < bench.counted_traffic("f64") < 2 * alg
+
+
+def test_trace_summary_covers_the_timed_stencil():
+    """The kernel-trace summary holds the 32^4 FP64 block-staged stencil whose
+    launches the roofline object reports, with the HIP-event time beside it."""
+    text = open(os.path.join(ROOT, "profiles", "estimate_wilson8_dd16_kernel_trace.md")).read()
+    rows = [l for l in text.splitlines() if "k_dslash_blk<double, 4, 0, 0>" in l and "1048576x1x1" in l]
+    assert rows, "no 32^4 FP64 k_dslash_blk row"
+    avg_us = float(rows[0].strip().strip("|").split("|")[3])
+    assert 150.0 < avg_us < 300.0
+    assert "bench.py's own HIP" in text
