@@ -473,24 +473,21 @@ __global__ __launch_bounds__(NT) void k_slot_norm2(Geo g, const int32_t *active,
     if (threadIdx.x == 0) out[(long)m * g.nblk + slot] = s;
 }
 
-// Block-solve residual, workgroup (slot, m): on the selected slots
-// [slot0, slot0 + nslots) r = b - t (t NULL: r already holds the residual)
-// and out[m * nblk + slot] = |r|^2 over the slot (the order of
-// k_slot_norm2); every other slot of r is set to zero
-__global__ __launch_bounds__(NT) void k_block_resid_norm(Geo g, const int32_t *active, long n, const double2 *b,
-                                                         const double2 *t, double2 *r, double *out, int slot0,
-                                                         int nslots)
+// Block-solve residual, workgroup (slot0 + blockIdx.x, m) of RESID_NT threads:
+// r = b - t on the slot (t NULL: r already holds the residual) and
+// out[m * nblk + slot] = |r|^2 over the slot.  Other slots are not touched
+// (the caller keeps them zero).
+constexpr int RESID_NT = 1024;
+__global__ __launch_bounds__(RESID_NT) void k_block_resid_norm(Geo g, const int32_t *active, long n,
+                                                               const double2 *b, const double2 *t, double2 *r,
+                                                               double *out, int slot0)
 {
-    __shared__ double sh[4];
-    const int slot = blockIdx.x, m = blockIdx.y;
-    const long cnt = 12L * g.Vb, base = m * n + (long)slot * cnt;
-    if (slot < slot0 || slot >= slot0 + nslots) {
-        for (long i = threadIdx.x; i < cnt; i += NT) r[base + i] = make_double2(0.0, 0.0);
-        return;
-    }
+    __shared__ double sh[RESID_NT / 64];
+    const int slot = slot0 + blockIdx.x, m = blockIdx.y;
     if (off(active, m)) return;
+    const long cnt = 12L * g.Vb, base = m * n + (long)slot * cnt;
     double s = 0;
-    for (long i = threadIdx.x; i < cnt; i += NT) {
+    for (long i = threadIdx.x; i < cnt; i += RESID_NT) {
         double2 v;
         if (t) {
             const double2 u = b[base + i], w = t[base + i];
@@ -501,8 +498,15 @@ __global__ __launch_bounds__(NT) void k_block_resid_norm(Geo g, const int32_t *a
         }
         s += v.x * v.x + v.y * v.y;
     }
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) out[(long)m * g.nblk + slot] = s;
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0;
+#pragma unroll
+        for (int w = 0; w < RESID_NT / 64; ++w) tot += sh[w];
+        out[(long)m * g.nblk + slot] = tot;
+    }
 }
 
 inline unsigned nblk(long n) { return (unsigned)((n + NT - 1) / NT); }
@@ -610,7 +614,7 @@ void launch_keep_slots(const Geo &g, const Sys &sy, double2 *f, int slot0, int n
 void launch_block_resid_norm(const Geo &g, const Sys &sy, const double2 *b, const double2 *t, double2 *r,
                              double *out, int slot0, int nslots, hipStream_t s)
 {
-    k_block_resid_norm<<<dim3(g.nblk, sy.M), NT, 0, s>>>(g, sy.active, sy.n, b, t, r, out, slot0, nslots);
+    if (nslots > 0) k_block_resid_norm<<<dim3(nslots, sy.M), RESID_NT, 0, s>>>(g, sy.active, sy.n, b, t, r, out, slot0);
 }
 void launch_multi_axpy(const Sys &sy, const double2 *c, int cstride, double f, const double2 *const *v, int nv,
                        const int32_t *cnt, double2 *y, int acc, hipStream_t s)

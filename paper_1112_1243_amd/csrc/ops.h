@@ -101,8 +101,8 @@ void launch_convert(const Sys &sy, const T2<TI> *a, T2<TO> *out, hipStream_t s);
 void launch_convert_zero_f32(const Sys &sy, const double2 *a, float2 *out, float2 *z, hipStream_t s);
 template <typename T> void launch_zero(T2<T> *a, long n, hipStream_t s);
 // block-solve residual: on the slots [slot0, slot0 + nslots) r = b - t (t NULL:
-// r already holds it) and out[m * nblk + slot] = |r|^2 over the slot; zero
-// every other slot of r
+// r already holds it) and out[m * nblk + slot] = |r|^2 over the slot; the
+// other slots of r are left as they are
 void launch_block_resid_norm(const Geo &g, const Sys &sy, const double2 *b, const double2 *t, double2 *r,
                              double *out, int slot0, int nslots, hipStream_t s);
 // zero every site outside the slot range [slot0, slot0 + nslots) of each system

@@ -753,7 +753,8 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
             launch_block_mr<float>(g, sa, U.u32, r32.as<float2>(), d32.as<float2>(), (float)kappa, nmr, slot0, ns, s);
             launch_add_to64<float>(sa, d32.as<float2>(), x, s);
         }
-        // r = b - D_b x and its norm per block on the selected blocks, zero elsewhere
+        // r = b - D_b x and its norm per block on the selected blocks (r stays
+        // zero elsewhere: nothing below writes other blocks of r)
         const bool fused = launch_block_residual(g, sa, U.u64, x, b, r, kappa, slot0, ns, s);
         if (!fused) launch_dslash<double>(g, sa, U.u64, HOPS_IN, -1, 0, x, x, t, kappa, slot0, ns, s);
         launch_block_resid_norm(g, sa, b, fused ? nullptr : t, r, rn, slot0, ns, s);
