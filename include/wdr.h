@@ -87,7 +87,16 @@ typedef struct {
     double block_tol;    /* largest per-block relative residual of the
                             Dirichlet block solves (1e-13) */
     double adj_tol;      /* adjoint solves of the second-order sample (1e-7) */
-    wdr_prec inner;      /* precision of SAP / inner iterations */
+    wdr_prec inner;      /* precision of the innermost level: the Schwarz
+                            preconditioner (FGCR), the CG iterations (CGNE;
+                            F16 = FP16 storage with per-block scales, FP32
+                            arithmetic, the FP16 stencil) and the block MR */
+    wdr_prec middle;     /* CGNE only: F64 = two levels (the CG iterations
+                            in `inner` directly under the FP64 reliable
+                            updates); F32 = three levels (inner = F16: FP16
+                            iterations, FP32 reliable updates of the
+                            iterated residual, FP64 reliable updates of the
+                            solution with the true residual).  FGCR: F64 */
     int32_t block_mr_steps; /* MR steps per round of a defect-corrected block solve (16) */
     int32_t update_every;   /* CGNE steps between FP64 reliable-update / convergence points (4) */
     int32_t graph;          /* 1: CGNE replays each period of update_every steps as one HIP graph */
@@ -157,6 +166,18 @@ int32_t wdr_ctx_nblocks(const wdr_ctx *ctx);
 typedef enum { WDR_STENCIL_AUTO = 0, WDR_STENCIL_DIR = 1, WDR_STENCIL_BLK = 2 } wdr_stencil;
 wdr_status wdr_ctx_set_stencil(wdr_ctx *ctx, int32_t choice);
 
+/* Launch form of the FP32 and FP16 block MR of the Dirichlet block solves
+ * (Sec. 3: the block operators D_b inverted inside the Schur complement of
+ * eq. ddfactor) on 4^4 blocks; the arithmetic is the same either way.
+ * WDR_MR_AUTO (the default): WDR_MR_TWO_PER_CU when a launch has at least
+ * 2048 workgroups (blocks x systems), else WDR_MR_ONE_PER_CU.
+ * WDR_MR_ONE_PER_CU: no register cap (one block per CU).
+ * WDR_MR_TWO_PER_CU: compiled for four waves per SIMD (two blocks per CU,
+ * some registers spilled).  Applies to later calls on ctx; EINVAL for
+ * another value. */
+typedef enum { WDR_MR_AUTO = 0, WDR_MR_ONE_PER_CU = 1, WDR_MR_TWO_PER_CU = 2 } wdr_mr_form;
+wdr_status wdr_ctx_set_mr_form(wdr_ctx *ctx, int32_t choice);
+
 /* Geometry maps (Sec. 3), written to caller device buffers of V int32:
  * block id (lexicographic block coordinates), block colour, site parity and
  * position of the site in the black-first block ordering. Any may be NULL. */
@@ -189,8 +210,11 @@ int32_t wdr_gauge_is_su3(const wdr_gauge *g);
 wdr_status wdr_interpolate(wdr_ctx *ctx, const double *dev_U, const double *dev_Up, int32_t i, int32_t N,
                            double *dev_out, void *stream);
 
-/* Noise vector for path step `step`, sample k: for every site (all sites,
- * or only black-block sites if black_only), the words of
+/* Noise vector for path step `step`, sample k (paper Sec. 4: an independent
+ * complex Gaussian noise vector for every factor of eq. param; black sites
+ * only for the Schur complement, whose vectors live on the black blocks of
+ * Sec. 3): for every site (all sites, or only black-block sites if
+ * black_only), the words of
  * Philox4x64-10(counter = (site, step, k, j), key = (seed, 3)), j = 0..5,
  * give complex Gaussian components sqrt(-ln u) exp(2 pi i u') with
  * u = ((w >> 11) + 1/2) 2^-53 (E|eta|^2 = 1), or Z2 components
@@ -230,8 +254,10 @@ wdr_status wdr_apply_D(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec 
 wdr_status wdr_apply_Dblock(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t colour,
                             const double *dev_in, double *dev_out, void *stream);
 
-/* Block-interaction hops: from_colour 1 gives D_bw (white -> black sites),
- * 0 gives D_wb; zero on the sites of colour from_colour. */
+/* Block-interaction hops (Sec. 3, eq. domdec: the off-diagonal blocks D_bw
+ * and D_wb of D in the black/white block ordering, i.e. the hops that cross
+ * a block face): from_colour 1 gives D_bw (white -> black sites), 0 gives
+ * D_wb; zero on the sites of colour from_colour. */
 wdr_status wdr_apply_Dhop(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t from_colour,
                           const double *dev_in, double *dev_out, void *stream);
 
@@ -246,12 +272,21 @@ wdr_status wdr_apply_Dee(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_pre
 wdr_status wdr_sap(wdr_ctx *ctx, const wdr_gauge *U, double kappa, const wdr_solver_params *sp,
                    const double *dev_in, double *dev_out, void *stream);
 
-/* Solve D x = b to sp->tol (true FP64 residual). */
+/* Solve D x = b to sp->tol (true FP64 residual): the inversion that Sec. 4
+ * needs once for each factor of eq. param (D of the proposed field U_{i+1}).
+ * Either solver of sp->solver, at the precisions of sp->inner / sp->middle;
+ * info (host, may be NULL): iterations and the true residual.  ENOCONV at
+ * sp->max_iter with x and info written. */
 wdr_status wdr_solve(wdr_ctx *ctx, const wdr_gauge *U, double kappa, const wdr_solver_params *sp,
                      const double *dev_b, double *dev_x, wdr_solve_info *host_info, void *stream);
 
 /* Solve the Dirichlet block systems of one colour (2: all blocks) to
- * sp->block_tol: x = D_cc^-1 b on those blocks, zero elsewhere. */
+ * sp->block_tol (Sec. 3, eq. domdec: D_bb and D_ww are block diagonal with
+ * the Dirichlet block operators D_b on the diagonal, so their inverses in
+ * eq. ddfactor are independent block solves): x = D_cc^-1 b on those blocks,
+ * zero elsewhere; per-block relative residual <= block_tol.  Even-odd MR
+ * rounds in sp->inner with FP64 defect correction.  ENOCONV if a block
+ * stops above block_tol. */
 wdr_status wdr_block_solve(wdr_ctx *ctx, const wdr_gauge *U, double kappa, int32_t colour,
                            const wdr_solver_params *sp, const double *dev_b, double *dev_x,
                            wdr_solve_info *host_info, void *stream);
@@ -276,7 +311,9 @@ wdr_status wdr_logdet_ratio(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *U
                             wdr_solve_info *host_info, void *stream);
 
 /* The estimate of wdr_logdet_ratio for n independent proposals (possibly on
- * lattices of different sizes) in one batched pass.  Proposals that share a
+ * lattices of different sizes) in one batched pass (Sec. 4, eq. param: the
+ * factors of one proposal, and separate proposals, are independent given
+ * their paths and noise keys, so every factor is an independent system).  Proposals that share a
  * context are solved together: every (proposal, step, noise) sample is one
  * system of the same launches, with its own links, kappa and noise key
  * (props[j].seed; p->seed is not used).  Groups on different contexts run

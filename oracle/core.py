@@ -158,13 +158,11 @@ class Lattice:
 
 
 def block_order(lat: Lattice) -> np.ndarray:
-    """Site ordering of Sec. 3: the sites of the first black block come
-    first, then the second black block, ..., then the white blocks.  Blocks
-    of one colour are taken in lexicographic order of their block
-    coordinates; inside a block the even sites come before the odd sites and
-    each parity is in lexicographic order (the paper leaves the in-block order
-    open; this is the project's choice).  Returns perm with
-    perm[position] = canonical site.
+    """Black-first block ordering (Sec. 3, the block form of eq. domdec):
+    all black blocks precede all white blocks, each colour's blocks by
+    lexicographic block coordinates.  Within a block (an order the paper
+    does not fix; chosen here) even sites precede odd sites, each parity
+    lexicographic.  Returns perm with perm[position] = canonical site.
     """
     bid, col, par = lat.maps()
     x = lat.coords()

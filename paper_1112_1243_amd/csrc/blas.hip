@@ -69,7 +69,7 @@ __global__ __launch_bounds__(NT) void k_multidot_partial(const int32_t *active, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_dot_partial(const int32_t *active, const int32_t *list, long n,
+__global__ __launch_bounds__(NT) void k_dot_partial(const int32_t *active, const int32_t *list, long n, int hs,
                                                     const typename C2<T>::type *__restrict__ a,
                                                     const typename C2<T>::type *__restrict__ b, int norm,
                                                     double *partial)
@@ -79,13 +79,15 @@ __global__ __launch_bounds__(NT) void k_dot_partial(const int32_t *active, const
     if (off(active, m)) return;
     a += m * n;
     b += m * n;
+    const long ne = hs ? n >> 1 : n;
     double re = 0, im = 0;
-    for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)G * NT) {
-        const double2 x = toD<T>(a[i]);
+    for (long i = (long)blockIdx.x * NT + threadIdx.x; i < ne; i += (long)G * NT) {
+        const long e = emap(i, hs);
+        const double2 x = toD<T>(a[e]);
         if (norm) {
             re += x.x * x.x + x.y * x.y;
         } else {
-            const double2 y = toD<T>(b[i]);
+            const double2 y = toD<T>(b[e]);
             re += x.x * y.x + x.y * y.y;
             im += x.x * y.y - x.y * y.x;
         }
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(NT) void k_final(const int32_t *active, const int32
 // (|r|^2 / |w|^2, 0 when |w|^2 is not positive), x += alpha w, r -= alpha q
 // in T, and the partial sums of |r|^2 of the new r.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_cg_xr_partial(const int32_t *active, const int32_t *list, long n,
+__global__ __launch_bounds__(NT) void k_cg_xr_partial(const int32_t *active, const int32_t *list, long n, int hs,
                                                       const double2 *sc, int sstride,
                                                       typename C2<T>::type *__restrict__ x,
                                                       const typename C2<T>::type *__restrict__ w,
@@ -142,8 +144,10 @@ __global__ __launch_bounds__(NT) void k_cg_xr_partial(const int32_t *active, con
     w += m * n;
     r += m * n;
     q += m * n;
+    const long ne = hs ? n >> 1 : n;
     double re = 0;
-    for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)G * NT) {
+    for (long j = (long)blockIdx.x * NT + threadIdx.x; j < ne; j += (long)G * NT) {
+        const long i = emap(j, hs);
         typename C2<T>::type xi = x[i], ri = r[i];
         const typename C2<T>::type wi = w[i], qi = q[i];
         xi.x = xi.x + a * wi.x;
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(NT) void k_cgs_partial(const int32_t *active, long 
 }
 
 // r = b - a and the partial sums of |r|^2
-__global__ __launch_bounds__(NT) void k_sub_partial(const int32_t *active, const int32_t *list, long n,
+__global__ __launch_bounds__(NT) void k_sub_partial(const int32_t *active, const int32_t *list, long n, int hs,
                                                     const double2 *__restrict__ b, const double2 *__restrict__ a,
                                                     double2 *__restrict__ r, double *partial)
 {
@@ -329,8 +333,10 @@ __global__ __launch_bounds__(NT) void k_sub_partial(const int32_t *active, const
     a += m * n;
     b += m * n;
     r += m * n;
+    const long ne = hs ? n >> 1 : n;
     double s = 0;
-    for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)G * NT) {
+    for (long j = (long)blockIdx.x * NT + threadIdx.x; j < ne; j += (long)G * NT) {
+        const long i = emap(j, hs);
         const double2 u = b[i], v = a[i];
         const double2 d = make_double2(u.x - v.x, u.y - v.y);
         r[i] = d;
@@ -441,13 +447,13 @@ __global__ __launch_bounds__(NT) void k_sub(const int32_t *active, const int32_t
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_add_to64(const int32_t *active, const int32_t *list, long n, long total,
-                                                 const typename C2<T>::type *x, double2 *y)
+__global__ __launch_bounds__(NT) void k_add_to64(const int32_t *active, const int32_t *list, long n, int hs,
+                                                 long total, const typename C2<T>::type *x, double2 *y)
 {
     const long k = (long)blockIdx.x * NT + threadIdx.x;
     if (k >= total) return;
     int m;
-    const long i = batch_index(list, n, k, m);
+    const long i = batch_elem(list, n, hs, k, m);
     if (off(active, m)) return;
     const typename C2<T>::type u = x[i];
     const double2 v = y[i];
@@ -526,16 +532,16 @@ void launch_multidot(const Sys &sy, const T2<T> *const *v, int nv, const T2<T> *
 template <typename T>
 void launch_dot(const Sys &sy, const T2<T> *a, const T2<T> *b, double *red, double2 *out, int ostride, hipStream_t s)
 {
-    const int G = red_grid(sy.n, sy.launch_m());
-    k_dot_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, a, b, 0, red);
+    const int G = red_grid(sy.ne(), sy.launch_m());
+    k_dot_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, sy.hs, a, b, 0, red);
     k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, out, ostride);
 }
 
 template <typename T>
 void launch_norm2(const Sys &sy, const T2<T> *a, double *red, double2 *out, int ostride, hipStream_t s)
 {
-    const int G = red_grid(sy.n, sy.launch_m());
-    k_dot_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, a, a, 1, red);
+    const int G = red_grid(sy.ne(), sy.launch_m());
+    k_dot_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, sy.hs, a, a, 1, red);
     k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, out, ostride);
 }
 
@@ -543,9 +549,15 @@ template <typename T>
 void launch_cg_xr_norm(const Sys &sy, const double2 *sc, int sstride, T2<T> *x, const T2<T> *w, T2<T> *r,
                        const T2<T> *q, double *red, double2 *out, int ostride, hipStream_t s)
 {
-    const int G = red_grid(sy.n, sy.launch_m());
-    k_cg_xr_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, sc, sstride, x, w, r, q, red);
+    const int G = red_grid(sy.ne(), sy.launch_m());
+    k_cg_xr_partial<T><<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, sy.hs, sc, sstride, x, w, r, q,
+                                                              red);
     k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, out, ostride);
+}
+
+void launch_final(const Sys &sy, const double *partial, int G, double2 *out, int ostride, hipStream_t s)
+{
+    k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, partial, G, out, ostride);
 }
 
 void launch_norm_dot(const Sys &sy, const double2 *a, const double2 *b, double *red, double2 *out_n, int nstride,
@@ -586,8 +598,8 @@ void launch_cgs_norm_dot(const Sys &sy, const double2 *c, int cstride, const dou
 void launch_sub_norm(const Sys &sy, const double2 *b, const double2 *a, double2 *r, double *red, double2 *out,
                      int ostride, hipStream_t s)
 {
-    const int G = red_grid(sy.n, sy.launch_m());
-    k_sub_partial<<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, b, a, r, red);
+    const int G = red_grid(sy.ne(), sy.launch_m());
+    k_sub_partial<<<dim3(G, sy.launch_m()), NT, 0, s>>>(sy.active, sy.list, sy.n, sy.hs, b, a, r, red);
     k_final<<<sy.launch_m(), NT, 0, s>>>(sy.active, sy.list, red, G, out, ostride);
 }
 
@@ -629,8 +641,8 @@ void launch_sub(const Sys &sy, const double2 *b, const double2 *a, double2 *r, h
 }
 template <typename T> void launch_add_to64(const Sys &sy, const T2<T> *x, double2 *y, hipStream_t s)
 {
-    const long total = sy.n * sy.launch_m();
-    k_add_to64<T><<<nblk(total), NT, 0, s>>>(sy.active, sy.list, sy.n, total, x, y);
+    const long total = sy.ne() * sy.launch_m();
+    k_add_to64<T><<<nblk(total), NT, 0, s>>>(sy.active, sy.list, sy.n, sy.hs, total, x, y);
 }
 void launch_slot_norm2(const Geo &g, const Sys &sy, const double2 *a, double *out, int slot0, int nslots,
                        hipStream_t s)

@@ -1,0 +1,476 @@
+// FP16 storage for the even-odd CG of the global solves (the inversion that
+// paper Sec. 4 needs once for each factor of eq. param), 4^4 blocks, SU(3)
+// links.
+//
+// Layouts (internal to the CG; the FP16 fields of the C ABI keep theirs):
+//   E16 field  [system][slot][Vh][12] FP16 complex: one parity of every
+//              block, site-major, so the 12 values of a site are 48
+//              contiguous bytes (three 16-byte loads per lane); one
+//              power-of-two scale per (system, slot): stored value v / s,
+//              s = 2^ceil(log2 max |component|) over the block's half.
+//   E16 links  [slot][parity][mu] chunks of Vh links, each chunk the first
+//              four entries of rows 0-1 (16 bytes per link, Vh of them) then
+//              the last two (8 bytes per link): U_mu(x) of the sites of that
+//              parity, boundary phase folded in, third row rebuilt.
+// Arithmetic is FP32 throughout; norms are summed in FP64.
+#include "stencil.h"
+
+namespace wdr {
+namespace {
+
+using namespace dev;
+
+constexpr int B4 = 4, VB4 = 256, VH4 = 128;
+
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+typedef const __attribute__((address_space(1))) v4u *G4;  // 16-byte words in global memory
+union Q16 {
+    v4u u;
+    h2 h[4];
+};
+union D16 {
+    v2u u;
+    h2 h[2];
+};
+
+template <typename P> __device__ __forceinline__ const __attribute__((address_space(1))) P *glob(const P *p)
+{
+    return (const __attribute__((address_space(1))) P *)p;
+}
+__device__ __forceinline__ G4 g4(const uint4 *p) { return (G4)p; }
+
+// the 12 values of site `site` (index in units of sites) times scale s
+__device__ __forceinline__ void ld_site(G4 f, long site, float s, cx<float> v[12])
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        Q16 q;
+        q.u = f[site * 3 + k];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[4 * k + j] = mk<float>((float)q.h[j].x * s, (float)q.h[j].y * s);
+    }
+}
+__device__ __forceinline__ void st_site(uint4 *f, long site, const cx<float> v[12], float inv)
+{
+    __attribute__((address_space(1))) v4u *o = (__attribute__((address_space(1))) v4u *)f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        Q16 q;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) q.h[j] = to_h2(v[4 * k + j], inv);
+        o[site * 3 + k] = q.u;
+    }
+}
+// |v|^2 of the values as stored (rounded to FP16, times the scale)
+__device__ __forceinline__ double stored_norm2(const cx<float> v[12], float s, float inv)
+{
+    double n = 0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const h2 h = to_h2(v[c], inv);
+        const double re = (double)((float)h.x * s), im = (double)((float)h.y * s);
+        n += re * re + im * im;
+    }
+    return n;
+}
+
+// link chunk (slot, parity, mu): entries 0..3 for Vh sites, then 4..5
+__device__ __forceinline__ void ld_link(const __attribute__((address_space(1))) h2 *L, int chunk, int i, float sg,
+                                        su3<float> &u)
+{
+    const auto *base = L + (long)chunk * VH4 * 6;
+    Q16 a;
+    D16 b;
+    a.u = ((G4)base)[i];
+    b.u = ((const __attribute__((address_space(1))) v2u *)(base + VH4 * 4))[i];
+    u.m[0][0] = mk<float>((float)a.h[0].x, (float)a.h[0].y);
+    u.m[0][1] = mk<float>((float)a.h[1].x, (float)a.h[1].y);
+    u.m[0][2] = mk<float>((float)a.h[2].x, (float)a.h[2].y);
+    u.m[1][0] = mk<float>((float)a.h[3].x, (float)a.h[3].y);
+    u.m[1][1] = mk<float>((float)b.h[0].x, (float)b.h[0].y);
+    u.m[1][2] = mk<float>((float)b.h[1].x, (float)b.h[1].y);
+    // third row conj(row0 x row1), times the boundary sign that the stored
+    // rows carry when the link wraps around the lattice
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int p = (c + 1) % 3, q = (c + 2) % 3;
+        const cx<float> v = u.m[0][p] * u.m[1][q] - u.m[0][q] * u.m[1][p];
+        u.m[2][c] = mk<float>(sg * v.re, -sg * v.im);
+    }
+}
+
+// largest |component| over the workgroup of NT threads; sh: NT / 64 floats
+template <int NT> __device__ __forceinline__ float block_max(float v, float *sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float r = sh[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) r = fmaxf(r, sh[w]);
+    return r;
+}
+template <int NT> __device__ __forceinline__ double block_sum(double v, double *sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = sh[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) r += sh[w];
+    return r;
+}
+
+// the block's power-of-two scale of v (all threads), rounded store, and the
+// norm of the stored values into partial (2 doubles per (system, slot), the
+// layout of the deterministic reduction's first pass) when asked
+__device__ __forceinline__ void store_block(const cx<float> v[12], uint4 *outv, float *outs, long site, long blk,
+                                            double *partial, long pidx)
+{
+    __shared__ float redf[VH4 / 64];
+    __shared__ double redd[VH4 / 64];
+    float mx = 0.f;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) mx = fmaxf(mx, fmaxf(fabsf(v[c].re), fabsf(v[c].im)));
+    const float s = pow2_at_least(block_max<VH4>(mx, redf)), inv = 1.f / s;
+    st_site(outv, site, v, inv);
+    if (threadIdx.x == 0) outs[blk] = s;
+    if (partial) {
+        const double n = block_sum<VH4>(stored_norm2(v, s, inv), redd);
+        if (threadIdx.x == 0) {
+            partial[2 * pidx] = n;
+            partial[2 * pidx + 1] = 0.0;
+        }
+    }
+}
+
+// The two hops of direction MU at output site t (coords x, parity par) of
+// block `slot`: neighbours of the other parity from the block's LDS copy sh
+// or, across a face, from the FP16 field (times the neighbour block's
+// scale); links from the E16 link chunks.  DAG applies gamma_5 to the loaded
+// spinors (the caller to the result).
+template <int MU, int DAG>
+__device__ __forceinline__ void hop16(const float2 (*sh)[VH4], G4 inf,
+                                      const float *ins, long fbase, const __attribute__((address_space(1))) h2 *L,
+                                      int slot, const int nbr[8], int par, int t, const int x[4], spinor<float> &acc,
+                                      float wrap_f, float wrap_b)
+{
+    typedef Cube<B4> CB;
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+        const bool fwd = dir == 0;
+        const bool inside = fwd ? x[MU] + 1 < B4 : x[MU] > 0;
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        y[MU] = fwd ? (inside ? x[MU] + 1 : 0) : (inside ? x[MU] - 1 : B4 - 1);
+        const int ns = inside ? slot : nbr[2 * MU + dir];
+        const int j = CB::index(y) - (1 - par) * VH4;
+        spinor<float> p;
+        if (inside) {
+#pragma unroll
+            for (int c = 0; c < 12; ++c) p.s[c / 3].c[c % 3] = mk<float>(sh[c][j].x, sh[c][j].y);
+        } else {
+            cx<float> v[12];
+            ld_site(inf, (fbase + ns) * VH4 + j, ins[fbase + ns], v);
+#pragma unroll
+            for (int c = 0; c < 12; ++c) p.s[c / 3].c[c % 3] = v[c];
+        }
+        su3<float> u;
+        if (fwd)
+            ld_link(L, (slot * 2 + par) * 4 + MU, t, wrap_f, u);
+        else
+            ld_link(L, (ns * 2 + (1 - par)) * 4 + MU, j, wrap_b, u);
+        if (DAG) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                p.s[2].c[a] = neg(p.s[2].c[a]);
+                p.s[3].c[a] = neg(p.s[3].c[a]);
+            }
+        }
+        vec3<float> a0, a1;
+        A_dn(MU, p.s[2], p.s[3], a0, a1);
+        vec3<float> h0, h1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            h0.c[a] = fwd ? p.s[0].c[a] - a0.c[a] : p.s[0].c[a] + a0.c[a];
+            h1.c[a] = fwd ? p.s[1].c[a] - a1.c[a] : p.s[1].c[a] + a1.c[a];
+        }
+        const vec3<float> c0 = fwd ? mul(u, h0) : mul_dag(u, h0);
+        const vec3<float> c1 = fwd ? mul(u, h1) : mul_dag(u, h1);
+        vec3<float> d0, d1;
+        Adag_h(MU, c0, c1, d0, d1);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
+            acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
+            acc.s[2].c[a] = fwd ? acc.s[2].c[a] - d0.c[a] : acc.s[2].c[a] + d0.c[a];
+            acc.s[3].c[a] = fwd ? acc.s[3].c[a] - d1.c[a] : acc.s[3].c[a] + d1.c[a];
+        }
+    }
+}
+
+// out = diag + f H_{par, 1-par} in on the sites of parity par (gamma_5 on
+// both sides of H for DAG), f = fs kappa_m (or fk without a kappa table);
+// FP16 E16 fields in and out, diag optional.  One workgroup per block and
+// system, one lane per output site; the block's input half is staged in LDS
+// as FP32.  partial (optional): |out|^2 of the stored values per block.
+template <int DAG>
+__global__ __launch_bounds__(VH4) void k_eo16(Geo g, const int32_t *__restrict__ active,
+                                              const int32_t *__restrict__ list, const h2 *const *__restrict__ ltab,
+                                              const double *__restrict__ kap, float fs, float fk, int par,
+                                              const int32_t *__restrict__ sched, const uint4 *__restrict__ inv,
+                                              const float *__restrict__ ins, const uint4 *__restrict__ dgv,
+                                              const float *__restrict__ dgs, uint4 *__restrict__ outv,
+                                              float *__restrict__ outs, double *__restrict__ partial)
+{
+    typedef Cube<B4> CB;
+    __shared__ float2 sh[12][VH4];  // the block's input half, component-major
+    const int m = sys_at(list, blockIdx.y);
+    if (active && !active[m]) return;
+    const float f = kap ? fs * (float)kap[m] : fk;
+    const int slot = sched[blockIdx.x];
+    const int t = threadIdx.x;
+    const long fbase = (long)m * g.nblk;
+    const G4 inf = g4(inv);
+    {
+        cx<float> v[12];
+        ld_site(inf, (fbase + slot) * VH4 + t, ins[fbase + slot], v);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) sh[c][t] = make_float2(v[c].re, v[c].im);
+    }
+    int x[4];
+    CB::coords(par * VH4 + t, x);
+    int nbr[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
+    const int bl = g.slot_blk[slot];
+    const auto *L = glob(ltab[m]);
+    __syncthreads();
+    spinor<float> acc;
+    zero(acc);
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        float wf = 1.f, wb = 1.f;
+        if (g.bc[mu] < 0) {
+            int b2 = bl;
+            for (int d = 0; d < mu; ++d) b2 /= g.NB[d];
+            const int nmu = b2 % g.NB[mu];
+            if (nmu == g.NB[mu] - 1 && x[mu] == B4 - 1) wf = -1.f;
+            if (nmu == 0 && x[mu] == 0) wb = -1.f;
+        }
+        switch (mu) {
+        case 0: hop16<0, DAG>(sh, inf, ins, fbase, L, slot, nbr, par, t, x, acc, wf, wb); break;
+        case 1: hop16<1, DAG>(sh, inf, ins, fbase, L, slot, nbr, par, t, x, acc, wf, wb); break;
+        case 2: hop16<2, DAG>(sh, inf, ins, fbase, L, slot, nbr, par, t, x, acc, wf, wb); break;
+        default: hop16<3, DAG>(sh, inf, ins, fbase, L, slot, nbr, par, t, x, acc, wf, wb); break;
+        }
+    }
+    const long site = (fbase + slot) * VH4 + t;
+    cx<float> dg[12];
+    if (dgv) ld_site(g4(dgv), site, dgs[fbase + slot], dg);
+    cx<float> res[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        cx<float> v = scale(f, acc.s[c / 3].c[c % 3]);
+        if (DAG && c >= 6) v = neg(v);
+        res[c] = dgv ? v + dg[c] : v;
+    }
+    store_block(res, outv, outs, site, fbase + slot, partial, fbase + slot);
+}
+
+// one CG step on the FP16 vectors of system m, alpha = sc[8m].x / sc[8m+1].x:
+// x += alpha w (x FP32, the internal component-major layout, even sites),
+// r -= alpha q (FP16, fresh block scales), partial sums of |r|^2
+__global__ __launch_bounds__(VH4) void k_xr16(Geo g, const int32_t *__restrict__ active,
+                                              const int32_t *__restrict__ list, const double2 *__restrict__ sc,
+                                              float2 *__restrict__ x, const uint4 *__restrict__ wv,
+                                              const float *__restrict__ ws, const uint4 *__restrict__ qv,
+                                              const float *__restrict__ qs, uint4 *__restrict__ rv,
+                                              float *__restrict__ rs, double *__restrict__ partial)
+{
+    const int m = sys_at(list, blockIdx.y);
+    if (active && !active[m]) return;
+    const int slot = blockIdx.x, t = threadIdx.x;
+    const double ww = sc[8L * m + 1].x;
+    const float a = (float)(ww > 0 ? sc[8L * m].x / ww : 0.0);
+    const long blk = (long)m * g.nblk + slot, site = blk * VH4 + t;
+    cx<float> w[12], q[12], r[12];
+    ld_site(g4(wv), site, ws[blk], w);
+    ld_site(g4(qv), site, qs[blk], q);
+    ld_site(g4(rv), site, rs[blk], r);
+    float2 *xs = x + blk * 12 * VB4 + t;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        float2 xv = xs[c * VB4];
+        xv.x += a * w[c].re;
+        xv.y += a * w[c].im;
+        xs[c * VB4] = xv;
+        r[c] = r[c] - scale(a, q[c]);
+    }
+    __syncthreads();  // every lane has read its r before the block's scale is rewritten
+    store_block(r, rv, rs, site, blk, partial, blk);
+}
+
+// p = r + beta p (beta = sc[8m + 4].x), or p = r with copy
+__global__ __launch_bounds__(VH4) void k_p16(Geo g, const int32_t *__restrict__ active,
+                                             const int32_t *__restrict__ list, const double2 *__restrict__ sc,
+                                             int copy, const uint4 *__restrict__ rv, const float *__restrict__ rs,
+                                             uint4 *__restrict__ pv, float *__restrict__ ps)
+{
+    const int m = sys_at(list, blockIdx.y);
+    if (active && !active[m]) return;
+    const int slot = blockIdx.x, t = threadIdx.x;
+    const long blk = (long)m * g.nblk + slot, site = blk * VH4 + t;
+    cx<float> r[12], p[12];
+    ld_site(g4(rv), site, rs[blk], r);
+    if (!copy) {
+        const float b = (float)sc[8L * m + 4].x;
+        ld_site(g4(pv), site, ps[blk], p);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) r[c] = r[c] + scale(b, p[c]);
+    }
+    __syncthreads();
+    store_block(r, pv, ps, site, blk, nullptr, 0);
+}
+
+// the middle level's residual: r = bh - d on even sites (FP32, component-major)
+// into the FP16 iterated residual, and the partial sums of |r|^2 of the FP32
+// values
+__global__ __launch_bounds__(VH4) void k_r16_from32(Geo g, const int32_t *__restrict__ active,
+                                                    const int32_t *__restrict__ list, const float2 *__restrict__ bh,
+                                                    const float2 *__restrict__ d, uint4 *__restrict__ rv,
+                                                    float *__restrict__ rs, double *__restrict__ partial)
+{
+    __shared__ double redd[VH4 / 64];
+    const int m = sys_at(list, blockIdx.y);
+    if (active && !active[m]) return;
+    const int slot = blockIdx.x, t = threadIdx.x;
+    const long blk = (long)m * g.nblk + slot, site = blk * VH4 + t;
+    const long e0 = blk * 12 * VB4 + t;
+    cx<float> r[12];
+    double n = 0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const float2 a = bh[e0 + c * VB4], b = d[e0 + c * VB4];
+        r[c] = mk<float>(a.x - b.x, a.y - b.y);
+        n += (double)r[c].re * r[c].re + (double)r[c].im * r[c].im;
+    }
+    n = block_sum<VH4>(n, redd);
+    if (t == 0) {
+        partial[2 * blk] = n;
+        partial[2 * blk + 1] = 0.0;
+    }
+    store_block(r, rv, rs, site, blk, nullptr, 0);
+}
+
+// the outer level's reliable update (after x64 += x32 and r64 = bh - Dhat
+// x64): the middle system restarts from r64, bh32 = (float) r64, x32 = 0,
+// and the FP16 iterated residual r = r64
+__global__ __launch_bounds__(VH4) void k_r16_from64(Geo g, const int32_t *__restrict__ active,
+                                                    const int32_t *__restrict__ list, const double2 *__restrict__ r64,
+                                                    float2 *__restrict__ bh, float2 *__restrict__ x,
+                                                    uint4 *__restrict__ rv, float *__restrict__ rs)
+{
+    const int m = sys_at(list, blockIdx.y);
+    if (active && !active[m]) return;
+    const int slot = blockIdx.x, t = threadIdx.x;
+    const long blk = (long)m * g.nblk + slot, site = blk * VH4 + t;
+    const long e0 = blk * 12 * VB4 + t;
+    cx<float> r[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const double2 v = r64[e0 + c * VB4];
+        r[c] = mk<float>((float)v.x, (float)v.y);
+        bh[e0 + c * VB4] = make_float2(r[c].re, r[c].im);
+        x[e0 + c * VB4] = make_float2(0.f, 0.f);
+    }
+    store_block(r, rv, rs, site, blk, nullptr, 0);
+}
+
+// E16 links from the internal FP64 links ([slot][mu][9][Vb], boundary phase
+// folded in), rounded through FP32 like every FP16 copy of the library
+__global__ __launch_bounds__(256) void k_pack_links_e16(long total, const double2 *__restrict__ u64,
+                                                        h2 *__restrict__ out)
+{
+    const long k = (long)blockIdx.x * 256 + threadIdx.x;  // (slot, mu, l)
+    if (k >= total) return;
+    const int l = (int)(k % VB4);
+    const long sm = k / VB4;
+    const int mu = (int)(sm % 4);
+    const long slot = sm / 4;
+    const int par = l >= VH4 ? 1 : 0, i = l - par * VH4;
+    const double2 *src = u64 + sm * 9 * VB4 + l;
+    h2 *chunk = out + ((slot * 2 + par) * 4 + mu) * VH4 * 6;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+        const double2 v = src[(long)e * VB4];
+        h2 h;
+        h.x = (_Float16)(float)v.x;
+        h.y = (_Float16)(float)v.y;
+        if (e < 4)
+            chunk[i * 4 + e] = h;
+        else
+            chunk[VH4 * 4 + i * 2 + (e - 4)] = h;
+    }
+}
+
+}  // namespace
+
+bool e16_geometry(const Geo &g)
+{
+    return g.B[0] == B4 && g.B[1] == B4 && g.B[2] == B4 && g.B[3] == B4 && g.colourable;
+}
+
+size_t e16_field_bytes(const Geo &g, int M) { return (size_t)M * g.nblk * (VH4 * 48 + sizeof(float)); }
+
+E16 e16_field(const Geo &g, int M, void *p)
+{
+    uint4 *v = static_cast<uint4 *>(p);
+    return E16{v, reinterpret_cast<float *>(v + (size_t)M * g.nblk * VH4 * 3)};
+}
+
+void launch_pack_links_e16(const Geo &g, const double2 *u64, h2 *e16, hipStream_t s)
+{
+    const long total = (long)g.nblk * 4 * VB4;
+    k_pack_links_e16<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(total, u64, e16);
+}
+
+void launch_eo16(const Geo &g, const Sys &sy, Links16 U, float fs, float fk, int par, int dag, E16c in, E16c diag,
+                 E16 out, double *partial, hipStream_t s)
+{
+    const int si = sched_index(g, 0, g.nblk);
+    const dim3 grid(g.nblk, sy.launch_m());
+    if (dag)
+        k_eo16<1><<<grid, VH4, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, fs, fk, par, g.sched[si], in.v, in.s,
+                                       diag.v, diag.s, out.v, out.s, partial);
+    else
+        k_eo16<0><<<grid, VH4, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, fs, fk, par, g.sched[si], in.v, in.s,
+                                       diag.v, diag.s, out.v, out.s, partial);
+}
+
+void launch_xr16(const Geo &g, const Sys &sy, const double2 *sc, float2 *x, E16c w, E16c q, E16 r, double *partial,
+                 hipStream_t s)
+{
+    k_xr16<<<dim3(g.nblk, sy.launch_m()), VH4, 0, s>>>(g, sy.active, sy.list, sc, x, w.v, w.s, q.v, q.s, r.v, r.s,
+                                                        partial);
+}
+
+void launch_p16(const Geo &g, const Sys &sy, const double2 *sc, int copy, E16c r, E16 p, hipStream_t s)
+{
+    k_p16<<<dim3(g.nblk, sy.launch_m()), VH4, 0, s>>>(g, sy.active, sy.list, sc, copy, r.v, r.s, p.v, p.s);
+}
+
+void launch_r16_from32(const Geo &g, const Sys &sy, const float2 *bh, const float2 *d, E16 r, double *partial,
+                       hipStream_t s)
+{
+    k_r16_from32<<<dim3(g.nblk, sy.launch_m()), VH4, 0, s>>>(g, sy.active, sy.list, bh, d, r.v, r.s, partial);
+}
+
+void launch_r16_from64(const Geo &g, const Sys &sy, const double2 *r64, float2 *bh, float2 *x, E16 r, hipStream_t s)
+{
+    k_r16_from64<<<dim3(g.nblk, sy.launch_m()), VH4, 0, s>>>(g, sy.active, sy.list, r64, bh, x, r.v, r.s);
+}
+
+}  // namespace wdr

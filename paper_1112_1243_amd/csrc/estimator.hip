@@ -28,14 +28,17 @@ namespace wdr {
 namespace {
 
 struct TmpGauge {
-    Work u64, u32, u16;
-    TmpGauge(wdr_ctx *c, bool su3)
+    Work u64, u32, u16, e16;
+    // su3: FP16 links for the block MR / Schwarz kernels; cg16: E16 links
+    // for the FP16 even-odd CG as well
+    TmpGauge(wdr_ctx *c, bool su3, bool cg16)
         : u64(c, (size_t)c->g.V * 36 * sizeof(double2)), u32(c, (size_t)c->g.V * 36 * sizeof(float2)),
-          u16(c, su3 ? (size_t)c->g.V * 24 * sizeof(h2) : 256), has16(su3)
+          u16(c, su3 ? (size_t)c->g.V * 24 * sizeof(h2) : 256),
+          e16(c, su3 && cg16 ? (size_t)c->g.V * 24 * sizeof(h2) : 256), has16(su3), hase16(su3 && cg16)
     {
     }
-    bool ok() const { return u64.ok() && u32.ok() && u16.ok(); }
-    bool has16;
+    bool ok() const { return u64.ok() && u32.ok() && u16.ok() && e16.ok(); }
+    bool has16, hase16;
 };
 
 // U_0 .. U_N of one proposal into pts[0 .. N]: the end points are copies, the
@@ -58,6 +61,7 @@ void make_path_gauges(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, int N
         TmpGauge &dst = *pts[i];
         launch_convert_gauge_f32(c->g, dst.u64.as<double2>(), dst.u32.as<float2>(), s);
         if (dst.has16) launch_pack_links_h16(c->g, dst.u64.as<double2>(), dst.u16.as<h2>(), s);
+        if (dst.hase16) launch_pack_links_e16(c->g, dst.u64.as<double2>(), dst.e16.as<h2>(), s);
     }
 }
 
@@ -70,7 +74,7 @@ constexpr double CHUNK_BYTES = 48e9;
 struct Path {
     std::vector<std::unique_ptr<TmpGauge>> pts;
     int N = 0, su3 = 1;
-    bool has16 = false;
+    bool has16 = false, hase16 = false;
     TmpGauge &at(int prop, int i) const { return *pts[(size_t)prop * (N + 1) + i]; }
 };
 
@@ -81,10 +85,11 @@ static wdr_status build_path(wdr_ctx *c, const std::vector<Proposal> &props, con
     path.su3 = 1;
     for (const Proposal &q : props) path.su3 = path.su3 && q.U->su3 && q.Up->su3;  // the geodesic stays in SU(3)
     path.has16 = path.su3 && p.sp.inner == WDR_F16;
+    path.hase16 = path.has16 && p.sp.solver == WDR_SOLVER_CGNE && e16_geometry(c->g);
     for (const Proposal &q : props) {
         std::vector<TmpGauge *> pts;
         for (int i = 0; i <= path.N; ++i) {
-            path.pts.emplace_back(new TmpGauge(c, path.has16));
+            path.pts.emplace_back(new TmpGauge(c, path.has16, path.hase16));
             if (!path.pts.back()->ok()) return WDR_ENOMEM;
             pts.push_back(path.pts.back().get());
         }
@@ -107,6 +112,7 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
     const int nout = op == WDR_OP_BLOCKS ? g.nblk : 1;
     const int su3 = path.su3;
     const bool want16 = path.has16;
+    const bool wante16 = path.hase16;
     auto point = [&](int prop, int i) -> TmpGauge & { return path.at(prop, i); };
 
     // chunk size: sample fields plus solver work space per system
@@ -127,13 +133,13 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
         const int M = std::min(Mmax, total - m0);
         const size_t fbm = fb * M;
         Work eta(c, fbm), y(c, fbm), z(c, fbm), w(c, fbm), r(c, fbm), t(c, fbm), pr(c, sizeof(double) * g.nblk * M);
-        Work tabs(c, 6 * M * sizeof(void *)), idx(c, 2 * M * sizeof(int32_t)), kw(c, M * sizeof(double)),
+        Work tabs(c, 8 * M * sizeof(void *)), idx(c, 2 * M * sizeof(int32_t)), kw(c, M * sizeof(double)),
             sw(c, M * sizeof(uint64_t));
         if (!eta.ok() || !y.ok() || !z.ok() || !w.ok() || !r.ok() || !t.ok() || !pr.ok() || !tabs.ok() || !idx.ok() ||
             !kw.ok() || !sw.ok())
             return WDR_ENOMEM;
         // per-system tables: X on U_i, X' on U_{i+1}; noise (step, sample, key); kappa
-        std::vector<const void *> ht(6 * M, nullptr);
+        std::vector<const void *> ht(8 * M, nullptr);
         std::vector<int32_t> hi(2 * M);
         std::vector<double> hk(M);
         std::vector<uint64_t> hs(M);
@@ -146,6 +152,10 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
             if (want16) {
                 ht[4 * M + j] = point(q, i).u16.as<void>();
                 ht[5 * M + j] = point(q, i + 1).u16.as<void>();
+            }
+            if (wante16) {
+                ht[6 * M + j] = point(q, i).e16.as<void>();
+                ht[7 * M + j] = point(q, i + 1).e16.as<void>();
             }
             hi[j] = i;
             hi[M + j] = k;
@@ -160,10 +170,12 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
         const double *kap = kw.as<const double>();
         const GaugeTab X{{reinterpret_cast<UTab<double>>(tb), su3, kap},
                          {reinterpret_cast<UTab<float>>(tb + M), su3, kap},
-                         {want16 ? reinterpret_cast<const h2 *const *>(tb + 4 * M) : nullptr, kap}};
+                         {want16 ? reinterpret_cast<const h2 *const *>(tb + 4 * M) : nullptr, kap},
+                         {wante16 ? reinterpret_cast<const h2 *const *>(tb + 6 * M) : nullptr, kap}};
         const GaugeTab Xp{{reinterpret_cast<UTab<double>>(tb + 2 * M), su3, kap},
                           {reinterpret_cast<UTab<float>>(tb + 3 * M), su3, kap},
-                          {want16 ? reinterpret_cast<const h2 *const *>(tb + 5 * M) : nullptr, kap}};
+                          {want16 ? reinterpret_cast<const h2 *const *>(tb + 5 * M) : nullptr, kap},
+                          {wante16 ? reinterpret_cast<const h2 *const *>(tb + 7 * M) : nullptr, kap}};
         const Sys all = all_sys(c, M);
         double2 *E = eta.as<double2>(), *Y = y.as<double2>(), *Z = z.as<double2>(), *W = w.as<double2>(),
                 *R = r.as<double2>(), *Tm = t.as<double2>();

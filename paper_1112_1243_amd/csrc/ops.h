@@ -23,8 +23,22 @@ struct Sys {
     // size their grids by count (the others launch over all M, still correct)
     const int32_t *list = nullptr;
     int count = 0;
+    // hs = log2(Vh) > 0: the elementwise passes that support it (norms, dots,
+    // the CG updates, add_to64, sub_norm) visit only the even sites of every
+    // block (the first Vh entries of each run of Vb = 2 Vh; the even-odd
+    // solvers keep the odd halves of their vectors at zero)
+    int hs = 0;
     int launch_m() const { return list ? count : M; }
+    long ne() const { return hs ? n >> 1 : n; }  // elements visited per system
 };
+
+// log2(Vh) when the half-block volume is a power of two, else 0
+inline int even_shift(const Geo &g)
+{
+    int s = 0;
+    while ((1 << s) < g.Vh) ++s;
+    return (1 << s) == g.Vh ? s : 0;
+}
 
 template <typename T> using T2 = typename C2<T>::type;
 template <typename T> using UTab = const T2<T> *const *;  // device [M] gauge pointers
@@ -188,6 +202,44 @@ void launch_pack_links_h16(const Geo &g, const double2 *u64, h2 *u16, hipStream_
 // if the geometry or the links do not allow it
 bool launch_mr_h16(int mode, const Geo &g, const Sys &sy, Links16 U, H16c src, H16 dst, float kappa, int nmr,
                    int slot0, int nslots, hipStream_t s);
+
+// ---------------------------------------------------------------- FP16 even-odd CG
+// One parity of every block in FP16, site-major ([M][slot][Vh][12] complex,
+// 48 bytes per site) with one power-of-two scale per (system, slot); the CG
+// vectors of the FP16 inner level of the even-odd CGNE (4^4 blocks).
+struct E16 {
+    uint4 *v;
+    float *s;
+};
+struct E16c {
+    const uint4 *v;
+    const float *s;
+};
+inline E16c cref(const E16 &f) { return E16c{f.v, f.s}; }
+// 4^4 blocks in a 2-colourable checkerboard
+bool e16_geometry(const Geo &g);
+size_t e16_field_bytes(const Geo &g, int M);
+E16 e16_field(const Geo &g, int M, void *p);
+// E16 links (first two rows, [slot][parity][mu] chunks) of internal FP64 links
+void launch_pack_links_e16(const Geo &g, const double2 *u64, h2 *e16, hipStream_t s);
+// out = diag + f H_{par, 1-par} in (gamma_5 on both sides for dag), f = fs
+// kappa_m with a kappa table in U, else fk; partial (may be NULL): |out|^2
+// per (system, slot) for the deterministic reduction (2 doubles each)
+void launch_eo16(const Geo &g, const Sys &sy, Links16 U, float fs, float fk, int par, int dag, E16c in, E16c diag,
+                 E16 out, double *partial, hipStream_t s);
+// x += alpha w (x FP32 internal layout, even sites), r -= alpha q, |r|^2 partials;
+// alpha = sc[8m].x / sc[8m + 1].x
+void launch_xr16(const Geo &g, const Sys &sy, const double2 *sc, float2 *x, E16c w, E16c q, E16 r, double *partial,
+                 hipStream_t s);
+// p = r + sc[8m + 4].x p, or p = r (copy)
+void launch_p16(const Geo &g, const Sys &sy, const double2 *sc, int copy, E16c r, E16 p, hipStream_t s);
+// r = bh - d (FP32 internal layout, even sites) into FP16, |r|^2 partials
+void launch_r16_from32(const Geo &g, const Sys &sy, const float2 *bh, const float2 *d, E16 r, double *partial,
+                       hipStream_t s);
+// r = r64 into FP16, bh = (float) r64, x = 0 (even sites)
+void launch_r16_from64(const Geo &g, const Sys &sy, const double2 *r64, float2 *bh, float2 *x, E16 r, hipStream_t s);
+// out[m * ostride].x = sum of the G partial pairs of system m (fixed order)
+void launch_final(const Sys &sy, const double *partial, int G, double2 *out, int ostride, hipStream_t s);
 
 // ---------------------------------------------------------------- noise, path
 // system m gets the noise of path step steps[m], sample ks[m] (device

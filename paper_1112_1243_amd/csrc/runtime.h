@@ -48,7 +48,8 @@ struct wdr_gauge {
     double2 *u64 = nullptr;  // internal FP64 links, boundary phases folded in
     float2 *u32 = nullptr;   // internal FP32 copy
     wdr::h2 *u16 = nullptr;  // FP16 copy of the first two rows (SU(3) fields only)
-    void **tab = nullptr;    // device table {u64, u32, u16} for single-system launches
+    wdr::h2 *e16 = nullptr;  // the same in the even-odd CG's layout (SU(3) fields, 4^4 blocks)
+    void **tab = nullptr;    // device table {u64, u32, u16, e16} for single-system launches
     int su3 = 0;             // every link is SU(3) to SU3_TOL (checked at upload)
 };
 
@@ -94,12 +95,14 @@ struct GaugeTab {
     Links<double> u64;
     Links<float> u32;
     Links16 u16;  // tab NULL when the fields are not SU(3)
+    Links16 e16;  // E16 links of the FP16 even-odd CG; tab NULL when absent
 };
 inline GaugeTab view(const wdr_gauge *g)
 {
     return {{reinterpret_cast<UTab<double>>(g->tab), g->su3},
             {reinterpret_cast<UTab<float>>(g->tab + 1), g->su3},
-            {g->u16 ? reinterpret_cast<const h2 *const *>(g->tab + 2) : nullptr}};
+            {g->u16 ? reinterpret_cast<const h2 *const *>(g->tab + 2) : nullptr},
+            {g->e16 ? reinterpret_cast<const h2 *const *>(g->tab + 3) : nullptr}};
 }
 
 struct Stats {

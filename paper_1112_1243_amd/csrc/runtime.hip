@@ -90,17 +90,27 @@ wdr_status check_params(const wdr_ctx *c, const wdr_solver_params &sp, bool need
         set_error("inner precision must be F64, F32 or F16");
         return WDR_EINVAL;
     }
+    if (sp.middle != WDR_F64 && sp.middle != WDR_F32) {
+        set_error("middle precision must be F64 or F32");
+        return WDR_EINVAL;
+    }
+    if (sp.middle == WDR_F32 && (sp.solver != WDR_SOLVER_CGNE || sp.inner != WDR_F16)) {
+        set_error("an F32 middle level needs CGNE with F16 inner iterations");
+        return WDR_EINVAL;
+    }
     if (sp.inner == WDR_F16) {
-        // FP16 storage is implemented in the 4^4-block Schwarz / block solver
-        if (sp.solver != WDR_SOLVER_FGCR_SAP && !needs_blocks) {
-            set_error("FP16 inner precision applies to the Schwarz preconditioner and block solves");
-            return WDR_EINVAL;
-        }
+        // FP16 storage is implemented for 4^4 blocks: the Schwarz / block
+        // solver and the even-odd CG (which also needs a 2-colourable
+        // checkerboard of blocks)
         for (int mu = 0; mu < 4; ++mu)
             if (c->g.B[mu] != 4) {
                 set_error("FP16 inner precision needs 4^4 blocks");
                 return WDR_EINVAL;
             }
+        if (sp.solver == WDR_SOLVER_CGNE && !c->g.colourable) {
+            set_error("the FP16 even-odd CG needs L[mu]/B[mu] even in every direction");
+            return WDR_EINVAL;
+        }
     }
     if (sp.solver == WDR_SOLVER_FGCR_SAP || needs_blocks) {
         if (sp.restart < 1 || sp.restart > 16 || sp.sap_cycles < 1 || sp.mr_steps < 1) {
@@ -146,6 +156,7 @@ void wdr_default_solver_params(wdr_solver_params *out)
     out->block_tol = 1e-13;
     out->adj_tol = 1e-7;
     out->inner = WDR_F32;
+    out->middle = WDR_F64;
     out->block_mr_steps = 16;
     out->update_every = 4;
     out->graph = 1;
@@ -203,6 +214,7 @@ wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)
     g.nblk = nblk;
     g.colourable = colourable;
     g.stencil = WDR_STENCIL_AUTO;
+    g.mr_form = WDR_MR_AUTO;
 
     // in-block order: even sites then odd sites, lexicographic within each
     std::vector<uint32_t> loc_coord(Vb);
@@ -359,6 +371,21 @@ wdr_status wdr_ctx_set_stencil(wdr_ctx *c, int32_t choice)
     return WDR_OK;
 }
 
+wdr_status wdr_ctx_set_mr_form(wdr_ctx *c, int32_t choice)
+{
+    if (!c) {
+        set_error("null context");
+        return WDR_EINVAL;
+    }
+    if (choice < WDR_MR_AUTO || choice > WDR_MR_TWO_PER_CU) {
+        set_error("block-MR form must be WDR_MR_AUTO, WDR_MR_ONE_PER_CU or WDR_MR_TWO_PER_CU");
+        return WDR_EINVAL;
+    }
+    c->g.mr_form = choice;
+    if (c->twin) c->twin->g.mr_form = choice;
+    return WDR_OK;
+}
+
 wdr_status wdr_gauge_create(wdr_ctx *c, const double *dev_U, wdr_gauge **out, void *stream)
 {
     if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
@@ -373,7 +400,7 @@ wdr_status wdr_gauge_create(wdr_ctx *c, const double *dev_U, wdr_gauge **out, vo
     g->device = c->device;
     const size_t n = (size_t)c->g.V * 36;
     if (hipMalloc(&g->u64, n * sizeof(double2)) != hipSuccess || hipMalloc(&g->u32, n * sizeof(float2)) != hipSuccess ||
-        hipMalloc(&g->tab, 3 * sizeof(void *)) != hipSuccess) {
+        hipMalloc(&g->tab, 4 * sizeof(void *)) != hipSuccess) {
         set_error("gauge allocation failed");
         return WDR_ENOMEM;
     }
@@ -397,8 +424,15 @@ wdr_status wdr_gauge_create(wdr_ctx *c, const double *dev_U, wdr_gauge **out, vo
             return WDR_ENOMEM;
         }
         launch_pack_links_h16(c->g, g->u64, g->u16, s);
+        if (e16_geometry(c->g)) {
+            if (hipMalloc(&g->e16, (size_t)c->g.V * 24 * sizeof(h2)) != hipSuccess) {
+                set_error("gauge allocation failed");
+                return WDR_ENOMEM;
+            }
+            launch_pack_links_e16(c->g, g->u64, g->e16, s);
+        }
     }
-    void *tab[3] = {g->u64, g->u32, g->u16};
+    void *tab[4] = {g->u64, g->u32, g->u16, g->e16};
     WDR_HIP(hipMemcpyAsync(g->tab, tab, sizeof(tab), hipMemcpyHostToDevice, s));
     WDR_HIP(hipStreamSynchronize(s));
     WDR_HIP(hipGetLastError());
@@ -416,6 +450,7 @@ wdr_status wdr_gauge_destroy(wdr_gauge *g)
     if (g->u64) (void)hipFree(g->u64);
     if (g->u32) (void)hipFree(g->u32);
     if (g->u16) (void)hipFree(g->u16);
+    if (g->e16) (void)hipFree(g->e16);
     if (g->tab) (void)hipFree(g->tab);
     delete g;
     return WDR_OK;

@@ -696,6 +696,14 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) __attribute__((amdgpu_waves_per_eu
 // block solves with at least this many workgroups (blocks x systems) use the
 // four-waves-per-SIMD form: two blocks per CU, at the price of a few spills
 constexpr long MR_OCC4_WORKGROUPS = 2048;
+// the block-MR form of a block-solve launch of `wgs` workgroups (the
+// context's wdr_mr_form choice, or the workgroup threshold)
+inline bool two_per_cu(const Geo &g, long wgs)
+{
+    if (g.mr_form == WDR_MR_TWO_PER_CU) return true;
+    if (g.mr_form == WDR_MR_ONE_PER_CU) return false;
+    return wgs >= MR_OCC4_WORKGROUPS;
+}
 
 template <typename T, int MODE>
 bool launch_mr_cube4(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *src, T2<T> *dst, T kappa, int nmr,
@@ -708,7 +716,7 @@ bool launch_mr_cube4(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *src, 
     if constexpr (sizeof(T) == 4) {  // the FP64 partial sums would not fit in LDS next to the links
         const auto *tab = reinterpret_cast<const void *const *>(U.tab);
         if constexpr (MODE == 1) {
-            if ((long)nslots * sy.M >= MR_OCC4_WORKGROUPS) {
+            if (two_per_cu(g, (long)nslots * sy.M)) {
                 k_block_mr_dir<T, MODE, 4, 0, 4><<<dim3(nslots, sy.M), 4 * Cube<4>::Vh, 0, s>>>(
                     g, sy.active, tab, U.kap, sy.n, g.sched[si], src, nullptr, dst, nullptr, kappa, nmr);
                 return true;
@@ -754,7 +762,7 @@ bool launch_mr_h16(int mode, const Geo &g, const Sys &sy, Links16 U, H16c src, H
     if (mode == 0)
         k_block_mr_dir<float, 0, 4, 1><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
                                                                        src.v, src.s, dst.v, dst.s, kappa, nmr);
-    else if ((long)nslots * sy.M >= MR_OCC4_WORKGROUPS)
+    else if (two_per_cu(g, (long)nslots * sy.M))
         k_block_mr_dir<float, 1, 4, 1, 4><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
                                                                        src.v, src.s, dst.v, dst.s, kappa, nmr);
     else

@@ -27,13 +27,13 @@ namespace {
 // [4] beta, [5] true residual (alpha = rr / ww is formed where it is used)
 // p = r + beta p
 template <typename T>
-__global__ __launch_bounds__(256) void k_cg_p(const int32_t *active, const int32_t *list, long n, long total,
+__global__ __launch_bounds__(256) void k_cg_p(const int32_t *active, const int32_t *list, long n, int hs, long total,
                                               const double2 *sc, const T2<T> *r, T2<T> *p)
 {
     const long k = (long)blockIdx.x * 256 + threadIdx.x;
     if (k >= total) return;
     int m;
-    const long i = batch_index(list, n, k, m);
+    const long i = batch_elem(list, n, hs, k, m);
     if (active && !active[m]) return;
     const T b = (T)sc[8L * m + 4].x;
     const T2<T> ri = r[i], pi = p[i];
@@ -86,13 +86,13 @@ __global__ void k_cgm_update(int M, double2 *sc, const double *bn2, double tol2,
 }
 // r = (FP32) r64 and e = 0 for the updated systems; clears their flag
 template <typename T>
-__global__ __launch_bounds__(256) void k_cgm_refresh(const int32_t *list, long n, long total, int32_t *upd,
+__global__ __launch_bounds__(256) void k_cgm_refresh(const int32_t *list, long n, int hs, long total, int32_t *upd,
                                                      const double2 *r64, T2<T> *r, T2<T> *e)
 {
     const long k = (long)blockIdx.x * 256 + threadIdx.x;
     if (k >= total) return;
     int m;
-    const long i = batch_index(list, n, k, m);
+    const long i = batch_elem(list, n, hs, k, m);
     if (!upd[m]) return;
     const double2 v = r64[i];
     r[i].x = (T)v.x;
@@ -245,32 +245,53 @@ __global__ void k_fgcr_outer(int M, const double2 *nr, const double *bn2, double
 // ---- block-solve control on the device (one thread per system): the worst
 // relative residual over the selected blocks decides convergence
 
-__global__ void k_block_init(int M, int nblk, int slot0, int ns, const double *bn, int32_t *alive, int32_t *its,
-                             double *worst)
+// per-system control of a block solve, one workgroup of BC_NT threads per
+// system: the largest per-block ratio |r_b|^2 / |b_b|^2 over the slots in
+// range (blocks with b_b = 0 are left out)
+constexpr int BC_NT = 256;
+__device__ double worst_ratio(int m, int nblk, int slot0, int ns, const double *bn, const double *rn)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    bool any = false;
-    for (int i = slot0; i < slot0 + ns; ++i) any = any || bn[(size_t)m * nblk + i] > 0;
-    alive[m] = any;
-    its[m] = 0;
-    worst[m] = 0;
+    __shared__ double sh[BC_NT];
+    double wv = 0;
+    for (int i = slot0 + threadIdx.x; i < slot0 + ns; i += BC_NT) {
+        const size_t k = (size_t)m * nblk + i;
+        const double b = bn[k];
+        if (b > 0) wv = fmax(wv, rn ? rn[k] / b : 1.0);
+    }
+    sh[threadIdx.x] = wv;
+    __syncthreads();
+    for (int off = BC_NT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    return sh[0];
 }
 
-__global__ void k_block_check(int M, int nblk, int slot0, int ns, const double *bn, const double *rn, double tol2,
-                              int32_t *alive, int32_t *its, double *worst)
+// alive = some block has a nonzero right-hand side
+__global__ __launch_bounds__(BC_NT) void k_block_init(int nblk, int slot0, int ns, const double *bn, int32_t *alive,
+                                                      int32_t *its, double *worst)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M || !alive[m]) return;
-    ++its[m];
-    double wv = 0;
-    for (int i = slot0; i < slot0 + ns; ++i) {
-        const size_t k = (size_t)m * nblk + i;
-        if (bn[k] > 0) wv = fmax(wv, rn[k] / bn[k]);
+    const int m = blockIdx.x;
+    const double any = worst_ratio(m, nblk, slot0, ns, bn, nullptr);
+    if (threadIdx.x == 0) {
+        alive[m] = any > 0;
+        its[m] = 0;
+        worst[m] = 0;
     }
-    if (!isfinite(wv)) wv = INFINITY;
-    worst[m] = wv;
-    if (!(wv > tol2)) alive[m] = 0;
+}
+
+__global__ __launch_bounds__(BC_NT) void k_block_check(int nblk, int slot0, int ns, const double *bn, const double *rn,
+                                                       double tol2, int32_t *alive, int32_t *its, double *worst)
+{
+    const int m = blockIdx.x;
+    if (!alive[m]) return;
+    double wv = worst_ratio(m, nblk, slot0, ns, bn, rn);
+    if (threadIdx.x == 0) {
+        ++its[m];
+        if (!isfinite(wv)) wv = INFINITY;
+        worst[m] = wv;
+        if (!(wv > tol2)) alive[m] = 0;
+    }
 }
 
 }  // namespace
@@ -585,7 +606,10 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     U64n.kneg = 1;
     const T kT = (T)kappa;
     const Sys all = all_sys(c, M);
+    // the iterated vectors live on even sites: their updates and norms skip
+    // the odd halves (zero) where the half-block volume allows it
     Sys sa{M, alive, n}, su{M, upd, n};
+    sa.hs = su.hs = even_shift(g);
     std::vector<int32_t> live;
     int launch_m = M;
     const unsigned nbm = nb64(M);
@@ -607,7 +631,7 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     // one period: ue steps, then the reliable update of the flagged systems
     const int ue = sp.update_every;
     auto period = [&](hipStream_t q) {
-        const long tl = n * sa.launch_m();
+        const long tl = sa.ne() * sa.launch_m();
         for (int i = 0; i < ue; ++i) {
             // w = Dhat^+ p, q = Dhat w, e += alpha w, r -= alpha q, p = r + beta p
             apply_dhat<T>(g, sa, UT, kT, 1, p, t, w, q);
@@ -616,14 +640,14 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
             launch_cg_xr_norm<T>(sa, sc, 8, e, w, r, qv, red.as<double>(), sc + 3, 8, q);
             k_cgm_beta<<<nbm, 64, 0, q>>>(M, sc, RELIABLE_DELTA * RELIABLE_DELTA, sp.max_iter, alive, rmax, upd,
                                           its);
-            k_cg_p<T><<<nb256(tl), 256, 0, q>>>(alive, sa.list, n, tl, sc, r, p);
+            k_cg_p<T><<<nb256(tl), 256, 0, q>>>(alive, sa.list, n, sa.hs, tl, sc, r, p);
         }
         // x_e += e, r = bh - Dhat x_e in FP64
         launch_add_to64<T>(su, e, x, q);
         apply_dhat<double>(g, su, U.u64, kappa, 0, x, o64, t64, q);
         launch_sub_norm(su, bh, t64, r64, red.as<double>(), sc + 5, 8, q);
         k_cgm_update<<<nbm, 64, 0, q>>>(M, sc, bn2, tol * tol, sp.max_iter, its, alive, upd, rmax);
-        k_cgm_refresh<T><<<nb256(tl), 256, 0, q>>>(su.list, n, tl, upd, r64, r, e);
+        k_cgm_refresh<T><<<nb256(tl), 256, 0, q>>>(su.list, n, su.hs, tl, upd, r64, r, e);
         k_cgm_clear<<<nbm, 64, 0, q>>>(M, upd);
     };
     // With sp.graph the period's launches (kernels only) are captured once on
@@ -690,12 +714,224 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     return WDR_OK;
 }
 
+// ---- FP16 even-odd CGNE control (one thread per system); sc[8 m + k]:
+// 0 iterated rr, 1 |w|^2, 3 new rr, 4 beta, 5 FP64 true residual^2,
+// 6 FP32 (middle) true residual^2
+// after the middle level's residual: restart the iterated residual from it;
+// ask for the outer update when it fell by OUTER_DELTA below the middle
+// system's right-hand side, reached the tolerance, or at the iteration limit
+__global__ void k_c16_mid(int M, double2 *sc, const double *bn2, const double *b32n2, double tol2, double delta2,
+                          int max_iter, const int32_t *its, int32_t *upd, int32_t *upd64, double *rmax)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M || !upd[m]) return;
+    const double r = sc[8L * m + 6].x;
+    sc[8L * m] = make_double2(r, 0.0);
+    rmax[m] = r;
+    if (!(r > delta2 * b32n2[m]) || !(r > tol2 * bn2[m]) || its[m] >= max_iter) upd64[m] = 1;
+    upd[m] = 0;
+}
+// two levels: every reliable update goes to the FP64 level
+__global__ void k_c16_promote(int M, int32_t *upd, int32_t *upd64)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M || !upd[m]) return;
+    upd64[m] = 1;
+    upd[m] = 0;
+}
+// after the FP64 true residual: retire converged systems, else restart the
+// middle system (right-hand side = that residual) and the iterated residual
+__global__ void k_c16_outer(int M, double2 *sc, const double *bn2, double *b32n2, double tol2, int max_iter,
+                            const int32_t *its, int32_t *alive, int32_t *upd64, double *rmax)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M || !upd64[m]) return;
+    const double r = sc[8L * m + 5].x;
+    if (!isfinite(r) || r <= tol2 * bn2[m] || its[m] >= max_iter) alive[m] = 0;
+    sc[8L * m] = make_double2(r, 0.0);
+    rmax[m] = r;
+    b32n2[m] = r;
+}
+__global__ void k_c16_clear(int M, int32_t *upd64)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < M) upd64[m] = 0;
+}
+
+// the middle level hands a system to the FP64 level once its residual fell
+// by this factor (FP32 arithmetic resolves the middle system several orders
+// further, so the FP64 updates stay rare)
+constexpr double OUTER_DELTA = 1e-4;
+
+// Even-odd CG on the normal equations with FP16 storage (4^4 blocks, SU(3)
+// links), the system and FP64 residual of cgne_eo.  Inner level: CG steps
+// on FP16 vectors (E16 layout, per-block scales) with the FP16 stencil and
+// FP32 arithmetic; the solution increment accumulates in FP32.  Three
+// levels (middle = F32): when the iterated residual has fallen by
+// RELIABLE_DELTA, it is replaced by the FP32 true residual of the middle
+// system Dhat x32 = bh32; when that has fallen by OUTER_DELTA (or reached the
+// tolerance), x32 is folded into the FP64 solution, the FP64 true residual
+// becomes the middle system's new right-hand side and x32 restarts at zero.
+// Two levels (middle = F64): every reliable update is the FP64 one.  The
+// search direction is kept across updates (Sleijpen and van der Vorst).
+static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
+                            double tol, const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
+{
+    const auto &g = c->g;
+    if (!U.e16.tab || !e16_geometry(g)) {
+        set_error("the FP16 even-odd CG needs SU(3) links and 4^4 blocks in a 2-colourable checkerboard");
+        return WDR_EINVAL;
+    }
+    const bool three = sp.middle == WDR_F32;
+    const long n = field_n(c), total = n * M;
+    const size_t fb = field_bytes(c, WDR_F64) * M, f32 = field_bytes(c, WDR_F32) * M, fe = e16_field_bytes(g, M);
+    Work bhw(c, fb), r64w(c, fb), t64w(c, fb), o64w(c, fb), x32w(c, f32), b32w(c, f32), d32w(c, f32), t32w(c, f32),
+        pw(c, fe), ww(c, fe), qw(c, fe), rw(c, fe), tw(c, fe), scal(c, sizeof(double2) * 8 * M),
+        red(c, sizeof(double) * std::max<long>(red_scratch(M), 2L * g.nblk * M)),
+        ctl(c, 3 * sizeof(double) * M + 4 * sizeof(int32_t) * M), lw(c, sizeof(int32_t) * M);
+    FlagPoll poll(c, M);
+    if (!bhw.ok() || !r64w.ok() || !t64w.ok() || !o64w.ok() || !x32w.ok() || !b32w.ok() || !d32w.ok() || !t32w.ok() ||
+        !pw.ok() || !ww.ok() || !qw.ok() || !rw.ok() || !tw.ok() || !scal.ok() || !red.ok() || !ctl.ok() ||
+        !lw.ok() || !poll.ok)
+        return WDR_ENOMEM;
+    double2 *bh = bhw.as<double2>(), *r64 = r64w.as<double2>(), *t64 = t64w.as<double2>(), *o64 = o64w.as<double2>();
+    float2 *x32 = x32w.as<float2>(), *b32 = b32w.as<float2>(), *d32 = d32w.as<float2>(), *t32 = t32w.as<float2>();
+    const E16 P = e16_field(g, M, pw.as<void>()), W = e16_field(g, M, ww.as<void>()),
+              Q = e16_field(g, M, qw.as<void>()), R = e16_field(g, M, rw.as<void>()),
+              T = e16_field(g, M, tw.as<void>());
+    double2 *sc = scal.as<double2>();
+    double *part = red.as<double>();
+    double *bn2 = ctl.as<double>(), *rmax = bn2 + M, *b32n2 = rmax + M;
+    int32_t *alive = reinterpret_cast<int32_t *>(b32n2 + M), *upd = alive + M, *upd64 = upd + M, *its = upd64 + M;
+    const Links<double> U64 = U.u64;
+    Links<double> U64n = U.u64;
+    U64n.kneg = 1;
+    const Links<float> U32 = U.u32;
+    const Links16 U16 = U.e16;
+    const float kf = (float)kappa;
+    const Sys all = all_sys(c, M);
+    Sys sa{M, alive, n}, su{M, upd, n}, s64{M, upd64, n};
+    sa.hs = su.hs = s64.hs = even_shift(g);
+    std::vector<int32_t> live;
+    int launch_m = M;
+    const unsigned nbm = nb64(M);
+    const int G = g.nblk;
+
+    // bh = [b_e + k H_eo b_o; 0]; x = 0; r64 = bh; every system starts an outer update
+    launch_zero<double>(x, total, s);
+    launch_zero<double>(bh, total, s);
+    launch_zero<double>(t64, total, s);
+    launch_dslash<double>(g, all, U64n, HOPS_ALL, 0, 0, b, b, bh, -kappa, 0, g.nblk, s);
+    launch_norm2<double>(all, b, red.as<double>(), sc + 5, 8, s);
+    k_cgm_init<<<nbm, 64, 0, s>>>(M, sc, bn2, rmax, alive, upd, its);  // |b|^2 of the full system
+    launch_zero<float>(x32, total, s);
+    launch_norm2<double>(sa, bh, red.as<double>(), sc, 8, s);          // |bh|^2 (even sites)
+    launch_r16_from64(g, all, bh, b32, x32, R, s);
+    launch_p16(g, all, sc, 1, cref(R), P, s);
+    k_cgm_rmax<<<nbm, 64, 0, s>>>(M, sc, rmax);
+    k_cgm_rmax<<<nbm, 64, 0, s>>>(M, sc, b32n2);
+    k_c16_clear<<<nbm, 64, 0, s>>>(M, upd64);
+    const E16c none{nullptr, nullptr};
+    const int ue = sp.update_every;
+    auto period = [&](hipStream_t q) {
+        for (int i = 0; i < ue; ++i) {
+            // w = Dhat^+ p (with |w|^2), q = Dhat w, x += alpha w, r -= alpha q, p = r + beta p
+            launch_eo16(g, sa, U16, -1.f, -kf, 1, 1, cref(P), none, T, nullptr, q);
+            launch_eo16(g, sa, U16, 1.f, kf, 0, 1, cref(T), cref(P), W, part, q);
+            launch_final(sa, part, G, sc + 1, 8, q);
+            launch_eo16(g, sa, U16, -1.f, -kf, 1, 0, cref(W), none, T, nullptr, q);
+            launch_eo16(g, sa, U16, 1.f, kf, 0, 0, cref(T), cref(W), Q, nullptr, q);
+            launch_xr16(g, sa, sc, x32, cref(W), cref(Q), R, part, q);
+            launch_final(sa, part, G, sc + 3, 8, q);
+            k_cgm_beta<<<nbm, 64, 0, q>>>(M, sc, RELIABLE_DELTA * RELIABLE_DELTA, sp.max_iter, alive, rmax, upd,
+                                          its);
+            launch_p16(g, sa, sc, 0, cref(R), P, q);
+        }
+        if (three) {
+            // middle: r = bh32 - Dhat x32 in FP32 for the flagged systems
+            apply_dhat<float>(g, su, U32, kf, 0, x32, t32, d32, q);
+            launch_r16_from32(g, su, b32, d32, R, part, q);
+            launch_final(su, part, G, sc + 6, 8, q);
+            k_c16_mid<<<nbm, 64, 0, q>>>(M, sc, bn2, b32n2, tol * tol, OUTER_DELTA * OUTER_DELTA, sp.max_iter, its,
+                                         upd, upd64, rmax);
+        } else {
+            k_c16_promote<<<nbm, 64, 0, q>>>(M, upd, upd64);
+        }
+        // outer: x += x32, r64 = bh - Dhat x in FP64; the middle system restarts from r64
+        launch_add_to64<float>(s64, x32, x, q);
+        apply_dhat<double>(g, s64, U64, kappa, 0, x, o64, t64, q);
+        launch_sub_norm(s64, bh, t64, r64, red.as<double>(), sc + 5, 8, q);
+        k_c16_outer<<<nbm, 64, 0, q>>>(M, sc, bn2, b32n2, tol * tol, sp.max_iter, its, alive, upd64, rmax);
+        launch_r16_from64(g, s64, r64, b32, x32, R, q);
+        k_c16_clear<<<nbm, 64, 0, q>>>(M, upd64);
+    };
+    PeriodGraph pg(s);
+    for (int pt = 0;; ++pt) {
+        if (sp.graph) {
+            if (!pg.exec) {
+                const wdr_status cs = pg.capture(c, period);
+                if (cs != WDR_OK) return cs;
+            }
+            WDR_HIP(hipGraphLaunch(pg.exec, s));
+        } else {
+            period(s);
+        }
+        poll.post(alive, pt & 1, s);
+        if (pt > 0) {
+            if (poll.none((pt - 1) & 1)) break;
+            const int32_t *fl = poll.slot((pt - 1) & 1);
+            int cnt = 0;
+            for (int m = 0; m < M; ++m) cnt += fl[m] != 0;
+            if (2 * cnt <= launch_m) {
+                live.clear();
+                for (int m = 0; m < M; ++m)
+                    if (fl[m]) live.push_back(m);
+                WDR_HIP(hipMemcpyAsync(lw.as<void>(), live.data(), live.size() * sizeof(int32_t),
+                                       hipMemcpyHostToDevice, s));
+                launch_m = cnt;
+                sa.list = su.list = s64.list = lw.as<int32_t>();
+                sa.count = su.count = s64.count = cnt;
+                pg.reset();
+            }
+        }
+    }
+    // x_o = b_o + k H_oe x_e
+    launch_zero<double>(t64, total, s);
+    launch_dslash<double>(g, all, U64n, HOPS_ALL, 1, 0, x, b, t64, -kappa, 0, g.nblk, s);
+    launch_add_to64<double>(all, t64, x, s);
+
+    std::vector<double> hbn2(M), rn2;
+    std::vector<int32_t> hits(M);
+    WDR_HIP(hipMemcpyAsync(hbn2.data(), bn2, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+    WDR_HIP(hipMemcpyAsync(hits.data(), its, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+    read_x(sc + 5, M, 8, rn2, s);
+    st.assign(M, Stats());
+    bool ok = true;
+    for (int m = 0; m < M; ++m) {
+        st[m].iters = hits[m];
+        st[m].total = hits[m];
+        st[m].rel = hbn2[m] > 0 ? std::sqrt(rn2[m] / hbn2[m]) : 0.0;
+        st[m].converged = st[m].rel <= tol;
+        ok = ok && st[m].converged;
+    }
+    WDR_HIP(hipGetLastError());
+    if (!ok) {
+        const Stats sm = summarize(st);
+        set_error("CGNE (FP16 inner) stopped at " + std::to_string(sm.iters) + " iterations, relative residual " +
+                  std::to_string(sm.rel));
+        return WDR_ENOCONV;
+    }
+    return WDR_OK;
+}
+
 wdr_status solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp, double tol,
                    const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
-    if (sp.solver == WDR_SOLVER_CGNE)
+    if (sp.solver == WDR_SOLVER_CGNE) {
+        if (sp.inner == WDR_F16) return cgne_eo16(c, M, U, kappa, sp, tol, b, x, st, s);
         return sp.inner == WDR_F64 ? cgne_eo<double>(c, M, U, kappa, sp, tol, b, x, st, s)
                                    : cgne_eo<float>(c, M, U, kappa, sp, tol, b, x, st, s);
+    }
     return fgcr(c, M, U, kappa, sp, tol, b, x, st, s);
 }
 
@@ -717,7 +953,6 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
     double2 *r = rw.as<double2>(), *t = tw.as<double2>();
     double *worst = ctl.as<double>();
     int32_t *alive = reinterpret_cast<int32_t *>(worst + M), *its = alive + M;
-    const unsigned nbm = (unsigned)((M + 63) / 64);
     const Sys all = all_sys(c, M);
     launch_zero<double>(x, n * M, s);
     launch_convert<double, double>(all, b, r, s);
@@ -727,7 +962,7 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
     if (sp.inner == WDR_F64) launch_zero<double>(d64.as<double2>(), n * M, s);
     double *bn = nrm.as<double>(), *rn = bn + (size_t)g.nblk * M;
     launch_slot_norm2(g, all, r, bn, slot0, ns, s);
-    k_block_init<<<nbm, 64, 0, s>>>(M, g.nblk, slot0, ns, bn, alive, its, worst);
+    k_block_init<<<M, BC_NT, 0, s>>>(g.nblk, slot0, ns, bn, alive, its, worst);
     const int nmr = sp.block_mr_steps;
     const Sys sa{M, alive, n};
     std::unique_ptr<H16Work> r16, d16;
@@ -758,7 +993,7 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
         const bool fused = launch_block_residual(g, sa, U.u64, x, b, r, kappa, slot0, ns, s);
         if (!fused) launch_dslash<double>(g, sa, U.u64, HOPS_IN, -1, 0, x, x, t, kappa, slot0, ns, s);
         launch_block_resid_norm(g, sa, b, fused ? nullptr : t, r, rn, slot0, ns, s);
-        k_block_check<<<nbm, 64, 0, s>>>(M, g.nblk, slot0, ns, bn, rn, tol * tol, alive, its, worst);
+        k_block_check<<<M, BC_NT, 0, s>>>(g.nblk, slot0, ns, bn, rn, tol * tol, alive, its, worst);
         poll.post(alive, round & 1, s);
         // round is queued; stop once round - 1 left no system alive
         if (round > 0 && poll.none((round - 1) & 1)) break;

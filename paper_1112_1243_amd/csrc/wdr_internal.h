@@ -49,6 +49,7 @@ struct Geo {
     // of blocks are dealt to the same XCD (workgroup i runs on XCD i % 8)
     const int32_t *sched[3];
     int stencil;  // wdr_stencil choice for D and D_b on 4^4 blocks
+    int mr_form;  // wdr_mr_form choice for the FP32 / FP16 block MR of block solves
 };
 
 // which schedule covers the slot range [slot0, slot0 + n), or -1
@@ -79,6 +80,21 @@ __device__ __forceinline__ long batch_index(const int32_t *list, long n, long k,
     const int j = (int)(k / n);
     m = sys_at(list, j);
     return k + (long)(m - j) * n;
+}
+
+// field element visited by index i of an elementwise pass: every element
+// (hs = 0), or with hs = log2(Vh) the even-site half of every (slot,
+// component) run of Vb = 2 Vh entries
+__device__ __forceinline__ long emap(long i, int hs) { return hs ? i + ((i >> hs) << hs) : i; }
+// element of the whole batch for launch element k of an elementwise launch
+// that visits ne = n or n / 2 (hs > 0) elements per system (a compacted
+// launch covers the systems of list back to back); m receives the system
+__device__ __forceinline__ long batch_elem(const int32_t *list, long n, int hs, long k, int &m)
+{
+    const long ne = hs ? n >> 1 : n;
+    const int j = (int)(k / ne);
+    m = sys_at(list, j);
+    return (long)m * n + emap(k - (long)j * ne, hs);
 }
 
 template <typename T> struct Field {  // one spinor field in the internal layout

@@ -81,6 +81,12 @@ def spinor(L, seed: int, tag: int = 7) -> np.ndarray:
     return (r.standard_normal((V, 4, 3)) + 1j * r.standard_normal((V, 4, 3))) / np.sqrt(2)
 
 
+# Solver settings (fields of wdr_solver_params, by name) of the mixed-precision
+# form of the large-lattice workloads: CG on the normal equations (their kappa
+# lies above the free-field critical value, where the Schwarz-preconditioned
+# GCR stalls) with FP16 inner precision under FP64 reliable updates.
+LARGE_MIXED = dict(solver=1, inner=2, middle=0, max_iter=20000)
+
 # Workloads: lattice, blocks, kappa, link scale, noise and solver settings of
 # the standard cases.  "seed" keys the Philox streams above.
 WORKLOADS = {
@@ -89,9 +95,11 @@ WORKLOADS = {
     "wilson8_dd16": dict(L=(8, 8, 8, 8), B=(4, 4, 4, 4), kappa=0.135, scale=0.5, op="schur", noise="gauss",
                          n_noise=8, proposal="active", seed=1112124301),
     "wilson16_dd256": dict(L=(16, 16, 16, 16), B=(4, 4, 4, 4), kappa=0.150, scale=0.25, op="schur",
-                           noise="gauss", n_noise=16, proposal="black_blocks", seed=1112124302),
+                           noise="gauss", n_noise=16, proposal="black_blocks", seed=1112124302,
+                           mixed=LARGE_MIXED),
     "wilson32_dd4096": dict(L=(32, 32, 32, 32), B=(4, 4, 4, 4), kappa=0.155, scale=0.2, op="schur",
-                            noise="gauss", n_noise=32, proposal="active", seed=1112124303),
+                            noise="gauss", n_noise=32, proposal="active", seed=1112124303,
+                            mixed=LARGE_MIXED),
     # recursive DD in the block geometry of the paper's realistic run: 8^4
     # blocks with 4^4 sub-blocks, links of a 6^4 core redrawn in every block
     "recursive16_dd8": dict(L=(16, 16, 16, 16), B=(8, 8, 8, 8), Bsub=(4, 4, 4, 4), kappa=0.150, scale=0.25,

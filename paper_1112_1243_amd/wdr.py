@@ -21,6 +21,7 @@ LIB_PATH = os.environ.get("WDR_LIB", os.path.join(_HERE, "libwdr.so"))
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
 F64, F32, F16 = 0, 1, 2
 STENCIL_AUTO, STENCIL_DIR, STENCIL_BLK = 0, 1, 2
+MR_AUTO, MR_ONE_PER_CU, MR_TWO_PER_CU = 0, 1, 2
 NOISE_Z2, NOISE_GAUSS = 0, 1
 OP_FULL, OP_SCHUR, OP_BLOCKS, OP_DD = 0, 1, 2, 3
 SOLVER_FGCR_SAP, SOLVER_CGNE = 0, 1
@@ -34,7 +35,8 @@ class SolverParams(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int), ("restart", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("sap_cycles", ctypes.c_int32), ("mr_steps", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("block_tol", ctypes.c_double), ("adj_tol", ctypes.c_double), ("inner", ctypes.c_int),
-                ("block_mr_steps", ctypes.c_int32), ("update_every", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("middle", ctypes.c_int), ("block_mr_steps", ctypes.c_int32), ("update_every", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -94,6 +96,7 @@ def lib():
         L.wdr_ctx_nblocks.argtypes = [P]
         L.wdr_ctx_nblocks.restype = ctypes.c_int32
         L.wdr_ctx_set_stencil.argtypes = [P, i32]
+        L.wdr_ctx_set_mr_form.argtypes = [P, i32]
         L.wdr_site_maps.argtypes = [P, P, P, P, P, P]
         L.wdr_active_links.argtypes = [P, i32, i32, P, P]
         L.wdr_gauge_create.argtypes = [P, P, ctypes.POINTER(P), P]
@@ -208,6 +211,11 @@ class Context:
     def set_stencil(self, choice: int):
         """Stencil kernel for D and D_b (STENCIL_AUTO, STENCIL_DIR, STENCIL_BLK)."""
         _check(lib().wdr_ctx_set_stencil(self.handle, int(choice)))
+
+    def set_mr_form(self, choice: int):
+        """Launch form of the FP32 / FP16 block MR of block solves (MR_AUTO,
+        MR_ONE_PER_CU, MR_TWO_PER_CU)."""
+        _check(lib().wdr_ctx_set_mr_form(self.handle, int(choice)))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -47,8 +47,9 @@ int main(void) {
          sizeof(wdr_solve_info), sizeof(wdr_est_params), offsetof(wdr_solver_params, tol),
          offsetof(wdr_est_params, sp), offsetof(wdr_solver_params, inner), offsetof(wdr_est_params, max_batch),
          sizeof(wdr_proposal), offsetof(wdr_proposal, kappa), offsetof(wdr_proposal, seed));
-  printf("%zu %zu %zu %zu %zu\n", offsetof(wdr_solver_params, block_mr_steps), offsetof(wdr_solver_params, graph),
-         sizeof(wdr_solver_params), offsetof(wdr_filter_info, log_ratio), sizeof(wdr_filter_info));
+  printf("%zu %zu %zu %zu %zu %zu\n", offsetof(wdr_solver_params, block_mr_steps), offsetof(wdr_solver_params, graph),
+         sizeof(wdr_solver_params), offsetof(wdr_filter_info, log_ratio), sizeof(wdr_filter_info),
+         offsetof(wdr_solver_params, middle));
   return 0;
 }'''
     import tempfile
@@ -63,7 +64,7 @@ int main(void) {
             wdr.SolverParams.inner.offset, wdr.EstParams.max_batch.offset, ctypes.sizeof(wdr.Proposal),
             wdr.Proposal.kappa.offset, wdr.Proposal.seed.offset, wdr.SolverParams.block_mr_steps.offset,
             wdr.SolverParams.graph.offset, ctypes.sizeof(wdr.SolverParams), wdr.FilterInfo.log_ratio.offset,
-            ctypes.sizeof(wdr.FilterInfo)]
+            ctypes.sizeof(wdr.FilterInfo), wdr.SolverParams.middle.offset]
     assert vals == want
 
 
@@ -72,6 +73,7 @@ def test_default_params_from_library():
     p = wdr.default_params()
     assert p.restart == 16 and p.sap_cycles == 4 and p.mr_steps == 5 and p.tol == 1e-10
     assert p.block_mr_steps == 16 and p.update_every == 4 and p.graph == 1
+    assert p.inner == wdr.F32 and p.middle == wdr.F64
 
 
 def test_missing_library_raises(monkeypatch):

@@ -20,16 +20,22 @@ def _proposal(wdr, ctx, lat, scale, seed, kappa, noise_seed):
 
 
 def test_batch_of_uneven_lattices_matches_oracle():
-    """Two 4^4 proposals and one 8^4 proposal (FULL ratio, Z2 noise, CGNE)
-    in one call: every sample within 1e-8 of the oracle and equal to the
-    single-proposal call."""
+    """Two 4^4 proposals, one 8^4 and one 12^4 proposal (FULL ratio, Z2
+    noise, CGNE with FP32 iterations) in one call: every sample within 1e-8
+    of the oracle and equal to the single-proposal call.  The 12^4 lattice is
+    the middle size of the batched workload: 81 blocks of 4^4, three per
+    direction (no 2-colouring; the full operator needs none), a block count
+    that is not a multiple of the 8 XCDs."""
     torch_cuda()
     from paper_1112_1243_amd import wdr
-    L4, L8 = (4, 4, 4, 4), (8, 8, 8, 8)
-    c4, c8 = wdr.Context(L4, (2, 2, 2, 2)), wdr.Context(L8, (4, 4, 4, 4))
+    L4, L8, L12 = (4, 4, 4, 4), (8, 8, 8, 8), (12, 12, 12, 12)
+    c4, c8, c12 = wdr.Context(L4, (2, 2, 2, 2)), wdr.Context(L8, (4, 4, 4, 4)), wdr.Context(L12, (4, 4, 4, 4))
     l4, l8 = oracle.Lattice(L4, (2, 2, 2, 2)), oracle.Lattice(L8, (4, 4, 4, 4))
+    l12 = oracle.Lattice(L12, (4, 4, 4, 4))
+    assert c12.nblocks == 81
     props = [_proposal(wdr, c4, l4, 0.3, 401, 0.12, 1112124400),
              _proposal(wdr, c8, l8, 0.3, 403, 0.13, 1112124401),
+             _proposal(wdr, c12, l12, 0.3, 407, 0.125, 1112124403),
              _proposal(wdr, c4, l4, 0.3, 405, 0.14, 1112124402)]
     N, K = 2, 1
     p = wdr.default_params(solver=wdr.SOLVER_CGNE)
@@ -49,6 +55,7 @@ def test_batch_of_uneven_lattices_matches_oracle():
         del q["gU"], q["gUp"]
     c4.close()
     c8.close()
+    c12.close()
 
 
 @pytest.mark.parametrize("op", [oracle.OP_SCHUR, oracle.OP_BLOCKS])

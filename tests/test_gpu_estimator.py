@@ -20,16 +20,22 @@ def _setup(L, B, scale, seed, bc=(1, 1, 1, 1)):
     return wdr, lat, ctx, U
 
 
-@pytest.mark.parametrize("solver,kappa,scale,inner", [(0, 0.135, 0.5, 1), (1, 0.135, 0.5, 1), (1, 0.150, 0.25, 1),
-                                                      (1, 0.150, 0.25, 0), (0, 0.135, 0.5, 0), (0, 0.135, 0.5, 2)])
-def test_solve_true_residual(solver, kappa, scale, inner):
+@pytest.mark.parametrize("solver,kappa,scale,inner,middle,bc", [
+    (0, 0.135, 0.5, 1, 0, (1, 1, 1, 1)), (1, 0.135, 0.5, 1, 0, (1, 1, 1, 1)), (1, 0.150, 0.25, 1, 0, (1, 1, 1, 1)),
+    (1, 0.150, 0.25, 0, 0, (1, 1, 1, 1)), (0, 0.135, 0.5, 0, 0, (1, 1, 1, 1)), (0, 0.135, 0.5, 2, 0, (1, 1, 1, 1)),
+    # FP16 even-odd CG: two levels and three levels, periodic and antiperiodic time
+    (1, 0.150, 0.25, 2, 0, (1, 1, 1, 1)), (1, 0.150, 0.25, 2, 1, (1, 1, 1, 1)),
+    (1, 0.155, 0.2, 2, 1, (1, 1, 1, -1)), (1, 0.135, 0.5, 2, 1, (1, -1, 1, -1)),
+])
+def test_solve_true_residual(solver, kappa, scale, inner, middle, bc):
     """The oracle's own stencil checks the GPU solution: ||b - D x|| <= 1e-10 ||b||
-    (CGNE with inner FP32 is the mixed-precision form: FP32 CG cycles inside
-    FP64 defect correction)."""
-    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), scale, 201)
+    (CGNE with inner FP32: FP32 CG steps under FP64 reliable updates; inner
+    FP16: FP16 CG steps, with an FP32 middle level when middle = F32)."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), scale, 201, bc)
     b = synth.spinor(lat.L, 202)
     gU = ctx.gauge(dev(U))
-    x, info = ctx.solve(gU, kappa, dev(b), wdr.default_params(solver=solver, inner=inner))
+    x, info = ctx.solve(gU, kappa, dev(b), wdr.default_params(solver=solver, inner=inner, middle=middle,
+                                                              max_iter=20000))
     x = host(x)
     r = np.linalg.norm(b - oracle.apply_D(lat, U, kappa, x)) / np.linalg.norm(b)
     say("solve", solver, kappa, info.as_dict(), "oracle residual", r)
@@ -50,35 +56,82 @@ def _pair(lat, U, scale, seed, rule):
     return synth.redraw(U, mask, scale, seed)
 
 
+# solver settings of the parity cases: (solver, inner, middle)
+SOLVERS = {
+    "fgcr_f32": (0, 1, 0),   # FGCR(16) + FP32 Schwarz, FP32 block MR
+    "fgcr_f16": (0, 2, 0),   # FGCR(16) + FP16 Schwarz, FP16 block MR
+    "cgne_f64": (1, 0, 0),   # FP64 everywhere
+    "cgne_f32": (1, 1, 0),   # FP32 CG iterations, FP64 reliable updates, FP32 block MR
+    "cgne_f16": (1, 2, 0),   # FP16 CG iterations and block MR under FP64 reliable updates
+    "cgne_f16_3": (1, 2, 1),  # three levels: FP16 CG steps, FP32 middle updates, FP64 outer updates
+}
+
+
+def _params(wdr, name, **kw):
+    solver, inner, middle = SOLVERS[name]
+    return wdr.default_params(solver=solver, inner=inner, middle=middle, max_iter=20000, **kw)
+
+
 @pytest.mark.parametrize("op,kind,L,B,kappa,scale,rule,N,K,solver", [
     # 4^4 lattice, kappa 0.12, Z2 noise, Bernoulli(0.1) proposal (the small workload)
-    (oracle.OP_FULL, oracle.NOISE_Z2, (4, 4, 4, 4), (2, 2, 2, 2), 0.12, 0.3, "bernoulli", 3, 2, 1),
-    (oracle.OP_FULL, oracle.NOISE_GAUSS, (4, 4, 4, 4), (2, 2, 2, 2), 0.12, 0.3, "bernoulli", 2, 2, 0),
+    (oracle.OP_FULL, oracle.NOISE_Z2, (4, 4, 4, 4), (2, 2, 2, 2), 0.12, 0.3, "bernoulli", 3, 2, "cgne_f32"),
+    (oracle.OP_FULL, oracle.NOISE_GAUSS, (4, 4, 4, 4), (2, 2, 2, 2), 0.12, 0.3, "bernoulli", 2, 2, "fgcr_f32"),
     # 8^4 lattice with 16 blocks of 4^4, active links redrawn, Gaussian noise
-    (oracle.OP_SCHUR, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 2, 1, 0),
-    (oracle.OP_BLOCKS, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 2, 1, 0),
-    (oracle.OP_SCHUR, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.150, 0.25, "active", 1, 1, 1),
+    (oracle.OP_SCHUR, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 2, 1, "fgcr_f32"),
+    (oracle.OP_BLOCKS, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 2, 1, "fgcr_f32"),
+    (oracle.OP_SCHUR, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.150, 0.25, "active", 1, 1, "cgne_f32"),
     # FP16 Schwarz preconditioner and FP16 block solves inside the FP64 outer solves
-    (oracle.OP_SCHUR, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 2, 1, 2),
-    (oracle.OP_BLOCKS, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 1, 1, 2),
+    (oracle.OP_SCHUR, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 2, 1, "fgcr_f16"),
+    (oracle.OP_BLOCKS, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 1, 1, "fgcr_f16"),
+    # the solver form of the 16^4 and 32^4 workloads (CGNE with FP16 inner
+    # precision) on the subcritical and the supercritical kappa
+    (oracle.OP_SCHUR, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "active", 2, 1, "cgne_f16"),
+    (oracle.OP_SCHUR, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.155, 0.2, "active", 2, 1, "cgne_f16"),
+    (oracle.OP_BLOCKS, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.155, 0.2, "active", 2, 1, "cgne_f16"),
+    (oracle.OP_FULL, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.150, 0.25, "active", 2, 1, "cgne_f16"),
+    (oracle.OP_SCHUR, oracle.NOISE_GAUSS, (8, 8, 8, 8), (4, 4, 4, 4), 0.155, 0.2, "active", 2, 2, "cgne_f16_3"),
+    (oracle.OP_FULL, oracle.NOISE_Z2, (8, 8, 8, 8), (4, 4, 4, 4), 0.135, 0.5, "bernoulli", 3, 1, "cgne_f16_3"),
 ])
 def test_samples_match_oracle(op, kind, L, B, kappa, scale, rule, N, K, solver):
-    """s_{i,k} within 1e-8 absolute of the oracle at solver residual 1e-10
-    (solver 2: FGCR with the FP16 inner solver)."""
+    """s_{i,k} within 1e-8 absolute of the oracle at solver residual 1e-10."""
     wdr, lat, ctx, U = _setup(L, B, scale, 1112124300 + len(L) * L[0])
     Up = _pair(lat, U, scale, 303, rule)
     gU, gUp = ctx.gauge(dev(U)), ctx.gauge(dev(Up))
     seed = 99
-    p = wdr.default_params(solver=0, inner=wdr.F16) if solver == 2 else wdr.default_params(solver=solver)
+    p = _params(wdr, solver)
     s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, op, N, K, kind, seed, p)
     want, lr_want = oracle.logdet_ratio(lat, U, Up, kappa, op, N, K, kind, seed)
     err = np.abs(s - want).max()
-    say("samples op", op, "max |ds|", err, "log R", lr, lr_want, info.as_dict())
+    say("samples op", op, solver, "max |ds|", err, "log R", lr, lr_want, info.as_dict())
     assert s.shape == want.shape
     assert info.converged
     assert err < 1e-8
     # the library sums the per-block log ratios of BLOCKS
     assert abs(lr - float(np.sum(lr_want))) < 1e-8 * max(1, s.size)
+    del gU, gUp
+    ctx.close()
+
+
+@pytest.mark.parametrize("solver,form,kappa,scale", [("cgne_f16", 2, 0.155, 0.2), ("cgne_f32", 2, 0.155, 0.2),
+                                                     ("fgcr_f16", 2, 0.135, 0.5), ("cgne_f16", 1, 0.155, 0.2)])
+def test_dd_samples_match_oracle(solver, form, kappa, scale):
+    """The DD estimate (every block ratio and the Schur ratio of one
+    proposal in one call) against the oracle's BLOCKS and SCHUR samples,
+    with the block-MR launch form forced: two blocks per CU (the form the
+    block solves of the 16^4 and 32^4 estimates take by their size) or one.
+    FGCR + Schwarz runs at the subcritical kappa (it stalls above 1/8)."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), scale, 1112124334)
+    ctx.set_mr_form(form)
+    Up = _pair(lat, U, scale, 311, "active")
+    gU, gUp = ctx.gauge(dev(U)), ctx.gauge(dev(Up))
+    N = 2
+    s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, wdr.OP_DD, N, 1, wdr.NOISE_GAUSS, 43, _params(wdr, solver))
+    wb, lb = oracle.logdet_ratio(lat, U, Up, kappa, oracle.OP_BLOCKS, N, 1, oracle.NOISE_GAUSS, 43)
+    ws, ls = oracle.logdet_ratio(lat, U, Up, kappa, oracle.OP_SCHUR, N, 1, oracle.NOISE_GAUSS, 43)
+    eb, es = np.abs(s[..., :-1] - wb).max(), np.abs(s[..., -1] - ws).max()
+    say("dd", solver, "form", form, "max |ds| blocks", eb, "schur", es, info.as_dict())
+    assert info.converged and eb < 1e-8 and es < 1e-8
+    assert abs(lr - (float(np.sum(lb)) + float(ls))) < 1e-8 * s.size
     del gU, gUp
     ctx.close()
 
@@ -196,9 +249,12 @@ def test_abi_errors():
     with pytest.raises(wdr.WdrError) as e:
         ctx.solve(gU2, 0.135, psi, wdr.default_params(max_iter=1))
     assert e.value.status == wdr.ENOCONV
-    for bad in (dict(update_every=0), dict(update_every=65), dict(graph=2)):
+    for bad in (dict(update_every=0), dict(update_every=65), dict(graph=2), dict(middle=2),
+                dict(middle=wdr.F32, inner=wdr.F32), dict(middle=wdr.F32, inner=wdr.F16, solver=wdr.SOLVER_FGCR_SAP)):
+        kw = dict(solver=wdr.SOLVER_CGNE)
+        kw.update(bad)
         with pytest.raises(wdr.WdrError) as e:
-            ctx.solve(gU2, 0.135, psi, wdr.default_params(solver=wdr.SOLVER_CGNE, **bad))
+            ctx.solve(gU2, 0.135, psi, wdr.default_params(**kw))
         assert e.value.status == wdr.EINVAL
     # blocks of 8^4 are too large for the block solver
     big = wdr.Context((16, 16, 16, 16), (8, 8, 8, 8))

@@ -96,6 +96,11 @@ def test_apply_block_parts(case):
         want = oracle.apply_Dhop(lat, U, k, psi, fc)
         got = host(ctx.apply_Dhop(gU, k, dev(psi), fc, wdr.F64))
         assert rel(got, want) < 1e-14
+        got32 = host(ctx.apply_Dhop(gU, k, dev(psi), fc, wdr.F32))
+        say("Dhop from", fc, "f64 rel", rel(got, want), "f32 rel", rel(got32, want))
+        assert rel(got32, want) < 2e-6
+        # sites of the source colour are exactly zero in both precisions
+        assert np.all(got32[oracle.colour_mask(lat, fc)] == 0)
 
 
 @pytest.mark.parametrize("blocked", [False, True])
@@ -226,12 +231,17 @@ def test_sap_f16_matches_oracle():
     ctx.close()
 
 
-@pytest.mark.parametrize("inner", [0, 1, 2])
-def test_block_solve(inner):
+@pytest.mark.parametrize("inner,form", [(0, 0), (1, 0), (2, 0), (1, 2), (2, 2), (1, 1)])
+def test_block_solve(inner, form):
+    """Block solves of each colour to 1e-13 against the oracle, with the
+    block-MR launch form the context picks (form 0), or forced: two blocks
+    per CU (form 2, the form the 16^4 and 32^4 block solves take by their
+    size) and one per CU (form 1)."""
     from paper_1112_1243_amd import wdr
     L, B = (8, 8, 8, 8), (4, 4, 4, 4)
     lat = oracle.Lattice(L, B)
     ctx = _ctx(L, B, (1, 1, 1, 1))
+    ctx.set_mr_form(form)
     U = synth.gauge_field(L, 0.5, 108)
     b = synth.spinor(L, 109)
     gU = ctx.gauge(dev(U))
@@ -310,5 +320,9 @@ def test_stencil_choice_errors():
         with pytest.raises(wdr.WdrError) as e:
             ctx.set_stencil(bad)
         assert e.value.status == wdr.EINVAL
+        with pytest.raises(wdr.WdrError) as e:
+            ctx.set_mr_form(bad)
+        assert e.value.status == wdr.EINVAL
     ctx.set_stencil(wdr.STENCIL_AUTO)
+    ctx.set_mr_form(wdr.MR_AUTO)
     ctx.close()
