@@ -1,19 +1,21 @@
 #!/usr/bin/env python
 """Benchmark of the fermion-determinant-ratio path on one MI355X.
 
-Workload (one "step" = one complete estimate of log det(D'^+D')/det(D^+D)
-for one proposal U -> U', through the domain-decomposition factorisation
-det D = prod_b det D_b * det Dhat of the paper's Sec. 3):
-  8^4 lattice, kappa = 0.135, links exp(i 0.5 H), 16 blocks of 4^4, U'
-  redraws the active links of every block; the 16 block ratios (BLOCKS) and
-  the Schur-complement ratio (SCHUR) in one DD call, each over a path of
-  N = 8 factors with one complex Gaussian noise vector per factor;
-  FGCR(16)+SAP to 1e-10 with FP32 preconditioner and block solves refined in
-  FP64; Schwarz and block-solve depths chosen by wdr_autotune beforehand.
+Headline workload (one "step" = one complete estimate of the Schur-complement
+ratio log det(Dhat'^+ Dhat') / det(Dhat^+ Dhat) of the paper's Sec. 3 eq.
+ddfactor for one proposal U -> U', Sec. 4):
+  32^4 lattice, 4096 blocks of 4^4, kappa = 0.155, links exp(i 0.2 H), U'
+  redraws the active links of every block; N = 32 factors of eq. param with
+  one complex Gaussian noise vector each, all 32 samples solved as one batch;
+  CG on the normal equations with FP16 inner iterations, an FP32 middle level
+  and FP64 outer reliable updates (true residual 1e-10), FP16 block solves
+  with FP64 defect correction to 1e-13; block-solve depth and launch forms
+  chosen by wdr_autotune beforehand.
 
-Prints one JSON line: estimates/s of the mixed-precision form, the plain
-FP64 form on the same GPU, the stencil's HBM roofline fraction at 32^4, and
-the FP64 CPU oracle on a bounded sample.
+Prints one JSON line: estimates/s of that form, the plain FP64
+single-proposal form on the same GPU, the dominant kernel's HBM roofline
+fraction, the whole estimate's compulsory bytes against its time, and the
+FP64 CPU oracle on a bounded sample.  Other workloads follow as extra keys.
 """
 from __future__ import annotations
 
@@ -85,9 +87,10 @@ def proposal_mask(ctx, rule):
 
 def dd_workload(wdr, torch, name):
     """One estimate of a larger lattice workload of synth.WORKLOADS: the mixed
-    form (FP16 block solves, CGNE with FP32 iterations and FP64 reliable
-    updates, all samples batched) against the plain FP64 form (FP64 block
-    solves and CGNE, one sample at a time)."""
+    form (the workload's settings: FP16 block solves, CGNE with FP16
+    iterations, FP32 middle and FP64 outer reliable updates, all samples
+    batched) against the plain FP64 form (FP64 block solves and CGNE, one
+    sample at a time)."""
     from paper_1112_1243_amd import synth
     w = synth.WORKLOADS[name]
     t0 = time.perf_counter()
@@ -100,7 +103,7 @@ def dd_workload(wdr, torch, name):
     op = {"schur": wdr.OP_SCHUR, "full": wdr.OP_FULL, "blocks": wdr.OP_BLOCKS}[w["op"]]
     noise = wdr.NOISE_GAUSS if w["noise"] == "gauss" else wdr.NOISE_Z2
     N = w["n_noise"]
-    mixed = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F16, max_iter=20000)
+    mixed = wdr.default_params(**w["mixed"])
     plain = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F64, max_iter=20000)
     ctx.logdet_ratio(gU, gUp, w["kappa"], op, 1, 1, noise, 1, mixed)  # warm-up
     torch.cuda.synchronize()
@@ -117,7 +120,8 @@ def dd_workload(wdr, torch, name):
     del gU, gUp
     ctx.close()
     return {"workload": "%s: %s lattice, %s blocks, kappa %.3f, links exp(i %.2f H), %s ratio, N=%d factors x 1 %s "
-                        "noise, CGNE to 1e-10" % (name, "x".join(map(str, w["L"])), "x".join(map(str, w["B"])),
+                        "noise, CGNE (FP16/FP32/FP64 levels) to 1e-10" % (name, "x".join(map(str, w["L"])),
+                                                                           "x".join(map(str, w["B"])),
                                                   w["kappa"], w["scale"], w["op"].upper(), N, w["noise"]),
             "value": round(1.0 / t_m, 4), "unit": "estimates/s", "converged": bool(info_m.converged),
             "cg_iterations_total": int(info_m.total_iters),
@@ -144,7 +148,7 @@ def recursive_dd(wdr, torch):
     del U, Up
     log("recursive16_dd8: inputs ready in %.1f s" % (time.perf_counter() - t0))
     N = w["n_noise"]
-    mixed = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F16, max_iter=20000)
+    mixed = wdr.default_params(**synth.LARGE_MIXED)
     plain = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F64, max_iter=20000)
     ctx.block_schur_ratio(gU, gUp, w["kappa"], sub, 1, 1, wdr.NOISE_GAUSS, 1, mixed)  # warm-up
     torch.cuda.synchronize()
@@ -601,54 +605,299 @@ def block_determinants(wdr, torch):
     return res
 
 
-def cpu_baseline(wl, U, Up, budget_s=20.0):
-    """FP64 CPU oracle on a bounded sample: one BLOCKS and one SCHUR sample
-    (one factor, one noise vector) of the same workload, scaled to a full
-    estimate (2 ops x n_steps x n_noise samples)."""
+def cpu_info():
+    """CPU model (from /proc/cpuinfo) and the logical CPUs this process may use."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    return model, ncpu
+
+
+ORACLE_STENCIL_CHILD = r"""
+import sys, time
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_1112_1243_amd import synth
+L = (16, 16, 16, 16)
+lat = oracle.Lattice(L, (4, 4, 4, 4))
+U, psi = synth.gauge_field(L, 0.25, 1112124302), synth.spinor(L, 11)
+oracle.apply_D(lat, U, 0.150, psi)
+ts = []
+for _ in range(3):
+    t = time.perf_counter()
+    oracle.apply_D(lat, U, 0.150, psi)
+    ts.append(time.perf_counter() - t)
+print(sorted(ts)[1])
+"""
+
+
+def oracle_stencil_ms(threads):
+    """Median of 3 oracle stencil applications at 16^4 in a child process
+    with `threads` OpenMP threads (ms)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+    r = subprocess.run([sys.executable, "-c", ORACLE_STENCIL_CHILD, ROOT], capture_output=True, text=True, env=env,
+                       timeout=600)
+    return float(r.stdout.strip().splitlines()[-1]) * 1e3
+
+
+def cpu_baseline():
+    """The FP64 CPU oracle on a bounded sample of the headline workload's work
+    unit: one (factor, noise) item of the Schur estimate -- the oracle's
+    Schur complement (block solves to 1e-14), the global CGNE solve and its
+    adjoint to 1e-13, the second-order sample -- timed on the 16^4 lattice
+    of the same recipe (kappa 0.150, links exp(i 0.25 H), black-block links
+    redrawn) with all threads; the 32^4 item does not fit the benchmark's
+    time (about ten minutes).  Extrapolated to the headline estimate by the
+    volume ratio (16) and the N = 32 items.  Beside it the oracle's stencil
+    at 16^4, median of 3, with all threads and with one thread."""
     import oracle
-    lat = oracle.Lattice(wl["L"], wl["B"])
-    Ui1 = oracle.interpolate(U, Up, 1, wl["n_steps"])
-    t0 = time.perf_counter()
-    for op in (oracle.OP_BLOCKS, oracle.OP_SCHUR):
-        eta = oracle.noise(lat, oracle.NOISE_GAUSS, 7, 0, 0, support=oracle.noise_support(lat, op))
-        oracle.sample(lat, U, Ui1, wl["kappa"], op, eta, tol=1e-10, block_tol=1e-13)
-    dt = time.perf_counter() - t0
-    per_estimate = dt / 2 * 2 * wl["n_steps"] * wl["n_noise"]
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    # the oracle's stencil on the 16^4 lattice, median of 3, in the compulsory
-    # bytes of a full-link FP64 stencil (960 B/site)
     from paper_1112_1243_amd import synth
-    L16 = (16, 16, 16, 16)
-    lat16 = oracle.Lattice(L16, (4, 4, 4, 4))
-    U16, psi16 = synth.gauge_field(L16, 0.25, 1112124302), synth.spinor(L16, 11)
-    ts = []
-    for _ in range(3):
+    from tests.golden import make_golden
+    model, ncpu = cpu_info()
+    threads = int(os.environ.get("OMP_NUM_THREADS", ncpu))
+    w, lat, U, Up = make_golden.inputs("wilson16_dd256")
+    U1 = oracle.interpolate(U, Up, 1, w["n_noise"])
+    eta = oracle.noise(lat, oracle.NOISE_GAUSS, w["seed"], 0, 0, support=oracle.noise_support(lat, oracle.OP_SCHUR))
+    t0 = time.perf_counter()
+    oracle.sample(lat, U, U1, w["kappa"], oracle.OP_SCHUR, eta)
+    item = time.perf_counter() - t0
+    vol_ratio = (32 ** 4) / lat.V
+    per_estimate = item * vol_ratio * 32
+    ms_all = oracle_stencil_ms(threads)
+    ms_one = oracle_stencil_ms(1)
+    V16 = 16 ** 4
+    return {"value": round(1.0 / per_estimate, 7), "unit": "estimates/s", "cores": threads, "kind": "oracle",
+            "extrapolated": True, "cpu_model": model, "logical_cpus": ncpu,
+            "sample": "one SCHUR (factor, noise) item of the 16^4 lattice (same recipe as the 32^4 headline at "
+                      "kappa 0.150), oracle solves to 1e-13: %.1f s on %d threads; x%d (volume) x32 (items) = one "
+                      "32^4 estimate, extrapolated" % (item, threads, vol_ratio),
+            "item_seconds": round(item, 3),
+            "stencil": {"lattice": "16x16x16x16", "unit": "GB/s", "kind": "oracle apply_D, FP64, median of 3",
+                        "ms_all_threads": round(ms_all, 2), "ms_one_thread": round(ms_one, 2),
+                        "value_all_threads": round(960 * V16 / (ms_all * 1e-3) / 1e9, 2),
+                        "value_one_thread": round(960 * V16 / (ms_one * 1e-3) / 1e9, 2)}}
+
+
+# the headline workload (the largest configuration: 32^4, 4096 blocks of 4^4)
+HEADLINE = "wilson32_dd4096"
+# compulsory bytes of one k_eo16 launch per system of V sites (one even-odd
+# half in FP16: the input half, the output half and every link of the
+# lattice, FP16 two-row, 24 B per link), plus the FP16 diagonal half if any
+EO16_SOURCES = ["paper_1112_1243_amd/csrc/cg16.hip", "paper_1112_1243_amd/csrc/stencil.h",
+                "paper_1112_1243_amd/csrc/wdr_internal.h"]
+EO16_COUNTERS = os.path.join(ROOT, "profiles", "eo16_32x32x32x32_counters.md")
+
+
+def eo16_bytes(V, diag):
+    return V // 2 * 48 * (3 if diag else 2) + V * 96
+
+
+def headline_estimate(wdr, torch, steps, warmup, fp64=True):
+    """The headline: K estimates of the 32^4 Schur ratio (N = 32) in the
+    mixed-precision form after W warm-up estimates, and the plain FP64
+    single-proposal form (FP64 CGNE, FP64 block solves, one sample at a
+    time, no graphs) on the same proposal."""
+    from paper_1112_1243_amd import synth
+    w = synth.WORKLOADS[HEADLINE]
+    N = w["n_noise"]
+    t0 = time.perf_counter()
+    ctx = wdr.Context(w["L"], w["B"])
+    U = synth.gauge_field(w["L"], w["scale"], w["seed"])
+    Up = synth.redraw(U, proposal_mask(ctx, w["proposal"]), w["scale"], w["seed"])
+    gU, gUp = ctx.gauge(torch.from_numpy(U).cuda()), ctx.gauge(torch.from_numpy(Up).cuda())
+    del U, Up
+    log("%s: inputs ready in %.1f s" % (HEADLINE, time.perf_counter() - t0))
+    t0 = time.perf_counter()
+    mixed, t_trial = ctx.autotune(gU, gUp, w["kappa"], wdr.OP_SCHUR, N, 1, wdr.NOISE_GAUSS, 500,
+                                  wdr.default_params(**w["mixed"]))
+    log("%s: autotuned in %.1f s: block MR %d (trial estimate %.3f s)" % (HEADLINE, time.perf_counter() - t0,
+                                                                          mixed.block_mr_steps, t_trial))
+    for k in range(warmup):
+        ctx.logdet_ratio(gU, gUp, w["kappa"], wdr.OP_SCHUR, N, 1, wdr.NOISE_GAUSS, 1000 + k, mixed)
+    torch.cuda.synchronize()
+    wdr.traffic(reset=True)
+    t0 = time.perf_counter()
+    ok, iters, lrs, s_first = True, 0, [], None
+    for k in range(steps):
+        s, lr, info = ctx.logdet_ratio(gU, gUp, w["kappa"], wdr.OP_SCHUR, N, 1, wdr.NOISE_GAUSS, 2000 + k, mixed)
+        ok &= bool(info.converged) and info.true_rel_resid <= 1e-10
+        iters += info.total_iters
+        lrs.append(lr)
+        if s_first is None:
+            s_first = s
+        log("step %d: log R = %.10f converged=%s CG iterations=%d" % (k, lr, bool(info.converged),
+                                                                       info.total_iters))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    traffic = wdr.traffic(reset=True)
+    out = {"steps": steps, "seconds": dt, "converged": ok, "cg_iterations": iters, "mean_log_ratio": float(np.mean(lrs)),
+           "params": mixed, "traffic_bytes": traffic}
+    if fp64:
+        plain = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F64, middle=wdr.F64, max_iter=20000, graph=0)
         t1 = time.perf_counter()
-        oracle.apply_D(lat16, U16, 0.150, psi16)
-        ts.append(time.perf_counter() - t1)
-    ms = sorted(ts)[1] * 1e3
-    return {"value": round(1.0 / per_estimate, 6), "unit": "estimates/s", "cores": threads, "kind": "oracle",
-            "sample": "1 BLOCKS + 1 SCHUR sample (one path factor, one noise vector) at 8^4, FP64 CGNE to 1e-10, "
-                      "%.1f s, scaled x%d to one estimate" % (dt, wl["n_steps"] * wl["n_noise"]),
-            "stencil": {"lattice": "16x16x16x16", "ms": round(ms, 2), "unit": "GB/s",
-                        "value": round(960 * lat16.V / (ms * 1e-3) / 1e9, 2), "kind": "oracle apply_D, FP64, median of 3"}}
+        s_p, lr_p, info_p = ctx.logdet_ratio(gU, gUp, w["kappa"], wdr.OP_SCHUR, N, 1, wdr.NOISE_GAUSS, 2000, plain,
+                                             max_batch=1)
+        torch.cuda.synchronize()
+        out["fp64_seconds"] = time.perf_counter() - t1
+        out["fp64_converged"] = bool(info_p.converged)
+        out["max_abs_sample_diff_vs_fp64"] = float(np.abs(s_first - s_p).max())
+        log("%s plain fp64: %.3f s, max |ds| vs mixed %.2e" % (HEADLINE, out["fp64_seconds"],
+                                                               out["max_abs_sample_diff_vs_fp64"]))
+    out["nsys"] = N
+    del gU, gUp
+    ctx.close()
+    return out
+
+
+def eo16_roofline(wdr, torch, nsys, reps=20):
+    """Average duration of one k_eo16 launch (one even-odd half of the FP16
+    CG stencil) at 32^4 with nsys systems per launch, the launch shape of the
+    headline estimate, by HIP events on the stream it is launched on: pairs
+    of launches as a CG step issues them (odd sites from even without a
+    diagonal term, even sites from odd with one)."""
+    from paper_1112_1243_amd import synth
+    w = synth.WORKLOADS[HEADLINE]
+    ctx = wdr.Context(w["L"], w["B"])
+    U = synth.gauge_field(w["L"], w["scale"], w["seed"])
+    gU = ctx.gauge(torch.from_numpy(U).cuda())
+    del U
+    one = ctx.pack_eo16(torch.from_numpy(synth.spinor(w["L"], 5)).cuda(), 0)
+    vals, nsc = one.numel() - ctx.nblocks * 4, ctx.nblocks * 4
+    ev = ctx.eo16_field(nsys)
+    for m in range(nsys):  # nsys copies: values first, then the scales
+        ev[m * vals:(m + 1) * vals] = one[:vals]
+        ev[nsys * vals + m * nsc:nsys * vals + (m + 1) * nsc] = one[vals:]
+    od, out = ctx.eo16_field(nsys), ctx.eo16_field(nsys)
+    k = w["kappa"]
+
+    def pair():
+        ctx.apply_hop_eo_internal(gU, k, wdr.F16, 1, 0, ev, None, od, nsys)
+        ctx.apply_hop_eo_internal(gU, k, wdr.F16, 0, 0, od, ev, out, nsys)
+    for _ in range(3):
+        pair()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        pair()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / (2 * reps)
+    V = ctx.V
+    alg = nsys * (eo16_bytes(V, False) + eo16_bytes(V, True)) // 2
+    gbs = alg / (ms * 1e-3) / 1e9
+    del gU, ev, od, out, one
+    ctx.close()
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": counted_traffic_eo16(nsys),
+            "kernel": "k_eo16 (FP16 even-odd half of the CG stencil, site-major FP16 fields and links)",
+            "lattice": "32x32x32x32", "systems_per_launch": nsys, "avg_launch_us": round(ms * 1e3, 2),
+            "bytes_per_launch": int(alg),
+            "bytes_per_site": "per system: V/2 x 48 B in + V/2 x 48 B out (+ V/2 x 48 B diagonal on every other "
+                              "launch) + V x 96 B links"}
+
+
+def sources_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counted_traffic_eo16(nsys):
+    """HBM bytes per k_eo16 launch from the committed counter summary (for
+    that many systems per launch), or None when cg16.hip changed since."""
+    try:
+        with open(EO16_COUNTERS) as fh:
+            for line in fh:
+                if line.startswith("traffic_json:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if rec.get("sources_sha256_16") == sources_hash(EO16_SOURCES) and rec.get("nsys") == nsys:
+                        return rec["bytes_per_launch"]
+    except OSError:
+        pass
+    return None
+
+
+def dd8_workload(wdr, torch, steps, warmup, fp64=True):
+    """The 8^4 domain-decomposition estimate: 16 block ratios and the Schur
+    ratio (one DD call), N = 8 factors x 1 Gaussian noise, FGCR(16) + SAP
+    to 1e-10 with FP32 preconditioner, autotuned; the plain FP64 form beside."""
+    from paper_1112_1243_amd import synth
+    wl = WORKLOAD
+    ctx = wdr.Context(wl["L"], wl["B"])
+    U = make_inputs(wl)
+    Up = synth.redraw(U, proposal_mask(ctx, "active"), wl["scale"], wl["seed"])
+    gU = ctx.gauge(torch.from_numpy(U).cuda())
+    gUp = ctx.gauge(torch.from_numpy(Up).cuda())
+    mixed, _ = ctx.autotune(gU, gUp, wl["kappa"], wdr.OP_DD, wl["n_steps"], wl["n_noise"], wdr.NOISE_GAUSS, 500,
+                            wdr.default_params(inner=wdr.F32))
+    p64, _ = ctx.autotune(gU, gUp, wl["kappa"], wdr.OP_DD, wl["n_steps"], wl["n_noise"], wdr.NOISE_GAUSS, 500,
+                          wdr.default_params(inner=wdr.F64))
+    for k in range(warmup):
+        estimate(ctx, wdr, gU, gUp, wl, mixed, 1000 + k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ok, iters = True, 0
+    for k in range(steps):
+        _, c, it = estimate(ctx, wdr, gU, gUp, wl, mixed, 2000 + k)
+        ok &= c
+        iters += it
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"workload": "%s: 8^4 lattice, 16 blocks of 4^4, kappa 0.135, links exp(i 0.5 H), active links redrawn, "
+                       "BLOCKS + SCHUR ratios (DD), N=8 factors x 1 Gaussian noise, FGCR(16)+SAP (autotuned depth) "
+                       "to 1e-10" % wl["name"], "value": round(steps / dt, 3), "unit": "estimates/s",
+           "converged": ok, "total_outer_iters": iters,
+           "schedule": {"mixed": {"sap_cycles": mixed.sap_cycles, "mr_steps": mixed.mr_steps,
+                                  "block_mr_steps": mixed.block_mr_steps},
+                        "fp64": {"sap_cycles": p64.sap_cycles, "mr_steps": p64.mr_steps,
+                                 "block_mr_steps": p64.block_mr_steps}}}
+    if fp64:
+        t1 = time.perf_counter()
+        n64 = max(1, min(5, steps))
+        for k in range(n64):
+            estimate(ctx, wdr, gU, gUp, wl, p64, 2000 + k)
+        torch.cuda.synchronize()
+        out["fp64_estimates_per_s"] = round(n64 / (time.perf_counter() - t1), 3)
+    del gU, gUp
+    ctx.close()
+    log("dd8:", out)
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the 32^4 headline estimates (for profiling): no FP64 form, rooflines or extras")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-dslash", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-proposal workload")
-    ap.add_argument("--no-large", action="store_true", help="skip the 16^4 and 32^4 workloads")
+    ap.add_argument("--no-large", action="store_true", help="skip the 16^4 workload")
+    ap.add_argument("--no-dd8", action="store_true", help="skip the 8^4 domain-decomposition workload")
     ap.add_argument("--no-blockdet", action="store_true", help="skip the exact block determinants")
     ap.add_argument("--no-recursive", action="store_true", help="skip the recursive-DD workload")
-    ap.add_argument("--no-filter", action="store_true", help="skip the filter and acceptance-rate runs")
+    ap.add_argument("--no-filter", action="store_true", help="skip the filter run")
+    ap.add_argument("--acceptance", action="store_true", help="also run the exact-acceptance variance study")
     ap.add_argument("--stencil", choices=("auto", "dir", "blk"), default="auto",
-                    help="stencil kernel for the 32^4 roofline launches (default: the library's choice)")
+                    help="stencil kernel for the 32^4 full-stencil launches (default: the library's choice)")
     ap.add_argument("--rocprof-summary", metavar="DIR", help="print a markdown summary of rocprofv3 CSV output")
     args = ap.parse_args()
     if args.rocprof_summary:
@@ -658,77 +907,50 @@ def main():
         print("bench.py runs on one GPU: the library has no multi-GPU path (every proposal, path factor and "
               "noise vector is independent, so they would be dealt out to one process per GPU)", file=sys.stderr)
         sys.exit(2)
+    if args.headline_only:
+        args.no_cpu = args.no_fp64 = args.no_dslash = args.no_batch = args.no_large = args.no_dd8 = True
+        args.no_blockdet = args.no_recursive = args.no_filter = True
 
     import torch
     from paper_1112_1243_amd import synth, wdr
 
-    wl = WORKLOAD
-    ctx = wdr.Context(wl["L"], wl["B"])
-    U = make_inputs(wl)
-    Up = synth.redraw(U, proposal_mask(ctx, "active"), wl["scale"], wl["seed"])
-    gU = ctx.gauge(torch.from_numpy(U).cuda())
-    gUp = ctx.gauge(torch.from_numpy(Up).cuda())
-    # schedule autotuning (Schwarz depth, block-solve rounds) on a short
-    # estimate with another noise key, outside the timed region
-    mixed, t_mixed = ctx.autotune(gU, gUp, wl["kappa"], wdr.OP_DD, wl["n_steps"], wl["n_noise"], wdr.NOISE_GAUSS,
-                                  500, wdr.default_params(inner=wdr.F32))
-    fp64, t_fp64 = ctx.autotune(gU, gUp, wl["kappa"], wdr.OP_DD, wl["n_steps"], wl["n_noise"], wdr.NOISE_GAUSS,
-                                500, wdr.default_params(inner=wdr.F64))
-    log("autotuned: mixed SAP(%d,%d) block MR %d; fp64 SAP(%d,%d) block MR %d"
-        % (mixed.sap_cycles, mixed.mr_steps, mixed.block_mr_steps, fp64.sap_cycles, fp64.mr_steps,
-           fp64.block_mr_steps))
-
-    for w in range(args.warmup):
-        estimate(ctx, wdr, gU, gUp, wl, mixed, 1000 + w)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    all_ok = True
-    iters = 0
-    lrs = []
-    for k in range(args.steps):
-        lr, ok, it = estimate(ctx, wdr, gU, gUp, wl, mixed, 2000 + k)
-        all_ok &= ok
-        iters += it
-        lrs.append(lr)
-        log("step %d: log R = %.10f converged=%s iters=%d" % (k, lr, ok, it))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    w = synth.WORKLOADS[HEADLINE]
+    head = headline_estimate(wdr, torch, args.steps, args.warmup, fp64=not args.no_fp64)
+    dt = head["seconds"]
     value = args.steps / dt
-
-    fp64_rate = None
-    if not args.no_fp64:
-        t1 = time.perf_counter()
-        n64 = max(1, min(5, args.steps))
-        for k in range(n64):
-            estimate(ctx, wdr, gU, gUp, wl, fp64, 2000 + k)
-        torch.cuda.synchronize()
-        fp64_rate = n64 / (time.perf_counter() - t1)
-        log("plain fp64 form: %.3f estimates/s" % fp64_rate)
-    del gU, gUp
-    ctx.close()
+    mixed = head["params"]
 
     roof = None
     if not args.no_dslash:
-        # the FP64 stencil is the global operator of the outer solve
+        roof = eo16_roofline(wdr, torch, head["nsys"])
+        log("k_eo16:", roof)
+        # the full Wilson stencil (the Dslash half of the metric) beside it
         sc = {"auto": wdr.STENCIL_AUTO, "dir": wdr.STENCIL_DIR, "blk": wdr.STENCIL_BLK}[args.stencil]
-        roof = dslash_roofline(wdr, torch, prec_name="f64", stencil=sc)
+        r64 = dslash_roofline(wdr, torch, prec_name="f64", stencil=sc)
         r32 = dslash_roofline(wdr, torch, prec_name="f32", stencil=sc)
-        log("dslash f64:", roof)
+        log("dslash f64:", r64)
         log("dslash f32:", r32)
-        roof["f32"] = {k: r32[k] for k in ("achieved", "frac", "traffic", "kernel", "avg_launch_us",
-                                           "bytes_per_launch")}
-        roof["f16"] = dslash_f16(wdr, torch)
-        log("dslash f16:", roof["f16"])
+        roof["stencil_f64"] = r64
+        roof["stencil_f32"] = {k: r32[k] for k in ("achieved", "frac", "traffic", "kernel", "avg_launch_us",
+                                                    "bytes_per_launch")}
+        roof["stencil_f16"] = dslash_f16(wdr, torch)
+        log("dslash f16:", roof["stencil_f16"])
         roof["copy_ceiling"] = copy_ceiling(torch)
         log("copy ceiling:", roof["copy_ceiling"])
+    whole = None
+    if head["traffic_bytes"]:
+        per = head["traffic_bytes"] / args.steps
+        gbs = per / (dt / args.steps) / 1e9
+        whole = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(gbs / HBM_PEAK_GBS, 4), "compulsory_bytes_per_estimate": int(per),
+                 "what": "compulsory bytes of every kernel of one estimate (the library's wdr_traffic count from "
+                         "per-system iteration, update and round counts) over the estimate's wall time"}
 
+    dd8 = None if args.no_dd8 else dd8_workload(wdr, torch, max(5, args.steps), 2, fp64=not args.no_fp64)
     batch = None if args.no_batch else batched_proposals(wdr, torch)
     if batch:
         log("batched proposals:", batch)
-    large = None
-    if not args.no_large:
-        large = {name: dd_workload(wdr, torch, name) for name in ("wilson16_dd256", "wilson32_dd4096")}
-
+    large = None if args.no_large else {"wilson16_dd256": dd_workload(wdr, torch, "wilson16_dd256")}
     bdet = None if args.no_blockdet else block_determinants(wdr, torch)
     rdd = None if args.no_recursive else recursive_dd(wdr, torch)
     if rdd:
@@ -736,12 +958,12 @@ def main():
     filt = None if args.no_filter else filter_run(wdr, torch)
     if filt:
         log("filter:", filt)
-    acc = None if args.no_filter else exact_acceptance(wdr, torch)
-
-    cpu = None if args.no_cpu else cpu_baseline(wl, U, Up)
+    acc = exact_acceptance(wdr, torch) if args.acceptance else None
+    cpu = None if args.no_cpu else cpu_baseline()
     if cpu:
         log("cpu baseline:", cpu)
 
+    fp64_rate = 1.0 / head["fp64_seconds"] if "fp64_seconds" in head else None
     out = {
         "metric": "Dslash HBM GB/s (% peak) + det-ratio estimates/sec at 1e-10 residual vs FP64",
         "value": round(value, 4),
@@ -753,18 +975,22 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "f16+f32+f64",
         "data": "synthetic",
-        "config": {"workload": "%s: 8^4 lattice, 16 blocks of 4^4, kappa 0.135, links exp(i 0.5 H), active links "
-                               "redrawn, BLOCKS + SCHUR ratios (DD), N=8 factors x 1 Gaussian noise, FGCR(16)+SAP "
-                               "(autotuned depth) to 1e-10" % wl["name"],
-                   "converged": all_ok, "total_outer_iters": iters, "mean_log_ratio": float(np.mean(lrs)),
-                   "schedule": {"mixed": {"sap_cycles": mixed.sap_cycles, "mr_steps": mixed.mr_steps,
-                                          "block_mr_steps": mixed.block_mr_steps},
-                                "fp64": {"sap_cycles": fp64.sap_cycles, "mr_steps": fp64.mr_steps,
-                                         "block_mr_steps": fp64.block_mr_steps}}},
+        "config": {"workload": "%s: 32^4 lattice, 4096 blocks of 4^4, kappa 0.155, links exp(i 0.2 H), active links "
+                               "redrawn, SCHUR ratio, N=32 factors x 1 Gaussian noise (batched), CGNE with FP16 inner "
+                               "iterations, FP32 middle and FP64 outer reliable updates to 1e-10, FP16 block solves "
+                               "to 1e-13" % HEADLINE,
+                   "converged": head["converged"], "cg_iterations": head["cg_iterations"],
+                   "mean_log_ratio": head["mean_log_ratio"],
+                   "schedule": {"block_mr_steps": mixed.block_mr_steps, "inner": mixed.inner,
+                                "middle": mixed.middle}},
         "fp64_estimates_per_s": None if fp64_rate is None else round(fp64_rate, 4),
+        "speedup_vs_fp64": None if fp64_rate is None else round(value / fp64_rate, 3),
+        "max_abs_sample_diff_vs_fp64": head.get("max_abs_sample_diff_vs_fp64"),
         "roofline": roof,
+        "whole_estimate_roofline": whole,
+        "wilson8_dd16": dd8,
         "batched_proposals": batch,
         "large_lattices": large,
         "block_determinants": bdet,

@@ -153,6 +153,15 @@ wdr_status wdr_ctx_destroy(wdr_ctx *ctx);
 int64_t wdr_ctx_volume(const wdr_ctx *ctx);
 int32_t wdr_ctx_nblocks(const wdr_ctx *ctx);
 
+/* Algorithmic device-memory traffic of the estimates of this process: the
+ * compulsory bytes (every operand of a kernel read or written once; spinors
+ * of the sites a kernel covers, each link and neighbour once) of the work
+ * done by wdr_logdet_ratio / _batch and the solvers they call (CGNE and
+ * the block solves, counted from their per-system iteration, update and
+ * round counts; the FGCR / Schwarz solver is not counted), summed over all
+ * contexts since the last reset.  reset = 1 returns the sum and clears it. */
+int64_t wdr_traffic(int32_t reset);
+
 /* Stencil kernel for the full operator D and the Dirichlet block operators
  * D_b (the hops of Sec. 3's blocks) on SU(3) fields with 4^4 blocks; the
  * result is the same operator either way, up to rounding order.
@@ -244,6 +253,37 @@ wdr_status wdr_unpack(wdr_ctx *ctx, wdr_prec prec, const void *dev_internal, dou
 wdr_status wdr_apply_D_internal(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec,
                                 const void *dev_in, void *dev_out, void *stream);
 
+/* Even-odd halves on internal fields (the stencil of the even-odd CG of
+ * wdr_solve; D = 1 - kappa H splits into the hops H_eo from odd to even
+ * sites and H_oe from even to odd).  One call is exactly one kernel launch
+ * on `stream`:
+ *   out = diag - kappa H_{p, 1-p} in   on the sites of parity p = parity,
+ * with gamma_5 H gamma_5 in place of H when dag = 1 (the half of D^+);
+ * dev_diag may be NULL (no diagonal term); in, diag and out must not alias.
+ * nsys systems share the gauge field U and sit back to back:
+ *   F64 / F32: nsys fields of wdr_field_bytes(ctx, prec) bytes each; the
+ *              sites of the other parity are read from in, written in
+ *              out nowhere.
+ *   F16:       the layout of the FP16 even-odd CG, which holds one parity
+ *              of every block: nsys x wdr_eo16_field_bytes(ctx) bytes, all
+ *              values first ([system][block slot][site of that parity in
+ *              the in-block order][12] FP16 complex, 48 bytes per site),
+ *              then one float power-of-two scale per (system, slot) >= the
+ *              largest |component| of that block's half (stored value =
+ *              value / scale); in holds parity 1 - p, diag and out parity p,
+ *              and out receives fresh scales.  Needs 4^4 blocks in a
+ *              2-colourable checkerboard and an SU(3) field.
+ * EINVAL otherwise. */
+int64_t wdr_eo16_field_bytes(const wdr_ctx *ctx);
+wdr_status wdr_apply_hop_eo_internal(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t parity,
+                                     int32_t dag, int32_t nsys, const void *dev_in, const void *dev_diag,
+                                     void *dev_out, void *stream);
+/* The sites of parity `parity` of a canonical spinor into one F16 half field
+ * of that layout (scales from the block maxima), and back (the other
+ * parity's sites of dev_canon set to zero). */
+wdr_status wdr_pack_eo16(wdr_ctx *ctx, int32_t parity, const double *dev_canon, void *dev_eo16, void *stream);
+wdr_status wdr_unpack_eo16(wdr_ctx *ctx, int32_t parity, const void *dev_eo16, double *dev_canon, void *stream);
+
 /* out = D in (canonical spinors), computed in precision `prec` (F16 as for
  * wdr_apply_D_internal, input rounded by wdr_pack). */
 wdr_status wdr_apply_D(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, const double *dev_in,
@@ -330,12 +370,16 @@ wdr_status wdr_logdet_ratio_batch(int32_t n, const wdr_proposal *props, const wd
 
 /* Schedule autotuner for wdr_logdet_ratio on this context: times a short
  * estimate (at most eight path factors, the noise key of *p plus one; the
- * faster of two runs after a warm-up run) for a set of Schwarz depths (cycles x MR steps, FGCR only) and then of block-solve
- * MR depths (ratios with block solves), and writes the fastest into p->sp.
- * Every candidate solves to the tolerances of p->sp, so the choice changes
- * time only.  The result is cached in the context per (ratio, solver, inner
- * precision, kappa); host_seconds (may be NULL) receives the time of the
- * chosen candidate. */
+ * faster of two runs after a warm-up run) for a set of Schwarz depths
+ * (cycles x MR steps, FGCR only), then of block-solve MR depths (ratios with
+ * block solves), then of launch forms (the block-MR form of
+ * wdr_ctx_set_mr_form, then the stencil kernel of wdr_ctx_set_stencil), and
+ * writes the fastest depths into p->sp and the fastest forms into the
+ * context (as the two setters would).  Every candidate solves to the
+ * tolerances of p->sp, so the choice changes time only.  The result is
+ * cached in the context per (ratio, solver, inner and middle precision,
+ * kappa); a cached result restores its forms.  host_seconds (may be NULL)
+ * receives the time of the chosen candidate. */
 wdr_status wdr_autotune(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *Up, double kappa, wdr_est_params *p,
                         double *host_seconds, void *stream);
 

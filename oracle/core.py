@@ -37,6 +37,7 @@ Pins (tests under ``tests/test_oracle_*.py``):
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from dataclasses import dataclass, field
@@ -410,6 +411,11 @@ def sample(lat: Lattice, U0, U1, kappa: float, op: int, eta, tol: float = 1e-13,
     ||M eta||^2 = ||P z||^2 with z = A'^-1 y is evaluated as
     ||P z~||^2 + 2 Re w^+ (y - A' z~), A'^+ w = P z~, which equals it up to
     ||A'^-1 (y - A' z~)||^2 (both solves tight).
+
+    s itself is the sum over sites of |eta(x)|^2 - |P z(x)|^2 - 2 Re w(x)^+
+    r(x), the difference taken per site in FP64 and the sum correctly
+    rounded (math.fsum): s is a small difference of two sums of order 12 V,
+    whose separate rounding would cost up to ~1e-8 absolute at 32^4.
     """
     eta = _c(eta)
     if op == OP_FULL:
@@ -417,16 +423,14 @@ def sample(lat: Lattice, U0, U1, kappa: float, op: int, eta, tol: float = 1e-13,
         z, w, _, _ = solve(lat, U1, kappa, y, "full", 2, tol)
         # with CGNE, z = A'^+ w exactly, so w solves A'^+ w = z
         r = y - apply_D(lat, U1, kappa, z)
-        q = np.vdot(z, z).real + 2 * _dot(w, r).real
-        return float(np.vdot(eta, eta).real - q)
+        return math.fsum(_site_terms(eta, z, w, r))
     if op == OP_BLOCKS:
         bid, _, _ = lat.maps()
         y = apply_Dblock(lat, U0, kappa, eta, 2)
         z, w, _, _ = solve(lat, U1, kappa, y, "block", 2, block_tol)
         r = y - apply_Dblock(lat, U1, kappa, z, 2)
-        per_site = (np.abs(eta) ** 2).sum(axis=(1, 2)) - (np.abs(z) ** 2).sum(axis=(1, 2)) \
-            - 2 * np.real(np.conj(w) * r).sum(axis=(1, 2))
-        return np.bincount(bid, weights=per_site, minlength=lat.nblocks)
+        per_site = _site_terms(eta, z, w, r)
+        return np.array([math.fsum(per_site[bid == b]) for b in range(lat.nblocks)])
     if op == OP_SCHUR:
         black = colour_mask(lat, 0)
         e = eta.copy()
@@ -440,9 +444,15 @@ def sample(lat: Lattice, U0, U1, kappa: float, op: int, eta, tol: float = 1e-13,
         v, _, _, _ = solve(lat, U1, kappa, g5(pz), "full", 2, tol)
         w = g5(v)
         r = y - apply_D(lat, U1, kappa, z)
-        q = np.vdot(pz, pz).real + 2 * _dot(w, r).real
-        return float(np.vdot(e, e).real - q)
+        return math.fsum(_site_terms(e, pz, w, r))
     raise ValueError("unknown operator")
+
+
+def _site_terms(eta, z, w, r) -> np.ndarray:
+    """|eta(x)|^2 - |z(x)|^2 - 2 Re w(x)^+ r(x) per site (Sec. 4 sample,
+    second-order form)."""
+    return ((np.abs(eta) ** 2).sum(axis=(1, 2)) - (np.abs(z) ** 2).sum(axis=(1, 2))
+            - 2 * np.real(np.conj(w) * r).sum(axis=(1, 2)))
 
 
 def noise_support(lat: Lattice, op: int):

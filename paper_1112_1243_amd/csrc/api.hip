@@ -263,12 +263,104 @@ wdr_status wdr_unpack(wdr_ctx *c, wdr_prec prec, const void *internal, double *c
         Work t(c, field_bytes(c, WDR_F64));
         if (!t.ok()) return WDR_ENOMEM;
         const H16 f = f16_field(c, const_cast<void *>(internal));
-        launch_from_h16(c->g, all_sys(c, 1), H16c{f.v, f.s}, t.as<double2>(), 0, S(stream));
+        launch_from_h16(c->g, all_sys(c, 1), H16c{f.v, f.s}, t.as<double2>(), 0, 0, c->g.nblk, S(stream));
         launch_unpack_spinor<double>(c->g, t.as<double2>(), reinterpret_cast<double2 *>(canon), S(stream));
     } else {
         set_error("precision must be F64, F32 or F16");
         return WDR_EINVAL;
     }
+    return finish(S(stream));
+}
+
+int64_t wdr_eo16_field_bytes(const wdr_ctx *c)
+{
+    if (!c || !e16_geometry(c->g)) return 0;
+    return (int64_t)e16_field_bytes(c->g, 1);
+}
+
+wdr_status wdr_pack_eo16(wdr_ctx *c, int32_t parity, const double *canon, void *eo16, void *stream)
+{
+    wdr_status e = pre(c, canon, eo16);
+    if (e != WDR_OK) return e;
+    if (!e16_geometry(c->g) || (parity != 0 && parity != 1)) {
+        set_error("FP16 half fields need 4^4 blocks in a 2-colourable checkerboard; parity 0 or 1");
+        return WDR_EINVAL;
+    }
+    Work t(c, field_bytes(c, WDR_F64));
+    if (!t.ok()) return WDR_ENOMEM;
+    launch_pack_spinor<double>(c->g, reinterpret_cast<const double2 *>(canon), t.as<double2>(), S(stream));
+    launch_e16_from64(c->g, 1, parity, t.as<double2>(), e16_field(c->g, 1, eo16), S(stream));
+    return finish(S(stream));
+}
+
+wdr_status wdr_unpack_eo16(wdr_ctx *c, int32_t parity, const void *eo16, double *canon, void *stream)
+{
+    wdr_status e = pre(c, eo16, canon);
+    if (e != WDR_OK) return e;
+    if (!e16_geometry(c->g) || (parity != 0 && parity != 1)) {
+        set_error("FP16 half fields need 4^4 blocks in a 2-colourable checkerboard; parity 0 or 1");
+        return WDR_EINVAL;
+    }
+    Work t(c, field_bytes(c, WDR_F64));
+    if (!t.ok()) return WDR_ENOMEM;
+    launch_e16_to64(c->g, 1, parity, cref(e16_field(c->g, 1, const_cast<void *>(eo16))), t.as<double2>(), S(stream));
+    launch_unpack_spinor<double>(c->g, t.as<double2>(), reinterpret_cast<double2 *>(canon), S(stream));
+    return finish(S(stream));
+}
+
+wdr_status wdr_apply_hop_eo_internal(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t parity,
+                                     int32_t dag, int32_t nsys, const void *in, const void *diag, void *out,
+                                     void *stream)
+{
+    wdr_status e = pre(c, in, out);
+    if (e != WDR_OK) return e;
+    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
+    if ((parity != 0 && parity != 1) || (dag != 0 && dag != 1) || nsys < 1) {
+        set_error("parity and dag must be 0 or 1, nsys >= 1");
+        return WDR_EINVAL;
+    }
+    if (in == out || diag == out || diag == in) {
+        set_error("in, diag and out must not alias");
+        return WDR_EINVAL;
+    }
+    const Geo &g = c->g;
+    GaugeTab tab = view(U);
+    Sys sy = all_sys(c, nsys);
+    if (prec == WDR_F16) {
+        if (!e16_geometry(g) || !tab.e16.tab) {
+            set_error("FP16 half fields need 4^4 blocks in a 2-colourable checkerboard and an SU(3) field");
+            return WDR_EINVAL;
+        }
+        // one gauge pointer for every system of the launch (a table the handle keeps)
+        const void *const *t = replicated(const_cast<wdr_gauge *>(U), 3, nsys, S(stream));
+        if (!t) {
+            set_error("gauge table allocation failed");
+            return WDR_ENOMEM;
+        }
+        const Links16 L{reinterpret_cast<const h2 *const *>(t), nullptr};
+        const E16c din = cref(e16_field(g, nsys, const_cast<void *>(in)));
+        const E16c ddg = diag ? cref(e16_field(g, nsys, const_cast<void *>(diag))) : E16c{nullptr, nullptr};
+        launch_eo16(g, sy, L, -1.f, -(float)kappa, parity, dag, din, ddg, e16_field(g, nsys, out), nullptr,
+                    S(stream));
+        return finish(S(stream));
+    }
+    if (prec != WDR_F64 && prec != WDR_F32) {
+        set_error("precision must be F64, F32 or F16");
+        return WDR_EINVAL;
+    }
+    const void *const *t = replicated(const_cast<wdr_gauge *>(U), prec == WDR_F64 ? 0 : 1, nsys, S(stream));
+    if (!t) {
+        set_error("gauge table allocation failed");
+        return WDR_ENOMEM;
+    }
+    if (prec == WDR_F64)
+        launch_dslash<double>(g, sy, Links<double>{reinterpret_cast<UTab<double>>(t), U->su3}, HOPS_ALL, parity,
+                              dag, static_cast<const double2 *>(in), static_cast<const double2 *>(diag),
+                              static_cast<double2 *>(out), kappa, 0, g.nblk, S(stream));
+    else
+        launch_dslash<float>(g, sy, Links<float>{reinterpret_cast<UTab<float>>(t), U->su3}, HOPS_ALL, parity, dag,
+                             static_cast<const float2 *>(in), static_cast<const float2 *>(diag),
+                             static_cast<float2 *>(out), (float)kappa, 0, g.nblk, S(stream));
     return finish(S(stream));
 }
 

@@ -389,6 +389,36 @@ __global__ __launch_bounds__(VH4) void k_r16_from64(Geo g, const int32_t *__rest
     store_block(r, rv, rs, site, blk, nullptr, 0);
 }
 
+// the sites of parity par of an internal FP64 field (component-major) into
+// an E16 field with fresh scales, or back (the other parity's sites of the
+// FP64 field set to zero)
+__global__ __launch_bounds__(VH4) void k_e16_from64(Geo g, int par, const double2 *__restrict__ in,
+                                                    uint4 *__restrict__ ov, float *__restrict__ os)
+{
+    const int slot = blockIdx.x, m = blockIdx.y, t = threadIdx.x;
+    const long blk = (long)m * g.nblk + slot, e0 = blk * 12 * VB4 + par * VH4 + t;
+    cx<float> v[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const double2 d = in[e0 + c * VB4];
+        v[c] = mk<float>((float)d.x, (float)d.y);
+    }
+    store_block(v, ov, os, blk * VH4 + t, blk, nullptr, 0);
+}
+__global__ __launch_bounds__(VH4) void k_e16_to64(Geo g, int par, const uint4 *__restrict__ iv,
+                                                  const float *__restrict__ is, double2 *__restrict__ out)
+{
+    const int slot = blockIdx.x, m = blockIdx.y, t = threadIdx.x;
+    const long blk = (long)m * g.nblk + slot, e0 = blk * 12 * VB4 + t;
+    cx<float> v[12];
+    ld_site(g4(iv), blk * VH4 + t, is[blk], v);
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        out[e0 + c * VB4 + par * VH4] = make_double2((double)v[c].re, (double)v[c].im);
+        out[e0 + c * VB4 + (1 - par) * VH4] = make_double2(0.0, 0.0);
+    }
+}
+
 // E16 links from the internal FP64 links ([slot][mu][9][Vb], boundary phase
 // folded in), rounded through FP32 like every FP16 copy of the library
 __global__ __launch_bounds__(256) void k_pack_links_e16(long total, const double2 *__restrict__ u64,
@@ -448,6 +478,16 @@ void launch_eo16(const Geo &g, const Sys &sy, Links16 U, float fs, float fk, int
     else
         k_eo16<0><<<grid, VH4, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, fs, fk, par, g.sched[si], in.v, in.s,
                                        diag.v, diag.s, out.v, out.s, partial);
+}
+
+void launch_e16_from64(const Geo &g, int M, int par, const double2 *in, E16 out, hipStream_t s)
+{
+    k_e16_from64<<<dim3(g.nblk, M), VH4, 0, s>>>(g, par, in, out.v, out.s);
+}
+
+void launch_e16_to64(const Geo &g, int M, int par, E16c in, double2 *out, hipStream_t s)
+{
+    k_e16_to64<<<dim3(g.nblk, M), VH4, 0, s>>>(g, par, in.v, in.s, out);
 }
 
 void launch_xr16(const Geo &g, const Sys &sy, const double2 *sc, float2 *x, E16c w, E16c q, E16 r, double *partial,

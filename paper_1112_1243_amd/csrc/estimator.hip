@@ -48,6 +48,11 @@ void make_path_gauges(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, int N
                       hipStream_t s)
 {
     const size_t n = (size_t)c->g.V * 36;
+    // compulsory bytes: both fields read and every interior point written,
+    // the two end points copied, and the FP32 / FP16 copies of every point
+    const double lb = 36.0 * sizeof(double2), V = c->g.V;
+    add_traffic(V * ((2 + (N - 1)) * lb + 4 * lb +
+                     (N + 1) * (lb + lb / 2 + (pts[0]->has16 ? lb + 96 : 0) + (pts[0]->hase16 ? lb + 96 : 0))));
     (void)hipMemcpyAsync(pts[0]->u64.as<double2>(), U->u64, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
     (void)hipMemcpyAsync(pts[N]->u64.as<double2>(), Up->u64, n * sizeof(double2), hipMemcpyDeviceToDevice, s);
     std::vector<double> t;
@@ -65,8 +70,9 @@ void make_path_gauges(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, int N
     }
 }
 
-// device memory budget for the fields of one chunk of samples
-constexpr double CHUNK_BYTES = 48e9;
+// device memory budget for the fields of one chunk of samples (the 32
+// factors of a 32^4 estimate fit in one chunk)
+constexpr double CHUNK_BYTES = 96e9;
 
 }  // namespace
 
@@ -226,6 +232,20 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
             launch_g5<double>(g, all, W, W, s);
         }
         launch_sample_terms(g, all, E, Z, W, R, pr.as<double>(), s);
+        {
+            // compulsory bytes of this chunk's kernels outside the solvers
+            // (which count their own): the noise, the operator applications,
+            // differences, gamma_5 and clears, the sample sums
+            double lin = 0;
+            for (int mu = 0; mu < 4; ++mu) lin += (double)(g.B[mu] - 1) / g.B[mu];
+            const double V = g.V, sb = spin_b<double>(), lk = su3 ? 384.0 : 576.0;
+            const double D = V * (2 * sb + lk), Din = V * (2 * sb + lin * (su3 ? 96.0 : 144.0));
+            double b = V * sb + V * 3 * sb + V * 4 * sb;  // noise, r = y - X' z, sample sums
+            if (op == WDR_OP_FULL) b += 2 * D + 2 * V * 2 * sb;
+            else if (op == WDR_OP_BLOCKS) b += 2 * Din + 2 * V * 2 * sb;
+            else b += V * sb + Din / 2 + D + V * sb + 2 * V * 2 * sb;
+            add_traffic(M * b);
+        }
         WDR_HIP(hipMemcpyAsync(per.data(), pr.as<double>(), (size_t)g.nblk * M * sizeof(double), hipMemcpyDeviceToHost,
                                s));
         WDR_HIP(hipStreamSynchronize(s));

@@ -43,14 +43,16 @@ __global__ __launch_bounds__(NT) void k_to_h16(Geo g, const int32_t *__restrict_
     if (threadIdx.x == 0) scale[(long)m * g.nblk + slot] = s;
 }
 
-__global__ __launch_bounds__(NT) void k_from_h16(Geo g, const int32_t *__restrict__ active, long n, long total,
-                                                const h2 *__restrict__ in, const float *__restrict__ scale,
-                                                double2 *__restrict__ y, int add)
+// elements of the slots [slot0, slot0 + cnt / (12 Vb)) of every system
+__global__ __launch_bounds__(NT) void k_from_h16(Geo g, const int32_t *__restrict__ active, long n, long cnt,
+                                                int slot0, long total, const h2 *__restrict__ in,
+                                                const float *__restrict__ scale, double2 *__restrict__ y, int add)
 {
-    const long i = (long)blockIdx.x * NT + threadIdx.x;
-    if (i >= total) return;
-    const int m = (int)(i / n);
+    const long k = (long)blockIdx.x * NT + threadIdx.x;
+    if (k >= total) return;
+    const int m = (int)(k / cnt);
     if (active && !active[m]) return;
+    const long i = (long)m * n + 12L * g.Vb * slot0 + (k - (long)m * cnt);
     const int slot = (int)((i - (long)m * n) / (12L * g.Vb));
     const float s = scale[(long)m * g.nblk + slot];
     const h2 v = in[i];
@@ -193,10 +195,11 @@ void launch_to_h16(const Geo &g, const Sys &sy, const T2<T> *in, H16 out, int sl
     if (nslots <= 0 || sy.M <= 0) return;
     k_to_h16<T><<<dim3(nslots, sy.M), NT, 0, s>>>(g, sy.active, sy.n, slot0, in, out.v, out.s);
 }
-void launch_from_h16(const Geo &g, const Sys &sy, H16c in, double2 *y, int add, hipStream_t s)
+void launch_from_h16(const Geo &g, const Sys &sy, H16c in, double2 *y, int add, int slot0, int nslots, hipStream_t s)
 {
-    const long total = sy.n * sy.M;
-    if (total > 0) k_from_h16<<<nblocks(total), NT, 0, s>>>(g, sy.active, sy.n, total, in.v, in.s, y, add);
+    const long cnt = 12L * g.Vb * nslots, total = cnt * sy.M;
+    if (total > 0)
+        k_from_h16<<<nblocks(total), NT, 0, s>>>(g, sy.active, sy.n, cnt, slot0, total, in.v, in.s, y, add);
 }
 void launch_zero_h16(const Geo &g, const Sys &sy, H16 f, hipStream_t s)
 {

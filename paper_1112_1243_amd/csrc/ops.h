@@ -191,8 +191,9 @@ void launch_slot_norm2(const Geo &g, const Sys &sy, const double2 *a, double *ou
 // out = FP16 copy of in on the slots [slot0, slot0 + nslots) with fresh block scales
 template <typename T>
 void launch_to_h16(const Geo &g, const Sys &sy, const T2<T> *in, H16 out, int slot0, int nslots, hipStream_t s);
-// y (+)= in for every slot (add = 1: y += in)
-void launch_from_h16(const Geo &g, const Sys &sy, H16c in, double2 *y, int add, hipStream_t s);
+// y (+)= in on the slots [slot0, slot0 + nslots) (add = 1: y += in); other slots untouched
+void launch_from_h16(const Geo &g, const Sys &sy, H16c in, double2 *y, int add, int slot0, int nslots,
+                     hipStream_t s);
 // values 0, scales 1
 void launch_zero_h16(const Geo &g, const Sys &sy, H16 f, hipStream_t s);
 // FP16 copy of the first two rows of the internal FP64 links
@@ -238,6 +239,10 @@ void launch_r16_from32(const Geo &g, const Sys &sy, const float2 *bh, const floa
                        hipStream_t s);
 // r = r64 into FP16, bh = (float) r64, x = 0 (even sites)
 void launch_r16_from64(const Geo &g, const Sys &sy, const double2 *r64, float2 *bh, float2 *x, E16 r, hipStream_t s);
+// the sites of parity par of M internal FP64 fields into E16 (fresh scales),
+// and back (the other parity set to zero)
+void launch_e16_from64(const Geo &g, int M, int par, const double2 *in, E16 out, hipStream_t s);
+void launch_e16_to64(const Geo &g, int M, int par, E16c in, double2 *out, hipStream_t s);
 // out[m * ostride].x = sum of the G partial pairs of system m (fixed order)
 void launch_final(const Sys &sy, const double *partial, int G, double2 *out, int ostride, hipStream_t s);
 

@@ -38,8 +38,10 @@ struct wdr_ctx {
     wdr_ctx *twin = nullptr;
     // stream on which solver periods are captured into HIP graphs (created on first use)
     hipStream_t cap = nullptr;
-    // autotuned solver schedules, keyed by (ratio, solver, inner precision, kappa)
+    // autotuned solver schedules and launch forms (wdr_stencil, wdr_mr_form),
+    // keyed by (ratio, solver, inner and middle precision, kappa)
     std::map<std::string, wdr_solver_params> tuned;
+    std::map<std::string, std::pair<int, int>> tuned_forms;
 };
 
 struct wdr_gauge {
@@ -51,6 +53,10 @@ struct wdr_gauge {
     wdr::h2 *e16 = nullptr;  // the same in the even-odd CG's layout (SU(3) fields, 4^4 blocks)
     void **tab = nullptr;    // device table {u64, u32, u16, e16} for single-system launches
     int su3 = 0;             // every link is SU(3) to SU3_TOL (checked at upload)
+    // the same four pointers repeated for launches of several systems on this
+    // field: rep + k * rep_cap holds rep_cap copies of entry k of tab
+    void **rep = nullptr;
+    int rep_cap = 0;
 };
 
 // largest |U U^+ - 1| and |det U - 1| entry for which a gauge field counts as
@@ -90,6 +96,11 @@ inline wdr::H16 f16_field(const wdr_ctx *c, void *p)
     return wdr::H16{v, reinterpret_cast<float *>(v + (size_t)c->g.V * 12)};
 }
 
+// device table of nsys copies of entry k (0 u64, 1 u32, 2 u16, 3 e16) of the
+// gauge's pointers (grown, and the stream synchronised, when too short);
+// NULL if the allocation fails
+const void *const *replicated(wdr_gauge *g, int k, int nsys, hipStream_t s);
+
 // per-system gauge tables (device arrays of M pointers)
 struct GaugeTab {
     Links<double> u64;
@@ -103,6 +114,24 @@ inline GaugeTab view(const wdr_gauge *g)
             {reinterpret_cast<UTab<float>>(g->tab + 1), g->su3},
             {g->u16 ? reinterpret_cast<const h2 *const *>(g->tab + 2) : nullptr},
             {g->e16 ? reinterpret_cast<const h2 *const *>(g->tab + 3) : nullptr}};
+}
+
+// ---- algorithmic traffic: the compulsory device-memory bytes of the work
+// done (every operand of a kernel read or written once: spinors of the sites
+// a kernel covers, each link and each neighbour counted once), summed over
+// the process and read by wdr_traffic.  The drivers add their totals from
+// the exact work counts (iterations, updates, rounds) of every system, so
+// launches that skip converged systems add nothing.
+void add_traffic(double bytes);
+// bytes per lattice site: a spinor of precision T (24 reals), the two-row
+// links of a site (4 links x 12 reals), an FP16 half-field site (48 bytes)
+template <typename T> constexpr double spin_b() { return 24.0 * sizeof(T); }
+template <typename T> constexpr double link_b() { return 48.0 * sizeof(T); }
+// one even-odd half of the stencil over V sites (V / 2 outputs, V / 2
+// inputs, every link of the lattice), with or without a diagonal term
+template <typename T> constexpr double half_b(double V, bool diag)
+{
+    return V / 2 * (diag ? 3 : 2) * spin_b<T>() + V * link_b<T>();
 }
 
 struct Stats {

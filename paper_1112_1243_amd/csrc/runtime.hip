@@ -4,6 +4,8 @@
 #include <memory>
 #include <string>
 
+#include <atomic>
+
 #include "runtime.h"
 
 namespace wdr {
@@ -126,6 +128,36 @@ wdr_status check_params(const wdr_ctx *c, const wdr_solver_params &sp, bool need
 }  // namespace wdr
 
 using namespace wdr;
+
+namespace wdr {
+const void *const *replicated(wdr_gauge *g, int k, int nsys, hipStream_t s)
+{
+    if (nsys > g->rep_cap) {
+        int cap = 64;
+        while (cap < nsys) cap *= 2;
+        if (hipStreamSynchronize(s) != hipSuccess) return nullptr;  // launches may still read the old table
+        void **rep = nullptr;
+        if (hipMalloc(&rep, sizeof(void *) * 4 * cap) != hipSuccess) return nullptr;
+        std::vector<void *> h(4 * (size_t)cap);
+        void *src[4] = {g->u64, g->u32, g->u16, g->e16};
+        for (int j = 0; j < 4; ++j)
+            for (int m = 0; m < cap; ++m) h[(size_t)j * cap + m] = src[j];
+        if (hipMemcpy(rep, h.data(), sizeof(void *) * h.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(rep);
+            return nullptr;
+        }
+        if (g->rep) (void)hipFree(g->rep);
+        g->rep = rep;
+        g->rep_cap = cap;
+    }
+    return g->rep + (size_t)k * g->rep_cap;
+}
+}  // namespace wdr
+
+namespace wdr {
+static std::atomic<long long> g_traffic{0};
+void add_traffic(double bytes) { g_traffic.fetch_add((long long)bytes, std::memory_order_relaxed); }
+}  // namespace wdr
 
 extern "C" {
 
@@ -354,6 +386,11 @@ wdr_status wdr_ctx_destroy(wdr_ctx *c)
 }
 
 int64_t wdr_ctx_volume(const wdr_ctx *c) { return c ? c->g.V : 0; }
+
+int64_t wdr_traffic(int32_t reset)
+{
+    return reset ? (int64_t)g_traffic.exchange(0) : (int64_t)g_traffic.load();
+}
 int32_t wdr_ctx_nblocks(const wdr_ctx *c) { return c ? c->g.nblk : 0; }
 
 wdr_status wdr_ctx_set_stencil(wdr_ctx *c, int32_t choice)
@@ -451,6 +488,7 @@ wdr_status wdr_gauge_destroy(wdr_gauge *g)
     if (g->u32) (void)hipFree(g->u32);
     if (g->u16) (void)hipFree(g->u16);
     if (g->e16) (void)hipFree(g->e16);
+    if (g->rep) (void)hipFree(g->rep);
     if (g->tab) (void)hipFree(g->tab);
     delete g;
     return WDR_OK;

@@ -75,10 +75,11 @@ __global__ void k_cgm_beta(int M, double2 *sc, double delta2, int max_iter, cons
 // after the FP64 true residual of the updated systems: retire converged ones,
 // restart the reference of the others from the true residual
 __global__ void k_cgm_update(int M, double2 *sc, const double *bn2, double tol2, int max_iter, const int32_t *its,
-                             int32_t *alive, int32_t *upd, double *rmax)
+                             int32_t *alive, int32_t *upd, double *rmax, int32_t *nupd)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M || !upd[m]) return;
+    ++nupd[m];
     const double r = sc[8L * m + 5].x;
     if (!isfinite(r) || r <= tol2 * bn2[m] || its[m] >= max_iter) alive[m] = 0;
     sc[8L * m] = make_double2(r, 0.0);
@@ -360,7 +361,7 @@ wdr_status sap64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, con
             if (!launch_mr_h16(0, g, sy, U.u16, eh.cf(), xh.f(), (float)kappa, sp.mr_steps, b0, bn, s) ||
                 !launch_mr_h16(0, g, sy, U.u16, eh.cf(), xh.f(), (float)kappa, sp.mr_steps, w0, wn, s))
                 return need16(GaugeTab{});
-        launch_from_h16(g, sy, xh.cf(), out, 0, s);
+        launch_from_h16(g, sy, xh.cf(), out, 0, 0, g.nblk, s);
         return WDR_OK;
     }
     Work e(c, field_bytes(c, WDR_F32) * sy.M), x(c, field_bytes(c, WDR_F32) * sy.M);
@@ -589,7 +590,7 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     const size_t fb = field_bytes(c, WDR_F64) * M, fbT = field_bytes(c, prec) * M;
     Work bhw(c, fb), r64w(c, fb), t64w(c, fb), o64w(c, fb), rw(c, fbT), pw(c, fbT), ww(c, fbT), qw(c, fbT),
         ew(c, fbT), tw(c, fbT), scal(c, sizeof(double2) * 8 * M), red(c, sizeof(double) * red_scratch(M)),
-        ctl(c, 2 * sizeof(double) * M + 3 * sizeof(int32_t) * M), lw(c, sizeof(int32_t) * M);
+        ctl(c, 2 * sizeof(double) * M + 4 * sizeof(int32_t) * M), lw(c, sizeof(int32_t) * M);
     FlagPoll poll(c, M);
     if (!bhw.ok() || !r64w.ok() || !t64w.ok() || !o64w.ok() || !rw.ok() || !pw.ok() || !ww.ok() || !qw.ok() ||
         !ew.ok() || !tw.ok() || !scal.ok() || !red.ok() || !ctl.ok() || !lw.ok() || !poll.ok)
@@ -599,7 +600,7 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
           *e = ew.as<T2<T>>(), *t = tw.as<T2<T>>();
     double2 *sc = scal.as<double2>();
     double *bn2 = ctl.as<double>(), *rmax = bn2 + M;
-    int32_t *alive = reinterpret_cast<int32_t *>(rmax + M), *upd = alive + M, *its = upd + M;
+    int32_t *alive = reinterpret_cast<int32_t *>(rmax + M), *upd = alive + M, *its = upd + M, *nupd = its + M;
     const auto &g = c->g;
     const Links<T> UT = links_of<T>(U);
     Links<double> U64n = U.u64;
@@ -628,6 +629,7 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     launch_zero<T>(qv, total, s);
     launch_norm2<T>(sa, r, red.as<double>(), sc, 8, s);
     k_cgm_rmax<<<nbm, 64, 0, s>>>(M, sc, rmax);
+    k_cgm_clear<<<nbm, 64, 0, s>>>(M, nupd);
     // one period: ue steps, then the reliable update of the flagged systems
     const int ue = sp.update_every;
     auto period = [&](hipStream_t q) {
@@ -646,7 +648,7 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
         launch_add_to64<T>(su, e, x, q);
         apply_dhat<double>(g, su, U.u64, kappa, 0, x, o64, t64, q);
         launch_sub_norm(su, bh, t64, r64, red.as<double>(), sc + 5, 8, q);
-        k_cgm_update<<<nbm, 64, 0, q>>>(M, sc, bn2, tol * tol, sp.max_iter, its, alive, upd, rmax);
+        k_cgm_update<<<nbm, 64, 0, q>>>(M, sc, bn2, tol * tol, sp.max_iter, its, alive, upd, rmax, nupd);
         k_cgm_refresh<T><<<nb256(tl), 256, 0, q>>>(su.list, n, su.hs, tl, upd, r64, r, e);
         k_cgm_clear<<<nbm, 64, 0, q>>>(M, upd);
     };
@@ -691,19 +693,34 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     launch_add_to64<double>(all, t64, x, s);
 
     std::vector<double> hbn2(M), rn2;
-    std::vector<int32_t> hits(M);
+    std::vector<int32_t> hits(M), hupd(M);
     WDR_HIP(hipMemcpyAsync(hbn2.data(), bn2, sizeof(double) * M, hipMemcpyDeviceToHost, s));
     WDR_HIP(hipMemcpyAsync(hits.data(), its, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+    WDR_HIP(hipMemcpyAsync(hupd.data(), nupd, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
     read_x(sc + 5, M, 8, rn2, s);
     st.assign(M, Stats());
     bool ok = true;
+    // compulsory bytes per system: setup and final step, then per CG step
+    // (four halves in T, |w|^2, the x / r update, the p update) and per
+    // reliable update (e into x, FP64 Dhat x, r64 = bh - Dhat x, the refresh)
+    const double V = g.V, H = V / 2;
+    const double setup = 3 * V * spin_b<double>() + half_b<double>(V, true) + V * spin_b<double>() +
+                         V * (spin_b<double>() + spin_b<T>()) + 2 * V * spin_b<T>() + 3 * V * spin_b<T>() +
+                         H * spin_b<T>() + V * spin_b<double>() + half_b<double>(V, true) + 3 * V * spin_b<double>();
+    const double step = 2 * half_b<T>(V, false) + 2 * half_b<T>(V, true) + H * spin_b<T>() + 6 * H * spin_b<T>() +
+                        3 * H * spin_b<T>();
+    const double update = H * (spin_b<T>() + 2 * spin_b<double>()) + half_b<double>(V, false) +
+                          half_b<double>(V, true) + 3 * H * spin_b<double>() + H * (spin_b<double>() + 2 * spin_b<T>());
+    double bytes = 0;
     for (int m = 0; m < M; ++m) {
+        bytes += setup + hits[m] * step + hupd[m] * update;
         st[m].iters = hits[m];
         st[m].total = hits[m];
         st[m].rel = hbn2[m] > 0 ? std::sqrt(rn2[m] / hbn2[m]) : 0.0;
         st[m].converged = st[m].rel <= tol;
         ok = ok && st[m].converged;
     }
+    add_traffic(bytes);
     WDR_HIP(hipGetLastError());
     if (!ok) {
         const Stats sm = summarize(st);
@@ -721,10 +738,11 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
 // ask for the outer update when it fell by OUTER_DELTA below the middle
 // system's right-hand side, reached the tolerance, or at the iteration limit
 __global__ void k_c16_mid(int M, double2 *sc, const double *bn2, const double *b32n2, double tol2, double delta2,
-                          int max_iter, const int32_t *its, int32_t *upd, int32_t *upd64, double *rmax)
+                          int max_iter, const int32_t *its, int32_t *upd, int32_t *upd64, double *rmax, int32_t *nmid)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M || !upd[m]) return;
+    ++nmid[m];
     const double r = sc[8L * m + 6].x;
     sc[8L * m] = make_double2(r, 0.0);
     rmax[m] = r;
@@ -742,10 +760,11 @@ __global__ void k_c16_promote(int M, int32_t *upd, int32_t *upd64)
 // after the FP64 true residual: retire converged systems, else restart the
 // middle system (right-hand side = that residual) and the iterated residual
 __global__ void k_c16_outer(int M, double2 *sc, const double *bn2, double *b32n2, double tol2, int max_iter,
-                            const int32_t *its, int32_t *alive, int32_t *upd64, double *rmax)
+                            const int32_t *its, int32_t *alive, int32_t *upd64, double *rmax, int32_t *nout)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M || !upd64[m]) return;
+    ++nout[m];
     const double r = sc[8L * m + 5].x;
     if (!isfinite(r) || r <= tol2 * bn2[m] || its[m] >= max_iter) alive[m] = 0;
     sc[8L * m] = make_double2(r, 0.0);
@@ -788,7 +807,7 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     Work bhw(c, fb), r64w(c, fb), t64w(c, fb), o64w(c, fb), x32w(c, f32), b32w(c, f32), d32w(c, f32), t32w(c, f32),
         pw(c, fe), ww(c, fe), qw(c, fe), rw(c, fe), tw(c, fe), scal(c, sizeof(double2) * 8 * M),
         red(c, sizeof(double) * std::max<long>(red_scratch(M), 2L * g.nblk * M)),
-        ctl(c, 3 * sizeof(double) * M + 4 * sizeof(int32_t) * M), lw(c, sizeof(int32_t) * M);
+        ctl(c, 3 * sizeof(double) * M + 6 * sizeof(int32_t) * M), lw(c, sizeof(int32_t) * M);
     FlagPoll poll(c, M);
     if (!bhw.ok() || !r64w.ok() || !t64w.ok() || !o64w.ok() || !x32w.ok() || !b32w.ok() || !d32w.ok() || !t32w.ok() ||
         !pw.ok() || !ww.ok() || !qw.ok() || !rw.ok() || !tw.ok() || !scal.ok() || !red.ok() || !ctl.ok() ||
@@ -803,6 +822,7 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     double *part = red.as<double>();
     double *bn2 = ctl.as<double>(), *rmax = bn2 + M, *b32n2 = rmax + M;
     int32_t *alive = reinterpret_cast<int32_t *>(b32n2 + M), *upd = alive + M, *upd64 = upd + M, *its = upd64 + M;
+    int32_t *nmid = its + M, *nout = nmid + M;  // middle and outer updates per system
     const Links<double> U64 = U.u64;
     Links<double> U64n = U.u64;
     U64n.kneg = 1;
@@ -831,6 +851,8 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     k_cgm_rmax<<<nbm, 64, 0, s>>>(M, sc, rmax);
     k_cgm_rmax<<<nbm, 64, 0, s>>>(M, sc, b32n2);
     k_c16_clear<<<nbm, 64, 0, s>>>(M, upd64);
+    k_c16_clear<<<nbm, 64, 0, s>>>(M, nmid);
+    k_c16_clear<<<nbm, 64, 0, s>>>(M, nout);
     const E16c none{nullptr, nullptr};
     const int ue = sp.update_every;
     auto period = [&](hipStream_t q) {
@@ -853,7 +875,7 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
             launch_r16_from32(g, su, b32, d32, R, part, q);
             launch_final(su, part, G, sc + 6, 8, q);
             k_c16_mid<<<nbm, 64, 0, q>>>(M, sc, bn2, b32n2, tol * tol, OUTER_DELTA * OUTER_DELTA, sp.max_iter, its,
-                                         upd, upd64, rmax);
+                                         upd, upd64, rmax, nmid);
         } else {
             k_c16_promote<<<nbm, 64, 0, q>>>(M, upd, upd64);
         }
@@ -861,7 +883,7 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
         launch_add_to64<float>(s64, x32, x, q);
         apply_dhat<double>(g, s64, U64, kappa, 0, x, o64, t64, q);
         launch_sub_norm(s64, bh, t64, r64, red.as<double>(), sc + 5, 8, q);
-        k_c16_outer<<<nbm, 64, 0, q>>>(M, sc, bn2, b32n2, tol * tol, sp.max_iter, its, alive, upd64, rmax);
+        k_c16_outer<<<nbm, 64, 0, q>>>(M, sc, bn2, b32n2, tol * tol, sp.max_iter, its, alive, upd64, rmax, nout);
         launch_r16_from64(g, s64, r64, b32, x32, R, q);
         k_c16_clear<<<nbm, 64, 0, q>>>(M, upd64);
     };
@@ -901,19 +923,37 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     launch_add_to64<double>(all, t64, x, s);
 
     std::vector<double> hbn2(M), rn2;
-    std::vector<int32_t> hits(M);
+    std::vector<int32_t> hits(M), hmid(M), hout(M);
     WDR_HIP(hipMemcpyAsync(hbn2.data(), bn2, sizeof(double) * M, hipMemcpyDeviceToHost, s));
     WDR_HIP(hipMemcpyAsync(hits.data(), its, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+    WDR_HIP(hipMemcpyAsync(hmid.data(), nmid, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+    WDR_HIP(hipMemcpyAsync(hout.data(), nout, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
     read_x(sc + 5, M, 8, rn2, s);
     st.assign(M, Stats());
     bool ok = true;
+    // compulsory bytes per system (V sites): setup and final step, then per
+    // CG step (four FP16 halves, the x / r update, the p update), per middle
+    // update (FP32 Dhat x32, the residual into FP16) and per outer update
+    // (x += x32, FP64 Dhat x, r64 = bh - Dhat x, the restart)
+    const double V = g.V, H = V / 2;
+    const double setup = 3 * V * spin_b<double>() + half_b<double>(V, true) + V * spin_b<double>() +
+                         V * spin_b<float>() + H * spin_b<double>() + H * (spin_b<double>() + 2 * spin_b<float>() + 48) +
+                         H * 96 + V * spin_b<double>() + half_b<double>(V, true) + 3 * V * spin_b<double>();
+    const double half16 = H * 96 + V * 96, step = 4 * half16 + 2 * H * 48 + H * 384 + H * 144;
+    const double mid = half_b<float>(V, false) + half_b<float>(V, true) + H * (2 * spin_b<float>() + 48);
+    const double outer = H * (spin_b<float>() + 2 * spin_b<double>()) + half_b<double>(V, false) +
+                         half_b<double>(V, true) + 3 * H * spin_b<double>() +
+                         H * (spin_b<double>() + 2 * spin_b<float>() + 48);
+    double bytes = 0;
     for (int m = 0; m < M; ++m) {
+        bytes += setup + hits[m] * step + hmid[m] * mid + hout[m] * outer;
         st[m].iters = hits[m];
         st[m].total = hits[m];
         st[m].rel = hbn2[m] > 0 ? std::sqrt(rn2[m] / hbn2[m]) : 0.0;
         st[m].converged = st[m].rel <= tol;
         ok = ok && st[m].converged;
     }
+    add_traffic(bytes);
     WDR_HIP(hipGetLastError());
     if (!ok) {
         const Stats sm = summarize(st);
@@ -974,6 +1014,7 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
         if (!r16->ok() || !d16->ok()) return WDR_ENOMEM;
         launch_zero_h16(g, all, d16->f(), s);
     }
+    bool fused = true;
     for (int round = 0; round < 40; ++round) {
         if (sp.inner == WDR_F64) {
             launch_block_mr<double>(g, sa, U.u64, r, d64.as<double2>(), kappa, nmr, slot0, ns, s);
@@ -982,7 +1023,7 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
             launch_to_h16<double>(g, sa, r, r16->f(), slot0, ns, s);
             if (!launch_mr_h16(1, g, sa, U.u16, r16->cf(), d16->f(), (float)kappa, nmr, slot0, ns, s))
                 return need16(GaugeTab{});
-            launch_from_h16(g, sa, d16->cf(), x, 1, s);
+            launch_from_h16(g, sa, d16->cf(), x, 1, slot0, ns, s);
         } else {
             launch_convert<float, double>(sa, r, r32.as<float2>(), s);
             launch_block_mr<float>(g, sa, U.u32, r32.as<float2>(), d32.as<float2>(), (float)kappa, nmr, slot0, ns, s);
@@ -990,7 +1031,7 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
         }
         // r = b - D_b x and its norm per block on the selected blocks (r stays
         // zero elsewhere: nothing below writes other blocks of r)
-        const bool fused = launch_block_residual(g, sa, U.u64, x, b, r, kappa, slot0, ns, s);
+        fused = launch_block_residual(g, sa, U.u64, x, b, r, kappa, slot0, ns, s);
         if (!fused) launch_dslash<double>(g, sa, U.u64, HOPS_IN, -1, 0, x, x, t, kappa, slot0, ns, s);
         launch_block_resid_norm(g, sa, b, fused ? nullptr : t, r, rn, slot0, ns, s);
         k_block_check<<<M, BC_NT, 0, s>>>(g.nblk, slot0, ns, bn, rn, tol * tol, alive, its, worst);
@@ -1005,13 +1046,33 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
     WDR_HIP(hipStreamSynchronize(s));
     bool ok = true;
     st.assign(M, Stats());
+    // compulsory bytes per system: setup, then per round the block MR (its
+    // right-hand side, result and in-block links) with its conversions, the
+    // FP64 residual b - D_b x on the selected blocks and its norm
+    const double V = g.V, Vs = (double)ns * g.Vb;
+    double lin = 0;  // in-block links per site
+    for (int mu = 0; mu < 4; ++mu) lin += (double)(g.B[mu] - 1) / g.B[mu];
+    const double ps = sp.inner == WDR_F64 ? spin_b<double>() : sp.inner == WDR_F32 ? spin_b<float>() : 48.0;
+    const double pl = sp.inner == WDR_F64 ? 96.0 : sp.inner == WDR_F32 ? 48.0 : 24.0;  // one two-row link
+    double setup = V * (4 * spin_b<double>()) + Vs * spin_b<double>();
+    setup += sp.inner == WDR_F16 ? V * 48 : V * ps;
+    double round_b = Vs * (2 * ps + lin * pl);
+    if (sp.inner == WDR_F16)
+        round_b += Vs * (spin_b<double>() + 48) + Vs * (48 + 2 * spin_b<double>());
+    else
+        round_b += V * (ps + spin_b<double>()) * (sp.inner == WDR_F32 ? 1 : 0) + V * (ps + 2 * spin_b<double>());
+    round_b += fused ? Vs * (4 * spin_b<double>() + lin * 96.0)
+                     : Vs * (2 * spin_b<double>() + lin * 96.0) + Vs * 3 * spin_b<double>();
+    double bytes = 0;
     for (int m = 0; m < M; ++m) {
+        bytes += setup + hits[m] * round_b;
         st[m].iters = hits[m];
         st[m].total = hits[m];
         st[m].rel = std::sqrt(hworst[m]);
         st[m].converged = st[m].rel <= tol;
         ok = ok && st[m].converged;
     }
+    add_traffic(bytes);
     WDR_HIP(hipGetLastError());
     if (!ok) {
         set_error("block solve stopped at relative residual " + std::to_string(summarize(st).rel));
@@ -1058,6 +1119,16 @@ wdr_status schur64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr
     // out = in - t2 on black, zero on white
     launch_sub(all, in, t2.as<double2>(), out, s);
     launch_keep_slots(g, all, out, b0, bn, s);
+    // compulsory bytes of the kernels above (the block solves count their own):
+    // two clears, two cross-block hops onto one colour (its sites, the
+    // neighbours across the faces, the crossing links), the difference, the clear
+    double face = 1, cross = 0;
+    for (int mu = 0; mu < 4; ++mu) {
+        face *= g.B[mu] > 2 ? (double)(g.B[mu] - 2) / g.B[mu] : 0.0;
+        cross += 2.0 / g.B[mu];
+    }
+    const double V = g.V, sb = spin_b<double>();
+    add_traffic(M * (2 * V * sb + 2 * (V / 2) * (sb + (1 - face) * sb + cross * 96.0) + V * 3 * sb + V * sb));
     return e;
 }
 

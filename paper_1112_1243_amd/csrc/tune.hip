@@ -1,8 +1,9 @@
 // Schedule autotuner: the depth of the Schwarz preconditioner (cycles x MR
 // steps per block) and of the block-solve rounds decide how the work of a
-// solve is cut into block launches; every choice solves to the same
-// tolerances, so the fastest one is picked by timing a short estimate on
-// the caller's data and cached in the context.
+// solve is cut into block launches, and the launch forms (stencil kernel of
+// D and D_b, block-MR form) how blocks map onto the CUs; every choice solves
+// to the same tolerances, so the fastest one is picked by timing a short
+// estimate on the caller's data and cached in the context.
 #include <chrono>
 #include <cmath>
 #include <algorithm>
@@ -64,15 +65,25 @@ wdr_status wdr_autotune(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, dou
     if (e != WDR_OK) return e;
     WDR_HIP(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
-    char key[96];
-    std::snprintf(key, sizeof(key), "op%d solver%d inner%d kappa%.9g", (int)p->op, (int)p->sp.solver,
-                  (int)p->sp.inner, kappa);
+    char key[112];
+    std::snprintf(key, sizeof(key), "op%d solver%d inner%d middle%d kappa%.9g", (int)p->op, (int)p->sp.solver,
+                  (int)p->sp.inner, (int)p->sp.middle, kappa);
     double best_t = INFINITY;
+    auto set_forms = [&](int stencil, int mr) {
+        c->g.stencil = stencil;
+        c->g.mr_form = mr;
+        if (c->twin) {
+            c->twin->g.stencil = stencil;
+            c->twin->g.mr_form = mr;
+        }
+    };
     auto hit = c->tuned.find(key);
     if (hit != c->tuned.end()) {
         p->sp.sap_cycles = hit->second.sap_cycles;
         p->sp.mr_steps = hit->second.mr_steps;
         p->sp.block_mr_steps = hit->second.block_mr_steps;
+        const auto &f = c->tuned_forms[key];
+        set_forms(f.first, f.second);
     } else {
         wdr_est_params q = *p;
         // up to 8 path factors: the systems per launch set the balance
@@ -96,7 +107,7 @@ wdr_status wdr_autotune(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, dou
             }
         }
         if (p->op != WDR_OP_FULL) {
-            static const int bmr[] = {6, 8, 12, 16, 24, 32};
+            static const int bmr[] = {6, 8, 12, 16, 24, 32, 48, 64};
             const wdr_solver_params base = best;
             for (int b : bmr) {
                 q.sp = base;
@@ -108,6 +119,30 @@ wdr_status wdr_autotune(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, dou
                 }
             }
         }
+        // launch forms, one at a time from the context's current choice
+        int st0 = c->g.stencil, mr0 = c->g.mr_form;
+        q.sp = best;
+        if (!std::isfinite(best_t)) best_t = trial(c, U, Up, kappa, q, s);
+        if (p->op != WDR_OP_FULL)
+            for (int mr : {WDR_MR_AUTO, WDR_MR_ONE_PER_CU, WDR_MR_TWO_PER_CU}) {
+                if (mr == mr0) continue;
+                set_forms(st0, mr);
+                const double t = trial(c, U, Up, kappa, q, s);
+                if (t < best_t) {
+                    best_t = t;
+                    mr0 = mr;
+                }
+            }
+        for (int sc : {WDR_STENCIL_AUTO, WDR_STENCIL_DIR, WDR_STENCIL_BLK}) {
+            if (sc == st0) continue;
+            set_forms(sc, mr0);
+            const double t = trial(c, U, Up, kappa, q, s);
+            if (t < best_t) {
+                best_t = t;
+                st0 = sc;
+            }
+        }
+        set_forms(st0, mr0);
         if (!std::isfinite(best_t)) {
             set_error("no candidate schedule converged");
             return WDR_ENOCONV;
@@ -116,6 +151,7 @@ wdr_status wdr_autotune(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, dou
         p->sp.mr_steps = best.mr_steps;
         p->sp.block_mr_steps = best.block_mr_steps;
         c->tuned[key] = p->sp;
+        c->tuned_forms[key] = {st0, mr0};
     }
     if (host_seconds) *host_seconds = best_t;
     WDR_HIP(hipGetLastError());

@@ -84,8 +84,9 @@ def spinor(L, seed: int, tag: int = 7) -> np.ndarray:
 # Solver settings (fields of wdr_solver_params, by name) of the mixed-precision
 # form of the large-lattice workloads: CG on the normal equations (their kappa
 # lies above the free-field critical value, where the Schwarz-preconditioned
-# GCR stalls) with FP16 inner precision under FP64 reliable updates.
-LARGE_MIXED = dict(solver=1, inner=2, middle=0, max_iter=20000)
+# GCR stalls) with FP16 inner iterations, an FP32 middle level and FP64 outer
+# reliable updates; FP16 block solves.
+LARGE_MIXED = dict(solver=1, inner=2, middle=1, max_iter=20000)
 
 # Workloads: lattice, blocks, kappa, link scale, noise and solver settings of
 # the standard cases.  "seed" keys the Philox streams above.

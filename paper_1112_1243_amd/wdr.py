@@ -97,6 +97,8 @@ def lib():
         L.wdr_ctx_nblocks.restype = ctypes.c_int32
         L.wdr_ctx_set_stencil.argtypes = [P, i32]
         L.wdr_ctx_set_mr_form.argtypes = [P, i32]
+        L.wdr_traffic.argtypes = [i32]
+        L.wdr_traffic.restype = ctypes.c_int64
         L.wdr_site_maps.argtypes = [P, P, P, P, P, P]
         L.wdr_active_links.argtypes = [P, i32, i32, P, P]
         L.wdr_gauge_create.argtypes = [P, P, ctypes.POINTER(P), P]
@@ -110,6 +112,11 @@ def lib():
         L.wdr_pack.argtypes = [P, ctypes.c_int, P, P, P]
         L.wdr_unpack.argtypes = [P, ctypes.c_int, P, P, P]
         L.wdr_apply_D_internal.argtypes = [P, P, d, ctypes.c_int, P, P, P]
+        L.wdr_eo16_field_bytes.argtypes = [P]
+        L.wdr_eo16_field_bytes.restype = ctypes.c_int64
+        L.wdr_pack_eo16.argtypes = [P, i32, P, P, P]
+        L.wdr_unpack_eo16.argtypes = [P, i32, P, P, P]
+        L.wdr_apply_hop_eo_internal.argtypes = [P, P, d, ctypes.c_int, i32, i32, i32, P, P, P, P]
         for f in ("wdr_apply_D",):
             getattr(L, f).argtypes = [P, P, d, ctypes.c_int, P, P, P]
         for f in ("wdr_apply_Dblock", "wdr_apply_Dhop", "wdr_apply_Dee"):
@@ -147,6 +154,11 @@ def _check(status: int, allow=(OK,)):
     if status not in allow:
         raise WdrError(status, lib().wdr_last_error().decode())
     return status
+
+
+def traffic(reset: bool = False) -> int:
+    """Compulsory device-memory bytes of the estimates since the last reset."""
+    return int(lib().wdr_traffic(int(reset)))
 
 
 def default_params(**kw) -> SolverParams:
@@ -293,6 +305,36 @@ class Context:
         _check(lib().wdr_unpack(self.handle, prec, ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                 _stream()))
         return out
+
+    def eo16_field(self, nsys: int = 1):
+        """Flat byte tensor for nsys half fields in the FP16 layout of the
+        even-odd CG."""
+        torch = _torch()
+        n = int(lib().wdr_eo16_field_bytes(self.handle))
+        if n <= 0:
+            raise WdrError(EINVAL, "FP16 half fields need 4^4 blocks in a 2-colourable checkerboard")
+        return self._empty(n * nsys, dtype=torch.uint8)
+
+    def pack_eo16(self, psi, parity: int):
+        out = self.eo16_field()
+        _check(lib().wdr_pack_eo16(self.handle, parity, _dev(psi, (self.V, 4, 3)), ctypes.c_void_p(out.data_ptr()),
+                                   _stream()))
+        return out
+
+    def unpack_eo16(self, f, parity: int):
+        out = self.spinor_like()
+        _check(lib().wdr_unpack_eo16(self.handle, parity, ctypes.c_void_p(f.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def apply_hop_eo_internal(self, gauge, kappa, prec, parity, dag, fin, fdiag, fout, nsys: int = 1):
+        """out = diag - kappa H_{parity, 1-parity} in (gamma_5-conjugated for dag) on
+        internal fields of nsys systems: one kernel launch."""
+        _check(lib().wdr_apply_hop_eo_internal(self.handle, gauge.handle, kappa, prec, parity, dag, nsys,
+                                               ctypes.c_void_p(fin.data_ptr()),
+                                               None if fdiag is None else ctypes.c_void_p(fdiag.data_ptr()),
+                                               ctypes.c_void_p(fout.data_ptr()), _stream()))
+        return fout
 
     def apply_D_internal(self, gauge, kappa, fin, fout, prec=F64):
         _check(lib().wdr_apply_D_internal(self.handle, gauge.handle, kappa, prec, ctypes.c_void_p(fin.data_ptr()),

@@ -175,3 +175,149 @@ def test_f16_errors():
     del gs, gN, gU
     small.close()
     ctx.close()
+
+
+def f16_half(lat, psi, parity):
+    """The FP16 half-field rule of the even-odd CG: per block, the sites of
+    one parity, s = 2^ceil(log2 m) over their components; returns the
+    rounded field (other parity zero) as complex128."""
+    perm = oracle.block_order(lat)
+    Vb = int(np.prod(lat.B))
+    nb, Vh = lat.V // Vb, Vb // 2
+    sites = perm.reshape(nb, Vb)[:, parity * Vh:(parity + 1) * Vh]
+    blk = psi[sites].reshape(nb, Vh * 12)
+    re, im = blk.real.astype(np.float32), blk.imag.astype(np.float32)
+    m = np.maximum(np.abs(re).max(axis=1), np.abs(im).max(axis=1))
+    s = _pow2_at_least(m)
+    inv = (np.float32(1.0) / s)[:, None]
+    hr, hi = _round16(re, inv), _round16(im, inv)
+    q = (hr.astype(np.float32) * s[:, None]).astype(np.float64) + 1j * (hi.astype(np.float32) * s[:, None]).astype(
+        np.float64)
+    out = np.zeros_like(psi)
+    out[sites.ravel()] = q.reshape(nb * Vh, 4, 3)
+    return out
+
+
+def _half_block_max(lat, f, parity):
+    perm = oracle.block_order(lat)
+    Vb = int(np.prod(lat.B))
+    sites = perm.reshape(lat.V // Vb, Vb)[:, parity * (Vb // 2):(parity + 1) * (Vb // 2)]
+    return np.abs(np.concatenate([f.real, f.imag], axis=-1))[sites].reshape(sites.shape[0], -1).max(axis=1), sites
+
+
+EO_CASES = [((8, 8, 8, 8), (1, 1, 1, -1)), ((8, 16, 8, 8), (1, -1, 1, 1)), ((8, 8, 8, 8), (0, 0, 0, 0))]
+
+
+@pytest.mark.parametrize("L,bc", EO_CASES)
+def test_eo16_pack_bit_exact(L, bc):
+    """FP16 half fields of the even-odd CG: packing each parity follows the
+    per-block rule bit for bit, the other parity unpacks to zero."""
+    wdr = _wdr()
+    B = (4, 4, 4, 4)
+    ctx, lat = wdr.Context(L, B, bc), oracle.Lattice(L, B, bc)
+    psi = synth.spinor(L, 1611) * 2.3
+    _, _, par = lat.maps()
+    for p in (0, 1):
+        got = host(ctx.unpack_eo16(ctx.pack_eo16(dev(psi), p), p))
+        want = f16_half(lat, psi, p)
+        say("eo16 pack parity", p, "rel", rel(got, psi * (par == p)[:, None, None]))
+        assert np.array_equal(got, want)
+        assert not np.any(got[par != p])
+    ctx.close()
+
+
+@pytest.mark.parametrize("L,bc", EO_CASES)
+@pytest.mark.parametrize("parity,dag,with_diag", [(0, 0, True), (1, 0, False), (0, 1, False), (1, 1, True)])
+def test_eo16_stencil(L, bc, parity, dag, with_diag):
+    """One even-odd half in FP16 (the kernel of the FP16 CG): out = diag -
+    kappa H_{p,1-p} in (gamma_5-conjugated for dag) against the FP64 oracle
+    on the rounded input, diagonal and links: the difference stays within the
+    rounding of the output (2^-11 of each block half's maximum) plus FP32
+    arithmetic; and within 4e-3 of the exact operator."""
+    wdr = _wdr()
+    B = (4, 4, 4, 4)
+    ctx, lat = wdr.Context(L, B, bc), oracle.Lattice(L, B, bc)
+    U = synth.gauge_field(L, 0.5, 1612)
+    gU = ctx.gauge(dev(U))
+    k = 0.152
+    psi, dg = synth.spinor(L, 1613), synth.spinor(L, 1614)
+    _, _, par = lat.maps()
+    fin = ctx.pack_eo16(dev(psi), 1 - parity)
+    fdg = ctx.pack_eo16(dev(dg), parity) if with_diag else None
+    out = ctx.apply_hop_eo_internal(gU, k, wdr.F16, parity, dag, fin, fdg, ctx.eo16_field())
+    got = host(ctx.unpack_eo16(out, parity))
+
+    def expected(links, src, diag):
+        # with src on parity 1-p only, (D src) on parity p is -kappa H_{p,1-p} src
+        s = oracle.g5(src) if dag else src
+        h = oracle.apply_D(lat, links, k, s)
+        if dag:
+            h = oracle.g5(h)
+        h[par != parity] = 0
+        return h + (diag if diag is not None else 0)
+
+    q = f16_half(lat, psi, 1 - parity)
+    qd = f16_half(lat, dg, parity) if with_diag else None
+    want = expected(f16_links(U), q, qd)
+    bm, sites = _half_block_max(lat, want, parity)
+    d = got - want
+    err = np.abs(np.concatenate([d.real, d.imag], axis=-1))[sites].reshape(sites.shape[0], -1).max(axis=1)
+    bound = 2.0 ** -11 * bm * (1 + 1e-5) + 4e-6 * np.abs(want).max()
+    exact = expected(U, psi * (par == 1 - parity)[:, None, None], dg * (par == parity)[:, None, None]
+                     if with_diag else None)
+    say("eo16 p", parity, "dag", dag, "diag", with_diag, "max err / bound", float((err / bound).max()),
+        "rel vs exact", rel(got, exact))
+    assert not np.any(got[par != parity])
+    assert np.all(err <= bound)
+    assert rel(got, exact) < 4e-3
+    # several systems in one launch give each system's result
+    # two systems: all values first, then all block scales
+    vals, nsc = fin.numel() - ctx.nblocks * 4, ctx.nblocks * 4
+
+    def twice(f):
+        f2 = ctx.eo16_field(2)
+        f2[:vals] = f[:vals]
+        f2[vals:2 * vals] = f[:vals]
+        f2[2 * vals:2 * vals + nsc] = f[vals:]
+        f2[2 * vals + nsc:] = f[vals:]
+        return f2
+    f2 = twice(fin)
+    d2 = twice(fdg) if with_diag else None
+    o2 = ctx.apply_hop_eo_internal(gU, k, wdr.F16, parity, dag, f2, d2, ctx.eo16_field(2), nsys=2)
+    torch = torch_cuda()
+    assert torch.equal(o2[:vals], out[:vals]) and torch.equal(o2[vals:2 * vals], out[:vals])
+    assert torch.equal(o2[2 * vals:2 * vals + ctx.nblocks * 4], out[vals:])
+    assert torch.equal(o2[2 * vals + ctx.nblocks * 4:], out[vals:])
+    del gU
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_eo_halves_internal(prec):
+    """The FP64 and FP32 even-odd halves on internal fields (one launch each)
+    against the oracle, with and without the diagonal term and gamma_5."""
+    wdr = _wdr()
+    L, B = (8, 8, 8, 8), (4, 4, 4, 4)
+    ctx, lat = wdr.Context(L, B, (1, 1, 1, -1)), oracle.Lattice(L, B, (1, 1, 1, -1))
+    U = synth.gauge_field(L, 0.5, 1615)
+    gU = ctx.gauge(dev(U))
+    k = 0.147
+    psi, dg = synth.spinor(L, 1616), synth.spinor(L, 1617)
+    _, _, par = lat.maps()
+    for parity in (0, 1):
+        for dag in (0, 1):
+            src = psi * (par == 1 - parity)[:, None, None]
+            h = oracle.apply_D(lat, U, k, oracle.g5(src) if dag else src)
+            if dag:
+                h = oracle.g5(h)
+            h[par != parity] = 0
+            want = h + dg * (par == parity)[:, None, None]
+            out = ctx.internal_field(prec)
+            ctx.apply_hop_eo_internal(gU, k, prec, parity, dag, ctx.pack(dev(psi), prec), ctx.pack(dev(dg), prec),
+                                      out)
+            got = host(ctx.unpack(out, prec))
+            got[par != parity] = 0
+            say("eo halves prec", prec, "p", parity, "dag", dag, "rel", rel(got, want))
+            assert rel(got, want) < (1e-14 if prec == 0 else 2e-6)
+    del gU
+    ctx.close()

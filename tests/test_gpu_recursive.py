@@ -85,6 +85,36 @@ def test_block_schur_ratio_matches_oracle():
     sub.close()
 
 
+def test_block_schur_ratio_paper_geometry_matches_oracle():
+    """The benchmark's recursive workload (the block geometry of the paper's
+    Sec. 6): 8^4 blocks of a 16^4 lattice, 4^4 sub-blocks, links of every
+    block's 6^4 core redrawn, solved with the large-lattice settings (FP16
+    even-odd CG with FP32 and FP64 reliable updates, FP16 sub-block solves):
+    sampled blocks against the oracle on the extracted open block."""
+    wdr = _wdr()
+    L, B, kappa, seed = (16, 16, 16, 16), (8, 8, 8, 8), 0.150, 710
+    ctx, lat = wdr.Context(L, B), oracle.Lattice(L, B)
+    sub, slat = wdr.Context(B, (4, 4, 4, 4), OPEN), oracle.Lattice(B, (4, 4, 4, 4), OPEN)
+    U = synth.gauge_field(L, 0.25, 711)
+    Up = synth.redraw(U, oracle.active_links(lat, 1, 6), 0.25, 712)
+    gU, gUp = ctx.gauge(dev(U)), ctx.gauge(dev(Up))
+    N, K = 2, 1
+    p = wdr.default_params(**synth.LARGE_MIXED)
+    s, lrs, info = ctx.block_schur_ratio(gU, gUp, kappa, sub, N, K, wdr.NOISE_GAUSS, seed, p)
+    assert info.converged and s.shape == (ctx.nblocks, N, K)
+    for b in (0, 9):
+        Ub, _ = extract_block(lat, U, b)
+        Upb, _ = extract_block(lat, Up, b)
+        want, lr_want = oracle.logdet_ratio(slat, Ub, Upb, kappa, oracle.OP_SCHUR, N, K, oracle.NOISE_GAUSS,
+                                            seed + b)
+        say("paper geometry block", b, s[b].ravel(), want.ravel())
+        assert np.abs(s[b] - want).max() < 1e-8
+        assert abs(lrs[b] - float(np.sum(lr_want))) < 1e-8
+    del gU, gUp
+    ctx.close()
+    sub.close()
+
+
 def test_recursive_exact_agrees_with_stochastic():
     """eq. ddrec gives the block Schur ratio exactly from block determinants
     on two levels: log det(Dhat_b'^+ Dhat_b') - log det(Dhat_b^+ Dhat_b) =
