@@ -436,11 +436,13 @@ def copy_ceiling(torch, reps=10):
             "achieved": round(2 * 4 * n / (ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
 
 
-def rocprof_summary(path, kernel_regex="k_dslash"):
+def rocprof_summary(path, kernel_regex="k_dslash|k_eo16|k_block_mr"):
     """Markdown summary of rocprofv3 CSV output under `path`: per-kernel
-    totals (rocprofv3's kernel_stats), the kernels matching kernel_regex split
-    by grid size (kernel_trace), and per-dispatch counter means by kernel and
-    grid size (counter_collection)."""
+    totals (rocprofv3's kernel_stats); when a marker trace holds the timed
+    range of the headline, the kernels inside it by name and grid (time
+    share, launches and time per estimate, average launch); the kernels
+    matching kernel_regex by grid over the whole run (kernel_trace); and
+    per-dispatch counter means by kernel and grid (counter_collection)."""
     import csv
     import glob
     import re
@@ -455,12 +457,19 @@ def rocprof_summary(path, kernel_regex="k_dslash"):
 
     def short(name):
         name = name.replace("wdr::(anonymous namespace)::", "").replace("(anonymous namespace)::", "")
+        m = re.match(r"_ZN3wdr12_GLOBAL__N_1\d+(k_\w+?)(I|E)", name)
+        if m:
+            name = m.group(1) + ("<...>" if m.group(2) == "I" else "")
         return re.sub(r"\(.*", "", name)[:90]
+
+    def grid(r):
+        return "x".join(r.get("grid_size_%s" % d, "?") for d in "xyz")
 
     lines = []
     stats = rows("*kernel_stats.csv")
     if stats:
-        lines += ["| kernel | calls | total us | avg us | % |", "|---|---|---|---|---|"]
+        lines += ["All kernels of the run (rocprofv3 kernel_stats):", "",
+                  "| kernel | calls | total us | avg us | % |", "|---|---|---|---|---|"]
         stats.sort(key=lambda r: -float(r.get("totaldurationns", 0)))
         for r in stats[:15]:
             lines.append("| %s | %s | %.1f | %.2f | %.2f |" % (short(r["name"]), r["calls"],
@@ -468,18 +477,36 @@ def rocprof_summary(path, kernel_regex="k_dslash"):
                                                              float(r["averagens"]) / 1e3,
                                                              float(r.get("percentage", 0))))
     trace = rows("*kernel_trace.csv")
+    marks = [r for r in rows("*marker_api_trace.csv") if any(TIMED_RANGE in str(v) for v in r.values())]
+    if trace and marks:
+        t0 = min(int(r["start_timestamp"]) for r in marks)
+        t1 = max(int(r["end_timestamp"]) for r in marks)
+        inside = [r for r in trace if int(r["start_timestamp"]) >= t0 and int(r["end_timestamp"]) <= t1]
+        steps = None
+        m = re.search(r"--steps\s+(\d+)", " ".join(sys.argv))
+        agg = defaultdict(list)
+        for r in inside:
+            agg[(short(r["kernel_name"]), grid(r))].append((int(r["end_timestamp"]) - int(r["start_timestamp"])) / 1e3)
+        tot = sum(sum(v) for v in agg.values())
+        lines += ["", "Kernels inside the timed range of the headline (%d launches, %.1f ms of kernel time, "
+                  "%.1f ms wall):" % (len(inside), tot / 1e3, (t1 - t0) / 1e6), "",
+                  "| kernel | grid (work-items) | launches | total us | avg us | % of kernel time |",
+                  "|---|---|---|---|---|---|"]
+        for (k, gr), v in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:25]:
+            lines.append("| %s | %s | %d | %.1f | %.2f | %.2f |" % (k, gr, len(v), sum(v), sum(v) / len(v),
+                                                                  100 * sum(v) / tot))
+        del steps, m
     if trace:
         agg = defaultdict(list)
         for r in trace:
-            if re.search(kernel_regex, r["kernel_name"]):
-                grid = "x".join(r.get("grid_size_%s" % d, "?") for d in "xyz")
-                agg[(short(r["kernel_name"]), grid)].append(
+            if re.search(kernel_regex, short(r["kernel_name"])):
+                agg[(short(r["kernel_name"]), grid(r))].append(
                     (int(r["end_timestamp"]) - int(r["start_timestamp"])) / 1e3)
         if agg:
-            lines += ["", "| kernel (%s) | grid (work-items) | launches | avg us | min us | max us |" % kernel_regex,
-                      "|---|---|---|---|---|---|"]
-            for (k, grid), v in sorted(agg.items()):
-                lines.append("| %s | %s | %d | %.2f | %.2f | %.2f |" % (k, grid, len(v), sum(v) / len(v), min(v),
+            lines += ["", "| kernel (%s), whole run | grid (work-items) | launches | avg us | min us | max us |"
+                      % kernel_regex, "|---|---|---|---|---|---|"]
+            for (k, gr), v in sorted(agg.items()):
+                lines.append("| %s | %s | %d | %.2f | %.2f | %.2f |" % (k, gr, len(v), sum(v) / len(v), min(v),
                                                                        max(v)))
     cnt = rows("*counter_collection.csv")
     if cnt:
@@ -488,9 +515,9 @@ def rocprof_summary(path, kernel_regex="k_dslash"):
             agg[(short(r["kernel_name"]), r.get("grid_size", "?"), r["counter_name"])].append(
                 float(r["counter_value"]))
         lines += ["", "| kernel | grid size | counter | dispatches | mean per dispatch |", "|---|---|---|---|---|"]
-        for (k, grid, c), v in sorted(agg.items()):
+        for (k, gr, c), v in sorted(agg.items()):
             if re.search(kernel_regex + "|elementwise", k):
-                lines.append("| %s | %s | %s | %d | %.1f |" % (k, grid, c, len(v), sum(v) / len(v)))
+                lines.append("| %s | %s | %s | %d | %.1f |" % (k, gr, c, len(v), sum(v) / len(v)))
     return "\n".join(lines)
 
 
@@ -691,6 +718,7 @@ def cpu_baseline():
 
 # the headline workload (the largest configuration: 32^4, 4096 blocks of 4^4)
 HEADLINE = "wilson32_dd4096"
+TIMED_RANGE = "timed estimates"
 # compulsory bytes of one k_eo16 launch per system of V sites (one even-odd
 # half in FP16: the input half, the output half and every link of the
 # lattice, FP16 two-row, 24 B per link), plus the FP16 diagonal half if any
@@ -727,6 +755,9 @@ def headline_estimate(wdr, torch, steps, warmup, fp64=True):
         ctx.logdet_ratio(gU, gUp, w["kappa"], wdr.OP_SCHUR, N, 1, wdr.NOISE_GAUSS, 1000 + k, mixed)
     torch.cuda.synchronize()
     wdr.traffic(reset=True)
+    # a marker range around the timed estimates (rocprofv3 --marker-trace
+    # records it; --rocprof-summary keeps the kernels inside it)
+    torch.cuda.nvtx.range_push(TIMED_RANGE)
     t0 = time.perf_counter()
     ok, iters, lrs, s_first = True, 0, [], None
     for k in range(steps):
@@ -740,6 +771,7 @@ def headline_estimate(wdr, torch, steps, warmup, fp64=True):
                                                                        info.total_iters))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    torch.cuda.nvtx.range_pop()
     traffic = wdr.traffic(reset=True)
     out = {"steps": steps, "seconds": dt, "converged": ok, "cg_iterations": iters, "mean_log_ratio": float(np.mean(lrs)),
            "params": mixed, "traffic_bytes": traffic}
@@ -886,6 +918,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--headline-only", action="store_true",
                     help="only the 32^4 headline estimates (for profiling): no FP64 form, rooflines or extras")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the roofline launches (k_eo16 in the headline's launch shape, the 32^4 stencils, "
+                         "the copy ceiling), for counter runs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-dslash", action="store_true")
@@ -914,7 +949,14 @@ def main():
     import torch
     from paper_1112_1243_amd import synth, wdr
 
-    w = synth.WORKLOADS[HEADLINE]
+    if args.roofline_only:
+        roof = eo16_roofline(wdr, torch, synth.WORKLOADS[HEADLINE]["n_noise"])
+        log("k_eo16:", roof)
+        for prec in ("f64", "f32"):
+            log("dslash %s:" % prec, dslash_roofline(wdr, torch, prec_name=prec))
+        log("dslash f16:", dslash_f16(wdr, torch))
+        log("copy ceiling:", copy_ceiling(torch))
+        return
     head = headline_estimate(wdr, torch, args.steps, args.warmup, fp64=not args.no_fp64)
     dt = head["seconds"]
     value = args.steps / dt

@@ -34,12 +34,25 @@ def test_counter_summary_matches_stencil_sources():
     assert alg < bench.counted_traffic("f64") < 2 * alg
 
 
-def test_trace_summary_covers_the_timed_stencil():
-    """The kernel-trace summary holds the 32^4 FP64 block-staged stencil whose
-    launches the roofline object reports, with the HIP-event time beside it."""
-    text = open(os.path.join(ROOT, "profiles", "estimate_wilson8_dd16_kernel_trace.md")).read()
-    rows = [l for l in text.splitlines() if "k_dslash_blk<double, 4, 0, 0>" in l and "1048576x1x1" in l]
-    assert rows, "no 32^4 FP64 k_dslash_blk row"
-    avg_us = float(rows[0].strip().strip("|").split("|")[3])
-    assert 150.0 < avg_us < 300.0
-    assert "bench.py's own HIP" in text
+def test_eo16_counter_summary_is_fresh():
+    """The roofline's traffic for the dominant kernel of the headline comes
+    from a counter summary of the current cg16.hip, within 1.0x-1.5x of the
+    algorithmic bytes."""
+    bench = load_bench()
+    t = bench.counted_traffic_eo16(32)
+    assert t is not None, "k_eo16 counter summary is stale"
+    alg = 32 * (bench.eo16_bytes(32 ** 4, False) + bench.eo16_bytes(32 ** 4, True)) // 2
+    assert alg < t < 1.5 * alg
+
+
+def test_trace_summary_covers_the_headline():
+    """The kernel-trace summary isolates the timed 32^4 estimates and holds
+    the dominant kernel k_eo16 in the launch shape of the roofline object
+    (32 systems per launch), with bench.py's own timing beside it."""
+    text = open(os.path.join(ROOT, "profiles", "estimate_wilson32_dd4096_kernel_trace.md")).read()
+    assert "Kernels inside the timed range" in text
+    rows = [l for l in text.splitlines() if l.startswith("| k_eo16") and "524288x32x1" in l]
+    assert rows, "no k_eo16 row at 32 systems per launch"
+    avg_us = float(rows[0].strip().strip("|").split("|")[4])
+    assert 500.0 < avg_us < 2000.0
+    assert "bench.py reported" in text
