@@ -147,16 +147,85 @@ __device__ __forceinline__ void store_block(const cx<float> v[12], uint4 *outv, 
     }
 }
 
-// The two hops of direction MU at output site t (coords x, parity par) of
-// block `slot`: neighbours of the other parity from the block's LDS copy sh
-// or, across a face, from the FP16 field (times the neighbour block's
-// scale); links from the E16 link chunks.  DAG applies gamma_5 to the loaded
-// spinors (the caller to the result).
+// LDS copy of FP16 sites: 12 complex FP16 per site, 48 bytes, read as three
+// 16-byte words
+struct Site16 {
+    v4u q[3];
+};
+__device__ __forceinline__ void ld_site_lds(const Site16 *sh, int i, float s, spinor<float> &p)
+{
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        Q16 q;
+        q.u = sh[i].q[k];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = 4 * k + j;
+            p.s[c / 3].c[c % 3] = mk<float>((float)q.h[j].x * s, (float)q.h[j].y * s);
+        }
+    }
+}
+// a link's two rows as loaded (16 + 8 bytes), unpacked later
+struct Link16 {
+    Q16 a;
+    D16 b;
+};
+__device__ __forceinline__ void ld_link_raw(const __attribute__((address_space(1))) h2 *L, int chunk, int i,
+                                            Link16 &k)
+{
+    const auto *base = L + (long)chunk * VH4 * 6;
+    k.a.u = ((G4)base)[i];
+    k.b.u = ((const __attribute__((address_space(1))) v2u *)(base + VH4 * 4))[i];
+}
+__device__ __forceinline__ void unpack_link(const Link16 &k, float sg, su3<float> &u)
+{
+    u.m[0][0] = mk<float>((float)k.a.h[0].x, (float)k.a.h[0].y);
+    u.m[0][1] = mk<float>((float)k.a.h[1].x, (float)k.a.h[1].y);
+    u.m[0][2] = mk<float>((float)k.a.h[2].x, (float)k.a.h[2].y);
+    u.m[1][0] = mk<float>((float)k.a.h[3].x, (float)k.a.h[3].y);
+    u.m[1][1] = mk<float>((float)k.b.h[0].x, (float)k.b.h[0].y);
+    u.m[1][2] = mk<float>((float)k.b.h[1].x, (float)k.b.h[1].y);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int p = (c + 1) % 3, q = (c + 2) % 3;
+        const cx<float> v = u.m[0][p] * u.m[1][q] - u.m[0][q] * u.m[1][p];
+        u.m[2][c] = mk<float>(sg * v.re, -sg * v.im);
+    }
+}
+
+// Halo of one block half: the sites of parity q in the boundary layer of the
+// neighbour block across face f = 2 mu + d (d = 0: +mu, layer x_mu = 0 of
+// that block; d = 1: -mu, layer x_mu = B - 1), 32 per face for 4^4 blocks.
+// Entry k of a face: the three other coordinates (increasing direction) are
+// (u, v, w) with w = k >> 3, v = (k >> 1) & 3 and u the value of parity q in
+// {2 (k & 1), 2 (k & 1) + 1}.
+__device__ __forceinline__ void halo_site(int f, int k, int q, int y[4])
+{
+    const int mu = f >> 1;
+    y[mu] = (f & 1) ? B4 - 1 : 0;
+    int o[3], n = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d)
+        if (d != mu) o[n++] = d;
+    const int w = k >> 3, v = (k >> 1) & 3;
+    y[o[2]] = w;
+    y[o[1]] = v;
+    y[o[0]] = 2 * (k & 1) + ((q + y[mu] + v + w) & 1);
+}
+template <int MU> __device__ __forceinline__ int halo_entry(const int y[4])
+{
+    constexpr int o0 = MU == 0 ? 1 : 0, o1 = MU <= 1 ? 2 : 1, o2 = MU <= 2 ? 3 : 2;
+    return (y[o2] << 3) | (y[o1] << 1) | (y[o0] >> 1);
+}
+
+// The two hops of direction MU at output site x (parity par): neighbours from
+// the block's LDS copy (own) or the LDS halo (across a face, with that
+// neighbour block's scale), links from the prefetched registers.  DAG
+// applies gamma_5 to the loaded spinors (the caller to the result).
 template <int MU, int DAG>
-__device__ __forceinline__ void hop16(const float2 (*sh)[VH4], G4 inf,
-                                      const float *ins, long fbase, const __attribute__((address_space(1))) h2 *L,
-                                      int slot, const int nbr[8], int par, int t, const int x[4], spinor<float> &acc,
-                                      float wrap_f, float wrap_b)
+__device__ __forceinline__ void hop16(const Site16 *own, const Site16 *halo, float s_own, const float *s_face, int par,
+                                      const int x[4], const Link16 &lf, const Link16 &lb, float wrap_f, float wrap_b,
+                                      spinor<float> &acc)
 {
     typedef Cube<B4> CB;
 #pragma unroll
@@ -165,23 +234,13 @@ __device__ __forceinline__ void hop16(const float2 (*sh)[VH4], G4 inf,
         const bool inside = fwd ? x[MU] + 1 < B4 : x[MU] > 0;
         int y[4] = {x[0], x[1], x[2], x[3]};
         y[MU] = fwd ? (inside ? x[MU] + 1 : 0) : (inside ? x[MU] - 1 : B4 - 1);
-        const int ns = inside ? slot : nbr[2 * MU + dir];
-        const int j = CB::index(y) - (1 - par) * VH4;
         spinor<float> p;
-        if (inside) {
-#pragma unroll
-            for (int c = 0; c < 12; ++c) p.s[c / 3].c[c % 3] = mk<float>(sh[c][j].x, sh[c][j].y);
-        } else {
-            cx<float> v[12];
-            ld_site(inf, (fbase + ns) * VH4 + j, ins[fbase + ns], v);
-#pragma unroll
-            for (int c = 0; c < 12; ++c) p.s[c / 3].c[c % 3] = v[c];
-        }
-        su3<float> u;
-        if (fwd)
-            ld_link(L, (slot * 2 + par) * 4 + MU, t, wrap_f, u);
+        if (inside)
+            ld_site_lds(own, CB::index(y) - (1 - par) * VH4, s_own, p);
         else
-            ld_link(L, (ns * 2 + (1 - par)) * 4 + MU, j, wrap_b, u);
+            ld_site_lds(halo, (2 * MU + dir) * 32 + halo_entry<MU>(y), s_face[2 * MU + dir], p);
+        su3<float> u;
+        unpack_link(fwd ? lf : lb, fwd ? wrap_f : wrap_b, u);
         if (DAG) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -214,8 +273,11 @@ __device__ __forceinline__ void hop16(const float2 (*sh)[VH4], G4 inf,
 // out = diag + f H_{par, 1-par} in on the sites of parity par (gamma_5 on
 // both sides of H for DAG), f = fs kappa_m (or fk without a kappa table);
 // FP16 E16 fields in and out, diag optional.  One workgroup per block and
-// system, one lane per output site; the block's input half is staged in LDS
-// as FP32.  partial (optional): |out|^2 of the stored values per block.
+// system, one lane per output site.  Every global load is issued up front:
+// the block's input half and its halo (the 256 face sites of the neighbour
+// blocks, two per lane) go to LDS as FP16, the eight links of the lane's
+// hops to registers; the hops then read LDS and registers only.
+// partial (optional): |out|^2 of the stored values per block.
 template <int DAG>
 __global__ __launch_bounds__(VH4) void k_eo16(Geo g, const int32_t *__restrict__ active,
                                               const int32_t *__restrict__ list, const h2 *const *__restrict__ ltab,
@@ -226,47 +288,74 @@ __global__ __launch_bounds__(VH4) void k_eo16(Geo g, const int32_t *__restrict__
                                               float *__restrict__ outs, double *__restrict__ partial)
 {
     typedef Cube<B4> CB;
-    __shared__ float2 sh[12][VH4];  // the block's input half, component-major
+    __shared__ Site16 own[VH4];       // the block's input half
+    __shared__ Site16 halo[8 * 32];   // face sites of the neighbour blocks
     const int m = sys_at(list, blockIdx.y);
     if (active && !active[m]) return;
     const float f = kap ? fs * (float)kap[m] : fk;
     const int slot = sched[blockIdx.x];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, q = 1 - par;
     const long fbase = (long)m * g.nblk;
     const G4 inf = g4(inv);
-    {
-        cx<float> v[12];
-        ld_site(inf, (fbase + slot) * VH4 + t, ins[fbase + slot], v);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) sh[c][t] = make_float2(v[c].re, v[c].im);
-    }
-    int x[4];
-    CB::coords(par * VH4 + t, x);
     int nbr[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
-    const int bl = g.slot_blk[slot];
+    // input half and halo to LDS (raw FP16 words)
+    {
+        const long si = ((fbase + slot) * VH4 + t) * 3;
+        own[t].q[0] = inf[si];
+        own[t].q[1] = inf[si + 1];
+        own[t].q[2] = inf[si + 2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int e = t + r * VH4, fc = e >> 5;
+            int y[4];
+            halo_site(fc, e & 31, q, y);
+            const long hi = ((fbase + nbr[fc]) * VH4 + CB::index(y) - q * VH4) * 3;
+            halo[e].q[0] = inf[hi];
+            halo[e].q[1] = inf[hi + 1];
+            halo[e].q[2] = inf[hi + 2];
+        }
+    }
+    int x[4];
+    CB::coords(par * VH4 + t, x);
+    // the eight links of this lane's hops: U_mu(x) and U_mu(x - mu)
     const auto *L = glob(ltab[m]);
-    __syncthreads();
-    spinor<float> acc;
-    zero(acc);
-#pragma unroll 1
+    Link16 lf[4], lb[4];
+#pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-        float wf = 1.f, wb = 1.f;
+        ld_link_raw(L, (slot * 2 + par) * 4 + mu, t, lf[mu]);
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        const bool inside = x[mu] > 0;
+        y[mu] = inside ? x[mu] - 1 : B4 - 1;
+        ld_link_raw(L, ((inside ? slot : nbr[2 * mu + 1]) * 2 + q) * 4 + mu, CB::index(y) - q * VH4, lb[mu]);
+    }
+    const float s_own = ins[fbase + slot];
+    float s_face[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s_face[k] = ins[fbase + nbr[k]];
+    // boundary signs of the links that wrap around the lattice (their stored
+    // rows carry bc; the rebuilt third row needs it once more)
+    float wf[4], wb[4];
+    const int bl = g.slot_blk[slot];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        wf[mu] = wb[mu] = 1.f;
         if (g.bc[mu] < 0) {
             int b2 = bl;
             for (int d = 0; d < mu; ++d) b2 /= g.NB[d];
             const int nmu = b2 % g.NB[mu];
-            if (nmu == g.NB[mu] - 1 && x[mu] == B4 - 1) wf = -1.f;
-            if (nmu == 0 && x[mu] == 0) wb = -1.f;
-        }
-        switch (mu) {
-        case 0: hop16<0, DAG>(sh, inf, ins, fbase, L, slot, nbr, par, t, x, acc, wf, wb); break;
-        case 1: hop16<1, DAG>(sh, inf, ins, fbase, L, slot, nbr, par, t, x, acc, wf, wb); break;
-        case 2: hop16<2, DAG>(sh, inf, ins, fbase, L, slot, nbr, par, t, x, acc, wf, wb); break;
-        default: hop16<3, DAG>(sh, inf, ins, fbase, L, slot, nbr, par, t, x, acc, wf, wb); break;
+            if (nmu == g.NB[mu] - 1 && x[mu] == B4 - 1) wf[mu] = -1.f;
+            if (nmu == 0 && x[mu] == 0) wb[mu] = -1.f;
         }
     }
+    __syncthreads();
+    spinor<float> acc;
+    zero(acc);
+    hop16<0, DAG>(own, halo, s_own, s_face, par, x, lf[0], lb[0], wf[0], wb[0], acc);
+    hop16<1, DAG>(own, halo, s_own, s_face, par, x, lf[1], lb[1], wf[1], wb[1], acc);
+    hop16<2, DAG>(own, halo, s_own, s_face, par, x, lf[2], lb[2], wf[2], wb[2], acc);
+    hop16<3, DAG>(own, halo, s_own, s_face, par, x, lf[3], lb[3], wf[3], wb[3], acc);
     const long site = (fbase + slot) * VH4 + t;
     cx<float> dg[12];
     if (dgv) ld_site(g4(dgv), site, dgs[fbase + slot], dg);
