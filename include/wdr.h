@@ -289,6 +289,19 @@ wdr_status wdr_unpack_eo16(wdr_ctx *ctx, int32_t parity, const void *dev_eo16, d
 wdr_status wdr_apply_D(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, const double *dev_in,
                        double *dev_out, void *stream);
 
+/* wdr_apply_D (F64 or F32) without any device allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  The two internal-layout staging fields
+ * of a call live in a static device array of 64 MiB that each device the
+ * library runs on holds until the process ends (its address is taken once
+ * per device by wdr_ctx_create), so V x 12 complex of prec, twice, must fit:
+ * at most 174762 sites in F64, 349525 in F32; EINVAL beyond.  Every call on
+ * one device shares that array: calls that overlap on one GPU (on different
+ * streams or host threads) race, and the caller must order them.  Results
+ * equal wdr_apply_D's bit for bit. */
+wdr_status wdr_apply_D_noalloc(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, const double *dev_in,
+                               double *dev_out, void *stream);
+
 /* Dirichlet block operators (Sec. 3, eq. domdec): colour 0 gives D_bb,
  * 1 gives D_ww, 2 both; zero on sites outside the selected blocks. */
 wdr_status wdr_apply_Dblock(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t colour,

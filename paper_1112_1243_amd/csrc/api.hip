@@ -4,12 +4,24 @@
 #include <thread>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 
 #include "runtime.h"
 
 using namespace wdr;
 
 namespace {
+
+// Staging area of wdr_apply_D_noalloc: the two internal-layout fields of a
+// call live in this static device array, which every device the library runs
+// on holds until the process ends.  Host code never passes the array's name
+// to a kernel or a copy (on the host it is only a stand-in): scratch_dev[d]
+// holds device d's address of its copy, taken by init_scratch.
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+std::mutex scratch_mu;
+void *scratch_dev[MAX_DEVICES];
 
 hipStream_t S(void *stream) { return (hipStream_t)stream; }
 
@@ -144,6 +156,28 @@ double now()
 }
 
 }  // namespace
+
+namespace wdr {
+// the address of the staging array on `device` (the current device), once
+// per device; called by wdr_ctx_create
+wdr_status init_scratch(int device)
+{
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (device < 0 || device >= MAX_DEVICES) {
+        set_error("device index beyond the staging table");
+        return WDR_EINVAL;
+    }
+    if (scratch_dev[device]) return WDR_OK;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        set_error(std::string("hipGetSymbolAddress of the staging array: ") + hipGetErrorString(e));
+        return WDR_EDEVICE;
+    }
+    scratch_dev[device] = p;
+    return WDR_OK;
+}
+}  // namespace wdr
 
 extern "C" {
 
@@ -401,6 +435,55 @@ wdr_status wdr_apply_D(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr_prec pr
                        void *stream)
 {
     return stencil_entry(c, U, kappa, prec, 0, 0, in, out, stream);
+}
+
+wdr_status wdr_apply_D_noalloc(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr_prec prec, const double *in,
+                               double *out, void *stream)
+{
+    wdr_status e = pre(c, in, out);
+    if (e != WDR_OK) return e;
+    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
+    if (prec != WDR_F64 && prec != WDR_F32) {
+        set_error("wdr_apply_D_noalloc computes in F64 or F32");
+        return WDR_EINVAL;
+    }
+    const size_t fb = (field_bytes(c, prec) + 255) / 256 * 256;
+    if (2 * fb > NOALLOC_BYTES) {
+        set_error("wdr_apply_D_noalloc needs " + std::to_string(2 * fb) + " bytes of staging, more than its " +
+                  std::to_string(NOALLOC_BYTES) + "-byte static array");
+        return WDR_EINVAL;
+    }
+    void *base;
+    {
+        std::lock_guard<std::mutex> lock(scratch_mu);
+        base = c->device >= 0 && c->device < MAX_DEVICES ? scratch_dev[c->device] : nullptr;
+    }
+    if (!base) {
+        set_error("the staging array of this device was not set up");
+        return WDR_ESTATE;
+    }
+    unsigned char *a = static_cast<unsigned char *>(base), *b = a + fb;
+    const hipStream_t s = S(stream);
+    const Geo &g = c->g;
+    const Sys one = all_sys(c, 1);
+    // the output field starts at zero (a kernel clears it, like the pooled
+    // form); the input field is written in full by the pack
+    if (prec == WDR_F64) {
+        launch_pack_spinor<double>(g, reinterpret_cast<const double2 *>(in), reinterpret_cast<double2 *>(a), s);
+        launch_zero<double>(reinterpret_cast<double2 *>(b), field_n(c), s);
+        launch_dslash<double>(g, one, links<double>(U), HOPS_ALL, -1, 0, reinterpret_cast<const double2 *>(a),
+                              reinterpret_cast<const double2 *>(a), reinterpret_cast<double2 *>(b), kappa, 0, g.nblk,
+                              s);
+        launch_unpack_spinor<double>(g, reinterpret_cast<const double2 *>(b), reinterpret_cast<double2 *>(out), s);
+    } else {
+        launch_pack_spinor<float>(g, reinterpret_cast<const double2 *>(in), reinterpret_cast<float2 *>(a), s);
+        launch_zero<float>(reinterpret_cast<float2 *>(b), field_n(c), s);
+        launch_dslash<float>(g, one, links<float>(U), HOPS_ALL, -1, 0, reinterpret_cast<const float2 *>(a),
+                             reinterpret_cast<const float2 *>(a), reinterpret_cast<float2 *>(b), (float)kappa, 0,
+                             g.nblk, s);
+        launch_unpack_spinor<float>(g, reinterpret_cast<const float2 *>(b), reinterpret_cast<double2 *>(out), s);
+    }
+    return finish(s);
 }
 
 wdr_status wdr_apply_Dblock(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t colour,

@@ -59,6 +59,12 @@ struct wdr_gauge {
     int rep_cap = 0;
 };
 
+namespace wdr {
+// device address of wdr_apply_D_noalloc's static staging array on `device`
+// (the current device), looked up once per device
+wdr_status init_scratch(int device);
+}  // namespace wdr
+
 // largest |U U^+ - 1| and |det U - 1| entry for which a gauge field counts as
 // SU(3), so that kernels may rebuild the third row of its links
 constexpr double SU3_TOL = 1e-10;

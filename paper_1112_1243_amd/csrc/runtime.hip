@@ -226,6 +226,10 @@ wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)
         return WDR_EINVAL;
     }
     WDR_HIP(hipSetDevice(device));
+    {
+        const wdr_status se = init_scratch(device);
+        if (se != WDR_OK) return se;
+    }
 
     wdr_ctx *c = new wdr_ctx();
     c->device = device;

@@ -117,7 +117,7 @@ def lib():
         L.wdr_pack_eo16.argtypes = [P, i32, P, P, P]
         L.wdr_unpack_eo16.argtypes = [P, i32, P, P, P]
         L.wdr_apply_hop_eo_internal.argtypes = [P, P, d, ctypes.c_int, i32, i32, i32, P, P, P, P]
-        for f in ("wdr_apply_D",):
+        for f in ("wdr_apply_D", "wdr_apply_D_noalloc"):
             getattr(L, f).argtypes = [P, P, d, ctypes.c_int, P, P, P]
         for f in ("wdr_apply_Dblock", "wdr_apply_Dhop", "wdr_apply_Dee"):
             getattr(L, f).argtypes = [P, P, d, ctypes.c_int, i32, P, P, P]
@@ -343,6 +343,13 @@ class Context:
 
     def apply_D(self, gauge, kappa, psi, prec=F64):
         return self._op("wdr_apply_D", gauge, kappa, psi, prec)
+
+    def apply_D_noalloc(self, gauge, kappa, psi, out, prec=F64):
+        """D psi into the caller's out (complex128 [V, 4, 3]) with the library's
+        static staging array: no device allocation in the call."""
+        _check(lib().wdr_apply_D_noalloc(self.handle, gauge.handle, kappa, prec, _dev(psi, (self.V, 4, 3)),
+                                         _dev(out, (self.V, 4, 3)), _stream()))
+        return out
 
     def apply_Dblock(self, gauge, kappa, psi, colour, prec=F64):
         return self._op("wdr_apply_Dblock", gauge, kappa, psi, prec, colour)
