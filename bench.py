@@ -242,19 +242,52 @@ def filter_run(wdr, torch, steps=6):
     return out
 
 
+def fit_variance(lr, Ns, n_boot=2000, seed=1112124306):
+    """Var over pairs of log Rhat_N (lr[pair, j] for N = Ns[j]) fitted as
+    a + b / N (eq. param: the noise part of each factor's variance falls as
+    1 / N; Sec. 5 extrapolates 1 / N -> 0).  Weighted least squares with the
+    standard error of a variance estimate from P pairs, model(N)
+    sqrt(2 / (P - 1)), the model refitted three times from equal weights;
+    errors by bootstrap over pairs (the same pairs enter every N, so the
+    variances are correlated and the bootstrap keeps that).  Returns the
+    variances and their bootstrap errors, a, b, the bootstrap standard
+    error of a and its central 68% interval."""
+    lr = np.asarray(lr, dtype=np.float64)
+    P = lr.shape[0]
+    X = np.vstack([np.ones(len(Ns)), 1.0 / np.asarray(Ns, dtype=np.float64)]).T
+
+    def fit(v):
+        w = np.ones(len(Ns))
+        coef = np.zeros(2)
+        for _ in range(3):
+            coef, _, _, _ = np.linalg.lstsq(X / w[:, None], v / w, rcond=None)
+            w = np.maximum(X @ coef, 1e-12 * max(float(v.max()), 1e-300)) * np.sqrt(2.0 / (P - 1))
+        return coef
+
+    var = lr.var(axis=0, ddof=1)
+    a, b = fit(var)
+    rng = np.random.Generator(np.random.Philox(key=[seed, 7]))
+    boot_a, boot_var = np.empty(n_boot), np.empty((n_boot, len(Ns)))
+    for k in range(n_boot):
+        vk = lr[rng.integers(0, P, P)].var(axis=0, ddof=1)
+        boot_var[k] = vk
+        boot_a[k] = fit(vk)[0]
+    return {"var": var.tolist(), "var_err": boot_var.std(axis=0, ddof=1).tolist(), "a": float(a), "b": float(b),
+            "a_err": float(boot_a.std(ddof=1)), "a_68": np.percentile(boot_a, [16, 84]).tolist()}
+
+
 def exact_acceptance(wdr, torch):
     """The exact acceptance rate of the global step (Sec. 5): for pairs
     (U, U') of a quenched beta = 5.8 chain (10 heat-bath sweeps apart) and
     one block step each, the variance over pairs of the global estimate
-    log Rhat for several N, fitted as a + b / N (eq. param: the noise part
-    falls as 1/N; weighted by the standard error of each variance estimate);
-    a is the exact variance sigma_2^2 and erfc(sqrt(a / 8)) the acceptance
-    (eq. acceptance).  Beside it, N = 8 after 20 sweeps of
+    log Rhat for several N, fitted as a + b / N (fit_variance: weighted by
+    the model's standard error, bootstrap errors over pairs); a is the exact
+    variance sigma_2^2 and erfc(sqrt(a / 8)) the acceptance (eq. acceptance).  Beside it, N = 8 after 20 sweeps of
     relative gauge fixing of U' to U (Sec. 4), for the same pairs."""
     from scipy import special
     beta, kappa, seed = 5.8, 0.15462, 1112124305
     res = {}
-    for L, pairs, Ns in (((8, 8, 8, 8), 96, (8, 16, 32, 64)), ((16, 16, 16, 16), 24, (8, 16, 32, 64))):
+    for L, pairs, Ns in (((8, 8, 8, 8), 96, (8, 16, 32, 64)), ((16, 16, 16, 16), 64, (8, 16, 32, 64))):
         t0 = time.perf_counter()
         ctx = wdr.Context(L, (4, 4, 4, 4))
         U, allm = thermalised(wdr, torch, ctx, L, beta, seed, 200)
@@ -280,18 +313,13 @@ def exact_acceptance(wdr, torch):
             _, lr_fixed[q], _ = ctx.logdet_ratio(gU, gUf, kappa, wdr.OP_SCHUR, 8, 1, wdr.NOISE_GAUSS,
                                                  seed + 1000 * q + 8, p)
             del gU, gUp, gUf
-        var = lr.var(axis=0, ddof=1)
-        # weighted fit: a variance estimate from P pairs has standard error
-        # sigma^2 sqrt(2 / (P - 1))
-        sd = var * np.sqrt(2.0 / (pairs - 1))
-        A = np.vstack([np.ones(len(Ns)), 1.0 / np.array(Ns)]).T / sd[:, None]
-        coef, _, _, _ = np.linalg.lstsq(A, var / sd, rcond=None)
-        a, b = coef
-        a_err = float(np.sqrt(np.linalg.inv(A.T @ A)[0, 0]))
+        fit = fit_variance(lr, Ns)
+        var, a, b, a_err = np.array(fit["var"]), fit["a"], fit["b"], fit["a_err"]
         name = "x".join(map(str, L))
         res[name] = {"pairs": pairs, "N": list(Ns), "var_log_ratio": [round(float(v), 4) for v in var],
+                     "var_log_ratio_err": [round(float(v), 4) for v in fit["var_err"]],
                      "mean_log_ratio": [round(float(v), 4) for v in lr.mean(axis=0)], "fit_a": round(float(a), 4),
-                     "fit_a_err": round(a_err, 4),
+                     "fit_a_err": round(a_err, 4), "fit_a_68": [round(float(v), 4) for v in fit["a_68"]],
                      "fit_b": round(float(b), 3), "block_acceptance": round(float(bacc) / pairs, 3),
                      "acceptance_erfc": round(float(special.erfc(np.sqrt(max(a, 0.0) / 8))), 3),
                      "var_log_ratio_N8_relative_gauge": round(float(lr_fixed.var(ddof=1)), 4),

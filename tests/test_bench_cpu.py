@@ -56,3 +56,29 @@ def test_trace_summary_covers_the_headline():
     avg_us = float(rows[0].strip().strip("|").split("|")[4])
     assert 500.0 < avg_us < 2000.0
     assert "bench.py reported" in text
+
+
+def test_variance_fit_recovers_known_model():
+    """fit_variance on synthetic pairs with a known law: log Rhat_N of pair q
+    is g_q + e_{q,N} with g_q ~ N(0, a) shared by every N of the pair and
+    independent e ~ N(0, b / N), so Var(log Rhat_N) = a + b / N.  The fit
+    recovers a within four bootstrap errors, the bootstrap error is close to
+    the spread of the estimate over independent repetitions, and the 68%
+    interval covers the truth in about 68% of them."""
+    bench = load_bench()
+    import numpy as np
+    a_true, b_true, Ns, P = 0.4, 20.0, (8, 16, 32, 64), 200
+    rng = np.random.Generator(np.random.Philox(key=[7, 11]))
+    ests, errs, cover = [], [], 0
+    for rep in range(40):
+        g = rng.normal(0.0, np.sqrt(a_true), P)
+        lr = np.stack([g + rng.normal(0.0, np.sqrt(b_true / N), P) for N in Ns], axis=1)
+        f = bench.fit_variance(lr, Ns, n_boot=300, seed=rep)
+        ests.append(f["a"])
+        errs.append(f["a_err"])
+        cover += f["a_68"][0] <= a_true <= f["a_68"][1]
+        assert abs(f["a"] - a_true) < 4 * f["a_err"] + 1e-12
+        assert abs(f["b"] - b_true) < 0.5 * b_true
+    spread = float(np.std(ests, ddof=1))
+    assert 0.6 < float(np.mean(errs)) / spread < 1.6
+    assert 16 <= cover <= 38
