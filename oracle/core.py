@@ -33,6 +33,13 @@ Pins (tests under ``tests/test_oracle_*.py``):
                       involution
   * relative gauge    F never decreases; block determinants unchanged; a
                       gauge copy of U is driven back to U
+  * clover term       constant abelian fluxes in a magnetic and an electric
+                      plane (closed forms worked out by hand); zero on the
+                      unit field; hermitian, chiral, spin-traceless; gauge
+                      covariance; a changed link reaches exactly the 14
+                      corners of its plaquettes; D_b = D minus the crossing
+                      hops; solves and FULL / BLOCKS / SCHUR samples against
+                      dense linear algebra
 """
 from __future__ import annotations
 
@@ -72,12 +79,12 @@ def lib():
         d = ctypes.c_double
         L.oracle_gamma.argtypes = [i, P]
         L.oracle_site_maps.argtypes = [P, P, P, P, P]
-        L.oracle_apply_D.argtypes = [P, P, d, P, P, P]
-        L.oracle_apply_Dblock.argtypes = [P, P, P, d, P, i, P, P]
+        L.oracle_apply_D.argtypes = [P, P, d, P, P, P, P]
+        L.oracle_apply_Dblock.argtypes = [P, P, P, d, P, P, i, P, P]
         L.oracle_apply_Dhop.argtypes = [P, P, P, d, P, i, P, P]
         L.oracle_apply_Dee.argtypes = [P, P, P, d, P, i, P, P]
         L.oracle_mul_g5.argtypes = [ctypes.c_long, P, P]
-        L.oracle_cgne.argtypes = [P, P, P, d, P, i, i, P, P, P, d, i, P]
+        L.oracle_cgne.argtypes = [P, P, P, d, P, P, i, i, P, P, P, d, i, P]
         L.oracle_cgne.restype = i
         L.oracle_sap.argtypes = [P, P, P, d, P, i, i, P, P]
         L.oracle_philox4x64_10.argtypes = [P, P, P]
@@ -88,6 +95,11 @@ def lib():
 
 def _p(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _pc(clov):
+    """Pointer to a clover term [V, 12, 12] (complex128), or NULL."""
+    return None if clov is None else _p(clov)
 
 
 def _i4(v):
@@ -234,20 +246,24 @@ def g5(psi: np.ndarray) -> np.ndarray:
     return out
 
 
-def apply_D(lat: Lattice, U, kappa: float, psi) -> np.ndarray:
+def apply_D(lat: Lattice, U, kappa: float, psi, clov=None) -> np.ndarray:
+    """D psi; with clov (clover_term) the diagonal is 1 + T(x)."""
     U, psi = _c(U), _c(psi)
+    clov = None if clov is None else _c(clov)
     out = np.empty_like(psi)
     L, _, bc = lat.arrays()
-    lib().oracle_apply_D(_p(L), _p(bc), kappa, _p(U), _p(psi), _p(out))
+    lib().oracle_apply_D(_p(L), _p(bc), kappa, _p(U), _pc(clov), _p(psi), _p(out))
     return out
 
 
-def apply_Dblock(lat: Lattice, U, kappa: float, psi, colour: int) -> np.ndarray:
-    """D_bb (colour 0), D_ww (colour 1) or both (2): Dirichlet block operators."""
+def apply_Dblock(lat: Lattice, U, kappa: float, psi, colour: int, clov=None) -> np.ndarray:
+    """D_bb (colour 0), D_ww (colour 1) or both (2): Dirichlet block operators
+    (their diagonal is that of D, with the clover term when clov is given)."""
     U, psi = _c(U), _c(psi)
+    clov = None if clov is None else _c(clov)
     out = np.empty_like(psi)
     L, B, bc = lat.arrays()
-    lib().oracle_apply_Dblock(_p(L), _p(B), _p(bc), kappa, _p(U), colour, _p(psi), _p(out))
+    lib().oracle_apply_Dblock(_p(L), _p(B), _p(bc), kappa, _p(U), _pc(clov), colour, _p(psi), _p(out))
     return out
 
 
@@ -269,6 +285,75 @@ def apply_Dee(lat: Lattice, U, kappa: float, psi, blocked: bool = False) -> np.n
     return out
 
 
+# ----------------------------------------------------------------------------
+# Clover term (Sheikholeslami-Wohlert).  Sec. 3 defines the active links for
+# Wilson fermions with clover term and Sec. 7 names the clover action as the
+# next one; the paper does not write the term out, so this is the standard
+# one (Sheikholeslami and Wohlert, Nucl. Phys. B 259 (1985) 572; Luscher,
+# Sint, Sommer and Weisz, Nucl. Phys. B 478 (1996) 365), in the hopping
+# normalisation of D = 1 - kappa H used here:
+#     D = 1 + T - kappa H,   T(x) = c_sw kappa (i/2) sum_{mu,nu} sigma_{mu nu} Fhat_{mu nu}(x),
+#     sigma_{mu nu} = (i/2) [gamma_mu, gamma_nu],
+#     Fhat_{mu nu}(x) = (Q_{mu nu}(x) - Q_{nu mu}(x)) / 8,
+# Q_{mu nu}(x) the sum of the four plaquettes of the (mu, nu) plane that
+# begin and end at x, each run mu-side first.  The gauge loops are closed, so
+# the fermion boundary phases do not enter.
+
+
+def sigma(mu: int, nu: int) -> np.ndarray:
+    """sigma_{mu nu} = (i/2) [gamma_mu, gamma_nu] (4 x 4)."""
+    a, b = gamma(mu), gamma(nu)
+    return 0.5j * (a @ b - b @ a)
+
+
+def _nbr(lat: Lattice, mu: int, d: int) -> np.ndarray:
+    """Canonical index of x + d mu-hat for every site x (periodic)."""
+    x = lat.coords()
+    x[:, mu] = (x[:, mu] + d) % lat.L[mu]
+    return x[:, 0] + lat.L[0] * (x[:, 1] + lat.L[1] * (x[:, 2] + lat.L[2] * x[:, 3]))
+
+
+def clover_leaves(lat: Lattice, U, mu: int, nu: int) -> np.ndarray:
+    """Q_{mu nu}(x) [V, 3, 3]: the four plaquettes of the (mu, nu) plane at x,
+    each a closed path from x, taken in the same sense of rotation."""
+    U = _c(U)
+    dag = lambda m: np.conj(np.swapaxes(m, -1, -2))
+    Um, Un = U[:, mu], U[:, nu]
+    fm, bm, fn, bn = _nbr(lat, mu, 1), _nbr(lat, mu, -1), _nbr(lat, nu, 1), _nbr(lat, nu, -1)
+    bm_fn = fn[bm]  # x - mu + nu
+    bm_bn = bn[bm]  # x - mu - nu
+    fm_bn = bn[fm]  # x + mu - nu
+    # x -> x+mu -> x+mu+nu -> x+nu -> x
+    Q = Um @ Un[fm] @ dag(Um[fn]) @ dag(Un)
+    # x -> x+nu -> x-mu+nu -> x-mu -> x
+    Q = Q + Un @ dag(Um[bm_fn]) @ dag(Un[bm]) @ Um[bm]
+    # x -> x-mu -> x-mu-nu -> x-nu -> x
+    Q = Q + dag(Um[bm]) @ dag(Un[bm_bn]) @ Um[bm_bn] @ Un[bn]
+    # x -> x-nu -> x+mu-nu -> x+mu -> x
+    Q = Q + dag(Un[bn]) @ Um[bn] @ Un[fm_bn] @ dag(Um)
+    return Q
+
+
+def field_strength(lat: Lattice, U, mu: int, nu: int) -> np.ndarray:
+    """Fhat_{mu nu}(x) = (Q_{mu nu} - Q_{nu mu}) / 8 [V, 3, 3]."""
+    return (clover_leaves(lat, U, mu, nu) - clover_leaves(lat, U, nu, mu)) / 8.0
+
+
+def clover_term(lat: Lattice, U, csw: float, kappa: float) -> np.ndarray:
+    """T(x) = c_sw kappa (i/2) sum_{mu != nu} sigma_{mu nu} (x) Fhat_{mu nu}(x)
+    as [V, 12, 12], row and column index 3 * spin + colour (the layout of
+    psi[V, 4, 3] flattened), so that (1 + T(x)) psi(x) is the diagonal term
+    of D."""
+    T = np.zeros((lat.V, 4, 3, 4, 3), dtype=np.complex128)
+    for mu in range(4):
+        for nu in range(4):
+            if mu == nu:
+                continue
+            F = field_strength(lat, U, mu, nu)
+            T += np.einsum("st,xab->xsatb", sigma(mu, nu), F)
+    return (csw * kappa * 0.5j) * T.reshape(lat.V, 12, 12)
+
+
 def colour_mask(lat: Lattice, colour: int) -> np.ndarray:
     _, col, _ = lat.maps()
     return col == colour
@@ -283,17 +368,18 @@ class NoConvergence(RuntimeError):
 
 
 def solve(lat: Lattice, U, kappa: float, b, op: str = "full", colour: int = 2, tol: float = 1e-13,
-          maxit: int = 100000):
+          maxit: int = 100000, clov=None):
     """Solve A x = b, A = D (op 'full') or the Dirichlet blocks of one colour
-    (op 'block'), by CG on A A^+ y = b.  Returns (x, y, iterations, true
-    relative residual)."""
+    (op 'block'), with the clover term clov when given, by CG on A A^+ y = b.
+    Returns (x, y, iterations, true relative residual)."""
     U, b = _c(U), _c(b)
+    clov = None if clov is None else _c(clov)
     x = np.empty_like(b)
     y = np.empty_like(b)
     res = ctypes.c_double()
     L, B, bc = lat.arrays()
-    it = lib().oracle_cgne(_p(L), _p(B), _p(bc), kappa, _p(U), 0 if op == "full" else 1, colour, _p(b), _p(x),
-                           _p(y), tol, maxit, ctypes.byref(res))
+    it = lib().oracle_cgne(_p(L), _p(B), _p(bc), kappa, _p(U), _pc(clov), 0 if op == "full" else 1, colour, _p(b),
+                           _p(x), _p(y), tol, maxit, ctypes.byref(res))
     if it < 0:
         raise NoConvergence("oracle CGNE did not reach %g (residual %g)" % (tol, res.value))
     return x, y, it, res.value
@@ -309,16 +395,16 @@ def sap(lat: Lattice, U, kappa: float, eta, ncy: int, nmr: int) -> np.ndarray:
     return x
 
 
-def schur_apply(lat: Lattice, U, kappa: float, eta, block_tol: float = 1e-14) -> np.ndarray:
+def schur_apply(lat: Lattice, U, kappa: float, eta, block_tol: float = 1e-14, clov=None) -> np.ndarray:
     """Dhat eta = eta - D_bb^-1 D_bw D_ww^-1 D_wb eta on black sites
     (Sec. 3, eq. ddfactor).  White sites of the result are zero."""
     black = colour_mask(lat, 0)
     e = _c(eta).copy()
     e[~black] = 0
-    t = apply_Dhop(lat, U, kappa, e, from_colour=0)            # D_wb eta   (white)
-    t, _, _, _ = solve(lat, U, kappa, t, "block", 1, block_tol)  # D_ww^-1   (white)
-    t = apply_Dhop(lat, U, kappa, t, from_colour=1)            # D_bw ...   (black)
-    t, _, _, _ = solve(lat, U, kappa, t, "block", 0, block_tol)  # D_bb^-1   (black)
+    t = apply_Dhop(lat, U, kappa, e, from_colour=0)                        # D_wb eta   (white)
+    t, _, _, _ = solve(lat, U, kappa, t, "block", 1, block_tol, clov=clov)  # D_ww^-1   (white)
+    t = apply_Dhop(lat, U, kappa, t, from_colour=1)                        # D_bw ...   (black)
+    t, _, _, _ = solve(lat, U, kappa, t, "block", 0, block_tol, clov=clov)  # D_bb^-1   (black)
     out = e - t
     out[~black] = 0
     return out
@@ -400,10 +486,12 @@ def _dot(a, b) -> complex:
     return complex(np.vdot(a.ravel(), b.ravel()))
 
 
-def sample(lat: Lattice, U0, U1, kappa: float, op: int, eta, tol: float = 1e-13, block_tol: float = 1e-14):
+def sample(lat: Lattice, U0, U1, kappa: float, op: int, eta, tol: float = 1e-13, block_tol: float = 1e-14,
+           csw: float = 0.0):
     """One sample s = -eta^+ (M^+ M - 1) eta, M = X'^-1 X with X = D (FULL),
     X = the Dirichlet blocks (BLOCKS, one value per block) or X = Dhat
-    (SCHUR), X built on U0 and X' on U1 (Sec. 4).
+    (SCHUR), X built on U0 and X' on U1 (Sec. 4); csw != 0 adds the clover
+    term with that coefficient to D (and so to its blocks and Dhat).
 
     E over complex Gaussian eta of exp(s) is det(M^+ M)^-1 =
     det(X'^+ X') / det(X^+ X), the ratio the acceptance step needs.
@@ -418,32 +506,34 @@ def sample(lat: Lattice, U0, U1, kappa: float, op: int, eta, tol: float = 1e-13,
     whose separate rounding would cost up to ~1e-8 absolute at 32^4.
     """
     eta = _c(eta)
+    c0 = clover_term(lat, U0, csw, kappa) if csw else None
+    c1 = clover_term(lat, U1, csw, kappa) if csw else None
     if op == OP_FULL:
-        y = apply_D(lat, U0, kappa, eta)
-        z, w, _, _ = solve(lat, U1, kappa, y, "full", 2, tol)
+        y = apply_D(lat, U0, kappa, eta, c0)
+        z, w, _, _ = solve(lat, U1, kappa, y, "full", 2, tol, clov=c1)
         # with CGNE, z = A'^+ w exactly, so w solves A'^+ w = z
-        r = y - apply_D(lat, U1, kappa, z)
+        r = y - apply_D(lat, U1, kappa, z, c1)
         return math.fsum(_site_terms(eta, z, w, r))
     if op == OP_BLOCKS:
         bid, _, _ = lat.maps()
-        y = apply_Dblock(lat, U0, kappa, eta, 2)
-        z, w, _, _ = solve(lat, U1, kappa, y, "block", 2, block_tol)
-        r = y - apply_Dblock(lat, U1, kappa, z, 2)
+        y = apply_Dblock(lat, U0, kappa, eta, 2, c0)
+        z, w, _, _ = solve(lat, U1, kappa, y, "block", 2, block_tol, clov=c1)
+        r = y - apply_Dblock(lat, U1, kappa, z, 2, c1)
         per_site = _site_terms(eta, z, w, r)
         return np.array([math.fsum(per_site[bid == b]) for b in range(lat.nblocks)])
     if op == OP_SCHUR:
         black = colour_mask(lat, 0)
         e = eta.copy()
         e[~black] = 0
-        phi = schur_apply(lat, U0, kappa, e, block_tol)
-        y = apply_Dblock(lat, U1, kappa, phi, 0)               # A' Dhat eta, black
-        z, _, _, _ = solve(lat, U1, kappa, y, "full", 2, tol)  # D' z = [y; 0]
+        phi = schur_apply(lat, U0, kappa, e, block_tol, clov=c0)
+        y = apply_Dblock(lat, U1, kappa, phi, 0, c1)                     # A' Dhat eta, black
+        z, _, _, _ = solve(lat, U1, kappa, y, "full", 2, tol, clov=c1)   # D' z = [y; 0]
         pz = z.copy()
         pz[~black] = 0
         # adjoint: D'^+ w = P z  <=>  D' (g5 w) = g5 P z
-        v, _, _, _ = solve(lat, U1, kappa, g5(pz), "full", 2, tol)
+        v, _, _, _ = solve(lat, U1, kappa, g5(pz), "full", 2, tol, clov=c1)
         w = g5(v)
-        r = y - apply_D(lat, U1, kappa, z)
+        r = y - apply_D(lat, U1, kappa, z, c1)
         return math.fsum(_site_terms(e, pz, w, r))
     raise ValueError("unknown operator")
 
@@ -471,10 +561,10 @@ def combine(samples: np.ndarray) -> np.ndarray:
 
 
 def logdet_ratio(lat: Lattice, U, Up, kappa: float, op: int, n_steps: int, n_noise: int, kind: int, seed: int,
-                 tol: float = 1e-13, block_tol: float = 1e-14):
+                 tol: float = 1e-13, block_tol: float = 1e-14, csw: float = 0.0):
     """Stochastic estimate of log det(X'^+ X') / det(X^+ X) along the path
-    U_0 = U ... U_N = U' (eq. param), one noise vector per factor and sample.
-    Returns (samples, log Rhat)."""
+    U_0 = U ... U_N = U' (eq. param), one noise vector per factor and sample;
+    csw != 0: with the clover term.  Returns (samples, log Rhat)."""
     support = noise_support(lat, op)
     shape = (n_steps, n_noise) + ((lat.nblocks,) if op == OP_BLOCKS else ())
     samples = np.zeros(shape)
@@ -483,7 +573,7 @@ def logdet_ratio(lat: Lattice, U, Up, kappa: float, op: int, n_steps: int, n_noi
         Ui1 = interpolate(U, Up, i + 1, n_steps)
         for k in range(n_noise):
             eta = noise(lat, kind, seed, i, k, support)
-            samples[i, k] = sample(lat, Ui, Ui1, kappa, op, eta, tol, block_tol)
+            samples[i, k] = sample(lat, Ui, Ui1, kappa, op, eta, tol, block_tol, csw)
         Ui = Ui1
     return samples, combine(samples)
 
@@ -512,11 +602,13 @@ def log_abs_det(M: np.ndarray) -> float:
     return float(ld)
 
 
-def exact_log_ratio(lat: Lattice, U, Up, kappa: float) -> float:
+def exact_log_ratio(lat: Lattice, U, Up, kappa: float, csw: float = 0.0) -> float:
     """log det(D'^+ D') - log det(D^+ D) = 2 (log|det D'| - log|det D|) by
-    dense LU (Sec. 2, two-step acceptance)."""
-    D0 = dense(lambda v: apply_D(lat, U, kappa, v), lat.V)
-    D1 = dense(lambda v: apply_D(lat, Up, kappa, v), lat.V)
+    dense LU (Sec. 2, two-step acceptance); csw != 0: with the clover term."""
+    c0 = clover_term(lat, U, csw, kappa) if csw else None
+    c1 = clover_term(lat, Up, csw, kappa) if csw else None
+    D0 = dense(lambda v: apply_D(lat, U, kappa, v, c0), lat.V)
+    D1 = dense(lambda v: apply_D(lat, Up, kappa, v, c1), lat.V)
     return 2.0 * (log_abs_det(D1) - log_abs_det(D0))
 
 

@@ -20,6 +20,11 @@
  * with the spin matrices applied as full 4x4 matrices (no projection trick).
  * A hop that wraps around the lattice in direction mu is multiplied by bc[mu].
  *
+ * With the clover term (Sheikholeslami-Wohlert; Sec. 3 names Wilson fermions
+ * with clover term, Sec. 7 the clover action) the diagonal 1 becomes 1 + T(x),
+ * T(x) a 12 x 12 matrix per site built in core.py from its definition and
+ * passed in as clov[site][12][12] (row 3*spin + colour); NULL means no term.
+ *
  * Domain decomposition (paper Sec. 3, eq. domdec): non-overlapping blocks of
  * extent B[mu]; the block colour is (sum_mu floor(x_mu/B_mu)) mod 2, black =
  * 0.  D_b keeps only hops whose both ends lie in block b (Dirichlet
@@ -148,8 +153,9 @@ void oracle_site_maps(const int *L, const int *B, int32_t *block_id, int32_t *co
 /* ------------------------------------------------------------------ */
 /* Generic hopping operator.
  *
- *   out(x) = diag * in(x) - kappa * sum over selected hops (x <- y)
+ *   out(x) = diag * (1 + T(x)) in(x) - kappa * sum over selected hops (x <- y)
  *
+ * with T = 0 when clov is NULL.
  * selection:
  *   hops      0 = every hop, 1 = only hops inside a block, 2 = only hops
  *             that cross a block boundary
@@ -161,8 +167,8 @@ void oracle_site_maps(const int *L, const int *B, int32_t *block_id, int32_t *co
  */
 enum { HOPS_ALL = 0, HOPS_IN_BLOCK = 1, HOPS_CROSS = 2 };
 
-static void wilson_generic(const geom_t *g, double kappa, const cplx *U, const cplx *in, cplx *out,
-                           int diag, int hops, int out_col, int in_col, int out_par, int in_par)
+static void wilson_generic(const geom_t *g, double kappa, const cplx *U, const cplx *clov, const cplx *in,
+                           cplx *out, int diag, int hops, int out_col, int in_col, int out_par, int in_par)
 {
 #pragma omp parallel for schedule(static) if (g->V >= OMP_MIN_SITES)
     for (long s = 0; s < g->V; ++s) {
@@ -175,6 +181,11 @@ static void wilson_generic(const geom_t *g, double kappa, const cplx *U, const c
         }
         for (int sp = 0; sp < 4; ++sp)
             for (int a = 0; a < 3; ++a) acc[sp][a] = diag ? in[12 * s + 3 * sp + a] : 0;
+        if (diag && clov) {
+            const cplx *Tx = clov + 144 * s;
+            for (int i = 0; i < 12; ++i)
+                for (int j = 0; j < 12; ++j) acc[i / 3][i % 3] += Tx[12 * i + j] * in[12 * s + j];
+        }
 
         for (int mu = 0; mu < 4; ++mu) {
             for (int dir = +1; dir >= -1; dir -= 2) {
@@ -218,20 +229,22 @@ static void wilson_generic(const geom_t *g, double kappa, const cplx *U, const c
     }
 }
 
-/* full D */
-void oracle_apply_D(const int *L, const int *bc, double kappa, const double *U, const double *in, double *out)
+/* full D (clov: clover term or NULL) */
+void oracle_apply_D(const int *L, const int *bc, double kappa, const double *U, const double *clov, const double *in,
+                    double *out)
 {
     geom_t g = make_geom(L, NULL, bc);
-    wilson_generic(&g, kappa, (const cplx *)U, (const cplx *)in, (cplx *)out, 1, HOPS_ALL, -1, -1, -1, -1);
+    wilson_generic(&g, kappa, (const cplx *)U, (const cplx *)clov, (const cplx *)in, (cplx *)out, 1, HOPS_ALL, -1,
+                   -1, -1, -1);
 }
 
 /* block-diagonal Dirichlet operator on the blocks of one colour (0 black,
  * 1 white, 2 both); zero on the sites of the other colour. */
-void oracle_apply_Dblock(const int *L, const int *B, const int *bc, double kappa, const double *U, int colour,
-                         const double *in, double *out)
+void oracle_apply_Dblock(const int *L, const int *B, const int *bc, double kappa, const double *U,
+                         const double *clov, int colour, const double *in, double *out)
 {
     geom_t g = make_geom(L, B, bc);
-    wilson_generic(&g, kappa, (const cplx *)U, (const cplx *)in, (cplx *)out, 1, HOPS_IN_BLOCK,
+    wilson_generic(&g, kappa, (const cplx *)U, (const cplx *)clov, (const cplx *)in, (cplx *)out, 1, HOPS_IN_BLOCK,
                    colour == 2 ? -1 : colour, -1, -1, -1);
 }
 
@@ -241,7 +254,7 @@ void oracle_apply_Dhop(const int *L, const int *B, const int *bc, double kappa, 
                        const double *in, double *out)
 {
     geom_t g = make_geom(L, B, bc);
-    wilson_generic(&g, kappa, (const cplx *)U, (const cplx *)in, (cplx *)out, 0, HOPS_CROSS, 1 - from_colour,
+    wilson_generic(&g, kappa, (const cplx *)U, NULL, (const cplx *)in, (cplx *)out, 0, HOPS_CROSS, 1 - from_colour,
                    from_colour, -1, -1);
 }
 
@@ -257,8 +270,8 @@ void oracle_apply_Dee(const int *L, const int *B, const int *bc, double kappa, c
     cplx *u = calloc(n, sizeof(cplx));
     int hops = blocked ? HOPS_IN_BLOCK : HOPS_ALL;
     /* t = -kappa H_oe psi_e ; u = -kappa H_eo t = kappa^2 H_eo H_oe psi_e */
-    wilson_generic(&g, kappa, (const cplx *)U, (const cplx *)in, t, 0, hops, -1, -1, 1, 0);
-    wilson_generic(&g, kappa, (const cplx *)U, t, u, 0, hops, -1, -1, 0, 1);
+    wilson_generic(&g, kappa, (const cplx *)U, NULL, (const cplx *)in, t, 0, hops, -1, -1, 1, 0);
+    wilson_generic(&g, kappa, (const cplx *)U, NULL, t, u, 0, hops, -1, -1, 0, 1);
     const cplx *psi = (const cplx *)in;
     cplx *o = (cplx *)out;
     for (long s = 0; s < g.V; ++s) {
@@ -302,21 +315,22 @@ static double norm2(long n, const cplx *a) { return creal(dot(n, a, a)); }
 typedef struct {
     const geom_t *g;
     double kappa;
-    const cplx *U;
+    const cplx *U, *clov;
     int op, colour;
 } opdesc_t;
 
 static void op_apply(const opdesc_t *o, const cplx *in, cplx *out)
 {
     if (o->op == 0)
-        wilson_generic(o->g, o->kappa, o->U, in, out, 1, HOPS_ALL, -1, -1, -1, -1);
+        wilson_generic(o->g, o->kappa, o->U, o->clov, in, out, 1, HOPS_ALL, -1, -1, -1, -1);
     else
-        wilson_generic(o->g, o->kappa, o->U, in, out, 1, HOPS_IN_BLOCK, o->colour == 2 ? -1 : o->colour, -1, -1,
-                       -1);
+        wilson_generic(o->g, o->kappa, o->U, o->clov, in, out, 1, HOPS_IN_BLOCK, o->colour == 2 ? -1 : o->colour,
+                       -1, -1, -1);
 }
 
 /* A^+ = g5 A g5 (gamma_5-hermiticity of the Wilson operator and of its
- * Dirichlet block restriction) */
+ * Dirichlet block restriction; the clover term is hermitian and commutes
+ * with gamma_5, so it keeps the property) */
 static void op_apply_dag(const opdesc_t *o, const cplx *in, cplx *out, cplx *tmp)
 {
     mul_g5(o->g->V, in, tmp);
@@ -332,11 +346,11 @@ static void op_apply_dag(const opdesc_t *o, const cplx *in, cplx *out, cplx *tmp
  * maxit was reached.  On return y holds the normal-equation solution, x =
  * A^+ y and *rel_resid the true relative residual.
  */
-int oracle_cgne(const int *L, const int *B, const int *bc, double kappa, const double *Ud, int op, int colour,
-                const double *bd, double *xd, double *yd, double tol, int maxit, double *rel_resid)
+int oracle_cgne(const int *L, const int *B, const int *bc, double kappa, const double *Ud, const double *clov, int op,
+                int colour, const double *bd, double *xd, double *yd, double tol, int maxit, double *rel_resid)
 {
     geom_t g = make_geom(L, B, bc);
-    opdesc_t o = {&g, kappa, (const cplx *)Ud, op, colour};
+    opdesc_t o = {&g, kappa, (const cplx *)Ud, (const cplx *)clov, op, colour};
     long n = 12 * g.V;
     const cplx *b = (const cplx *)bd;
     cplx *x = (cplx *)xd, *y = (cplx *)yd;
@@ -422,7 +436,7 @@ static void mr_blocks_eo(const geom_t *g, double kappa, const cplx *U, int colou
     double *den = calloc(nblk, sizeof(double));
 
     /* t = -kappa H_eo r_o (in-block), rhs_e = r_e - t */
-    wilson_generic(g, kappa, U, r, t, 0, HOPS_IN_BLOCK, colour, -1, 0, 1);
+    wilson_generic(g, kappa, U, NULL, r, t, 0, HOPS_IN_BLOCK, colour, -1, 0, 1);
     for (long s = 0; s < g->V; ++s) {
         int x[4];
         coords(g, s, x);
@@ -435,8 +449,8 @@ static void mr_blocks_eo(const geom_t *g, double kappa, const cplx *U, int colou
     }
     for (int k = 0; k < nmr; ++k) {
         /* p = rho - kappa^2 H_eo H_oe rho (in-block) */
-        wilson_generic(g, kappa, U, rho, t, 0, HOPS_IN_BLOCK, colour, -1, 1, 0);
-        wilson_generic(g, kappa, U, t, u, 0, HOPS_IN_BLOCK, colour, -1, 0, 1);
+        wilson_generic(g, kappa, U, NULL, rho, t, 0, HOPS_IN_BLOCK, colour, -1, 1, 0);
+        wilson_generic(g, kappa, U, NULL, t, u, 0, HOPS_IN_BLOCK, colour, -1, 0, 1);
         for (long i = 0; i < n; ++i) p[i] = rho[i] - u[i];
         for (long b = 0; b < nblk; ++b) num[b] = 0, den[b] = 0;
         for (long s = 0; s < g->V; ++s)
@@ -453,7 +467,7 @@ static void mr_blocks_eo(const geom_t *g, double kappa, const cplx *U, int colou
         }
     }
     /* d_o = r_o + kappa H_oe d_e = r_o - t, t = -kappa H_oe d_e (in-block) */
-    wilson_generic(g, kappa, U, d, t, 0, HOPS_IN_BLOCK, colour, -1, 1, 0);
+    wilson_generic(g, kappa, U, NULL, d, t, 0, HOPS_IN_BLOCK, colour, -1, 1, 0);
     for (long s = 0; s < g->V; ++s) {
         int x[4];
         coords(g, s, x);
@@ -491,7 +505,7 @@ void oracle_sap(const int *L, const int *B, const int *bc, double kappa, const d
     for (long i = 0; i < n; ++i) x[i] = 0;
     for (int cy = 0; cy < ncy; ++cy)
         for (int c = 0; c < 2; ++c) {
-            wilson_generic(&g, kappa, U, x, Dx, 1, HOPS_ALL, -1, -1, -1, -1);
+            wilson_generic(&g, kappa, U, NULL, x, Dx, 1, HOPS_ALL, -1, -1, -1, -1);
             for (long s = 0; s < g.V; ++s)
                 for (int a = 0; a < 12; ++a) r[12 * s + a] = col[s] == c ? eta[12 * s + a] - Dx[12 * s + a] : 0;
             mr_blocks_eo(&g, kappa, U, c, nmr, r, d, blk, nblk);
