@@ -213,6 +213,32 @@ wdr_status wdr_gauge_destroy(wdr_gauge *g);
  * the paths that read all nine entries. */
 int32_t wdr_gauge_is_su3(const wdr_gauge *g);
 
+/* Attach the clover (Sheikholeslami-Wohlert) term to U: Sec. 3 defines the
+ * active links for Wilson fermions with clover term and Sec. 7 names the
+ * clover action.  The paper does not write the term out; it is the standard
+ * one in the hopping normalisation of D = 1 - kappa H:
+ *     D = A - kappa H,  A(x) = 1 + c_sw kappa (i/2) sum_{mu,nu} sigma_{mu nu} Fhat_{mu nu}(x),
+ *     sigma_{mu nu} = (i/2) [gamma_mu, gamma_nu],  Fhat_{mu nu} = (Q_{mu nu} - Q_{nu mu}) / 8,
+ * Q_{mu nu}(x) the four plaquettes of the (mu, nu) plane at x (the clover
+ * leaves).  The handle then keeps A and A^-1 (two hermitian 6 x 6 blocks per
+ * site, FP64 and FP32: 1728 bytes per site) built for this csw and kappa, and
+ * every call that takes U applies the clover operator: D, D_b and D_ee in F64
+ * / F32 (wdr_apply_D, wdr_apply_D_internal, wdr_apply_D_noalloc,
+ * wdr_apply_Dblock, wdr_apply_Dee; the hops of wdr_apply_Dhop have no
+ * diagonal term), wdr_solve with CGNE and an F64 / F32 inner level, and FULL
+ * estimates by such solves (wdr_logdet_ratio / _batch; both fields of a ratio
+ * must carry the same csw).  Those calls must pass this kappa (EINVAL
+ * otherwise); every other call taking U returns EINVAL.  csw = 0 removes the
+ * term.  EINVAL also for a context with open boundaries (bc = 0) and when a
+ * block of A is (nearly) singular (its LDL^H pivots are checked).  Waits for
+ * the device: launches queued on U may still read the previous term. */
+wdr_status wdr_gauge_set_clover(wdr_ctx *ctx, wdr_gauge *U, double csw, double kappa, void *stream);
+
+/* A (inverse 0) or A^-1 (inverse 1) of U's clover term as canonical
+ * [V][12][12] complex in device memory dev_out (row and column 3 * spin +
+ * colour, chiral basis); EINVAL if U carries no clover term. */
+wdr_status wdr_clover_field(wdr_ctx *ctx, const wdr_gauge *U, int32_t inverse, double *dev_out, void *stream);
+
 /* Path of eq. param: out = U_i = exp((i/N) log(U' U^+)) U link by link
  * (geodesic with the traceless branch of the logarithm; U_0 = U and U_N = U'
  * exactly; links with U' == U copied). dev_out: canonical, V*4*9 complex. */

@@ -39,7 +39,9 @@ wdr_status pre(wdr_ctx *c, const void *a, const void *b)
     return WDR_OK;
 }
 
-wdr_status check_gauge(const wdr_ctx *c, const wdr_gauge *U)
+// clover_ok: the call supports gauge fields that carry a clover term, whose
+// hopping parameter must then be kappa; every other call refuses them
+wdr_status check_gauge(const wdr_ctx *c, const wdr_gauge *U, bool clover_ok = false, double kappa = 0)
 {
     if (!U) {
         set_error("null gauge handle");
@@ -48,6 +50,33 @@ wdr_status check_gauge(const wdr_ctx *c, const wdr_gauge *U)
     if (U->ctx != c) {
         set_error("gauge handle belongs to another context");
         return WDR_ESTATE;
+    }
+    if (U->c64) {
+        if (!clover_ok) {
+            set_error("this call does not support a gauge field with a clover term (supported: D, D_b, the block "
+                      "hops and D_ee in F64 / F32, CGNE solves with F64 / F32 inner precision, FULL estimates by "
+                      "such solves)");
+            return WDR_EINVAL;
+        }
+        if (kappa != U->ckappa) {
+            set_error("kappa differs from the hopping parameter the clover term was built with");
+            return WDR_EINVAL;
+        }
+    }
+    return WDR_OK;
+}
+
+// an estimate supports the clover term for the FULL ratio by CGNE with an
+// FP64 or FP32 inner level
+bool clover_est_ok(const wdr_est_params *p)
+{
+    return p && p->op == WDR_OP_FULL && p->sp.solver == WDR_SOLVER_CGNE && p->sp.inner != WDR_F16;
+}
+wdr_status check_pair(const wdr_gauge *U, const wdr_gauge *Up)
+{
+    if (U->csw != Up->csw) {
+        set_error("the two gauge fields of a ratio must carry the same clover coefficient");
+        return WDR_EINVAL;
     }
     return WDR_OK;
 }
@@ -87,9 +116,20 @@ wdr_status with_fields(wdr_ctx *c, const double *in, double *out, hipStream_t s,
     return finish(s);
 }
 
-template <typename T> Links<T> links(const wdr_gauge *U);
-template <> Links<double> links<double>(const wdr_gauge *U) { return view(U).u64; }
-template <> Links<float> links<float>(const wdr_gauge *U) { return view(U).u32; }
+// the links of U in precision T, with clover mode cmode for a clover term
+template <typename T> Links<T> links(const wdr_gauge *U, int cmode = CLOV_DIAG);
+template <> Links<double> links<double>(const wdr_gauge *U, int cmode)
+{
+    Links<double> L = view(U).u64;
+    L.cmode = cmode;
+    return L;
+}
+template <> Links<float> links<float>(const wdr_gauge *U, int cmode)
+{
+    Links<float> L = view(U).u32;
+    L.cmode = cmode;
+    return L;
+}
 
 template <typename T>
 wdr_status stencil_call(wdr_ctx *c, const wdr_gauge *U, double kappa, int kind, int arg, const double *in,
@@ -110,10 +150,10 @@ wdr_status stencil_call(wdr_ctx *c, const wdr_gauge *U, double kappa, int kind, 
             int s0, n;
             colour_slots(c, 1 - arg, s0, n);
             launch_dslash<T>(g, one, links<T>(U), HOPS_CROSS, -1, 0, a, nullptr, b, k, s0, n, s);
-        } else {  // even-odd reduced, blocked = arg
+        } else {  // even-odd reduced, blocked = arg: A_ee - kappa^2 H_eo A_oo^-1 H_oe
             Work t(c, field_bytes(c, sizeof(T) == 8 ? WDR_F64 : WDR_F32));
             const int hops = arg ? HOPS_IN : HOPS_ALL;
-            launch_dslash<T>(g, one, links<T>(U), hops, 1, 0, a, nullptr, t.as<T2>(), k, 0, g.nblk, s);
+            launch_dslash<T>(g, one, links<T>(U, CLOV_INV), hops, 1, 0, a, nullptr, t.as<T2>(), k, 0, g.nblk, s);
             launch_dslash<T>(g, one, links<T>(U), hops, 0, 0, t.as<T2>(), a, b, (T)(-kappa), 0, g.nblk, s);
         }
     });
@@ -124,7 +164,7 @@ wdr_status stencil_entry(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr_prec 
 {
     wdr_status e = pre(c, in, out);
     if (e != WDR_OK) return e;
-    if ((e = check_gauge(c, U)) != WDR_OK) return e;
+    if ((e = check_gauge(c, U, prec == WDR_F64 || prec == WDR_F32, kappa)) != WDR_OK) return e;
     if ((e = check_kappa(kappa)) != WDR_OK) return e;
     if ((kind == 1 || kind == 2) && (e = check_blocks_usable(c, false)) != WDR_OK) return e;
     if (prec == WDR_F64) return stencil_call<double>(c, U, kappa, kind, arg, in, out, S(stream));
@@ -403,7 +443,9 @@ wdr_status wdr_apply_D_internal(wdr_ctx *c, const wdr_gauge *U, double kappa, wd
 {
     wdr_status e = pre(c, in, out);
     if (e != WDR_OK) return e;
-    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
+    if ((e = check_gauge(c, U, prec == WDR_F64 || prec == WDR_F32, kappa)) != WDR_OK ||
+        (e = check_kappa(kappa)) != WDR_OK)
+        return e;
     if (in == out) {
         set_error("in and out must not alias");
         return WDR_EINVAL;
@@ -411,11 +453,11 @@ wdr_status wdr_apply_D_internal(wdr_ctx *c, const wdr_gauge *U, double kappa, wd
     const Geo &g = c->g;
     Sys one = all_sys(c, 1);
     if (prec == WDR_F64)
-        launch_dslash<double>(g, one, view(U).u64, HOPS_ALL, -1, 0, static_cast<const double2 *>(in),
+        launch_dslash<double>(g, one, links<double>(U), HOPS_ALL, -1, 0, static_cast<const double2 *>(in),
                               static_cast<const double2 *>(in), static_cast<double2 *>(out), kappa, 0, g.nblk,
                               S(stream));
     else if (prec == WDR_F32)
-        launch_dslash<float>(g, one, view(U).u32, HOPS_ALL, -1, 0, static_cast<const float2 *>(in),
+        launch_dslash<float>(g, one, links<float>(U), HOPS_ALL, -1, 0, static_cast<const float2 *>(in),
                              static_cast<const float2 *>(in), static_cast<float2 *>(out), (float)kappa, 0, g.nblk,
                              S(stream));
     else if (prec == WDR_F16) {
@@ -442,7 +484,9 @@ wdr_status wdr_apply_D_noalloc(wdr_ctx *c, const wdr_gauge *U, double kappa, wdr
 {
     wdr_status e = pre(c, in, out);
     if (e != WDR_OK) return e;
-    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
+    if ((e = check_gauge(c, U, prec == WDR_F64 || prec == WDR_F32, kappa)) != WDR_OK ||
+        (e = check_kappa(kappa)) != WDR_OK)
+        return e;
     if (prec != WDR_F64 && prec != WDR_F32) {
         set_error("wdr_apply_D_noalloc computes in F64 or F32");
         return WDR_EINVAL;
@@ -537,11 +581,13 @@ wdr_status wdr_solve(wdr_ctx *c, const wdr_gauge *U, double kappa, const wdr_sol
 {
     wdr_status e = pre(c, b, x);
     if (e != WDR_OK) return e;
-    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
     if (!sp) {
         set_error("null solver parameters");
         return WDR_EINVAL;
     }
+    if ((e = check_gauge(c, U, sp->solver == WDR_SOLVER_CGNE && sp->inner != WDR_F16, kappa)) != WDR_OK ||
+        (e = check_kappa(kappa)) != WDR_OK)
+        return e;
     if ((e = check_params(c, *sp, false)) != WDR_OK) return e;
     const double t0 = now();
     std::vector<Stats> st;
@@ -614,9 +660,11 @@ wdr_status wdr_logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up,
 {
     if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
     wdr_status e;
-    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_gauge(c, Up)) != WDR_OK) return e;
-    if ((e = check_kappa(kappa)) != WDR_OK) return e;
     if ((e = check_est(c, p)) != WDR_OK) return e;
+    if ((e = check_gauge(c, U, clover_est_ok(p), kappa)) != WDR_OK ||
+        (e = check_gauge(c, Up, clover_est_ok(p), kappa)) != WDR_OK || (e = check_pair(U, Up)) != WDR_OK)
+        return e;
+    if ((e = check_kappa(kappa)) != WDR_OK) return e;
     WDR_HIP(hipSetDevice(c->device));
     const double t0 = now();
     Stats st;
@@ -641,8 +689,9 @@ wdr_status wdr_logdet_ratio_batch(int32_t n, const wdr_proposal *props, const wd
         wdr_ctx *c = props[j].ctx;
         if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
         wdr_status e;
-        if ((e = check_gauge(c, props[j].U)) != WDR_OK || (e = check_gauge(c, props[j].Up)) != WDR_OK ||
-            (e = check_kappa(props[j].kappa)) != WDR_OK)
+        if ((e = check_gauge(c, props[j].U, clover_est_ok(p), props[j].kappa)) != WDR_OK ||
+            (e = check_gauge(c, props[j].Up, clover_est_ok(p), props[j].kappa)) != WDR_OK ||
+            (e = check_pair(props[j].U, props[j].Up)) != WDR_OK || (e = check_kappa(props[j].kappa)) != WDR_OK)
             return e;
         const size_t gi = std::find(ctxs.begin(), ctxs.end(), c) - ctxs.begin();
         if (gi == ctxs.size()) {
@@ -761,8 +810,21 @@ wdr_status wdr_block_fields(wdr_ctx *c, const wdr_gauge *U, double *out, void *s
 {
     wdr_status e = pre(c, U, out);
     if (e != WDR_OK) return e;
-    if ((e = check_gauge(c, U)) != WDR_OK) return e;
+    if ((e = check_gauge(c, U, true, U->ckappa)) != WDR_OK) return e;
     launch_block_fields(c->g, c->geom.bc, U->u64, reinterpret_cast<double2 *>(out), S(stream));
+    return finish(S(stream));
+}
+
+wdr_status wdr_clover_field(wdr_ctx *c, const wdr_gauge *U, int32_t inverse, double *out, void *stream)
+{
+    wdr_status e = pre(c, U, out);
+    if (e != WDR_OK) return e;
+    if ((e = check_gauge(c, U, true, U->ckappa)) != WDR_OK) return e;
+    if (!U->c64 || (inverse != 0 && inverse != 1)) {
+        set_error(U->c64 ? "inverse must be 0 or 1" : "the gauge field carries no clover term");
+        return WDR_EINVAL;
+    }
+    launch_clover_canon(c->g, U->c64, inverse, reinterpret_cast<double2 *>(out), S(stream));
     return finish(S(stream));
 }
 

@@ -9,10 +9,13 @@
 // the rest (even-odd halves, cross-boundary hops, gamma_5-conjugated forms,
 // general links), one wavefront per direction over 64 sites of a block,
 // partial sums combined in LDS.  Both read two rows per SU(3) link and
-// rebuild the third.  Other block
+// rebuild the third.  With a clover term the diagonal term is A times the
+// diagonal input, or the whole result is multiplied by A^-1 (clover.h), in
+// the same launch.  Other block
 // shapes: k_dslash, one lane per site and 256 consecutive sites of one block
 // per workgroup.  In both, a wavefront reads each spinor / link component of
 // 64 consecutive sites as one contiguous 512 B (FP32) or 1 KiB (FP64) run.
+#include "clover.h"
 #include "stencil.h"
 
 namespace wdr {
@@ -37,10 +40,11 @@ template <typename T> struct G5Loader {
     }
 };
 
-template <typename T, int HOPS>
+template <typename T, int HOPS, int CL>
 __global__ __launch_bounds__(256) void k_dslash(Geo g, const int32_t *__restrict__ active,
                                                 const int32_t *__restrict__ list, UTab<T> Utab,
-                                                const double *__restrict__ kap, int kneg, long n,
+                                                const double *__restrict__ kap, int kneg,
+                                                const T *const *__restrict__ ctab, long n,
                                                 int par, int dag, const typename C2<T>::type *__restrict__ in,
                                                 const typename C2<T>::type *__restrict__ diag,
                                                 typename C2<T>::type *__restrict__ out, T kappa, int slot0)
@@ -64,6 +68,19 @@ __global__ __launch_bounds__(256) void k_dslash(Geo g, const int32_t *__restrict
     hop_sum<T, HOPS>(g, U, slot, l, x, G5Loader<T>{in, Vb, dag}, acc);
 
     const long base = (long)slot * 12 * Vb + l;
+    if (CL) {
+        cx<T> v[12], dg[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            v[c] = scale(-kappa, acc.s[c / 3].c[c % 3]);
+            if (dag && c >= 6) v[c] = neg(v[c]);
+            dg[c] = diag ? ld<T>(diag, base + (long)c * Vb) : mk<T>(0, 0);
+        }
+        clov_site<T, CL>(ctab[m], (long)g.V, slot, Vb, l, dg, v);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) st<T>(out, base + (long)c * Vb, v[c]);
+        return;
+    }
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -82,11 +99,14 @@ __global__ __launch_bounds__(256) void k_dslash(Geo g, const int32_t *__restrict
 // (mu is uniform per wavefront, so its spin projection is specialised at
 // compile time) and issues the loads of both hops in one round trip.  The
 // four partial sums meet in LDS; wavefront w then adds spin w of the diagonal
-// term and writes spin w of the result (contiguous over the 64 sites).
-template <typename T, int HOPS, int B, int DAG, int R2>
+// term and writes spin w of the result (contiguous over the 64 sites).  With
+// the clover term wavefront w forms both spins of its chirality and keeps
+// the rows of spin w of the block product.
+template <typename T, int HOPS, int B, int DAG, int R2, int CL>
 __global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__restrict__ active,
                                                     const int32_t *__restrict__ list, UTab<T> Utab,
-                                                    const double *__restrict__ kap, int kneg, long n,
+                                                    const double *__restrict__ kap, int kneg,
+                                                    const T *const *__restrict__ ctab, long n,
                                                     const int32_t *__restrict__ sched, int par, int chunks,
                                                     int xcd8, const T2<T> *__restrict__ in,
                                                     const T2<T> *__restrict__ diag, T2<T> *__restrict__ out, T kappa)
@@ -119,12 +139,17 @@ __global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__rest
     int nbr[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
-    // spin mu of the diagonal term, issued early
-    cx<T> dg[3] = {mk<T>(0, 0), mk<T>(0, 0), mk<T>(0, 0)};
+    // spin mu of the diagonal term (with the clover term both spins of its
+    // chirality), issued early
+    constexpr int ND = CL ? 6 : 3;
+    const int chi = mu >> 1;
+    cx<T> dg[ND];
+#pragma unroll
+    for (int a = 0; a < ND; ++a) dg[a] = mk<T>(0, 0);
     const long obase = m * n + (long)slot * 12 * Vb + l;
     if (diag) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) dg[a] = ld<T>(diag, obase + (long)(3 * mu + a) * Vb);
+        for (int a = 0; a < ND; ++a) dg[a] = ld<T>(diag, obase + (long)((CL ? 6 * chi : 3 * mu) + a) * Vb);
     }
     // boundary sign of the forward and backward links of this site when they
     // wrap around the lattice (only needed to rebuild a third row)
@@ -149,6 +174,29 @@ __global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__rest
 #pragma unroll
         for (int a = 0; a < 3; ++a) st<T>(&part[w][0][0], (3 * sp + a) * 64 + lane, acc.s[sp].c[a]);
     __syncthreads();
+    if (CL) {
+        // both spins of chirality chi over the four directions, the block
+        // product, and the three rows of spin mu
+        cx<T> v[6], x[6], y[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const int c = 6 * chi + i;
+            cx<T> t = ld<T>(&part[0][0][0], c * 64 + lane);
+#pragma unroll
+            for (int d = 1; d < 4; ++d) t = t + ld<T>(&part[d][0][0], c * 64 + lane);
+            t = scale(-kappa, t);
+            v[i] = DAG && chi ? neg(t) : t;
+            x[i] = CL == CLOV_DIAG ? dg[i % ND] : dg[i % ND] + v[i];
+        }
+        clov_mul6<T>(clov_at<T>(ctab[m], (long)g.V, CL == CLOV_INV, slot, chi, Vb, l), Vb, x, y);
+        const bool upper = mu & 1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const cx<T> yo = upper ? y[3 + a] : y[a], vo = upper ? v[3 + a] : v[a];
+            st_nt<T>(out, obase + (long)(3 * mu + a) * Vb, CL == CLOV_DIAG ? yo + vo : yo);
+        }
+        return;
+    }
     // wavefront w sums spin w over the four directions
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -158,7 +206,7 @@ __global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__rest
         for (int d = 1; d < 4; ++d) v = v + ld<T>(&part[d][0][0], c * 64 + lane);
         v = scale(-kappa, v);
         if (DAG && mu >= 2) v = neg(v);
-        st_nt<T>(out, obase + (long)c * Vb, v + dg[a]);
+        st_nt<T>(out, obase + (long)c * Vb, v + dg[a % ND]);
     }
 }
 
@@ -244,11 +292,13 @@ __device__ __forceinline__ void hop_blk(const T2<T> *sh, int off, const __attrib
 
 //
 // RES: write the residual b - out instead of out (the residual of a block
-// solve, r = b - D_b x, in one pass).
-template <typename T, int B, int HOPS, int RES = 0>
+// solve, r = b - D_b x, in one pass).  CL = CLOV_DIAG: the diagonal term is
+// A times the staged input.
+template <typename T, int B, int HOPS, int RES = 0, int CL = CLOV_NONE>
 __global__ __launch_bounds__(Cube<B>::Vb) void k_dslash_blk(Geo g, const int32_t *__restrict__ active,
                                                            const int32_t *__restrict__ list, UTab<T> Utab,
-                                                           const double *__restrict__ kap, int kneg, long n,
+                                                           const double *__restrict__ kap, int kneg,
+                                                           const T *const *__restrict__ ctab, long n,
                                                            const int32_t *__restrict__ sched,
                                                            const T2<T> *__restrict__ in, const T2<T> *__restrict__ b,
                                                            T2<T> *__restrict__ out, T kappa)
@@ -297,6 +347,21 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_dslash_blk(Geo g, const int32_t
         default: hop_blk<T, B, 3, HOPS, 0, Vb>(&sh[0][0], 0, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
         }
     }
+    if (CL) {
+        cx<T> v[12], dg[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            v[c] = scale(-kappa, acc.s[c / 3].c[c % 3]);
+            dg[c] = ld<T>(&sh[c][0], l);
+        }
+        clov_site<T, CLOV_DIAG>(ctab[m], (long)g.V, slot, Vb, l, dg, v);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            const long i = m * n + base + (long)c * Vb;
+            st_nt<T>(out, i, RES ? ld<T>(b, i) - v[c] : v[c]);
+        }
+        return;
+    }
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -313,10 +378,11 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_dslash_blk(Geo g, const int32_t
 // parity par, with gamma_5 on both sides for DAG.  One workgroup per block,
 // one lane per output site; the block's input sites of the other parity are
 // read once into LDS.
-template <typename T, int B, int DAG>
+template <typename T, int B, int DAG, int CL>
 __global__ __launch_bounds__(Cube<B>::Vh) void k_dslash_blk_eo(Geo g, const int32_t *__restrict__ active,
                                                               const int32_t *__restrict__ list, UTab<T> Utab,
-                                                              const double *__restrict__ kap, int kneg, long n,
+                                                              const double *__restrict__ kap, int kneg,
+                                                              const T *const *__restrict__ ctab, long n,
                                                               const int32_t *__restrict__ sched, int par,
                                                               const T2<T> *__restrict__ in,
                                                               const T2<T> *__restrict__ diag, T2<T> *__restrict__ out,
@@ -366,6 +432,19 @@ __global__ __launch_bounds__(Cube<B>::Vh) void k_dslash_blk_eo(Geo g, const int3
         }
     }
     const long obase = m * n + sbase + l;
+    if (CL) {
+        cx<T> v[12], dg[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            v[c] = scale(-kappa, acc.s[c / 3].c[c % 3]);
+            if (DAG && c >= 6) v[c] = neg(v[c]);
+            dg[c] = diag ? ld<T>(diag, obase + (long)c * Vb) : mk<T>(0, 0);
+        }
+        clov_site<T, CL>(ctab[m], (long)g.V, slot, Vb, l, dg, v);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) st_nt<T>(out, obase + (long)c * Vb, v[c]);
+        return;
+    }
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -382,6 +461,49 @@ __global__ __launch_bounds__(Cube<B>::Vh) void k_dslash_blk_eo(Geo g, const int3
 // k_dslash_dir keeps more of the GPU busy
 constexpr long BLK_MIN_WORKGROUPS = 2048;
 
+// the direction-parallel kernel for one (hops, clover mode); dag and the
+// two-row link reads are chosen at run time
+template <typename T, int B, int H, int CL>
+void launch_dir(const Geo &g, const Sys &sy, Links<T> U, int par, int dag, const T2<T> *in, const T2<T> *diag,
+                T2<T> *out, T kappa, int nslots, const int32_t *sc, hipStream_t s)
+{
+    const int chunks = (par < 0 ? Cube<B>::Vb : Cube<B>::Vh) / 64;
+    const dim3 grid(nslots * chunks, sy.launch_m());
+    const int xcd8 = nslots % 8 == 0;
+#define WDR_DIR(D, R)                                                                                          \
+    k_dslash_dir<T, H, B, D, R, CL><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, U.ctab, sy.n, \
+                                                         sc, par, chunks, xcd8, in, diag, out, kappa)
+    if (dag) {
+        if (U.su3) WDR_DIR(1, 1);
+        else WDR_DIR(1, 0);
+    } else {
+        if (U.su3) WDR_DIR(0, 1);
+        else WDR_DIR(0, 0);
+    }
+#undef WDR_DIR
+}
+
+template <typename T, int B, int CL>
+void launch_blk_eo(const Geo &g, const Sys &sy, Links<T> U, int par, int dag, const T2<T> *in, const T2<T> *diag,
+                   T2<T> *out, T kappa, int nslots, const int32_t *sc, hipStream_t s)
+{
+    const dim3 gb(nslots, sy.launch_m());
+    if (dag)
+        k_dslash_blk_eo<T, B, 1, CL><<<gb, Cube<B>::Vh, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, U.ctab,
+                                                               sy.n, sc, par, in, diag, out, kappa);
+    else
+        k_dslash_blk_eo<T, B, 0, CL><<<gb, Cube<B>::Vh, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, U.ctab,
+                                                               sy.n, sc, par, in, diag, out, kappa);
+}
+
+// clover mode of a launch: the links' mode when they carry a clover term and
+// the launch has a diagonal term or multiplies by A^-1 (hops across block
+// faces have neither)
+template <typename T> int clover_mode(const Links<T> &U, int hops)
+{
+    return U.ctab && hops != HOPS_CROSS ? U.cmode : CLOV_NONE;
+}
+
 template <typename T, int B>
 bool launch_cube(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int dag, const T2<T> *in,
                  const T2<T> *diag, T2<T> *out, T kappa, int slot0, int nslots, hipStream_t s)
@@ -389,57 +511,46 @@ bool launch_cube(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int
     if (g.B[0] != B || g.B[1] != B || g.B[2] != B || g.B[3] != B) return false;
     const int si = sched_index(g, slot0, nslots);
     if (si < 0) return false;
-    const int nt = par < 0 ? Cube<B>::Vb : Cube<B>::Vh;
     static_assert(Cube<B>::Vh % 64 == 0, "sites of one parity fill whole wavefronts");
-    const int chunks = nt / 64;
     const int32_t *sc = g.sched[si];
+    const int cl = clover_mode(U, hops);
     // D or D_b with the input as diagonal term, with enough blocks to fill
     // the GPU (one workgroup per block): the block-staged kernel
     const bool big = (long)nslots * sy.launch_m() >= BLK_MIN_WORKGROUPS;
-    if (par < 0 && !dag && U.su3 && diag == in && (hops == HOPS_ALL || hops == HOPS_IN) &&
-        (g.stencil == WDR_STENCIL_BLK || (g.stencil == WDR_STENCIL_AUTO && big))) {
+    const bool blk = g.stencil == WDR_STENCIL_BLK || (g.stencil == WDR_STENCIL_AUTO && big);
+    if (par < 0 && !dag && U.su3 && diag == in && (hops == HOPS_ALL || hops == HOPS_IN) && cl != CLOV_INV && blk) {
         const dim3 gb(nslots, sy.launch_m());
-        if (hops == HOPS_ALL)
-            k_dslash_blk<T, B, HOPS_ALL><<<gb, Cube<B>::Vb, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n,
-                                                                   sc, in, nullptr, out, kappa);
-        else
-            k_dslash_blk<T, B, HOPS_IN><<<gb, Cube<B>::Vb, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n,
-                                                                  sc, in, nullptr, out, kappa);
+#define WDR_BLK(H, C)                                                                                          \
+    k_dslash_blk<T, B, H, 0, C><<<gb, Cube<B>::Vb, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, U.ctab, sy.n, \
+                                                           sc, in, nullptr, out, kappa)
+        if (hops == HOPS_ALL) {
+            if (cl) WDR_BLK(HOPS_ALL, CLOV_DIAG);
+            else WDR_BLK(HOPS_ALL, CLOV_NONE);
+        } else {
+            if (cl) WDR_BLK(HOPS_IN, CLOV_DIAG);
+            else WDR_BLK(HOPS_IN, CLOV_NONE);
+        }
+#undef WDR_BLK
         return true;
     }
     // the even-odd halves (all hops), same choice
-    if (par >= 0 && hops == HOPS_ALL && U.su3 && (g.stencil == WDR_STENCIL_BLK || (g.stencil == WDR_STENCIL_AUTO && big))) {
-        const dim3 gb(nslots, sy.launch_m());
-        if (dag)
-            k_dslash_blk_eo<T, B, 1><<<gb, Cube<B>::Vh, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, sc,
-                                                               par, in, diag, out, kappa);
-        else
-            k_dslash_blk_eo<T, B, 0><<<gb, Cube<B>::Vh, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, sc,
-                                                               par, in, diag, out, kappa);
+    if (par >= 0 && hops == HOPS_ALL && U.su3 && blk) {
+        if (cl == CLOV_DIAG) launch_blk_eo<T, B, CLOV_DIAG>(g, sy, U, par, dag, in, diag, out, kappa, nslots, sc, s);
+        else if (cl == CLOV_INV) launch_blk_eo<T, B, CLOV_INV>(g, sy, U, par, dag, in, diag, out, kappa, nslots, sc, s);
+        else launch_blk_eo<T, B, CLOV_NONE>(g, sy, U, par, dag, in, diag, out, kappa, nslots, sc, s);
         return true;
     }
-    const dim3 grid(nslots * chunks, sy.launch_m());
-    const int xcd8 = nslots % 8 == 0;
-#define WDR_DIR(H, D, R)                                                                                     \
-    k_dslash_dir<T, H, B, D, R><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, sc, par, chunks, xcd8, in, diag, out, \
-                                                     kappa)
-#define WDR_DIR2(H, D)                                                                                       \
-    do {                                                                                                     \
-        if (U.su3) WDR_DIR(H, D, 1);                                                                        \
-        else WDR_DIR(H, D, 0);                                                                               \
-    } while (0)
-    if (hops == HOPS_ALL) {
-        if (dag) WDR_DIR2(HOPS_ALL, 1);
-        else WDR_DIR2(HOPS_ALL, 0);
-    } else if (hops == HOPS_IN) {
-        if (dag) WDR_DIR2(HOPS_IN, 1);
-        else WDR_DIR2(HOPS_IN, 0);
+    if (hops == HOPS_CROSS) {
+        launch_dir<T, B, HOPS_CROSS, CLOV_NONE>(g, sy, U, par, dag, in, diag, out, kappa, nslots, sc, s);
+    } else if (hops == HOPS_ALL) {
+        if (cl == CLOV_DIAG) launch_dir<T, B, HOPS_ALL, CLOV_DIAG>(g, sy, U, par, dag, in, diag, out, kappa, nslots, sc, s);
+        else if (cl == CLOV_INV) launch_dir<T, B, HOPS_ALL, CLOV_INV>(g, sy, U, par, dag, in, diag, out, kappa, nslots, sc, s);
+        else launch_dir<T, B, HOPS_ALL, CLOV_NONE>(g, sy, U, par, dag, in, diag, out, kappa, nslots, sc, s);
     } else {
-        if (dag) WDR_DIR2(HOPS_CROSS, 1);
-        else WDR_DIR2(HOPS_CROSS, 0);
+        if (cl == CLOV_DIAG) launch_dir<T, B, HOPS_IN, CLOV_DIAG>(g, sy, U, par, dag, in, diag, out, kappa, nslots, sc, s);
+        else if (cl == CLOV_INV) launch_dir<T, B, HOPS_IN, CLOV_INV>(g, sy, U, par, dag, in, diag, out, kappa, nslots, sc, s);
+        else launch_dir<T, B, HOPS_IN, CLOV_NONE>(g, sy, U, par, dag, in, diag, out, kappa, nslots, sc, s);
     }
-#undef WDR_DIR2
-#undef WDR_DIR
     return true;
 }
 
@@ -492,18 +603,6 @@ __global__ __launch_bounds__(256) void k_max_final(int n, const double *partial,
 }
 
 // ---------------------------------------------------------------- packing
-
-__device__ __forceinline__ long canon_index(const Geo &g, int slot, int l, int x[4])
-{
-    int b = g.slot_blk[slot];
-    const uint32_t c = g.loc_coord[l];
-    int loc[4] = {(int)(c & 255u), (int)((c >> 8) & 255u), (int)((c >> 16) & 255u), (int)(c >> 24)};
-    for (int mu = 0; mu < 4; ++mu) {
-        x[mu] = (b % g.NB[mu]) * g.B[mu] + loc[mu];
-        b /= g.NB[mu];
-    }
-    return x[0] + (long)g.L[0] * (x[1] + (long)g.L[1] * (x[2] + (long)g.L[2] * x[3]));
-}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_pack_spinor(Geo g, const double2 *__restrict__ canon,
@@ -618,25 +717,34 @@ void launch_dslash(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, i
     if (launch_cube<T, 4>(g, sy, U, hops, par, dag, in, diag, out, kappa, slot0, nslots, s)) return;
     const int nloc = par < 0 ? g.Vb : g.Vh;
     dim3 grid((nloc + 255) / 256, nslots, sy.launch_m());
-    if (hops == HOPS_ALL)
-        k_dslash<T, HOPS_ALL><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, par, dag, in, diag, out, kappa, slot0);
-    else if (hops == HOPS_IN)
-        k_dslash<T, HOPS_IN><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, par, dag, in, diag, out, kappa, slot0);
-    else
-        k_dslash<T, HOPS_CROSS><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, par, dag, in, diag, out, kappa, slot0);
+    const int cl = clover_mode(U, hops);
+#define WDR_GEN(H, C)                                                                                        \
+    k_dslash<T, H, C><<<grid, 256, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, U.ctab, sy.n, par, dag, in, \
+                                           diag, out, kappa, slot0)
+#define WDR_GEN2(H)                                                                                          \
+    do {                                                                                                     \
+        if (cl == CLOV_DIAG) WDR_GEN(H, CLOV_DIAG);                                                         \
+        else if (cl == CLOV_INV) WDR_GEN(H, CLOV_INV);                                                      \
+        else WDR_GEN(H, CLOV_NONE);                                                                          \
+    } while (0)
+    if (hops == HOPS_ALL) WDR_GEN2(HOPS_ALL);
+    else if (hops == HOPS_IN) WDR_GEN2(HOPS_IN);
+    else WDR_GEN(HOPS_CROSS, CLOV_NONE);
+#undef WDR_GEN2
+#undef WDR_GEN
 }
 
 bool launch_block_residual(const Geo &g, const Sys &sy, Links<double> U, const double2 *x, const double2 *b,
                            double2 *r, double kappa, int slot0, int nslots, hipStream_t s)
 {
     if (nslots <= 0 || sy.M <= 0) return true;
-    if (g.B[0] != 4 || g.B[1] != 4 || g.B[2] != 4 || g.B[3] != 4 || !U.su3) return false;
+    if (g.B[0] != 4 || g.B[1] != 4 || g.B[2] != 4 || g.B[3] != 4 || !U.su3 || U.ctab) return false;
     const bool big = (long)nslots * sy.launch_m() >= BLK_MIN_WORKGROUPS;
     if (!(g.stencil == WDR_STENCIL_BLK || (g.stencil == WDR_STENCIL_AUTO && big))) return false;
     const int si = sched_index(g, slot0, nslots);
     if (si < 0) return false;
     k_dslash_blk<double, 4, HOPS_IN, 1><<<dim3(nslots, sy.launch_m()), Cube<4>::Vb, 0, s>>>(
-        g, sy.active, sy.list, U.tab, U.kap, U.kneg, sy.n, g.sched[si], x, b, r, kappa);
+        g, sy.active, sy.list, U.tab, U.kap, U.kneg, nullptr, sy.n, g.sched[si], x, b, r, kappa);
     return true;
 }
 

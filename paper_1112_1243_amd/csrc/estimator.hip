@@ -28,24 +28,28 @@ namespace wdr {
 namespace {
 
 struct TmpGauge {
-    Work u64, u32, u16, e16;
+    Work u64, u32, u16, e16, c64, c32;
     // su3: FP16 links for the block MR / Schwarz kernels; cg16: E16 links
-    // for the FP16 even-odd CG as well
-    TmpGauge(wdr_ctx *c, bool su3, bool cg16)
+    // for the FP16 even-odd CG as well; clov: the clover term (A, A^-1) in
+    // FP64 and FP32
+    TmpGauge(wdr_ctx *c, bool su3, bool cg16, bool clov)
         : u64(c, (size_t)c->g.V * 36 * sizeof(double2)), u32(c, (size_t)c->g.V * 36 * sizeof(float2)),
           u16(c, su3 ? (size_t)c->g.V * 24 * sizeof(h2) : 256),
-          e16(c, su3 && cg16 ? (size_t)c->g.V * 24 * sizeof(h2) : 256), has16(su3), hase16(su3 && cg16)
+          e16(c, su3 && cg16 ? (size_t)c->g.V * 24 * sizeof(h2) : 256),
+          c64(c, clov ? (size_t)c->g.V * 144 * sizeof(double) : 256),
+          c32(c, clov ? (size_t)c->g.V * 144 * sizeof(float) : 256), has16(su3), hase16(su3 && cg16), clov(clov)
     {
     }
-    bool ok() const { return u64.ok() && u32.ok() && u16.ok() && e16.ok(); }
-    bool has16, hase16;
+    bool ok() const { return u64.ok() && u32.ok() && u16.ok() && e16.ok() && c64.ok() && c32.ok(); }
+    bool has16, hase16, clov;
 };
 
 // U_0 .. U_N of one proposal into pts[0 .. N]: the end points are copies, the
 // interior points come from one interpolation launch; then the FP32 and FP16
-// copies of every point
-void make_path_gauges(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, int N, TmpGauge *const *pts,
-                      hipStream_t s)
+// copies of every point, and its clover term (coefficient csw, hopping
+// parameter kappa; worst[i] receives the worst pivot measure of point i)
+void make_path_gauges(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, int N, TmpGauge *const *pts, double csw,
+                      double kappa, void *cwork, double *worst, hipStream_t s)
 {
     const size_t n = (size_t)c->g.V * 36;
     // compulsory bytes: both fields read and every interior point written,
@@ -67,7 +71,13 @@ void make_path_gauges(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, int N
         launch_convert_gauge_f32(c->g, dst.u64.as<double2>(), dst.u32.as<float2>(), s);
         if (dst.has16) launch_pack_links_h16(c->g, dst.u64.as<double2>(), dst.u16.as<h2>(), s);
         if (dst.hase16) launch_pack_links_e16(c->g, dst.u64.as<double2>(), dst.e16.as<h2>(), s);
+        if (dst.clov)
+            launch_clover_build(c->g, dst.u64.as<double2>(), csw, kappa, cwork, dst.c64.as<double>(),
+                                dst.c32.as<float>(), worst + i, s);
     }
+    // clover build per point: the links, the field strengths written and read
+    // back, A and A^-1 in FP64, their FP32 copy
+    if (pts[0]->clov) add_traffic(V * (N + 1) * (lb + 2 * 54 * 16.0 + 2 * 144 * 8.0 + 144 * 4.0));
 }
 
 // device memory budget for the fields of one chunk of samples (the 32
@@ -80,7 +90,7 @@ constexpr double CHUNK_BYTES = 96e9;
 struct Path {
     std::vector<std::unique_ptr<TmpGauge>> pts;
     int N = 0, su3 = 1;
-    bool has16 = false, hase16 = false;
+    bool has16 = false, hase16 = false, clov = false;
     TmpGauge &at(int prop, int i) const { return *pts[(size_t)prop * (N + 1) + i]; }
 };
 
@@ -92,14 +102,33 @@ static wdr_status build_path(wdr_ctx *c, const std::vector<Proposal> &props, con
     for (const Proposal &q : props) path.su3 = path.su3 && q.U->su3 && q.Up->su3;  // the geodesic stays in SU(3)
     path.has16 = path.su3 && p.sp.inner == WDR_F16;
     path.hase16 = path.has16 && p.sp.solver == WDR_SOLVER_CGNE && e16_geometry(c->g);
-    for (const Proposal &q : props) {
+    path.clov = props[0].U->c64 != nullptr;
+    std::unique_ptr<Work> cwork, worst;
+    if (path.clov) {
+        cwork.reset(new Work(c, clover_work_bytes(c->g)));
+        worst.reset(new Work(c, sizeof(double) * props.size() * (path.N + 1)));
+        if (!cwork->ok() || !worst->ok()) return WDR_ENOMEM;
+    }
+    for (size_t k = 0; k < props.size(); ++k) {
+        const Proposal &q = props[k];
         std::vector<TmpGauge *> pts;
         for (int i = 0; i <= path.N; ++i) {
-            path.pts.emplace_back(new TmpGauge(c, path.has16, path.hase16));
+            path.pts.emplace_back(new TmpGauge(c, path.has16, path.hase16, path.clov));
             if (!path.pts.back()->ok()) return WDR_ENOMEM;
             pts.push_back(path.pts.back().get());
         }
-        make_path_gauges(c, q.U, q.Up, path.N, pts.data(), s);
+        make_path_gauges(c, q.U, q.Up, path.N, pts.data(), q.U->csw, q.kappa, path.clov ? cwork->as<void>() : nullptr,
+                         path.clov ? worst->as<double>() + k * (path.N + 1) : nullptr, s);
+    }
+    if (path.clov) {
+        std::vector<double> h(props.size() * (path.N + 1));
+        WDR_HIP(hipMemcpyAsync(h.data(), worst->as<double>(), sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+        WDR_HIP(hipStreamSynchronize(s));
+        for (double v : h)
+            if (!(v < 1e8)) {
+                set_error("the clover term of a point on the path has a (nearly) singular block");
+                return WDR_EINVAL;
+            }
     }
     return WDR_OK;
 }
@@ -139,13 +168,13 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
         const int M = std::min(Mmax, total - m0);
         const size_t fbm = fb * M;
         Work eta(c, fbm), y(c, fbm), z(c, fbm), w(c, fbm), r(c, fbm), t(c, fbm), pr(c, sizeof(double) * g.nblk * M);
-        Work tabs(c, 8 * M * sizeof(void *)), idx(c, 2 * M * sizeof(int32_t)), kw(c, M * sizeof(double)),
+        Work tabs(c, 12 * M * sizeof(void *)), idx(c, 2 * M * sizeof(int32_t)), kw(c, M * sizeof(double)),
             sw(c, M * sizeof(uint64_t));
         if (!eta.ok() || !y.ok() || !z.ok() || !w.ok() || !r.ok() || !t.ok() || !pr.ok() || !tabs.ok() || !idx.ok() ||
             !kw.ok() || !sw.ok())
             return WDR_ENOMEM;
         // per-system tables: X on U_i, X' on U_{i+1}; noise (step, sample, key); kappa
-        std::vector<const void *> ht(8 * M, nullptr);
+        std::vector<const void *> ht(12 * M, nullptr);
         std::vector<int32_t> hi(2 * M);
         std::vector<double> hk(M);
         std::vector<uint64_t> hs(M);
@@ -163,6 +192,12 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
                 ht[6 * M + j] = point(q, i).e16.as<void>();
                 ht[7 * M + j] = point(q, i + 1).e16.as<void>();
             }
+            if (path.clov) {
+                ht[8 * M + j] = point(q, i).c64.as<void>();
+                ht[9 * M + j] = point(q, i).c32.as<void>();
+                ht[10 * M + j] = point(q, i + 1).c64.as<void>();
+                ht[11 * M + j] = point(q, i + 1).c32.as<void>();
+            }
             hi[j] = i;
             hi[M + j] = k;
             hk[j] = props[q].kappa;
@@ -174,14 +209,20 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
         WDR_HIP(hipMemcpyAsync(sw.as<void>(), hs.data(), hs.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s));
         const void *const *tb = tabs.as<const void *const>();
         const double *kap = kw.as<const double>();
-        const GaugeTab X{{reinterpret_cast<UTab<double>>(tb), su3, kap},
-                         {reinterpret_cast<UTab<float>>(tb + M), su3, kap},
-                         {want16 ? reinterpret_cast<const h2 *const *>(tb + 4 * M) : nullptr, kap},
-                         {wante16 ? reinterpret_cast<const h2 *const *>(tb + 6 * M) : nullptr, kap}};
-        const GaugeTab Xp{{reinterpret_cast<UTab<double>>(tb + 2 * M), su3, kap},
-                          {reinterpret_cast<UTab<float>>(tb + 3 * M), su3, kap},
-                          {want16 ? reinterpret_cast<const h2 *const *>(tb + 5 * M) : nullptr, kap},
-                          {wante16 ? reinterpret_cast<const h2 *const *>(tb + 7 * M) : nullptr, kap}};
+        GaugeTab X{{reinterpret_cast<UTab<double>>(tb), su3, kap},
+                   {reinterpret_cast<UTab<float>>(tb + M), su3, kap},
+                   {want16 ? reinterpret_cast<const h2 *const *>(tb + 4 * M) : nullptr, kap},
+                   {wante16 ? reinterpret_cast<const h2 *const *>(tb + 6 * M) : nullptr, kap}};
+        GaugeTab Xp{{reinterpret_cast<UTab<double>>(tb + 2 * M), su3, kap},
+                    {reinterpret_cast<UTab<float>>(tb + 3 * M), su3, kap},
+                    {want16 ? reinterpret_cast<const h2 *const *>(tb + 5 * M) : nullptr, kap},
+                    {wante16 ? reinterpret_cast<const h2 *const *>(tb + 7 * M) : nullptr, kap}};
+        if (path.clov) {
+            X.u64.ctab = reinterpret_cast<const double *const *>(tb + 8 * M);
+            X.u32.ctab = reinterpret_cast<const float *const *>(tb + 9 * M);
+            Xp.u64.ctab = reinterpret_cast<const double *const *>(tb + 10 * M);
+            Xp.u32.ctab = reinterpret_cast<const float *const *>(tb + 11 * M);
+        }
         const Sys all = all_sys(c, M);
         double2 *E = eta.as<double2>(), *Y = y.as<double2>(), *Z = z.as<double2>(), *W = w.as<double2>(),
                 *R = r.as<double2>(), *Tm = t.as<double2>();
@@ -239,7 +280,8 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
             double lin = 0;
             for (int mu = 0; mu < 4; ++mu) lin += (double)(g.B[mu] - 1) / g.B[mu];
             const double V = g.V, sb = spin_b<double>(), lk = su3 ? 384.0 : 576.0;
-            const double D = V * (2 * sb + lk), Din = V * (2 * sb + lin * (su3 ? 96.0 : 144.0));
+            const double D = V * (2 * sb + lk + (path.clov ? clov_b<double>() : 0.0)),
+                         Din = V * (2 * sb + lin * (su3 ? 96.0 : 144.0));
             double b = V * sb + V * 3 * sb + V * 4 * sb;  // noise, r = y - X' z, sample sums
             if (op == WDR_OP_FULL) b += 2 * D + 2 * V * 2 * sb;
             else if (op == WDR_OP_BLOCKS) b += 2 * Din + 2 * V * 2 * sb;

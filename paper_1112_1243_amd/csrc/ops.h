@@ -40,8 +40,28 @@ inline int even_shift(const Geo &g)
     return (1 << s) == g.Vh ? s : 0;
 }
 
+// canonical site index (site = x0 + L0*(x1 + L1*(x2 + L2*x3))) of local
+// site l of slot `slot`; x receives the global coordinates
+__device__ __forceinline__ long canon_index(const Geo &g, int slot, int l, int x[4])
+{
+    int b = g.slot_blk[slot];
+    const uint32_t c = g.loc_coord[l];
+    int loc[4] = {(int)(c & 255u), (int)((c >> 8) & 255u), (int)((c >> 16) & 255u), (int)(c >> 24)};
+    for (int mu = 0; mu < 4; ++mu) {
+        x[mu] = (b % g.NB[mu]) * g.B[mu] + loc[mu];
+        b /= g.NB[mu];
+    }
+    return x[0] + (long)g.L[0] * (x[1] + (long)g.L[1] * (x[2] + (long)g.L[2] * x[3]));
+}
+
 template <typename T> using T2 = typename C2<T>::type;
 template <typename T> using UTab = const T2<T> *const *;  // device [M] gauge pointers
+
+// what a stencil launch does with the clover term when its links carry one
+// (the term and its layout: clover.h)
+//   CLOV_DIAG  out = A diag - kappa H in      (the diagonal input times A)
+//   CLOV_INV   out = A^-1 (diag - kappa H in) (diag may be absent)
+enum { CLOV_NONE = 0, CLOV_DIAG = 1, CLOV_INV = 2 };
 
 // the links of a batch: the device table of per-system gauge pointers,
 // whether every field in it is SU(3) to SU3_TOL (then kernels may read two
@@ -53,6 +73,11 @@ template <typename T> struct Links {
     int su3;
     const double *kap = nullptr;
     int kneg = 0;  // stencil launches use -kap[m] (the kappa argument is then -kappa too)
+    // clover term: device table of per-system clover fields (A then A^-1,
+    // layout in clover.h; NULL: no clover term) and what a stencil launch
+    // does with it (CLOV_NONE / CLOV_DIAG / CLOV_INV of clover.h)
+    const T *const *ctab = nullptr;
+    int cmode = 0;
 };
 
 // FP16 fields: [M][slot][12][Vb] values v / s with one power-of-two scale
@@ -91,6 +116,25 @@ bool launch_block_residual(const Geo &g, const Sys &sy, Links<double> U, const d
 template <typename T>
 void launch_dslash(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int dag, const T2<T> *in,
                    const T2<T> *diag, T2<T> *out, T kappa, int slot0, int nslots, hipStream_t s);
+
+// ---------------------------------------------------------------- clover term
+// A = 1 + T and A^-1 of every site (clover.h layout) in FP64 into c64 (144 V
+// doubles) and rounded to FP32 into c32 (144 V floats), from the internal
+// FP64 links U (boundary phases folded in; they cancel around the closed
+// loops).  work: clover_work_bytes(g); worst (device, one double): the
+// largest 1 / |pivot| of the LDL^H factorisations of the blocks (a singular
+// block gives inf or nan).
+size_t clover_work_bytes(const Geo &g);
+void launch_clover_build(const Geo &g, const double2 *U, double csw, double kappa, void *work, double *c64, float *c32,
+                         double *worst, hipStream_t s);
+// out = A in (inv 0) or A^-1 in (inv 1) on the sites of parity par (-1: all)
+// of every system; other sites of out are untouched
+template <typename T>
+void launch_clover_mul(const Geo &g, const Sys &sy, const T *const *ctab, int inv, int par, const T2<T> *in,
+                       T2<T> *out, hipStream_t s);
+// A (inv 0) or A^-1 (inv 1) of one FP64 clover field as canonical [V][12][12]
+// complex (row and column 3 * spin + colour)
+void launch_clover_canon(const Geo &g, const double *c64, int inv, double2 *canon, hipStream_t s);
 
 // canonical FP64 AoS spinor <-> internal layout in precision T (one field)
 template <typename T> void launch_pack_spinor(const Geo &g, const double2 *canon, T2<T> *out, hipStream_t s);

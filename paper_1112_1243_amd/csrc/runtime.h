@@ -51,7 +51,13 @@ struct wdr_gauge {
     float2 *u32 = nullptr;   // internal FP32 copy
     wdr::h2 *u16 = nullptr;  // FP16 copy of the first two rows (SU(3) fields only)
     wdr::h2 *e16 = nullptr;  // the same in the even-odd CG's layout (SU(3) fields, 4^4 blocks)
-    void **tab = nullptr;    // device table {u64, u32, u16, e16} for single-system launches
+    // clover term (wdr_gauge_set_clover): A and A^-1 in FP64 and FP32, the
+    // coefficient and the hopping parameter they were built with (csw = 0:
+    // none)
+    double *c64 = nullptr;
+    float *c32 = nullptr;
+    double csw = 0, ckappa = 0;
+    void **tab = nullptr;    // device table {u64, u32, u16, e16, c64, c32} for single-system launches
     int su3 = 0;             // every link is SU(3) to SU3_TOL (checked at upload)
     // the same four pointers repeated for launches of several systems on this
     // field: rep + k * rep_cap holds rep_cap copies of entry k of tab
@@ -116,11 +122,19 @@ struct GaugeTab {
 };
 inline GaugeTab view(const wdr_gauge *g)
 {
-    return {{reinterpret_cast<UTab<double>>(g->tab), g->su3},
-            {reinterpret_cast<UTab<float>>(g->tab + 1), g->su3},
-            {g->u16 ? reinterpret_cast<const h2 *const *>(g->tab + 2) : nullptr},
-            {g->e16 ? reinterpret_cast<const h2 *const *>(g->tab + 3) : nullptr}};
+    GaugeTab t{{reinterpret_cast<UTab<double>>(g->tab), g->su3},
+               {reinterpret_cast<UTab<float>>(g->tab + 1), g->su3},
+               {g->u16 ? reinterpret_cast<const h2 *const *>(g->tab + 2) : nullptr},
+               {g->e16 ? reinterpret_cast<const h2 *const *>(g->tab + 3) : nullptr}};
+    if (g->c64) {
+        t.u64.ctab = reinterpret_cast<const double *const *>(g->tab + 4);
+        t.u32.ctab = reinterpret_cast<const float *const *>(g->tab + 5);
+    }
+    return t;
 }
+
+// bytes per site of one clover block pair (A or A^-1) in precision T
+template <typename T> constexpr double clov_b() { return 72.0 * sizeof(T); }
 
 // ---- algorithmic traffic: the compulsory device-memory bytes of the work
 // done (every operand of a kernel read or written once: spinors of the sites

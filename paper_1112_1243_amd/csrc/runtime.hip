@@ -5,6 +5,7 @@
 #include <string>
 
 #include <atomic>
+#include <cmath>
 
 #include "runtime.h"
 
@@ -441,7 +442,7 @@ wdr_status wdr_gauge_create(wdr_ctx *c, const double *dev_U, wdr_gauge **out, vo
     g->device = c->device;
     const size_t n = (size_t)c->g.V * 36;
     if (hipMalloc(&g->u64, n * sizeof(double2)) != hipSuccess || hipMalloc(&g->u32, n * sizeof(float2)) != hipSuccess ||
-        hipMalloc(&g->tab, 4 * sizeof(void *)) != hipSuccess) {
+        hipMalloc(&g->tab, 6 * sizeof(void *)) != hipSuccess) {
         set_error("gauge allocation failed");
         return WDR_ENOMEM;
     }
@@ -473,7 +474,7 @@ wdr_status wdr_gauge_create(wdr_ctx *c, const double *dev_U, wdr_gauge **out, vo
             launch_pack_links_e16(c->g, g->u64, g->e16, s);
         }
     }
-    void *tab[4] = {g->u64, g->u32, g->u16, g->e16};
+    void *tab[6] = {g->u64, g->u32, g->u16, g->e16, nullptr, nullptr};
     WDR_HIP(hipMemcpyAsync(g->tab, tab, sizeof(tab), hipMemcpyHostToDevice, s));
     WDR_HIP(hipStreamSynchronize(s));
     WDR_HIP(hipGetLastError());
@@ -482,6 +483,69 @@ wdr_status wdr_gauge_create(wdr_ctx *c, const double *dev_U, wdr_gauge **out, vo
 }
 
 int32_t wdr_gauge_is_su3(const wdr_gauge *g) { return g && g->su3 ? 1 : 0; }
+
+wdr_status wdr_gauge_set_clover(wdr_ctx *c, wdr_gauge *U, double csw, double kappa, void *stream)
+{
+    if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
+    if (!U) {
+        set_error("null gauge handle");
+        return WDR_EINVAL;
+    }
+    if (U->ctx != c) {
+        set_error("gauge handle belongs to another context");
+        return WDR_ESTATE;
+    }
+    if (!std::isfinite(csw) || !std::isfinite(kappa) || (csw != 0 && !(kappa > 0))) {
+        set_error("csw must be finite and kappa positive");
+        return WDR_EINVAL;
+    }
+    for (int mu = 0; mu < 4; ++mu)
+        if (csw != 0 && c->geom.bc[mu] == 0) {
+            set_error("the clover term needs periodic or antiperiodic boundaries (bc = +1 / -1) in every direction");
+            return WDR_EINVAL;
+        }
+    WDR_HIP(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    // launches already queued may read the old term
+    WDR_HIP(hipStreamSynchronize(s));
+    WDR_HIP(hipDeviceSynchronize());
+    if (U->c64) (void)hipFree(U->c64);
+    if (U->c32) (void)hipFree(U->c32);
+    U->c64 = nullptr;
+    U->c32 = nullptr;
+    U->csw = U->ckappa = 0;
+    void *none[2] = {nullptr, nullptr};
+    WDR_HIP(hipMemcpy(U->tab + 4, none, sizeof(none), hipMemcpyHostToDevice));
+    if (csw == 0) return WDR_OK;
+    const size_t n = (size_t)c->g.V * 144;
+    if (hipMalloc(&U->c64, n * sizeof(double)) != hipSuccess || hipMalloc(&U->c32, n * sizeof(float)) != hipSuccess) {
+        set_error("clover allocation failed");
+        return WDR_ENOMEM;
+    }
+    {
+        Work w(c, clover_work_bytes(c->g) + sizeof(double));
+        if (!w.ok()) return WDR_ENOMEM;
+        double *worst = reinterpret_cast<double *>(w.as<char>() + clover_work_bytes(c->g));
+        launch_clover_build(c->g, U->u64, csw, kappa, w.as<void>(), U->c64, U->c32, worst, s);
+        double h = 0;
+        WDR_HIP(hipMemcpyAsync(&h, worst, sizeof(double), hipMemcpyDeviceToHost, s));
+        WDR_HIP(hipStreamSynchronize(s));
+        WDR_HIP(hipGetLastError());
+        if (!(h < 1e8)) {
+            (void)hipFree(U->c64);
+            (void)hipFree(U->c32);
+            U->c64 = nullptr;
+            U->c32 = nullptr;
+            set_error("the clover term has a (nearly) singular block: largest 1/|pivot| " + std::to_string(h));
+            return WDR_EINVAL;
+        }
+    }
+    void *ct[2] = {U->c64, U->c32};
+    WDR_HIP(hipMemcpy(U->tab + 4, ct, sizeof(ct), hipMemcpyHostToDevice));
+    U->csw = csw;
+    U->ckappa = kappa;
+    return WDR_OK;
+}
 
 wdr_status wdr_gauge_destroy(wdr_gauge *g)
 {
@@ -492,6 +556,8 @@ wdr_status wdr_gauge_destroy(wdr_gauge *g)
     if (g->u32) (void)hipFree(g->u32);
     if (g->u16) (void)hipFree(g->u16);
     if (g->e16) (void)hipFree(g->e16);
+    if (g->c64) (void)hipFree(g->c64);
+    if (g->c32) (void)hipFree(g->c32);
     if (g->rep) (void)hipFree(g->rep);
     if (g->tab) (void)hipFree(g->tab);
     delete g;

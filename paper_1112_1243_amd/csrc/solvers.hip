@@ -300,7 +300,18 @@ __global__ __launch_bounds__(BC_NT) void k_block_check(int nblk, int slot0, int 
 void apply_D64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const double2 *in, double2 *out,
                hipStream_t s)
 {
-    launch_dslash<double>(c->g, sy, U.u64, HOPS_ALL, -1, 0, in, in, out, kappa, 0, c->g.nblk, s);
+    Links<double> L = U.u64;
+    L.cmode = CLOV_DIAG;  // with a clover term the diagonal is A
+    launch_dslash<double>(c->g, sy, L, HOPS_ALL, -1, 0, in, in, out, kappa, 0, c->g.nblk, s);
+}
+
+// the solvers other than even-odd CGNE with an FP64 / FP32 inner level do not
+// handle the clover term
+static wdr_status no_clover(const GaugeTab &U, const char *what)
+{
+    if (!U.u64.ctab) return WDR_OK;
+    set_error(std::string(what) + " does not support the clover term");
+    return WDR_EINVAL;
 }
 
 // ------------------------------------------------------------ SAP
@@ -342,6 +353,7 @@ static wdr_status need16(const GaugeTab &U)
 wdr_status sap64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
                  const double2 *in, double2 *out, hipStream_t s)
 {
+    if (no_clover(U, "the Schwarz alternating procedure") != WDR_OK) return WDR_EINVAL;
     if (sp.inner == WDR_F64) {
         sap_run<double>(c, sy, U.u64, kappa, sp.sap_cycles, sp.mr_steps, in, out, s);
         return WDR_OK;
@@ -508,12 +520,14 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
 
 // ------------------------------------------------------------ CGNE
 
-// Even-odd reduction: with D = [[1, -k H_eo], [-k H_oe, 1]] on (even, odd)
-// sites, D x = b becomes
-//     Dhat x_e = bh_e,  Dhat = 1 - k^2 H_eo H_oe,  bh_e = b_e + k H_eo b_o,
-//     x_o = b_o + k H_oe x_e,
-// and then b - D x is bh_e - Dhat x_e on even sites and exactly 0 on odd
-// ones, so the solver's FP64 residual is that of the full system.  CG runs on
+// Even-odd reduction: with D = [[A_ee, -k H_eo], [-k H_oe, A_oo]] on (even,
+// odd) sites (A = 1 without a clover term), D x = b becomes
+//     Dhat x_e = bh_e,  Dhat = A_ee - k^2 H_eo A_oo^-1 H_oe,
+//     bh_e = b_e + k H_eo A_oo^-1 b_o,  x_o = A_oo^-1 (b_o + k H_oe x_e),
+// and then b - D x is bh_e - Dhat x_e on even sites and 0 on odd ones (up to
+// the rounding of A_oo^-1), so the solver's FP64 residual is that of the
+// full system.  The clover factors ride in the stencil launches (CLOV_INV
+// on the odd half, CLOV_DIAG on the even half).  CG runs on
 // Dhat Dhat^+ y = bh (x_e = Dhat^+ y; Dhat^+ = g5 Dhat g5) with vectors and
 // stencil in T, and reliable updates in FP64 (the scheme of Sleijpen and van
 // der Vorst): whenever the iterated residual has fallen by RELIABLE_DELTA
@@ -569,15 +583,17 @@ template <typename T> Links<T> links_of(const GaugeTab &U);
 template <> Links<double> links_of<double>(const GaugeTab &U) { return U.u64; }
 template <> Links<float> links_of<float>(const GaugeTab &U) { return U.u32; }
 
-// out_e = (Dhat in)_e, or (Dhat^+ in)_e with dag; tmp receives -k H_oe in_e
-// on odd sites; odd sites of out are not written
+// out_e = (Dhat in)_e, or (Dhat^+ in)_e with dag; tmp receives
+// -k A_oo^-1 H_oe in_e on odd sites; odd sites of out are not written
 template <typename T>
 static void apply_dhat(const Geo &g, const Sys &sy, Links<T> U, T kappa, int dag, const T2<T> *in, T2<T> *tmp,
                        T2<T> *out, hipStream_t s)
 {
-    Links<T> Un = U;
+    Links<T> Ui = U, Un = U;
+    Ui.cmode = CLOV_INV;
     Un.kneg = 1;
-    launch_dslash<T>(g, sy, U, HOPS_ALL, 1, dag, in, nullptr, tmp, kappa, 0, g.nblk, s);
+    Un.cmode = CLOV_DIAG;
+    launch_dslash<T>(g, sy, Ui, HOPS_ALL, 1, dag, in, nullptr, tmp, kappa, 0, g.nblk, s);
     launch_dslash<T>(g, sy, Un, HOPS_ALL, 0, dag, tmp, in, out, -kappa, 0, g.nblk, s);
 }
 
@@ -615,11 +631,13 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     int launch_m = M;
     const unsigned nbm = nb64(M);
 
-    // bh = [b_e + k H_eo b_o; 0]; odd parts of every iterated field stay 0
+    // bh = [b_e + k H_eo A_oo^-1 b_o; 0]; odd parts of every iterated field stay 0
     launch_zero<double>(x, total, s);
     launch_zero<double>(bh, total, s);
     launch_zero<double>(t64, total, s);
-    launch_dslash<double>(g, all, U64n, HOPS_ALL, 0, 0, b, b, bh, -kappa, 0, g.nblk, s);
+    const bool clov = U.u64.ctab != nullptr;
+    if (clov) launch_clover_mul<double>(g, all, U.u64.ctab, 1, 1, b, o64, s);  // odd sites of o64
+    launch_dslash<double>(g, all, U64n, HOPS_ALL, 0, 0, clov ? o64 : b, b, bh, -kappa, 0, g.nblk, s);
     launch_norm2<double>(all, b, red.as<double>(), sc + 5, 8, s);
     k_cgm_init<<<nbm, 64, 0, s>>>(M, sc, bn2, rmax, alive, upd, its);  // |b|^2 of the full system
     launch_convert<T, double>(all, bh, r, s);
@@ -687,9 +705,11 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
             }
         }
     }
-    // x_o = b_o + k H_oe x_e
+    // x_o = A_oo^-1 (b_o + k H_oe x_e)
     launch_zero<double>(t64, total, s);
-    launch_dslash<double>(g, all, U64n, HOPS_ALL, 1, 0, x, b, t64, -kappa, 0, g.nblk, s);
+    Links<double> U64i = U64n;
+    U64i.cmode = CLOV_INV;
+    launch_dslash<double>(g, all, U64i, HOPS_ALL, 1, 0, x, b, t64, -kappa, 0, g.nblk, s);
     launch_add_to64<double>(all, t64, x, s);
 
     std::vector<double> hbn2(M), rn2;
@@ -711,9 +731,12 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
                         3 * H * spin_b<T>();
     const double update = H * (spin_b<T>() + 2 * spin_b<double>()) + half_b<double>(V, false) +
                           half_b<double>(V, true) + 3 * H * spin_b<double>() + H * (spin_b<double>() + 2 * spin_b<T>());
+    // the clover blocks of every output site of every half (and A_oo^-1 b_o)
+    const double cl_setup = clov ? H * (2 * spin_b<double>() + clov_b<double>()) + H * clov_b<double>() : 0;
+    const double cl_step = clov ? 4 * H * clov_b<T>() : 0, cl_update = clov ? 2 * H * clov_b<double>() : 0;
     double bytes = 0;
     for (int m = 0; m < M; ++m) {
-        bytes += setup + hits[m] * step + hupd[m] * update;
+        bytes += setup + cl_setup + hits[m] * (step + cl_step) + hupd[m] * (update + cl_update);
         st[m].iters = hits[m];
         st[m].total = hits[m];
         st[m].rel = hbn2[m] > 0 ? std::sqrt(rn2[m] / hbn2[m]) : 0.0;
@@ -968,10 +991,14 @@ wdr_status solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr
                    const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
     if (sp.solver == WDR_SOLVER_CGNE) {
-        if (sp.inner == WDR_F16) return cgne_eo16(c, M, U, kappa, sp, tol, b, x, st, s);
+        if (sp.inner == WDR_F16) {
+            if (no_clover(U, "the FP16 inner level") != WDR_OK) return WDR_EINVAL;
+            return cgne_eo16(c, M, U, kappa, sp, tol, b, x, st, s);
+        }
         return sp.inner == WDR_F64 ? cgne_eo<double>(c, M, U, kappa, sp, tol, b, x, st, s)
                                    : cgne_eo<float>(c, M, U, kappa, sp, tol, b, x, st, s);
     }
+    if (no_clover(U, "FGCR with Schwarz preconditioning") != WDR_OK) return WDR_EINVAL;
     return fgcr(c, M, U, kappa, sp, tol, b, x, st, s);
 }
 
@@ -980,6 +1007,7 @@ wdr_status solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr
 wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int colour, const wdr_solver_params &sp,
                          double tol, const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
+    if (no_clover(U, "the block solver") != WDR_OK) return WDR_EINVAL;
     const auto &g = c->g;
     int slot0, ns;
     colour_slots(c, colour, slot0, ns);
@@ -1086,6 +1114,7 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
 wdr_status schur64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
                    const double2 *in, double2 *out, std::vector<Stats> &st, hipStream_t s)
 {
+    if (no_clover(U, "the Schur complement") != WDR_OK) return WDR_EINVAL;
     const auto &g = c->g;
     const long n = field_n(c);
     const size_t fb = field_bytes(c, WDR_F64) * M;

@@ -53,6 +53,10 @@ wdr_status wdr_autotune(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up, dou
         set_error("gauge handles of another context (or NULL)");
         return WDR_ESTATE;
     }
+    if (U->c64 || Up->c64) {
+        set_error("the autotuner does not support gauge fields with a clover term");
+        return WDR_EINVAL;
+    }
     if (!(kappa > 0) || !p || p->n_steps < 1 || p->n_noise < 1) {
         set_error("invalid kappa or estimator parameters");
         return WDR_EINVAL;

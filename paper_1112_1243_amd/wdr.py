@@ -105,6 +105,8 @@ def lib():
         L.wdr_gauge_destroy.argtypes = [P]
         L.wdr_gauge_is_su3.argtypes = [P]
         L.wdr_gauge_is_su3.restype = i32
+        L.wdr_gauge_set_clover.argtypes = [P, P, d, d, P]
+        L.wdr_clover_field.argtypes = [P, P, i32, P, P]
         L.wdr_interpolate.argtypes = [P, P, P, i32, i32, P, P]
         L.wdr_noise.argtypes = [P, ctypes.c_int, ctypes.c_uint64, i32, i32, i32, P, P]
         L.wdr_field_bytes.argtypes = [P, ctypes.c_int]
@@ -263,10 +265,25 @@ class Context:
         return m
 
     # ---- gauge fields and path
-    def gauge(self, U) -> Gauge:
+    def gauge(self, U, csw: float = 0.0, kappa: float = 0.0) -> Gauge:
+        """Upload U; with csw != 0 attach the clover term for (csw, kappa)."""
         h = ctypes.c_void_p()
         _check(lib().wdr_gauge_create(self.handle, _dev(U, (self.V, 4, 3, 3)), ctypes.byref(h), _stream()))
-        return Gauge(self, h)
+        g = Gauge(self, h)
+        if csw:
+            self.set_clover(g, csw, kappa)
+        return g
+
+    def set_clover(self, U: Gauge, csw: float, kappa: float):
+        """Attach (csw != 0) or remove (csw = 0) the clover term of U."""
+        _check(lib().wdr_gauge_set_clover(self.handle, U.handle, float(csw), float(kappa), _stream()))
+
+    def clover_field(self, U: Gauge, inverse: bool = False):
+        """A or A^-1 of U's clover term: [V, 12, 12] complex128 on the device."""
+        out = self._empty(self.V, 12, 12)
+        _check(lib().wdr_clover_field(self.handle, U.handle, int(bool(inverse)), ctypes.c_void_p(out.data_ptr()),
+                                      _stream()))
+        return out
 
     def interpolate(self, U, Up, i: int, N: int):
         out = self._empty(self.V, 4, 3, 3)
