@@ -37,6 +37,9 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SITE = {("f64", True): 96 * 8, ("f32", True): 96 * 4, ("f64", False): 120 * 8, ("f32", False): 120 * 4}
 KERNEL = {"f64": "k_dslash_blk<double, B=4, all hops> (SU(3) links, two rows)",
           "f32": "k_dslash_blk<float, B=4, all hops> (SU(3) links, two rows)"}
+# the clover term adds its two hermitian 6 x 6 blocks per site (72 reals)
+CLOVER_BYTES_PER_SITE = {"f64": 72 * 8, "f32": 72 * 4}
+CSW = 1.7
 # HBM traffic per launch from rocprofv3 counter runs on the committed kernel
 # sources (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0: a plain 1 GiB elementwise copy
 # reads 1 GiB as FETCH_SIZE 0.5 GiB because every read request on gfx950 is
@@ -83,6 +86,38 @@ def proposal_mask(ctx, rule):
         nb = y[0] + L[0] * (y[1] + L[1] * (y[2] + L[2] * y[3]))
         mask[:, mu] = (bid == bid[nb]) & (col == 0)
     return mask
+
+
+def clover_workload(wdr, torch, L=(16, 16, 16, 16), N=8, kappa=0.135, scale=0.5, seed=1112124310):
+    """FULL estimates with and without the clover term (c_sw 1.7) on the same
+    16^4 proposal: N factors x 1 Gaussian noise, all batched, CGNE with FP32
+    iterations and FP64 reliable updates to 1e-10."""
+    from paper_1112_1243_amd import synth
+    ctx = wdr.Context(L, (4, 4, 4, 4))
+    U = synth.gauge_field(L, scale, seed)
+    Up = synth.redraw(U, proposal_mask(ctx, "active"), scale, seed)
+    p = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F32, max_iter=20000)
+    out = {"workload": "%s lattice, 4^4 blocks, kappa %.3f, links exp(i %.1f H), active links redrawn, FULL ratio, "
+                       "N=%d factors x 1 Gaussian noise (batched), CGNE FP32 iterations + FP64 reliable updates to "
+                       "1e-10" % ("x".join(map(str, L)), kappa, scale, N), "unit": "estimates/s"}
+    for csw in (CSW, 0.0):
+        gU = ctx.gauge(torch.from_numpy(U).cuda(), csw, kappa)
+        gUp = ctx.gauge(torch.from_numpy(Up).cuda(), csw, kappa)
+        ctx.logdet_ratio(gU, gUp, kappa, wdr.OP_FULL, 1, 1, wdr.NOISE_GAUSS, 1, p)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, wdr.OP_FULL, N, 1, wdr.NOISE_GAUSS, seed, p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        key = "clover" if csw else "wilson"
+        out[key] = {"value": round(1.0 / dt, 3), "cg_iterations_total": int(info.total_iters),
+                    "converged": bool(info.converged), "log_ratio": round(float(lr), 4)}
+        if csw:
+            out[key]["csw"] = csw
+        log("%s FULL 16^4: %.3f s, CG its %d, log R %.4f" % (key, dt, info.total_iters, lr))
+        del gU, gUp
+    ctx.close()
+    return out
 
 
 def dd_workload(wdr, torch, name):
@@ -363,17 +398,18 @@ def counted_traffic(prec_name):
     return None
 
 
-def dslash_roofline(wdr, torch, L=(32, 32, 32, 32), prec_name="f64", reps=30, stencil=0):
+def dslash_roofline(wdr, torch, L=(32, 32, 32, 32), prec_name="f64", reps=30, stencil=0, csw=0.0):
     """Average duration of one stencil launch on internal fields (SU(3)
     links), by HIP events on the stream the kernel is launched on; stencil
-    is the context's kernel choice (0 = automatic)."""
+    is the context's kernel choice (0 = automatic); csw != 0: with the
+    clover term (its blocks read once per site)."""
     from paper_1112_1243_amd import synth
     prec = wdr.F32 if prec_name == "f32" else wdr.F64
     ctx = wdr.Context(L, (4, 4, 4, 4))
     ctx.set_stencil(stencil)
     V = ctx.V
     U = synth.gauge_field(L, 0.2, 1112124303)
-    gU = ctx.gauge(torch.from_numpy(U).cuda())
+    gU = ctx.gauge(torch.from_numpy(U).cuda(), csw, 0.155)
     del U
     psi = torch.from_numpy(synth.spinor(L, 5)).cuda()
     a = ctx.pack(psi, prec)
@@ -392,18 +428,22 @@ def dslash_roofline(wdr, torch, L=(32, 32, 32, 32), prec_name="f64", reps=30, st
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
     su3 = gU.su3
-    alg = BYTES_PER_SITE[(prec_name, su3)] * V
+    per_site = BYTES_PER_SITE[(prec_name, su3)] + (CLOVER_BYTES_PER_SITE[prec_name] if csw else 0)
+    alg = per_site * V
     gbs = alg / (ms * 1e-3) / 1e9
     del gU, a, b, psi
     ctx.close()
-    traffic = counted_traffic(prec_name) if su3 and stencil != wdr.STENCIL_DIR else None
+    key = prec_name + ("_clover" if csw else "")
+    traffic = counted_traffic(key) if su3 and stencil != wdr.STENCIL_DIR else None
+    kernel = (KERNEL[prec_name] if stencil != wdr.STENCIL_DIR else
+              "k_dslash_dir<%s, all hops, B=4, R2=1>" % ("double" if prec_name == "f64" else "float")) \
+        if su3 else "k_dslash_dir<%s, all hops, B=4, R2=0>" % ("double" if prec_name == "f64" else "float")
+    if csw:
+        kernel += " with the clover term (A times the staged input)"
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": (KERNEL[prec_name] if stencil != wdr.STENCIL_DIR else
-                       "k_dslash_dir<%s, all hops, B=4, R2=1>" % ("double" if prec_name == "f64" else "float"))
-            if su3 else "k_dslash_dir<%s, all hops, B=4, R2=0>" % ("double" if prec_name == "f64" else "float"),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
             "lattice": "x".join(map(str, L)), "avg_launch_us": round(ms * 1e3, 2),
-            "bytes_per_launch": alg, "bytes_per_site": BYTES_PER_SITE[(prec_name, su3)]}
+            "bytes_per_launch": alg, "bytes_per_site": per_site}
 
 
 def dslash_f16(wdr, torch, L=(32, 32, 32, 32), reps=32, copies=4):
@@ -958,6 +998,7 @@ def main():
     ap.add_argument("--no-blockdet", action="store_true", help="skip the exact block determinants")
     ap.add_argument("--no-recursive", action="store_true", help="skip the recursive-DD workload")
     ap.add_argument("--no-filter", action="store_true", help="skip the filter run")
+    ap.add_argument("--no-clover", action="store_true", help="skip the clover FULL estimates")
     ap.add_argument("--acceptance", action="store_true", help="also run the exact-acceptance variance study")
     ap.add_argument("--stencil", choices=("auto", "dir", "blk"), default="auto",
                     help="stencil kernel for the 32^4 full-stencil launches (default: the library's choice)")
@@ -972,7 +1013,7 @@ def main():
         sys.exit(2)
     if args.headline_only:
         args.no_cpu = args.no_fp64 = args.no_dslash = args.no_batch = args.no_large = args.no_dd8 = True
-        args.no_blockdet = args.no_recursive = args.no_filter = True
+        args.no_blockdet = args.no_recursive = args.no_filter = args.no_clover = True
 
     import torch
     from paper_1112_1243_amd import synth, wdr
@@ -982,6 +1023,7 @@ def main():
         log("k_eo16:", roof)
         for prec in ("f64", "f32"):
             log("dslash %s:" % prec, dslash_roofline(wdr, torch, prec_name=prec))
+            log("dslash %s clover:" % prec, dslash_roofline(wdr, torch, prec_name=prec, csw=CSW))
         log("dslash f16:", dslash_f16(wdr, torch))
         log("copy ceiling:", copy_ceiling(torch))
         return
@@ -1003,6 +1045,10 @@ def main():
         roof["stencil_f64"] = r64
         roof["stencil_f32"] = {k: r32[k] for k in ("achieved", "frac", "traffic", "kernel", "avg_launch_us",
                                                     "bytes_per_launch")}
+        r64c = dslash_roofline(wdr, torch, prec_name="f64", stencil=sc, csw=CSW)
+        log("dslash f64 clover:", r64c)
+        roof["stencil_f64_clover"] = {k: r64c[k] for k in ("achieved", "frac", "traffic", "kernel", "avg_launch_us",
+                                                           "bytes_per_launch", "bytes_per_site")}
         roof["stencil_f16"] = dslash_f16(wdr, torch)
         log("dslash f16:", roof["stencil_f16"])
         roof["copy_ceiling"] = copy_ceiling(torch)
@@ -1025,6 +1071,7 @@ def main():
     rdd = None if args.no_recursive else recursive_dd(wdr, torch)
     if rdd:
         log("recursive dd:", rdd)
+    clov = None if args.no_clover else clover_workload(wdr, torch)
     filt = None if args.no_filter else filter_run(wdr, torch)
     if filt:
         log("filter:", filt)
@@ -1066,6 +1113,7 @@ def main():
         "block_determinants": bdet,
         "recursive_dd": rdd,
         "filter": filt,
+        "clover_full_16": clov,
         "exact_acceptance": acc,
         "cpu_baseline": cpu,
     }
