@@ -375,8 +375,8 @@ wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)
 wdr_status wdr_ctx_destroy(wdr_ctx *c)
 {
     if (!c) return WDR_OK;
-    hipSetDevice(c->device);
-    hipDeviceSynchronize();
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
     if (c->twin) wdr_ctx_destroy(c->twin);  // tables NULL: the twin frees only its own pool
     for (void *p : c->owned) (void)hipFree(p);
     if (c->tables) (void)hipFree(c->tables);
