@@ -112,6 +112,15 @@ __global__ void k_cgm_clear(int M, int32_t *upd)
     if (m < M) upd[m] = 0;
 }
 
+// relative residual from |r|^2 and |b|^2: 0 for b = 0 (x = 0 is exact), and
+// infinite when either norm is not finite (a NaN right-hand side must not
+// count as solved)
+inline double rel_resid(double r2, double b2)
+{
+    if (!std::isfinite(b2) || !std::isfinite(r2)) return INFINITY;
+    return b2 > 0 ? std::sqrt(r2 / b2) : 0.0;
+}
+
 inline unsigned nb256(long n) { return (unsigned)((n + 255) / 256); }
 inline unsigned nb64(long n) { return (unsigned)((n + 63) / 64); }
 
@@ -248,7 +257,8 @@ __global__ void k_fgcr_outer(int M, const double2 *nr, const double *bn2, double
 
 // per-system control of a block solve, one workgroup of BC_NT threads per
 // system: the largest per-block ratio |r_b|^2 / |b_b|^2 over the slots in
-// range (blocks with b_b = 0 are left out)
+// range (blocks with b_b = 0 are left out); a non-finite norm makes it
+// infinite (fmax alone would drop a NaN)
 constexpr int BC_NT = 256;
 __device__ double worst_ratio(int m, int nblk, int slot0, int ns, const double *bn, const double *rn)
 {
@@ -257,7 +267,12 @@ __device__ double worst_ratio(int m, int nblk, int slot0, int ns, const double *
     for (int i = slot0 + threadIdx.x; i < slot0 + ns; i += BC_NT) {
         const size_t k = (size_t)m * nblk + i;
         const double b = bn[k];
-        if (b > 0) wv = fmax(wv, rn ? rn[k] / b : 1.0);
+        if (!isfinite(b)) {
+            wv = INFINITY;
+        } else if (b > 0) {
+            const double q = rn ? rn[k] / b : 1.0;
+            wv = isfinite(q) ? fmax(wv, q) : INFINITY;
+        }
     }
     sh[threadIdx.x] = wv;
     __syncthreads();
@@ -268,16 +283,17 @@ __device__ double worst_ratio(int m, int nblk, int slot0, int ns, const double *
     return sh[0];
 }
 
-// alive = some block has a nonzero right-hand side
+// alive = some block has a nonzero right-hand side; a non-finite right-hand
+// side ends the system at once, unconverged
 __global__ __launch_bounds__(BC_NT) void k_block_init(int nblk, int slot0, int ns, const double *bn, int32_t *alive,
                                                       int32_t *its, double *worst)
 {
     const int m = blockIdx.x;
     const double any = worst_ratio(m, nblk, slot0, ns, bn, nullptr);
     if (threadIdx.x == 0) {
-        alive[m] = any > 0;
+        alive[m] = any > 0 && isfinite(any);
         its[m] = 0;
-        worst[m] = 0;
+        worst[m] = isfinite(any) ? 0 : INFINITY;
     }
 }
 
@@ -289,9 +305,9 @@ __global__ __launch_bounds__(BC_NT) void k_block_check(int nblk, int slot0, int 
     double wv = worst_ratio(m, nblk, slot0, ns, bn, rn);
     if (threadIdx.x == 0) {
         ++its[m];
-        if (!isfinite(wv)) wv = INFINITY;
         worst[m] = wv;
-        if (!(wv > tol2)) alive[m] = 0;
+        // converged, or a residual that is no longer finite (nothing more to gain)
+        if (!(wv > tol2) || !isfinite(wv)) alive[m] = 0;
     }
 }
 
@@ -504,7 +520,7 @@ static wdr_status fgcr(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const
     for (int m = 0; m < M; ++m) {
         st[m].iters = itsh[m];
         st[m].total = itsh[m];
-        st[m].rel = bn2h[m] > 0 ? std::sqrt(rn2[m] / bn2h[m]) : 0.0;
+        st[m].rel = rel_resid(rn2[m], bn2h[m]);
         st[m].converged = st[m].rel <= tol;
         ok = ok && st[m].converged;
     }
@@ -739,7 +755,7 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
         bytes += setup + cl_setup + hits[m] * (step + cl_step) + hupd[m] * (update + cl_update);
         st[m].iters = hits[m];
         st[m].total = hits[m];
-        st[m].rel = hbn2[m] > 0 ? std::sqrt(rn2[m] / hbn2[m]) : 0.0;
+        st[m].rel = rel_resid(rn2[m], hbn2[m]);
         st[m].converged = st[m].rel <= tol;
         ok = ok && st[m].converged;
     }
@@ -972,7 +988,7 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
         bytes += setup + hits[m] * step + hmid[m] * mid + hout[m] * outer;
         st[m].iters = hits[m];
         st[m].total = hits[m];
-        st[m].rel = hbn2[m] > 0 ? std::sqrt(rn2[m] / hbn2[m]) : 0.0;
+        st[m].rel = rel_resid(rn2[m], hbn2[m]);
         st[m].converged = st[m].rel <= tol;
         ok = ok && st[m].converged;
     }

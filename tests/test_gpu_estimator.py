@@ -265,3 +265,26 @@ def test_abi_errors():
     del gU, gU2, gB
     for c in (ctx, other, big):
         c.close()
+
+
+def test_non_finite_inputs_end_solves():
+    """A NaN in the right-hand side ends CGNE, FGCR and the block solver at
+    once with ENOCONV (no run to the iteration cap, and a NaN block is never
+    counted as converged)."""
+    import time
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 1112124340)
+    gU = ctx.gauge(dev(U))
+    b = synth.spinor(lat.L, 341)
+    b[37, 1, 2] = np.nan
+    for params in (wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F32, max_iter=20000),
+                   wdr.default_params(solver=wdr.SOLVER_FGCR_SAP, max_iter=20000)):
+        t0 = time.perf_counter()
+        x, info = ctx.solve(gU, 0.135, dev(b), params, allow_noconv=True)
+        dt = time.perf_counter() - t0
+        say("NaN rhs solver", params.solver, info.as_dict(), "%.3f s" % dt)
+        assert info.converged == 0 and info.iters <= 1 and dt < 5
+    with pytest.raises(wdr.WdrError) as e:
+        ctx.block_solve(gU, 0.135, 2, dev(b), wdr.default_params(inner=wdr.F32))
+    assert e.value.status == wdr.ENOCONV
+    del gU
+    ctx.close()
