@@ -775,9 +775,12 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
 // 6 FP32 (middle) true residual^2
 // after the middle level's residual: restart the iterated residual from it;
 // ask for the outer update when it fell by OUTER_DELTA below the middle
-// system's right-hand side, reached the tolerance, or at the iteration limit
+// system's right-hand side, reached the tolerance, stopped falling (less
+// than 2x since the previous middle update: the FP32 level has reached what
+// its arithmetic resolves), or at the iteration limit
 __global__ void k_c16_mid(int M, double2 *sc, const double *bn2, const double *b32n2, double tol2, double delta2,
-                          int max_iter, const int32_t *its, int32_t *upd, int32_t *upd64, double *rmax, int32_t *nmid)
+                          int max_iter, const int32_t *its, int32_t *upd, int32_t *upd64, double *rmax, double *rprev,
+                          int32_t *nmid)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M || !upd[m]) return;
@@ -785,7 +788,9 @@ __global__ void k_c16_mid(int M, double2 *sc, const double *bn2, const double *b
     const double r = sc[8L * m + 6].x;
     sc[8L * m] = make_double2(r, 0.0);
     rmax[m] = r;
-    if (!(r > delta2 * b32n2[m]) || !(r > tol2 * bn2[m]) || its[m] >= max_iter) upd64[m] = 1;
+    const bool stalled = !(r < 0.25 * rprev[m]);
+    rprev[m] = r;
+    if (!(r > delta2 * b32n2[m]) || !(r > tol2 * bn2[m]) || its[m] >= max_iter || stalled) upd64[m] = 1;
     upd[m] = 0;
 }
 // two levels: every reliable update goes to the FP64 level
@@ -799,7 +804,8 @@ __global__ void k_c16_promote(int M, int32_t *upd, int32_t *upd64)
 // after the FP64 true residual: retire converged systems, else restart the
 // middle system (right-hand side = that residual) and the iterated residual
 __global__ void k_c16_outer(int M, double2 *sc, const double *bn2, double *b32n2, double tol2, int max_iter,
-                            const int32_t *its, int32_t *alive, int32_t *upd64, double *rmax, int32_t *nout)
+                            const int32_t *its, int32_t *alive, int32_t *upd64, double *rmax, double *rprev,
+                            int32_t *nout)
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M || !upd64[m]) return;
@@ -809,6 +815,7 @@ __global__ void k_c16_outer(int M, double2 *sc, const double *bn2, double *b32n2
     sc[8L * m] = make_double2(r, 0.0);
     rmax[m] = r;
     b32n2[m] = r;
+    rprev[m] = r;
 }
 __global__ void k_c16_clear(int M, int32_t *upd64)
 {
@@ -820,13 +827,19 @@ __global__ void k_c16_clear(int M, int32_t *upd64)
 // by this factor (FP32 arithmetic resolves the middle system several orders
 // further, so the FP64 updates stay rare)
 constexpr double OUTER_DELTA = 1e-4;
+// the FP16 steps hand over to the middle (or outer) level once the iterated
+// residual fell by this factor.  Each middle update costs an FP32 Dhat and a
+// conversion, about half a CG step; at the 32^4 workload 0.03 keeps the CG
+// iteration count of 0.1 (0.02 and 0.01 add iterations) with fewer updates:
+// 931 vs 980 ms per estimate (0.05: 961 ms)
+constexpr double RELIABLE_DELTA_F16 = 0.03;
 
 // Even-odd CG on the normal equations with FP16 storage (4^4 blocks, SU(3)
 // links), the system and FP64 residual of cgne_eo.  Inner level: CG steps
 // on FP16 vectors (E16 layout, per-block scales) with the FP16 stencil and
 // FP32 arithmetic; the solution increment accumulates in FP32.  Three
 // levels (middle = F32): when the iterated residual has fallen by
-// RELIABLE_DELTA, it is replaced by the FP32 true residual of the middle
+// RELIABLE_DELTA_F16, it is replaced by the FP32 true residual of the middle
 // system Dhat x32 = bh32; when that has fallen by OUTER_DELTA (or reached the
 // tolerance), x32 is folded into the FP64 solution, the FP64 true residual
 // becomes the middle system's new right-hand side and x32 restarts at zero.
@@ -846,7 +859,7 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     Work bhw(c, fb), r64w(c, fb), t64w(c, fb), o64w(c, fb), x32w(c, f32), b32w(c, f32), d32w(c, f32), t32w(c, f32),
         pw(c, fe), ww(c, fe), qw(c, fe), rw(c, fe), tw(c, fe), scal(c, sizeof(double2) * 8 * M),
         red(c, sizeof(double) * std::max<long>(red_scratch(M), 2L * g.nblk * M)),
-        ctl(c, 3 * sizeof(double) * M + 6 * sizeof(int32_t) * M), lw(c, sizeof(int32_t) * M);
+        ctl(c, 4 * sizeof(double) * M + 6 * sizeof(int32_t) * M), lw(c, sizeof(int32_t) * M);
     FlagPoll poll(c, M);
     if (!bhw.ok() || !r64w.ok() || !t64w.ok() || !o64w.ok() || !x32w.ok() || !b32w.ok() || !d32w.ok() || !t32w.ok() ||
         !pw.ok() || !ww.ok() || !qw.ok() || !rw.ok() || !tw.ok() || !scal.ok() || !red.ok() || !ctl.ok() ||
@@ -859,8 +872,8 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
               T = e16_field(g, M, tw.as<void>());
     double2 *sc = scal.as<double2>();
     double *part = red.as<double>();
-    double *bn2 = ctl.as<double>(), *rmax = bn2 + M, *b32n2 = rmax + M;
-    int32_t *alive = reinterpret_cast<int32_t *>(b32n2 + M), *upd = alive + M, *upd64 = upd + M, *its = upd64 + M;
+    double *bn2 = ctl.as<double>(), *rmax = bn2 + M, *b32n2 = rmax + M, *rprev = b32n2 + M;
+    int32_t *alive = reinterpret_cast<int32_t *>(rprev + M), *upd = alive + M, *upd64 = upd + M, *its = upd64 + M;
     int32_t *nmid = its + M, *nout = nmid + M;  // middle and outer updates per system
     const Links<double> U64 = U.u64;
     Links<double> U64n = U.u64;
@@ -889,6 +902,7 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     launch_p16(g, all, sc, 1, cref(R), P, s);
     k_cgm_rmax<<<nbm, 64, 0, s>>>(M, sc, rmax);
     k_cgm_rmax<<<nbm, 64, 0, s>>>(M, sc, b32n2);
+    k_cgm_rmax<<<nbm, 64, 0, s>>>(M, sc, rprev);
     k_c16_clear<<<nbm, 64, 0, s>>>(M, upd64);
     k_c16_clear<<<nbm, 64, 0, s>>>(M, nmid);
     k_c16_clear<<<nbm, 64, 0, s>>>(M, nout);
@@ -904,8 +918,8 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
             launch_eo16(g, sa, U16, 1.f, kf, 0, 0, cref(T), cref(W), Q, nullptr, q);
             launch_xr16(g, sa, sc, x32, cref(W), cref(Q), R, part, q);
             launch_final(sa, part, G, sc + 3, 8, q);
-            k_cgm_beta<<<nbm, 64, 0, q>>>(M, sc, RELIABLE_DELTA * RELIABLE_DELTA, sp.max_iter, alive, rmax, upd,
-                                          its);
+            k_cgm_beta<<<nbm, 64, 0, q>>>(M, sc, RELIABLE_DELTA_F16 * RELIABLE_DELTA_F16, sp.max_iter, alive, rmax,
+                                          upd, its);
             launch_p16(g, sa, sc, 0, cref(R), P, q);
         }
         if (three) {
@@ -914,7 +928,7 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
             launch_r16_from32(g, su, b32, d32, R, part, q);
             launch_final(su, part, G, sc + 6, 8, q);
             k_c16_mid<<<nbm, 64, 0, q>>>(M, sc, bn2, b32n2, tol * tol, OUTER_DELTA * OUTER_DELTA, sp.max_iter, its,
-                                         upd, upd64, rmax, nmid);
+                                         upd, upd64, rmax, rprev, nmid);
         } else {
             k_c16_promote<<<nbm, 64, 0, q>>>(M, upd, upd64);
         }
@@ -922,7 +936,8 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
         launch_add_to64<float>(s64, x32, x, q);
         apply_dhat<double>(g, s64, U64, kappa, 0, x, o64, t64, q);
         launch_sub_norm(s64, bh, t64, r64, red.as<double>(), sc + 5, 8, q);
-        k_c16_outer<<<nbm, 64, 0, q>>>(M, sc, bn2, b32n2, tol * tol, sp.max_iter, its, alive, upd64, rmax, nout);
+        k_c16_outer<<<nbm, 64, 0, q>>>(M, sc, bn2, b32n2, tol * tol, sp.max_iter, its, alive, upd64, rmax, rprev,
+                                       nout);
         launch_r16_from64(g, s64, r64, b32, x32, R, q);
         k_c16_clear<<<nbm, 64, 0, q>>>(M, upd64);
     };
