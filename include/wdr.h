@@ -89,8 +89,9 @@ typedef struct {
     double adj_tol;      /* adjoint solves of the second-order sample (1e-7) */
     wdr_prec inner;      /* precision of the innermost level: the Schwarz
                             preconditioner (FGCR), the CG iterations (CGNE;
-                            F16 = FP16 storage with per-block scales, FP32
-                            arithmetic, the FP16 stencil) and the block MR */
+                            F16 = FP16 storage with per-block scales, the
+                            FP16 stencil with its hops in packed FP16
+                            arithmetic, FP32 updates) and the block MR */
     wdr_prec middle;     /* CGNE only: F64 = two levels (the CG iterations
                             in `inner` directly under the FP64 reliable
                             updates); F32 = three levels (inner = F16: FP16
@@ -297,8 +298,10 @@ wdr_status wdr_apply_D_internal(wdr_ctx *ctx, const wdr_gauge *U, double kappa, 
  *              then one float power-of-two scale per (system, slot) >= the
  *              largest |component| of that block's half (stored value =
  *              value / scale); in holds parity 1 - p, diag and out parity p,
- *              and out receives fresh scales.  Needs 4^4 blocks in a
- *              2-colourable checkerboard and an SU(3) field.
+ *              and out receives fresh scales.  The hops are computed in
+ *              packed FP16 on the stored values, each hop scaled and summed
+ *              in FP32.  Needs 4^4 blocks in a 2-colourable checkerboard
+ *              and an SU(3) field.
  * EINVAL otherwise. */
 int64_t wdr_eo16_field_bytes(const wdr_ctx *ctx);
 wdr_status wdr_apply_hop_eo_internal(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_prec prec, int32_t parity,

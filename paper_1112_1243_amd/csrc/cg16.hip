@@ -12,7 +12,11 @@
 //              four entries of rows 0-1 (16 bytes per link, Vh of them) then
 //              the last two (8 bytes per link): U_mu(x) of the sites of that
 //              parity, boundary phase folded in, third row rebuilt.
-// Arithmetic is FP32 throughout; norms are summed in FP64.
+// The hops of the stencil (spin projection, third link row, link times half
+// spinor) run in packed FP16 on the stored values, whose magnitude is at
+// most 1 (one v_pk_fma_f16 handles a complex pair; the kernel was bound by
+// its FP32 instruction issue); everything else is FP32, and norms are summed
+// in FP64.
 #include "stencil.h"
 
 namespace wdr {
@@ -218,52 +222,118 @@ template <int MU> __device__ __forceinline__ int halo_entry(const int y[4])
     return (y[o2] << 3) | (y[o1] << 1) | (y[o0] >> 1);
 }
 
+// ---- packed FP16 arithmetic on (re, im) pairs: one v_pk_* instruction
+// acts on both halves of a complex number
+__device__ __forceinline__ h2 hbr(_Float16 a) { return (h2){a, a}; }
+// acc + u v
+__device__ __forceinline__ h2 hcfma(h2 u, h2 v, h2 acc)
+{
+    const h2 t = hbr(u.x) * v + acc;
+    return hbr(u.y) * (h2){-v.y, v.x} + t;
+}
+// acc + conj(u) v
+__device__ __forceinline__ h2 hcjfma(h2 u, h2 v, h2 acc)
+{
+    const h2 t = hbr(u.x) * v + acc;
+    return hbr(u.y) * (h2){v.y, -v.x} + t;
+}
+// the map of A psi_dn (see A_dn): 0 identity, 1 negate, 2 times i, 3 times -i
+__device__ __forceinline__ h2 hmap(h2 v, int op)
+{
+    return op == 0 ? v : op == 1 ? -v : op == 2 ? (h2){-v.y, v.x} : (h2){v.y, -v.x};
+}
+
 // The two hops of direction MU at output site x (parity par): neighbours from
 // the block's LDS copy (own) or the LDS halo (across a face, with that
-// neighbour block's scale), links from the prefetched registers.  DAG
-// applies gamma_5 to the loaded spinors (the caller to the result).
+// neighbour block's scale), links from the prefetched registers.  The spin
+// projection, the third link row and the link times half spinor run in
+// packed FP16 on the stored values (at most 1 in magnitude, the block scale
+// divided out); each hop's half spinor is then scaled and accumulated in
+// FP32.  DAG applies gamma_5 to the loaded spinors (the caller to the
+// result).
 template <int MU, int DAG>
 __device__ __forceinline__ void hop16(const Site16 *own, const Site16 *halo, float s_own, const float *s_face, int par,
                                       const int x[4], const Link16 &lf, const Link16 &lb, float wrap_f, float wrap_b,
                                       spinor<float> &acc)
 {
     typedef Cube<B4> CB;
+    // A psi_dn for psi_dn = (d0, d1): (o0, o1) = (map(d_i0), map(d_i1))
+    constexpr int i0 = MU == 0 ? 1 : MU == 1 ? 1 : 0, i1 = MU == 0 ? 0 : MU == 1 ? 0 : 1;
+    constexpr int m0 = MU == 0 ? 3 : MU == 1 ? 1 : MU == 2 ? 3 : 0, m1 = MU == 0 ? 3 : MU == 1 ? 0 : MU == 2 ? 2 : 0;
 #pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
         const bool fwd = dir == 0;
         const bool inside = fwd ? x[MU] + 1 < B4 : x[MU] > 0;
         int y[4] = {x[0], x[1], x[2], x[3]};
         y[MU] = fwd ? (inside ? x[MU] + 1 : 0) : (inside ? x[MU] - 1 : B4 - 1);
-        spinor<float> p;
-        if (inside)
-            ld_site_lds(own, CB::index(y) - (1 - par) * VH4, s_own, p);
-        else
-            ld_site_lds(halo, (2 * MU + dir) * 32 + halo_entry<MU>(y), s_face[2 * MU + dir], p);
-        su3<float> u;
-        unpack_link(fwd ? lf : lb, fwd ? wrap_f : wrap_b, u);
-        if (DAG) {
+        const int e = inside ? CB::index(y) - (1 - par) * VH4 : (2 * MU + dir) * 32 + halo_entry<MU>(y);
+        const Site16 &st = inside ? own[e] : halo[e];
+        const float s = inside ? s_own : s_face[2 * MU + dir];
+        h2 p[12];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                p.s[2].c[a] = neg(p.s[2].c[a]);
-                p.s[3].c[a] = neg(p.s[3].c[a]);
+        for (int k = 0; k < 3; ++k) {
+            Q16 q;
+            q.u = st.q[k];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) p[4 * k + j] = q.h[j];
+        }
+        // h = psi_up -+ A psi_dn (forward -, backward +; gamma_5 flips psi_dn)
+        const bool minus = fwd != (DAG != 0);
+        h2 h0[3], h1[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const h2 o0 = hmap(p[6 + 3 * i0 + a], m0), o1 = hmap(p[6 + 3 * i1 + a], m1);
+            h0[a] = minus ? p[a] - o0 : p[a] + o0;
+            h1[a] = minus ? p[3 + a] - o1 : p[3 + a] + o1;
+        }
+        // the link: rows 0 and 1 as stored, row 2 = sg conj(row0 x row1)
+        const Link16 &lk = fwd ? lf : lb;
+        const float sg = fwd ? wrap_f : wrap_b;
+        h2 u[3][3];
+        u[0][0] = lk.a.h[0];
+        u[0][1] = lk.a.h[1];
+        u[0][2] = lk.a.h[2];
+        u[1][0] = lk.a.h[3];
+        u[1][1] = lk.b.h[0];
+        u[1][2] = lk.b.h[1];
+        const h2 sgc = (h2){(_Float16)sg, (_Float16)(-sg)};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int pp = (c + 1) % 3, qq = (c + 2) % 3;
+            const h2 v = hcfma(u[0][qq], -u[1][pp], hcfma(u[0][pp], u[1][qq], (h2){0, 0}));
+            u[2][c] = v * sgc;
+        }
+        // c = U h (forward) or U^+ h (backward)
+        h2 c0[3], c1[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            h2 r0 = (h2){0, 0}, r1 = (h2){0, 0};
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (fwd) {
+                    r0 = hcfma(u[a][b], h0[b], r0);
+                    r1 = hcfma(u[a][b], h1[b], r1);
+                } else {
+                    r0 = hcjfma(u[b][a], h0[b], r0);
+                    r1 = hcjfma(u[b][a], h1[b], r1);
+                }
             }
+            c0[a] = r0;
+            c1[a] = r1;
         }
-        vec3<float> a0, a1;
-        A_dn(MU, p.s[2], p.s[3], a0, a1);
-        vec3<float> h0, h1;
+        // scaled to FP32, spins 2 and 3 rebuilt as -+ A^+ c
+        vec3<float> f0, f1;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            h0.c[a] = fwd ? p.s[0].c[a] - a0.c[a] : p.s[0].c[a] + a0.c[a];
-            h1.c[a] = fwd ? p.s[1].c[a] - a1.c[a] : p.s[1].c[a] + a1.c[a];
+            f0.c[a] = mk<float>(s * (float)c0[a].x, s * (float)c0[a].y);
+            f1.c[a] = mk<float>(s * (float)c1[a].x, s * (float)c1[a].y);
         }
-        const vec3<float> c0 = fwd ? mul(u, h0) : mul_dag(u, h0);
-        const vec3<float> c1 = fwd ? mul(u, h1) : mul_dag(u, h1);
         vec3<float> d0, d1;
-        Adag_h(MU, c0, c1, d0, d1);
+        Adag_h(MU, f0, f1, d0, d1);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
-            acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
+            acc.s[0].c[a] = acc.s[0].c[a] + f0.c[a];
+            acc.s[1].c[a] = acc.s[1].c[a] + f1.c[a];
             acc.s[2].c[a] = fwd ? acc.s[2].c[a] - d0.c[a] : acc.s[2].c[a] + d0.c[a];
             acc.s[3].c[a] = fwd ? acc.s[3].c[a] - d1.c[a] : acc.s[3].c[a] + d1.c[a];
         }
