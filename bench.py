@@ -790,8 +790,8 @@ TIMED_RANGE = "timed estimates"
 # compulsory bytes of one k_eo16 launch per system of V sites (one even-odd
 # half in FP16: the input half, the output half and every link of the
 # lattice, FP16 two-row, 24 B per link), plus the FP16 diagonal half if any
-EO16_SOURCES = ["paper_1112_1243_amd/csrc/cg16.hip", "paper_1112_1243_amd/csrc/stencil.h",
-                "paper_1112_1243_amd/csrc/wdr_internal.h"]
+EO16_SOURCES = ["paper_1112_1243_amd/csrc/cg16.hip", "paper_1112_1243_amd/csrc/half2.h",
+                "paper_1112_1243_amd/csrc/stencil.h", "paper_1112_1243_amd/csrc/wdr_internal.h"]
 EO16_COUNTERS = os.path.join(ROOT, "profiles", "eo16_32x32x32x32_counters.md")
 
 

@@ -17,6 +17,7 @@
 // most 1 (one v_pk_fma_f16 handles a complex pair; the kernel was bound by
 // its FP32 instruction issue); everything else is FP32, and norms are summed
 // in FP64.
+#include "half2.h"
 #include "stencil.h"
 
 namespace wdr {
@@ -220,27 +221,6 @@ template <int MU> __device__ __forceinline__ int halo_entry(const int y[4])
 {
     constexpr int o0 = MU == 0 ? 1 : 0, o1 = MU <= 1 ? 2 : 1, o2 = MU <= 2 ? 3 : 2;
     return (y[o2] << 3) | (y[o1] << 1) | (y[o0] >> 1);
-}
-
-// ---- packed FP16 arithmetic on (re, im) pairs: one v_pk_* instruction
-// acts on both halves of a complex number
-__device__ __forceinline__ h2 hbr(_Float16 a) { return (h2){a, a}; }
-// acc + u v
-__device__ __forceinline__ h2 hcfma(h2 u, h2 v, h2 acc)
-{
-    const h2 t = hbr(u.x) * v + acc;
-    return hbr(u.y) * (h2){-v.y, v.x} + t;
-}
-// acc + conj(u) v
-__device__ __forceinline__ h2 hcjfma(h2 u, h2 v, h2 acc)
-{
-    const h2 t = hbr(u.x) * v + acc;
-    return hbr(u.y) * (h2){v.y, -v.x} + t;
-}
-// the map of A psi_dn (see A_dn): 0 identity, 1 negate, 2 times i, 3 times -i
-__device__ __forceinline__ h2 hmap(h2 v, int op)
-{
-    return op == 0 ? v : op == 1 ? -v : op == 2 ? (h2){-v.y, v.x} : (h2){v.y, -v.x};
 }
 
 // The two hops of direction MU at output site x (parity par): neighbours from

@@ -10,6 +10,7 @@
 // is solved by MR steps with both half fields resident in LDS; only the
 // links are read from global memory (they stay in L2 across the steps).
 // Per-block inner products are wavefront shuffles plus an LDS tree.
+#include "half2.h"
 #include "lds_stencil.h"
 
 namespace wdr {
@@ -693,6 +694,333 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) __attribute__((amdgpu_waves_per_eu
     }
 }
 
+// ---------------------------------------------------------------- FP16 hops
+// The block-solve form (MODE 1, FP16 storage) of k_block_mr_dir with its hop
+// phases in packed FP16 arithmetic: the LDS half fields and the partial sums
+// hold FP16, the links sit in registers as FP16 (third rows rebuilt once),
+// and each hop's spin projection, link times half spinor and accumulation
+// run on (re, im) pairs with v_pk_* instructions; the MR vectors, the
+// inner products and the step coefficients stay FP32.  The FP32 kernel was
+// bound by its vector instruction issue (about 585 per wavefront and MR
+// step); this form halves the hop arithmetic and the LDS bytes.  The MR
+// iterate goes to LDS times a power-of-two factor sigma that keeps its RMS
+// near 1 (from |rho|^2 of the previous step, which MR never increases), so
+// the FP16 values neither overflow nor lose their small components; the
+// operator's output is divided by sigma again in FP32.
+
+// the FP16 links and LDS neighbour indices of thread (MU, h), as HopRegs
+struct HopRegs16 {
+    h2 f[2][9], b[2][9];
+    int nf[2], nb[2];
+};
+
+// rows 0, 1 of the FP16 two-row link at site l, direction MU, and the third
+// row conj(row0 x row1) (in-block links never carry a boundary sign)
+template <int MU>
+__device__ __forceinline__ void load_link16(const h2 *U16, int slot, int l, h2 u[9])
+{
+    constexpr int Vb = Cube<4>::Vb;
+    const auto *Ug = as_global(U16);
+    const long base = (long)slot * 4 * 6 * Vb + (long)MU * 6 * Vb + l;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) u[e] = Ug[base + (long)e * Vb];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int a = (c + 1) % 3, b = (c + 2) % 3;
+        const h2 v = hcfma(u[b], -u[3 + a], hcfma(u[a], u[3 + b], (h2){0, 0}));
+        u[6 + c] = (h2){v.x, -v.y};
+    }
+}
+
+template <int MU>
+__device__ __forceinline__ void load_hop_regs16(const h2 *U16, int slot, int h, const int xe[4], const int xo[4],
+                                                HopRegs16 &R)
+{
+    typedef Cube<4> CB;
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+        const int *x = par ? xo : xe;
+        const int l = par * CB::Vh + h;
+        const int off = par ? 0 : CB::Vh;  // the neighbours have the other parity
+        int y[4] = {x[0], x[1], x[2], x[3]};
+        R.nf[par] = R.nb[par] = -1;
+        if (x[MU] + 1 < 4) {
+            y[MU] = x[MU] + 1;
+            R.nf[par] = CB::index(y) - off;
+            load_link16<MU>(U16, slot, l, R.f[par]);
+        }
+        if (x[MU] > 0) {
+            y[MU] = x[MU] - 1;
+            const int nl = CB::index(y);
+            R.nb[par] = nl - off;
+            load_link16<MU>(U16, slot, nl, R.b[par]);
+        }
+    }
+}
+
+// the in-block hops of direction MU at one output site: neighbours from the
+// FP16 LDS half field sh ([12][Vh]), links from registers; the sum of the
+// (at most two) hops into acc (12 FP16 complex, component 3 spin + colour)
+template <int MU>
+__device__ __forceinline__ void hop_dir16(const h2 *sh, const h2 *uf, const h2 *ub, int nf, int nb, h2 acc[12])
+{
+    constexpr int Vh = Cube<4>::Vh;
+    constexpr int i0 = MU <= 1 ? 1 : 0, i1 = MU <= 1 ? 0 : 1;  // A psi_dn takes (d_i0, d_i1)
+    constexpr int m0 = MU == 0 ? 3 : MU == 1 ? 1 : MU == 2 ? 3 : 0, m1 = MU == 0 ? 3 : MU == 1 ? 0 : MU == 2 ? 2 : 0;
+    constexpr int r0 = MU == 0 ? 2 : MU == 1 ? 0 : MU == 2 ? 2 : 0, r1 = MU == 0 ? 2 : MU == 1 ? 1 : MU == 2 ? 3 : 0;
+    constexpr int j0 = MU <= 1 ? 1 : 0, j1 = MU <= 1 ? 0 : 1;  // A^+ h takes (c_j0, c_j1)
+#pragma unroll
+    for (int a = 0; a < 12; ++a) acc[a] = (h2){0, 0};
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+        const bool fwd = dir == 0;
+        const int nl = fwd ? nf : nb;
+        if (nl < 0) continue;
+        h2 p[12];
+#pragma unroll
+        for (int c = 0; c < 12; ++c) p[c] = sh[c * Vh + nl];
+        h2 hh[2][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const h2 o0 = hmap(p[6 + 3 * i0 + a], m0), o1 = hmap(p[6 + 3 * i1 + a], m1);
+            hh[0][a] = fwd ? p[a] - o0 : p[a] + o0;
+            hh[1][a] = fwd ? p[3 + a] - o1 : p[3 + a] + o1;
+        }
+        const h2 *u = fwd ? uf : ub;
+        h2 c[2][3];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                h2 r = (h2){0, 0};
+#pragma unroll
+                for (int b = 0; b < 3; ++b) r = fwd ? hcfma(u[3 * a + b], hh[s][b], r) : hcjfma(u[3 * b + a], hh[s][b], r);
+                c[s][a] = r;
+            }
+        // spins 2, 3: -+ A^+ c
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            acc[a] = acc[a] + c[0][a];
+            acc[3 + a] = acc[3 + a] + c[1][a];
+            const h2 d0 = hmap(c[j0][a], r0), d1 = hmap(c[j1][a], r1);
+            acc[6 + a] = fwd ? acc[6 + a] - d0 : acc[6 + a] + d0;
+            acc[9 + a] = fwd ? acc[9 + a] - d1 : acc[9 + a] + d1;
+        }
+    }
+}
+
+// hop phase of thread (w4, h) into the FP16 partial sums
+__device__ __forceinline__ void hop_phase16(int w4, int par, int h, const h2 *sh, const HopRegs16 &R, h2 *part)
+{
+    constexpr int Vh = Cube<4>::Vh;
+    h2 acc[12];
+    switch (w4) {
+    case 0: hop_dir16<0>(sh, R.f[par], R.b[par], R.nf[par], R.nb[par], acc); break;
+    case 1: hop_dir16<1>(sh, R.f[par], R.b[par], R.nf[par], R.nb[par], acc); break;
+    case 2: hop_dir16<2>(sh, R.f[par], R.b[par], R.nf[par], R.nb[par], acc); break;
+    default: hop_dir16<3>(sh, R.f[par], R.b[par], R.nf[par], R.nb[par], acc); break;
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) part[(w4 * 12 + c) * Vh + h] = acc[c];
+}
+// spin q of site h summed over the four FP16 partial sums, in FP32
+__device__ __forceinline__ void sum_part16(const h2 *part, int q, int h, cx<float> v[3])
+{
+    constexpr int Vh = Cube<4>::Vh;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int c = 3 * q + a;
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const h2 t = part[(d * 12 + c) * Vh + h];
+            re += (float)t.x;
+            im += (float)t.y;
+        }
+        v[a] = mk<float>(re, im);
+    }
+}
+__device__ __forceinline__ h2 to16(cx<float> a, float f) { return (h2){(_Float16)(a.re * f), (_Float16)(a.im * f)}; }
+
+template <int OCC>
+__global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu(OCC))) void k_block_mr_h16(
+    Geo g, const int32_t *__restrict__ active, const void *const *__restrict__ Utab, const double *__restrict__ kap,
+    long n, const int32_t *__restrict__ sched, const void *__restrict__ src_v, const float *__restrict__ src_s,
+    void *__restrict__ dst_v, float *__restrict__ dst_s, float kappa, int nmr)
+{
+    typedef Cube<4> CB;
+    constexpr int Vb = CB::Vb, Vh = CB::Vh, NT = 4 * Vh;
+    __shared__ h2 she[12 * Vh];
+    __shared__ h2 sho[12 * Vh];
+    __shared__ h2 part[4 * 12 * Vh];
+    __shared__ float red[4][NT / 64];
+    __shared__ float coef[3];
+    const int m = blockIdx.y;
+    if (active && !active[m]) return;
+    if (kap) kappa = (float)kap[m];
+    const h2 *__restrict__ src16 = static_cast<const h2 *>(src_v) + m * n;
+    h2 *__restrict__ dst16 = static_cast<h2 *>(dst_v) + m * n;
+    const int slot = sched[blockIdx.x];
+    // every vector below is in units of the right-hand side's block scale
+    const float s_src = src_s[(long)m * g.nblk + slot];
+    const int tid = threadIdx.x;
+    const int w4 = __builtin_amdgcn_readfirstlane(tid / Vh);  // mu in hop phases, spin q in vector phases
+    const int h = tid % Vh;
+    int xe[4], xo[4];
+    CB::coords(h, xe);
+    CB::coords(Vh + h, xo);
+    const long be = (long)slot * 12 * Vb + h, bo = be + Vh;
+
+    HopRegs16 R;
+    const h2 *U16 = static_cast<const h2 *>(Utab[m]);
+    switch (w4) {
+    case 0: load_hop_regs16<0>(U16, slot, h, xe, xo, R); break;
+    case 1: load_hop_regs16<1>(U16, slot, h, xe, xo, R); break;
+    case 2: load_hop_regs16<2>(U16, slot, h, xe, xo, R); break;
+    default: load_hop_regs16<3>(U16, slot, h, xe, xo, R); break;
+    }
+    // the right-hand side as stored (|value| <= 1): spin q of site h
+    cx<float> re[3], ro[3], v[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const h2 x = src16[be + (long)(3 * w4 + a) * Vb], y = src16[bo + (long)(3 * w4 + a) * Vb];
+        re[a] = mk<float>((float)x.x, (float)x.y);
+        ro[a] = mk<float>((float)y.x, (float)y.y);
+        sho[(3 * w4 + a) * Vh + h] = y;
+    }
+    __syncthreads();
+    // rhs_e = r_e + kappa H_eo r_o
+    hop_phase16(w4, 0, h, sho, R, part);
+    __syncthreads();
+    cx<float> rho[3], del[3];
+    sum_part16(part, w4, h, v);
+    float rr = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rho[a] = re[a] + scale(kappa, v[a]);
+        del[a] = mk<float>(0, 0);
+        rr += rho[a].re * rho[a].re + rho[a].im * rho[a].im;
+    }
+    // the first scale from |rho|^2
+    rr = wave_sum(rr, 64);
+    if ((tid & 63) == 0) red[3][tid >> 6] = rr;
+    __syncthreads();
+    if (tid == 0) {
+        float t = 0.f;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) t += red[3][w];
+        coef[2] = t > 0.f ? exp2f(-rintf(0.5f * log2f(t / (12.f * Vh)))) : 1.f;
+    }
+    __syncthreads();
+    float sig = coef[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) she[(3 * w4 + a) * Vh + h] = to16(rho[a], sig);
+
+    const float k2 = kappa * kappa;
+    for (int it = 0; it < nmr; ++it) {
+        __syncthreads();
+        hop_phase16(w4, 1, h, she, R, part);  // t_o = sigma H_oe rho
+        __syncthreads();
+        sum_part16(part, w4, h, v);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sho[(3 * w4 + a) * Vh + h] = to16(v[a], 1.f);
+        __syncthreads();
+        hop_phase16(w4, 0, h, sho, R, part);  // sigma H_eo H_oe rho
+        __syncthreads();
+        sum_part16(part, w4, h, v);
+        const float isig = 1.f / sig;
+        float pr = 0, pi = 0, pp = 0, r2 = 0;
+        cx<float> p[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            p[a] = rho[a] - scale(k2 * isig, v[a]);
+            const cx<float> q = conjmul(p[a], rho[a]);
+            pr += q.re;
+            pi += q.im;
+            pp += p[a].re * p[a].re + p[a].im * p[a].im;
+            r2 += rho[a].re * rho[a].re + rho[a].im * rho[a].im;
+        }
+        pr = wave_sum(pr, 64);
+        pi = wave_sum(pi, 64);
+        pp = wave_sum(pp, 64);
+        r2 = wave_sum(r2, 64);
+        if ((tid & 63) == 0) {
+            red[0][tid >> 6] = pr;
+            red[1][tid >> 6] = pi;
+            red[2][tid >> 6] = pp;
+            red[3][tid >> 6] = r2;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            float sr = 0, si = 0, sq = 0, st = 0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) {
+                sr += red[0][w];
+                si += red[1][w];
+                sq += red[2][w];
+                st += red[3][w];
+            }
+            coef[0] = sq > 0 ? sr / sq : 0.f;
+            coef[1] = sq > 0 ? si / sq : 0.f;
+            // |rho_new|^2 <= |rho|^2: the scale of the next stored iterate
+            coef[2] = st > 0.f ? exp2f(-rintf(0.5f * log2f(st / (12.f * Vh)))) : 1.f;
+        }
+        __syncthreads();
+        const cx<float> al = mk<float>(coef[0], coef[1]);
+        sig = coef[2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            del[a] = del[a] + al * rho[a];
+            rho[a] = rho[a] - al * p[a];
+            she[(3 * w4 + a) * Vh + h] = to16(rho[a], sig);
+        }
+    }
+
+    // d_o = r_o + kappa H_oe d_e, with d_e scaled to at most 1 in LDS
+    float mx = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) mx = fmaxf(mx, fmaxf(fabsf(del[a].re), fabsf(del[a].im)));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_down(mx, off, 64));
+    __syncthreads();  // the last step's LDS reads are done; red is free
+    if ((tid & 63) == 0) red[0][tid >> 6] = mx;
+    __syncthreads();
+    mx = red[0][0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) mx = fmaxf(mx, red[0][w]);
+    const float sd = pow2_at_least(mx), isd = 1.f / sd;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) she[(3 * w4 + a) * Vh + h] = to16(del[a], isd);
+    __syncthreads();
+    hop_phase16(w4, 1, h, she, R, part);
+    __syncthreads();
+    sum_part16(part, w4, h, v);
+    // the new values of spin q at even site h (ye) and odd site h (yo)
+    cx<float> ye[3], yo[3];
+    float mo = 0.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ye[a] = scale(s_src, del[a]);
+        yo[a] = scale(s_src, ro[a] + scale(kappa * sd, v[a]));
+        mo = fmaxf(mo, fmaxf(fmaxf(fabsf(ye[a].re), fabsf(ye[a].im)), fmaxf(fabsf(yo[a].re), fabsf(yo[a].im))));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mo = fmaxf(mo, __shfl_down(mo, off, 64));
+    __syncthreads();
+    if ((tid & 63) == 0) red[0][tid >> 6] = mo;
+    __syncthreads();
+    mo = red[0][0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) mo = fmaxf(mo, red[0][w]);
+    const float sc = pow2_at_least(mo), inv = 1.f / sc;
+    if (tid == 0) dst_s[(long)m * g.nblk + slot] = sc;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        dst16[be + (long)(3 * w4 + a) * Vb] = to_h2(ye[a], inv);
+        dst16[bo + (long)(3 * w4 + a) * Vb] = to_h2(yo[a], inv);
+    }
+}
+
 // block solves with at least this many workgroups (blocks x systems) use the
 // four-waves-per-SIMD form: two blocks per CU, at the price of a few spills
 constexpr long MR_OCC4_WORKGROUPS = 2048;
@@ -763,11 +1091,11 @@ bool launch_mr_h16(int mode, const Geo &g, const Sys &sy, Links16 U, H16c src, H
         k_block_mr_dir<float, 0, 4, 1><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
                                                                        src.v, src.s, dst.v, dst.s, kappa, nmr);
     else if (two_per_cu(g, (long)nslots * sy.M))
-        k_block_mr_dir<float, 1, 4, 1, 4><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
-                                                                       src.v, src.s, dst.v, dst.s, kappa, nmr);
+        k_block_mr_h16<4><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si], src.v, src.s,
+                                                            dst.v, dst.s, kappa, nmr);
     else
-        k_block_mr_dir<float, 1, 4, 1><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
-                                                                       src.v, src.s, dst.v, dst.s, kappa, nmr);
+        k_block_mr_h16<1><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si], src.v, src.s,
+                                                            dst.v, dst.s, kappa, nmr);
     return true;
 }
 
