@@ -226,9 +226,13 @@ int32_t wdr_gauge_is_su3(const wdr_gauge *g);
  * every call that takes U applies the clover operator: D, D_b and D_ee in F64
  * / F32 (wdr_apply_D, wdr_apply_D_internal, wdr_apply_D_noalloc,
  * wdr_apply_Dblock, wdr_apply_Dee; the hops of wdr_apply_Dhop have no
- * diagonal term), wdr_solve with CGNE and an F64 / F32 inner level, and FULL
- * estimates by such solves (wdr_logdet_ratio / _batch; both fields of a ratio
- * must carry the same csw).  Those calls must pass this kappa (EINVAL
+ * diagonal term), wdr_solve with CGNE and an F64 / F32 inner level,
+ * wdr_block_solve and wdr_apply_schur with an F64 / F32 inner level (the
+ * block solves then run as FP64 defect correction around an even-odd CGNE of
+ * the block operator, not the block MR), and FULL, BLOCKS, SCHUR and DD
+ * estimates by such solves (wdr_logdet_ratio / _batch; CGNE wherever D is
+ * inverted; both fields of a ratio must carry the same csw).  Those calls
+ * must pass this kappa (EINVAL
  * otherwise); every other call taking U returns EINVAL.  csw = 0 removes the
  * term.  EINVAL also for a context with open boundaries (bc = 0) and when a
  * block of A is (nearly) singular (its LDL^H pivots are checked).  Waits for
@@ -367,8 +371,9 @@ wdr_status wdr_solve(wdr_ctx *ctx, const wdr_gauge *U, double kappa, const wdr_s
  * the Dirichlet block operators D_b on the diagonal, so their inverses in
  * eq. ddfactor are independent block solves): x = D_cc^-1 b on those blocks,
  * zero elsewhere; per-block relative residual <= block_tol.  Even-odd MR
- * rounds in sp->inner with FP64 defect correction.  ENOCONV if a block
- * stops above block_tol. */
+ * rounds in sp->inner with FP64 defect correction (with a clover term:
+ * rounds of even-odd CGNE on the blocks of the colour, sp->inner F64 or
+ * F32).  ENOCONV if a block stops above block_tol. */
 wdr_status wdr_block_solve(wdr_ctx *ctx, const wdr_gauge *U, double kappa, int32_t colour,
                            const wdr_solver_params *sp, const double *dev_b, double *dev_x,
                            wdr_solve_info *host_info, void *stream);

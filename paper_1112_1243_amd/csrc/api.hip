@@ -54,8 +54,8 @@ wdr_status check_gauge(const wdr_ctx *c, const wdr_gauge *U, bool clover_ok = fa
     if (U->c64) {
         if (!clover_ok) {
             set_error("this call does not support a gauge field with a clover term (supported: D, D_b, the block "
-                      "hops and D_ee in F64 / F32, CGNE solves with F64 / F32 inner precision, FULL estimates by "
-                      "such solves)");
+                      "hops and D_ee in F64 / F32; CGNE solves, block solves and the Schur complement with F64 / "
+                      "F32 inner precision; FULL, BLOCKS, SCHUR and DD estimates by such solves)");
             return WDR_EINVAL;
         }
         if (kappa != U->ckappa) {
@@ -66,11 +66,11 @@ wdr_status check_gauge(const wdr_ctx *c, const wdr_gauge *U, bool clover_ok = fa
     return WDR_OK;
 }
 
-// an estimate supports the clover term for the FULL ratio by CGNE with an
-// FP64 or FP32 inner level
+// an estimate supports the clover term with an FP64 or FP32 inner level, by
+// CGNE wherever it solves with D (every ratio but BLOCKS)
 bool clover_est_ok(const wdr_est_params *p)
 {
-    return p && p->op == WDR_OP_FULL && p->sp.solver == WDR_SOLVER_CGNE && p->sp.inner != WDR_F16;
+    return p && p->sp.inner != WDR_F16 && (p->op == WDR_OP_BLOCKS || p->sp.solver == WDR_SOLVER_CGNE);
 }
 wdr_status check_pair(const wdr_gauge *U, const wdr_gauge *Up)
 {
@@ -605,7 +605,8 @@ wdr_status wdr_block_solve(wdr_ctx *c, const wdr_gauge *U, double kappa, int32_t
 {
     wdr_status e = pre(c, b, x);
     if (e != WDR_OK) return e;
-    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
+    if ((e = check_gauge(c, U, sp && sp->inner != WDR_F16, kappa)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK)
+        return e;
     if (!sp || colour < 0 || colour > 2) {
         set_error("null solver parameters or colour not in 0..2");
         return WDR_EINVAL;
@@ -627,7 +628,8 @@ wdr_status wdr_apply_schur(wdr_ctx *c, const wdr_gauge *U, double kappa, const w
 {
     wdr_status e = pre(c, in, out);
     if (e != WDR_OK) return e;
-    if ((e = check_gauge(c, U)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
+    if ((e = check_gauge(c, U, sp && sp->inner != WDR_F16, kappa)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK)
+        return e;
     if (!sp) {
         set_error("null solver parameters");
         return WDR_EINVAL;

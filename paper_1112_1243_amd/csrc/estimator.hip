@@ -223,6 +223,9 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
             Xp.u64.ctab = reinterpret_cast<const double *const *>(tb + 10 * M);
             Xp.u32.ctab = reinterpret_cast<const float *const *>(tb + 11 * M);
         }
+        // the block operators D_b: with a clover term their diagonal is A
+        Links<double> Xb = X.u64, Xpb = Xp.u64;
+        Xb.cmode = Xpb.cmode = CLOV_DIAG;
         const Sys all = all_sys(c, M);
         double2 *E = eta.as<double2>(), *Y = y.as<double2>(), *Z = z.as<double2>(), *W = w.as<double2>(),
                 *R = r.as<double2>(), *Tm = t.as<double2>();
@@ -249,12 +252,12 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
             apply_D64(c, all, Xp, kappa, Z, Tm, s);
             launch_sub(all, Y, Tm, R, s);                                                  // r = y - D' z
         } else if (op == WDR_OP_BLOCKS) {
-            launch_dslash<double>(g, all, X.u64, HOPS_IN, -1, 0, E, E, Y, kappa, 0, g.nblk, s);  // y = D_blk eta
+            launch_dslash<double>(g, all, Xb, HOPS_IN, -1, 0, E, E, Y, kappa, 0, g.nblk, s);  // y = D_blk eta
             if (!take(block_solve64(c, M, Xp, kappa, 2, sp, sp.block_tol, Y, Z, s1, s), true)) return hard;
             launch_g5<double>(g, all, Z, Tm, s);
             if (!take(block_solve64(c, M, Xp, kappa, 2, sp, sp.block_tol, Tm, W, s1, s), false)) return hard;
             launch_g5<double>(g, all, W, W, s);
-            launch_dslash<double>(g, all, Xp.u64, HOPS_IN, -1, 0, Z, Z, Tm, kappa, 0, g.nblk, s);
+            launch_dslash<double>(g, all, Xpb, HOPS_IN, -1, 0, Z, Z, Tm, kappa, 0, g.nblk, s);
             launch_sub(all, Y, Tm, R, s);
         } else {  // SCHUR
             wdr_status e = schur64(c, M, X, kappa, sp, E, Tm, s1, s);                     // Dhat eta (black)
@@ -263,7 +266,7 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
                 else return e;
             }
             launch_zero<double>(Y, n * M, s);                                              // y = A' Dhat eta
-            launch_dslash<double>(g, all, Xp.u64, HOPS_IN, -1, 0, Tm, Tm, Y, kappa, b0, bn, s);
+            launch_dslash<double>(g, all, Xpb, HOPS_IN, -1, 0, Tm, Tm, Y, kappa, b0, bn, s);
             if (!take(solve64(c, M, Xp, kappa, sp, sp.tol, Y, Z, s1, s), true)) return hard;  // D' z = [y; 0]
             apply_D64(c, all, Xp, kappa, Z, Tm, s);
             launch_sub(all, Y, Tm, R, s);                                                  // r = y - D' z
@@ -281,7 +284,7 @@ static wdr_status run_op(wdr_ctx *c, const Path &path, const std::vector<Proposa
             for (int mu = 0; mu < 4; ++mu) lin += (double)(g.B[mu] - 1) / g.B[mu];
             const double V = g.V, sb = spin_b<double>(), lk = su3 ? 384.0 : 576.0;
             const double D = V * (2 * sb + lk + (path.clov ? clov_b<double>() : 0.0)),
-                         Din = V * (2 * sb + lin * (su3 ? 96.0 : 144.0));
+                         Din = V * (2 * sb + lin * (su3 ? 96.0 : 144.0) + (path.clov ? clov_b<double>() : 0.0));
             double b = V * sb + V * 3 * sb + V * 4 * sb;  // noise, r = y - X' z, sample sums
             if (op == WDR_OP_FULL) b += 2 * D + 2 * V * 2 * sb;
             else if (op == WDR_OP_BLOCKS) b += 2 * Din + 2 * V * 2 * sb;

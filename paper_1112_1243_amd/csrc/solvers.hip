@@ -311,6 +311,13 @@ __global__ __launch_bounds__(BC_NT) void k_block_check(int nblk, int slot0, int 
     }
 }
 
+// clears the fields of the systems whose flag is 0
+__global__ __launch_bounds__(256) void k_zero_dead(const int32_t *alive, long n, long total, double2 *f)
+{
+    const long i = blockIdx.x * 256L + threadIdx.x;
+    if (i < total && !alive[i / n]) f[i] = make_double2(0.0, 0.0);
+}
+
 }  // namespace
 
 void apply_D64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const double2 *in, double2 *out,
@@ -599,23 +606,37 @@ template <typename T> Links<T> links_of(const GaugeTab &U);
 template <> Links<double> links_of<double>(const GaugeTab &U) { return U.u64; }
 template <> Links<float> links_of<float>(const GaugeTab &U) { return U.u32; }
 
+// The operator an even-odd solve works on: D (all hops, every block), or
+// the Dirichlet block operator D_b (hops inside the blocks) on the blocks of
+// slots [slot0, slot0 + ns), whose even-odd reduction is again block by block
+// (a block of even extent holds both parities of its sites).
+struct EoOp {
+    int hops = HOPS_ALL;
+    int slot0 = 0, ns = -1;  // ns < 0: every block
+    int count(const Geo &g) const { return ns < 0 ? g.nblk : ns; }
+};
+
 // out_e = (Dhat in)_e, or (Dhat^+ in)_e with dag; tmp receives
-// -k A_oo^-1 H_oe in_e on odd sites; odd sites of out are not written
+// -k A_oo^-1 H_oe in_e on odd sites; odd sites of out are not written (nor
+// blocks outside op's slots)
 template <typename T>
 static void apply_dhat(const Geo &g, const Sys &sy, Links<T> U, T kappa, int dag, const T2<T> *in, T2<T> *tmp,
-                       T2<T> *out, hipStream_t s)
+                       T2<T> *out, hipStream_t s, const EoOp &op = EoOp())
 {
     Links<T> Ui = U, Un = U;
     Ui.cmode = CLOV_INV;
     Un.kneg = 1;
     Un.cmode = CLOV_DIAG;
-    launch_dslash<T>(g, sy, Ui, HOPS_ALL, 1, dag, in, nullptr, tmp, kappa, 0, g.nblk, s);
-    launch_dslash<T>(g, sy, Un, HOPS_ALL, 0, dag, tmp, in, out, -kappa, 0, g.nblk, s);
+    launch_dslash<T>(g, sy, Ui, op.hops, 1, dag, in, nullptr, tmp, kappa, op.slot0, op.count(g), s);
+    launch_dslash<T>(g, sy, Un, op.hops, 0, dag, tmp, in, out, -kappa, op.slot0, op.count(g), s);
 }
 
+// op selects D or the Dirichlet blocks of some slots (b must then vanish on
+// the other blocks, and x does there)
 template <typename T>
 static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp, double tol,
-                          const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
+                          const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s,
+                          const EoOp &op = EoOp())
 {
     const long n = field_n(c), total = n * M;
     const int prec = sizeof(T) == 8 ? WDR_F64 : WDR_F32;
@@ -637,8 +658,10 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     const Links<T> UT = links_of<T>(U);
     Links<double> U64n = U.u64;
     U64n.kneg = 1;
+    U64n.cmode = CLOV_NONE;  // the diagonal input b_e enters as it is
     const T kT = (T)kappa;
     const Sys all = all_sys(c, M);
+    const int o0 = op.slot0, on = op.count(g);
     // the iterated vectors live on even sites: their updates and norms skip
     // the odd halves (zero) where the half-block volume allows it
     Sys sa{M, alive, n}, su{M, upd, n};
@@ -653,7 +676,7 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     launch_zero<double>(t64, total, s);
     const bool clov = U.u64.ctab != nullptr;
     if (clov) launch_clover_mul<double>(g, all, U.u64.ctab, 1, 1, b, o64, s);  // odd sites of o64
-    launch_dslash<double>(g, all, U64n, HOPS_ALL, 0, 0, clov ? o64 : b, b, bh, -kappa, 0, g.nblk, s);
+    launch_dslash<double>(g, all, U64n, op.hops, 0, 0, clov ? o64 : b, b, bh, -kappa, o0, on, s);
     launch_norm2<double>(all, b, red.as<double>(), sc + 5, 8, s);
     k_cgm_init<<<nbm, 64, 0, s>>>(M, sc, bn2, rmax, alive, upd, its);  // |b|^2 of the full system
     launch_convert<T, double>(all, bh, r, s);
@@ -670,8 +693,8 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
         const long tl = sa.ne() * sa.launch_m();
         for (int i = 0; i < ue; ++i) {
             // w = Dhat^+ p, q = Dhat w, e += alpha w, r -= alpha q, p = r + beta p
-            apply_dhat<T>(g, sa, UT, kT, 1, p, t, w, q);
-            apply_dhat<T>(g, sa, UT, kT, 0, w, t, qv, q);
+            apply_dhat<T>(g, sa, UT, kT, 1, p, t, w, q, op);
+            apply_dhat<T>(g, sa, UT, kT, 0, w, t, qv, q, op);
             launch_norm2<T>(sa, w, red.as<double>(), sc + 1, 8, q);
             launch_cg_xr_norm<T>(sa, sc, 8, e, w, r, qv, red.as<double>(), sc + 3, 8, q);
             k_cgm_beta<<<nbm, 64, 0, q>>>(M, sc, RELIABLE_DELTA * RELIABLE_DELTA, sp.max_iter, alive, rmax, upd,
@@ -680,7 +703,7 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
         }
         // x_e += e, r = bh - Dhat x_e in FP64
         launch_add_to64<T>(su, e, x, q);
-        apply_dhat<double>(g, su, U.u64, kappa, 0, x, o64, t64, q);
+        apply_dhat<double>(g, su, U.u64, kappa, 0, x, o64, t64, q, op);
         launch_sub_norm(su, bh, t64, r64, red.as<double>(), sc + 5, 8, q);
         k_cgm_update<<<nbm, 64, 0, q>>>(M, sc, bn2, tol * tol, sp.max_iter, its, alive, upd, rmax, nupd);
         k_cgm_refresh<T><<<nb256(tl), 256, 0, q>>>(su.list, n, su.hs, tl, upd, r64, r, e);
@@ -725,7 +748,7 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     launch_zero<double>(t64, total, s);
     Links<double> U64i = U64n;
     U64i.cmode = CLOV_INV;
-    launch_dslash<double>(g, all, U64i, HOPS_ALL, 1, 0, x, b, t64, -kappa, 0, g.nblk, s);
+    launch_dslash<double>(g, all, U64i, op.hops, 1, 0, x, b, t64, -kappa, o0, on, s);
     launch_add_to64<double>(all, t64, x, s);
 
     std::vector<double> hbn2(M), rn2;
@@ -738,18 +761,20 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     bool ok = true;
     // compulsory bytes per system: setup and final step, then per CG step
     // (four halves in T, |w|^2, the x / r update, the p update) and per
-    // reliable update (e into x, FP64 Dhat x, r64 = bh - Dhat x, the refresh)
-    const double V = g.V, H = V / 2;
-    const double setup = 3 * V * spin_b<double>() + half_b<double>(V, true) + V * spin_b<double>() +
+    // reliable update (e into x, FP64 Dhat x, r64 = bh - Dhat x, the refresh);
+    // the stencil halves cover the sites of op's blocks (Vo), the vector
+    // kernels whole fields
+    const double V = g.V, H = V / 2, Vo = V * on / g.nblk, Ho = Vo / 2;
+    const double setup = 3 * V * spin_b<double>() + half_b<double>(Vo, true) + V * spin_b<double>() +
                          V * (spin_b<double>() + spin_b<T>()) + 2 * V * spin_b<T>() + 3 * V * spin_b<T>() +
-                         H * spin_b<T>() + V * spin_b<double>() + half_b<double>(V, true) + 3 * V * spin_b<double>();
-    const double step = 2 * half_b<T>(V, false) + 2 * half_b<T>(V, true) + H * spin_b<T>() + 6 * H * spin_b<T>() +
+                         H * spin_b<T>() + V * spin_b<double>() + half_b<double>(Vo, true) + 3 * V * spin_b<double>();
+    const double step = 2 * half_b<T>(Vo, false) + 2 * half_b<T>(Vo, true) + H * spin_b<T>() + 6 * H * spin_b<T>() +
                         3 * H * spin_b<T>();
-    const double update = H * (spin_b<T>() + 2 * spin_b<double>()) + half_b<double>(V, false) +
-                          half_b<double>(V, true) + 3 * H * spin_b<double>() + H * (spin_b<double>() + 2 * spin_b<T>());
+    const double update = H * (spin_b<T>() + 2 * spin_b<double>()) + half_b<double>(Vo, false) +
+                          half_b<double>(Vo, true) + 3 * H * spin_b<double>() + H * (spin_b<double>() + 2 * spin_b<T>());
     // the clover blocks of every output site of every half (and A_oo^-1 b_o)
-    const double cl_setup = clov ? H * (2 * spin_b<double>() + clov_b<double>()) + H * clov_b<double>() : 0;
-    const double cl_step = clov ? 4 * H * clov_b<T>() : 0, cl_update = clov ? 2 * H * clov_b<double>() : 0;
+    const double cl_setup = clov ? H * (2 * spin_b<double>() + clov_b<double>()) + Ho * clov_b<double>() : 0;
+    const double cl_step = clov ? 4 * Ho * clov_b<T>() : 0, cl_update = clov ? 2 * Ho * clov_b<double>() : 0;
     double bytes = 0;
     for (int m = 0; m < M; ++m) {
         bytes += setup + cl_setup + hits[m] * (step + cl_step) + hupd[m] * (update + cl_update);
@@ -1035,10 +1060,112 @@ wdr_status solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr
 
 // ------------------------------------------------------------ block solves
 
+// the relative residual each round of the clover block solves asks of its
+// even-odd CG (over all blocks of the colour at once); two rounds reach the
+// usual block tolerances
+constexpr double BLOCK_EO_TOL = 1e-7;
+
+// Dirichlet block solves with the clover term (its 6 x 6 blocks per site do
+// not fit beside the block MR's fields in LDS): defect correction in FP64
+// around the even-odd CGNE of the block operator D_b = A - kappa H_in on the
+// blocks of the colour, all of them one block-diagonal system.  Each round
+// solves D_b d = r to a relative residual max(tol / 2, BLOCK_EO_TOL) with
+// sp.inner iterations and FP64 reliable updates, adds d to x and forms the
+// FP64 residual r = b - D_b x block by block; as in the MR rounds, the worst
+// block ratio |r_b| / |b_b| decides.  Systems that have converged get r = 0,
+// which their next CG ends at once.
+static wdr_status block_solve_clover(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int colour,
+                                     const wdr_solver_params &sp, double tol, const double2 *b, double2 *x,
+                                     std::vector<Stats> &st, hipStream_t s)
+{
+    if (sp.inner == WDR_F16) {
+        set_error("the block solver with the clover term needs an F64 or F32 inner precision");
+        return WDR_EINVAL;
+    }
+    const auto &g = c->g;
+    int slot0, ns;
+    colour_slots(c, colour, slot0, ns);
+    const long n = field_n(c), total = n * M;
+    const size_t fb = field_bytes(c, WDR_F64) * M;
+    Work rw(c, fb), tw(c, fb), dw(c, fb), nrm(c, 2 * sizeof(double) * g.nblk * M);
+    Work ctl(c, sizeof(double) * M + 2 * sizeof(int32_t) * M);
+    if (!rw.ok() || !tw.ok() || !dw.ok() || !nrm.ok() || !ctl.ok()) return WDR_ENOMEM;
+    double2 *r = rw.as<double2>(), *t = tw.as<double2>(), *d = dw.as<double2>();
+    double *worst = ctl.as<double>();
+    int32_t *alive = reinterpret_cast<int32_t *>(worst + M), *its = alive + M;
+    const Sys all = all_sys(c, M), sa{M, alive, n};
+    launch_zero<double>(x, total, s);
+    launch_convert<double, double>(all, b, r, s);
+    launch_keep_slots(g, all, r, slot0, ns, s);
+    double *bn = nrm.as<double>(), *rn = bn + (size_t)g.nblk * M;
+    launch_slot_norm2(g, all, r, bn, slot0, ns, s);
+    k_block_init<<<M, BC_NT, 0, s>>>(g.nblk, slot0, ns, bn, alive, its, worst);
+    Links<double> Ud = U.u64;
+    Ud.cmode = CLOV_DIAG;
+    EoOp op;
+    op.hops = HOPS_IN;
+    op.slot0 = slot0;
+    op.ns = ns;
+    const double tin = std::max(0.5 * tol, BLOCK_EO_TOL);
+    std::vector<int32_t> halive(M);
+    std::vector<long> inner(M, 0);
+    int rounds = 0;
+    for (int round = 0; round < 40; ++round) {
+        k_zero_dead<<<nb256(total), 256, 0, s>>>(alive, n, total, r);
+        std::vector<Stats> si;
+        const wdr_status e = sp.inner == WDR_F64 ? cgne_eo<double>(c, M, U, kappa, sp, tin, r, d, si, s, op)
+                                                 : cgne_eo<float>(c, M, U, kappa, sp, tin, r, d, si, s, op);
+        if (e != WDR_OK && e != WDR_ENOCONV) return e;
+        for (int m = 0; m < M; ++m) inner[m] += si[m].total;
+        // x += d, r = b - D_b x and its norm per block on the selected blocks
+        launch_add_to64<double>(sa, d, x, s);
+        launch_dslash<double>(g, sa, Ud, HOPS_IN, -1, 0, x, x, t, kappa, slot0, ns, s);
+        launch_block_resid_norm(g, sa, b, t, r, rn, slot0, ns, s);
+        k_block_check<<<M, BC_NT, 0, s>>>(g.nblk, slot0, ns, bn, rn, tol * tol, alive, its, worst);
+        WDR_HIP(hipMemcpyAsync(halive.data(), alive, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+        WDR_HIP(hipStreamSynchronize(s));
+        ++rounds;
+        bool any = false;
+        for (int m = 0; m < M; ++m) any = any || halive[m];
+        if (!any) break;
+    }
+    std::vector<double> hworst(M);
+    std::vector<int32_t> hits(M);
+    WDR_HIP(hipMemcpyAsync(hworst.data(), worst, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+    WDR_HIP(hipMemcpyAsync(hits.data(), its, sizeof(int32_t) * M, hipMemcpyDeviceToHost, s));
+    WDR_HIP(hipStreamSynchronize(s));
+    // compulsory bytes outside the CG (which counts its own): setup, then
+    // per round the clear, x += d, D_b x on the selected blocks (with their
+    // clover blocks) and r = b - D_b x with its norms
+    const double V = g.V, Vs = (double)ns * g.Vb, sb = spin_b<double>();
+    double lin = 0;
+    for (int mu = 0; mu < 4; ++mu) lin += (double)(g.B[mu] - 1) / g.B[mu];
+    const double setup = V * 4 * sb + Vs * sb;
+    const double round_b = V * sb + V * 3 * sb + Vs * (2 * sb + lin * 96.0 + clov_b<double>()) + Vs * 3 * sb;
+    bool ok = true;
+    st.assign(M, Stats());
+    double bytes = 0;
+    for (int m = 0; m < M; ++m) {
+        bytes += setup + rounds * round_b;
+        st[m].iters = hits[m];
+        st[m].total = inner[m];
+        st[m].rel = std::sqrt(hworst[m]);
+        st[m].converged = st[m].rel <= tol;
+        ok = ok && st[m].converged;
+    }
+    add_traffic(bytes);
+    WDR_HIP(hipGetLastError());
+    if (!ok) {
+        set_error("block solve stopped at relative residual " + std::to_string(summarize(st).rel));
+        return WDR_ENOCONV;
+    }
+    return WDR_OK;
+}
+
 wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int colour, const wdr_solver_params &sp,
                          double tol, const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
-    if (no_clover(U, "the block solver") != WDR_OK) return WDR_EINVAL;
+    if (U.u64.ctab) return block_solve_clover(c, M, U, kappa, colour, sp, tol, b, x, st, s);
     const auto &g = c->g;
     int slot0, ns;
     colour_slots(c, colour, slot0, ns);
@@ -1145,7 +1272,6 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
 wdr_status schur64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
                    const double2 *in, double2 *out, std::vector<Stats> &st, hipStream_t s)
 {
-    if (no_clover(U, "the Schur complement") != WDR_OK) return WDR_EINVAL;
     const auto &g = c->g;
     const long n = field_n(c);
     const size_t fb = field_bytes(c, WDR_F64) * M;

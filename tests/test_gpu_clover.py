@@ -1,9 +1,10 @@
 """GPU parity of the clover (Sheikholeslami-Wohlert) term against the FP64
 oracle: the term itself and its inverse, D / D_b / D_ee with the term on
 both stencil forms and on a general block shape, CGNE solves with FP64 and
-FP32 inner levels, FULL samples; the C-ABI error paths of the calls that do
+FP32 inner levels, Dirichlet block solves and the Schur complement, FULL,
+BLOCKS, SCHUR and DD samples; the C-ABI error paths of the calls that do
 not take the term (Sec. 3: active links for Wilson fermions with clover
-term; Sec. 7: the clover action)."""
+term, eqs. domdec and ddfactor; Sec. 7: the clover action)."""
 import numpy as np
 import pytest
 
@@ -155,6 +156,108 @@ def test_clover_full_samples(inner, kind, N, K):
     ctx.close()
 
 
+@pytest.mark.parametrize("L,B", GEOMS)
+@pytest.mark.parametrize("inner", [0, 1])
+def test_clover_block_solve(L, B, inner):
+    """Dirichlet block solves with the clover term (black, white, all
+    blocks; FP64 / FP32 CG iterations inside FP64 defect correction): every
+    block's residual, taken with the oracle's block operator, within 1e-13 of
+    its right-hand side, and the solution within 1e-11 of the oracle's."""
+    wdr, lat, ctx, U = _setup(L, B, 0.6, 514)
+    kappa = 0.14
+    T = oracle.clover_term(lat, U, CSW, kappa)
+    gU = ctx.gauge(dev(U), CSW, kappa)
+    b = synth.spinor(lat.L, 515)
+    bid, col, _ = lat.maps()
+    p = wdr.default_params(inner=inner)
+    for colour in (0, 1, 2):
+        x, info = ctx.block_solve(gU, kappa, colour, dev(b), p)
+        x = host(x)
+        sel = np.ones(lat.V, bool) if colour == 2 else col == colour
+        bb = b.copy()
+        bb[~sel] = 0
+        assert np.all(x[~sel] == 0)
+        r = bb - oracle.apply_Dblock(lat, U, kappa, x, colour, T)
+        worst = max(np.linalg.norm(r[bid == k]) / np.linalg.norm(bb[bid == k]) for k in np.unique(bid[sel]))
+        want, _, _, _ = oracle.solve(lat, U, kappa, bb, "block", colour, tol=1e-14, clov=T)
+        say("clover block solve", inner, colour, info.as_dict(), "worst block", worst, "vs oracle", rel(x, want))
+        assert info.converged and info.true_rel_resid <= 1e-13 and worst <= 1.05e-13
+        assert rel(x, want) < 1e-11
+    # the term matters: the plain block solution differs
+    plain, _, _, _ = oracle.solve(lat, U, kappa, b, "block", 2, tol=1e-14)
+    assert rel(x, plain) > 1e-2
+    del gU
+    ctx.close()
+
+
+@pytest.mark.parametrize("inner", [0, 1])
+def test_clover_schur(inner):
+    """The Schur complement 1 - D_bb^-1 D_bw D_ww^-1 D_wb with the clover
+    term in every block operator, within 1e-11 of the oracle's; white sites
+    exactly zero."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.6, 516)
+    kappa = 0.14
+    T = oracle.clover_term(lat, U, CSW, kappa)
+    gU = ctx.gauge(dev(U), CSW, kappa)
+    eta = synth.spinor(lat.L, 517)
+    got = host(ctx.schur(gU, kappa, dev(eta), wdr.default_params(inner=inner)))
+    want = oracle.schur_apply(lat, U, kappa, eta, clov=T)
+    e = rel(got, want)
+    say("clover schur", inner, e)
+    assert e < 1e-11
+    assert np.all(got[~oracle.colour_mask(lat, 0)] == 0)
+    assert rel(want, oracle.schur_apply(lat, U, kappa, eta)) > 1e-2
+    del gU
+    ctx.close()
+
+
+@pytest.mark.parametrize("op,inner,N,K", [("BLOCKS", 1, 2, 1), ("BLOCKS", 0, 1, 2), ("SCHUR", 1, 2, 1),
+                                          ("SCHUR", 0, 1, 1)])
+def test_clover_block_and_schur_samples(op, inner, N, K):
+    """BLOCKS (one sample per block) and SCHUR samples of the clover
+    operator (CGNE for D, FP32 / FP64 inner level) within 1e-8 of the
+    oracle's, over a path whose interior points carry clover terms the
+    library builds itself."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 518)
+    kappa = 0.135
+    Up = synth.redraw(U, oracle.active_links(lat), 0.5, 519)
+    gU, gUp = ctx.gauge(dev(U), CSW, kappa), ctx.gauge(dev(Up), CSW, kappa)
+    p = wdr.default_params(solver=1, inner=inner, max_iter=20000)
+    wop, oop = getattr(wdr, "OP_" + op), getattr(oracle, "OP_" + op)
+    s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, wop, N, K, wdr.NOISE_GAUSS, 79, p)
+    want, lr_want = oracle.logdet_ratio(lat, U, Up, kappa, oop, N, K, oracle.NOISE_GAUSS, 79, csw=CSW)
+    err = np.abs(s - want).max()
+    say("clover", op, "samples inner", inner, "max |ds|", err, "log R", lr, float(np.sum(lr_want)), info.as_dict())
+    assert s.shape == want.shape
+    assert info.converged and err < 1e-8
+    assert abs(lr - float(np.sum(lr_want))) < 1e-8 * max(1, s.size)
+    plain, _ = oracle.logdet_ratio(lat, U, Up, kappa, oop, 1, 1, oracle.NOISE_GAUSS, 79)
+    assert np.abs(plain[0, 0] - want[0, 0]).max() > 1e-3
+    del gU, gUp
+    ctx.close()
+
+
+def test_clover_dd_samples():
+    """The DD estimate with the clover term (every block ratio and the Schur
+    ratio of one proposal in one call, the two parts on concurrent
+    contexts) against the oracle's BLOCKS and SCHUR samples."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 520)
+    kappa = 0.135
+    Up = synth.redraw(U, oracle.active_links(lat), 0.5, 521)
+    gU, gUp = ctx.gauge(dev(U), CSW, kappa), ctx.gauge(dev(Up), CSW, kappa)
+    N = 1
+    p = wdr.default_params(solver=1, inner=1, max_iter=20000)
+    s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, wdr.OP_DD, N, 1, wdr.NOISE_GAUSS, 45, p)
+    wb, lb = oracle.logdet_ratio(lat, U, Up, kappa, oracle.OP_BLOCKS, N, 1, oracle.NOISE_GAUSS, 45, csw=CSW)
+    ws, ls = oracle.logdet_ratio(lat, U, Up, kappa, oracle.OP_SCHUR, N, 1, oracle.NOISE_GAUSS, 45, csw=CSW)
+    eb, es = np.abs(s[..., :-1] - wb).max(), np.abs(s[..., -1] - ws).max()
+    say("clover dd max |ds| blocks", eb, "schur", es, info.as_dict())
+    assert info.converged and eb < 1e-8 and es < 1e-8
+    assert abs(lr - (float(np.sum(lb)) + float(ls))) < 1e-8 * s.size
+    del gU, gUp
+    ctx.close()
+
+
 def test_clover_16x16x16x16_operator_and_solve():
     """16^4 (256 blocks of 4^4): D with the clover term against the oracle on
     both stencil forms, and a CGNE solve whose true residual the oracle's
@@ -194,12 +297,14 @@ def test_clover_error_paths():
 
     refused(lambda: ctx.apply_D(gU, 0.13, psi))                       # another kappa
     refused(lambda: ctx.apply_D(gU, kappa, psi, wdr.F16))             # FP16 stencil
-    refused(lambda: ctx.block_solve(gU, kappa, 0, psi, wdr.default_params()))
-    refused(lambda: ctx.schur(gU, kappa, psi, wdr.default_params()))
+    refused(lambda: ctx.block_solve(gU, kappa, 0, psi, wdr.default_params(inner=2)))   # FP16 block MR
+    refused(lambda: ctx.schur(gU, kappa, psi, wdr.default_params(inner=2)))
     refused(lambda: ctx.sap(gU, kappa, psi, wdr.default_params()))
     refused(lambda: ctx.solve(gU, kappa, psi, wdr.default_params(solver=0)))
     refused(lambda: ctx.solve(gU, kappa, psi, wdr.default_params(solver=1, inner=2)))
-    refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_SCHUR, 1, 1, 1, 1, wdr.default_params(solver=1)))
+    refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_SCHUR, 1, 1, 1, 1, wdr.default_params(solver=0)))
+    refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_BLOCKS, 1, 1, 1, 1, wdr.default_params(inner=2)))
+    refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_DD, 1, 1, 1, 1, wdr.default_params(solver=0)))
     refused(lambda: ctx.logdet_ratio(gU, gP, kappa, wdr.OP_FULL, 1, 1, 1, 1, wdr.default_params(solver=1)))
     refused(lambda: ctx.block_logdet(gU, kappa))
     refused(lambda: ctx.clover_field(gP))
