@@ -89,33 +89,37 @@ def proposal_mask(ctx, rule):
 
 
 def clover_workload(wdr, torch, L=(16, 16, 16, 16), N=8, kappa=0.135, scale=0.5, seed=1112124310):
-    """FULL estimates with and without the clover term (c_sw 1.7) on the same
-    16^4 proposal: N factors x 1 Gaussian noise, all batched, CGNE with FP32
-    iterations and FP64 reliable updates to 1e-10."""
+    """FULL and SCHUR estimates with and without the clover term (c_sw 1.7)
+    on the same 16^4 proposal: N factors x 1 Gaussian noise, all batched,
+    CGNE with FP32 iterations and FP64 reliable updates to 1e-10; block
+    solves to 1e-13 (FP32 block MR rounds without the term, FP32 even-odd
+    CGNE rounds on the blocks with it)."""
     from paper_1112_1243_amd import synth
     ctx = wdr.Context(L, (4, 4, 4, 4))
     U = synth.gauge_field(L, scale, seed)
     Up = synth.redraw(U, proposal_mask(ctx, "active"), scale, seed)
     p = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F32, max_iter=20000)
-    out = {"workload": "%s lattice, 4^4 blocks, kappa %.3f, links exp(i %.1f H), active links redrawn, FULL ratio, "
-                       "N=%d factors x 1 Gaussian noise (batched), CGNE FP32 iterations + FP64 reliable updates to "
-                       "1e-10" % ("x".join(map(str, L)), kappa, scale, N), "unit": "estimates/s"}
-    for csw in (CSW, 0.0):
-        gU = ctx.gauge(torch.from_numpy(U).cuda(), csw, kappa)
-        gUp = ctx.gauge(torch.from_numpy(Up).cuda(), csw, kappa)
-        ctx.logdet_ratio(gU, gUp, kappa, wdr.OP_FULL, 1, 1, wdr.NOISE_GAUSS, 1, p)  # warm-up
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, wdr.OP_FULL, N, 1, wdr.NOISE_GAUSS, seed, p)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        key = "clover" if csw else "wilson"
-        out[key] = {"value": round(1.0 / dt, 3), "cg_iterations_total": int(info.total_iters),
-                    "converged": bool(info.converged), "log_ratio": round(float(lr), 4)}
-        if csw:
-            out[key]["csw"] = csw
-        log("%s FULL 16^4: %.3f s, CG its %d, log R %.4f" % (key, dt, info.total_iters, lr))
-        del gU, gUp
+    out = {"workload": "%s lattice, 4^4 blocks, kappa %.3f, links exp(i %.1f H), active links redrawn, FULL and "
+                       "SCHUR ratios, N=%d factors x 1 Gaussian noise (batched), CGNE FP32 iterations + FP64 reliable "
+                       "updates to 1e-10, block solves to 1e-13" % ("x".join(map(str, L)), kappa, scale, N),
+           "unit": "estimates/s"}
+    for op, suffix in ((wdr.OP_FULL, ""), (wdr.OP_SCHUR, "_schur")):
+        for csw in (CSW, 0.0):
+            gU = ctx.gauge(torch.from_numpy(U).cuda(), csw, kappa)
+            gUp = ctx.gauge(torch.from_numpy(Up).cuda(), csw, kappa)
+            ctx.logdet_ratio(gU, gUp, kappa, op, 1, 1, wdr.NOISE_GAUSS, 1, p)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, op, N, 1, wdr.NOISE_GAUSS, seed, p)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            key = ("clover" if csw else "wilson") + suffix
+            out[key] = {"value": round(1.0 / dt, 3), "iterations_total": int(info.total_iters),
+                        "converged": bool(info.converged), "log_ratio": round(float(lr), 4)}
+            if csw:
+                out[key]["csw"] = csw
+            log("%s 16^4: %.3f s, iterations %d, log R %.4f" % (key, dt, info.total_iters, lr))
+            del gU, gUp
     ctx.close()
     return out
 
@@ -1113,7 +1117,7 @@ def main():
         "block_determinants": bdet,
         "recursive_dd": rdd,
         "filter": filt,
-        "clover_full_16": clov,
+        "clover_16": clov,
         "exact_acceptance": acc,
         "cpu_baseline": cpu,
     }
