@@ -124,6 +124,44 @@ def clover_workload(wdr, torch, L=(16, 16, 16, 16), N=8, kappa=0.135, scale=0.5,
     return out
 
 
+def cg_forms(wdr, torch, N=16, kappa=0.135, scale=0.5, seed=1112124320):
+    """FULL estimates (N factors x 1 Gaussian noise, all batched; CGNE with
+    FP32 steps and FP64 reliable updates to 1e-10) at 8^4, 16^4 and 32^4 with
+    the CG steps as separate launches (the default form) and as one
+    cooperative launch per period of update_every steps (grid-wide barriers
+    between the phases); the faster of three timed runs of each."""
+    from paper_1112_1243_amd import synth
+    out = {"workload": "FULL ratio, 4^4 blocks, kappa %.3f, links exp(i %.1f H), active links redrawn, N=%d factors "
+                       "x 1 Gaussian noise (batched), CGNE FP32 steps + FP64 reliable updates to 1e-10"
+                       % (kappa, scale, N), "unit": "ms per estimate"}
+    p = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F32, max_iter=20000)
+    for L in ((8, 8, 8, 8), (16, 16, 16, 16), (32, 32, 32, 32)):
+        ctx = wdr.Context(L, (4, 4, 4, 4))
+        U = synth.gauge_field(L, scale, seed)
+        Up = synth.redraw(U, proposal_mask(ctx, "active"), scale, seed + 1)
+        gU, gUp = ctx.gauge(torch.from_numpy(U).cuda()), ctx.gauge(torch.from_numpy(Up).cuda())
+        del U, Up
+        row = {}
+        for name, form in (("launches", wdr.CG_LAUNCHES), ("persistent", wdr.CG_PERSISTENT)):
+            ctx.set_cg_form(form)
+            ctx.logdet_ratio(gU, gUp, kappa, wdr.OP_FULL, N, 1, wdr.NOISE_GAUSS, 5, p)  # warm-up
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, wdr.OP_FULL, N, 1, wdr.NOISE_GAUSS, seed, p)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            row[name] = {"ms": round(min(ts) * 1e3, 3), "cg_steps_max": int(info.iters),
+                         "cg_steps_total": int(info.total_iters), "log_ratio": round(float(lr), 6)}
+        row["persistent_over_launches"] = round(row["persistent"]["ms"] / row["launches"]["ms"], 3)
+        out["x".join(map(str, L))] = row
+        log("cg forms %s: %s" % ("x".join(map(str, L)), row))
+        del gU, gUp
+        ctx.close()
+    return out
+
+
 def dd_workload(wdr, torch, name):
     """One estimate of a larger lattice workload of synth.WORKLOADS: the mixed
     form (the workload's settings: FP16 block solves, CGNE with FP16
@@ -508,7 +546,7 @@ def copy_ceiling(torch, reps=10):
             "achieved": round(2 * 4 * n / (ms * 1e-3) / 1e9, 1), "unit": "GB/s"}
 
 
-def rocprof_summary(path, kernel_regex="k_dslash|k_eo16|k_block_mr"):
+def rocprof_summary(path, kernel_regex="k_dslash|k_eo16|k_block_mr|k_cg_steps"):
     """Markdown summary of rocprofv3 CSV output under `path`: per-kernel
     totals (rocprofv3's kernel_stats); when a marker trace holds the timed
     range of the headline, the kernels inside it by name and grid (time
@@ -1003,6 +1041,8 @@ def main():
     ap.add_argument("--no-recursive", action="store_true", help="skip the recursive-DD workload")
     ap.add_argument("--no-filter", action="store_true", help="skip the filter run")
     ap.add_argument("--no-clover", action="store_true", help="skip the clover FULL estimates")
+    ap.add_argument("--no-cg-forms", action="store_true", help="skip the CG launch-form comparison")
+    ap.add_argument("--cg-forms-only", action="store_true", help="run only the CG launch-form comparison")
     ap.add_argument("--acceptance", action="store_true", help="also run the exact-acceptance variance study")
     ap.add_argument("--stencil", choices=("auto", "dir", "blk"), default="auto",
                     help="stencil kernel for the 32^4 full-stencil launches (default: the library's choice)")
@@ -1017,10 +1057,14 @@ def main():
         sys.exit(2)
     if args.headline_only:
         args.no_cpu = args.no_fp64 = args.no_dslash = args.no_batch = args.no_large = args.no_dd8 = True
-        args.no_blockdet = args.no_recursive = args.no_filter = args.no_clover = True
+        args.no_blockdet = args.no_recursive = args.no_filter = args.no_clover = args.no_cg_forms = True
 
     import torch
     from paper_1112_1243_amd import synth, wdr
+
+    if args.cg_forms_only:
+        print(json.dumps(cg_forms(wdr, torch)), flush=True)
+        return
 
     if args.roofline_only:
         roof = eo16_roofline(wdr, torch, synth.WORKLOADS[HEADLINE]["n_noise"])
@@ -1076,6 +1120,7 @@ def main():
     if rdd:
         log("recursive dd:", rdd)
     clov = None if args.no_clover else clover_workload(wdr, torch)
+    forms = None if args.no_cg_forms else cg_forms(wdr, torch)
     filt = None if args.no_filter else filter_run(wdr, torch)
     if filt:
         log("filter:", filt)
@@ -1118,6 +1163,7 @@ def main():
         "recursive_dd": rdd,
         "filter": filt,
         "clover_16": clov,
+        "cg_forms": forms,
         "exact_acceptance": acc,
         "cpu_baseline": cpu,
     }

@@ -188,6 +188,24 @@ wdr_status wdr_ctx_set_stencil(wdr_ctx *ctx, int32_t choice);
 typedef enum { WDR_MR_AUTO = 0, WDR_MR_ONE_PER_CU = 1, WDR_MR_TWO_PER_CU = 2 } wdr_mr_form;
 wdr_status wdr_ctx_set_mr_form(wdr_ctx *ctx, int32_t choice);
 
+/* Launch form of the CG steps of the even-odd CGNE with an F64 or F32 inner
+ * level (the inversions of Sec. 4, "one inversion for each factor" of eq.
+ * param); the arithmetic is the same either way, the inner products are
+ * added in another order.  WDR_CG_LAUNCHES (the default): one kernel launch
+ * per stencil half, reduction and update, about ten per step, captured as
+ * HIP graphs with sp->graph.  WDR_CG_PERSISTENT: the sp->update_every steps
+ * between two reliable updates run as one cooperative launch whose phases
+ * are separated by grid-wide barriers (no graph capture); it applies to
+ * 4^4 blocks with SU(3) links and no clover term, other solves keep the
+ * launches.  The cooperative launch holds every resident workgroup slot of
+ * the GPU it can use, so two of them must not run at once: the batched
+ * estimate runs its contexts one after another when one of them has this
+ * form, and the caller must not drive two such contexts of one GPU from two
+ * threads.  EDEVICE from a solve whose cooperative launch the device
+ * refuses.  Applies to later calls on ctx; EINVAL for another value. */
+typedef enum { WDR_CG_LAUNCHES = 0, WDR_CG_PERSISTENT = 1 } wdr_cg_form;
+wdr_status wdr_ctx_set_cg_form(wdr_ctx *ctx, int32_t choice);
+
 /* Geometry maps (Sec. 3), written to caller device buffers of V int32:
  * block id (lexicographic block coordinates), block colour, site parity and
  * position of the site in the black-first block ordering. Any may be NULL. */

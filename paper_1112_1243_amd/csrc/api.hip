@@ -735,8 +735,13 @@ wdr_status wdr_logdet_ratio_batch(int32_t n, const wdr_proposal *props, const wd
         (void)hipStreamSynchronize(s);
         if (ge[gi] != WDR_OK) gmsg[gi] = wdr_last_error();
     };
-    if (G == 1) {
-        run(0, S(stream));
+    // contexts with the persistent CG form run one after another: two
+    // cooperative launches sized to the whole GPU must never wait on each
+    // other's workgroups
+    bool coop = false;
+    for (wdr_ctx *c : ctxs) coop = coop || c->g.cg_form == WDR_CG_PERSISTENT;
+    if (G == 1 || coop) {
+        for (size_t gi = 0; gi < G; ++gi) run(gi, S(stream));
     } else {
         // fork: each context's stream starts after the work queued on `stream`
         hipEvent_t fork;

@@ -15,6 +15,10 @@
 // shapes: k_dslash, one lane per site and 256 consecutive sites of one block
 // per workgroup.  In both, a wavefront reads each spinor / link component of
 // 64 consecutive sites as one contiguous 512 B (FP32) or 1 KiB (FP64) run.
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
+
 #include "clover.h"
 #include "stencil.h"
 
@@ -377,25 +381,20 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_dslash_blk(Geo g, const int32_t
 // reduced solvers): out = diag - kappa H_{par, 1-par} in on the sites of
 // parity par, with gamma_5 on both sides for DAG.  One workgroup per block,
 // one lane per output site; the block's input sites of the other parity are
-// read once into LDS.
-template <typename T, int B, int DAG, int CL>
-__global__ __launch_bounds__(Cube<B>::Vh) void k_dslash_blk_eo(Geo g, const int32_t *__restrict__ active,
-                                                              const int32_t *__restrict__ list, UTab<T> Utab,
-                                                              const double *__restrict__ kap, int kneg,
-                                                              const T *const *__restrict__ ctab, long n,
-                                                              const int32_t *__restrict__ sched, int par,
-                                                              const T2<T> *__restrict__ in,
-                                                              const T2<T> *__restrict__ diag, T2<T> *__restrict__ out,
-                                                              T kappa)
+// read once into LDS (sh).  blk_eo_block is one workgroup's block (system m,
+// slot `slot`, lane t = threadIdx.x); with NRM it returns the lane's
+// |out|^2 in FP64 (0 otherwise).  It ends with the LDS still in use: a
+// caller that runs it again on the same sh synchronises the workgroup first.
+template <typename T, int B, int DAG, int CL, int NRM>
+__device__ __forceinline__ double blk_eo_block(const Geo &g, int m, int slot, int t, UTab<T> Utab,
+                                               const double *__restrict__ kap, int kneg,
+                                               const T *const *__restrict__ ctab, long n, int par,
+                                               const T2<T> *__restrict__ in, const T2<T> *__restrict__ diag,
+                                               T2<T> *__restrict__ out, T kappa, T2<T> (*sh)[Cube<B>::Vh])
 {
     typedef Cube<B> CB;
     constexpr int Vb = CB::Vb, Vh = CB::Vh;
-    __shared__ T2<T> sh[12][Vh];  // the block's input on the other parity, component-major
-    const int m = sys_at(list, blockIdx.y);
-    if (active && !active[m]) return;
     if (kap) kappa = kneg ? -(T)kap[m] : (T)kap[m];
-    const int slot = sched[blockIdx.x];
-    const int t = threadIdx.x;
     const int off = (1 - par) * Vh;  // first local index of the input parity
     const auto *Ug = as_global(Utab[m]);
     const auto *ing = as_global(in + m * n);
@@ -432,6 +431,7 @@ __global__ __launch_bounds__(Cube<B>::Vh) void k_dslash_blk_eo(Geo g, const int3
         }
     }
     const long obase = m * n + sbase + l;
+    double nrm = 0;
     if (CL) {
         cx<T> v[12], dg[12];
 #pragma unroll
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(Cube<B>::Vh) void k_dslash_blk_eo(Geo g, const int3
         clov_site<T, CL>(ctab[m], (long)g.V, slot, Vb, l, dg, v);
 #pragma unroll
         for (int c = 0; c < 12; ++c) st_nt<T>(out, obase + (long)c * Vb, v[c]);
-        return;
+        return nrm;
     }
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
@@ -454,7 +454,26 @@ __global__ __launch_bounds__(Cube<B>::Vh) void k_dslash_blk_eo(Geo g, const int3
             if (DAG && sp >= 2) v = neg(v);
             if (diag) v = v + ld<T>(diag, i);
             st_nt<T>(out, i, v);
+            if (NRM) nrm += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
         }
+    return nrm;
+}
+
+template <typename T, int B, int DAG, int CL>
+__global__ __launch_bounds__(Cube<B>::Vh) void k_dslash_blk_eo(Geo g, const int32_t *__restrict__ active,
+                                                              const int32_t *__restrict__ list, UTab<T> Utab,
+                                                              const double *__restrict__ kap, int kneg,
+                                                              const T *const *__restrict__ ctab, long n,
+                                                              const int32_t *__restrict__ sched, int par,
+                                                              const T2<T> *__restrict__ in,
+                                                              const T2<T> *__restrict__ diag, T2<T> *__restrict__ out,
+                                                              T kappa)
+{
+    __shared__ T2<T> sh[12][Cube<B>::Vh];  // the block's input on the other parity, component-major
+    const int m = sys_at(list, blockIdx.y);
+    if (active && !active[m]) return;
+    blk_eo_block<T, B, DAG, CL, 0>(g, m, sched[blockIdx.x], threadIdx.x, Utab, kap, kneg, ctab, n, par, in, diag, out,
+                                   kappa, sh);
 }
 
 // below this many workgroups (blocks x systems) the 4-workgroups-per-block
@@ -494,6 +513,169 @@ void launch_blk_eo(const Geo &g, const Sys &sy, Links<T> U, int par, int dag, co
     else
         k_dslash_blk_eo<T, B, 0, CL><<<gb, Cube<B>::Vh, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, U.ctab,
                                                                sy.n, sc, par, in, diag, out, kappa);
+}
+
+// ---------------------------------------------------------------- persistent CG steps
+// The steps of the even-odd CGNE (Dhat Dhat^+ y = bh, vectors in T on the
+// even sites) as one cooperative launch: each step's four stencil halves, its
+// x / r update and its new search direction are phases of one grid,
+// separated by grid-wide barriers instead of kernel boundaries.  A phase's
+// work items are (block, system) pairs dealt round-robin to the workgroups,
+// one lane per even site; the stencil halves are blk_eo_block.  Inner
+// products go through one partial sum per item (|w|^2 in the second half,
+// |r|^2 in the update), which every workgroup adds over the blocks of a
+// system in the same order, so all workgroups hold the same scalars.  The
+// control of a step (iteration count, reliable-update flag, largest residual)
+// is that of k_cgm_beta, done by the workgroup holding the system's first
+// block; the CG scalars are written back after the last step.
+
+template <typename T> struct CgSteps {
+    const int32_t *active, *list;
+    int nsys, nslots, steps, max_iter;
+    UTab<T> U;
+    const double *kap;
+    long n;
+    const int32_t *sched;
+    T kappa;
+    T2<T> *p, *t, *w, *q, *r, *e;
+    double2 *sc;    // 8 per system: [0] rr, [1] |w|^2, [3] new rr, [4] beta
+    double *part;   // 3 x items: |w|^2, then |r|^2 of even and of odd steps
+    double delta2;  // reliable-update threshold (squared)
+    double *rmax;
+    int32_t *upd, *its;
+};
+
+// sum over the 128 lanes of a workgroup (two wavefronts); every lane gets it
+__device__ __forceinline__ double wg_sum(double v, double *sh)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const double r = sh[0] + sh[1];
+    __syncthreads();
+    return r;
+}
+
+// the partial sums of system j's items, added in the same order everywhere
+__device__ __forceinline__ double sys_sum(const double *part, int j, int nslots, double *sh)
+{
+    double v = 0;
+    for (int i = threadIdx.x; i < nslots; i += Cube<4>::Vh) v += part[(long)j * nslots + i];
+    return wg_sum(v, sh);
+}
+
+template <typename T>
+__global__ __launch_bounds__(Cube<4>::Vh) void k_cg_steps(Geo g, CgSteps<T> a)
+{
+    constexpr int B = 4, Vb = Cube<B>::Vb, Vh = Cube<B>::Vh;
+    __shared__ T2<T> sh[12][Vh];
+    __shared__ double rs[2];
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    const int t = threadIdx.x, items = a.nslots * a.nsys, G = gridDim.x;
+    double *pww = a.part, *prr[2] = {a.part + items, a.part + 2 * (long)items};
+    // the residual the step starts from: the stored one, or the last step's
+    auto rr_in = [&](int k, int j, int m) -> double {
+        return k == 0 ? a.sc[8L * m].x : sys_sum(prr[(k + 1) & 1], j, a.nslots, rs);
+    };
+    for (int k = 0; k < a.steps; ++k) {
+        // w = Dhat^+ p: odd half from p, then the even half with p as diagonal
+        for (int it = blockIdx.x; it < items; it += G) {
+            const int m = sys_at(a.list, it / a.nslots);
+            if (a.active && !a.active[m]) continue;
+            blk_eo_block<T, B, 1, CLOV_NONE, 0>(g, m, a.sched[it % a.nslots], t, a.U, a.kap, 0, nullptr, a.n, 1, a.p,
+                                                nullptr, a.t, a.kappa, sh);
+            __syncthreads();
+        }
+        grid.sync();
+        for (int it = blockIdx.x; it < items; it += G) {
+            const int m = sys_at(a.list, it / a.nslots);
+            if (a.active && !a.active[m]) continue;
+            const double v = blk_eo_block<T, B, 1, CLOV_NONE, 1>(g, m, a.sched[it % a.nslots], t, a.U, a.kap, 1,
+                                                                 nullptr, a.n, 0, a.t, a.p, a.w, -a.kappa, sh);
+            const double s = wg_sum(v, rs);
+            if (t == 0) pww[it] = s;
+        }
+        grid.sync();
+        // q = Dhat w
+        for (int it = blockIdx.x; it < items; it += G) {
+            const int m = sys_at(a.list, it / a.nslots);
+            if (a.active && !a.active[m]) continue;
+            blk_eo_block<T, B, 0, CLOV_NONE, 0>(g, m, a.sched[it % a.nslots], t, a.U, a.kap, 0, nullptr, a.n, 1, a.w,
+                                                nullptr, a.t, a.kappa, sh);
+            __syncthreads();
+        }
+        grid.sync();
+        for (int it = blockIdx.x; it < items; it += G) {
+            const int m = sys_at(a.list, it / a.nslots);
+            if (a.active && !a.active[m]) continue;
+            blk_eo_block<T, B, 0, CLOV_NONE, 0>(g, m, a.sched[it % a.nslots], t, a.U, a.kap, 1, nullptr, a.n, 0, a.t,
+                                                a.w, a.q, -a.kappa, sh);
+            __syncthreads();
+        }
+        grid.sync();
+        // alpha = rr / |w|^2; e += alpha w, r -= alpha q on the block's even
+        // sites, and the partial |r|^2
+        for (int it = blockIdx.x; it < items; it += G) {
+            const int j = it / a.nslots, m = sys_at(a.list, j);
+            if (a.active && !a.active[m]) continue;
+            const double ww = sys_sum(pww, j, a.nslots, rs), rr = rr_in(k, j, m);
+            const T al = (T)(ww > 0 ? rr / ww : 0.0);
+            const long base = m * a.n + (long)a.sched[it % a.nslots] * 12 * Vb + t;
+            double nr = 0;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const long i = base + (long)c * Vb;
+                T2<T> ei = a.e[i], ri = a.r[i];
+                const T2<T> wi = a.w[i], qi = a.q[i];
+                ei.x = ei.x + al * wi.x;
+                ei.y = ei.y + al * wi.y;
+                ri.x = ri.x - al * qi.x;
+                ri.y = ri.y - al * qi.y;
+                a.e[i] = ei;
+                a.r[i] = ri;
+                nr += (double)ri.x * (double)ri.x + (double)ri.y * (double)ri.y;
+            }
+            const double s = wg_sum(nr, rs);
+            if (t == 0) prr[k & 1][it] = s;
+        }
+        grid.sync();
+        // beta = rr_new / rr, p = r + beta p; the step's control
+        for (int it = blockIdx.x; it < items; it += G) {
+            const int j = it / a.nslots, m = sys_at(a.list, j);
+            if (a.active && !a.active[m]) continue;
+            const double rr0 = rr_in(k, j, m), rr = sys_sum(prr[k & 1], j, a.nslots, rs);
+            const T b = (T)(rr0 > 0 ? rr / rr0 : 0.0);
+            const long base = m * a.n + (long)a.sched[it % a.nslots] * 12 * Vb + t;
+#pragma unroll
+            for (int c = 0; c < 12; ++c) {
+                const long i = base + (long)c * Vb;
+                const T2<T> ri = a.r[i], pi = a.p[i];
+                a.p[i].x = ri.x + b * pi.x;
+                a.p[i].y = ri.y + b * pi.y;
+            }
+            if (it % a.nslots == 0 && t == 0) {
+                const int kk = ++a.its[m];
+                a.rmax[m] = fmax(a.rmax[m], rr);
+                if (!(rr > a.delta2 * a.rmax[m]) || kk >= a.max_iter) a.upd[m] = 1;
+            }
+        }
+        grid.sync();
+    }
+    // the CG scalars of the last step, as the step-by-step form leaves them
+    for (int it = blockIdx.x; it < items; it += G) {
+        if (it % a.nslots) continue;
+        const int j = it / a.nslots, m = sys_at(a.list, j);
+        if (a.active && !a.active[m]) continue;
+        const double rr0 = rr_in(a.steps - 1, j, m), rr = sys_sum(prr[(a.steps - 1) & 1], j, a.nslots, rs);
+        const double ww = sys_sum(pww, j, a.nslots, rs);
+        if (t == 0) {
+            a.sc[8L * m + 1] = make_double2(ww, 0.0);
+            a.sc[8L * m + 3] = make_double2(rr, 0.0);
+            a.sc[8L * m + 4] = make_double2(rr0 > 0 ? rr / rr0 : 0.0, 0.0);
+            a.sc[8L * m] = make_double2(rr, 0.0);
+        }
+    }
 }
 
 // clover mode of a launch: the links' mode when they carry a clover term and
@@ -786,7 +968,40 @@ template <typename T> void launch_g5(const Geo &g, const Sys &sy, const T2<T> *i
     k_g5<T><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(total, g.Vb, in, out);
 }
 
+bool cg_steps_fit(const Geo &g, bool su3, bool clover)
+{
+    return g.B[0] == 4 && g.B[1] == 4 && g.B[2] == 4 && g.B[3] == 4 && su3 && !clover &&
+           sched_index(g, 0, g.nblk) >= 0;
+}
+
+template <typename T>
+hipError_t launch_cg_steps(const Geo &g, const Sys &sy, Links<T> U, T kappa, int steps, T2<T> *p, T2<T> *t,
+                           T2<T> *w, T2<T> *q, T2<T> *r, T2<T> *e, double2 *sc, double *part, double delta2,
+                           int max_iter, double *rmax, int32_t *upd, int32_t *its, hipStream_t s)
+{
+    if (!cg_steps_fit(g, U.su3, U.ctab != nullptr)) return hipErrorInvalidValue;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e0 = hipGetDevice(&dev);
+    if (e0 == hipSuccess) e0 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e0 == hipSuccess)
+        e0 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_cg_steps<T>),
+                                                          Cube<4>::Vh, 0);
+    if (e0 != hipSuccess) return e0;
+    const long items = (long)g.nblk * sy.launch_m();
+    // every workgroup must be resident at once (the launch is refused otherwise)
+    const int G = (int)std::max<long>(1, std::min<long>(items, (long)per_cu * cus));
+    Geo gc = g;
+    CgSteps<T> a{sy.active, sy.list, sy.launch_m(), g.nblk, steps, max_iter, U.tab, U.kap, sy.n,
+                 g.sched[sched_index(g, 0, g.nblk)], kappa, p, t, w, q, r, e, sc, part, delta2, rmax, upd, its};
+    void *args[] = {&gc, &a};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_cg_steps<T>), dim3(G), dim3(Cube<4>::Vh),
+                                      args, 0, s);
+}
+
 #define INST(T)                                                                                                  \
+    template hipError_t launch_cg_steps<T>(const Geo &, const Sys &, Links<T>, T, int, T2<T> *, T2<T> *,          \
+                                           T2<T> *, T2<T> *, T2<T> *, T2<T> *, double2 *, double *, double, int,  \
+                                           double *, int32_t *, int32_t *, hipStream_t);                          \
     template void launch_dslash<T>(const Geo &, const Sys &, Links<T>, int, int, int, const T2<T> *,              \
                                    const T2<T> *, T2<T> *, T, int, int, hipStream_t);                            \
     template void launch_pack_spinor<T>(const Geo &, const double2 *, C2<T>::type *, hipStream_t);               \

@@ -117,6 +117,18 @@ template <typename T>
 void launch_dslash(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int dag, const T2<T> *in,
                    const T2<T> *diag, T2<T> *out, T kappa, int slot0, int nslots, hipStream_t s);
 
+// Persistent form of `steps` steps of the even-odd CGNE (the step loop of
+// the CG in solvers.hip: w = Dhat^+ p, q = Dhat w, x / r update, new p, the
+// per-step control of k_cgm_beta) as one cooperative launch; part holds
+// 3 * nblk * launch_m doubles.  Fits 4^4 blocks with SU(3) links and no
+// clover term (cg_steps_fit); returns the launch status (nothing ran unless
+// hipSuccess).
+bool cg_steps_fit(const Geo &g, bool su3, bool clover);
+template <typename T>
+hipError_t launch_cg_steps(const Geo &g, const Sys &sy, Links<T> U, T kappa, int steps, T2<T> *p, T2<T> *t,
+                           T2<T> *w, T2<T> *q, T2<T> *r, T2<T> *e, double2 *sc, double *part, double delta2,
+                           int max_iter, double *rmax, int32_t *upd, int32_t *its, hipStream_t s);
+
 // ---------------------------------------------------------------- clover term
 // A = 1 + T and A^-1 of every site (clover.h layout) in FP64 into c64 (144 V
 // doubles) and rounded to FP32 into c32 (144 V floats), from the internal

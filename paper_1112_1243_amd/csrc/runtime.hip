@@ -252,6 +252,7 @@ wdr_status wdr_ctx_create(const wdr_geom *geom, int device, wdr_ctx **out)
     g.colourable = colourable;
     g.stencil = WDR_STENCIL_AUTO;
     g.mr_form = WDR_MR_AUTO;
+    g.cg_form = WDR_CG_LAUNCHES;
 
     // in-block order: even sites then odd sites, lexicographic within each
     std::vector<uint32_t> loc_coord(Vb);
@@ -425,6 +426,21 @@ wdr_status wdr_ctx_set_mr_form(wdr_ctx *c, int32_t choice)
     }
     c->g.mr_form = choice;
     if (c->twin) c->twin->g.mr_form = choice;
+    return WDR_OK;
+}
+
+wdr_status wdr_ctx_set_cg_form(wdr_ctx *c, int32_t choice)
+{
+    if (!c) {
+        set_error("null context");
+        return WDR_EINVAL;
+    }
+    if (choice != WDR_CG_LAUNCHES && choice != WDR_CG_PERSISTENT) {
+        set_error("CG form must be WDR_CG_LAUNCHES or WDR_CG_PERSISTENT");
+        return WDR_EINVAL;
+    }
+    c->g.cg_form = choice;
+    if (c->twin) c->twin->g.cg_form = choice;
     return WDR_OK;
 }
 

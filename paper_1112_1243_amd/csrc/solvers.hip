@@ -669,6 +669,12 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     std::vector<int32_t> live;
     int launch_m = M;
     const unsigned nbm = nb64(M);
+    // the persistent form of the steps (wdr_cg_form) on the whole operator
+    const bool persist = g.cg_form == WDR_CG_PERSISTENT && op.hops == HOPS_ALL && op.count(g) == g.nblk &&
+                         cg_steps_fit(g, UT.su3, U.u64.ctab != nullptr);
+    Work partw(c, persist ? sizeof(double) * 3 * g.nblk * M : 64);
+    if (!partw.ok()) return WDR_ENOMEM;
+    hipError_t persist_err = hipSuccess;
 
     // bh = [b_e + k H_eo A_oo^-1 b_o; 0]; odd parts of every iterated field stay 0
     launch_zero<double>(x, total, s);
@@ -691,7 +697,12 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     const int ue = sp.update_every;
     auto period = [&](hipStream_t q) {
         const long tl = sa.ne() * sa.launch_m();
-        for (int i = 0; i < ue; ++i) {
+        if (persist) {
+            const hipError_t le = launch_cg_steps<T>(g, sa, UT, kT, ue, p, t, w, qv, r, e, sc, partw.as<double>(),
+                                                     RELIABLE_DELTA * RELIABLE_DELTA, sp.max_iter, rmax, upd, its, q);
+            if (le != hipSuccess && persist_err == hipSuccess) persist_err = le;
+        }
+        for (int i = 0; i < (persist ? 0 : ue); ++i) {
             // w = Dhat^+ p, q = Dhat w, e += alpha w, r -= alpha q, p = r + beta p
             apply_dhat<T>(g, sa, UT, kT, 1, p, t, w, q, op);
             apply_dhat<T>(g, sa, UT, kT, 0, w, t, qv, q, op);
@@ -714,7 +725,7 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
     // whenever compaction changes the launch list.
     PeriodGraph pg(s);
     for (int pt = 0;; ++pt) {
-        if (sp.graph) {
+        if (sp.graph && !persist) {
             if (!pg.exec) {
                 const wdr_status cs = pg.capture(c, period);
                 if (cs != WDR_OK) return cs;
@@ -743,6 +754,13 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
                 pg.reset();
             }
         }
+        if (persist_err != hipSuccess) break;
+    }
+    if (persist_err != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+        set_error(std::string("cooperative launch of the CG steps refused: ") + hipGetErrorString(persist_err));
+        return WDR_EDEVICE;
     }
     // x_o = A_oo^-1 (b_o + k H_oe x_e)
     launch_zero<double>(t64, total, s);

@@ -50,6 +50,7 @@ struct Geo {
     const int32_t *sched[3];
     int stencil;  // wdr_stencil choice for D and D_b on 4^4 blocks
     int mr_form;  // wdr_mr_form choice for the FP32 / FP16 block MR of block solves
+    int cg_form;  // wdr_cg_form choice for the steps of the FP32 / FP64 even-odd CGNE
 };
 
 // which schedule covers the slot range [slot0, slot0 + n), or -1

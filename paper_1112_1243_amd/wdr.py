@@ -22,6 +22,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5
 F64, F32, F16 = 0, 1, 2
 STENCIL_AUTO, STENCIL_DIR, STENCIL_BLK = 0, 1, 2
 MR_AUTO, MR_ONE_PER_CU, MR_TWO_PER_CU = 0, 1, 2
+CG_LAUNCHES, CG_PERSISTENT = 0, 1
 NOISE_Z2, NOISE_GAUSS = 0, 1
 OP_FULL, OP_SCHUR, OP_BLOCKS, OP_DD = 0, 1, 2, 3
 SOLVER_FGCR_SAP, SOLVER_CGNE = 0, 1
@@ -97,6 +98,7 @@ def lib():
         L.wdr_ctx_nblocks.restype = ctypes.c_int32
         L.wdr_ctx_set_stencil.argtypes = [P, i32]
         L.wdr_ctx_set_mr_form.argtypes = [P, i32]
+        L.wdr_ctx_set_cg_form.argtypes = [P, i32]
         L.wdr_traffic.argtypes = [i32]
         L.wdr_traffic.restype = ctypes.c_int64
         L.wdr_site_maps.argtypes = [P, P, P, P, P, P]
@@ -230,6 +232,11 @@ class Context:
         """Launch form of the FP32 / FP16 block MR of block solves (MR_AUTO,
         MR_ONE_PER_CU, MR_TWO_PER_CU)."""
         _check(lib().wdr_ctx_set_mr_form(self.handle, int(choice)))
+
+    def set_cg_form(self, choice: int):
+        """Launch form of the CG steps of the FP64 / FP32 even-odd CGNE
+        (CG_LAUNCHES, CG_PERSISTENT)."""
+        _check(lib().wdr_ctx_set_cg_form(self.handle, int(choice)))
 
     def close(self):
         if getattr(self, "handle", None):
