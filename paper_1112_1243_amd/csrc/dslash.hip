@@ -377,6 +377,101 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_dslash_blk(Geo g, const int32_t
         }
 }
 
+// The end of a round of the FP16 block solves in one pass over each block
+// (one workgroup per block, one lane per site): x += d (d the FP16 block-MR
+// result with its block scale), r = b - D_b x in FP64 (hops inside the
+// block, the new x staged in LDS), the block's |r|^2 into rn, and r in FP16
+// for the next round (block scale 2^ceil(log2 max |component|), the rounding
+// of k_to_h16).  The FP64 r itself is not stored.
+__global__ __launch_bounds__(Cube<4>::Vb) void k_block_round16(Geo g, const int32_t *__restrict__ active,
+                                                              UTab<double> Utab, const double *__restrict__ kap,
+                                                              long n, const int32_t *__restrict__ sched,
+                                                              const h2 *__restrict__ d16,
+                                                              const float *__restrict__ dscale,
+                                                              double2 *__restrict__ x, const double2 *__restrict__ b,
+                                                              h2 *__restrict__ r16, float *__restrict__ rscale,
+                                                              double *__restrict__ rn, double kappa)
+{
+    typedef Cube<4> CB;
+    constexpr int Vb = CB::Vb;
+    __shared__ double2 sh[12][Vb];
+    __shared__ double red[Vb / 64];
+    __shared__ float redm[Vb / 64];
+    const int m = blockIdx.y;
+    if (active && !active[m]) return;
+    if (kap) kappa = kap[m];
+    const int slot = sched[blockIdx.x];
+    const int l = threadIdx.x;
+    const auto *Ug = as_global(Utab[m]);
+    const long base = m * n + (long)slot * 12 * Vb + l;
+    const float ds = dscale[(long)m * g.nblk + slot];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+        const long i = base + (long)c * Vb;
+        const h2 dv = d16[i];
+        const double2 xo = x[i];
+        const double2 xn = make_double2(xo.x + (double)((float)dv.x * ds), xo.y + (double)((float)dv.y * ds));
+        x[i] = xn;
+        sh[c][l] = xn;
+    }
+    int xc[4];
+    CB::coords(l, xc);
+    int nbr[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
+    __syncthreads();
+    spinor<double> acc;
+    zero(acc);
+    const auto *xg = as_global(static_cast<const double2 *>(x + m * n));  // not read: the hops stay in the block
+#pragma unroll 1
+    for (int mu = 0; mu < 4; ++mu) {
+        int pin = 0;
+        asm volatile("" : "+s"(pin));
+        switch (mu) {
+        case 0: hop_blk<double, 4, 0, HOPS_IN, 0, Vb>(&sh[0][0], 0, xg, Ug, slot, nbr, l, xc, pin, acc, 1.0, 1.0); break;
+        case 1: hop_blk<double, 4, 1, HOPS_IN, 0, Vb>(&sh[0][0], 0, xg, Ug, slot, nbr, l, xc, pin, acc, 1.0, 1.0); break;
+        case 2: hop_blk<double, 4, 2, HOPS_IN, 0, Vb>(&sh[0][0], 0, xg, Ug, slot, nbr, l, xc, pin, acc, 1.0, 1.0); break;
+        default: hop_blk<double, 4, 3, HOPS_IN, 0, Vb>(&sh[0][0], 0, xg, Ug, slot, nbr, l, xc, pin, acc, 1.0, 1.0); break;
+        }
+    }
+    cx<double> r[12];
+    double nr = 0;
+    float mx = 0.f;
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int c = 3 * sp + a;
+            const cx<double> v = ld<double>(&sh[c][0], l) - scale(kappa, acc.s[sp].c[a]);
+            r[c] = ld<double>(b, base + (long)c * Vb) - v;
+            nr += r[c].re * r[c].re + r[c].im * r[c].im;
+            mx = fmaxf(mx, fmaxf(fabsf((float)r[c].re), fabsf((float)r[c].im)));
+        }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        nr += __shfl_down(nr, off, 64);
+        mx = fmaxf(mx, __shfl_down(mx, off, 64));
+    }
+    if ((l & 63) == 0) {
+        red[l >> 6] = nr;
+        redm[l >> 6] = mx;
+    }
+    __syncthreads();
+    float bmax = redm[0];
+#pragma unroll
+    for (int w = 1; w < Vb / 64; ++w) bmax = fmaxf(bmax, redm[w]);
+    const float rs = pow2_at_least(bmax), inv = 1.f / rs;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) r16[base + (long)c * Vb] = to_h2(mk<float>((float)r[c].re, (float)r[c].im), inv);
+    if (l == 0) {
+        double tot = 0;
+#pragma unroll
+        for (int w = 0; w < Vb / 64; ++w) tot += red[w];
+        rn[(long)m * g.nblk + slot] = tot;
+        rscale[(long)m * g.nblk + slot] = rs;
+    }
+}
+
 // The even-odd halves of the same operator (the stencil of the even-odd
 // reduced solvers): out = diag - kappa H_{par, 1-par} in on the sites of
 // parity par, with gamma_5 on both sides for DAG.  One workgroup per block,
@@ -966,6 +1061,18 @@ template <typename T> void launch_g5(const Geo &g, const Sys &sy, const T2<T> *i
 {
     const long total = sy.n * sy.M;
     k_g5<T><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(total, g.Vb, in, out);
+}
+
+bool launch_block_round16(const Geo &g, const Sys &sy, Links<double> U, H16c d, double2 *x, const double2 *b,
+                          H16 r16, double *rn, double kappa, int slot0, int nslots, hipStream_t s)
+{
+    if (nslots <= 0 || sy.M <= 0) return true;
+    if (g.B[0] != 4 || g.B[1] != 4 || g.B[2] != 4 || g.B[3] != 4 || !U.su3 || U.ctab || sy.list) return false;
+    const int si = sched_index(g, slot0, nslots);
+    if (si < 0) return false;
+    k_block_round16<<<dim3(nslots, sy.M), Cube<4>::Vb, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, g.sched[si], d.v,
+                                                              d.s, x, b, r16.v, r16.s, rn, kappa);
+    return true;
 }
 
 bool cg_steps_fit(const Geo &g, bool su3, bool clover)

@@ -116,6 +116,14 @@ bool launch_block_residual(const Geo &g, const Sys &sy, Links<double> U, const d
 template <typename T>
 void launch_dslash(const Geo &g, const Sys &sy, Links<T> U, int hops, int par, int dag, const T2<T> *in,
                    const T2<T> *diag, T2<T> *out, T kappa, int slot0, int nslots, hipStream_t s);
+// End of a round of the FP16 block solves on the slots [slot0, slot0 +
+// nslots), in one pass: x += d (FP16 with block scales), then r = b - D_b x
+// (FP64, in-block hops), rn[m * nblk + slot] = |r|^2 over the block and r16
+// = r in FP16 with block scales (as launch_to_h16 rounds it); the FP64 r is
+// not stored.  false (nothing launched) unless the blocks are 4^4, the links
+// SU(3) without a clover term and the slot range has a schedule.
+bool launch_block_round16(const Geo &g, const Sys &sy, Links<double> U, H16c d, double2 *x, const double2 *b,
+                          H16 r16, double *rn, double kappa, int slot0, int nslots, hipStream_t s);
 
 // Persistent form of `steps` steps of the even-odd CGNE (the step loop of
 // the CG in solvers.hip: w = Dhat^+ p, q = Dhat w, x / r update, new p, the

@@ -1219,15 +1219,22 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
         launch_zero_h16(g, all, d16->f(), s);
     }
     bool fused = true;
+    // FP16 rounds after the first: the previous round's fused end already
+    // left r in FP16 (round16), and the FP64 r is not kept
+    bool round16 = false;
     for (int round = 0; round < 40; ++round) {
+        bool have_norms = false;
         if (sp.inner == WDR_F64) {
             launch_block_mr<double>(g, sa, U.u64, r, d64.as<double2>(), kappa, nmr, slot0, ns, s);
             launch_add_to64<double>(sa, d64.as<double2>(), x, s);
         } else if (sp.inner == WDR_F16) {
-            launch_to_h16<double>(g, sa, r, r16->f(), slot0, ns, s);
+            if (!round16) launch_to_h16<double>(g, sa, r, r16->f(), slot0, ns, s);
             if (!launch_mr_h16(1, g, sa, U.u16, r16->cf(), d16->f(), (float)kappa, nmr, slot0, ns, s))
                 return need16(GaugeTab{});
-            launch_from_h16(g, sa, d16->cf(), x, 1, slot0, ns, s);
+            // x += d, r = b - D_b x with its block norms and its FP16 form
+            round16 = launch_block_round16(g, sa, U.u64, d16->cf(), x, b, r16->f(), rn, kappa, slot0, ns, s);
+            have_norms = round16;
+            if (!round16) launch_from_h16(g, sa, d16->cf(), x, 1, slot0, ns, s);
         } else {
             launch_convert<float, double>(sa, r, r32.as<float2>(), s);
             launch_block_mr<float>(g, sa, U.u32, r32.as<float2>(), d32.as<float2>(), (float)kappa, nmr, slot0, ns, s);
@@ -1235,9 +1242,11 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
         }
         // r = b - D_b x and its norm per block on the selected blocks (r stays
         // zero elsewhere: nothing below writes other blocks of r)
-        fused = launch_block_residual(g, sa, U.u64, x, b, r, kappa, slot0, ns, s);
-        if (!fused) launch_dslash<double>(g, sa, U.u64, HOPS_IN, -1, 0, x, x, t, kappa, slot0, ns, s);
-        launch_block_resid_norm(g, sa, b, fused ? nullptr : t, r, rn, slot0, ns, s);
+        if (!have_norms) {
+            fused = launch_block_residual(g, sa, U.u64, x, b, r, kappa, slot0, ns, s);
+            if (!fused) launch_dslash<double>(g, sa, U.u64, HOPS_IN, -1, 0, x, x, t, kappa, slot0, ns, s);
+            launch_block_resid_norm(g, sa, b, fused ? nullptr : t, r, rn, slot0, ns, s);
+        }
         k_block_check<<<M, BC_NT, 0, s>>>(g.nblk, slot0, ns, bn, rn, tol * tol, alive, its, worst);
         poll.post(alive, round & 1, s);
         // round is queued; stop once round - 1 left no system alive
@@ -1261,12 +1270,15 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
     double setup = V * (4 * spin_b<double>()) + Vs * spin_b<double>();
     setup += sp.inner == WDR_F16 ? V * 48 : V * ps;
     double round_b = Vs * (2 * ps + lin * pl);
-    if (sp.inner == WDR_F16)
+    if (sp.inner == WDR_F16 && round16)  // the fused end: d, x, b, links in; x, r16 out
+        round_b += Vs * (48 + 3 * spin_b<double>() + lin * 96.0 + 48);
+    else if (sp.inner == WDR_F16)
         round_b += Vs * (spin_b<double>() + 48) + Vs * (48 + 2 * spin_b<double>());
     else
         round_b += V * (ps + spin_b<double>()) * (sp.inner == WDR_F32 ? 1 : 0) + V * (ps + 2 * spin_b<double>());
-    round_b += fused ? Vs * (4 * spin_b<double>() + lin * 96.0)
-                     : Vs * (2 * spin_b<double>() + lin * 96.0) + Vs * 3 * spin_b<double>();
+    if (!(sp.inner == WDR_F16 && round16))
+        round_b += fused ? Vs * (4 * spin_b<double>() + lin * 96.0)
+                         : Vs * (2 * spin_b<double>() + lin * 96.0) + Vs * 3 * spin_b<double>();
     double bytes = 0;
     for (int m = 0; m < M; ++m) {
         bytes += setup + hits[m] * round_b;
