@@ -47,7 +47,7 @@ CSW = 1.7
 # Reported only while the stencil sources hash to the value recorded there.
 COUNTERS = os.path.join(ROOT, "profiles", "dslash_blk_32x32x32x32_counters.md")
 STENCIL_SOURCES = ["paper_1112_1243_amd/csrc/dslash.hip", "paper_1112_1243_amd/csrc/half.hip",
-                   "paper_1112_1243_amd/csrc/stencil.h",
+                   "paper_1112_1243_amd/csrc/stencil.h", "paper_1112_1243_amd/csrc/blk_stencil.h",
                    "paper_1112_1243_amd/csrc/wdr_internal.h"]
 
 WORKLOAD = dict(name="wilson8_dd16", L=(8, 8, 8, 8), B=(4, 4, 4, 4), kappa=0.135, scale=0.5, n_steps=8,

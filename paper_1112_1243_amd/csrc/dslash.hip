@@ -15,12 +15,7 @@
 // shapes: k_dslash, one lane per site and 256 consecutive sites of one block
 // per workgroup.  In both, a wavefront reads each spinor / link component of
 // 64 consecutive sites as one contiguous 512 B (FP32) or 1 KiB (FP64) run.
-#include <hip/hip_cooperative_groups.h>
-
-#include <algorithm>
-
-#include "clover.h"
-#include "stencil.h"
+#include "blk_stencil.h"
 
 namespace wdr {
 namespace {
@@ -214,7 +209,6 @@ __global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__rest
     }
 }
 
-
 // Block-staged stencil for B^4 blocks (full-lattice operator D or the
 // Dirichlet block operator D_b, diagonal term = the input): one workgroup per
 // block and one lane per site.  The block's input spinor is read once into
@@ -223,77 +217,6 @@ __global__ __launch_bounds__(256) void k_dslash_dir(Geo g, const int32_t *__rest
 // global memory.  Against k_dslash_dir this cuts the vector-memory
 // instructions per site (each in-block spinor is read once instead of once
 // per neighbour), which bound that kernel.
-// The two hops of direction MU at site l: in-block neighbours from the LDS
-// copy sh ([12][NS], entry (c, nl - off)), the others from global memory;
-// DAG applies gamma_5 to the loaded spinors (the caller to the result).
-template <typename T, int B, int MU, int HOPS, int DAG, int NS>
-__device__ __forceinline__ void hop_blk(const T2<T> *sh, int off, const __attribute__((address_space(1))) T2<T> *in,
-                                        const __attribute__((address_space(1))) T2<T> *Ug, int slot, const int nbr[8],
-                                        int l, const int x[4], int pin, spinor<T> &acc, T wrap_f, T wrap_b)
-{
-    typedef Cube<B> CB;
-    constexpr int Vb = CB::Vb;
-#pragma unroll
-    for (int dir = 0; dir < 2; ++dir) {
-        const bool fwd = dir == 0;
-        const bool inside = fwd ? x[MU] + 1 < B : x[MU] > 0;
-        if (HOPS == HOPS_IN && !inside) continue;
-        int y[4] = {x[0], x[1], x[2], x[3]};
-        y[MU] = fwd ? (inside ? x[MU] + 1 : 0) : (inside ? x[MU] - 1 : B - 1);
-        const int ns = inside ? slot : nbr[2 * MU + dir];
-        const int nl = CB::index(y);
-        spinor<T> p;
-        if (inside) {
-#pragma unroll
-            for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) p.s[sp].c[a] = ld<T>(sh, (3 * sp + a) * NS + nl - off);
-        } else {
-#pragma unroll
-            for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-                for (int a = 0; a < 3; ++a) p.s[sp].c[a] = ldg<T>(in, ns * 12 * Vb + nl + pin + (3 * sp + a) * Vb);
-        }
-        su3<T> u;
-        const int ls = fwd ? slot : ns, ll = fwd ? l : nl;
-#pragma unroll
-        for (int e = 0; e < 6; ++e) u.m[e / 3][e % 3] = ldg<T>(Ug, (ls * 4 + MU) * 9 * Vb + ll + pin + e * Vb);
-        const T sg = fwd ? wrap_f : wrap_b;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const int a = (c + 1) % 3, b = (c + 2) % 3;
-            const cx<T> v = u.m[0][a] * u.m[1][b] - u.m[0][b] * u.m[1][a];
-            u.m[2][c] = mk<T>(sg * v.re, -sg * v.im);
-        }
-        if (DAG) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                p.s[2].c[a] = neg(p.s[2].c[a]);
-                p.s[3].c[a] = neg(p.s[3].c[a]);
-            }
-        }
-        vec3<T> a0, a1;
-        A_dn(MU, p.s[2], p.s[3], a0, a1);
-        vec3<T> h0, h1;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            h0.c[a] = fwd ? p.s[0].c[a] - a0.c[a] : p.s[0].c[a] + a0.c[a];
-            h1.c[a] = fwd ? p.s[1].c[a] - a1.c[a] : p.s[1].c[a] + a1.c[a];
-        }
-        const vec3<T> c0 = fwd ? mul(u, h0) : mul_dag(u, h0);
-        const vec3<T> c1 = fwd ? mul(u, h1) : mul_dag(u, h1);
-        vec3<T> d0, d1;
-        Adag_h(MU, c0, c1, d0, d1);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
-            acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
-            acc.s[2].c[a] = fwd ? acc.s[2].c[a] - d0.c[a] : acc.s[2].c[a] + d0.c[a];
-            acc.s[3].c[a] = fwd ? acc.s[3].c[a] - d1.c[a] : acc.s[3].c[a] + d1.c[a];
-        }
-    }
-}
-
 //
 // RES: write the residual b - out instead of out (the residual of a block
 // solve, r = b - D_b x, in one pass).  CL = CLOV_DIAG: the diagonal term is
@@ -377,183 +300,10 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_dslash_blk(Geo g, const int32_t
         }
 }
 
-// The end of a round of the FP16 block solves in one pass over each block
-// (one workgroup per block, one lane per site): x += d (d the FP16 block-MR
-// result with its block scale), r = b - D_b x in FP64 (hops inside the
-// block, the new x staged in LDS), the block's |r|^2 into rn, and r in FP16
-// for the next round (block scale 2^ceil(log2 max |component|), the rounding
-// of k_to_h16).  The FP64 r itself is not stored.
-__global__ __launch_bounds__(Cube<4>::Vb) void k_block_round16(Geo g, const int32_t *__restrict__ active,
-                                                              UTab<double> Utab, const double *__restrict__ kap,
-                                                              long n, const int32_t *__restrict__ sched,
-                                                              const h2 *__restrict__ d16,
-                                                              const float *__restrict__ dscale,
-                                                              double2 *__restrict__ x, const double2 *__restrict__ b,
-                                                              h2 *__restrict__ r16, float *__restrict__ rscale,
-                                                              double *__restrict__ rn, double kappa)
-{
-    typedef Cube<4> CB;
-    constexpr int Vb = CB::Vb;
-    __shared__ double2 sh[12][Vb];
-    __shared__ double red[Vb / 64];
-    __shared__ float redm[Vb / 64];
-    const int m = blockIdx.y;
-    if (active && !active[m]) return;
-    if (kap) kappa = kap[m];
-    const int slot = sched[blockIdx.x];
-    const int l = threadIdx.x;
-    const auto *Ug = as_global(Utab[m]);
-    const long base = m * n + (long)slot * 12 * Vb + l;
-    const float ds = dscale[(long)m * g.nblk + slot];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        const long i = base + (long)c * Vb;
-        const h2 dv = d16[i];
-        const double2 xo = x[i];
-        const double2 xn = make_double2(xo.x + (double)((float)dv.x * ds), xo.y + (double)((float)dv.y * ds));
-        x[i] = xn;
-        sh[c][l] = xn;
-    }
-    int xc[4];
-    CB::coords(l, xc);
-    int nbr[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
-    __syncthreads();
-    spinor<double> acc;
-    zero(acc);
-    const auto *xg = as_global(static_cast<const double2 *>(x + m * n));  // not read: the hops stay in the block
-#pragma unroll 1
-    for (int mu = 0; mu < 4; ++mu) {
-        int pin = 0;
-        asm volatile("" : "+s"(pin));
-        switch (mu) {
-        case 0: hop_blk<double, 4, 0, HOPS_IN, 0, Vb>(&sh[0][0], 0, xg, Ug, slot, nbr, l, xc, pin, acc, 1.0, 1.0); break;
-        case 1: hop_blk<double, 4, 1, HOPS_IN, 0, Vb>(&sh[0][0], 0, xg, Ug, slot, nbr, l, xc, pin, acc, 1.0, 1.0); break;
-        case 2: hop_blk<double, 4, 2, HOPS_IN, 0, Vb>(&sh[0][0], 0, xg, Ug, slot, nbr, l, xc, pin, acc, 1.0, 1.0); break;
-        default: hop_blk<double, 4, 3, HOPS_IN, 0, Vb>(&sh[0][0], 0, xg, Ug, slot, nbr, l, xc, pin, acc, 1.0, 1.0); break;
-        }
-    }
-    cx<double> r[12];
-    double nr = 0;
-    float mx = 0.f;
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int c = 3 * sp + a;
-            const cx<double> v = ld<double>(&sh[c][0], l) - scale(kappa, acc.s[sp].c[a]);
-            r[c] = ld<double>(b, base + (long)c * Vb) - v;
-            nr += r[c].re * r[c].re + r[c].im * r[c].im;
-            mx = fmaxf(mx, fmaxf(fabsf((float)r[c].re), fabsf((float)r[c].im)));
-        }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        nr += __shfl_down(nr, off, 64);
-        mx = fmaxf(mx, __shfl_down(mx, off, 64));
-    }
-    if ((l & 63) == 0) {
-        red[l >> 6] = nr;
-        redm[l >> 6] = mx;
-    }
-    __syncthreads();
-    float bmax = redm[0];
-#pragma unroll
-    for (int w = 1; w < Vb / 64; ++w) bmax = fmaxf(bmax, redm[w]);
-    const float rs = pow2_at_least(bmax), inv = 1.f / rs;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) r16[base + (long)c * Vb] = to_h2(mk<float>((float)r[c].re, (float)r[c].im), inv);
-    if (l == 0) {
-        double tot = 0;
-#pragma unroll
-        for (int w = 0; w < Vb / 64; ++w) tot += red[w];
-        rn[(long)m * g.nblk + slot] = tot;
-        rscale[(long)m * g.nblk + slot] = rs;
-    }
-}
-
 // The even-odd halves of the same operator (the stencil of the even-odd
 // reduced solvers): out = diag - kappa H_{par, 1-par} in on the sites of
-// parity par, with gamma_5 on both sides for DAG.  One workgroup per block,
-// one lane per output site; the block's input sites of the other parity are
-// read once into LDS (sh).  blk_eo_block is one workgroup's block (system m,
-// slot `slot`, lane t = threadIdx.x); with NRM it returns the lane's
-// |out|^2 in FP64 (0 otherwise).  It ends with the LDS still in use: a
-// caller that runs it again on the same sh synchronises the workgroup first.
-template <typename T, int B, int DAG, int CL, int NRM>
-__device__ __forceinline__ double blk_eo_block(const Geo &g, int m, int slot, int t, UTab<T> Utab,
-                                               const double *__restrict__ kap, int kneg,
-                                               const T *const *__restrict__ ctab, long n, int par,
-                                               const T2<T> *__restrict__ in, const T2<T> *__restrict__ diag,
-                                               T2<T> *__restrict__ out, T kappa, T2<T> (*sh)[Cube<B>::Vh])
-{
-    typedef Cube<B> CB;
-    constexpr int Vb = CB::Vb, Vh = CB::Vh;
-    if (kap) kappa = kneg ? -(T)kap[m] : (T)kap[m];
-    const int off = (1 - par) * Vh;  // first local index of the input parity
-    const auto *Ug = as_global(Utab[m]);
-    const auto *ing = as_global(in + m * n);
-    const long sbase = (long)slot * 12 * Vb;
-#pragma unroll
-    for (int c = 0; c < 12; ++c) st<T>(&sh[c][0], t, ldg<T>(ing, sbase + off + t + c * Vb));
-    const int l = par * Vh + t;
-    int x[4];
-    CB::coords(l, x);
-    int nbr[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) nbr[k] = g.slot_nbr[slot * 8 + k];
-    const int bl = g.slot_blk[slot];
-    __syncthreads();
-    spinor<T> acc;
-    zero(acc);
-#pragma unroll 1
-    for (int mu = 0; mu < 4; ++mu) {
-        int pin = 0;
-        asm volatile("" : "+s"(pin));
-        T wf = 1, wb = 1;
-        if (g.bc[mu] < 0) {
-            int b2 = bl;
-            for (int d = 0; d < mu; ++d) b2 /= g.NB[d];
-            const int nmu = b2 % g.NB[mu];
-            if (nmu == g.NB[mu] - 1 && x[mu] == B - 1) wf = -1;
-            if (nmu == 0 && x[mu] == 0) wb = -1;
-        }
-        switch (mu) {
-        case 0: hop_blk<T, B, 0, HOPS_ALL, DAG, Vh>(&sh[0][0], off, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
-        case 1: hop_blk<T, B, 1, HOPS_ALL, DAG, Vh>(&sh[0][0], off, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
-        case 2: hop_blk<T, B, 2, HOPS_ALL, DAG, Vh>(&sh[0][0], off, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
-        default: hop_blk<T, B, 3, HOPS_ALL, DAG, Vh>(&sh[0][0], off, ing, Ug, slot, nbr, l, x, pin, acc, wf, wb); break;
-        }
-    }
-    const long obase = m * n + sbase + l;
-    double nrm = 0;
-    if (CL) {
-        cx<T> v[12], dg[12];
-#pragma unroll
-        for (int c = 0; c < 12; ++c) {
-            v[c] = scale(-kappa, acc.s[c / 3].c[c % 3]);
-            if (DAG && c >= 6) v[c] = neg(v[c]);
-            dg[c] = diag ? ld<T>(diag, obase + (long)c * Vb) : mk<T>(0, 0);
-        }
-        clov_site<T, CL>(ctab[m], (long)g.V, slot, Vb, l, dg, v);
-#pragma unroll
-        for (int c = 0; c < 12; ++c) st_nt<T>(out, obase + (long)c * Vb, v[c]);
-        return nrm;
-    }
-#pragma unroll
-    for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const long i = obase + (long)(3 * sp + a) * Vb;
-            cx<T> v = scale(-kappa, acc.s[sp].c[a]);
-            if (DAG && sp >= 2) v = neg(v);
-            if (diag) v = v + ld<T>(diag, i);
-            st_nt<T>(out, i, v);
-            if (NRM) nrm += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
-        }
-    return nrm;
-}
-
+// parity par, gamma_5 on both sides for DAG; one workgroup per block, the
+// body blk_eo_block (blk_stencil.h).
 template <typename T, int B, int DAG, int CL>
 __global__ __launch_bounds__(Cube<B>::Vh) void k_dslash_blk_eo(Geo g, const int32_t *__restrict__ active,
                                                               const int32_t *__restrict__ list, UTab<T> Utab,
@@ -608,169 +358,6 @@ void launch_blk_eo(const Geo &g, const Sys &sy, Links<T> U, int par, int dag, co
     else
         k_dslash_blk_eo<T, B, 0, CL><<<gb, Cube<B>::Vh, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, U.kneg, U.ctab,
                                                                sy.n, sc, par, in, diag, out, kappa);
-}
-
-// ---------------------------------------------------------------- persistent CG steps
-// The steps of the even-odd CGNE (Dhat Dhat^+ y = bh, vectors in T on the
-// even sites) as one cooperative launch: each step's four stencil halves, its
-// x / r update and its new search direction are phases of one grid,
-// separated by grid-wide barriers instead of kernel boundaries.  A phase's
-// work items are (block, system) pairs dealt round-robin to the workgroups,
-// one lane per even site; the stencil halves are blk_eo_block.  Inner
-// products go through one partial sum per item (|w|^2 in the second half,
-// |r|^2 in the update), which every workgroup adds over the blocks of a
-// system in the same order, so all workgroups hold the same scalars.  The
-// control of a step (iteration count, reliable-update flag, largest residual)
-// is that of k_cgm_beta, done by the workgroup holding the system's first
-// block; the CG scalars are written back after the last step.
-
-template <typename T> struct CgSteps {
-    const int32_t *active, *list;
-    int nsys, nslots, steps, max_iter;
-    UTab<T> U;
-    const double *kap;
-    long n;
-    const int32_t *sched;
-    T kappa;
-    T2<T> *p, *t, *w, *q, *r, *e;
-    double2 *sc;    // 8 per system: [0] rr, [1] |w|^2, [3] new rr, [4] beta
-    double *part;   // 3 x items: |w|^2, then |r|^2 of even and of odd steps
-    double delta2;  // reliable-update threshold (squared)
-    double *rmax;
-    int32_t *upd, *its;
-};
-
-// sum over the 128 lanes of a workgroup (two wavefronts); every lane gets it
-__device__ __forceinline__ double wg_sum(double v, double *sh)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    const double r = sh[0] + sh[1];
-    __syncthreads();
-    return r;
-}
-
-// the partial sums of system j's items, added in the same order everywhere
-__device__ __forceinline__ double sys_sum(const double *part, int j, int nslots, double *sh)
-{
-    double v = 0;
-    for (int i = threadIdx.x; i < nslots; i += Cube<4>::Vh) v += part[(long)j * nslots + i];
-    return wg_sum(v, sh);
-}
-
-template <typename T>
-__global__ __launch_bounds__(Cube<4>::Vh) void k_cg_steps(Geo g, CgSteps<T> a)
-{
-    constexpr int B = 4, Vb = Cube<B>::Vb, Vh = Cube<B>::Vh;
-    __shared__ T2<T> sh[12][Vh];
-    __shared__ double rs[2];
-    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
-    const int t = threadIdx.x, items = a.nslots * a.nsys, G = gridDim.x;
-    double *pww = a.part, *prr[2] = {a.part + items, a.part + 2 * (long)items};
-    // the residual the step starts from: the stored one, or the last step's
-    auto rr_in = [&](int k, int j, int m) -> double {
-        return k == 0 ? a.sc[8L * m].x : sys_sum(prr[(k + 1) & 1], j, a.nslots, rs);
-    };
-    for (int k = 0; k < a.steps; ++k) {
-        // w = Dhat^+ p: odd half from p, then the even half with p as diagonal
-        for (int it = blockIdx.x; it < items; it += G) {
-            const int m = sys_at(a.list, it / a.nslots);
-            if (a.active && !a.active[m]) continue;
-            blk_eo_block<T, B, 1, CLOV_NONE, 0>(g, m, a.sched[it % a.nslots], t, a.U, a.kap, 0, nullptr, a.n, 1, a.p,
-                                                nullptr, a.t, a.kappa, sh);
-            __syncthreads();
-        }
-        grid.sync();
-        for (int it = blockIdx.x; it < items; it += G) {
-            const int m = sys_at(a.list, it / a.nslots);
-            if (a.active && !a.active[m]) continue;
-            const double v = blk_eo_block<T, B, 1, CLOV_NONE, 1>(g, m, a.sched[it % a.nslots], t, a.U, a.kap, 1,
-                                                                 nullptr, a.n, 0, a.t, a.p, a.w, -a.kappa, sh);
-            const double s = wg_sum(v, rs);
-            if (t == 0) pww[it] = s;
-        }
-        grid.sync();
-        // q = Dhat w
-        for (int it = blockIdx.x; it < items; it += G) {
-            const int m = sys_at(a.list, it / a.nslots);
-            if (a.active && !a.active[m]) continue;
-            blk_eo_block<T, B, 0, CLOV_NONE, 0>(g, m, a.sched[it % a.nslots], t, a.U, a.kap, 0, nullptr, a.n, 1, a.w,
-                                                nullptr, a.t, a.kappa, sh);
-            __syncthreads();
-        }
-        grid.sync();
-        for (int it = blockIdx.x; it < items; it += G) {
-            const int m = sys_at(a.list, it / a.nslots);
-            if (a.active && !a.active[m]) continue;
-            blk_eo_block<T, B, 0, CLOV_NONE, 0>(g, m, a.sched[it % a.nslots], t, a.U, a.kap, 1, nullptr, a.n, 0, a.t,
-                                                a.w, a.q, -a.kappa, sh);
-            __syncthreads();
-        }
-        grid.sync();
-        // alpha = rr / |w|^2; e += alpha w, r -= alpha q on the block's even
-        // sites, and the partial |r|^2
-        for (int it = blockIdx.x; it < items; it += G) {
-            const int j = it / a.nslots, m = sys_at(a.list, j);
-            if (a.active && !a.active[m]) continue;
-            const double ww = sys_sum(pww, j, a.nslots, rs), rr = rr_in(k, j, m);
-            const T al = (T)(ww > 0 ? rr / ww : 0.0);
-            const long base = m * a.n + (long)a.sched[it % a.nslots] * 12 * Vb + t;
-            double nr = 0;
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const long i = base + (long)c * Vb;
-                T2<T> ei = a.e[i], ri = a.r[i];
-                const T2<T> wi = a.w[i], qi = a.q[i];
-                ei.x = ei.x + al * wi.x;
-                ei.y = ei.y + al * wi.y;
-                ri.x = ri.x - al * qi.x;
-                ri.y = ri.y - al * qi.y;
-                a.e[i] = ei;
-                a.r[i] = ri;
-                nr += (double)ri.x * (double)ri.x + (double)ri.y * (double)ri.y;
-            }
-            const double s = wg_sum(nr, rs);
-            if (t == 0) prr[k & 1][it] = s;
-        }
-        grid.sync();
-        // beta = rr_new / rr, p = r + beta p; the step's control
-        for (int it = blockIdx.x; it < items; it += G) {
-            const int j = it / a.nslots, m = sys_at(a.list, j);
-            if (a.active && !a.active[m]) continue;
-            const double rr0 = rr_in(k, j, m), rr = sys_sum(prr[k & 1], j, a.nslots, rs);
-            const T b = (T)(rr0 > 0 ? rr / rr0 : 0.0);
-            const long base = m * a.n + (long)a.sched[it % a.nslots] * 12 * Vb + t;
-#pragma unroll
-            for (int c = 0; c < 12; ++c) {
-                const long i = base + (long)c * Vb;
-                const T2<T> ri = a.r[i], pi = a.p[i];
-                a.p[i].x = ri.x + b * pi.x;
-                a.p[i].y = ri.y + b * pi.y;
-            }
-            if (it % a.nslots == 0 && t == 0) {
-                const int kk = ++a.its[m];
-                a.rmax[m] = fmax(a.rmax[m], rr);
-                if (!(rr > a.delta2 * a.rmax[m]) || kk >= a.max_iter) a.upd[m] = 1;
-            }
-        }
-        grid.sync();
-    }
-    // the CG scalars of the last step, as the step-by-step form leaves them
-    for (int it = blockIdx.x; it < items; it += G) {
-        if (it % a.nslots) continue;
-        const int j = it / a.nslots, m = sys_at(a.list, j);
-        if (a.active && !a.active[m]) continue;
-        const double rr0 = rr_in(a.steps - 1, j, m), rr = sys_sum(prr[(a.steps - 1) & 1], j, a.nslots, rs);
-        const double ww = sys_sum(pww, j, a.nslots, rs);
-        if (t == 0) {
-            a.sc[8L * m + 1] = make_double2(ww, 0.0);
-            a.sc[8L * m + 3] = make_double2(rr, 0.0);
-            a.sc[8L * m + 4] = make_double2(rr0 > 0 ? rr / rr0 : 0.0, 0.0);
-            a.sc[8L * m] = make_double2(rr, 0.0);
-        }
-    }
 }
 
 // clover mode of a launch: the links' mode when they carry a clover term and
@@ -1063,52 +650,7 @@ template <typename T> void launch_g5(const Geo &g, const Sys &sy, const T2<T> *i
     k_g5<T><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(total, g.Vb, in, out);
 }
 
-bool launch_block_round16(const Geo &g, const Sys &sy, Links<double> U, H16c d, double2 *x, const double2 *b,
-                          H16 r16, double *rn, double kappa, int slot0, int nslots, hipStream_t s)
-{
-    if (nslots <= 0 || sy.M <= 0) return true;
-    if (g.B[0] != 4 || g.B[1] != 4 || g.B[2] != 4 || g.B[3] != 4 || !U.su3 || U.ctab || sy.list) return false;
-    const int si = sched_index(g, slot0, nslots);
-    if (si < 0) return false;
-    k_block_round16<<<dim3(nslots, sy.M), Cube<4>::Vb, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, g.sched[si], d.v,
-                                                              d.s, x, b, r16.v, r16.s, rn, kappa);
-    return true;
-}
-
-bool cg_steps_fit(const Geo &g, bool su3, bool clover)
-{
-    return g.B[0] == 4 && g.B[1] == 4 && g.B[2] == 4 && g.B[3] == 4 && su3 && !clover &&
-           sched_index(g, 0, g.nblk) >= 0;
-}
-
-template <typename T>
-hipError_t launch_cg_steps(const Geo &g, const Sys &sy, Links<T> U, T kappa, int steps, T2<T> *p, T2<T> *t,
-                           T2<T> *w, T2<T> *q, T2<T> *r, T2<T> *e, double2 *sc, double *part, double delta2,
-                           int max_iter, double *rmax, int32_t *upd, int32_t *its, hipStream_t s)
-{
-    if (!cg_steps_fit(g, U.su3, U.ctab != nullptr)) return hipErrorInvalidValue;
-    int dev = 0, cus = 0, per_cu = 0;
-    hipError_t e0 = hipGetDevice(&dev);
-    if (e0 == hipSuccess) e0 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e0 == hipSuccess)
-        e0 = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_cg_steps<T>),
-                                                          Cube<4>::Vh, 0);
-    if (e0 != hipSuccess) return e0;
-    const long items = (long)g.nblk * sy.launch_m();
-    // every workgroup must be resident at once (the launch is refused otherwise)
-    const int G = (int)std::max<long>(1, std::min<long>(items, (long)per_cu * cus));
-    Geo gc = g;
-    CgSteps<T> a{sy.active, sy.list, sy.launch_m(), g.nblk, steps, max_iter, U.tab, U.kap, sy.n,
-                 g.sched[sched_index(g, 0, g.nblk)], kappa, p, t, w, q, r, e, sc, part, delta2, rmax, upd, its};
-    void *args[] = {&gc, &a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_cg_steps<T>), dim3(G), dim3(Cube<4>::Vh),
-                                      args, 0, s);
-}
-
 #define INST(T)                                                                                                  \
-    template hipError_t launch_cg_steps<T>(const Geo &, const Sys &, Links<T>, T, int, T2<T> *, T2<T> *,          \
-                                           T2<T> *, T2<T> *, T2<T> *, T2<T> *, double2 *, double *, double, int,  \
-                                           double *, int32_t *, int32_t *, hipStream_t);                          \
     template void launch_dslash<T>(const Geo &, const Sys &, Links<T>, int, int, int, const T2<T> *,              \
                                    const T2<T> *, T2<T> *, T, int, int, hipStream_t);                            \
     template void launch_pack_spinor<T>(const Geo &, const double2 *, C2<T>::type *, hipStream_t);               \
