@@ -124,6 +124,60 @@ def clover_workload(wdr, torch, L=(16, 16, 16, 16), N=8, kappa=0.135, scale=0.5,
     return out
 
 
+def slab_halo(wdr, torch, kappa=0.155, scale=0.2, seed=1112124330, reps=50):
+    """One GPU's share of a 32^4 lattice cut along t over 8 GPUs: the slab
+    32^3 x 4 (one block in t) with an open t boundary.  Times (HIP events,
+    FP32 internal fields) the slab's own D, the face pack and the unpack of
+    the hops across both faces, next to the plain D of the same slab with a
+    periodic t boundary (the one-GPU stand-in for the exchange); the faces
+    are what one peer copy per direction would move over xGMI."""
+    from paper_1112_1243_amd import synth
+    L, B = (32, 32, 32, 4), (4, 4, 4, 4)
+    U = synth.gauge_field(L, scale, seed)
+    psi = synth.spinor(L, seed + 1)
+    Ud, pd = torch.from_numpy(U).cuda(), torch.from_numpy(psi).cuda()
+    ctx, per = wdr.Context(L, B, (1, 1, 1, 0)), wdr.Context(L, B, (1, 1, 1, 1))
+    gU, gP = ctx.gauge(Ud), per.gauge(Ud)
+    prec = wdr.F32
+    fin, fout, fref = ctx.pack(pd, prec), ctx.internal_field(prec), per.internal_field(prec)
+    lo, hi = ctx.halo_field(prec), ctx.halo_field(prec)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    t_int = timed(lambda: ctx.apply_D_internal(gU, kappa, fin, fout, prec))
+    t_pack = timed(lambda: ctx.halo_pack(Ud, fin, lo, hi, prec))
+    t_unp = timed(lambda: ctx.halo_unpack(Ud, kappa, hi, lo, 1, 1, fout, prec))
+    t_per = timed(lambda: per.apply_D_internal(gP, kappa, fin, fref, prec))
+    # the sharded pieces give the periodic D (ring of one slab)
+    ctx.apply_D_internal(gU, kappa, fin, fout, prec)
+    ctx.halo_pack(Ud, fin, lo, hi, prec)
+    ctx.halo_unpack(Ud, kappa, hi, lo, 1, 1, fout, prec)
+    a, b = ctx.unpack(fout, prec), per.unpack(fref, prec)
+    diff = float((a - b).abs().max() / b.abs().max())
+    face = int(lo.numel())
+    out = {"workload": "32x32x32x4 slab of a 32^4 lattice cut along t over 8 GPUs, 4^4 blocks, kappa %.3f, links "
+                       "exp(i %.1f H), FP32 fields" % (kappa, scale),
+           "unit": "us", "slab_D_open_t_us": round(t_int, 2), "halo_pack_us": round(t_pack, 2),
+           "halo_unpack_us": round(t_unp, 2), "periodic_D_us": round(t_per, 2),
+           "face_bytes_per_direction": face,
+           "xgmi_us_per_direction_at_153GBs": round(face / 153e9 * 1e6, 2),
+           "sharded_vs_periodic_max_rel_diff": diff}
+    log("slab halo:", out)
+    del gU, gP
+    ctx.close()
+    per.close()
+    return out
+
+
 def cg_forms(wdr, torch, N=16, kappa=0.135, scale=0.5, seed=1112124320):
     """FULL estimates (N factors x 1 Gaussian noise, all batched; CGNE with
     FP32 steps and FP64 reliable updates to 1e-10) at 8^4, 16^4 and 32^4 with
@@ -1043,6 +1097,8 @@ def main():
     ap.add_argument("--no-clover", action="store_true", help="skip the clover FULL estimates")
     ap.add_argument("--no-cg-forms", action="store_true", help="skip the CG launch-form comparison")
     ap.add_argument("--cg-forms-only", action="store_true", help="run only the CG launch-form comparison")
+    ap.add_argument("--no-slab", action="store_true", help="skip the slab-halo timing")
+    ap.add_argument("--slab-only", action="store_true", help="run only the slab-halo timing")
     ap.add_argument("--acceptance", action="store_true", help="also run the exact-acceptance variance study")
     ap.add_argument("--stencil", choices=("auto", "dir", "blk"), default="auto",
                     help="stencil kernel for the 32^4 full-stencil launches (default: the library's choice)")
@@ -1058,12 +1114,16 @@ def main():
     if args.headline_only:
         args.no_cpu = args.no_fp64 = args.no_dslash = args.no_batch = args.no_large = args.no_dd8 = True
         args.no_blockdet = args.no_recursive = args.no_filter = args.no_clover = args.no_cg_forms = True
+        args.no_slab = True
 
     import torch
     from paper_1112_1243_amd import synth, wdr
 
     if args.cg_forms_only:
         print(json.dumps(cg_forms(wdr, torch)), flush=True)
+        return
+    if args.slab_only:
+        print(json.dumps(slab_halo(wdr, torch)), flush=True)
         return
 
     if args.roofline_only:
@@ -1121,6 +1181,7 @@ def main():
         log("recursive dd:", rdd)
     clov = None if args.no_clover else clover_workload(wdr, torch)
     forms = None if args.no_cg_forms else cg_forms(wdr, torch)
+    slab = None if args.no_slab else slab_halo(wdr, torch)
     filt = None if args.no_filter else filter_run(wdr, torch)
     if filt:
         log("filter:", filt)
@@ -1164,6 +1225,7 @@ def main():
         "filter": filt,
         "clover_16": clov,
         "cg_forms": forms,
+        "slab_halo": slab,
         "exact_acceptance": acc,
         "cpu_baseline": cpu,
     }

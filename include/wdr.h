@@ -294,6 +294,35 @@ int64_t wdr_field_bytes(const wdr_ctx *ctx, wdr_prec prec);
 wdr_status wdr_pack(wdr_ctx *ctx, wdr_prec prec, const double *dev_canon, void *dev_internal, void *stream);
 wdr_status wdr_unpack(wdr_ctx *ctx, wdr_prec prec, const void *dev_internal, double *dev_canon, void *stream);
 
+/* Halo of a lattice cut along t into slabs of whole blocks, one per GPU
+ * (the sharding of a lattice too large for one GPU).  Sec. 3, eq. domdec:
+ * D is its block-diagonal part plus the hops between blocks; the hops
+ * between two slabs are block-interaction hops across the cut, and the rest
+ * is the slab's own D with an open t boundary (wdr_apply_D_internal on a
+ * context with bc[3] = 0; both calls below need such a context and EINVAL
+ * otherwise).  Fields are internal-layout F64 or F32 fields of the slab (EINVAL
+ * for F16); U is the slab's canonical FP64 links (the input of
+ * wdr_gauge_create, device memory).  A face buffer holds one t slice's half
+ * spinors, wdr_halo_bytes(ctx, prec) bytes: [6][F] complex of prec, F = L0
+ * L1 L2 sites in the order x0 + L0 (x1 + L1 x2), components h0 then h1 of
+ * the projected half spinor, colour fastest.
+ *   wdr_halo_pack: send_lo = (1 - g_t) psi on the slice t = 0, for the slab
+ *     below; send_hi = (1 + g_t) U_t^+ psi on the slice t = L3 - 1, for the
+ *     slab above (the link lives on this slab).
+ *   wdr_halo_unpack: out -= kappa [ sign_hi (1 - g_t) U_t(x) h on t = L3 - 1,
+ *     h = recv_hi (the send_lo of the slab above); sign_lo (1 + g_t) c on
+ *     t = 0, c = recv_lo (the send_hi of the slab below) ], the signs being
+ *     the boundary condition of links that cross the lattice's time boundary
+ *     (bc_t for the slabs at its two ends, else 1; 1 or -1, EINVAL otherwise).
+ * The exchange itself (send_lo to the slab below, send_hi to the slab
+ * above) is the caller's: one peer copy per face over xGMI.  Both calls
+ * queue one kernel on `stream` and allocate nothing. */
+int64_t wdr_halo_bytes(const wdr_ctx *ctx, wdr_prec prec);
+wdr_status wdr_halo_pack(wdr_ctx *ctx, const double *dev_U, wdr_prec prec, const void *dev_in, void *dev_send_lo,
+                         void *dev_send_hi, void *stream);
+wdr_status wdr_halo_unpack(wdr_ctx *ctx, const double *dev_U, double kappa, wdr_prec prec, const void *dev_recv_lo,
+                           const void *dev_recv_hi, int32_t sign_lo, int32_t sign_hi, void *dev_out, void *stream);
+
 /* out = D in on internal-layout fields of precision prec: exactly one
  * stencil kernel launch on `stream`, no conversion.  F16 (arithmetic in
  * FP32, output rounded with its own block scales) needs 4^4 blocks and an

@@ -301,6 +301,70 @@ int64_t wdr_field_bytes(const wdr_ctx *c, wdr_prec prec)
     return (int64_t)field_bytes(c, prec);
 }
 
+int64_t wdr_halo_bytes(const wdr_ctx *c, wdr_prec prec)
+{
+    if (!c || (prec != WDR_F64 && prec != WDR_F32)) return 0;
+    const int64_t F = (int64_t)c->g.L[0] * c->g.L[1] * c->g.L[2];
+    return 6 * F * (prec == WDR_F64 ? 16 : 8);
+}
+
+// shared checks of the halo calls: an open t boundary and F64 / F32
+static wdr_status halo_ok(wdr_ctx *c, const void *U, const void *a, const void *b, const void *f, wdr_prec prec)
+{
+    wdr_status e = pre(c, U, a);
+    if (e != WDR_OK) return e;
+    if (!b || !f) {
+        set_error("null field pointer");
+        return WDR_EINVAL;
+    }
+    if (c->g.bc[3] != 0) {
+        set_error("the halo calls need a context whose t boundary is open (bc[3] = 0): the slab of one GPU");
+        return WDR_EINVAL;
+    }
+    if (prec != WDR_F64 && prec != WDR_F32) {
+        set_error("the halo calls take F64 or F32 fields");
+        return WDR_EINVAL;
+    }
+    return WDR_OK;
+}
+
+wdr_status wdr_halo_pack(wdr_ctx *c, const double *U, wdr_prec prec, const void *in, void *send_lo, void *send_hi,
+                         void *stream)
+{
+    wdr_status e = halo_ok(c, U, in, send_lo, send_hi, prec);
+    if (e != WDR_OK) return e;
+    const double2 *u = reinterpret_cast<const double2 *>(U);
+    if (prec == WDR_F64)
+        launch_halo_pack<double>(c->g, u, static_cast<const double2 *>(in), static_cast<double2 *>(send_lo),
+                                 static_cast<double2 *>(send_hi), S(stream));
+    else
+        launch_halo_pack<float>(c->g, u, static_cast<const float2 *>(in), static_cast<float2 *>(send_lo),
+                                static_cast<float2 *>(send_hi), S(stream));
+    return finish(S(stream));
+}
+
+wdr_status wdr_halo_unpack(wdr_ctx *c, const double *U, double kappa, wdr_prec prec, const void *recv_lo,
+                           const void *recv_hi, int32_t sign_lo, int32_t sign_hi, void *out, void *stream)
+{
+    wdr_status e = halo_ok(c, U, recv_lo, recv_hi, out, prec);
+    if (e != WDR_OK) return e;
+    if ((e = check_kappa(kappa)) != WDR_OK) return e;
+    if ((sign_lo != 1 && sign_lo != -1) || (sign_hi != 1 && sign_hi != -1)) {
+        set_error("the boundary signs must be 1 or -1");
+        return WDR_EINVAL;
+    }
+    const double2 *u = reinterpret_cast<const double2 *>(U);
+    if (prec == WDR_F64)
+        launch_halo_unpack<double>(c->g, u, kappa, static_cast<const double2 *>(recv_lo),
+                                   static_cast<const double2 *>(recv_hi), (double)sign_lo, (double)sign_hi,
+                                   static_cast<double2 *>(out), S(stream));
+    else
+        launch_halo_unpack<float>(c->g, u, (float)kappa, static_cast<const float2 *>(recv_lo),
+                                  static_cast<const float2 *>(recv_hi), (float)sign_lo, (float)sign_hi,
+                                  static_cast<float2 *>(out), S(stream));
+    return finish(S(stream));
+}
+
 wdr_status wdr_pack(wdr_ctx *c, wdr_prec prec, const double *canon, void *internal, void *stream)
 {
     wdr_status e = pre(c, canon, internal);

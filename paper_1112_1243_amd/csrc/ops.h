@@ -132,6 +132,17 @@ bool launch_block_round16(const Geo &g, const Sys &sy, Links<double> U, H16c d, 
 // clover term (cg_steps_fit); returns the launch status (nothing ran unless
 // hipSuccess).
 bool cg_steps_fit(const Geo &g, bool su3, bool clover);
+
+// Halo of a slab cut along t (halo.hip): lo / hi receive the half spinors of
+// the first / last t slice that the slabs below / above need ([6][F]
+// complex, F = L0 L1 L2); unpack adds the hops across both faces from what
+// the neighbours sent, times slo / shi (the links' boundary sign).  U:
+// canonical FP64 links.
+template <typename T>
+void launch_halo_pack(const Geo &g, const double2 *U, const T2<T> *in, T2<T> *lo, T2<T> *hi, hipStream_t s);
+template <typename T>
+void launch_halo_unpack(const Geo &g, const double2 *U, T kappa, const T2<T> *lo, const T2<T> *hi, T slo, T shi,
+                        T2<T> *out, hipStream_t s);
 template <typename T>
 hipError_t launch_cg_steps(const Geo &g, const Sys &sy, Links<T> U, T kappa, int steps, T2<T> *p, T2<T> *t,
                            T2<T> *w, T2<T> *q, T2<T> *r, T2<T> *e, double2 *sc, double *part, double delta2,

@@ -113,6 +113,10 @@ def lib():
         L.wdr_noise.argtypes = [P, ctypes.c_int, ctypes.c_uint64, i32, i32, i32, P, P]
         L.wdr_field_bytes.argtypes = [P, ctypes.c_int]
         L.wdr_field_bytes.restype = ctypes.c_int64
+        L.wdr_halo_bytes.argtypes = [P, ctypes.c_int]
+        L.wdr_halo_bytes.restype = ctypes.c_int64
+        L.wdr_halo_pack.argtypes = [P, P, ctypes.c_int, P, P, P, P]
+        L.wdr_halo_unpack.argtypes = [P, P, d, ctypes.c_int, P, P, i32, i32, P, P]
         L.wdr_pack.argtypes = [P, ctypes.c_int, P, P, P]
         L.wdr_unpack.argtypes = [P, ctypes.c_int, P, P, P]
         L.wdr_apply_D_internal.argtypes = [P, P, d, ctypes.c_int, P, P, P]
@@ -358,6 +362,27 @@ class Context:
                                                ctypes.c_void_p(fin.data_ptr()),
                                                None if fdiag is None else ctypes.c_void_p(fdiag.data_ptr()),
                                                ctypes.c_void_p(fout.data_ptr()), _stream()))
+        return fout
+
+    # ---- halo of a slab cut along t (the context's t boundary open)
+    def halo_field(self, prec=F64):
+        """Flat byte tensor for one face buffer of half spinors."""
+        torch = _torch()
+        n = int(lib().wdr_halo_bytes(self.handle, prec))
+        return self._empty(n, dtype=torch.uint8)
+
+    def halo_pack(self, U, fin, send_lo, send_hi, prec=F64):
+        """send_lo = (1 - g_t) psi on t = 0, send_hi = (1 + g_t) U_t^+ psi on
+        the last t slice; U the canonical FP64 links of the slab."""
+        _check(lib().wdr_halo_pack(self.handle, _dev(U, (self.V, 4, 3, 3)), prec, ctypes.c_void_p(fin.data_ptr()),
+                                   ctypes.c_void_p(send_lo.data_ptr()), ctypes.c_void_p(send_hi.data_ptr()),
+                                   _stream()))
+
+    def halo_unpack(self, U, kappa, recv_lo, recv_hi, sign_lo, sign_hi, fout, prec=F64):
+        """fout -= kappa (hops across both t faces) from the neighbours' faces."""
+        _check(lib().wdr_halo_unpack(self.handle, _dev(U, (self.V, 4, 3, 3)), kappa, prec,
+                                     ctypes.c_void_p(recv_lo.data_ptr()), ctypes.c_void_p(recv_hi.data_ptr()),
+                                     int(sign_lo), int(sign_hi), ctypes.c_void_p(fout.data_ptr()), _stream()))
         return fout
 
     def apply_D_internal(self, gauge, kappa, fin, fout, prec=F64):
