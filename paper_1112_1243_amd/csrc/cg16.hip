@@ -420,36 +420,80 @@ __global__ __launch_bounds__(VH4) void k_eo16(Geo g, const int32_t *__restrict__
 }
 
 // one CG step on the FP16 vectors of system m, alpha = sc[8m].x / sc[8m+1].x:
-// x += alpha w (x FP32, the internal component-major layout, even sites),
-// r -= alpha q (FP16, fresh block scales), partial sums of |r|^2
+// x += alpha w (x FP32, the internal component-major layout, even sites;
+// XUPD = 0: x is left alone and alpha is stored in alpha[m] for a later
+// k_x16_flush), r -= alpha q (FP16, fresh block scales), partial sums of
+// |r|^2
+template <int XUPD>
 __global__ __launch_bounds__(VH4) void k_xr16(Geo g, const int32_t *__restrict__ active,
                                               const int32_t *__restrict__ list, const double2 *__restrict__ sc,
-                                              float2 *__restrict__ x, const uint4 *__restrict__ wv,
-                                              const float *__restrict__ ws, const uint4 *__restrict__ qv,
-                                              const float *__restrict__ qs, uint4 *__restrict__ rv,
-                                              float *__restrict__ rs, double *__restrict__ partial)
+                                              float2 *__restrict__ x, float *__restrict__ alpha,
+                                              const uint4 *__restrict__ wv, const float *__restrict__ ws,
+                                              const uint4 *__restrict__ qv, const float *__restrict__ qs,
+                                              uint4 *__restrict__ rv, float *__restrict__ rs,
+                                              double *__restrict__ partial)
 {
     const int m = sys_at(list, blockIdx.y);
     if (active && !active[m]) return;
     const int slot = blockIdx.x, t = threadIdx.x;
     const double ww = sc[8L * m + 1].x;
     const float a = (float)(ww > 0 ? sc[8L * m].x / ww : 0.0);
+    if (!XUPD && slot == 0 && t == 0) alpha[m] = a;
     const long blk = (long)m * g.nblk + slot, site = blk * VH4 + t;
-    cx<float> w[12], q[12], r[12];
-    ld_site(g4(wv), site, ws[blk], w);
+    cx<float> q[12], r[12];
     ld_site(g4(qv), site, qs[blk], q);
     ld_site(g4(rv), site, rs[blk], r);
-    float2 *xs = x + blk * 12 * VB4 + t;
+    if (XUPD) {
+        cx<float> w[12];
+        ld_site(g4(wv), site, ws[blk], w);
+        float2 *xs = x + blk * 12 * VB4 + t;
 #pragma unroll
-    for (int c = 0; c < 12; ++c) {
-        float2 xv = xs[c * VB4];
-        xv.x += a * w[c].re;
-        xv.y += a * w[c].im;
-        xs[c * VB4] = xv;
-        r[c] = r[c] - scale(a, q[c]);
+        for (int c = 0; c < 12; ++c) {
+            float2 xv = xs[c * VB4];
+            xv.x += a * w[c].re;
+            xv.y += a * w[c].im;
+            xs[c * VB4] = xv;
+        }
     }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) r[c] = r[c] - scale(a, q[c]);
     __syncthreads();  // every lane has read its r before the block's scale is rewritten
     store_block(r, rv, rs, site, blk, partial, blk);
+}
+
+// x += alpha_j w_j for the NK steps since the last flush, in step order and
+// with the rounding of the step-by-step update (x FP32 as in k_xr16; alpha_j
+// of system m at alpha[j * M + m], w_j in the E16 layout)
+struct W16Set {
+    const uint4 *v[4];
+    const float *s[4];
+};
+template <int NK>
+__global__ __launch_bounds__(VH4) void k_x16_flush(Geo g, const int32_t *__restrict__ active,
+                                                   const int32_t *__restrict__ list, const float *__restrict__ alpha,
+                                                   int M, W16Set w, float2 *__restrict__ x)
+{
+    const int m = sys_at(list, blockIdx.y);
+    if (active && !active[m]) return;
+    const int slot = blockIdx.x, t = threadIdx.x;
+    const long blk = (long)m * g.nblk + slot, site = blk * VH4 + t;
+    float2 *xs = x + blk * 12 * VB4 + t;
+    float2 xv[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) xv[c] = xs[c * VB4];
+#pragma unroll
+    for (int j = 0; j < NK; ++j) {
+        const float a = alpha[(long)j * M + m];
+        cx<float> wj[12];
+        ld_site(g4(w.v[j]), site, w.s[j][blk], wj);
+#pragma unroll
+        for (int c = 0; c < 12; ++c) {
+            xv[c].x += a * wj[c].re;
+            xv[c].y += a * wj[c].im;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 12; ++c) xs[c * VB4] = xv[c];
 }
 
 // p = r + beta p (beta = sc[8m + 4].x), or p = r with copy
@@ -629,11 +673,31 @@ void launch_e16_to64(const Geo &g, int M, int par, E16c in, double2 *out, hipStr
     k_e16_to64<<<dim3(g.nblk, M), VH4, 0, s>>>(g, par, in.v, in.s, out);
 }
 
-void launch_xr16(const Geo &g, const Sys &sy, const double2 *sc, float2 *x, E16c w, E16c q, E16 r, double *partial,
-                 hipStream_t s)
+void launch_xr16(const Geo &g, const Sys &sy, const double2 *sc, float2 *x, float *alpha, E16c w, E16c q, E16 r,
+                 double *partial, hipStream_t s)
 {
-    k_xr16<<<dim3(g.nblk, sy.launch_m()), VH4, 0, s>>>(g, sy.active, sy.list, sc, x, w.v, w.s, q.v, q.s, r.v, r.s,
-                                                        partial);
+    const dim3 gr(g.nblk, sy.launch_m());
+    if (x)
+        k_xr16<1><<<gr, VH4, 0, s>>>(g, sy.active, sy.list, sc, x, alpha, w.v, w.s, q.v, q.s, r.v, r.s, partial);
+    else
+        k_xr16<0><<<gr, VH4, 0, s>>>(g, sy.active, sy.list, sc, x, alpha, w.v, w.s, q.v, q.s, r.v, r.s, partial);
+}
+
+void launch_x16_flush(const Geo &g, const Sys &sy, const float *alpha, int M, const E16c *w, int nk, float2 *x,
+                      hipStream_t s)
+{
+    W16Set ws{};
+    for (int j = 0; j < nk && j < 4; ++j) {
+        ws.v[j] = w[j].v;
+        ws.s[j] = w[j].s;
+    }
+    const dim3 gr(g.nblk, sy.launch_m());
+    switch (nk) {
+    case 1: k_x16_flush<1><<<gr, VH4, 0, s>>>(g, sy.active, sy.list, alpha, M, ws, x); break;
+    case 2: k_x16_flush<2><<<gr, VH4, 0, s>>>(g, sy.active, sy.list, alpha, M, ws, x); break;
+    case 3: k_x16_flush<3><<<gr, VH4, 0, s>>>(g, sy.active, sy.list, alpha, M, ws, x); break;
+    default: k_x16_flush<4><<<gr, VH4, 0, s>>>(g, sy.active, sy.list, alpha, M, ws, x); break;
+    }
 }
 
 void launch_p16(const Geo &g, const Sys &sy, const double2 *sc, int copy, E16c r, E16 p, hipStream_t s)

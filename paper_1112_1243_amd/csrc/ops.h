@@ -304,9 +304,13 @@ void launch_pack_links_e16(const Geo &g, const double2 *u64, h2 *e16, hipStream_
 void launch_eo16(const Geo &g, const Sys &sy, Links16 U, float fs, float fk, int par, int dag, E16c in, E16c diag,
                  E16 out, double *partial, hipStream_t s);
 // x += alpha w (x FP32 internal layout, even sites), r -= alpha q, |r|^2 partials;
-// alpha = sc[8m].x / sc[8m + 1].x
-void launch_xr16(const Geo &g, const Sys &sy, const double2 *sc, float2 *x, E16c w, E16c q, E16 r, double *partial,
-                 hipStream_t s);
+// alpha = sc[8m].x / sc[8m + 1].x; x NULL: no x update, alpha stored in alpha[m]
+void launch_xr16(const Geo &g, const Sys &sy, const double2 *sc, float2 *x, float *alpha, E16c w, E16c q, E16 r,
+                 double *partial, hipStream_t s);
+// x += alpha_j w_j, j = 0 .. nk - 1 (nk <= 4) in step order: the x updates
+// that launch_xr16 with x = NULL deferred (alpha_j of system m at alpha[j M + m])
+void launch_x16_flush(const Geo &g, const Sys &sy, const float *alpha, int M, const E16c *w, int nk, float2 *x,
+                      hipStream_t s);
 // p = r + sc[8m + 4].x p, or p = r (copy)
 void launch_p16(const Geo &g, const Sys &sy, const double2 *sc, int copy, E16c r, E16 p, hipStream_t s);
 // r = bh - d (FP32 internal layout, even sites) into FP16, |r|^2 partials

@@ -877,6 +877,10 @@ constexpr double OUTER_DELTA = 1e-4;
 // 931 vs 980 ms per estimate (0.05: 961 ms)
 constexpr double RELIABLE_DELTA_F16 = 0.03;
 
+// the FP16 steps' x updates wait for up to this many steps and then run as
+// one pass over x (x is read and written once instead of once per step)
+constexpr int XDEFER = 4;
+
 // Even-odd CG on the normal equations with FP16 storage (4^4 blocks, SU(3)
 // links), the system and FP64 residual of cgne_eo.  Inner level: CG steps
 // on FP16 vectors (E16 layout, per-block scales) with the FP16 stencil and
@@ -899,6 +903,11 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     const bool three = sp.middle == WDR_F32;
     const long n = field_n(c), total = n * M;
     const size_t fb = field_bytes(c, WDR_F64) * M, f32 = field_bytes(c, WDR_F32) * M, fe = e16_field_bytes(g, M);
+    // the x updates of up to XDEFER steps wait for one pass over x (w of each
+    // of those steps kept, in its own buffer)
+    const int ue = sp.update_every, K = std::min(ue, XDEFER);
+    const size_t fes = (fe + 255) & ~(size_t)255;  // buffer stride, aligned for the 16 B loads
+    Work wx(c, fes * (K - 1) + 64), alw(c, sizeof(float) * XDEFER * M);
     Work bhw(c, fb), r64w(c, fb), t64w(c, fb), o64w(c, fb), x32w(c, f32), b32w(c, f32), d32w(c, f32), t32w(c, f32),
         pw(c, fe), ww(c, fe), qw(c, fe), rw(c, fe), tw(c, fe), scal(c, sizeof(double2) * 8 * M),
         red(c, sizeof(double) * std::max<long>(red_scratch(M), 2L * g.nblk * M)),
@@ -906,13 +915,19 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     FlagPoll poll(c, M);
     if (!bhw.ok() || !r64w.ok() || !t64w.ok() || !o64w.ok() || !x32w.ok() || !b32w.ok() || !d32w.ok() || !t32w.ok() ||
         !pw.ok() || !ww.ok() || !qw.ok() || !rw.ok() || !tw.ok() || !scal.ok() || !red.ok() || !ctl.ok() ||
-        !lw.ok() || !poll.ok)
+        !lw.ok() || !poll.ok || !wx.ok() || !alw.ok())
         return WDR_ENOMEM;
     double2 *bh = bhw.as<double2>(), *r64 = r64w.as<double2>(), *t64 = t64w.as<double2>(), *o64 = o64w.as<double2>();
     float2 *x32 = x32w.as<float2>(), *b32 = b32w.as<float2>(), *d32 = d32w.as<float2>(), *t32 = t32w.as<float2>();
-    const E16 P = e16_field(g, M, pw.as<void>()), W = e16_field(g, M, ww.as<void>()),
-              Q = e16_field(g, M, qw.as<void>()), R = e16_field(g, M, rw.as<void>()),
-              T = e16_field(g, M, tw.as<void>());
+    const E16 P = e16_field(g, M, pw.as<void>()), Q = e16_field(g, M, qw.as<void>()),
+              R = e16_field(g, M, rw.as<void>()), T = e16_field(g, M, tw.as<void>());
+    E16 Wk[XDEFER];
+    E16c Wc[XDEFER];
+    for (int j = 0; j < K; ++j) {
+        Wk[j] = e16_field(g, M, j == 0 ? ww.as<void>() : static_cast<void *>(wx.as<char>() + fes * (j - 1)));
+        Wc[j] = cref(Wk[j]);
+    }
+    float *alphas = alw.as<float>();
     double2 *sc = scal.as<double2>();
     double *part = red.as<double>();
     double *bn2 = ctl.as<double>(), *rmax = bn2 + M, *b32n2 = rmax + M, *rprev = b32n2 + M;
@@ -950,20 +965,23 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     k_c16_clear<<<nbm, 64, 0, s>>>(M, nmid);
     k_c16_clear<<<nbm, 64, 0, s>>>(M, nout);
     const E16c none{nullptr, nullptr};
-    const int ue = sp.update_every;
     auto period = [&](hipStream_t q) {
         for (int i = 0; i < ue; ++i) {
-            // w = Dhat^+ p (with |w|^2), q = Dhat w, x += alpha w, r -= alpha q, p = r + beta p
+            // w = Dhat^+ p (with |w|^2), q = Dhat w, r -= alpha q, p = r + beta p;
+            // x += alpha w for the last K steps at once (before the period's end)
+            const int j = i % K;
+            const E16 W = Wk[j];
             launch_eo16(g, sa, U16, -1.f, -kf, 1, 1, cref(P), none, T, nullptr, q);
             launch_eo16(g, sa, U16, 1.f, kf, 0, 1, cref(T), cref(P), W, part, q);
             launch_final(sa, part, G, sc + 1, 8, q);
             launch_eo16(g, sa, U16, -1.f, -kf, 1, 0, cref(W), none, T, nullptr, q);
             launch_eo16(g, sa, U16, 1.f, kf, 0, 0, cref(T), cref(W), Q, nullptr, q);
-            launch_xr16(g, sa, sc, x32, cref(W), cref(Q), R, part, q);
+            launch_xr16(g, sa, sc, nullptr, alphas + (long)j * M, cref(W), cref(Q), R, part, q);
             launch_final(sa, part, G, sc + 3, 8, q);
             k_cgm_beta<<<nbm, 64, 0, q>>>(M, sc, RELIABLE_DELTA_F16 * RELIABLE_DELTA_F16, sp.max_iter, alive, rmax,
                                           upd, its);
             launch_p16(g, sa, sc, 0, cref(R), P, q);
+            if (j == K - 1 || i == ue - 1) launch_x16_flush(g, sa, alphas, M, Wc, j + 1, x32, q);
         }
         if (three) {
             // middle: r = bh32 - Dhat x32 in FP32 for the flagged systems
@@ -1036,7 +1054,10 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     const double setup = 3 * V * spin_b<double>() + half_b<double>(V, true) + V * spin_b<double>() +
                          V * spin_b<float>() + H * spin_b<double>() + H * (spin_b<double>() + 2 * spin_b<float>() + 48) +
                          H * 96 + V * spin_b<double>() + half_b<double>(V, true) + 3 * V * spin_b<double>();
-    const double half16 = H * 96 + V * 96, step = 4 * half16 + 2 * H * 48 + H * 384 + H * 144;
+    // the x / r update (q in, r in and out) and the p update, then per step
+    // the share of the deferred x pass (w in, x32 in and out every K steps)
+    const double half16 = H * 96 + V * 96,
+                 step = 4 * half16 + 2 * H * 48 + H * 144 + H * 144 + H * (48 + 2 * spin_b<float>() / K);
     const double mid = half_b<float>(V, false) + half_b<float>(V, true) + H * (2 * spin_b<float>() + 48);
     const double outer = H * (spin_b<float>() + 2 * spin_b<double>()) + half_b<double>(V, false) +
                          half_b<double>(V, true) + 3 * H * spin_b<double>() +
