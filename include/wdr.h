@@ -249,7 +249,9 @@ int32_t wdr_gauge_is_su3(const wdr_gauge *g);
  * block solves then run as FP64 defect correction around an even-odd CGNE of
  * the block operator, not the block MR), and FULL, BLOCKS, SCHUR and DD
  * estimates by such solves (wdr_logdet_ratio / _batch; CGNE wherever D is
- * inverted; both fields of a ratio must carry the same csw).  Those calls
+ * inverted; both fields of a ratio must carry the same csw), and the exact
+ * block determinants (wdr_block_logdet / _ratio: det D_b = det A_oo det
+ * Dhat_b with Dhat_b = A_ee - kappa^2 H_eo A_oo^-1 H_oe).  Those calls
  * must pass this kappa (EINVAL
  * otherwise); every other call taking U returns EINVAL.  csw = 0 removes the
  * term.  EINVAL also for a context with open boundaries (bc = 0) and when a
@@ -485,7 +487,9 @@ wdr_status wdr_autotune(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *Up, d
  * device: the even-odd reduced normal matrix Dhat_b^+ Dhat_b (6 Vb rows,
  * det D_b = det Dhat_b) of each block is formed and Cholesky-factorised;
  * the result is 2 sum log L_ii.  Workspace: 16 (6 Vb rounded up to a
- * multiple of 64)^2 bytes per block matrix; the matrices are factorised in
+ * multiple of 64)^2 bytes per block matrix (with a clover term on U, see
+ * wdr_gauge_set_clover, the term enters Dhat_b and log det A_oo of the odd
+ * sites is added); the matrices are factorised in
  * passes of max_blocks (0: as many as fit in 8 GiB).  Returns after the
  * stream has finished.  EINVAL for blocks of more than 256 sites
  * or L/B odd in some direction; ENOCONV if a factorisation met a

@@ -612,12 +612,13 @@ def exact_log_ratio(lat: Lattice, U, Up, kappa: float, csw: float = 0.0) -> floa
     return 2.0 * (log_abs_det(D1) - log_abs_det(D0))
 
 
-def block_log_dets(lat: Lattice, U, kappa: float, blocks=None) -> np.ndarray:
+def block_log_dets(lat: Lattice, U, kappa: float, blocks=None, clov=None) -> np.ndarray:
     """log det(D_b^+ D_b) = 2 log|det D_b| of the Dirichlet operator of every
     block b (Sec. 3, eq. ddfactor: the block factors; eq. 4step: their ratios
     decide the first acceptance step), by dense LU of the 12 Vb x 12 Vb block
-    matrix.  Indexed by lexicographic block id; `blocks` restricts the work
-    to a subset (the other entries are NaN).
+    matrix; with clov (clover_term) the blocks carry the clover diagonal.
+    Indexed by lexicographic block id; `blocks` restricts the work to a
+    subset (the other entries are NaN).
 
     Dirichlet blocks do not couple, so a unit vector placed at the same
     in-block position of every block gives that column of every block
@@ -633,7 +634,7 @@ def block_log_dets(lat: Lattice, U, kappa: float, blocks=None) -> np.ndarray:
     for loc in range(Vb):
         for c in range(12):
             e[sites[:, loc], c] = 1.0
-            out = apply_Dblock(lat, U, kappa, e.reshape(lat.V, 4, 3), 2).reshape(lat.V, 12)
+            out = apply_Dblock(lat, U, kappa, e.reshape(lat.V, 4, 3), 2, clov).reshape(lat.V, 12)
             e[sites[:, loc], c] = 0.0
             for i, b in enumerate(blocks):
                 mats[i, :, 12 * loc + c] = out[sites[b]].reshape(-1)

@@ -55,7 +55,8 @@ wdr_status check_gauge(const wdr_ctx *c, const wdr_gauge *U, bool clover_ok = fa
         if (!clover_ok) {
             set_error("this call does not support a gauge field with a clover term (supported: D, D_b, the block "
                       "hops and D_ee in F64 / F32; CGNE solves, block solves and the Schur complement with F64 / "
-                      "F32 inner precision; FULL, BLOCKS, SCHUR and DD estimates by such solves)");
+                      "F32 inner precision; FULL, BLOCKS, SCHUR and DD estimates by such solves; exact block "
+                      "determinants)");
             return WDR_EINVAL;
         }
         if (kappa != U->ckappa) {
@@ -861,7 +862,9 @@ wdr_status wdr_block_logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gaug
 {
     if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
     wdr_status e;
-    if ((e = check_gauge(c, U)) != WDR_OK || (Up && (e = check_gauge(c, Up)) != WDR_OK)) return e;
+    if ((e = check_gauge(c, U, true, kappa)) != WDR_OK ||
+        (Up && ((e = check_gauge(c, Up, true, kappa)) != WDR_OK || (e = check_pair(U, Up)) != WDR_OK)))
+        return e;
     if ((e = check_kappa(kappa)) != WDR_OK) return e;
     if (!out || max_blocks < 0) {
         set_error("null output pointer or negative max_blocks");

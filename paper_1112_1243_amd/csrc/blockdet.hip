@@ -4,7 +4,10 @@
 // factorisation).
 //
 // With the even-odd reduction inside a Dirichlet block, det D_b = det Dhat_b,
-// Dhat_b = 1 - k^2 H_eo H_oe (in-block hops only), and the normal matrix
+// Dhat_b = 1 - k^2 H_eo H_oe (in-block hops only); with a clover term
+// det D_b = det A_oo det Dhat_b, Dhat_b = A_ee - k^2 H_eo A_oo^-1 H_oe, and
+// log det A_oo (the odd sites' 6 x 6 blocks) is added separately.  The
+// normal matrix
 //     A_b = Dhat_b^+ Dhat_b = g5 Dhat_b g5 Dhat_b        (n = 6 Vb rows)
 // is Hermitian positive definite, so
 //     log det(D_b^+ D_b) = log det A_b = 2 sum_i log L_ii,   A_b = L L^+.
@@ -30,6 +33,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "clover.h"
 #include "lds_stencil.h"
 #include "runtime.h"
 
@@ -51,14 +55,33 @@ __device__ __forceinline__ void unpack_coords(uint32_t v, int x[4])
     x[3] = v >> 24;
 }
 
+// A or A^-1 (inv) of the clover field C at site (slot, l) times the 12
+// components v, in place
+__device__ __forceinline__ void clov_apply(const double *C, long V, int inv, int slot, int Vb, int l,
+                                           spinor<double> &v)
+{
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi) {
+        cx<double> x[6], y[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) x[i] = v.s[(6 * chi + i) / 3].c[(6 * chi + i) % 3];
+        clov_mul6<double>(clov_at<double>(C, V, inv, slot, chi, Vb, l), Vb, x, y);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v.s[(6 * chi + i) / 3].c[(6 * chi + i) % 3] = y[i];
+    }
+}
+
 // Matrix q of a launch is (field q / nblk, slot q % nblk) with global index
-// q0 + blockIdx.y; its rows start at A + blockIdx.y * np * np.
+// q0 + blockIdx.y; its rows start at A + blockIdx.y * np * np.  C0 / C1:
+// the fields' clover terms (A, then A^-1; NULL without one).
 __global__ __launch_bounds__(256) void k_normal(Geo g, const double2 *__restrict__ U0, const double2 *__restrict__ U1,
+                                                const double *__restrict__ C0, const double *__restrict__ C1,
                                                 int q0, int cols, double kappa, long np, double2 *__restrict__ A)
 {
     __shared__ double2 she[12 * MAX_VH], sho[12 * MAX_VH];
     const int q = q0 + blockIdx.y, slot = q % g.nblk;
     const double2 *U = q / g.nblk ? U1 : U0;
+    const double *C = q / g.nblk ? C1 : C0;
     double2 *Aq = A + (long)blockIdx.y * np * np;
     const int Vh = g.Vh, n = 6 * g.Vb, l = threadIdx.x;
     const bool even = l < Vh;
@@ -83,7 +106,10 @@ __global__ __launch_bounds__(256) void k_normal(Geo g, const double2 *__restrict
             const bool odd_stage = stage & 1;
             if (odd_stage && !even) {
                 zero(acc);
-                if (dist <= stage) hop_sum<double, HOPS_IN>(g, U, slot, l, x, from_e, acc);
+                if (dist <= stage) {
+                    hop_sum<double, HOPS_IN>(g, U, slot, l, x, from_e, acc);
+                    if (C) clov_apply(C, g.V, 1, slot, g.Vb, l, acc);  // A_oo^-1 H_oe
+                }
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -91,12 +117,17 @@ __global__ __launch_bounds__(256) void k_normal(Geo g, const double2 *__restrict
             } else if (!odd_stage && even) {
                 zero(acc);
                 if (dist <= stage) hop_sum<double, HOPS_IN>(g, U, slot, l, x, from_o, acc);
+                // the diagonal term: the input, or A_ee times it (the input
+                // reaches distance 0 at stage 2, 2 at stage 4)
+                spinor<double> dg;
+                LdsLoader<double>{she, Vh, 0}(0, l, dg);
+                if (C && dist <= stage - 2) clov_apply(C, g.V, 0, slot, g.Vb, l, dg);
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         const long i = (long)(3 * sp + a) * Vh + l;
-                        cx<double> v = ld<double>(she, i) - scale(k2, acc.s[sp].c[a]);
+                        cx<double> v = dg.s[sp].c[a] - scale(k2, acc.s[sp].c[a]);
                         if (sp >= 2) v = neg(v);
                         if (stage == 2) {
                             st<double>(she, i, v);
@@ -199,6 +230,49 @@ __global__ __launch_bounds__(Cube<B>::Vb) void k_normal_cube(int nblk, const dou
             __syncthreads();
         }
     }
+}
+
+// out[f * nblk + slot] = sum over the block's odd sites of log |det A(x)|
+// (both 6 x 6 blocks), field f = blockIdx.y (C0, C1); elimination without
+// pivoting on the Hermitian block (its pivots are real)
+__global__ __launch_bounds__(256) void k_clover_logdet_odd(Geo g, const double *__restrict__ C0,
+                                                           const double *__restrict__ C1, double *__restrict__ out)
+{
+    __shared__ double red[4];
+    const int slot = blockIdx.x, f = blockIdx.y;
+    const double *C = f ? C1 : C0;
+    double s = 0;
+    for (int i = threadIdx.x; i < 2 * g.Vh; i += 256) {
+        const int l = g.Vh + i / 2, chi = i % 2;
+        const auto *p = clov_at<double>(C, (long)g.V, 0, slot, chi, g.Vb, l);
+        cx<double> a[6][6];
+#pragma unroll
+        for (int r = 0; r < 6; ++r) a[r][r] = mk<double>(p[(long)r * g.Vb], 0.0);
+#pragma unroll
+        for (int r = 0; r < 6; ++r)
+#pragma unroll
+            for (int c = r + 1; c < 6; ++c) {
+                const int k = herm_k(r, c);
+                a[r][c] = mk<double>(p[(long)(6 + 2 * k) * g.Vb], p[(long)(7 + 2 * k) * g.Vb]);
+                a[c][r] = mk<double>(a[r][c].re, -a[r][c].im);
+            }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double d = a[k][k].re;
+            s += log(fabs(d));
+#pragma unroll
+            for (int r = k + 1; r < 6; ++r) {
+                const cx<double> m = scale(1.0 / d, a[r][k]);
+#pragma unroll
+                for (int c = k + 1; c < 6; ++c) a[r][c] = a[r][c] - m * a[k][c];
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[(long)f * g.nblk + slot] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // rows n .. np-1 of every matrix: the identity
@@ -474,14 +548,17 @@ wdr_status block_logdet(wdr_ctx *c, const wdr_gauge *U0, const wdr_gauge *U1, do
     const int cols = (int)std::max<long>(12, (n * per_pass + 2047) / 2048);
     const int ncg = (int)((n + cols - 1) / cols);
     // SU(3) links of 4^4 blocks: links in LDS, compile-time geometry
-    const bool cube4 = g.B[0] == 4 && g.B[1] == 4 && g.B[2] == 4 && g.B[3] == 4 && U0->su3 && (!U1 || U1->su3);
+    // (the clover operator takes the general form)
+    const bool clov = U0->c64 != nullptr;
+    const bool cube4 = g.B[0] == 4 && g.B[1] == 4 && g.B[2] == 4 && g.B[3] == 4 && U0->su3 && (!U1 || U1->su3) && !clov;
+    const double *C0 = U0->c64, *C1 = U1 ? U1->c64 : U0->c64;
     for (int q0 = 0; q0 < nm; q0 += per_pass) {
         const int m = std::min(per_pass, nm - q0);
         if (cube4)
             k_normal_cube<4><<<dim3(ncg, m), 256, 0, s>>>(g.nblk, U0->u64, U1 ? U1->u64 : U0->u64, q0, cols, kappa,
                                                           np, A);
         else
-            k_normal<<<dim3(ncg, m), g.Vb, 0, s>>>(g, U0->u64, U1 ? U1->u64 : U0->u64, q0, cols, kappa, np, A);
+            k_normal<<<dim3(ncg, m), g.Vb, 0, s>>>(g, U0->u64, U1 ? U1->u64 : U0->u64, C0, C1, q0, cols, kappa, np, A);
         if (np > n) k_pad<<<dim3((unsigned)std::min<long>(64, ((np - n) * np + 255) / 256), m), 256, 0, s>>>(n, np, A);
         // panels in groups of GROUP: each panel updates only the rest of its
         // group; the tiles right of the group get one update per group
@@ -503,8 +580,15 @@ wdr_status block_logdet(wdr_ctx *c, const wdr_gauge *U0, const wdr_gauge *U1, do
         }
     }
     WDR_HIP(hipGetLastError());
-    std::vector<double> hl(nm);
+    std::vector<double> hl(nm), hc(nm, 0.0);
     std::vector<int32_t> hb(nm);
+    if (clov) {  // log |det A_oo| per block: det D_b = det A_oo det Dhat_b
+        Work cw(c, sizeof(double) * nm);
+        if (!cw.ok()) return WDR_ENOMEM;
+        k_clover_logdet_odd<<<dim3(g.nblk, nf), 256, 0, s>>>(g, C0, C1, cw.as<double>());
+        WDR_HIP(hipMemcpyAsync(hc.data(), cw.as<double>(), sizeof(double) * nm, hipMemcpyDeviceToHost, s));
+        WDR_HIP(hipStreamSynchronize(s));
+    }
     WDR_HIP(hipMemcpyAsync(hl.data(), ld, sizeof(double) * nm, hipMemcpyDeviceToHost, s));
     WDR_HIP(hipMemcpyAsync(hb.data(), bad, sizeof(int32_t) * nm, hipMemcpyDeviceToHost, s));
     WDR_HIP(hipStreamSynchronize(s));
@@ -512,7 +596,7 @@ wdr_status block_logdet(wdr_ctx *c, const wdr_gauge *U0, const wdr_gauge *U1, do
     for (int f = 0; f < nf; ++f)
         for (int b = 0; b < g.nblk; ++b) {
             const int q = f * g.nblk + c->slot_of_block[b];
-            out[f * g.nblk + b] = hb[q] ? NAN : hl[q];
+            out[f * g.nblk + b] = hb[q] ? NAN : hl[q] + 2.0 * hc[q];
             nbad += hb[q] != 0;
         }
     if (nbad) {

@@ -258,6 +258,32 @@ def test_clover_dd_samples():
     ctx.close()
 
 
+@pytest.mark.parametrize("L,B,blocks", [((4, 4, 8, 8), (2, 2, 4, 4), None), ((8, 8, 8, 8), (4, 4, 4, 4), [0, 9])])
+def test_clover_block_logdet(L, B, blocks):
+    """Exact block determinants with the clover term (det D_b = det A_oo
+    det Dhat_b, Dhat_b = A_ee - kappa^2 H_eo A_oo^-1 H_oe) within 1e-8 of the
+    oracle's dense LU of each block, and the ratios between two clover
+    fields; on the 8^4 lattice of 4^4 blocks two blocks are checked."""
+    wdr, lat, ctx, U = _setup(L, B, 0.6, 522)
+    kappa = 0.14
+    Up = synth.redraw(U, synth.bernoulli_links(lat.L, 0.1, 523), 0.6, 523)
+    T, Tp = oracle.clover_term(lat, U, CSW, kappa), oracle.clover_term(lat, Up, CSW, kappa)
+    gU, gUp = ctx.gauge(dev(U), CSW, kappa), ctx.gauge(dev(Up), CSW, kappa)
+    idx = np.arange(lat.nblocks) if blocks is None else np.asarray(blocks)
+    got = ctx.block_logdet(gU, kappa)
+    want = oracle.block_log_dets(lat, U, kappa, blocks=idx, clov=T)
+    e = np.abs(got[idx] - want[idx]).max()
+    ratio = ctx.block_logdet_ratio(gU, gUp, kappa)
+    want_r = oracle.block_log_dets(lat, Up, kappa, blocks=idx, clov=Tp) - want
+    er = np.abs(ratio[idx] - want_r[idx]).max()
+    say("clover block logdet", L, B, "max |d|", e, "ratio", er, "range", want[idx].min(), want[idx].max())
+    assert e < 1e-8 and er < 1e-8 and np.abs(want_r[idx]).max() > 1e-3
+    plain = ctx.gauge(dev(U))
+    assert np.abs(ctx.block_logdet(plain, kappa)[idx] - got[idx]).max() > 1e-2
+    del gU, gUp, plain
+    ctx.close()
+
+
 def test_clover_16x16x16x16_operator_and_solve():
     """16^4 (256 blocks of 4^4): D with the clover term against the oracle on
     both stencil forms, and a CGNE solve whose true residual the oracle's
@@ -306,7 +332,8 @@ def test_clover_error_paths():
     refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_BLOCKS, 1, 1, 1, 1, wdr.default_params(inner=2)))
     refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_DD, 1, 1, 1, 1, wdr.default_params(solver=0)))
     refused(lambda: ctx.logdet_ratio(gU, gP, kappa, wdr.OP_FULL, 1, 1, 1, 1, wdr.default_params(solver=1)))
-    refused(lambda: ctx.block_logdet(gU, kappa))
+    refused(lambda: ctx.block_logdet(gU, 0.13))                           # another kappa
+    refused(lambda: ctx.block_logdet_ratio(gU, gP, kappa))                 # csw differs
     refused(lambda: ctx.clover_field(gP))
     # removing the term gives back the plain operator
     ctx.set_clover(gU, 0.0, 0.0)

@@ -220,3 +220,25 @@ def test_clover_exact_log_ratio(clover_case):
     lat, U, Up, k, csw, D0, D1 = clover_case
     want = 2 * (oracle.log_abs_det(D1) - oracle.log_abs_det(D0))
     assert abs(oracle.exact_log_ratio(lat, U, Up, k, csw) - want) < 1e-9
+
+
+def test_clover_block_dets_are_diagonal_blocks_of_D():
+    """With the clover term each block entry is 2 log|det| of the block's
+    diagonal slice of the full clover D (assembled by apply_D: its clover
+    diagonal and in-block hops, not the block code), and the entries add up
+    to log det of D_bb + D_ww, the block-diagonal part of eq. domdec."""
+    lat = oracle.Lattice((4, 4, 4, 4), B=(2, 2, 2, 2))
+    U = synth.gauge_field(lat.L, 0.5, 47)
+    k, csw = 0.13, 1.7
+    T = oracle.clover_term(lat, U, csw, k)
+    bid, _, _ = lat.maps()
+    got = oracle.block_log_dets(lat, U, k, clov=T)
+    D = oracle.dense(lambda v: oracle.apply_D(lat, U, k, v, T), lat.V)
+    Dblk = np.zeros_like(D)
+    for b in range(lat.nblocks):
+        idx = oracle.site_dofs(bid == b)
+        Dblk[np.ix_(idx, idx)] = D[np.ix_(idx, idx)]
+        assert abs(got[b] - 2 * oracle.log_abs_det(D[np.ix_(idx, idx)])) < 1e-11
+    assert abs(got.sum() - 2 * oracle.log_abs_det(Dblk)) < 1e-9
+    # the term matters
+    assert np.abs(got - oracle.block_log_dets(lat, U, k)).max() > 1e-2
