@@ -86,7 +86,7 @@ def lib():
         L.oracle_mul_g5.argtypes = [ctypes.c_long, P, P]
         L.oracle_cgne.argtypes = [P, P, P, d, P, P, i, i, P, P, P, d, i, P]
         L.oracle_cgne.restype = i
-        L.oracle_sap.argtypes = [P, P, P, d, P, i, i, P, P]
+        L.oracle_sap.argtypes = [P, P, P, d, P, P, i, i, P, P]
         L.oracle_philox4x64_10.argtypes = [P, P, P]
         L.oracle_noise.argtypes = [P, i, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, P, P]
         _lib = L
@@ -385,13 +385,15 @@ def solve(lat: Lattice, U, kappa: float, b, op: str = "full", colour: int = 2, t
     return x, y, it, res.value
 
 
-def sap(lat: Lattice, U, kappa: float, eta, ncy: int, nmr: int) -> np.ndarray:
+def sap(lat: Lattice, U, kappa: float, eta, ncy: int, nmr: int, clov=None) -> np.ndarray:
     """Schwarz alternating procedure with ncy cycles and nmr even-odd MR
-    steps per block (Luscher hep-lat/0310048, cited in Secs. 1 and 3)."""
+    steps per block (Luscher hep-lat/0310048, cited in Secs. 1 and 3); with
+    clov (clover_term) the block systems carry the clover diagonal."""
     U, eta = _c(U), _c(eta)
+    clov = None if clov is None else _c(clov)
     x = np.empty_like(eta)
     L, B, bc = lat.arrays()
-    lib().oracle_sap(_p(L), _p(B), _p(bc), kappa, _p(U), ncy, nmr, _p(eta), _p(x))
+    lib().oracle_sap(_p(L), _p(B), _p(bc), kappa, _p(U), _pc(clov), ncy, nmr, _p(eta), _p(x))
     return x
 
 

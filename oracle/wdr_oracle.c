@@ -419,24 +419,78 @@ done_ok:
  *           for D_b delta_b = r_b, on the even-odd reduced block system
  *       x += delta
  *
- * Minimal residual on the reduced block system (D_b = 1 - kappa H_b):
- *   rhs_e = r_e + kappa H_eo r_o
- *   d_e = 0, rho = rhs_e; nmr times: p = (1 - kappa^2 H_eo H_oe) rho,
+ * Minimal residual on the reduced block system (D_b = A - kappa H_b, A = 1
+ * without a clover term, A = 1 + T with one):
+ *   rhs_e = r_e + kappa H_eo A_oo^-1 r_o
+ *   d_e = 0, rho = rhs_e; nmr times: p = (A_ee - kappa^2 H_eo A_oo^-1 H_oe) rho,
  *       alpha_b = <p, rho>_b / <p, p>_b, d_e += alpha_b rho, rho -= alpha_b p
- *   d_o = r_o + kappa H_oe d_e
+ *   d_o = A_oo^-1 (r_o + kappa H_oe d_e)
  * where H are the in-block (Dirichlet) hops and <.,.>_b sums over block b.
  */
-static void mr_blocks_eo(const geom_t *g, double kappa, const cplx *U, int colour, int nmr, const cplx *r,
-                         cplx *d, const int32_t *blk, long nblk)
+
+/* (1 + T(x))^-1 of every site (144 complex each), by Gauss-Jordan
+ * elimination with partial pivoting on [A | 1] */
+static cplx *clover_inverse(const geom_t *g, const cplx *clov)
+{
+    cplx *inv = malloc(144 * g->V * sizeof(cplx));
+    for (long s = 0; s < g->V; ++s) {
+        cplx a[12][24];
+        for (int i = 0; i < 12; ++i)
+            for (int j = 0; j < 24; ++j)
+                a[i][j] = j < 12 ? clov[144 * s + 12 * i + j] + (i == j ? 1.0 : 0.0) : (j - 12 == i ? 1.0 : 0.0);
+        for (int k = 0; k < 12; ++k) {
+            int piv = k;
+            for (int i = k + 1; i < 12; ++i)
+                if (cabs(a[i][k]) > cabs(a[piv][k])) piv = i;
+            for (int j = 0; j < 24; ++j) {
+                cplx tmp = a[k][j];
+                a[k][j] = a[piv][j];
+                a[piv][j] = tmp;
+            }
+            cplx f = 1.0 / a[k][k];
+            for (int j = 0; j < 24; ++j) a[k][j] *= f;
+            for (int i = 0; i < 12; ++i) {
+                if (i == k) continue;
+                cplx m = a[i][k];
+                for (int j = 0; j < 24; ++j) a[i][j] -= m * a[k][j];
+            }
+        }
+        for (int i = 0; i < 12; ++i)
+            for (int j = 0; j < 12; ++j) inv[144 * s + 12 * i + j] = a[i][12 + j];
+    }
+    return inv;
+}
+
+/* v <- M(x) v on the sites of this colour and parity, M per site (144 complex) */
+static void site_mul(const geom_t *g, const cplx *M, cplx *v, int colour, int par)
+{
+    for (long s = 0; s < g->V; ++s) {
+        int x[4];
+        coords(g, s, x);
+        if (colour_of(g, x) != colour || parity_of(x) != par) continue;
+        cplx w[12];
+        for (int i = 0; i < 12; ++i) {
+            w[i] = 0;
+            for (int j = 0; j < 12; ++j) w[i] += M[144 * s + 12 * i + j] * v[12 * s + j];
+        }
+        for (int i = 0; i < 12; ++i) v[12 * s + i] = w[i];
+    }
+}
+
+static void mr_blocks_eo(const geom_t *g, double kappa, const cplx *U, const cplx *clov, const cplx *Ainv,
+                         int colour, int nmr, const cplx *r, cplx *d, const int32_t *blk, long nblk)
 {
     long n = 12 * g->V;
+    if (n <= 0) return;
     cplx *rhs = calloc(n, sizeof(cplx)), *rho = calloc(n, sizeof(cplx)), *p = calloc(n, sizeof(cplx));
-    cplx *t = calloc(n, sizeof(cplx)), *u = calloc(n, sizeof(cplx));
+    cplx *t = calloc(n, sizeof(cplx)), *u = calloc(n, sizeof(cplx)), *w = calloc(n, sizeof(cplx));
     cplx *num = calloc(nblk, sizeof(cplx));
     double *den = calloc(nblk, sizeof(double));
 
-    /* t = -kappa H_eo r_o (in-block), rhs_e = r_e - t */
-    wilson_generic(g, kappa, U, NULL, r, t, 0, HOPS_IN_BLOCK, colour, -1, 0, 1);
+    /* w = A_oo^-1 r_o, t = -kappa H_eo w (in-block), rhs_e = r_e - t */
+    for (long i = 0; i < n; ++i) w[i] = r[i];
+    if (clov) site_mul(g, Ainv, w, colour, 1);
+    wilson_generic(g, kappa, U, NULL, w, t, 0, HOPS_IN_BLOCK, colour, -1, 0, 1);
     for (long s = 0; s < g->V; ++s) {
         int x[4];
         coords(g, s, x);
@@ -448,10 +502,15 @@ static void mr_blocks_eo(const geom_t *g, double kappa, const cplx *U, int colou
         }
     }
     for (int k = 0; k < nmr; ++k) {
-        /* p = rho - kappa^2 H_eo H_oe rho (in-block) */
+        /* p = A_ee rho - kappa^2 H_eo A_oo^-1 H_oe rho (in-block) */
         wilson_generic(g, kappa, U, NULL, rho, t, 0, HOPS_IN_BLOCK, colour, -1, 1, 0);
+        if (clov) site_mul(g, Ainv, t, colour, 1);
         wilson_generic(g, kappa, U, NULL, t, u, 0, HOPS_IN_BLOCK, colour, -1, 0, 1);
         for (long i = 0; i < n; ++i) p[i] = rho[i] - u[i];
+        if (clov)  /* + T rho on the even sites of the colour (rho vanishes elsewhere) */
+            for (long s = 0; s < g->V; ++s)
+                for (int i = 0; i < 12; ++i)
+                    for (int j = 0; j < 12; ++j) p[12 * s + i] += clov[144 * s + 12 * i + j] * rho[12 * s + j];
         for (long b = 0; b < nblk; ++b) num[b] = 0, den[b] = 0;
         for (long s = 0; s < g->V; ++s)
             for (int a = 0; a < 12; ++a) {
@@ -466,7 +525,7 @@ static void mr_blocks_eo(const geom_t *g, double kappa, const cplx *U, int colou
             }
         }
     }
-    /* d_o = r_o + kappa H_oe d_e = r_o - t, t = -kappa H_oe d_e (in-block) */
+    /* d_o = A_oo^-1 (r_o + kappa H_oe d_e) = A_oo^-1 (r_o - t), t = -kappa H_oe d_e (in-block) */
     wilson_generic(g, kappa, U, NULL, d, t, 0, HOPS_IN_BLOCK, colour, -1, 1, 0);
     for (long s = 0; s < g->V; ++s) {
         int x[4];
@@ -474,6 +533,8 @@ static void mr_blocks_eo(const geom_t *g, double kappa, const cplx *U, int colou
         if (colour_of(g, x) == colour && parity_of(x) == 1)
             for (int a = 0; a < 12; ++a) d[12 * s + a] = r[12 * s + a] - t[12 * s + a];
     }
+    if (clov) site_mul(g, Ainv, d, colour, 1);
+    free(w);
     free(rhs);
     free(rho);
     free(p);
@@ -483,11 +544,13 @@ static void mr_blocks_eo(const geom_t *g, double kappa, const cplx *U, int colou
     free(den);
 }
 
-void oracle_sap(const int *L, const int *B, const int *bc, double kappa, const double *Ud, int ncy, int nmr,
-                const double *etad, double *xd)
+void oracle_sap(const int *L, const int *B, const int *bc, double kappa, const double *Ud, const double *clovd,
+                int ncy, int nmr, const double *etad, double *xd)
 {
     geom_t g = make_geom(L, B, bc);
     const cplx *U = (const cplx *)Ud;
+    const cplx *clov = (const cplx *)clovd;
+    cplx *Ainv = clov ? clover_inverse(&g, clov) : NULL;
     const cplx *eta = (const cplx *)etad;
     cplx *x = (cplx *)xd;
     long n = 12 * g.V;
@@ -505,10 +568,10 @@ void oracle_sap(const int *L, const int *B, const int *bc, double kappa, const d
     for (long i = 0; i < n; ++i) x[i] = 0;
     for (int cy = 0; cy < ncy; ++cy)
         for (int c = 0; c < 2; ++c) {
-            wilson_generic(&g, kappa, U, NULL, x, Dx, 1, HOPS_ALL, -1, -1, -1, -1);
+            wilson_generic(&g, kappa, U, clov, x, Dx, 1, HOPS_ALL, -1, -1, -1, -1);
             for (long s = 0; s < g.V; ++s)
                 for (int a = 0; a < 12; ++a) r[12 * s + a] = col[s] == c ? eta[12 * s + a] - Dx[12 * s + a] : 0;
-            mr_blocks_eo(&g, kappa, U, c, nmr, r, d, blk, nblk);
+            mr_blocks_eo(&g, kappa, U, clov, Ainv, c, nmr, r, d, blk, nblk);
             for (long i = 0; i < n; ++i) x[i] += d[i];
         }
     free(blk);
@@ -516,6 +579,7 @@ void oracle_sap(const int *L, const int *B, const int *bc, double kappa, const d
     free(Dx);
     free(r);
     free(d);
+    free(Ainv);
 }
 
 /* ------------------------------------------------------------------ */

@@ -20,8 +20,8 @@ void oracle_apply_Dee(const int *L, const int *B, const int *bc, double kappa, c
 void oracle_mul_g5(long V, const double *in, double *out);
 int oracle_cgne(const int *L, const int *B, const int *bc, double kappa, const double *Ud, const double *clov, int op,
                 int colour, const double *bd, double *xd, double *yd, double tol, int maxit, double *rel_resid);
-void oracle_sap(const int *L, const int *B, const int *bc, double kappa, const double *Ud, int ncy, int nmr,
-                const double *etad, double *xd);
+void oracle_sap(const int *L, const int *B, const int *bc, double kappa, const double *Ud, const double *clovd,
+                int ncy, int nmr, const double *etad, double *xd);
 void oracle_philox4x64_10(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4]);
 void oracle_noise(const int *L, int kind, uint64_t seed, int32_t step, int32_t k, const uint8_t *mask, double *out);
 
@@ -66,7 +66,8 @@ static int run(const int L[4], const int B[4], const int bc[4])
     /* memory safety only: a random (non-hermitian) clover matrix may converge slowly */
     int it2 = oracle_cgne(L, B, bc, 0.1, U, clov, 1, 0, in, x, y, 1e-10, 200, &res);
     int it3 = oracle_cgne(L, B, bc, 0.1, U, NULL, 0, 2, in, x, y, 1e-10, 1, &res); /* iteration cap */
-    oracle_sap(L, B, bc, 0.1, U, 2, 3, in, x);
+    oracle_sap(L, B, bc, 0.1, U, NULL, 2, 3, in, x);
+    oracle_sap(L, B, bc, 0.1, U, clov, 2, 3, in, x);
     uint64_t ctr[4] = {1, 2, 3, 4}, key[2] = {5, 6}, o[4];
     oracle_philox4x64_10(ctr, key, o);
     for (long i = 0; i < V; ++i) mask[i] = (uint8_t)(i & 1);

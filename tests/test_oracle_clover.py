@@ -242,3 +242,54 @@ def test_clover_block_dets_are_diagonal_blocks_of_D():
     assert abs(got.sum() - 2 * oracle.log_abs_det(Dblk)) < 1e-9
     # the term matters
     assert np.abs(got - oracle.block_log_dets(lat, U, k)).max() > 1e-2
+
+
+def _schwarz_clover(lat, U, k, T, eta, ncy):
+    """Multiplicative Schwarz with exact block solves of the clover D: per
+    colour c, x <- x + K_c (eta - D x), K_c = sum_{b in c} P_b D_b^-1 P_b."""
+    bid, col, _ = lat.maps()
+    D = oracle.dense(lambda v: oracle.apply_D(lat, U, k, v, T), lat.V)
+    n = 12 * lat.V
+    K = [np.zeros((n, n), complex), np.zeros((n, n), complex)]
+    for b in range(lat.nblocks):
+        idx = oracle.site_dofs(bid == b)
+        c = col[idx[0] // 12]
+        K[c][np.ix_(idx, idx)] = np.linalg.inv(D[np.ix_(idx, idx)])
+    x = np.zeros(n, complex)
+    e = eta.reshape(-1)
+    for _ in range(ncy):
+        for c in (0, 1):
+            x = x + K[c] @ (e - D @ x)
+    return x.reshape(eta.shape)
+
+
+def test_clover_sap_exact_block_limit():
+    """With the clover term, many MR steps solve every block exactly: SAP
+    equals multiplicative Schwarz with dense inverses of the clover D's
+    diagonal blocks."""
+    lat = oracle.Lattice((4, 4, 4, 4), B=(2, 2, 2, 2))
+    U = synth.gauge_field(lat.L, 0.5, 49)
+    k = 0.11
+    T = oracle.clover_term(lat, U, 1.7, k)
+    eta = synth.spinor(lat.L, 50)
+    x = oracle.sap(lat, U, k, eta, ncy=3, nmr=80, clov=T)
+    want = _schwarz_clover(lat, U, k, T, eta, 3)
+    assert np.abs(x - want).max() < 1e-10 * np.abs(want).max()
+    assert np.abs(x - oracle.sap(lat, U, k, eta, ncy=3, nmr=80)).max() > 1e-3 * np.abs(want).max()
+
+
+def test_clover_sap_odd_equations_exact():
+    """The even-odd block solve with the clover term reconstructs the odd
+    sites exactly (d_o = A_oo^-1 (r_o + kappa H_oe d_e)): after the last
+    (white) half-cycle the clover residual vanishes on the odd white sites."""
+    lat = oracle.Lattice((8, 8, 4, 4), B=(4, 4, 2, 2))
+    U = synth.gauge_field(lat.L, 0.5, 51)
+    k = 0.13
+    T = oracle.clover_term(lat, U, 1.7, k)
+    eta = synth.spinor(lat.L, 52)
+    x = oracle.sap(lat, U, k, eta, ncy=2, nmr=3, clov=T)
+    r = eta - oracle.apply_D(lat, U, k, x, T)
+    _, col, par = lat.maps()
+    odd_white = (col == 1) & (par == 1)
+    assert np.abs(r[odd_white]).max() < 1e-13
+    assert np.abs(r[~odd_white]).max() > 1e-3
