@@ -55,22 +55,6 @@ __device__ __forceinline__ void unpack_coords(uint32_t v, int x[4])
     x[3] = v >> 24;
 }
 
-// A or A^-1 (inv) of the clover field C at site (slot, l) times the 12
-// components v, in place
-__device__ __forceinline__ void clov_apply(const double *C, long V, int inv, int slot, int Vb, int l,
-                                           spinor<double> &v)
-{
-#pragma unroll
-    for (int chi = 0; chi < 2; ++chi) {
-        cx<double> x[6], y[6];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) x[i] = v.s[(6 * chi + i) / 3].c[(6 * chi + i) % 3];
-        clov_mul6<double>(clov_at<double>(C, V, inv, slot, chi, Vb, l), Vb, x, y);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) v.s[(6 * chi + i) / 3].c[(6 * chi + i) % 3] = y[i];
-    }
-}
-
 // Matrix q of a launch is (field q / nblk, slot q % nblk) with global index
 // q0 + blockIdx.y; its rows start at A + blockIdx.y * np * np.  C0 / C1:
 // the fields' clover terms (A, then A^-1; NULL without one).
@@ -108,7 +92,7 @@ __global__ __launch_bounds__(256) void k_normal(Geo g, const double2 *__restrict
                 zero(acc);
                 if (dist <= stage) {
                     hop_sum<double, HOPS_IN>(g, U, slot, l, x, from_e, acc);
-                    if (C) clov_apply(C, g.V, 1, slot, g.Vb, l, acc);  // A_oo^-1 H_oe
+                    if (C) clov_spinor<double>(C, g.V, 1, slot, g.Vb, l, acc);  // A_oo^-1 H_oe
                 }
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp)
@@ -121,7 +105,7 @@ __global__ __launch_bounds__(256) void k_normal(Geo g, const double2 *__restrict
                 // reaches distance 0 at stage 2, 2 at stage 4)
                 spinor<double> dg;
                 LdsLoader<double>{she, Vh, 0}(0, l, dg);
-                if (C && dist <= stage - 2) clov_apply(C, g.V, 0, slot, g.Vb, l, dg);
+                if (C && dist <= stage - 2) clov_spinor<double>(C, g.V, 0, slot, g.Vb, l, dg);
 #pragma unroll
                 for (int sp = 0; sp < 4; ++sp)
 #pragma unroll

@@ -50,6 +50,21 @@ __device__ __forceinline__ void clov_mul6(const __attribute__((address_space(1))
         }
 }
 
+// v <- A v (inv = 0) or A^-1 v (inv = 1) at site (slot, l), in place
+template <typename T>
+__device__ __forceinline__ void clov_spinor(const T *base, long V, int inv, int slot, int Vb, int l, spinor<T> &v)
+{
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi) {
+        cx<T> x[6], y[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) x[i] = v.s[(6 * chi + i) / 3].c[(6 * chi + i) % 3];
+        clov_mul6<T>(clov_at<T>(base, V, inv, slot, chi, Vb, l), Vb, x, y);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v.s[(6 * chi + i) / 3].c[(6 * chi + i) % 3] = y[i];
+    }
+}
+
 // The clover part of a one-lane-per-site epilogue.  v holds the hop part
 // (-kappa H in, gamma_5-conjugated already for the adjoint), dg the diagonal
 // input (zeros where the launch has none); on return v holds the output:

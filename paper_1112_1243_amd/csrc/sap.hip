@@ -10,6 +10,7 @@
 // is solved by MR steps with both half fields resident in LDS; only the
 // links are read from global memory (they stay in L2 across the steps).
 // Per-block inner products are wavefront shuffles plus an LDS tree.
+#include "clover.h"
 #include "half2.h"
 #include "lds_stencil.h"
 
@@ -31,10 +32,14 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v, int width)
 // MODE 0: Schwarz sweep on one colour: r = eta - D x (global stencil on x),
 //         MR on the block, x += d.
 // MODE 1: block MR for a given right-hand side: d = MR(D_b, rhs).
-template <typename T, int MODE>
+// CL: with the clover term (ctab, A and A^-1 per site, clover.h): D_b = A -
+// kappa H_b, the reduced system (A_ee - kappa^2 H_eo A_oo^-1 H_oe) d_e =
+// r_e + kappa H_eo A_oo^-1 r_o and d_o = A_oo^-1 (r_o + kappa H_oe d_e); the
+// site blocks are read from memory where they are applied.
+template <typename T, int MODE, int CL>
 __global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const int32_t *__restrict__ active, UTab<T> Utab,
-                                                    const double *__restrict__ kap, long n,
-                                                    const typename C2<T>::type *__restrict__ src,
+                                                    const T *const *__restrict__ ctab, const double *__restrict__ kap,
+                                                    long n, const typename C2<T>::type *__restrict__ src,
                                                     typename C2<T>::type *__restrict__ dst, T kappa, int nmr,
                                                     int slot0)
 {
@@ -48,6 +53,8 @@ __global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const int32_t *__rest
     if (active && !active[m]) return;
     if (kap) kappa = (T)kap[m];
     const typename C2<T>::type *__restrict__ U = Utab[m];
+    const T *C = CL ? ctab[m] : nullptr;
+    const long V = g.V;
     src += m * n;
     dst += m * n;
     const int Vb = g.Vb, Vh = g.Vh;
@@ -67,6 +74,7 @@ __global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const int32_t *__rest
         spinor<T> e, xs;
         load_site<T>(src, slot, Vb, l, e);
         load_site<T>(dst, slot, Vb, l, xs);
+        if (CL) clov_spinor<T>(C, V, 0, slot, Vb, l, xs);  // the diagonal term A x
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -76,8 +84,12 @@ __global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const int32_t *__rest
         load_site<T>(src, slot, Vb, l, r);
     }
 
-    // ---- rhs_e = r_e + kappa H_eo r_o
-    if (!even) lds_store<T>(sho, Vh, hi, r);
+    // ---- rhs_e = r_e + kappa H_eo r_o (A_oo^-1 r_o with the clover term)
+    if (!even) {
+        spinor<T> ro = r;
+        if (CL) clov_spinor<T>(C, V, 1, slot, Vb, l, ro);
+        lds_store<T>(sho, Vh, hi, ro);
+    }
     __syncthreads();
     spinor<T> rho, del;
     if (even) {
@@ -96,20 +108,23 @@ __global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const int32_t *__rest
     const T k2 = kappa * kappa;
     for (int it = 0; it < nmr; ++it) {
         __syncthreads();
-        if (!even) {  // t_o = H_oe rho
+        if (!even) {  // t_o = H_oe rho (A_oo^-1 H_oe rho)
             hop_sum<T, HOPS_IN>(g, U, slot, l, x, LdsLoader<T>{she, Vh, 0}, acc);
+            if (CL) clov_spinor<T>(C, V, 1, slot, Vb, l, acc);
             lds_store<T>(sho, Vh, hi, acc);
         }
         __syncthreads();
         T pr = 0, pi = 0, pp = 0;
         spinor<T> p;
-        if (even) {  // p = rho - kappa^2 H_eo t_o
+        if (even) {  // p = rho - kappa^2 H_eo t_o (A_ee rho - ...)
             hop_sum<T, HOPS_IN>(g, U, slot, l, x, LdsLoader<T>{sho, Vh, Vh}, acc);
+            spinor<T> dg = rho;
+            if (CL) clov_spinor<T>(C, V, 0, slot, Vb, l, dg);
 #pragma unroll
             for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    p.s[sp].c[a] = rho.s[sp].c[a] - scale(k2, acc.s[sp].c[a]);
+                    p.s[sp].c[a] = dg.s[sp].c[a] - scale(k2, acc.s[sp].c[a]);
                     const cx<T> q = conjmul(p.s[sp].c[a], rho.s[sp].c[a]);
                     pr += q.re;
                     pi += q.im;
@@ -159,6 +174,7 @@ __global__ __launch_bounds__(MAXVB) void k_block_mr(Geo g, const int32_t *__rest
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
             for (int a = 0; a < 3; ++a) del.s[sp].c[a] = r.s[sp].c[a] + scale(kappa, acc.s[sp].c[a]);
+        if (CL) clov_spinor<T>(C, V, 1, slot, Vb, l, del);  // d_o = A_oo^-1 (...)
     }
 
     if (MODE == 0) {
@@ -1065,8 +1081,14 @@ void launch_sap_colour(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *eta
                        int slot0, int nslots, hipStream_t s)
 {
     if (nslots <= 0 || sy.M <= 0) return;
+    if (U.ctab) {  // the clover term: the one-lane-per-site form
+        k_block_mr<T, 0, 1><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, U.ctab, U.kap, sy.n, eta, x,
+                                                                kappa, nmr, slot0);
+        return;
+    }
     if (launch_mr_cube4<T, 0>(g, sy, U, eta, x, kappa, nmr, slot0, nslots, s)) return;
-    k_block_mr<T, 0><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, eta, x, kappa, nmr, slot0);
+    k_block_mr<T, 0, 0><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, nullptr, U.kap, sy.n, eta, x, kappa,
+                                                            nmr, slot0);
 }
 
 template <typename T>
@@ -1074,8 +1096,14 @@ void launch_block_mr(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *r, T2
                      int nslots, hipStream_t s)
 {
     if (nslots <= 0 || sy.M <= 0) return;
+    if (U.ctab) {
+        k_block_mr<T, 1, 1><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, U.ctab, U.kap, sy.n, r, d, kappa,
+                                                                nmr, slot0);
+        return;
+    }
     if (launch_mr_cube4<T, 1>(g, sy, U, r, d, kappa, nmr, slot0, nslots, s)) return;
-    k_block_mr<T, 1><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, U.kap, sy.n, r, d, kappa, nmr, slot0);
+    k_block_mr<T, 1, 0><<<dim3(nslots, sy.M), g.Vb, 0, s>>>(g, sy.active, U.tab, nullptr, U.kap, sy.n, r, d, kappa,
+                                                            nmr, slot0);
 }
 
 bool launch_mr_h16(int mode, const Geo &g, const Sys &sy, Links16 U, H16c src, H16 dst, float kappa, int nmr,

@@ -284,6 +284,73 @@ def test_clover_block_logdet(L, B, blocks):
     ctx.close()
 
 
+@pytest.mark.parametrize("L,B", GEOMS)
+def test_clover_sap_matches_oracle(L, B):
+    """The Schwarz procedure with the clover term (one lane per site in the
+    block MR, A and A^-1 applied where the reduced block system needs them)
+    against the oracle's, cycle for cycle: FP64 1e-12, FP32 2e-5."""
+    wdr, lat, ctx, U = _setup(L, B, 0.5, 524)
+    kappa = 0.135
+    T = oracle.clover_term(lat, U, CSW, kappa)
+    gU = ctx.gauge(dev(U), CSW, kappa)
+    eta = synth.spinor(lat.L, 525)
+    for ncy, nmr in ((1, 1), (2, 5)):
+        want = oracle.sap(lat, U, kappa, eta, ncy, nmr, clov=T)
+        for prec, tol in ((wdr.F64, 1e-12), (wdr.F32, 2e-5)):
+            p = wdr.default_params(sap_cycles=ncy, mr_steps=nmr, inner=prec)
+            e = rel(host(ctx.sap(gU, kappa, dev(eta), p)), want)
+            say("clover sap", L, ncy, nmr, prec, e)
+            assert e < tol
+    assert rel(want, oracle.sap(lat, U, kappa, eta, 2, 5)) > 1e-2
+    del gU
+    ctx.close()
+
+
+@pytest.mark.parametrize("inner", [0, 1])
+def test_clover_fgcr_solve(inner):
+    """FGCR with Schwarz preconditioning on the clover operator: the
+    oracle's clover stencil checks the true residual (<= 1.05e-10) and the
+    solution is within 1e-8 of the oracle's CGNE solution."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 526)
+    kappa = 0.125
+    T = oracle.clover_term(lat, U, CSW, kappa)
+    gU = ctx.gauge(dev(U), CSW, kappa)
+    b = synth.spinor(lat.L, 527)
+    x, info = ctx.solve(gU, kappa, dev(b), wdr.default_params(solver=0, inner=inner, max_iter=2000))
+    x = host(x)
+    r = np.linalg.norm(b - oracle.apply_D(lat, U, kappa, x, T)) / np.linalg.norm(b)
+    say("clover fgcr inner", inner, info.as_dict(), "oracle residual", r)
+    assert info.converged and r <= 1.05e-10
+    want, _, _, _ = oracle.solve(lat, U, kappa, b, tol=1e-13, clov=T)
+    assert rel(x, want) < 1e-8
+    del gU
+    ctx.close()
+
+
+@pytest.mark.parametrize("op", ["FULL", "SCHUR", "DD"])
+def test_clover_fgcr_samples(op):
+    """FULL, SCHUR and DD samples of the clover operator with FGCR + Schwarz
+    (FP32 inner level) within 1e-8 of the oracle's."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 528)
+    kappa = 0.125
+    Up = synth.redraw(U, oracle.active_links(lat), 0.5, 529)
+    gU, gUp = ctx.gauge(dev(U), CSW, kappa), ctx.gauge(dev(Up), CSW, kappa)
+    p = wdr.default_params(solver=0, inner=1, max_iter=2000)
+    s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, getattr(wdr, "OP_" + op), 1, 1, wdr.NOISE_GAUSS, 85, p)
+    if op == "DD":
+        wb, _ = oracle.logdet_ratio(lat, U, Up, kappa, oracle.OP_BLOCKS, 1, 1, oracle.NOISE_GAUSS, 85, csw=CSW)
+        ws, _ = oracle.logdet_ratio(lat, U, Up, kappa, oracle.OP_SCHUR, 1, 1, oracle.NOISE_GAUSS, 85, csw=CSW)
+        err = max(np.abs(s[..., :-1] - wb).max(), np.abs(s[..., -1] - ws).max())
+    else:
+        want, _ = oracle.logdet_ratio(lat, U, Up, kappa, getattr(oracle, "OP_" + op), 1, 1, oracle.NOISE_GAUSS, 85,
+                                      csw=CSW)
+        err = np.abs(s - want).max()
+    say("clover fgcr", op, "max |ds|", err, info.as_dict())
+    assert info.converged and err < 1e-8
+    del gU, gUp
+    ctx.close()
+
+
 def test_clover_16x16x16x16_operator_and_solve():
     """16^4 (256 blocks of 4^4): D with the clover term against the oracle on
     both stencil forms, and a CGNE solve whose true residual the oracle's
@@ -325,12 +392,12 @@ def test_clover_error_paths():
     refused(lambda: ctx.apply_D(gU, kappa, psi, wdr.F16))             # FP16 stencil
     refused(lambda: ctx.block_solve(gU, kappa, 0, psi, wdr.default_params(inner=2)))   # FP16 block MR
     refused(lambda: ctx.schur(gU, kappa, psi, wdr.default_params(inner=2)))
-    refused(lambda: ctx.sap(gU, kappa, psi, wdr.default_params()))
-    refused(lambda: ctx.solve(gU, kappa, psi, wdr.default_params(solver=0)))
+    refused(lambda: ctx.sap(gU, kappa, psi, wdr.default_params(inner=2)))          # FP16 Schwarz
+    refused(lambda: ctx.solve(gU, kappa, psi, wdr.default_params(solver=0, inner=2)))
     refused(lambda: ctx.solve(gU, kappa, psi, wdr.default_params(solver=1, inner=2)))
-    refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_SCHUR, 1, 1, 1, 1, wdr.default_params(solver=0)))
+    refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_SCHUR, 1, 1, 1, 1, wdr.default_params(inner=2)))
     refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_BLOCKS, 1, 1, 1, 1, wdr.default_params(inner=2)))
-    refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_DD, 1, 1, 1, 1, wdr.default_params(solver=0)))
+    refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_DD, 1, 1, 1, 1, wdr.default_params(inner=2)))
     refused(lambda: ctx.logdet_ratio(gU, gP, kappa, wdr.OP_FULL, 1, 1, 1, 1, wdr.default_params(solver=1)))
     refused(lambda: ctx.block_logdet(gU, 0.13))                           # another kappa
     refused(lambda: ctx.block_logdet_ratio(gU, gP, kappa))                 # csw differs
