@@ -244,11 +244,11 @@ int32_t wdr_gauge_is_su3(const wdr_gauge *g);
  * every call that takes U applies the clover operator: D, D_b and D_ee in F64
  * / F32 (wdr_apply_D, wdr_apply_D_internal, wdr_apply_D_noalloc,
  * wdr_apply_Dblock, wdr_apply_Dee; the hops of wdr_apply_Dhop have no
- * diagonal term), wdr_solve (CGNE or FGCR) and wdr_sap with an F64 / F32
- * inner level (the Schwarz blocks take the one-lane-per-site block MR),
- * wdr_block_solve and wdr_apply_schur with an F64 / F32 inner level (the
+ * diagonal term), wdr_solve with CGNE (any inner level) or FGCR and
+ * wdr_sap with an F64 / F32 inner level (the Schwarz blocks take the
+ * one-lane-per-site block MR), wdr_block_solve and wdr_apply_schur (the
  * block solves then run as FP64 defect correction around an even-odd CGNE of
- * the block operator, not the block MR), and FULL, BLOCKS, SCHUR and DD
+ * the block operator, FP32 for an F16 inner level), and FULL, BLOCKS, SCHUR and DD
  * estimates by such solves (wdr_logdet_ratio / _batch; both fields of a
  * ratio must carry the same csw), and the exact
  * block determinants (wdr_block_logdet / _ratio: det D_b = det A_oo det

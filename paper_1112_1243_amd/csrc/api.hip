@@ -54,9 +54,9 @@ wdr_status check_gauge(const wdr_ctx *c, const wdr_gauge *U, bool clover_ok = fa
     if (U->c64) {
         if (!clover_ok) {
             set_error("this call does not support a gauge field with a clover term (supported: D, D_b, the block "
-                      "hops and D_ee in F64 / F32; CGNE and FGCR solves, the Schwarz procedure, block solves and "
-                      "the Schur complement with F64 / F32 inner precision; FULL, BLOCKS, SCHUR and DD estimates "
-                      "by such solves; exact block determinants)");
+                      "hops and D_ee in F64 / F32; CGNE solves; FGCR and the Schwarz procedure with F64 / F32 "
+                      "inner precision; block solves and the Schur complement; FULL, BLOCKS, SCHUR and DD "
+                      "estimates by such solves; exact block determinants)");
             return WDR_EINVAL;
         }
         if (kappa != U->ckappa) {
@@ -67,10 +67,11 @@ wdr_status check_gauge(const wdr_ctx *c, const wdr_gauge *U, bool clover_ok = fa
     return WDR_OK;
 }
 
-// an estimate supports the clover term with an FP64 or FP32 inner level
+// an estimate supports the clover term except with FGCR and the FP16
+// Schwarz procedure (FP16 CG steps carry it, FP16 block solves take FP32 CG)
 bool clover_est_ok(const wdr_est_params *p)
 {
-    return p && p->sp.inner != WDR_F16;
+    return p && (p->sp.inner != WDR_F16 || p->sp.solver == WDR_SOLVER_CGNE || p->op == WDR_OP_BLOCKS);
 }
 wdr_status check_pair(const wdr_gauge *U, const wdr_gauge *Up)
 {
@@ -650,7 +651,7 @@ wdr_status wdr_solve(wdr_ctx *c, const wdr_gauge *U, double kappa, const wdr_sol
         set_error("null solver parameters");
         return WDR_EINVAL;
     }
-    if ((e = check_gauge(c, U, sp->inner != WDR_F16, kappa)) != WDR_OK ||
+    if ((e = check_gauge(c, U, sp->inner != WDR_F16 || sp->solver == WDR_SOLVER_CGNE, kappa)) != WDR_OK ||
         (e = check_kappa(kappa)) != WDR_OK)
         return e;
     if ((e = check_params(c, *sp, false)) != WDR_OK) return e;
@@ -670,8 +671,7 @@ wdr_status wdr_block_solve(wdr_ctx *c, const wdr_gauge *U, double kappa, int32_t
 {
     wdr_status e = pre(c, b, x);
     if (e != WDR_OK) return e;
-    if ((e = check_gauge(c, U, sp && sp->inner != WDR_F16, kappa)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK)
-        return e;
+    if ((e = check_gauge(c, U, sp != nullptr, kappa)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
     if (!sp || colour < 0 || colour > 2) {
         set_error("null solver parameters or colour not in 0..2");
         return WDR_EINVAL;
@@ -693,8 +693,7 @@ wdr_status wdr_apply_schur(wdr_ctx *c, const wdr_gauge *U, double kappa, const w
 {
     wdr_status e = pre(c, in, out);
     if (e != WDR_OK) return e;
-    if ((e = check_gauge(c, U, sp && sp->inner != WDR_F16, kappa)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK)
-        return e;
+    if ((e = check_gauge(c, U, sp != nullptr, kappa)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
     if (!sp) {
         set_error("null solver parameters");
         return WDR_EINVAL;

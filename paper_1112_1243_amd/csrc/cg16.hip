@@ -17,6 +17,7 @@
 // most 1 (one v_pk_fma_f16 handles a complex pair; the kernel was bound by
 // its FP32 instruction issue); everything else is FP32, and norms are summed
 // in FP64.
+#include "clover.h"
 #include "half2.h"
 #include "stencil.h"
 
@@ -327,15 +328,19 @@ __device__ __forceinline__ void hop16(const Site16 *own, const Site16 *halo, flo
 // the block's input half and its halo (the 256 face sites of the neighbour
 // blocks, two per lane) go to LDS as FP16, the eight links of the lane's
 // hops to registers; the hops then read LDS and registers only.
-// partial (optional): |out|^2 of the stored values per block.
-template <int DAG>
+// partial (optional): |out|^2 of the stored values per block.  CL: with the
+// clover term (ctab: the FP32 A and A^-1 of clover.h per system) the output
+// is A diag + f H in (CLOV_DIAG) or A^-1 (diag + f H in) (CLOV_INV), in FP32
+// before the rounded store.
+template <int DAG, int CL>
 __global__ __launch_bounds__(VH4) void k_eo16(Geo g, const int32_t *__restrict__ active,
                                               const int32_t *__restrict__ list, const h2 *const *__restrict__ ltab,
                                               const double *__restrict__ kap, float fs, float fk, int par,
                                               const int32_t *__restrict__ sched, const uint4 *__restrict__ inv,
                                               const float *__restrict__ ins, const uint4 *__restrict__ dgv,
                                               const float *__restrict__ dgs, uint4 *__restrict__ outv,
-                                              float *__restrict__ outs, double *__restrict__ partial)
+                                              float *__restrict__ outs, double *__restrict__ partial,
+                                              const float *const *__restrict__ ctab)
 {
     typedef Cube<B4> CB;
     __shared__ Site16 own[VH4];       // the block's input half
@@ -414,7 +419,13 @@ __global__ __launch_bounds__(VH4) void k_eo16(Geo g, const int32_t *__restrict__
     for (int c = 0; c < 12; ++c) {
         cx<float> v = scale(f, acc.s[c / 3].c[c % 3]);
         if (DAG && c >= 6) v = neg(v);
-        res[c] = dgv ? v + dg[c] : v;
+        res[c] = dgv && !CL ? v + dg[c] : v;
+    }
+    if (CL) {  // A diag + hops, or A^-1 (diag + hops)
+        if (!dgv)
+#pragma unroll
+            for (int c = 0; c < 12; ++c) dg[c] = mk<float>(0.f, 0.f);
+        clov_site<float, CL>(ctab[m], (long)g.V, slot, 2 * VH4, par * VH4 + t, dg, res);
     }
     store_block(res, outv, outs, site, fbase + slot, partial, fbase + slot);
 }
@@ -651,16 +662,24 @@ void launch_pack_links_e16(const Geo &g, const double2 *u64, h2 *e16, hipStream_
 }
 
 void launch_eo16(const Geo &g, const Sys &sy, Links16 U, float fs, float fk, int par, int dag, E16c in, E16c diag,
-                 E16 out, double *partial, hipStream_t s)
+                 E16 out, double *partial, hipStream_t s, const float *const *ctab, int cmode)
 {
     const int si = sched_index(g, 0, g.nblk);
     const dim3 grid(g.nblk, sy.launch_m());
-    if (dag)
-        k_eo16<1><<<grid, VH4, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, fs, fk, par, g.sched[si], in.v, in.s,
-                                       diag.v, diag.s, out.v, out.s, partial);
-    else
-        k_eo16<0><<<grid, VH4, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, fs, fk, par, g.sched[si], in.v, in.s,
-                                       diag.v, diag.s, out.v, out.s, partial);
+    const int cl = ctab ? cmode : CLOV_NONE;
+#define WDR_EO16(D, C)                                                                                         \
+    k_eo16<D, C><<<grid, VH4, 0, s>>>(g, sy.active, sy.list, U.tab, U.kap, fs, fk, par, g.sched[si], in.v, in.s, \
+                                      diag.v, diag.s, out.v, out.s, partial, ctab)
+    if (dag) {
+        if (cl == CLOV_DIAG) WDR_EO16(1, CLOV_DIAG);
+        else if (cl == CLOV_INV) WDR_EO16(1, CLOV_INV);
+        else WDR_EO16(1, CLOV_NONE);
+    } else {
+        if (cl == CLOV_DIAG) WDR_EO16(0, CLOV_DIAG);
+        else if (cl == CLOV_INV) WDR_EO16(0, CLOV_INV);
+        else WDR_EO16(0, CLOV_NONE);
+    }
+#undef WDR_EO16
 }
 
 void launch_e16_from64(const Geo &g, int M, int par, const double2 *in, E16 out, hipStream_t s)

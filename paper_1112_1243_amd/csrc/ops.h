@@ -300,9 +300,12 @@ E16 e16_field(const Geo &g, int M, void *p);
 void launch_pack_links_e16(const Geo &g, const double2 *u64, h2 *e16, hipStream_t s);
 // out = diag + f H_{par, 1-par} in (gamma_5 on both sides for dag), f = fs
 // kappa_m with a kappa table in U, else fk; partial (may be NULL): |out|^2
-// per (system, slot) for the deterministic reduction (2 doubles each)
+// per (system, slot) for the deterministic reduction (2 doubles each); ctab
+// (FP32 clover terms per system) with cmode CLOV_DIAG: A times the diagonal,
+// CLOV_INV: A^-1 times the whole output
 void launch_eo16(const Geo &g, const Sys &sy, Links16 U, float fs, float fk, int par, int dag, E16c in, E16c diag,
-                 E16 out, double *partial, hipStream_t s);
+                 E16 out, double *partial, hipStream_t s, const float *const *ctab = nullptr,
+                 int cmode = CLOV_NONE);
 // x += alpha w (x FP32 internal layout, even sites), r -= alpha q, |r|^2 partials;
 // alpha = sc[8m].x / sc[8m + 1].x; x NULL: no x update, alpha stored in alpha[m]
 void launch_xr16(const Geo &g, const Sys &sy, const double2 *sc, float2 *x, float *alpha, E16c w, E16c q, E16 r,

@@ -936,8 +936,12 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     const Links<double> U64 = U.u64;
     Links<double> U64n = U.u64;
     U64n.kneg = 1;
+    U64n.cmode = CLOV_NONE;  // the diagonal input b_e enters as it is
     const Links<float> U32 = U.u32;
     const Links16 U16 = U.e16;
+    // with a clover term: A_oo^-1 on the odd halves, A_ee on the diagonal (FP32 blocks)
+    const bool clov = U.u64.ctab != nullptr;
+    const float *const *C32 = U.u32.ctab;
     const float kf = (float)kappa;
     const Sys all = all_sys(c, M);
     Sys sa{M, alive, n}, su{M, upd, n}, s64{M, upd64, n};
@@ -947,11 +951,12 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     const unsigned nbm = nb64(M);
     const int G = g.nblk;
 
-    // bh = [b_e + k H_eo b_o; 0]; x = 0; r64 = bh; every system starts an outer update
+    // bh = [b_e + k H_eo A_oo^-1 b_o; 0]; x = 0; r64 = bh; every system starts an outer update
     launch_zero<double>(x, total, s);
     launch_zero<double>(bh, total, s);
     launch_zero<double>(t64, total, s);
-    launch_dslash<double>(g, all, U64n, HOPS_ALL, 0, 0, b, b, bh, -kappa, 0, g.nblk, s);
+    if (clov) launch_clover_mul<double>(g, all, U.u64.ctab, 1, 1, b, o64, s);  // odd sites of o64
+    launch_dslash<double>(g, all, U64n, HOPS_ALL, 0, 0, clov ? o64 : b, b, bh, -kappa, 0, g.nblk, s);
     launch_norm2<double>(all, b, red.as<double>(), sc + 5, 8, s);
     k_cgm_init<<<nbm, 64, 0, s>>>(M, sc, bn2, rmax, alive, upd, its);  // |b|^2 of the full system
     launch_zero<float>(x32, total, s);
@@ -971,11 +976,11 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
             // x += alpha w for the last K steps at once (before the period's end)
             const int j = i % K;
             const E16 W = Wk[j];
-            launch_eo16(g, sa, U16, -1.f, -kf, 1, 1, cref(P), none, T, nullptr, q);
-            launch_eo16(g, sa, U16, 1.f, kf, 0, 1, cref(T), cref(P), W, part, q);
+            launch_eo16(g, sa, U16, -1.f, -kf, 1, 1, cref(P), none, T, nullptr, q, C32, CLOV_INV);
+            launch_eo16(g, sa, U16, 1.f, kf, 0, 1, cref(T), cref(P), W, part, q, C32, CLOV_DIAG);
             launch_final(sa, part, G, sc + 1, 8, q);
-            launch_eo16(g, sa, U16, -1.f, -kf, 1, 0, cref(W), none, T, nullptr, q);
-            launch_eo16(g, sa, U16, 1.f, kf, 0, 0, cref(T), cref(W), Q, nullptr, q);
+            launch_eo16(g, sa, U16, -1.f, -kf, 1, 0, cref(W), none, T, nullptr, q, C32, CLOV_INV);
+            launch_eo16(g, sa, U16, 1.f, kf, 0, 0, cref(T), cref(W), Q, nullptr, q, C32, CLOV_DIAG);
             launch_xr16(g, sa, sc, nullptr, alphas + (long)j * M, cref(W), cref(Q), R, part, q);
             launch_final(sa, part, G, sc + 3, 8, q);
             k_cgm_beta<<<nbm, 64, 0, q>>>(M, sc, RELIABLE_DELTA_F16 * RELIABLE_DELTA_F16, sp.max_iter, alive, rmax,
@@ -1032,9 +1037,11 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
             }
         }
     }
-    // x_o = b_o + k H_oe x_e
+    // x_o = A_oo^-1 (b_o + k H_oe x_e)
     launch_zero<double>(t64, total, s);
-    launch_dslash<double>(g, all, U64n, HOPS_ALL, 1, 0, x, b, t64, -kappa, 0, g.nblk, s);
+    Links<double> U64i = U64n;
+    U64i.cmode = CLOV_INV;
+    launch_dslash<double>(g, all, U64i, HOPS_ALL, 1, 0, x, b, t64, -kappa, 0, g.nblk, s);
     launch_add_to64<double>(all, t64, x, s);
 
     std::vector<double> hbn2(M), rn2;
@@ -1062,9 +1069,13 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
     const double outer = H * (spin_b<float>() + 2 * spin_b<double>()) + half_b<double>(V, false) +
                          half_b<double>(V, true) + 3 * H * spin_b<double>() +
                          H * (spin_b<double>() + 2 * spin_b<float>() + 48);
+    // the clover blocks of every output site of the four halves, the middle
+    // and the outer Dhat (FP32 in the steps and the middle, FP64 outside)
+    const double cl_step = clov ? 4 * H * clov_b<float>() : 0, cl_mid = clov ? 2 * H * clov_b<float>() : 0,
+                 cl_out = clov ? 2 * H * clov_b<double>() : 0;
     double bytes = 0;
     for (int m = 0; m < M; ++m) {
-        bytes += setup + hits[m] * step + hmid[m] * mid + hout[m] * outer;
+        bytes += setup + hits[m] * (step + cl_step) + hmid[m] * (mid + cl_mid) + hout[m] * (outer + cl_out);
         st[m].iters = hits[m];
         st[m].total = hits[m];
         st[m].rel = rel_resid(rn2[m], hbn2[m]);
@@ -1086,10 +1097,7 @@ wdr_status solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr
                    const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
     if (sp.solver == WDR_SOLVER_CGNE) {
-        if (sp.inner == WDR_F16) {
-            if (no_clover(U, "the FP16 inner level") != WDR_OK) return WDR_EINVAL;
-            return cgne_eo16(c, M, U, kappa, sp, tol, b, x, st, s);
-        }
+        if (sp.inner == WDR_F16) return cgne_eo16(c, M, U, kappa, sp, tol, b, x, st, s);
         return sp.inner == WDR_F64 ? cgne_eo<double>(c, M, U, kappa, sp, tol, b, x, st, s)
                                    : cgne_eo<float>(c, M, U, kappa, sp, tol, b, x, st, s);
     }
@@ -1109,7 +1117,8 @@ constexpr double BLOCK_EO_TOL = 1e-7;
 // around the even-odd CGNE of the block operator D_b = A - kappa H_in on the
 // blocks of the colour, all of them one block-diagonal system.  Each round
 // solves D_b d = r to a relative residual max(tol / 2, BLOCK_EO_TOL) with
-// sp.inner iterations and FP64 reliable updates, adds d to x and forms the
+// sp.inner iterations (FP32 for an FP16 inner level) and FP64 reliable
+// updates, adds d to x and forms the
 // FP64 residual r = b - D_b x block by block; as in the MR rounds, the worst
 // block ratio |r_b| / |b_b| decides.  Systems that have converged get r = 0,
 // which their next CG ends at once.
@@ -1117,10 +1126,6 @@ static wdr_status block_solve_clover(wdr_ctx *c, int M, const GaugeTab &U, doubl
                                      const wdr_solver_params &sp, double tol, const double2 *b, double2 *x,
                                      std::vector<Stats> &st, hipStream_t s)
 {
-    if (sp.inner == WDR_F16) {
-        set_error("the block solver with the clover term needs an F64 or F32 inner precision");
-        return WDR_EINVAL;
-    }
     const auto &g = c->g;
     int slot0, ns;
     colour_slots(c, colour, slot0, ns);
@@ -1152,6 +1157,7 @@ static wdr_status block_solve_clover(wdr_ctx *c, int M, const GaugeTab &U, doubl
     for (int round = 0; round < 40; ++round) {
         k_zero_dead<<<nb256(total), 256, 0, s>>>(alive, n, total, r);
         std::vector<Stats> si;
+        // (an FP16 inner level takes FP32 CG steps here: the FP16 block MR has no clover term)
         const wdr_status e = sp.inner == WDR_F64 ? cgne_eo<double>(c, M, U, kappa, sp, tin, r, d, si, s, op)
                                                  : cgne_eo<float>(c, M, U, kappa, sp, tin, r, d, si, s, op);
         if (e != WDR_OK && e != WDR_ENOCONV) return e;

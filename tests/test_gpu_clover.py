@@ -351,6 +351,50 @@ def test_clover_fgcr_samples(op):
     ctx.close()
 
 
+@pytest.mark.parametrize("middle,bc", [(1, (1, 1, 1, -1)), (0, (1, 1, 1, -1)), (1, (1, -1, 1, -1))])
+def test_clover_f16_cg_solve(middle, bc):
+    """CGNE with FP16 steps on the clover operator (A_oo^-1 and A_ee in FP32
+    in the FP16 stencil halves), with an FP32 middle level or FP64 updates
+    only: the oracle's clover stencil checks the true residual (<= 1.05e-10)
+    and the solution is within 1e-8 of the oracle's."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 530, bc)
+    kappa = 0.135
+    T = oracle.clover_term(lat, U, CSW, kappa)
+    gU = ctx.gauge(dev(U), CSW, kappa)
+    b = synth.spinor(lat.L, 531)
+    x, info = ctx.solve(gU, kappa, dev(b), wdr.default_params(solver=1, inner=2, middle=middle, max_iter=20000))
+    x = host(x)
+    r = np.linalg.norm(b - oracle.apply_D(lat, U, kappa, x, T)) / np.linalg.norm(b)
+    say("clover f16 cg middle", middle, bc, info.as_dict(), "oracle residual", r)
+    assert info.converged and r <= 1.05e-10
+    want, _, _, _ = oracle.solve(lat, U, kappa, b, tol=1e-13, clov=T)
+    assert rel(x, want) < 1e-8
+    del gU
+    ctx.close()
+
+
+@pytest.mark.parametrize("op", ["FULL", "SCHUR", "BLOCKS"])
+def test_clover_f16_samples(op):
+    """Samples of the clover operator with the FP16 inner level (FP16 CG
+    steps, FP32 middle level; block solves by FP32 CG rounds) within 1e-8 of
+    the oracle's."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 532)
+    kappa = 0.135
+    Up = synth.redraw(U, oracle.active_links(lat), 0.5, 533)
+    gU, gUp = ctx.gauge(dev(U), CSW, kappa), ctx.gauge(dev(Up), CSW, kappa)
+    p = wdr.default_params(solver=1, inner=2, middle=1, max_iter=20000)
+    N = 2
+    s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, getattr(wdr, "OP_" + op), N, 1, wdr.NOISE_GAUSS, 87, p)
+    want, lr_want = oracle.logdet_ratio(lat, U, Up, kappa, getattr(oracle, "OP_" + op), N, 1, oracle.NOISE_GAUSS,
+                                        87, csw=CSW)
+    err = np.abs(s - want).max()
+    say("clover f16", op, "max |ds|", err, info.as_dict())
+    assert info.converged and err < 1e-8
+    assert abs(lr - float(np.sum(lr_want))) < 1e-8 * s.size
+    del gU, gUp
+    ctx.close()
+
+
 def test_clover_16x16x16x16_operator_and_solve():
     """16^4 (256 blocks of 4^4): D with the clover term against the oracle on
     both stencil forms, and a CGNE solve whose true residual the oracle's
@@ -390,13 +434,9 @@ def test_clover_error_paths():
 
     refused(lambda: ctx.apply_D(gU, 0.13, psi))                       # another kappa
     refused(lambda: ctx.apply_D(gU, kappa, psi, wdr.F16))             # FP16 stencil
-    refused(lambda: ctx.block_solve(gU, kappa, 0, psi, wdr.default_params(inner=2)))   # FP16 block MR
-    refused(lambda: ctx.schur(gU, kappa, psi, wdr.default_params(inner=2)))
     refused(lambda: ctx.sap(gU, kappa, psi, wdr.default_params(inner=2)))          # FP16 Schwarz
     refused(lambda: ctx.solve(gU, kappa, psi, wdr.default_params(solver=0, inner=2)))
-    refused(lambda: ctx.solve(gU, kappa, psi, wdr.default_params(solver=1, inner=2)))
     refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_SCHUR, 1, 1, 1, 1, wdr.default_params(inner=2)))
-    refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_BLOCKS, 1, 1, 1, 1, wdr.default_params(inner=2)))
     refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_DD, 1, 1, 1, 1, wdr.default_params(inner=2)))
     refused(lambda: ctx.logdet_ratio(gU, gP, kappa, wdr.OP_FULL, 1, 1, 1, 1, wdr.default_params(solver=1)))
     refused(lambda: ctx.block_logdet(gU, 0.13))                           # another kappa
