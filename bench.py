@@ -93,7 +93,8 @@ def clover_workload(wdr, torch, L=(16, 16, 16, 16), N=8, kappa=0.135, scale=0.5,
     on the same 16^4 proposal: N factors x 1 Gaussian noise, all batched,
     CGNE with FP32 iterations and FP64 reliable updates to 1e-10; block
     solves to 1e-13 (FP32 block MR rounds without the term, FP32 even-odd
-    CGNE rounds on the blocks with it)."""
+    CGNE rounds on the blocks with it).  The *_f16 entries: the clover
+    estimates with FP16 CG steps and an FP32 middle level."""
     from paper_1112_1243_amd import synth
     ctx = wdr.Context(L, (4, 4, 4, 4))
     U = synth.gauge_field(L, scale, seed)
@@ -103,14 +104,16 @@ def clover_workload(wdr, torch, L=(16, 16, 16, 16), N=8, kappa=0.135, scale=0.5,
                        "SCHUR ratios, N=%d factors x 1 Gaussian noise (batched), CGNE FP32 iterations + FP64 reliable "
                        "updates to 1e-10, block solves to 1e-13" % ("x".join(map(str, L)), kappa, scale, N),
            "unit": "estimates/s"}
-    for op, suffix in ((wdr.OP_FULL, ""), (wdr.OP_SCHUR, "_schur")):
-        for csw in (CSW, 0.0):
+    p16 = wdr.default_params(solver=wdr.SOLVER_CGNE, inner=wdr.F16, middle=wdr.F32, max_iter=20000)
+    for op, suffix, csws, prm in ((wdr.OP_FULL, "", (CSW, 0.0), p), (wdr.OP_SCHUR, "_schur", (CSW, 0.0), p),
+                                  (wdr.OP_FULL, "_f16", (CSW,), p16), (wdr.OP_SCHUR, "_schur_f16", (CSW,), p16)):
+        for csw in csws:
             gU = ctx.gauge(torch.from_numpy(U).cuda(), csw, kappa)
             gUp = ctx.gauge(torch.from_numpy(Up).cuda(), csw, kappa)
-            ctx.logdet_ratio(gU, gUp, kappa, op, 1, 1, wdr.NOISE_GAUSS, 1, p)  # warm-up
+            ctx.logdet_ratio(gU, gUp, kappa, op, 1, 1, wdr.NOISE_GAUSS, 1, prm)  # warm-up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, op, N, 1, wdr.NOISE_GAUSS, seed, p)
+            s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, op, N, 1, wdr.NOISE_GAUSS, seed, prm)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             key = ("clover" if csw else "wilson") + suffix
