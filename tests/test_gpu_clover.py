@@ -395,6 +395,24 @@ def test_clover_f16_samples(op):
     ctx.close()
 
 
+def test_clover_16x16x16x16_schur_f16_sample():
+    """A 16^4 SCHUR sample of the clover operator with the settings of the
+    large-lattice workloads (FP16 CG steps, FP32 middle level, FP64 reliable
+    updates; block solves by FP32 CG rounds) within 1e-8 of the oracle's."""
+    wdr, lat, ctx, U = _setup((16, 16, 16, 16), (4, 4, 4, 4), 0.25, 534)
+    kappa = 0.135
+    Up = synth.redraw(U, oracle.active_links(lat), 0.25, 535)
+    gU, gUp = ctx.gauge(dev(U), CSW, kappa), ctx.gauge(dev(Up), CSW, kappa)
+    p = wdr.default_params(solver=1, inner=2, middle=1, max_iter=20000)
+    s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, wdr.OP_SCHUR, 1, 1, wdr.NOISE_GAUSS, 89, p)
+    want, _ = oracle.logdet_ratio(lat, U, Up, kappa, oracle.OP_SCHUR, 1, 1, oracle.NOISE_GAUSS, 89, csw=CSW)
+    err = np.abs(s - want).max()
+    say("clover 16^4 SCHUR f16 max |ds|", err, "sample", float(want.ravel()[0]), info.as_dict())
+    assert info.converged and err < 1e-8
+    del gU, gUp
+    ctx.close()
+
+
 def test_clover_16x16x16x16_operator_and_solve():
     """16^4 (256 blocks of 4^4): D with the clover term against the oracle on
     both stencil forms, and a CGNE solve whose true residual the oracle's
