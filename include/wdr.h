@@ -244,9 +244,10 @@ int32_t wdr_gauge_is_su3(const wdr_gauge *g);
  * every call that takes U applies the clover operator: D, D_b and D_ee in F64
  * / F32 (wdr_apply_D, wdr_apply_D_internal, wdr_apply_D_noalloc,
  * wdr_apply_Dblock, wdr_apply_Dee; the hops of wdr_apply_Dhop have no
- * diagonal term), wdr_solve with CGNE (any inner level) or FGCR and
- * wdr_sap with an F64 / F32 inner level (the Schwarz blocks take the
- * one-lane-per-site block MR), wdr_block_solve and wdr_apply_schur (the
+ * diagonal term), wdr_solve with CGNE or FGCR and wdr_sap (the Schwarz
+ * blocks take the one-lane-per-site block MR; an F16 inner level sweeps in
+ * F32 there, since the FP16 sweep keeps no blocks of A beside its fields),
+ * wdr_block_solve and wdr_apply_schur (the
  * block solves then run as FP64 defect correction around an even-odd CGNE of
  * the block operator, FP32 for an F16 inner level), and FULL, BLOCKS, SCHUR and DD
  * estimates by such solves (wdr_logdet_ratio / _batch; both fields of a
@@ -404,7 +405,8 @@ wdr_status wdr_apply_Dee(wdr_ctx *ctx, const wdr_gauge *U, double kappa, wdr_pre
 
 /* Schwarz alternating procedure: sp->sap_cycles cycles over black then white
  * blocks, each block updated by sp->mr_steps even-odd minimal-residual steps,
- * in precision sp->inner.  out approximates D^-1 in. */
+ * in precision sp->inner (F32 for F16 when U carries a clover term).  out
+ * approximates D^-1 in. */
 wdr_status wdr_sap(wdr_ctx *ctx, const wdr_gauge *U, double kappa, const wdr_solver_params *sp,
                    const double *dev_in, double *dev_out, void *stream);
 
@@ -524,7 +526,9 @@ wdr_status wdr_block_fields(wdr_ctx *ctx, const wdr_gauge *U, double *dev_out, v
  * op WDR_OP_SCHUR, which p->op must be); block b uses the noise key
  * p->seed + b.  host_samples: nblocks x n_steps x n_noise; host_log_ratios:
  * nblocks; host_info: summed iterations, worst residual.  Needs SU(3) links
- * or none in both fields; EINVAL for a mismatched `sub`. */
+ * or none in both fields; EINVAL for a mismatched `sub`, and for fields that
+ * carry a clover term (the clover leaves at a block's faces reach links
+ * outside the block, which `sub` does not hold). */
 wdr_status wdr_block_schur_ratio(wdr_ctx *ctx, const wdr_gauge *U, const wdr_gauge *Up, double kappa, wdr_ctx *sub,
                                  const wdr_est_params *p, double *host_samples, double *host_log_ratios,
                                  wdr_solve_info *host_info, void *stream);

@@ -54,9 +54,9 @@ wdr_status check_gauge(const wdr_ctx *c, const wdr_gauge *U, bool clover_ok = fa
     if (U->c64) {
         if (!clover_ok) {
             set_error("this call does not support a gauge field with a clover term (supported: D, D_b, the block "
-                      "hops and D_ee in F64 / F32; CGNE solves; FGCR and the Schwarz procedure with F64 / F32 "
-                      "inner precision; block solves and the Schur complement; FULL, BLOCKS, SCHUR and DD "
-                      "estimates by such solves; exact block determinants)");
+                      "hops and D_ee in F64 / F32; CGNE and FGCR solves and the Schwarz procedure; block solves "
+                      "and the Schur complement; FULL, BLOCKS, SCHUR and DD estimates; exact block "
+                      "determinants)");
             return WDR_EINVAL;
         }
         if (kappa != U->ckappa) {
@@ -67,12 +67,6 @@ wdr_status check_gauge(const wdr_ctx *c, const wdr_gauge *U, bool clover_ok = fa
     return WDR_OK;
 }
 
-// an estimate supports the clover term except with FGCR and the FP16
-// Schwarz procedure (FP16 CG steps carry it, FP16 block solves take FP32 CG)
-bool clover_est_ok(const wdr_est_params *p)
-{
-    return p && (p->sp.inner != WDR_F16 || p->sp.solver == WDR_SOLVER_CGNE || p->op == WDR_OP_BLOCKS);
-}
 wdr_status check_pair(const wdr_gauge *U, const wdr_gauge *Up)
 {
     if (U->csw != Up->csw) {
@@ -626,8 +620,7 @@ wdr_status wdr_sap(wdr_ctx *c, const wdr_gauge *U, double kappa, const wdr_solve
 {
     wdr_status e = pre(c, in, out);
     if (e != WDR_OK) return e;
-    if ((e = check_gauge(c, U, sp && sp->inner != WDR_F16, kappa)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK)
-        return e;
+    if ((e = check_gauge(c, U, true, kappa)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
     if (!sp) {
         set_error("null solver parameters");
         return WDR_EINVAL;
@@ -651,9 +644,7 @@ wdr_status wdr_solve(wdr_ctx *c, const wdr_gauge *U, double kappa, const wdr_sol
         set_error("null solver parameters");
         return WDR_EINVAL;
     }
-    if ((e = check_gauge(c, U, sp->inner != WDR_F16 || sp->solver == WDR_SOLVER_CGNE, kappa)) != WDR_OK ||
-        (e = check_kappa(kappa)) != WDR_OK)
-        return e;
+    if ((e = check_gauge(c, U, true, kappa)) != WDR_OK || (e = check_kappa(kappa)) != WDR_OK) return e;
     if ((e = check_params(c, *sp, false)) != WDR_OK) return e;
     const double t0 = now();
     std::vector<Stats> st;
@@ -727,8 +718,8 @@ wdr_status wdr_logdet_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge *Up,
     if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
     wdr_status e;
     if ((e = check_est(c, p)) != WDR_OK) return e;
-    if ((e = check_gauge(c, U, clover_est_ok(p), kappa)) != WDR_OK ||
-        (e = check_gauge(c, Up, clover_est_ok(p), kappa)) != WDR_OK || (e = check_pair(U, Up)) != WDR_OK)
+    if ((e = check_gauge(c, U, true, kappa)) != WDR_OK ||
+        (e = check_gauge(c, Up, true, kappa)) != WDR_OK || (e = check_pair(U, Up)) != WDR_OK)
         return e;
     if ((e = check_kappa(kappa)) != WDR_OK) return e;
     WDR_HIP(hipSetDevice(c->device));
@@ -755,8 +746,8 @@ wdr_status wdr_logdet_ratio_batch(int32_t n, const wdr_proposal *props, const wd
         wdr_ctx *c = props[j].ctx;
         if (check_ctx(c) != WDR_OK) return WDR_EINVAL;
         wdr_status e;
-        if ((e = check_gauge(c, props[j].U, clover_est_ok(p), props[j].kappa)) != WDR_OK ||
-            (e = check_gauge(c, props[j].Up, clover_est_ok(p), props[j].kappa)) != WDR_OK ||
+        if ((e = check_gauge(c, props[j].U, true, props[j].kappa)) != WDR_OK ||
+            (e = check_gauge(c, props[j].Up, true, props[j].kappa)) != WDR_OK ||
             (e = check_pair(props[j].U, props[j].Up)) != WDR_OK || (e = check_kappa(props[j].kappa)) != WDR_OK)
             return e;
         const size_t gi = std::find(ctxs.begin(), ctxs.end(), c) - ctxs.begin();
@@ -907,6 +898,12 @@ wdr_status wdr_block_schur_ratio(wdr_ctx *c, const wdr_gauge *U, const wdr_gauge
 {
     if (check_ctx(c) != WDR_OK || check_ctx(sub) != WDR_OK) return WDR_EINVAL;
     wdr_status e;
+    if ((U && U->c64) || (Up && Up->c64)) {
+        // the leaves at a block's face reach outside the block, which a
+        // lattice of the block's extents with open boundaries does not hold
+        set_error("the block Schur ratio does not support the clover term");
+        return WDR_EINVAL;
+    }
     if ((e = check_gauge(c, U)) != WDR_OK || (e = check_gauge(c, Up)) != WDR_OK) return e;
     if ((e = check_kappa(kappa)) != WDR_OK) return e;
     for (int mu = 0; mu < 4; ++mu)

@@ -328,15 +328,6 @@ void apply_D64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const
     launch_dslash<double>(c->g, sy, L, HOPS_ALL, -1, 0, in, in, out, kappa, 0, c->g.nblk, s);
 }
 
-// the FP16 levels (the FP16 CG and Schwarz procedure) do not handle the
-// clover term
-static wdr_status no_clover(const GaugeTab &U, const char *what)
-{
-    if (!U.u64.ctab) return WDR_OK;
-    set_error(std::string(what) + " does not support the clover term");
-    return WDR_EINVAL;
-}
-
 // ------------------------------------------------------------ SAP
 
 // x_zero: x is already zero
@@ -376,12 +367,13 @@ static wdr_status need16(const GaugeTab &U)
 wdr_status sap64(wdr_ctx *c, const Sys &sy, const GaugeTab &U, double kappa, const wdr_solver_params &sp,
                  const double2 *in, double2 *out, hipStream_t s)
 {
-    if (sp.inner == WDR_F16 && no_clover(U, "the FP16 Schwarz procedure") != WDR_OK) return WDR_EINVAL;
     if (sp.inner == WDR_F64) {
         sap_run<double>(c, sy, U.u64, kappa, sp.sap_cycles, sp.mr_steps, in, out, s);
         return WDR_OK;
     }
-    if (sp.inner == WDR_F16) {
+    // the FP16 sweep kernels keep no 6 x 6 blocks of A beside their LDS
+    // fields: with the clover term an FP16 inner level sweeps in FP32
+    if (sp.inner == WDR_F16 && !U.u64.ctab) {
         wdr_status e = need16(U);
         if (e != WDR_OK) return e;
         H16Work eh(c, sy.M), xh(c, sy.M);
@@ -1101,7 +1093,6 @@ wdr_status solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr
         return sp.inner == WDR_F64 ? cgne_eo<double>(c, M, U, kappa, sp, tol, b, x, st, s)
                                    : cgne_eo<float>(c, M, U, kappa, sp, tol, b, x, st, s);
     }
-    if (sp.inner == WDR_F16 && no_clover(U, "FGCR with the FP16 Schwarz procedure") != WDR_OK) return WDR_EINVAL;
     return fgcr(c, M, U, kappa, sp, tol, b, x, st, s);
 }
 

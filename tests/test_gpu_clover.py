@@ -351,6 +351,62 @@ def test_clover_fgcr_samples(op):
     ctx.close()
 
 
+def test_clover_f16_schwarz_sweeps_in_f32():
+    """With the clover term an F16 inner level runs the Schwarz procedure in
+    FP32 (the FP16 sweep keeps no blocks of A): the same result as F32 bit
+    for bit, and the oracle's within 2e-5."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 531)
+    kappa = 0.135
+    T = oracle.clover_term(lat, U, CSW, kappa)
+    gU = ctx.gauge(dev(U), CSW, kappa)
+    eta = synth.spinor(lat.L, 532)
+    p16 = wdr.default_params(sap_cycles=2, mr_steps=5, inner=2)
+    p32 = wdr.default_params(sap_cycles=2, mr_steps=5, inner=1)
+    got = host(ctx.sap(gU, kappa, dev(eta), p16))
+    want = oracle.sap(lat, U, kappa, eta, 2, 5, clov=T)
+    say("clover F16 sap vs oracle", rel(got, want))
+    assert np.array_equal(got, host(ctx.sap(gU, kappa, dev(eta), p32))) and rel(got, want) < 2e-5
+    del gU
+    ctx.close()
+
+
+@pytest.mark.parametrize("op", ["solve", "SCHUR", "DD"])
+def test_clover_fgcr_f16(op):
+    """FGCR with an F16 inner level on the clover operator: the oracle's
+    clover stencil checks the solve's true residual (<= 1.05e-10) and its
+    solution (1e-8); SCHUR and DD samples within 1e-8 of the oracle's."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 533)
+    kappa = 0.125
+    p = wdr.default_params(solver=0, inner=2, max_iter=2000)
+    gU = ctx.gauge(dev(U), CSW, kappa)
+    if op == "solve":
+        T = oracle.clover_term(lat, U, CSW, kappa)
+        b = synth.spinor(lat.L, 534)
+        x, info = ctx.solve(gU, kappa, dev(b), p)
+        x = host(x)
+        r = np.linalg.norm(b - oracle.apply_D(lat, U, kappa, x, T)) / np.linalg.norm(b)
+        want, _, _, _ = oracle.solve(lat, U, kappa, b, tol=1e-13, clov=T)
+        say("clover fgcr F16 solve", info.as_dict(), "oracle residual", r, "vs oracle", rel(x, want))
+        assert info.converged and r <= 1.05e-10 and rel(x, want) < 1e-8
+        del gU
+        ctx.close()
+        return
+    Up = synth.redraw(U, oracle.active_links(lat), 0.5, 535)
+    gUp = ctx.gauge(dev(Up), CSW, kappa)
+    s, lr, info = ctx.logdet_ratio(gU, gUp, kappa, getattr(wdr, "OP_" + op), 1, 1, wdr.NOISE_GAUSS, 86, p)
+    if op == "DD":
+        wb, _ = oracle.logdet_ratio(lat, U, Up, kappa, oracle.OP_BLOCKS, 1, 1, oracle.NOISE_GAUSS, 86, csw=CSW)
+        ws, _ = oracle.logdet_ratio(lat, U, Up, kappa, oracle.OP_SCHUR, 1, 1, oracle.NOISE_GAUSS, 86, csw=CSW)
+        err = max(np.abs(s[..., :-1] - wb).max(), np.abs(s[..., -1] - ws).max())
+    else:
+        want, _ = oracle.logdet_ratio(lat, U, Up, kappa, oracle.OP_SCHUR, 1, 1, oracle.NOISE_GAUSS, 86, csw=CSW)
+        err = np.abs(s - want).max()
+    say("clover fgcr F16", op, "max |ds|", err, info.as_dict())
+    assert info.converged and err < 1e-8
+    del gU, gUp
+    ctx.close()
+
+
 @pytest.mark.parametrize("middle,bc", [(1, (1, 1, 1, -1)), (0, (1, 1, 1, -1)), (1, (1, -1, 1, -1))])
 def test_clover_f16_cg_solve(middle, bc):
     """CGNE with FP16 steps on the clover operator (A_oo^-1 and A_ee in FP32
@@ -452,10 +508,10 @@ def test_clover_error_paths():
 
     refused(lambda: ctx.apply_D(gU, 0.13, psi))                       # another kappa
     refused(lambda: ctx.apply_D(gU, kappa, psi, wdr.F16))             # FP16 stencil
-    refused(lambda: ctx.sap(gU, kappa, psi, wdr.default_params(inner=2)))          # FP16 Schwarz
-    refused(lambda: ctx.solve(gU, kappa, psi, wdr.default_params(solver=0, inner=2)))
-    refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_SCHUR, 1, 1, 1, 1, wdr.default_params(inner=2)))
-    refused(lambda: ctx.logdet_ratio(gU, gU, kappa, wdr.OP_DD, 1, 1, 1, 1, wdr.default_params(inner=2)))
+    sub = wdr.Context((4, 4, 4, 4), (2, 2, 2, 2), (0, 0, 0, 0))
+    # the clover term of a block needs links outside it: no recursive DD
+    refused(lambda: ctx.block_schur_ratio(gU, gU, kappa, sub, 1, 1, 1, 1, wdr.default_params()))
+    sub.close()
     refused(lambda: ctx.logdet_ratio(gU, gP, kappa, wdr.OP_FULL, 1, 1, 1, 1, wdr.default_params(solver=1)))
     refused(lambda: ctx.block_logdet(gU, 0.13))                           # another kappa
     refused(lambda: ctx.block_logdet_ratio(gU, gP, kappa))                 # csw differs
