@@ -29,6 +29,34 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v, int width)
     return v;
 }
 
+// x moved across lanes by the DPP control CTRL into the rows of ROWS (zero
+// where the source lane lies outside the row, and in the other rows)
+template <int CTRL, int ROWS> __device__ __forceinline__ float dpp_in(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xf, true));
+}
+// the sum over a full wavefront by DPP row shifts and row broadcasts (vector
+// ALU only, no LDS permutes), valid in lane 63
+__device__ __forceinline__ float wave_total63(float v)
+{
+    v += dpp_in<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_in<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_in<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_in<0x118, 0xf>(v);  // row_shr:8: lane 15 of a row holds the row's sum
+    v += dpp_in<0x142, 0xa>(v);  // row_bcast:15, into rows 1 and 3
+    v += dpp_in<0x143, 0xc>(v);  // row_bcast:31, into rows 2 and 3
+    return v;
+}
+// the lane of a wavefront that wave_total returns the full sum in
+template <typename T> constexpr int TOTAL_LANE = sizeof(T) == 4 ? 63 : 0;
+template <typename T> __device__ __forceinline__ T wave_total(T v)
+{
+    if constexpr (sizeof(T) == 4)
+        return wave_total63(v);
+    else
+        return wave_sum(v, 64);
+}
+
 // MODE 0: Schwarz sweep on one colour: r = eta - D x (global stencil on x),
 //         MR on the block, x += d.
 // MODE 1: block MR for a given right-hand side: d = MR(D_b, rhs).
@@ -627,10 +655,10 @@ __global__ __launch_bounds__(4 * Cube<B>::Vh) __attribute__((amdgpu_waves_per_eu
             pi += q.im;
             pp += p[a].re * p[a].re + p[a].im * p[a].im;
         }
-        pr = wave_sum(pr, 64);
-        pi = wave_sum(pi, 64);
-        pp = wave_sum(pp, 64);
-        if ((tid & 63) == 0) {
+        pr = wave_total(pr);
+        pi = wave_total(pi);
+        pp = wave_total(pp);
+        if ((tid & 63) == TOTAL_LANE<T>) {
             S.red[0][tid >> 6] = pr;
             S.red[1][tid >> 6] = pi;
             S.red[2][tid >> 6] = pp;
@@ -839,10 +867,14 @@ __device__ __forceinline__ void hop_phase16(int w4, int par, int h, const h2 *sh
 #pragma unroll
     for (int c = 0; c < 12; ++c) part[(w4 * 12 + c) * Vh + h] = acc[c];
 }
-// spin q of site h summed over the four FP16 partial sums, in FP32
+// spin q of site h summed over the four FP16 partial sums, in FP32: each
+// term enters through a mixed-precision dot product with (1, 0) or (0, 1),
+// the exact value of its FP16 part added to the FP32 sum (one instruction
+// instead of a conversion and an add)
 __device__ __forceinline__ void sum_part16(const h2 *part, int q, int h, cx<float> v[3])
 {
     constexpr int Vh = Cube<4>::Vh;
+    const h2 pick_re = {(_Float16)1, (_Float16)0}, pick_im = {(_Float16)0, (_Float16)1};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int c = 3 * q + a;
@@ -850,8 +882,8 @@ __device__ __forceinline__ void sum_part16(const h2 *part, int q, int h, cx<floa
 #pragma unroll
         for (int d = 0; d < 4; ++d) {
             const h2 t = part[(d * 12 + c) * Vh + h];
-            re += (float)t.x;
-            im += (float)t.y;
+            re = __builtin_amdgcn_fdot2(t, pick_re, re, false);
+            im = __builtin_amdgcn_fdot2(t, pick_im, im, false);
         }
         v[a] = mk<float>(re, im);
     }
@@ -870,7 +902,7 @@ __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu
     __shared__ h2 sho[12 * Vh];
     __shared__ h2 part[4 * 12 * Vh];
     __shared__ float red[4][NT / 64];
-    __shared__ float coef[3];
+    __shared__ float coef[4];
     const int m = blockIdx.y;
     if (active && !active[m]) return;
     if (kap) kappa = (float)kap[m];
@@ -917,18 +949,21 @@ __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu
         del[a] = mk<float>(0, 0);
         rr += rho[a].re * rho[a].re + rho[a].im * rho[a].im;
     }
-    // the first scale from |rho|^2
-    rr = wave_sum(rr, 64);
-    if ((tid & 63) == 0) red[3][tid >> 6] = rr;
+    // the first scale from |rho|^2 (coef[2]: a power of two, coef[3] its
+    // inverse)
+    rr = wave_total63(rr);
+    if ((tid & 63) == 63) red[3][tid >> 6] = rr;
     __syncthreads();
     if (tid == 0) {
         float t = 0.f;
 #pragma unroll
         for (int w = 0; w < NT / 64; ++w) t += red[3][w];
-        coef[2] = t > 0.f ? exp2f(-rintf(0.5f * log2f(t / (12.f * Vh)))) : 1.f;
+        const float e = t > 0.f ? rintf(0.5f * log2f(t / (12.f * Vh))) : 0.f;
+        coef[2] = exp2f(-e);
+        coef[3] = exp2f(e);
     }
     __syncthreads();
-    float sig = coef[2];
+    float sig = coef[2], isig = coef[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) she[(3 * w4 + a) * Vh + h] = to16(rho[a], sig);
 
@@ -944,7 +979,6 @@ __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu
         hop_phase16(w4, 0, h, sho, R, part);  // sigma H_eo H_oe rho
         __syncthreads();
         sum_part16(part, w4, h, v);
-        const float isig = 1.f / sig;
         float pr = 0, pi = 0, pp = 0, r2 = 0;
         cx<float> p[3];
 #pragma unroll
@@ -956,11 +990,11 @@ __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu
             pp += p[a].re * p[a].re + p[a].im * p[a].im;
             r2 += rho[a].re * rho[a].re + rho[a].im * rho[a].im;
         }
-        pr = wave_sum(pr, 64);
-        pi = wave_sum(pi, 64);
-        pp = wave_sum(pp, 64);
-        r2 = wave_sum(r2, 64);
-        if ((tid & 63) == 0) {
+        pr = wave_total63(pr);
+        pi = wave_total63(pi);
+        pp = wave_total63(pp);
+        r2 = wave_total63(r2);
+        if ((tid & 63) == 63) {
             red[0][tid >> 6] = pr;
             red[1][tid >> 6] = pi;
             red[2][tid >> 6] = pp;
@@ -979,11 +1013,14 @@ __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu
             coef[0] = sq > 0 ? sr / sq : 0.f;
             coef[1] = sq > 0 ? si / sq : 0.f;
             // |rho_new|^2 <= |rho|^2: the scale of the next stored iterate
-            coef[2] = st > 0.f ? exp2f(-rintf(0.5f * log2f(st / (12.f * Vh)))) : 1.f;
+            const float e = st > 0.f ? rintf(0.5f * log2f(st / (12.f * Vh))) : 0.f;
+            coef[2] = exp2f(-e);
+            coef[3] = exp2f(e);
         }
         __syncthreads();
         const cx<float> al = mk<float>(coef[0], coef[1]);
         sig = coef[2];
+        isig = coef[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             del[a] = del[a] + al * rho[a];
