@@ -889,6 +889,16 @@ __device__ __forceinline__ void sum_part16(const h2 *part, int q, int h, cx<floa
     }
 }
 __device__ __forceinline__ h2 to16(cx<float> a, float f) { return (h2){(_Float16)(a.re * f), (_Float16)(a.im * f)}; }
+// the power of two 2^-e that brings a block's RMS component, sqrt(st / 1536)
+// over the 12 x 128 components of a block half, to about 1, and 2^e (both
+// exact)
+__device__ __forceinline__ void rms_scale16(float st, float *out)
+{
+    constexpr float LOG2_1536 = 10.5849625007f;
+    const int e = st > 0.f ? (int)rintf(0.5f * (log2f(st) - LOG2_1536)) : 0;
+    out[0] = ldexpf(1.f, -e);
+    out[1] = ldexpf(1.f, e);
+}
 
 template <int OCC>
 __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu(OCC))) void k_block_mr_h16(
@@ -955,12 +965,10 @@ __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu
     if ((tid & 63) == 63) red[3][tid >> 6] = rr;
     __syncthreads();
     if (tid == 0) {
-        float t = 0.f;
+        float t = red[3][0];
 #pragma unroll
-        for (int w = 0; w < NT / 64; ++w) t += red[3][w];
-        const float e = t > 0.f ? rintf(0.5f * log2f(t / (12.f * Vh))) : 0.f;
-        coef[2] = exp2f(-e);
-        coef[3] = exp2f(e);
+        for (int w = 1; w < NT / 64; ++w) t += red[3][w];
+        rms_scale16(t, coef + 2);
     }
     __syncthreads();
     float sig = coef[2], isig = coef[3];
@@ -1001,21 +1009,19 @@ __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu
             red[3][tid >> 6] = r2;
         }
         __syncthreads();
-        if (tid == 0) {
-            float sr = 0, si = 0, sq = 0, st = 0;
+        if (tid == 0) {  // one lane: the step's coefficient and the next scale
+            float sr = red[0][0], si = red[1][0], sq = red[2][0], st = red[3][0];
 #pragma unroll
-            for (int w = 0; w < NT / 64; ++w) {
+            for (int w = 1; w < NT / 64; ++w) {
                 sr += red[0][w];
                 si += red[1][w];
                 sq += red[2][w];
                 st += red[3][w];
             }
-            coef[0] = sq > 0 ? sr / sq : 0.f;
-            coef[1] = sq > 0 ? si / sq : 0.f;
+            coef[0] = sq > 0 ? __fdividef(sr, sq) : 0.f;
+            coef[1] = sq > 0 ? __fdividef(si, sq) : 0.f;
             // |rho_new|^2 <= |rho|^2: the scale of the next stored iterate
-            const float e = st > 0.f ? rintf(0.5f * log2f(st / (12.f * Vh))) : 0.f;
-            coef[2] = exp2f(-e);
-            coef[3] = exp2f(e);
+            rms_scale16(st, coef + 2);
         }
         __syncthreads();
         const cx<float> al = mk<float>(coef[0], coef[1]);
