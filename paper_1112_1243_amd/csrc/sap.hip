@@ -787,24 +787,34 @@ __device__ __forceinline__ void load_hop_regs16(const h2 *U16, int slot, int h, 
         const int l = par * CB::Vh + h;
         const int off = par ? 0 : CB::Vh;  // the neighbours have the other parity
         int y[4] = {x[0], x[1], x[2], x[3]};
-        R.nf[par] = R.nb[par] = -1;
+        // a hop that leaves the block keeps LDS index 0 and a zero link: it
+        // adds exact zeros, so every lane takes both hops without a branch
+        R.nf[par] = R.nb[par] = 0;
         if (x[MU] + 1 < 4) {
             y[MU] = x[MU] + 1;
             R.nf[par] = CB::index(y) - off;
             load_link16<MU>(U16, slot, l, R.f[par]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) R.f[par][e] = (h2){0, 0};
         }
         if (x[MU] > 0) {
             y[MU] = x[MU] - 1;
             const int nl = CB::index(y);
             R.nb[par] = nl - off;
             load_link16<MU>(U16, slot, nl, R.b[par]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 9; ++e) R.b[par][e] = (h2){0, 0};
         }
     }
 }
 
 // the in-block hops of direction MU at one output site: neighbours from the
-// FP16 LDS half field sh ([12][Vh]), links from registers; the sum of the
-// (at most two) hops into acc (12 FP16 complex, component 3 spin + colour)
+// FP16 LDS half field sh ([12][Vh]), links from registers; the sum of the two
+// hops into acc (12 FP16 complex, component 3 spin + colour).  Both hops are
+// always taken (one that leaves the block has a zero link), so acc starts
+// from the forward hop's values and no lane branches.
 template <int MU>
 __device__ __forceinline__ void hop_dir16(const h2 *sh, const h2 *uf, const h2 *ub, int nf, int nb, h2 acc[12])
 {
@@ -813,13 +823,11 @@ __device__ __forceinline__ void hop_dir16(const h2 *sh, const h2 *uf, const h2 *
     constexpr int m0 = MU == 0 ? 3 : MU == 1 ? 1 : MU == 2 ? 3 : 0, m1 = MU == 0 ? 3 : MU == 1 ? 0 : MU == 2 ? 2 : 0;
     constexpr int r0 = MU == 0 ? 2 : MU == 1 ? 0 : MU == 2 ? 2 : 0, r1 = MU == 0 ? 2 : MU == 1 ? 1 : MU == 2 ? 3 : 0;
     constexpr int j0 = MU <= 1 ? 1 : 0, j1 = MU <= 1 ? 0 : 1;  // A^+ h takes (c_j0, c_j1)
-#pragma unroll
-    for (int a = 0; a < 12; ++a) acc[a] = (h2){0, 0};
+    h2 lo[6];  // spins 2, 3 of the forward hop before their sign
 #pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
         const bool fwd = dir == 0;
         const int nl = fwd ? nf : nb;
-        if (nl < 0) continue;
         h2 p[12];
 #pragma unroll
         for (int c = 0; c < 12; ++c) p[c] = sh[c * Vh + nl];
@@ -841,14 +849,21 @@ __device__ __forceinline__ void hop_dir16(const h2 *sh, const h2 *uf, const h2 *
                 for (int b = 0; b < 3; ++b) r = fwd ? hcfma(u[3 * a + b], hh[s][b], r) : hcjfma(u[3 * b + a], hh[s][b], r);
                 c[s][a] = r;
             }
-        // spins 2, 3: -+ A^+ c
+        // spins 2, 3: -A^+ c of the forward hop, +A^+ c of the backward one
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            acc[a] = acc[a] + c[0][a];
-            acc[3 + a] = acc[3 + a] + c[1][a];
             const h2 d0 = hmap(c[j0][a], r0), d1 = hmap(c[j1][a], r1);
-            acc[6 + a] = fwd ? acc[6 + a] - d0 : acc[6 + a] + d0;
-            acc[9 + a] = fwd ? acc[9 + a] - d1 : acc[9 + a] + d1;
+            if (fwd) {
+                acc[a] = c[0][a];
+                acc[3 + a] = c[1][a];
+                lo[a] = d0;
+                lo[3 + a] = d1;
+            } else {
+                acc[a] = acc[a] + c[0][a];
+                acc[3 + a] = acc[3 + a] + c[1][a];
+                acc[6 + a] = d0 - lo[a];
+                acc[9 + a] = d1 - lo[3 + a];
+            }
         }
     }
 }
