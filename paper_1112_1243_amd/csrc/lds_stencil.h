@@ -127,18 +127,19 @@ __device__ __forceinline__ void hop_dir_lds_rt(int mu, const typename C2<T>::typ
 
 // The two in-block hops of direction MU at one site with the links held in
 // registers: uf = U_mu(x), ub = U_mu(x - mu) (all three rows), nf / nb the
-// LDS indices (in sh, [12][Vh]) of x + mu and x - mu, or -1 where that hop
-// leaves the block.  Added to acc.
+// LDS indices (in sh, [12][Vh]) of x + mu and x - mu.  A hop that leaves the
+// block comes with a zero link and a valid index, so both hops are always
+// taken and no lane branches.  Their sum is written to acc.
 template <typename T, int MU>
 __device__ __forceinline__ void hop_dir_reg(const typename C2<T>::type *sh, int Vh, const su3<T> &uf,
                                             const su3<T> &ub, int nf, int nb, spinor<T> &acc)
 {
     LdsLoader<T> ldr{sh, Vh, 0};
+    vec3<T> lo0, lo1;  // spins 2, 3 of the forward hop before their sign
 #pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
         const bool fwd = dir == 0;
         const int nl = fwd ? nf : nb;
-        if (nl < 0) continue;
         spinor<T> p;
         ldr(0, nl, p);
         vec3<T> a0, a1;
@@ -155,10 +156,17 @@ __device__ __forceinline__ void hop_dir_reg(const typename C2<T>::type *sh, int 
         Adag_h(MU, c0, c1, d0, d1);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
-            acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
-            acc.s[2].c[a] = fwd ? acc.s[2].c[a] - d0.c[a] : acc.s[2].c[a] + d0.c[a];
-            acc.s[3].c[a] = fwd ? acc.s[3].c[a] - d1.c[a] : acc.s[3].c[a] + d1.c[a];
+            if (fwd) {
+                acc.s[0].c[a] = c0.c[a];
+                acc.s[1].c[a] = c1.c[a];
+                lo0.c[a] = d0.c[a];
+                lo1.c[a] = d1.c[a];
+            } else {
+                acc.s[0].c[a] = acc.s[0].c[a] + c0.c[a];
+                acc.s[1].c[a] = acc.s[1].c[a] + c1.c[a];
+                acc.s[2].c[a] = d0.c[a] - lo0.c[a];
+                acc.s[3].c[a] = d1.c[a] - lo1.c[a];
+            }
         }
     }
 }

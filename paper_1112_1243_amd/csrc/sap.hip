@@ -393,11 +393,18 @@ template <typename T, int B> struct DirLds {
 // The links and LDS neighbour indices of thread (MU, h) of k_block_mr_dir:
 // entry p is for the output site h of parity p (even xe / odd xo): forward
 // link U_mu(x), backward link U_mu(x - mu), and the indices of x + mu and
-// x - mu in the LDS half field of the other parity (-1: outside the block).
+// x - mu in the LDS half field of the other parity (a hop that leaves the
+// block: index 0 and a zero link).
 template <typename T> struct HopRegs {
     su3<T> f[2], b[2];
     int nf[2], nb[2];
 };
+
+template <typename T> __device__ __forceinline__ void zero_link(su3<T> &u)
+{
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u.m[e / 3][e % 3] = mk<T>(0, 0);
+}
 
 // reads the first two rows of the link at site l, direction MU, and rebuilds
 // the third (in-block links never carry the boundary sign)
@@ -430,29 +437,35 @@ __device__ __forceinline__ void load_hop_regs(const void *Utab_m, int slot, int 
         const int l = par * CB::Vh + h;
         const int off = par ? 0 : CB::Vh;  // the neighbours have the other parity
         int y[4] = {x[0], x[1], x[2], x[3]};
-        R.nf[par] = R.nb[par] = -1;
+        // a hop that leaves the block keeps LDS index 0 and a zero link: it
+        // adds exact zeros, so every lane takes both hops without a branch
+        R.nf[par] = R.nb[par] = 0;
         if (x[MU] + 1 < B) {
             y[MU] = x[MU] + 1;
             R.nf[par] = CB::index(y) - off;
             load_link_rows<T, B, MU, ST>(Utab_m, slot, l, R.f[par]);
+        } else {
+            zero_link(R.f[par]);
         }
         if (x[MU] > 0) {
             y[MU] = x[MU] - 1;
             const int nl = CB::index(y);
             R.nb[par] = nl - off;
             load_link_rows<T, B, MU, ST>(Utab_m, slot, nl, R.b[par]);
+        } else {
+            zero_link(R.b[par]);
         }
     }
 }
 
 // hop phase of thread (mu, h): the in-block hops of direction mu at site h of
-// parity par, neighbours from the LDS half field sh of the other parity
+// parity par, neighbours from the LDS half field sh of the other parity,
+// written to acc
 template <typename T, int B>
 __device__ __forceinline__ void hop_reg_rt(int mu, int par, const typename C2<T>::type *sh, const HopRegs<T> &R,
                                            spinor<T> &acc)
 {
     constexpr int Vh = Cube<B>::Vh;
-    zero(acc);
     switch (mu) {
     case 0: hop_dir_reg<T, 0>(sh, Vh, R.f[par], R.b[par], R.nf[par], R.nb[par], acc); break;
     case 1: hop_dir_reg<T, 1>(sh, Vh, R.f[par], R.b[par], R.nf[par], R.nb[par], acc); break;
