@@ -754,12 +754,11 @@ static wdr_status cgne_eo(wdr_ctx *c, int M, const GaugeTab &U, double kappa, co
         set_error(std::string("cooperative launch of the CG steps refused: ") + hipGetErrorString(persist_err));
         return WDR_EDEVICE;
     }
-    // x_o = A_oo^-1 (b_o + k H_oe x_e)
-    launch_zero<double>(t64, total, s);
+    // x_o = A_oo^-1 (b_o + k H_oe x_e), written into the odd sites of x in
+    // place: the launch reads only the even sites of x
     Links<double> U64i = U64n;
     U64i.cmode = CLOV_INV;
-    launch_dslash<double>(g, all, U64i, op.hops, 1, 0, x, b, t64, -kappa, o0, on, s);
-    launch_add_to64<double>(all, t64, x, s);
+    launch_dslash<double>(g, all, U64i, op.hops, 1, 0, x, b, x, -kappa, o0, on, s);
 
     std::vector<double> hbn2(M), rn2;
     std::vector<int32_t> hits(M), hupd(M);
@@ -1029,12 +1028,11 @@ static wdr_status cgne_eo16(wdr_ctx *c, int M, const GaugeTab &U, double kappa, 
             }
         }
     }
-    // x_o = A_oo^-1 (b_o + k H_oe x_e)
-    launch_zero<double>(t64, total, s);
+    // x_o = A_oo^-1 (b_o + k H_oe x_e), written into the odd sites of x in
+    // place: the launch reads only the even sites of x
     Links<double> U64i = U64n;
     U64i.cmode = CLOV_INV;
-    launch_dslash<double>(g, all, U64i, HOPS_ALL, 1, 0, x, b, t64, -kappa, 0, g.nblk, s);
-    launch_add_to64<double>(all, t64, x, s);
+    launch_dslash<double>(g, all, U64i, HOPS_ALL, 1, 0, x, b, x, -kappa, 0, g.nblk, s);
 
     std::vector<double> hbn2(M), rn2;
     std::vector<int32_t> hits(M), hmid(M), hout(M);
