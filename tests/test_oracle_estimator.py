@@ -219,8 +219,33 @@ def test_logdet_ratio_mean_over_seeds():
 
 
 def test_combine_log_mean_exp():
-    s = np.array([[0.1, -0.3, 0.2], [1.0, 1.5, -2.0]])
-    want = np.log(np.mean(np.exp(s[0]))) + np.log(np.mean(np.exp(s[1])))
-    assert abs(oracle.combine(s) - want) < 1e-14
-    big = np.array([[800.0, 801.0]])
-    assert np.isfinite(oracle.combine(big))
+    """The combination of eq. param (the product over factors of the noise
+    average of exp(sample), Sec. 4), pinned by facts that do not retype it:
+    hand-computed cases, invariances, overflow-safe values and the law of
+    large numbers for log-normal samples."""
+    # hand-computed: log((1 + 3) / 2) = log 2, and a constant factor is itself
+    assert abs(oracle.combine(np.array([[0.0, np.log(3.0)]])) - np.log(2.0)) < 1e-15
+    assert abs(oracle.combine(np.array([[0.7, 0.7, 0.7], [-1.2, -1.2, -1.2]])) - (0.7 - 1.2)) < 1e-15
+    # factors add, noise vectors average: reordering the noise vectors of a
+    # factor changes nothing, shifting a factor's samples by c shifts log R by c
+    rng = np.random.Generator(np.random.Philox(key=[3, 5]))
+    s = rng.normal(0.0, 1.0, (4, 6))
+    base = oracle.combine(s)
+    assert abs(oracle.combine(s[:, ::-1]) - base) < 1e-13
+    assert abs(oracle.combine(s + np.array([[0.5], [0.0], [-2.0], [1.0]])) - (base - 0.5)) < 1e-13
+    assert abs(oracle.combine(s[:2]) + oracle.combine(s[2:]) - base) < 1e-13
+    # Jensen: the log of the mean exceeds the mean of the logs (unbiased in R,
+    # not in log R), equal only for constant samples
+    assert base > s.mean(axis=1).sum()
+    # samples near 800 overflow exp in FP64: the value must still be exact
+    assert abs(oracle.combine(np.array([[800.0, 801.0]])) - (800.0 + np.log((1.0 + np.e) / 2.0))) < 1e-12
+    # log-normal samples: E exp(s) = exp(mu + sigma^2 / 2) for s ~ N(mu, sigma^2)
+    mu, sig = -0.4, 0.6
+    big = rng.normal(mu, sig, (1, 400000))
+    assert abs(oracle.combine(big) - (mu + sig * sig / 2)) < 5e-3
+    # the blocks axis of a DD estimate is carried through factor by factor
+    s3 = rng.normal(0.0, 1.0, (3, 5, 2))
+    got = oracle.combine(s3)
+    assert got.shape == (2,)
+    for b in range(2):
+        assert abs(got[b] - oracle.combine(s3[:, :, b])) < 1e-13
