@@ -247,9 +247,10 @@ int32_t wdr_gauge_is_su3(const wdr_gauge *g);
  * diagonal term), wdr_solve with CGNE or FGCR and wdr_sap (the Schwarz
  * blocks take the one-lane-per-site block MR; an F16 inner level sweeps in
  * F32 there, since the FP16 sweep keeps no blocks of A beside its fields),
- * wdr_block_solve and wdr_apply_schur (the
+ * wdr_block_solve and wdr_apply_schur (with an F64 / F32 inner level the
  * block solves then run as FP64 defect correction around an even-odd CGNE of
- * the block operator, FP32 for an F16 inner level), and FULL, BLOCKS, SCHUR and DD
+ * the block operator; with F16 the FP16 block MR keeps A_ee - 1 and A_oo^-1
+ * of the block as FP16 in LDS), and FULL, BLOCKS, SCHUR and DD
  * estimates by such solves (wdr_logdet_ratio / _batch; both fields of a
  * ratio must carry the same csw), and the exact
  * block determinants (wdr_block_logdet / _ratio: det D_b = det A_oo det
@@ -423,9 +424,9 @@ wdr_status wdr_solve(wdr_ctx *ctx, const wdr_gauge *U, double kappa, const wdr_s
  * the Dirichlet block operators D_b on the diagonal, so their inverses in
  * eq. ddfactor are independent block solves): x = D_cc^-1 b on those blocks,
  * zero elsewhere; per-block relative residual <= block_tol.  Even-odd MR
- * rounds in sp->inner with FP64 defect correction (with a clover term:
- * rounds of even-odd CGNE on the blocks of the colour, sp->inner F64 or
- * F32).  ENOCONV if a block stops above block_tol. */
+ * rounds in sp->inner with FP64 defect correction (with a clover term and
+ * sp->inner F64 or F32: rounds of even-odd CGNE on the blocks of the
+ * colour).  ENOCONV if a block stops above block_tol. */
 wdr_status wdr_block_solve(wdr_ctx *ctx, const wdr_gauge *U, double kappa, int32_t colour,
                            const wdr_solver_params *sp, const double *dev_b, double *dev_x,
                            wdr_solve_info *host_info, void *stream);

@@ -274,10 +274,11 @@ void launch_zero_h16(const Geo &g, const Sys &sy, H16 f, hipStream_t s);
 // FP16 copy of the first two rows of the internal FP64 links
 void launch_pack_links_h16(const Geo &g, const double2 *u64, h2 *u16, hipStream_t s);
 // block MR with FP16 storage (4^4 blocks, SU(3) links): mode 0 is the Schwarz
-// sweep of launch_sap_colour, mode 1 the block MR of launch_block_mr; false
-// if the geometry or the links do not allow it
+// sweep of launch_sap_colour, mode 1 the block MR of launch_block_mr (ctab:
+// the FP32 clover fields per system for the clover operator, mode 1 only);
+// false if the geometry or the links do not allow it
 bool launch_mr_h16(int mode, const Geo &g, const Sys &sy, Links16 U, H16c src, H16 dst, float kappa, int nmr,
-                   int slot0, int nslots, hipStream_t s);
+                   int slot0, int nslots, hipStream_t s, const float *const *ctab = nullptr);
 
 // ---------------------------------------------------------------- FP16 even-odd CG
 // One parity of every block in FP16, site-major ([M][slot][Vh][12] complex,

@@ -928,11 +928,51 @@ __device__ __forceinline__ void rms_scale16(float st, float *out)
     out[1] = ldexpf(1.f, e);
 }
 
-template <int OCC>
+// rows 3P, 3P + 1, 3P + 2 (spin 2 chi + P, colours 0-2) of one packed
+// hermitian 6 x 6 clover block held in LDS as FP16 (the layout of clover.h,
+// entries Vh apart) times the chirality's 6-vector x, in FP32
+template <int P>
+__device__ __forceinline__ void clov_rows16(const _Float16 *M, const cx<float> x[6], cx<float> y[3])
+{
+    constexpr int Vh = Cube<4>::Vh;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const int i = 3 * P + r;
+        cx<float> acc = scale((float)M[i * Vh], x[i]);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            if (j == i) continue;
+            const int k = j > i ? herm_k(i, j) : herm_k(j, i);
+            const float re = (float)M[(6 + 2 * k) * Vh], im = (float)M[(7 + 2 * k) * Vh];
+            acc = acc + mk<float>(re, j > i ? im : -im) * x[j];  // M_ij, or conj(M_ji) below the diagonal
+        }
+        y[r] = acc;
+    }
+}
+__device__ __forceinline__ void clov_rows16(int p, const _Float16 *M, const cx<float> x[6], cx<float> y[3])
+{
+    if (p)
+        clov_rows16<1>(M, x, y);
+    else
+        clov_rows16<0>(M, x, y);
+}
+
+// CL = 1: with the clover term (ctab: FP32 clover fields per system, A then
+// A^-1, clover.h).  The block system is then D_b = A - kappa H_in and the MR
+// runs on A_ee - kappa^2 H_eo A_oo^-1 H_oe with rhs_e = r_e + kappa H_eo
+// A_oo^-1 r_o and d_o = A_oo^-1 (r_o + kappa H_oe d_e).  The blocks that
+// enter, A_ee - 1 of the even sites and A_oo^-1 of the odd ones, are read
+// once per launch into LDS as FP16 (36 KB beside the 37 KB of the fields
+// and partial sums: still two blocks per CU).  A thread owns one spin, so
+// where a 6 x 6 block acts it sums the partial sums of both spins of its
+// chirality (after a hop phase) or reads them from the LDS copy of the
+// iterate (A_ee - 1 acting on it, in FP16 like the hops).
+template <int OCC, int CL>
 __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu(OCC))) void k_block_mr_h16(
     Geo g, const int32_t *__restrict__ active, const void *const *__restrict__ Utab, const double *__restrict__ kap,
-    long n, const int32_t *__restrict__ sched, const void *__restrict__ src_v, const float *__restrict__ src_s,
-    void *__restrict__ dst_v, float *__restrict__ dst_s, float kappa, int nmr)
+    const float *const *__restrict__ ctab, long n, const int32_t *__restrict__ sched,
+    const void *__restrict__ src_v, const float *__restrict__ src_s, void *__restrict__ dst_v,
+    float *__restrict__ dst_s, float kappa, int nmr)
 {
     typedef Cube<4> CB;
     constexpr int Vb = CB::Vb, Vh = CB::Vh, NT = 4 * Vh;
@@ -941,6 +981,8 @@ __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu
     __shared__ h2 part[4 * 12 * Vh];
     __shared__ float red[4][NT / 64];
     __shared__ float coef[4];
+    // [parity][chirality][36][Vh]: A_ee - 1 (even sites), A_oo^-1 (odd)
+    __shared__ _Float16 clv[CL ? 2 * 72 * Vh : 1];
     const int m = blockIdx.y;
     if (active && !active[m]) return;
     if (kap) kappa = (float)kap[m];
@@ -965,6 +1007,21 @@ __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu
     case 2: load_hop_regs16<2>(U16, slot, h, xe, xo, R); break;
     default: load_hop_regs16<3>(U16, slot, h, xe, xo, R); break;
     }
+    // the spin's chirality and its place in the chirality (clover term)
+    const int chi = w4 >> 1, pq = w4 & 1;
+    const int tee = chi * 36 * Vh + h, aoi = (72 + chi * 36) * Vh + h;  // clv offsets of site h
+    if constexpr (CL) {
+        // flat index f = (chirality * 36 + entry) * Vb + site of the block,
+        // even sites from A (diagonal minus 1), odd ones from A^-1
+        const auto *cb = as_global(ctab[m]);
+        const long base = (long)slot * 72 * Vb, inv = 72L * g.V;
+        for (int f = tid; f < 72 * Vb; f += NT) {
+            const int l = f % Vb, ck = f / Vb, par = l >= Vh ? 1 : 0;
+            float val = cb[base + f + (par ? inv : 0)];
+            if (!par && ck % 36 < 6) val -= 1.f;
+            clv[(par * 72 + ck) * Vh + l - par * Vh] = (_Float16)val;
+        }
+    }
     // the right-hand side as stored (|value| <= 1): spin q of site h
     cx<float> re[3], ro[3], v[3];
 #pragma unroll
@@ -975,7 +1032,20 @@ __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu
         sho[(3 * w4 + a) * Vh + h] = y;
     }
     __syncthreads();
-    // rhs_e = r_e + kappa H_eo r_o
+    if constexpr (CL) {  // sho <- A_oo^-1 r_o
+        cx<float> x6[6], y[3];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const h2 t = sho[(6 * chi + c) * Vh + h];
+            x6[c] = mk<float>((float)t.x, (float)t.y);
+        }
+        clov_rows16(pq, clv + aoi, x6, y);
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sho[(3 * w4 + a) * Vh + h] = to16(y[a], 1.f);
+        __syncthreads();
+    }
+    // rhs_e = r_e + kappa H_eo r_o (H_eo A_oo^-1 r_o with the clover term)
     hop_phase16(w4, 0, h, sho, R, part);
     __syncthreads();
     cx<float> rho[3], del[3];
@@ -1008,18 +1078,36 @@ __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu
         __syncthreads();
         hop_phase16(w4, 1, h, she, R, part);  // t_o = sigma H_oe rho
         __syncthreads();
-        sum_part16(part, w4, h, v);
+        if constexpr (CL) {  // t_o <- A_oo^-1 t_o
+            cx<float> x6[6];
+            sum_part16(part, 2 * chi, h, x6);
+            sum_part16(part, 2 * chi + 1, h, x6 + 3);
+            clov_rows16(pq, clv + aoi, x6, v);
+        } else {
+            sum_part16(part, w4, h, v);
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) sho[(3 * w4 + a) * Vh + h] = to16(v[a], 1.f);
         __syncthreads();
         hop_phase16(w4, 0, h, sho, R, part);  // sigma H_eo H_oe rho
         __syncthreads();
         sum_part16(part, w4, h, v);
+        cx<float> td[3];  // (A_ee - 1) rho, from the stored iterate
+        if constexpr (CL) {
+            cx<float> x6[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const h2 t = she[(6 * chi + c) * Vh + h];
+                x6[c] = mk<float>((float)t.x * isig, (float)t.y * isig);
+            }
+            clov_rows16(pq, clv + tee, x6, td);
+        }
         float pr = 0, pi = 0, pp = 0, r2 = 0;
         cx<float> p[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             p[a] = rho[a] - scale(k2 * isig, v[a]);
+            if constexpr (CL) p[a] = p[a] + td[a];
             const cx<float> q = conjmul(p[a], rho[a]);
             pr += q.re;
             pi += q.im;
@@ -1084,11 +1172,28 @@ __global__ __launch_bounds__(4 * Cube<4>::Vh) __attribute__((amdgpu_waves_per_eu
     sum_part16(part, w4, h, v);
     // the new values of spin q at even site h (ye) and odd site h (yo)
     cx<float> ye[3], yo[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) yo[a] = ro[a] + scale(kappa * sd, v[a]);
+    if constexpr (CL) {  // yo <- A_oo^-1 yo, the chirality's other spin through LDS (FP32)
+        float *wb = reinterpret_cast<float *>(part);
+        __syncthreads();  // every lane has read the partial sums
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            wb[2 * ((3 * w4 + a) * Vh + h)] = yo[a].re;
+            wb[2 * ((3 * w4 + a) * Vh + h) + 1] = yo[a].im;
+        }
+        __syncthreads();
+        cx<float> x6[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            x6[c] = mk<float>(wb[2 * ((6 * chi + c) * Vh + h)], wb[2 * ((6 * chi + c) * Vh + h) + 1]);
+        clov_rows16(pq, clv + aoi, x6, yo);
+    }
     float mo = 0.f;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         ye[a] = scale(s_src, del[a]);
-        yo[a] = scale(s_src, ro[a] + scale(kappa * sd, v[a]));
+        yo[a] = scale(s_src, yo[a]);
         mo = fmaxf(mo, fmaxf(fmaxf(fabsf(ye[a].re), fabsf(ye[a].im)), fmaxf(fabsf(yo[a].re), fabsf(yo[a].im))));
     }
 #pragma unroll
@@ -1178,23 +1283,31 @@ void launch_block_mr(const Geo &g, const Sys &sy, Links<T> U, const T2<T> *r, T2
 }
 
 bool launch_mr_h16(int mode, const Geo &g, const Sys &sy, Links16 U, H16c src, H16 dst, float kappa, int nmr,
-                   int slot0, int nslots, hipStream_t s)
+                   int slot0, int nslots, hipStream_t s, const float *const *ctab)
 {
     if (nslots <= 0 || sy.M <= 0) return true;
     if (!U.tab || g.B[0] != 4 || g.B[1] != 4 || g.B[2] != 4 || g.B[3] != 4) return false;
+    if (mode == 0 && ctab) return false;  // the FP16 Schwarz sweep has no clover form
     const int si = sched_index(g, slot0, nslots);
     if (si < 0) return false;
     const dim3 grid(nslots, sy.M);
     const auto *tab = reinterpret_cast<const void *const *>(U.tab);
+    const bool two = two_per_cu(g, (long)nslots * sy.M);
+#define WDR_MR16(OCC, CL)                                                                                    \
+    k_block_mr_h16<OCC, CL><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, ctab, sy.n, g.sched[si], \
+                                                             src.v, src.s, dst.v, dst.s, kappa, nmr)
     if (mode == 0)
         k_block_mr_dir<float, 0, 4, 1><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si],
                                                                        src.v, src.s, dst.v, dst.s, kappa, nmr);
-    else if (two_per_cu(g, (long)nslots * sy.M))
-        k_block_mr_h16<4><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si], src.v, src.s,
-                                                            dst.v, dst.s, kappa, nmr);
+    else if (ctab && two)
+        WDR_MR16(4, 1);
+    else if (ctab)
+        WDR_MR16(1, 1);
+    else if (two)
+        WDR_MR16(4, 0);
     else
-        k_block_mr_h16<1><<<grid, 4 * Cube<4>::Vh, 0, s>>>(g, sy.active, tab, U.kap, sy.n, g.sched[si], src.v, src.s,
-                                                            dst.v, dst.s, kappa, nmr);
+        WDR_MR16(1, 0);
+#undef WDR_MR16
     return true;
 }
 

@@ -1101,13 +1101,14 @@ wdr_status solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, const wdr
 // usual block tolerances
 constexpr double BLOCK_EO_TOL = 1e-7;
 
-// Dirichlet block solves with the clover term (its 6 x 6 blocks per site do
-// not fit beside the block MR's fields in LDS): defect correction in FP64
-// around the even-odd CGNE of the block operator D_b = A - kappa H_in on the
-// blocks of the colour, all of them one block-diagonal system.  Each round
-// solves D_b d = r to a relative residual max(tol / 2, BLOCK_EO_TOL) with
-// sp.inner iterations (FP32 for an FP16 inner level) and FP64 reliable
-// updates, adds d to x and forms the
+// Dirichlet block solves with the clover term and an F64 / F32 inner level
+// (the 6 x 6 blocks per site in those precisions do not fit beside the
+// block MR's fields in LDS; the FP16 block MR keeps them as FP16): defect
+// correction in FP64 around the even-odd CGNE of the block operator D_b = A -
+// kappa H_in on the blocks of the colour, all of them one block-diagonal
+// system.  Each round solves D_b d = r to a relative residual max(tol / 2,
+// BLOCK_EO_TOL) with sp.inner iterations and FP64 reliable updates, adds d
+// to x and forms the
 // FP64 residual r = b - D_b x block by block; as in the MR rounds, the worst
 // block ratio |r_b| / |b_b| decides.  Systems that have converged get r = 0,
 // which their next CG ends at once.
@@ -1146,7 +1147,6 @@ static wdr_status block_solve_clover(wdr_ctx *c, int M, const GaugeTab &U, doubl
     for (int round = 0; round < 40; ++round) {
         k_zero_dead<<<nb256(total), 256, 0, s>>>(alive, n, total, r);
         std::vector<Stats> si;
-        // (an FP16 inner level takes FP32 CG steps here: the FP16 block MR has no clover term)
         const wdr_status e = sp.inner == WDR_F64 ? cgne_eo<double>(c, M, U, kappa, sp, tin, r, d, si, s, op)
                                                  : cgne_eo<float>(c, M, U, kappa, sp, tin, r, d, si, s, op);
         if (e != WDR_OK && e != WDR_ENOCONV) return e;
@@ -1199,7 +1199,12 @@ static wdr_status block_solve_clover(wdr_ctx *c, int M, const GaugeTab &U, doubl
 wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int colour, const wdr_solver_params &sp,
                          double tol, const double2 *b, double2 *x, std::vector<Stats> &st, hipStream_t s)
 {
-    if (U.u64.ctab) return block_solve_clover(c, M, U, kappa, colour, sp, tol, b, x, st, s);
+    // the clover term: CG rounds for F64 / F32 inner levels, the FP16 block
+    // MR (with the blocks of A in LDS) for F16
+    if (U.u64.ctab && sp.inner != WDR_F16) return block_solve_clover(c, M, U, kappa, colour, sp, tol, b, x, st, s);
+    const bool clov = U.u64.ctab != nullptr;
+    Links<double> Ud = U.u64;  // D_b with its diagonal A where the term is present
+    if (clov) Ud.cmode = CLOV_DIAG;
     const auto &g = c->g;
     int slot0, ns;
     colour_slots(c, colour, slot0, ns);
@@ -1245,10 +1250,11 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
             launch_add_to64<double>(sa, d64.as<double2>(), x, s);
         } else if (sp.inner == WDR_F16) {
             if (!round16) launch_to_h16<double>(g, sa, r, r16->f(), slot0, ns, s);
-            if (!launch_mr_h16(1, g, sa, U.u16, r16->cf(), d16->f(), (float)kappa, nmr, slot0, ns, s))
+            if (!launch_mr_h16(1, g, sa, U.u16, r16->cf(), d16->f(), (float)kappa, nmr, slot0, ns, s, U.u32.ctab))
                 return need16(GaugeTab{});
             // x += d, r = b - D_b x with its block norms and its FP16 form
-            round16 = launch_block_round16(g, sa, U.u64, d16->cf(), x, b, r16->f(), rn, kappa, slot0, ns, s);
+            // (the fused end has no clover form)
+            round16 = launch_block_round16(g, sa, Ud, d16->cf(), x, b, r16->f(), rn, kappa, slot0, ns, s);
             have_norms = round16;
             if (!round16) launch_from_h16(g, sa, d16->cf(), x, 1, slot0, ns, s);
         } else {
@@ -1259,8 +1265,8 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
         // r = b - D_b x and its norm per block on the selected blocks (r stays
         // zero elsewhere: nothing below writes other blocks of r)
         if (!have_norms) {
-            fused = launch_block_residual(g, sa, U.u64, x, b, r, kappa, slot0, ns, s);
-            if (!fused) launch_dslash<double>(g, sa, U.u64, HOPS_IN, -1, 0, x, x, t, kappa, slot0, ns, s);
+            fused = launch_block_residual(g, sa, Ud, x, b, r, kappa, slot0, ns, s);
+            if (!fused) launch_dslash<double>(g, sa, Ud, HOPS_IN, -1, 0, x, x, t, kappa, slot0, ns, s);
             launch_block_resid_norm(g, sa, b, fused ? nullptr : t, r, rn, slot0, ns, s);
         }
         k_block_check<<<M, BC_NT, 0, s>>>(g.nblk, slot0, ns, bn, rn, tol * tol, alive, its, worst);
@@ -1285,7 +1291,7 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
     const double pl = sp.inner == WDR_F64 ? 96.0 : sp.inner == WDR_F32 ? 48.0 : 24.0;  // one two-row link
     double setup = V * (4 * spin_b<double>()) + Vs * spin_b<double>();
     setup += sp.inner == WDR_F16 ? V * 48 : V * ps;
-    double round_b = Vs * (2 * ps + lin * pl);
+    double round_b = Vs * (2 * ps + lin * pl + (clov ? clov_b<float>() : 0.0));
     if (sp.inner == WDR_F16 && round16)  // the fused end: d, x, b, links in; x, r16 out
         round_b += Vs * (48 + 3 * spin_b<double>() + lin * 96.0 + 48);
     else if (sp.inner == WDR_F16)
@@ -1294,7 +1300,8 @@ wdr_status block_solve64(wdr_ctx *c, int M, const GaugeTab &U, double kappa, int
         round_b += V * (ps + spin_b<double>()) * (sp.inner == WDR_F32 ? 1 : 0) + V * (ps + 2 * spin_b<double>());
     if (!(sp.inner == WDR_F16 && round16))
         round_b += fused ? Vs * (4 * spin_b<double>() + lin * 96.0)
-                         : Vs * (2 * spin_b<double>() + lin * 96.0) + Vs * 3 * spin_b<double>();
+                         : Vs * (2 * spin_b<double>() + lin * 96.0 + (clov ? clov_b<double>() : 0.0)) +
+                               Vs * 3 * spin_b<double>();
     double bytes = 0;
     for (int m = 0; m < M; ++m) {
         bytes += setup + hits[m] * round_b;

@@ -190,7 +190,39 @@ def test_clover_block_solve(L, B, inner):
     ctx.close()
 
 
-@pytest.mark.parametrize("inner", [0, 1])
+@pytest.mark.parametrize("form", ["one", "two"])
+def test_clover_f16_block_solve(form):
+    """Dirichlet block solves with the clover term and an FP16 inner level:
+    the FP16 block MR with A_ee - 1 and A_oo^-1 in LDS inside FP64 defect
+    correction, in both launch forms (one or two blocks per CU).  Every
+    block's residual, taken with the oracle's block operator, within 1e-13 of
+    its right-hand side; the solution within 1e-11 of the oracle's."""
+    wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.6, 536)
+    ctx.set_mr_form(wdr.MR_ONE_PER_CU if form == "one" else wdr.MR_TWO_PER_CU)
+    kappa = 0.14
+    T = oracle.clover_term(lat, U, CSW, kappa)
+    gU = ctx.gauge(dev(U), CSW, kappa)
+    b = synth.spinor(lat.L, 537)
+    bid, col, _ = lat.maps()
+    p = wdr.default_params(inner=2)
+    for colour in (0, 1, 2):
+        x, info = ctx.block_solve(gU, kappa, colour, dev(b), p)
+        x = host(x)
+        sel = np.ones(lat.V, bool) if colour == 2 else col == colour
+        bb = b.copy()
+        bb[~sel] = 0
+        assert np.all(x[~sel] == 0)
+        r = bb - oracle.apply_Dblock(lat, U, kappa, x, colour, T)
+        worst = max(np.linalg.norm(r[bid == k]) / np.linalg.norm(bb[bid == k]) for k in np.unique(bid[sel]))
+        want, _, _, _ = oracle.solve(lat, U, kappa, bb, "block", colour, tol=1e-14, clov=T)
+        say("clover F16 block solve", form, colour, info.as_dict(), "worst block", worst, "vs oracle", rel(x, want))
+        assert info.converged and info.true_rel_resid <= 1e-13 and worst <= 1.05e-13
+        assert rel(x, want) < 1e-11
+    del gU
+    ctx.close()
+
+
+@pytest.mark.parametrize("inner", [0, 1, 2])
 def test_clover_schur(inner):
     """The Schur complement 1 - D_bb^-1 D_bw D_ww^-1 D_wb with the clover
     term in every block operator, within 1e-11 of the oracle's; white sites
@@ -212,12 +244,12 @@ def test_clover_schur(inner):
 
 
 @pytest.mark.parametrize("op,inner,N,K", [("BLOCKS", 1, 2, 1), ("BLOCKS", 0, 1, 2), ("SCHUR", 1, 2, 1),
-                                          ("SCHUR", 0, 1, 1)])
+                                          ("SCHUR", 0, 1, 1), ("BLOCKS", 2, 2, 1), ("SCHUR", 2, 1, 2)])
 def test_clover_block_and_schur_samples(op, inner, N, K):
     """BLOCKS (one sample per block) and SCHUR samples of the clover
-    operator (CGNE for D, FP32 / FP64 inner level) within 1e-8 of the
-    oracle's, over a path whose interior points carry clover terms the
-    library builds itself."""
+    operator (CGNE for D; FP64, FP32 or FP16 inner level, the last with the
+    FP16 block MR) within 1e-8 of the oracle's, over a path whose interior
+    points carry clover terms the library builds itself."""
     wdr, lat, ctx, U = _setup((8, 8, 8, 8), (4, 4, 4, 4), 0.5, 518)
     kappa = 0.135
     Up = synth.redraw(U, oracle.active_links(lat), 0.5, 519)
