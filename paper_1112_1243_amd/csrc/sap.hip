@@ -906,9 +906,10 @@ __device__ __forceinline__ void sum_part16(const h2 *part, int q, int h, cx<floa
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int c = 3 * q + a;
-        float re = 0.f, im = 0.f;
+        const h2 t0 = part[c * Vh + h];
+        float re = (float)t0.x, im = (float)t0.y;
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
+        for (int d = 1; d < 4; ++d) {
             const h2 t = part[(d * 12 + c) * Vh + h];
             re = __builtin_amdgcn_fdot2(t, pick_re, re, false);
             im = __builtin_amdgcn_fdot2(t, pick_im, im, false);
