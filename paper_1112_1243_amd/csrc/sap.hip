@@ -36,15 +36,18 @@ template <int CTRL, int ROWS> __device__ __forceinline__ float dpp_in(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xf, true));
 }
 // the sum over a full wavefront by DPP row shifts and row broadcasts (vector
-// ALU only, no LDS permutes), valid in lane 63
+// ALU only, no LDS permutes), valid in lane 63.  The broadcasts write every
+// row (so each step is one DPP add): lane 31 then holds rows 0 + 1 and lane
+// 63 rows 2 + 3, then all four; the other lanes end with partial sums that
+// nothing reads.
 __device__ __forceinline__ float wave_total63(float v)
 {
     v += dpp_in<0x111, 0xf>(v);  // row_shr:1
     v += dpp_in<0x112, 0xf>(v);  // row_shr:2
     v += dpp_in<0x114, 0xf>(v);  // row_shr:4
     v += dpp_in<0x118, 0xf>(v);  // row_shr:8: lane 15 of a row holds the row's sum
-    v += dpp_in<0x142, 0xa>(v);  // row_bcast:15, into rows 1 and 3
-    v += dpp_in<0x143, 0xc>(v);  // row_bcast:31, into rows 2 and 3
+    v += dpp_in<0x142, 0xf>(v);  // row_bcast:15: lane 15 of each row into the next row
+    v += dpp_in<0x143, 0xf>(v);  // row_bcast:31: lane 31 into rows 2 and 3
     return v;
 }
 // the lane of a wavefront that wave_total returns the full sum in
