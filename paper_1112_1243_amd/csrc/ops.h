@@ -106,6 +106,8 @@ bool launch_dslash_h16(const Geo &g, const h2 *U16, H16c in, H16 out, float kapp
 //   diag    NULL (no diagonal term) or a field supplying the diagonal term
 //   slots   [slot0, slot0 + nslots) receive output; other slots untouched
 //   par     -1 every site of those slots, 0 / 1 only the even / odd sites
+//           (then in is read only at sites of the other parity, so out may
+//           be the same field as in: the odd half of x from its even half)
 //   dag     1: g5 (stencil) g5, the adjoint of D (gamma5-hermiticity)
 // r = b - D_b x on the slots [slot0, slot0 + nslots) (FP64, in-block hops)
 // in one block-staged launch; false (nothing launched) where that kernel is
